@@ -1,0 +1,536 @@
+"""CPU FP64 oracle of the DSMC collision step -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously-correct implementation of what the GPU library
+computes, used to check it.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package; the product
+package never does.  It shares no code with the GPU path: the per-cell loops
+live in ``dsmc_oracle.c`` (plain C, FP64, built with gcc) and the network parts
+below are plain numpy in FP64.
+
+Parity status of each function is recorded next to it; every function is
+pinned by a CPU test against something other than itself (closed forms,
+library routines, published test vectors, brute force, finite differences).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dsmc_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_dsmc_oracle.so")
+_lib = None
+
+KB = 1.380649e-23
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC",
+               "-shared", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or (
+                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+            build(force=True)
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
+_u32p = np.ctypeslib.ndpointer(np.uint32, flags="C")
+
+
+class Potential(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("A", C.c_double),
+                ("a1", C.c_double), ("a2", C.c_double), ("am1", C.c_double),
+                ("am2", C.c_double), ("beta_tt", C.c_double), ("C", C.c_double * 6),
+                ("R_eps", C.c_double), ("A_sr", C.c_double), ("a_sr", C.c_double),
+                ("d", C.c_double), ("K", C.c_double)]
+
+
+POT_JAGER, POT_HS, POT_INVPOW = 0, 1, 2
+
+
+def _declare(L):
+    L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    L.orc_sort_cells.argtypes = [C.c_int32, C.c_int32, _i32p, _i32p, _i32p]
+    L.orc_sort_cells.restype = C.c_int
+    L.orc_moments.argtypes = [C.c_int32, _i32p, _f64p, _f64p, _f64p, _f64p]
+    L.orc_select_ntc.argtypes = [C.c_int32, _i32p, _f64p, _f64p, _f64p, C.c_double,
+                                 C.c_double, _f64p, _f64p, C.c_uint64, C.c_uint32,
+                                 _i32p, _i32p, _i32p, _i32p, _i32p, C.c_int64,
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.orc_select_ntc.restype = C.c_int
+    L.orc_pair_latents.argtypes = [C.c_int64, _i32p, _i32p, C.c_uint64, C.c_uint32,
+                                   C.c_int, _f64p, _f64p, _f64p]
+    L.orc_vhs_dirs.argtypes = [C.c_int64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p,
+                               _f64p, _f64p]
+    L.orc_apply_dirs.argtypes = [C.c_int32, _i32p, _i32p, _i32p, _i32p, _f64p, _f64p,
+                                 _f64p, _f64p]
+    L.orc_apply_chi.argtypes = [C.c_int32, _i32p, _i32p, _i32p, _i32p, _f64p, _f64p,
+                                _f64p, _f64p, _f64p, _f64p]
+    L.orc_moment_match.argtypes = [C.c_int32, _i32p, _f64p, C.c_void_p, C.c_int, _f64p,
+                                   _f64p, _f64p]
+    L.orc_moment_match.restype = C.c_int32
+    L.orc_potential_V.argtypes = [C.POINTER(Potential), C.c_double]
+    L.orc_potential_V.restype = C.c_double
+    L.orc_chi.argtypes = [C.POINTER(Potential), C.c_double, C.c_double,
+                          C.POINTER(C.c_int), C.POINTER(C.c_int64)]
+    L.orc_chi.restype = C.c_double
+    L.orc_chi_batch.argtypes = [C.POINTER(Potential), C.c_int64, _f64p, _f64p, C.c_double,
+                                _f64p, _i32p, C.c_int]
+    L.orc_step_vhs.argtypes = [C.c_int32, _i32p, _f64p, _f64p, _f64p, C.c_double,
+                               C.c_double, _f64p, C.c_uint64, C.c_uint32, C.c_int, C.c_int,
+                               C.c_int]
+    L.orc_step_vhs.restype = C.c_int64
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ---------------------------------------------------------------------------
+# RNG, sort, moments
+# ---------------------------------------------------------------------------
+def philox(ctr, key):
+    """Philox4x32-10 of one (ctr[4], key[2]) -> 4 uint32 words."""
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_c(ctr, np.uint32), _c(key, np.uint32), out)
+    return out
+
+
+def sort_cells(cell_of, n_cells):
+    """Stable counting sort: (cell_start[n_cells+1], perm[n], n_bad)."""
+    cell_of = _c(cell_of, np.int32)
+    n = cell_of.shape[0]
+    cs = np.zeros(n_cells + 1, np.int32)
+    perm = np.zeros(max(n, 1), np.int32)
+    bad = lib().orc_sort_cells(n, n_cells, cell_of, cs, perm)
+    return cs, perm[: n - bad], bad
+
+
+def moments(cell_start, v):
+    """Per-cell (ux, uy, uz, S, cmax, E) for SoA v[3, n] in sorted order."""
+    n_cells = len(cell_start) - 1
+    mom = np.zeros(max(n_cells, 1) * 6)
+    v = _c(v, np.float64)
+    lib().orc_moments(n_cells, _c(cell_start, np.int32), _c(v[0], np.float64),
+                      _c(v[1], np.float64), _c(v[2], np.float64), mom)
+    return mom[: n_cells * 6].reshape(n_cells, 6)
+
+
+# ---------------------------------------------------------------------------
+# Cross sections (Bird 1994; the paper keeps the cross-section model of the
+# selection stage unchanged): sigma_T(g) g = C g^e.
+# ---------------------------------------------------------------------------
+def sigma_g_law(xs):
+    """(C, e) with sigma_T(g) * g = C * g**e for a cross-section description.
+
+    VHS: sigma_T = pi d_ref^2 (2 k T_ref / (m_r g^2))^(omega - 1/2) / Gamma(5/2 - omega)
+         with m_r = m/2, so C = pi d_ref^2 (2 k T_ref / m_r)^(omega-1/2) / Gamma(5/2-omega)
+         and e = 2 - 2 omega.
+    constant sigma: C = sigma, e = 1.
+    """
+    if xs["kind"] == "vhs":
+        mr = xs["m"] / 2.0
+        om = xs["omega"]
+        Cc = (math.pi * xs["d_ref"] ** 2 * (2.0 * KB * xs["T_ref"] / mr) ** (om - 0.5)
+              / math.gamma(2.5 - om))
+        return Cc, 2.0 - 2.0 * om
+    if xs["kind"] == "const":
+        return float(xs["sigma"]), 1.0
+    raise ValueError(xs["kind"])
+
+
+def select_ntc(cell_start, v, xs, lam, mom, seed, step, cap=None):
+    """NTC selection; returns dict with pair_off, pair_cnt, pair_i, pair_j,
+    pair_cell (dense, cell-major, candidate order), n_cand, overflow."""
+    cs = _c(cell_start, np.int32)
+    n_cells = len(cs) - 1
+    Cc, e = sigma_g_law(xs)
+    v = _c(v, np.float64)
+    if cap is None:
+        cap = 1 << 26
+    # candidates bound the accepted pairs; allocate lazily by a first count
+    nc, npair = C.c_int64(0), C.c_int64(0)
+    off = np.zeros(max(n_cells, 1), np.int32)
+    cnt = np.zeros(max(n_cells, 1), np.int32)
+    probe = np.zeros(1, np.int32)
+    rc = lib().orc_select_ntc(n_cells, cs, _c(v[0], np.float64), _c(v[1], np.float64),
+                              _c(v[2], np.float64), Cc, e, _c(lam, np.float64),
+                              _c(mom, np.float64).reshape(-1), int(seed), int(step), off,
+                              cnt, probe, probe, probe, -1, C.byref(nc), C.byref(npair))
+    total = nc.value
+    if total > cap:
+        return {"overflow": True, "n_cand": total, "pair_off": np.zeros(n_cells, np.int32),
+                "pair_cnt": np.zeros(n_cells, np.int32),
+                "pair_i": np.zeros(0, np.int32), "pair_j": np.zeros(0, np.int32),
+                "pair_cell": np.zeros(0, np.int32)}
+    pi = np.zeros(max(total, 1), np.int32)
+    pj = np.zeros(max(total, 1), np.int32)
+    pc = np.zeros(max(total, 1), np.int32)
+    rc = lib().orc_select_ntc(n_cells, cs, _c(v[0], np.float64), _c(v[1], np.float64),
+                              _c(v[2], np.float64), Cc, e, _c(lam, np.float64),
+                              _c(mom, np.float64).reshape(-1), int(seed), int(step), off,
+                              cnt, pi, pj, pc, total, C.byref(nc), C.byref(npair))
+    assert rc == 0
+    m = npair.value
+    return {"overflow": False, "n_cand": total, "pair_off": off[:n_cells],
+            "pair_cnt": cnt[:n_cells], "pair_i": pi[:m], "pair_j": pj[:m],
+            "pair_cell": pc[:m]}
+
+
+def pair_latents(sel, seed, step, lowp=False):
+    """(U[np,6], xi[np,3], z[np,2]) for the accepted pairs of a selection."""
+    m = len(sel["pair_i"])
+    U = np.zeros(max(m, 1) * 6)
+    xi = np.zeros(max(m, 1) * 3)
+    z = np.zeros(max(m, 1) * 2)
+    off = _c(sel["pair_off"], np.int32)
+    if len(off) == 0:
+        off = np.zeros(1, np.int32)
+    lib().orc_pair_latents(m, _c(sel["pair_cell"], np.int32) if m else np.zeros(1, np.int32),
+                           off, int(seed), int(step), int(bool(lowp)), U, xi, z)
+    return U[: 6 * m].reshape(m, 6), xi[: 3 * m].reshape(m, 3), z[: 2 * m].reshape(m, 2)
+
+
+def vhs_dirs(sel, v, U, xi):
+    """Phase A of the isotropic rule: unit post-collision directions u[np,3]."""
+    m = len(sel["pair_i"])
+    u = np.zeros(max(m, 1) * 3)
+    v = _c(v, np.float64)
+    if m:
+        lib().orc_vhs_dirs(m, _c(sel["pair_i"], np.int32), _c(sel["pair_j"], np.int32),
+                           _c(v[0], np.float64), _c(v[1], np.float64), _c(v[2], np.float64),
+                           _c(U, np.float64).reshape(-1), _c(xi, np.float64).reshape(-1), u)
+    return u[: 3 * m].reshape(m, 3)
+
+
+def _pairs_args(sel):
+    def nz(a):
+        a = _c(a, np.int32)
+        return a if a.size else np.zeros(1, np.int32)
+    return nz(sel["pair_off"]), nz(sel["pair_cnt"]), nz(sel["pair_i"]), nz(sel["pair_j"])
+
+
+def apply_dirs(sel, v, u):
+    """Phase B with directions: returns the updated copy of v[3, n]."""
+    v = np.array(v, dtype=np.float64, order="C", copy=True)
+    vx, vy, vz = [np.ascontiguousarray(v[q]) for q in range(3)]
+    n_cells = len(sel["pair_cnt"])
+    uu = _c(u, np.float64).reshape(-1)
+    if uu.size == 0:
+        uu = np.zeros(3)
+    lib().orc_apply_dirs(n_cells, *_pairs_args(sel), uu, vx, vy, vz)
+    return np.stack([vx, vy, vz])
+
+
+def apply_chi(sel, v, cos_chi, sin_chi, xi):
+    """Phase B with deflection angles: returns the updated copy of v[3, n]."""
+    v = np.array(v, dtype=np.float64, order="C", copy=True)
+    vx, vy, vz = [np.ascontiguousarray(v[q]) for q in range(3)]
+    n_cells = len(sel["pair_cnt"])
+    m = len(sel["pair_i"])
+    cc = _c(cos_chi, np.float64) if m else np.zeros(1)
+    sc = _c(sin_chi, np.float64) if m else np.zeros(1)
+    xx = _c(xi, np.float64).reshape(-1) if m else np.zeros(3)
+    lib().orc_apply_chi(n_cells, *_pairs_args(sel), cc, sc, xx, vx, vy, vz)
+    return np.stack([vx, vy, vz])
+
+
+def moment_match(cell_start, mom_pre, pair_cnt, v, centred=True):
+    """Cell-wise moment matching; returns (v_new[3, n], n_skipped)."""
+    v = np.array(v, dtype=np.float64, order="C", copy=True)
+    vx, vy, vz = [np.ascontiguousarray(v[q]) for q in range(3)]
+    n_cells = len(cell_start) - 1
+    pc = None if pair_cnt is None else _c(pair_cnt, np.int32)
+    skipped = lib().orc_moment_match(
+        n_cells, _c(cell_start, np.int32), _c(mom_pre, np.float64).reshape(-1),
+        None if pc is None else pc.ctypes.data_as(C.c_void_p), int(bool(centred)),
+        vx, vy, vz)
+    return np.stack([vx, vy, vz]), int(skipped)
+
+
+# ---------------------------------------------------------------------------
+# Deflection angle (section "Computational Implementation: The Exact vs.
+# Neural Paradigm").
+# ---------------------------------------------------------------------------
+def potential_jager(p):
+    P = Potential()
+    P.kind = POT_JAGER
+    P.A, P.a1, P.a2, P.am1, P.am2, P.beta_tt = p.A, p.a1, p.a2, p.am1, p.am2, p.beta_tt
+    for q in range(6):
+        P.C[q] = p.C[q]
+    P.R_eps, P.A_sr, P.a_sr = p.R_eps, p.A_sr, p.a_sr
+    return P
+
+
+def potential_hs(d_angstrom):
+    P = Potential()
+    P.kind = POT_HS
+    P.d = d_angstrom
+    return P
+
+
+def potential_invpow(K, n):
+    P = Potential()
+    P.kind = POT_INVPOW
+    P.K = K
+    P.n = n
+    return P
+
+
+def potential_V(P, r):
+    return lib().orc_potential_V(C.byref(P), float(r))
+
+
+def chi(P, b_angstrom, E_kelvin, with_evals=False):
+    """chi(b, E) for b in Angstrom and E/k_B in K."""
+    st = C.c_int(0)
+    ne = C.c_int64(0)
+    x = lib().orc_chi(C.byref(P), float(b_angstrom), float(E_kelvin), C.byref(st),
+                      C.byref(ne))
+    if with_evals:
+        return x, st.value, ne.value
+    return x
+
+
+def chi_batch(P, b_m, g, m_red, n_threads=1):
+    """chi for SI inputs (b in m, g in m/s, reduced mass in kg)."""
+    b_m = _c(b_m, np.float64)
+    g = _c(g, np.float64)
+    n = b_m.shape[0]
+    out = np.zeros(max(n, 1))
+    st = np.zeros(max(n, 1), np.int32)
+    lib().orc_chi_batch(C.byref(P), n, b_m if n else np.zeros(1), g if n else np.zeros(1),
+                        float(m_red), out, st, int(n_threads))
+    return out[:n], st[:n]
+
+
+def fold(chi_):
+    """Folded deflection angle theta = arccos(cos chi) in [0, pi]."""
+    return np.arccos(np.clip(np.cos(chi_), -1.0, 1.0))
+
+
+def impact_from_z(z, b_max):
+    """b = b_max * sqrt(1 - exp(-|z|^2 / 2)) (b^2 uniform for normal z)."""
+    z = np.asarray(z, np.float64)
+    return b_max * np.sqrt(-np.expm1(-0.5 * np.sum(z * z, axis=-1)))
+
+
+def rotate(vr, chi_, xi):
+    """v_r' = g (cos chi vhat + sin chi e_perp(xi, vhat)) for rows."""
+    vr = np.asarray(vr, np.float64)
+    g = np.linalg.norm(vr, axis=1)
+    vh = vr / np.where(g > 0, g, 1.0)[:, None]
+    w = xi - np.sum(xi * vh, axis=1, keepdims=True) * vh
+    e = w / np.linalg.norm(w, axis=1, keepdims=True)
+    return g[:, None] * (np.cos(chi_)[:, None] * vh + np.sin(chi_)[:, None] * e)
+
+
+# ---------------------------------------------------------------------------
+# Conditional MLP, projection, loss and gradients (sections "Cell-Based
+# Neural Collision Operator" and "Hard Conservation via Projection").
+# ---------------------------------------------------------------------------
+def act_fn(name, zz):
+    if name == "silu":
+        return zz / (1.0 + np.exp(-zz))
+    if name == "relu":
+        return np.maximum(zz, 0.0)
+    raise ValueError(name)
+
+
+def act_grad(name, zz):
+    if name == "silu":
+        s = 1.0 / (1.0 + np.exp(-zz))
+        return s * (1.0 + zz * (1.0 - s))
+    if name == "relu":
+        return (zz > 0.0).astype(np.float64)
+    raise ValueError(name)
+
+
+def mlp_forward(Ws, bs, x, act="silu", keep=False):
+    """h_l = act(W_l h_{l-1} + b_l) for hidden layers, linear output layer."""
+    h = np.asarray(x, np.float64)
+    zs, hs = [], [h]
+    L = len(Ws)
+    for l in range(L):
+        zz = h @ np.asarray(Ws[l], np.float64).T + np.asarray(bs[l], np.float64)
+        if l < L - 1:
+            zs.append(zz)
+            h = act_fn(act, zz)
+            hs.append(h)
+        else:
+            h = zz
+    return (h, zs, hs) if keep else h
+
+
+def network_input(vr, xi, z, sigma_v):
+    """x = [v_r / sigma_v, xi, z] (eq. mlp_input plus the impact latents)."""
+    return np.concatenate([np.asarray(vr) / sigma_v, xi, z], axis=1)
+
+
+def project(y, g, eps=1e-30):
+    """Energy-shell projection (eq. energy_shell_projection) with a floor on
+    the norm: u = y / max(|y|, eps), v_r' = g u."""
+    n = np.linalg.norm(y, axis=1)
+    u = y / np.maximum(n, eps)[:, None]
+    return g[:, None] * u, u, n
+
+
+def surrogate_loss(vr_new, vr_target, sigma_v):
+    """MSE on the post-collision velocities of the pair, written through v_r:
+    (1/B) sum 1/2 (|v_i'-v_i*|^2 + |v_j'-v_j*|^2)/sigma_v^2 = (1/B) sum |dv_r|^2/(4 sigma_v^2)."""
+    d = vr_new - vr_target
+    return float(np.sum(d * d) / (4.0 * sigma_v ** 2 * d.shape[0]))
+
+
+def surrogate_loss_grad(vr_new, vr_target, sigma_v):
+    d = vr_new - vr_target
+    return d / (2.0 * sigma_v ** 2 * d.shape[0])
+
+
+def project_backward(G, y, g):
+    """dL/dy from dL/dv_r' for v_r' = g y/|y|: (g/|y|)(G - (G.u) u)."""
+    n = np.linalg.norm(y, axis=1)
+    u = y / n[:, None]
+    Gu = np.sum(G * u, axis=1, keepdims=True)
+    return (g / n)[:, None] * (G - Gu * u)
+
+
+def mlp_backward(Ws, bs, x, dy, act="silu"):
+    """Gradients (dW list, db list, dx) of sum(dy * mlp(x)) in FP64."""
+    _, zs, hs = mlp_forward(Ws, bs, x, act, keep=True)
+    L = len(Ws)
+    dW = [None] * L
+    db = [None] * L
+    delta = np.asarray(dy, np.float64)
+    for l in range(L - 1, -1, -1):
+        dW[l] = delta.T @ hs[l]
+        db[l] = delta.sum(axis=0)
+        dh = delta @ np.asarray(Ws[l], np.float64)
+        if l > 0:
+            delta = dh * act_grad(act, zs[l - 1])
+        else:
+            dx = dh
+    return dW, db, dx
+
+
+def moment_match_group(v, v_pre):
+    """Centred moment matching of one group of velocities v[N,3] to the
+    moments of v_pre[N,3] (differentiable form used by the adjoint)."""
+    up = v_pre.mean(axis=0)
+    Sp = np.sum((v_pre - up) ** 2)
+    uq = v.mean(axis=0)
+    c = v - uq
+    Sq = np.sum(c * c)
+    a = math.sqrt(Sp / Sq)
+    return up + a * c
+
+
+def moment_match_group_backward(G, v, v_pre):
+    """Adjoint of moment_match_group w.r.t. v (v_pre held fixed):
+    dL/dv_m = a (G_m - mean G) - (a / S_post) (sum_i G_i . c_i) c_m."""
+    up = v_pre.mean(axis=0)
+    Sp = np.sum((v_pre - up) ** 2)
+    c = v - v.mean(axis=0)
+    Sq = np.sum(c * c)
+    a = math.sqrt(Sp / Sq)
+    Gc = float(np.sum(G * c))
+    return a * (G - G.mean(axis=0)) - (a / Sq) * Gc * c
+
+
+def adam_step(params, grads, m, s, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam (Kingma & Ba 2015), bias-corrected, in FP64; updates in place."""
+    for q in range(len(params)):
+        m[q] = beta1 * m[q] + (1 - beta1) * grads[q]
+        s[q] = beta2 * s[q] + (1 - beta2) * grads[q] ** 2
+        mh = m[q] / (1 - beta1 ** t)
+        sh = s[q] / (1 - beta2 ** t)
+        params[q] = params[q] - lr * mh / (np.sqrt(sh) + eps)
+    return params, m, s
+
+
+def cosine_lr(t, T, lr_max, lr_min=1e-6):
+    """Cosine annealing from lr_max to lr_min over T steps."""
+    return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * min(t, T) / T))
+
+
+# ---------------------------------------------------------------------------
+# Whole-step compositions (sorted arrays in, sorted arrays out)
+# ---------------------------------------------------------------------------
+def step(cell_start, v, xs, lam, seed, step_no, rule="vhs", lowp=False,
+         match=None, net=None, pot=None, b_max=1e-9, m_red=None, cap=None):
+    """One collision step on sorted velocities: select (pre-step velocities),
+    Phase A per pair, Phase B in candidate order per cell, then moment matching.
+
+    rule: "vhs" | "jager" | "neural".  net: dict(Ws, bs, act, sigma_v) for
+    the neural rule.  match: None -> on for "neural", off otherwise.
+    Returns (v_new, info dict).
+    """
+    v = np.asarray(v, np.float64)
+    mom = moments(cell_start, v)
+    sel = select_ntc(cell_start, v, xs, lam, mom, seed, step_no, cap=cap)
+    if sel["overflow"]:
+        return v.copy(), {"sel": sel, "mom": mom}
+    U, xi, z = pair_latents(sel, seed, step_no, lowp=lowp)
+    info = {"sel": sel, "mom": mom, "U": U, "xi": xi, "z": z}
+    if match is None:
+        match = rule == "neural"
+    if rule == "vhs":
+        u = vhs_dirs(sel, v, U, xi)
+        vn = apply_dirs(sel, v, u)
+        info["u"] = u
+    elif rule == "jager":
+        vr = v[:, sel["pair_i"]] - v[:, sel["pair_j"]]
+        g = np.sqrt(np.sum(vr * vr, axis=0))
+        b = b_max * np.sqrt(U[:, 4])
+        ch, st = chi_batch(pot, b, g, m_red)
+        info["chi"] = ch
+        info["chi_status"] = st
+        vn = apply_chi(sel, v, np.cos(ch), np.sin(ch), xi)
+    elif rule == "neural":
+        vr = (v[:, sel["pair_i"]] - v[:, sel["pair_j"]]).T
+        g = np.linalg.norm(vr, axis=1)
+        x = network_input(vr, xi, z, net["sigma_v"])
+        y = mlp_forward(net["Ws"], net["bs"], x, net.get("act", "silu"))
+        n = np.linalg.norm(y, axis=1)
+        u = y / np.maximum(n, 1e-30)[:, None]
+        small = n <= 1e-30
+        if np.any(small):
+            uv = vhs_dirs(sel, v, U, xi)
+            u[small] = uv[small]
+        info["u"] = u
+        info["y"] = y
+        vn = apply_dirs(sel, v, u)
+    else:
+        raise ValueError(rule)
+    if match:
+        vn, sk = moment_match(cell_start, mom, sel["pair_cnt"], vn, centred=True)
+        info["skipped"] = sk
+    return vn, info
+
+
+def step_vhs_fast(cell_start, v, xs, lam, seed, step_no, lowp=False, match=False,
+                  n_threads=1):
+    """Same as step(rule="vhs") but the whole step runs in C (for timing)."""
+    Cc, e = sigma_g_law(xs)
+    vx, vy, vz = [np.array(v[q], np.float64) for q in range(3)]
+    npairs = lib().orc_step_vhs(len(cell_start) - 1, _c(cell_start, np.int32), vx, vy, vz,
+                                Cc, e, _c(lam, np.float64), int(seed), int(step_no),
+                                int(bool(lowp)), int(bool(match)), int(n_threads))
+    return np.stack([vx, vy, vz]), int(npairs)

