@@ -318,7 +318,8 @@ static void unit_or_x(double a, double b, double c, double out[3], double* g)
 
 /* Isotropic scattering (VHS/HS law): cos(chi) uniform on [-1, 1].  It is taken
  * as 2 btilde^2 - 1 with btilde^2 = 1 - exp(-|z|^2/2); for Box-Muller z that
- * quantity equals the uniform U[4] exactly, which is what is used. */
+ * quantity equals the uniform U[4] exactly, which is what is used, and
+ * sin(chi) = sqrt((1-cos)(1+cos)) = 2 sqrt(U4 (1 - U4)). */
 void orc_vhs_dirs(int64_t np, const int32_t* pair_i, const int32_t* pair_j,
                   const double* vx, const double* vy, const double* vz,
                   const double* U, const double* xi, double* u)
@@ -328,7 +329,7 @@ void orc_vhs_dirs(int64_t np, const int32_t* pair_i, const int32_t* pair_j,
         double vh[3], g, e[3];
         unit_or_x(vx[a] - vx[b], vy[a] - vy[b], vz[a] - vz[b], vh, &g);
         double cc = 2.0 * U[6 * p + 4] - 1.0;
-        double sc = sqrt(fmax(0.0, 1.0 - cc * cc));
+        double sc = 2.0 * sqrt(U[6 * p + 4] * (1.0 - U[6 * p + 4]));
         perp_unit(xi + 3 * p, vh, e);
         for (int q = 0; q < 3; ++q) u[3 * p + q] = cc * vh[q] + sc * e[q];
     }
@@ -788,7 +789,7 @@ int64_t orc_step_vhs(int32_t n_cells, const int32_t* cell_start, double* vx,
                 latents_from_uniforms(U, xi, z);
                 int32_t ia = s0 + li[q], ib = s0 + lj[q];
                 unit_or_x(vx[ia] - vx[ib], vy[ia] - vy[ib], vz[ia] - vz[ib], vh, &g);
-                double cc = 2.0 * U[4] - 1.0, sc = sqrt(fmax(0.0, 1.0 - cc * cc));
+                double cc = 2.0 * U[4] - 1.0, sc = 2.0 * sqrt(U[4] * (1.0 - U[4]));
                 perp_unit(xi, vh, e);
                 for (int d = 0; d < 3; ++d) dirs[3 * q + d] = cc * vh[d] + sc * e[d];
             }
