@@ -1,0 +1,315 @@
+/*
+ * dsmc.h -- C-ABI of the MI355X (gfx950) DSMC collision-step library.
+ *
+ * The library implements the collision step of Direct Simulation Monte Carlo
+ * as the paper (Roohi, Shoja-sani, Stefanov, arXiv 2602.21244) states it in
+ * section "DSMC collision step and scope of replacement": particles are sorted
+ * into cells, candidate pairs are selected per cell by the No-Time-Counter
+ * scheme, and each accepted pair's post-collision relative velocity comes from
+ * a scattering rule -- the isotropic VHS law, the ab initio deflection angle
+ * chi(b, g) by quadrature of the classical deflection integral, or the paper's
+ * neural surrogate (conditional MLP with latent noise, energy-shell projection)
+ * -- followed by cell-wise moment matching.
+ *
+ * Conventions (all entry points):
+ *  - Every array argument is a caller-owned DEVICE pointer unless it says
+ *    "host".  The library never allocates or frees caller memory; scratch
+ *    memory is a caller-owned workspace whose size the *_ws query returns.
+ *  - Every call is asynchronous on the given HIP stream (NULL = the default
+ *    stream), performs no host synchronisation and no allocation, and can be
+ *    captured into a HIP graph.  Data-dependent outcomes (pair counts,
+ *    overflow, root-search failures) are written to a caller-owned device
+ *    status word, never returned to the host.
+ *  - Return value: DSMC_OK, or a negative code for errors detectable on the
+ *    host (null pointers, bad enums or sizes: DSMC_E_ARG; a failed launch:
+ *    DSMC_E_HIP; a shape without a compiled kernel: DSMC_E_UNSUPPORTED).
+ *    dsmc_last_error() returns a thread-local message for the last error.
+ *  - Velocities are structure-of-arrays (vx, vy, vz), FP64 or FP32, in m/s.
+ *    After dsmc_sort_cells they are in cell-sorted order: cell k owns sorted
+ *    slots [cell_start[k], cell_start[k+1]).
+ *  - Randomness is counter-based Philox4x32-10 keyed by (seed) with counter
+ *    (index, cell, step, slot), so results do not depend on launch shape or
+ *    schedule and are reproducible bit for bit.
+ */
+#ifndef DSMC_H
+#define DSMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* dsmc_stream_t; /* hipStream_t */
+
+enum { DSMC_OK = 0, DSMC_E_ARG = -1, DSMC_E_HIP = -2, DSMC_E_UNSUPPORTED = -3 };
+enum { DSMC_F32 = 0, DSMC_F64 = 1, DSMC_BF16 = 2 };
+
+/* SoA velocity components (device arrays of the chosen dtype). */
+typedef struct { void* x; void* y; void* z; } dsmc_vec3;
+
+/* Philox key and step counter of one collision step. */
+typedef struct { uint64_t seed; uint32_t step; uint32_t reserved; } dsmc_rng;
+
+/* Device status word (caller-owned device memory).  Counters accumulate
+ * across calls until dsmc_status_clear. */
+typedef struct {
+    uint32_t flags;     /* DSMC_ST_* bits */
+    int32_t bad_cell;   /* particles whose cell id was outside [0, n_cells) */
+    int64_t n_cand;     /* candidates of the last selection (capacity needed) */
+    int64_t n_pairs;    /* accepted pairs of the last selection */
+    int32_t root_fail;  /* deflection evaluations whose root search failed */
+    int32_t nonfinite;  /* non-finite values met (results left unchanged) */
+    int32_t mm_skipped; /* cells that moment matching left alone (S_post <= 0) */
+    int32_t reserved;
+} dsmc_status;
+enum {
+    DSMC_ST_PAIR_OVERFLOW = 1u, /* candidates exceeded the pair capacity */
+    DSMC_ST_BAD_CELL = 2u,
+    DSMC_ST_ROOT_FAIL = 4u,
+    DSMC_ST_NONFINITE = 8u
+};
+
+/* Accepted-pair list, dense and cell-major: the pairs of cell k are entries
+ * [off[k], off[k] + cnt[k]) in candidate order.  i and j are sorted slots. */
+typedef struct {
+    int32_t* off;  /* [n_cells] */
+    int32_t* cnt;  /* [n_cells] */
+    int32_t* i;    /* [cap] */
+    int32_t* j;    /* [cap] */
+    int32_t* cell; /* [cap] owning cell of each pair */
+    int64_t cap;   /* capacity of i, j, cell -- and the most candidates a
+                      selection may draw (more sets DSMC_ST_PAIR_OVERFLOW) */
+} dsmc_pairs;
+
+/* Cross-section law of the selection stage (kept unchanged by the paper):
+ * VHS sigma_T(g) = pi d_ref^2 (2 k T_ref/(m_r g^2))^(omega-1/2) / Gamma(5/2-omega),
+ * m_r = m/2 (Bird 1994); CONST: sigma (the paper's constant reference cross
+ * section).  All SI units. */
+enum { DSMC_XS_VHS = 0, DSMC_XS_CONST = 1 };
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double m, d_ref, omega, T_ref; /* VHS */
+    double sigma;                  /* CONST */
+} dsmc_xs;
+
+/* Interaction potential for the deflection angle.  r in Angstrom, V/k_B in K.
+ * JAGER: the paper's modified Tang-Toennies form (eq. jager_potential with the
+ *   damping of eq. damping) for r >= 0.4 R_eps, screened Coulomb A_sr/r
+ *   exp(-a_sr r) below.  C[] = C6..C16; beta_tt is the damping constant.
+ * HS: hard sphere of diameter d.  INVPOW: V = K / r^n (n = 1..12). */
+enum { DSMC_POT_JAGER = 0, DSMC_POT_HS = 1, DSMC_POT_INVPOW = 2 };
+typedef struct {
+    int32_t kind;
+    int32_t n;
+    double A, a1, a2, am1, am2, beta_tt;
+    double C[6];
+    double R_eps, A_sr, a_sr;
+    double d;
+    double K;
+} dsmc_potential;
+
+/* Quadrature settings of the deflection integral.  n_nodes: Gauss-Legendre
+ * nodes (8..128; 0 = 64).  scan_ratio: geometric step of the downward root
+ * scan at low energy (0 = 0.98).  max_iter: root refinement iterations
+ * (0 = 60). */
+typedef struct {
+    int32_t n_nodes;
+    int32_t max_iter;
+    double scan_ratio;
+} dsmc_quad;
+
+/* Conditional MLP f_theta (section "Cell-Based Neural Collision Operator"):
+ * h_l = act(W_l h_{l-1} + b_l) for hidden layers, linear output layer.
+ * W[l] is row-major [dims[l+1]][dims[l]].  wdtype DSMC_BF16: W in bf16, b in
+ * fp32, MFMA path (hidden widths multiples of 32 up to 256, dims[0] <= 32,
+ * dims[L] <= 32).  wdtype DSMC_F64: W, b in fp64, FP64 reference path (any
+ * width up to 256).  The input row is x = [v_r/sigma_v (3), xi (3), z (2)]
+ * (eq. mlp_input plus the two impact latents), so dims[0] must be 8 for the
+ * in-step entry point. */
+enum { DSMC_ACT_SILU = 0, DSMC_ACT_RELU = 1 };
+typedef struct {
+    int32_t n_layers;
+    int32_t dims[7];
+    int32_t act;
+    int32_t wdtype;
+    const void* W[6];
+    const void* b[6];
+    double sigma_v;
+} dsmc_mlp;
+
+/* Phase-B schedules: AUTO picks by pair count (autotuned threshold); LANE:
+ * one lane per cell; BLOCK: one workgroup per cell applying independent
+ * pairs in dependency rounds.  All schedules give bit-identical results. */
+enum { DSMC_SCHED_AUTO = 0, DSMC_SCHED_LANE = 1, DSMC_SCHED_BLOCK = 2 };
+
+/* Moment-matching modes (eq. cell_energy_clamp). */
+enum { DSMC_MM_CAPTURE = 0, DSMC_MM_APPLY = 1, DSMC_MM_APPLY_LITERAL = 2 };
+
+/* ---------------------------------------------------------------------- */
+
+/* Select the device used by later calls from this thread (hipSetDevice);
+ * optional. */
+int dsmc_init(int device);
+const char* dsmc_last_error(void);
+const char* dsmc_version(void);
+
+/* Zero the status word on the stream (a fill kernel, graph-safe). */
+int dsmc_status_clear(dsmc_status* st, dsmc_stream_t stream);
+
+/* Bin particles into cells (section "Computational Framework", item 1:
+ * particles sorted by cell index so each cell is contiguous).
+ * Stable counting sort by cell_of[n] (original order kept inside a cell):
+ * writes cell_start[n_cells+1] (exclusive prefix of the counts), perm[n]
+ * (perm[s] = original index of sorted slot s) and gathers v_in into v_out
+ * (distinct buffers).  Ids outside [0, n_cells) are dropped and counted in
+ * st->bad_cell; then cell_start[n_cells] < n and perm/v_out hold only the
+ * kept particles.  ws: dsmc_sort_cells_ws(n, n_cells) bytes. */
+size_t dsmc_sort_cells_ws(int32_t n, int32_t n_cells);
+int dsmc_sort_cells(int32_t n, int32_t n_cells, const int32_t* cell_of, int32_t dtype,
+                    dsmc_vec3 v_in, dsmc_vec3 v_out, int32_t* cell_start, int32_t* perm,
+                    void* ws, size_t ws_bytes, dsmc_status* st, dsmc_stream_t stream);
+
+/* Cell moments and cell-wise moment matching (section "Optional Cell-Wise
+ * Energy Drift Correction", eq. cell_energy_clamp), FP64 throughout.
+ * mom[6*n_cells] per cell: (ux, uy, uz, S, cmax, E) with u the mean velocity,
+ * S = sum |v-u|^2, cmax = max |v-u|, E = sum |v|^2.
+ * CAPTURE: write mom from v.  APPLY: for every cell with N >= 2 and (if
+ * pair_cnt is not NULL) pair_cnt[k] > 0, set v <- u_pre + alpha (v - u_post),
+ * alpha = sqrt(S_pre / S_post): restores the cell's momentum and energy.
+ * APPLY_LITERAL: v <- alpha v with alpha = sqrt(E_pre / E_post) (the
+ * equation as printed; conserves energy only).  Cells with a non-positive or
+ * non-finite post value are left unchanged and counted in st->mm_skipped. */
+int dsmc_moment_match(int32_t n_cells, const int32_t* cell_start, int32_t dtype,
+                      dsmc_vec3 v, double* mom, int32_t mode, const int32_t* pair_cnt,
+                      dsmc_status* st, dsmc_stream_t stream);
+
+/* No-Time-Counter pair selection (section "Cell partition and
+ * collision-pair selection"): per cell with N >= 2 particles,
+ *   M = floor(N (N-1)/2 * lambda_k * (sigma g)_max + U),
+ * (sigma g)_max from g_hat = 2 cmax (mom from CAPTURE, an exact bound on the
+ * cell's pair speeds); each candidate t draws an ordered pair i != j
+ * uniformly and is accepted iff U_t < sigma(g) g / (sigma g)_max, on the
+ * velocities as passed (pre-collision).  lambda[n_cells] = F_N dt / V_c.
+ * If the total candidate count exceeds pairs.cap no pair is written,
+ * DSMC_ST_PAIR_OVERFLOW is set and st->n_cand holds the capacity needed.
+ * ws: dsmc_select_pairs_ntc_ws(n_cells, cap) bytes. */
+size_t dsmc_select_pairs_ntc_ws(int32_t n_cells, int64_t cap);
+int dsmc_select_pairs_ntc(int32_t n_cells, const int32_t* cell_start, int32_t dtype,
+                          dsmc_vec3 v, dsmc_xs xs, const double* lambda, const double* mom,
+                          dsmc_rng rng, dsmc_pairs pairs, void* ws, size_t ws_bytes,
+                          dsmc_status* st, dsmc_stream_t stream);
+
+/* Workspace of the collide entry points below (per-pair Phase-A results). */
+size_t dsmc_collide_ws(int64_t cap, int32_t dtype);
+
+/* Isotropic VHS scattering (the plain rule the paper replaces; isotropy
+ * check of section "Generalization Test"): Phase A per accepted pair on the
+ * pre-collision velocities -- cos chi uniform on [-1,1], azimuth from the
+ * latent xi -- then Phase B per cell in candidate order on the current
+ * velocities: v_r' = |v_r| u, v_i = v_cm + v_r'/2, v_j = v_cm - v_r'/2
+ * (eq. v_update_pair).  Exactly conserves each pair's momentum and energy. */
+int dsmc_collide_vhs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pairs,
+                     dsmc_rng rng, int32_t schedule, void* ws, size_t ws_bytes,
+                     dsmc_stream_t stream);
+
+/* Ab initio deflection angle by quadrature (section "Computational
+ * Implementation: The Exact vs. Neural Paradigm"): for each of n pairs,
+ * E = m_red g^2 / 2, r_min = largest root of 1 - b^2/r^2 - V(r)/E, and
+ *   chi = pi - 2 b int_{r_min}^inf dr / (r^2 sqrt(1 - b^2/r^2 - V/E)),
+ * evaluated after u = r_min / r and u = 1 - t^2 with Gauss-Legendre in t.
+ * b (m), g (m/s) and chi (rad) are arrays of `dtype` (FP64 or FP32: the
+ * arithmetic precision).  fold = 1 returns theta = arccos(cos chi) in
+ * [0, pi].  A failed root search gives NaN and counts in st->root_fail. */
+int dsmc_deflect_jager(int64_t n, int32_t dtype, const void* b, const void* g, void* chi,
+                       double m_red, const dsmc_potential* pot, dsmc_quad quad, int32_t fold,
+                       dsmc_status* st, dsmc_stream_t stream);
+
+/* In-step ab initio rule: Phase A per accepted pair computes chi(b, g_pre)
+ * by the quadrature above with b = b_max sqrt(1 - exp(-|z|^2/2)) from the
+ * pair's latent z (b^2 uniform on [0, b_max^2]); Phase B rotates the current
+ * v_r by chi about the azimuth direction of the latent xi. */
+int dsmc_collide_jager(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pairs,
+                       dsmc_rng rng, double m_red, double b_max, const dsmc_potential* pot,
+                       dsmc_quad quad, int32_t schedule, void* ws, size_t ws_bytes,
+                       dsmc_status* st, dsmc_stream_t stream);
+
+/* Neural collision operator (sections "Cell-Based Neural Collision
+ * Operator" and "Hard Conservation via Projection and Pair Update"):
+ * Phase A per accepted pair: x = [v_r/sigma_v, xi, z] -> y = f_theta(x) ->
+ * u = y / max(|y|, 1e-30) (energy-shell projection; the isotropic direction
+ * if |y| <= 1e-30); Phase B as in dsmc_collide_vhs.  Follow with
+ * dsmc_moment_match(APPLY) for the paper's cell-wise correction.
+ * ws: dsmc_collide_ws(cap, dtype) bytes for a BF16 network; the FP64/FP32
+ * reference networks (wdtype == dtype) need dsmc_collide_ws(cap, dtype) +
+ * dsmc_neural_act_bytes(net, cap). */
+int dsmc_neural_collide(const dsmc_mlp* net, int32_t n_cells, int32_t dtype, dsmc_vec3 v,
+                        dsmc_pairs pairs, dsmc_rng rng, int32_t schedule, void* ws,
+                        size_t ws_bytes, dsmc_status* st, dsmc_stream_t stream);
+
+/* Rows form of the surrogate for training: for B rows x[B][dims[0]] and
+ * speeds g[B]: y_raw = f_theta(x) [B][dims[L]], vr_out = g * y/|y| [B][3].
+ * Array dtype: FP32 for the BF16 network, FP64 for the FP64 network.
+ * act_save (nullable): activations kept for dsmc_neural_backward, size
+ * dsmc_neural_act_bytes(net, B). */
+size_t dsmc_neural_act_bytes(const dsmc_mlp* net, int64_t B);
+int dsmc_neural_forward_rows(const dsmc_mlp* net, int64_t B, const void* x, const void* g,
+                             void* y_raw, void* vr_out, void* act_save, size_t act_bytes,
+                             dsmc_stream_t stream);
+
+/* Backward of the rows form (the hand-written adjoint of the MLP and the
+ * energy-shell projection):  given dL/dv_r' [B][3], writes dW[l], db[l]
+ * (FP32 for the BF16 network, FP64 for the FP64 network; accumulate = 1 adds
+ * to them) and, if dx != NULL, dL/dx [B][dims[0]].  The row reduction of dW
+ * runs in a fixed order (deterministic).  act_save from the forward call.
+ * ws: dsmc_neural_backward_ws(net, B) bytes. */
+size_t dsmc_neural_backward_ws(const dsmc_mlp* net, int64_t B);
+int dsmc_neural_backward(const dsmc_mlp* net, int64_t B, const void* x, const void* act_save,
+                         const void* y_raw, const void* g, const void* dL_dvr,
+                         void* const* dW, void* const* db, void* dx, int32_t accumulate,
+                         void* ws, size_t ws_bytes, dsmc_stream_t stream);
+
+/* Adjoint of the centred moment matching of one cell group (v -> u_pre +
+ * alpha (v - u_post)) with respect to the post-collision velocities:
+ *   dL/dv_m = alpha (G_m - mean G) - (alpha / S_post) (sum_i G_i . c_i) c_m,
+ * c = v - u_post.  FP64 arrays [3][n] SoA in sorted order, pre-moments from
+ * CAPTURE.  Cells with N < 2 or S_post <= 0 pass G through. */
+int dsmc_moment_match_backward(int32_t n_cells, const int32_t* cell_start, const double* mom_pre,
+                               const double* v_post_x, const double* v_post_y,
+                               const double* v_post_z, const double* G_x, const double* G_y,
+                               const double* G_z, double* out_x, double* out_y,
+                               double* out_z, dsmc_stream_t stream);
+
+/* Training helpers.  MSE on the post-collision velocities of the pair,
+ * L = (1/B) sum |v_r' - v_r'*|^2 / (4 sigma_v^2); writes dL/dv_r' and adds L
+ * to *loss (device double).  Arrays FP32 [B][3]. */
+int dsmc_mse_loss(int64_t B, const float* vr_new, const float* vr_target, double sigma_v,
+                  float* dL_dvr, double* loss, dsmc_stream_t stream);
+
+/* Adam (Kingma & Ba 2015) with bias correction on FP32 master parameters;
+ * also writes the bf16 copy used by the MFMA forward when param_bf16 != NULL.
+ * lr comes from the cosine schedule the caller evaluates. */
+int dsmc_adam_step(int64_t n, float* param, void* param_bf16, const float* grad, float* m,
+                   float* v, int64_t t, double lr, double beta1, double beta2, double eps,
+                   dsmc_stream_t stream);
+
+/* Training rows from the quadrature ("physics harvesting" on pairs the
+ * library generates): for rows (v_r, xi, z) in FP64, b from z as in
+ * dsmc_collide_jager, chi by quadrature, target v_r' = g (cos chi vhat +
+ * sin chi e_perp(xi)).  Also writes x = [v_r/sigma_v, xi, z] (FP32) and chi. */
+int dsmc_harvest_rows(int64_t B, const double* vr, const double* xi, const double* z,
+                      double sigma_v, double b_max, double m_red, const dsmc_potential* pot,
+                      dsmc_quad quad, float* x_out, float* g_out, float* target_out,
+                      double* chi_out, dsmc_status* st, dsmc_stream_t stream);
+
+/* Tuning knobs (host): threshold in pairs above which AUTO uses the BLOCK
+ * schedule; the autotuner in the Python package sets it. */
+int dsmc_set_block_threshold(int32_t pairs);
+int32_t dsmc_get_block_threshold(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSMC_H */

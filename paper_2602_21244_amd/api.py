@@ -1,0 +1,341 @@
+"""Python binding of the C-ABI with the same names (argument marshalling only).
+
+Device memory and streams come from PyTorch (ROCm build): arrays are torch
+tensors on a HIP device, the stream is torch's current stream.  Every step of
+the collision path runs in the library's HIP kernels; nothing here computes.
+Velocities are passed as one contiguous [3, N] tensor (SoA rows vx, vy, vz).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import torch
+
+from . import _lib as L
+from ._lib import check
+
+_DT = {torch.float32: L.F32, torch.float64: L.F64}
+
+
+def lib():
+    return L.load()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _vec3(v):
+    assert v.dim() == 2 and v.shape[0] == 3 and v.is_contiguous()
+    return L.Vec3(v[0].data_ptr(), v[1].data_ptr(), v[2].data_ptr())
+
+
+def _dtype(v):
+    if v.dtype not in _DT:
+        raise TypeError(f"velocities must be float32 or float64, got {v.dtype}")
+    return _DT[v.dtype]
+
+
+def workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def new_status(device):
+    st = torch.zeros(C.sizeof(L.Status), dtype=torch.uint8, device=device)
+    return st
+
+
+def read_status(st):
+    raw = st.cpu().numpy().tobytes()
+    return L.Status.from_buffer_copy(raw)
+
+
+def status_clear(st, stream=None):
+    check(lib().dsmc_status_clear(_ptr(st), _stream(stream)), "dsmc_status_clear")
+
+
+# ---------------------------------------------------------------------------
+# Parameter structs
+# ---------------------------------------------------------------------------
+def xs_struct(xs: dict):
+    x = L.Xs()
+    if xs["kind"] == "vhs":
+        x.kind = L.XS_VHS
+        x.m, x.d_ref, x.omega, x.T_ref = xs["m"], xs["d_ref"], xs["omega"], xs["T_ref"]
+    elif xs["kind"] == "const":
+        x.kind = L.XS_CONST
+        x.sigma = xs["sigma"]
+        x.m = xs.get("m", 0.0)
+    else:
+        raise ValueError(xs["kind"])
+    return x
+
+
+def rng_struct(seed, step):
+    return L.Rng(int(seed) & 0xFFFFFFFFFFFFFFFF, int(step) & 0xFFFFFFFF, 0)
+
+
+def potential_jager(p):
+    P = L.Potential()
+    P.kind = L.POT_JAGER
+    P.A, P.a1, P.a2, P.am1, P.am2, P.beta_tt = p.A, p.a1, p.a2, p.am1, p.am2, p.beta_tt
+    for q in range(6):
+        P.C[q] = p.C[q]
+    P.R_eps, P.A_sr, P.a_sr = p.R_eps, p.A_sr, p.a_sr
+    return P
+
+
+def potential_hs(d_angstrom):
+    P = L.Potential()
+    P.kind = L.POT_HS
+    P.d = d_angstrom
+    return P
+
+
+def potential_invpow(K, n):
+    P = L.Potential()
+    P.kind = L.POT_INVPOW
+    P.K = K
+    P.n = n
+    return P
+
+
+def quad_struct(n_nodes=64, max_iter=60, scan_ratio=0.98):
+    return L.Quad(int(n_nodes), int(max_iter), float(scan_ratio))
+
+
+class Net:
+    """Device copy of an MLP for the C-ABI (keeps the tensors alive)."""
+
+    def __init__(self, Ws, bs, act="silu", wdtype="bf16", sigma_v=1.0, device="cuda"):
+        self.dims = [int(Ws[0].shape[1])] + [int(w.shape[0]) for w in Ws]
+        self.act = act
+        self.wdtype = wdtype
+        self.sigma_v = float(sigma_v)
+        if wdtype == "bf16":
+            self.W = [torch.as_tensor(w, dtype=torch.float32).to(device).to(torch.bfloat16).contiguous() for w in Ws]
+            self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in bs]
+            self.code = L.BF16
+        elif wdtype == "f64":
+            self.W = [torch.as_tensor(w, dtype=torch.float64).to(device).contiguous() for w in Ws]
+            self.b = [torch.as_tensor(b, dtype=torch.float64).to(device).contiguous() for b in bs]
+            self.code = L.F64
+        elif wdtype == "f32":
+            self.W = [torch.as_tensor(w, dtype=torch.float32).to(device).contiguous() for w in Ws]
+            self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in bs]
+            self.code = L.F32
+        else:
+            raise ValueError(wdtype)
+        self.refresh()
+
+    def refresh(self):
+        m = L.Mlp()
+        m.n_layers = len(self.W)
+        for q, d in enumerate(self.dims):
+            m.dims[q] = d
+        m.act = L.ACT_SILU if self.act == "silu" else L.ACT_RELU
+        m.wdtype = self.code
+        for q in range(len(self.W)):
+            m.W[q] = self.W[q].data_ptr()
+            m.b[q] = self.b[q].data_ptr()
+        m.sigma_v = self.sigma_v
+        self.struct = m
+        return m
+
+
+# ---------------------------------------------------------------------------
+# Entry points
+# ---------------------------------------------------------------------------
+def sort_cells(cell_of, n_cells, v_in, st=None, stream=None):
+    """Returns (cell_start[n_cells+1], perm[n], v_sorted[3, n])."""
+    dev = cell_of.device
+    n = int(cell_of.numel())
+    v_out = torch.empty_like(v_in)
+    cs = torch.empty(n_cells + 1, dtype=torch.int32, device=dev)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    ws_b = lib().dsmc_sort_cells_ws(n, n_cells)
+    ws = workspace(ws_b, dev)
+    check(lib().dsmc_sort_cells(n, n_cells, _ptr(cell_of), _dtype(v_in), _vec3(v_in), _vec3(v_out),
+                                _ptr(cs), _ptr(perm), _ptr(ws), ws_b, _ptr(st), _stream(stream)),
+          "dsmc_sort_cells")
+    return cs, perm[:n], v_out
+
+
+def moment_match(cell_start, v, mom, mode, pair_cnt=None, st=None, stream=None):
+    n_cells = int(cell_start.numel()) - 1
+    check(lib().dsmc_moment_match(n_cells, _ptr(cell_start), _dtype(v), _vec3(v), _ptr(mom),
+                                  int(mode), _ptr(pair_cnt), _ptr(st), _stream(stream)),
+          "dsmc_moment_match")
+
+
+class PairList:
+    def __init__(self, n_cells, cap, device):
+        self.cap = int(cap)
+        self.off = torch.zeros(n_cells, dtype=torch.int32, device=device)
+        self.cnt = torch.zeros(n_cells, dtype=torch.int32, device=device)
+        self.i = torch.zeros(self.cap + 1, dtype=torch.int32, device=device)
+        self.j = torch.zeros(self.cap + 1, dtype=torch.int32, device=device)
+        self.cell = torch.zeros(self.cap + 1, dtype=torch.int32, device=device)
+
+    def struct(self):
+        return L.Pairs(self.off.data_ptr(), self.cnt.data_ptr(), self.i.data_ptr(),
+                       self.j.data_ptr(), self.cell.data_ptr(), self.cap)
+
+
+def select_pairs_ntc(cell_start, v, xs, lam, mom, seed, step, pairs, ws=None, st=None,
+                     stream=None):
+    n_cells = int(cell_start.numel()) - 1
+    need = lib().dsmc_select_pairs_ntc_ws(n_cells, pairs.cap)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, v.device)
+    check(lib().dsmc_select_pairs_ntc(n_cells, _ptr(cell_start), _dtype(v), _vec3(v),
+                                      xs_struct(xs), _ptr(lam), _ptr(mom), rng_struct(seed, step),
+                                      pairs.struct(), _ptr(ws), int(ws.numel()), _ptr(st),
+                                      _stream(stream)),
+          "dsmc_select_pairs_ntc")
+    return ws
+
+
+def collide_ws(cap, v, extra=0):
+    return workspace(lib().dsmc_collide_ws(int(cap), _dtype(v)) + int(extra), v.device)
+
+
+def collide_vhs(v, pairs, seed, step, schedule=L.SCHED_AUTO, ws=None, stream=None):
+    n_cells = int(pairs.off.numel())
+    if ws is None:
+        ws = collide_ws(pairs.cap, v)
+    check(lib().dsmc_collide_vhs(n_cells, _dtype(v), _vec3(v), pairs.struct(),
+                                 rng_struct(seed, step), int(schedule), _ptr(ws), int(ws.numel()),
+                                 _stream(stream)),
+          "dsmc_collide_vhs")
+    return ws
+
+
+def deflect_jager(b, g, m_red, pot, quad=None, fold=False, st=None, stream=None):
+    chi = torch.empty_like(g)
+    q = quad if quad is not None else quad_struct()
+    check(lib().dsmc_deflect_jager(int(b.numel()), _dtype(b), _ptr(b), _ptr(g), _ptr(chi),
+                                   float(m_red), C.byref(pot), q, int(bool(fold)), _ptr(st),
+                                   _stream(stream)),
+          "dsmc_deflect_jager")
+    return chi
+
+
+def collide_jager(v, pairs, seed, step, m_red, b_max, pot, quad=None, schedule=L.SCHED_AUTO,
+                  ws=None, st=None, stream=None):
+    n_cells = int(pairs.off.numel())
+    if ws is None:
+        ws = collide_ws(pairs.cap, v)
+    q = quad if quad is not None else quad_struct()
+    check(lib().dsmc_collide_jager(n_cells, _dtype(v), _vec3(v), pairs.struct(),
+                                   rng_struct(seed, step), float(m_red), float(b_max), C.byref(pot),
+                                   q, int(schedule), _ptr(ws), int(ws.numel()), _ptr(st),
+                                   _stream(stream)),
+          "dsmc_collide_jager")
+    return ws
+
+
+def neural_ws(net, pairs, v):
+    extra = 0
+    if net.wdtype != "bf16":
+        extra = lib().dsmc_neural_act_bytes(C.byref(net.struct), int(pairs.cap))
+    return collide_ws(pairs.cap, v, extra)
+
+
+def neural_collide(net, v, pairs, seed, step, schedule=L.SCHED_AUTO, ws=None, st=None,
+                   stream=None):
+    n_cells = int(pairs.off.numel())
+    if ws is None:
+        ws = neural_ws(net, pairs, v)
+    check(lib().dsmc_neural_collide(C.byref(net.struct), n_cells, _dtype(v), _vec3(v),
+                                    pairs.struct(), rng_struct(seed, step), int(schedule),
+                                    _ptr(ws), int(ws.numel()), _ptr(st), _stream(stream)),
+          "dsmc_neural_collide")
+    return ws
+
+
+def neural_act_bytes(net, B):
+    return int(lib().dsmc_neural_act_bytes(C.byref(net.struct), int(B)))
+
+
+def neural_forward_rows(net, x, g, act_save=None, stream=None):
+    """Rows form: returns (y_raw [B, dout], vr_out [B, 3])."""
+    B = int(x.shape[0])
+    y = torch.empty(B, net.dims[-1], dtype=x.dtype, device=x.device)
+    vr = torch.empty(B, 3, dtype=x.dtype, device=x.device)
+    ab = int(act_save.numel()) if act_save is not None else 0
+    check(lib().dsmc_neural_forward_rows(C.byref(net.struct), B, _ptr(x), _ptr(g), _ptr(y),
+                                         _ptr(vr), _ptr(act_save), ab, _stream(stream)),
+          "dsmc_neural_forward_rows")
+    return y, vr
+
+
+def neural_backward(net, x, act_save, y_raw, g, dL_dvr, dW, db, dx=None, accumulate=False,
+                    ws=None, stream=None):
+    B = int(x.shape[0])
+    need = lib().dsmc_neural_backward_ws(C.byref(net.struct), B)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, x.device)
+    nl = len(net.W)
+    dWp = (C.c_void_p * nl)(*[t.data_ptr() for t in dW])
+    dbp = (C.c_void_p * nl)(*[t.data_ptr() for t in db])
+    check(lib().dsmc_neural_backward(C.byref(net.struct), B, _ptr(x), _ptr(act_save),
+                                     _ptr(y_raw), _ptr(g), _ptr(dL_dvr), dWp, dbp, _ptr(dx),
+                                     int(bool(accumulate)), _ptr(ws), int(ws.numel()),
+                                     _stream(stream)),
+          "dsmc_neural_backward")
+    return ws
+
+
+def moment_match_backward(cell_start, mom_pre, v_post, G, stream=None):
+    out = torch.empty_like(G)
+    n_cells = int(cell_start.numel()) - 1
+    check(lib().dsmc_moment_match_backward(n_cells, _ptr(cell_start), _ptr(mom_pre),
+                                           _ptr(v_post[0]), _ptr(v_post[1]), _ptr(v_post[2]),
+                                           _ptr(G[0]), _ptr(G[1]), _ptr(G[2]), _ptr(out[0]),
+                                           _ptr(out[1]), _ptr(out[2]), _stream(stream)),
+          "dsmc_moment_match_backward")
+    return out
+
+
+def mse_loss(vr_new, vr_target, sigma_v, dL_dvr, loss, stream=None):
+    check(lib().dsmc_mse_loss(int(vr_new.shape[0]), _ptr(vr_new), _ptr(vr_target),
+                              float(sigma_v), _ptr(dL_dvr), _ptr(loss), _stream(stream)),
+          "dsmc_mse_loss")
+
+
+def adam_step(param, grad, m, v, t, lr, param_bf16=None, beta1=0.9, beta2=0.999, eps=1e-8,
+              stream=None):
+    check(lib().dsmc_adam_step(int(param.numel()), _ptr(param), _ptr(param_bf16), _ptr(grad),
+                               _ptr(m), _ptr(v), int(t), float(lr), float(beta1), float(beta2),
+                               float(eps), _stream(stream)),
+          "dsmc_adam_step")
+
+
+def harvest_rows(vr, xi, z, sigma_v, b_max, m_red, pot, quad=None, st=None, stream=None):
+    B = int(vr.shape[0])
+    dev = vr.device
+    x = torch.empty(B, 8, dtype=torch.float32, device=dev)
+    g = torch.empty(B, dtype=torch.float32, device=dev)
+    tgt = torch.empty(B, 3, dtype=torch.float32, device=dev)
+    chi = torch.empty(B, dtype=torch.float64, device=dev)
+    q = quad if quad is not None else quad_struct()
+    check(lib().dsmc_harvest_rows(B, _ptr(vr), _ptr(xi), _ptr(z), float(sigma_v), float(b_max),
+                                  float(m_red), C.byref(pot), q, _ptr(x), _ptr(g), _ptr(tgt),
+                                  _ptr(chi), _ptr(st), _stream(stream)),
+          "dsmc_harvest_rows")
+    return x, g, tgt, chi
+
+
+def set_block_threshold(pairs):
+    check(lib().dsmc_set_block_threshold(int(pairs)), "dsmc_set_block_threshold")
+
+
+def get_block_threshold():
+    return int(lib().dsmc_get_block_threshold())

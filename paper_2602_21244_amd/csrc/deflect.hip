@@ -1,0 +1,542 @@
+// Ab initio deflection angle by quadrature of the classical deflection
+// integral (section "Computational Implementation: The Exact vs. Neural
+// Paradigm"), one lane per pair, no cross-lane traffic:
+//   1. E = m_red g^2 / 2; r_min = largest root of D(r) = 1 - b^2/r^2 - V(r)/E,
+//      bracketed by a downward geometric scan (fine steps at low energy, where
+//      D can have several roots) and refined by safeguarded Newton steps.
+//   2. u = r_min / r maps the range to [0, 1]; u = 1 - t^2 removes the
+//      inverse-square-root singularity at u = 1, leaving the smooth integrand
+//      2 t / sqrt(F) with F = beta^2 t^2 (2 - t^2) + (V(r_min) - V(r))/E,
+//      beta = b / r_min, which is integrated by fixed-order Gauss-Legendre.
+//   3. chi = pi - 2 beta * integral.
+// Near r_min the potential difference is formed as -int V' dr (2-point
+// Gauss-Legendre) to avoid cancellation.
+#include <math.h>
+
+#include <string.h>
+
+#include <vector>
+
+#include "collide.hpp"
+
+namespace dsmc {
+
+constexpr int GL_MAX = 128;
+
+struct GLRule {
+    int n;
+    double t[GL_MAX];
+    double w[GL_MAX];
+};
+
+// Potential and the derived quantities a kernel needs.
+struct Pot {
+    dsmc_potential p;
+    double r_sw;     // short-range switch 0.4 R_eps (JAGER)
+    double r_zero;   // largest zero of V (JAGER); V < 0 beyond it
+    double e_scan;   // below this E (K), D may have several roots: fine scan
+    double fact[17]; // 1/k!
+};
+
+struct QuadCfg {
+    int max_iter;
+    double scan_ratio;
+};
+
+// ------------------------------------------------------------------------
+// Potential (T arithmetic)
+// ------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T dexp(T x) { return exp(x); }
+template <>
+__device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
+
+template <typename T>
+__device__ __forceinline__ T V_of(const Pot& P, T r)
+{
+    const dsmc_potential& p = P.p;
+    if (p.kind == DSMC_POT_INVPOW) {
+        T rn = r;
+        for (int q = 1; q < p.n; ++q) rn *= r;
+        return T(p.K) / rn;
+    }
+    if (r < T(P.r_sw)) return T(p.A_sr) / r * dexp<T>(-T(p.a_sr) * r);
+    const T ri = T(1) / r;
+    const T rep = T(p.A) * dexp<T>(T(p.a1) * r + T(p.a2) * r * r + T(p.am1) * ri + T(p.am2) * ri * ri);
+    const T x = T(p.beta_tt) * r;
+    const T ex = dexp<T>(-x);
+    const T ri2 = ri * ri;
+    T rpow = ri2 * ri2 * ri2;  // r^-6
+    T term = T(1), S = T(1), disp = T(0);
+#pragma unroll
+    for (int k = 1; k <= 16; ++k) {
+        term = term * x * T(1.0 / k);  // x^k / k!
+        S += term;
+        if (k >= 6 && (k & 1) == 0) {
+            disp += (T(1) - ex * S) * T(p.C[(k - 6) / 2]) * rpow;
+            rpow *= ri2;
+        }
+    }
+    return rep - disp;
+}
+
+template <typename T>
+__device__ __forceinline__ T dV_of(const Pot& P, T r)
+{
+    const dsmc_potential& p = P.p;
+    if (p.kind == DSMC_POT_INVPOW) {
+        T rn = r;
+        for (int q = 1; q < p.n; ++q) rn *= r;
+        return -T(p.n) * T(p.K) / (rn * r);
+    }
+    const T ri = T(1) / r;
+    if (r < T(P.r_sw)) {
+        const T v = T(p.A_sr) * ri * dexp<T>(-T(p.a_sr) * r);
+        return -v * (T(p.a_sr) + ri);
+    }
+    const T phi_r = T(p.a1) + T(2) * T(p.a2) * r - T(p.am1) * ri * ri - T(2) * T(p.am2) * ri * ri * ri;
+    const T rep = T(p.A) * dexp<T>(T(p.a1) * r + T(p.a2) * r * r + T(p.am1) * ri + T(p.am2) * ri * ri);
+    const T x = T(p.beta_tt) * r;
+    const T ex = dexp<T>(-x);
+    const T ri2 = ri * ri;
+    T rpow = ri2 * ri2 * ri2;
+    T term = T(1), S = T(1), dd = T(0);
+#pragma unroll
+    for (int k = 1; k <= 16; ++k) {
+        term = term * x * T(1.0 / k);  // x^k / k!
+        S += term;
+        if (k >= 6 && (k & 1) == 0) {
+            // d/dr [f_k(beta r) C_k r^-k], f_k'(x) = e^-x x^k / k!
+            dd += T(p.C[(k - 6) / 2]) * (T(p.beta_tt) * ex * term * rpow -
+                                        T(k) * (T(1) - ex * S) * rpow * ri);
+            rpow *= ri2;
+        }
+    }
+    return rep * phi_r - dd;
+}
+
+template <typename T> struct Consts;
+template <> struct Consts<double> {
+    static constexpr double pi = 3.14159265358979323846;
+    static constexpr double rtol = 4e-16;
+};
+template <> struct Consts<float> {
+    static constexpr float pi = 3.14159265358979f;
+    static constexpr float rtol = 2e-7f;
+};
+
+// D(r) = 1 - b^2/r^2 - V(r)/E
+template <typename T>
+__device__ __forceinline__ T D_of(const Pot& P, T b2, T E, T r)
+{
+    return T(1) - b2 / (r * r) - V_of<T>(P, r) / E;
+}
+
+// chi(b, E) with b in Angstrom, E/k_B in K.  Returns NaN if no root is found.
+template <typename T>
+__device__ T chi_quad(const Pot& P, const QuadCfg& q, const GLRule& gl, T b, T E)
+{
+    const T pi = Consts<T>::pi;
+    const T b2 = b * b;
+    T rmin, D0 = T(0);
+    if (P.p.kind == DSMC_POT_HS) {
+        const T d = T(P.p.d);
+        rmin = b > d ? b : d;
+        const T beta = b / rmin;
+        D0 = b > d ? T(0) : T(1) - beta * beta;
+    } else {
+        T rhi;
+        if (P.p.kind == DSMC_POT_JAGER) {
+            rhi = b > T(P.r_zero) ? b : T(P.r_zero);
+        } else {
+            const T rk = pow(T(2) * T(P.p.K) / E, T(1) / T(P.p.n));
+            rhi = T(2) * b > rk ? T(2) * b : rk;
+            if (!(rhi > T(0))) rhi = T(1);
+        }
+        T fhi = D_of<T>(P, b2, E, rhi);
+        if (fhi <= T(0)) {
+            rmin = rhi;
+        } else {
+            const T ratio = (E < T(P.e_scan)) ? T(q.scan_ratio) : T(0.7);
+            T rlo = rhi, flo = fhi;
+            bool found = false;
+            for (int it = 0; it < 4000; ++it) {
+                rlo = rhi * ratio;
+                flo = D_of<T>(P, b2, E, rlo);
+                if (flo <= T(0)) { found = true; break; }
+                rhi = rlo;
+                fhi = flo;
+                if (rlo < T(1e-4)) break;
+            }
+            if (!found) return T(NAN);
+            // safeguarded Newton inside [rlo, rhi], D(rlo) <= 0 < D(rhi)
+            T r = rhi;
+            for (int it = 0; it < q.max_iter; ++it) {
+                const T f = D_of<T>(P, b2, E, r);
+                if (f > T(0)) rhi = r; else rlo = r;
+                const T fp = T(2) * b2 / (r * r * r) - dV_of<T>(P, r) / E;
+                T rn = r - f / fp;
+                if (!(rn > rlo && rn < rhi)) rn = T(0.5) * (rlo + rhi);
+                const T step = rn - r;
+                r = rn;
+                if (fabs(step) <= Consts<T>::rtol * r || rhi - rlo <= Consts<T>::rtol * r) break;
+            }
+            rmin = r;
+        }
+    }
+    const T beta = b / rmin;
+    const T Vmin = (P.p.kind == DSMC_POT_HS) ? T(0) : V_of<T>(P, rmin);
+    const T g1 = T(0.5) - T(0.28867513459481287);  // 2-point Gauss-Legendre on [0,1]
+    const T g2 = T(0.5) + T(0.28867513459481287);
+    T I = T(0);
+    for (int k = 0; k < gl.n; ++k) {
+        const T t = T(gl.t[k]);
+        const T t2 = t * t;
+        const T dr = rmin * t2 / (T(1) - t2);
+        T dV = T(0);
+        if (P.p.kind != DSMC_POT_HS) {
+            if (t2 < T(1e-3))
+                dV = -dr * T(0.5) * (dV_of<T>(P, rmin + g1 * dr) + dV_of<T>(P, rmin + g2 * dr));
+            else
+                dV = Vmin - V_of<T>(P, rmin + dr);
+        }
+        const T F = beta * beta * t2 * (T(2) - t2) + dV / E + D0;
+        if (F > T(0)) I += T(gl.w[k]) * T(2) * t / sqrt(F);
+    }
+    return pi - T(2) * beta * I;
+}
+
+// ------------------------------------------------------------------------
+// Host side: Gauss-Legendre nodes by Newton on P_n, potential set-up.
+// ------------------------------------------------------------------------
+static int make_gl(int n, GLRule* g)
+{
+    if (n == 0) n = 64;
+    if (n < 2 || n > GL_MAX) return arg_error("dsmc_quad: n_nodes %d not in [2, %d]", n, GL_MAX);
+    g->n = n;
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double x = cos(pi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        // recompute derivative at the converged node
+        double p0 = 1.0, p1 = x;
+        for (int k = 2; k <= n; ++k) {
+            const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = pk;
+        }
+        dp = n * (x * p1 - p0) / (x * x - 1.0);
+        // map [-1, 1] -> [0, 1]
+        g->t[i] = 0.5 * (1.0 - x);
+        g->w[i] = 1.0 / ((1.0 - x * x) * dp * dp);  // (2 / ((1-x^2) P'^2)) / 2
+    }
+    return DSMC_OK;
+}
+
+static double host_V(const Pot& P, double r)
+{
+    const dsmc_potential& p = P.p;
+    if (r < P.r_sw) return p.A_sr / r * exp(-p.a_sr * r);
+    double rep = p.A * exp(p.a1 * r + p.a2 * r * r + p.am1 / r + p.am2 / (r * r));
+    double x = p.beta_tt * r, ex = exp(-x), term = 1, S = 1, disp = 0;
+    for (int k = 1; k <= 16; ++k) {
+        term *= x / k;
+        S += term;
+        if (k >= 6 && k % 2 == 0) disp += (1 - ex * S) * p.C[(k - 6) / 2] / pow(r, k);
+    }
+    return rep - disp;
+}
+
+static int make_pot(const dsmc_potential* pot, Pot* P)
+{
+    if (!pot) return arg_error("dsmc potential: null");
+    P->p = *pot;
+    P->fact[0] = 1.0;
+    for (int k = 1; k <= 16; ++k) P->fact[k] = P->fact[k - 1] * k;
+    P->r_sw = 0.0;
+    P->r_zero = 0.0;
+    P->e_scan = 0.0;
+    switch (pot->kind) {
+    case DSMC_POT_HS:
+        if (!(pot->d > 0)) return arg_error("dsmc potential: HS diameter must be > 0");
+        return DSMC_OK;
+    case DSMC_POT_INVPOW:
+        if (pot->n < 1 || pot->n > 12 || !(pot->K >= 0))
+            return arg_error("dsmc potential: INVPOW needs 1 <= n <= 12 and K >= 0");
+        return DSMC_OK;
+    case DSMC_POT_JAGER: {
+        if (!(pot->R_eps > 0) || !(pot->A > 0) || !(pot->beta_tt > 0))
+            return arg_error("dsmc potential: bad JAGER parameters");
+        P->r_sw = 0.4 * pot->R_eps;
+        // largest zero of V: scan in from 50 A, then bisect
+        double hi = 50.0, lo = 50.0;
+        while (host_V(*P, lo) <= 0.0 && lo > 0.05) lo *= 0.99;
+        if (host_V(*P, lo) <= 0.0) return arg_error("dsmc potential: V has no repulsive core");
+        for (int it = 0; it < 200; ++it) {
+            const double m = 0.5 * (lo + hi);
+            if (host_V(*P, m) > 0.0) lo = m; else hi = m;
+        }
+        P->r_zero = hi;
+        // Energy above which r^2 (1 - V(r)/E) is increasing in r on the
+        // outer region (single turning point for every b); below it the root
+        // scan must be fine.  Found on a grid, then doubled for margin.
+        double ecrit = 0.0;
+        for (double E = 1.0; E < 1e5; E *= 1.05) {
+            bool mono = true;
+            double prev = -1e300;
+            for (double r = 0.6 * P->r_zero; r < 40.0; r *= 1.002) {
+                const double B = r * r * (1.0 - host_V(*P, r) / E);
+                if (B < prev) { mono = false; break; }
+                prev = B;
+            }
+            if (mono) { ecrit = E; break; }
+        }
+        P->e_scan = ecrit > 0 ? 2.0 * ecrit : 1e30;
+        return DSMC_OK;
+    }
+    }
+    return arg_error("dsmc potential: kind %d", pot->kind);
+}
+
+// Host-side potential set-up is costly for JAGER (grid search); cache the
+// last one.
+static bool same_pot(const dsmc_potential& a, const dsmc_potential& b)
+{
+    return memcmp(&a, &b, sizeof(a)) == 0;
+}
+
+static int get_pot(const dsmc_potential* pot, Pot* out)
+{
+    static thread_local bool have = false;
+    static thread_local Pot cached;
+    if (have && pot && same_pot(cached.p, *pot)) {
+        *out = cached;
+        return DSMC_OK;
+    }
+    int rc = make_pot(pot, out);
+    if (rc == DSMC_OK) {
+        cached = *out;
+        have = true;
+    }
+    return rc;
+}
+
+static int make_cfg(const dsmc_quad& q, QuadCfg* c, GLRule* gl)
+{
+    c->max_iter = q.max_iter > 0 ? q.max_iter : 60;
+    c->scan_ratio = q.scan_ratio > 0 ? q.scan_ratio : 0.98;
+    if (!(c->scan_ratio > 0.5 && c->scan_ratio < 1.0))
+        return arg_error("dsmc_quad: scan_ratio %g not in (0.5, 1)", c->scan_ratio);
+    return make_gl(q.n_nodes, gl);
+}
+
+constexpr double KB = 1.380649e-23;
+
+// ------------------------------------------------------------------------
+// Kernels
+// ------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_deflect(int64_t n, const T* __restrict__ b, const T* __restrict__ g, T* __restrict__ chi,
+          T half_m_over_k, Pot P, QuadCfg q, GLRule gl, int fold, dsmc_status* st)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const T gg = g[p];
+        const T E = half_m_over_k * gg * gg;
+        T c = chi_quad<T>(P, q, gl, b[p] * T(1e10), E);
+        if (c != c) {
+            if (st) {
+                atomicAdd(&st->root_fail, 1);
+                atomicOr(&st->flags, (uint32_t)DSMC_ST_ROOT_FAIL);
+            }
+        } else if (fold) {
+            c = acos(cos(c));
+        }
+        chi[p] = c;
+    }
+}
+
+// Phase A of the in-step ab initio rule.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_phaseA_jager(int32_t n_cells, PairsView pr, dsmc_rng rng, V3<const T> v, T half_m_over_k,
+               T b_max_A, Pot P, QuadCfg q, GLRule gl, PairBuf<T> out, dsmc_status* st)
+{
+    const int64_t np = pr.total(n_cells);
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = pr.cell[p];
+        const uint32_t a = (uint32_t)(p - pr.off[k]);
+        T xi[3], z[2], u4;
+        pair_latents(rng, a, (uint32_t)k, xi, z, u4);
+        const int32_t i = pr.i[p], j = pr.j[p];
+        const T rx = v.x[i] - v.x[j], ry = v.y[i] - v.y[j], rz = v.z[i] - v.z[j];
+        const T g2 = rx * rx + ry * ry + rz * rz;
+        const T E = half_m_over_k * g2;
+        const T bb = b_max_A * sqrt(u4);  // b^2 / b_max^2 = 1 - exp(-|z|^2/2) = U4
+        T c = chi_quad<T>(P, q, gl, bb, E);
+        if (c != c) {
+            if (st) {
+                atomicAdd(&st->root_fail, 1);
+                atomicOr(&st->flags, (uint32_t)DSMC_ST_ROOT_FAIL);
+            }
+            c = T(0);  // no deflection for a failed evaluation
+        }
+        out.a[p] = cos(c);
+        out.b[p] = sin(c);
+        out.c[p] = xi[0];
+        out.d[p] = xi[1];
+        out.e[p] = xi[2];
+    }
+}
+
+// Harvest rows: targets from the quadrature.
+__global__ void __launch_bounds__(256)
+k_harvest(int64_t B, const double* __restrict__ vr, const double* __restrict__ xi,
+          const double* __restrict__ z, double inv_sv, double b_max_A, double half_m_over_k,
+          Pot P, QuadCfg q, GLRule gl, float* __restrict__ x_out, float* __restrict__ g_out,
+          float* __restrict__ tgt, double* __restrict__ chi_out, dsmc_status* st)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < B;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const double v0 = vr[3 * r], v1 = vr[3 * r + 1], v2 = vr[3 * r + 2];
+        const double x0 = xi[3 * r], x1 = xi[3 * r + 1], x2 = xi[3 * r + 2];
+        const double z0 = z[2 * r], z1 = z[2 * r + 1];
+        double vh[3], e[3];
+        const double g = unit3<double>(v0, v1, v2, vh);
+        const double bt2 = -expm1(-0.5 * (z0 * z0 + z1 * z1));
+        const double bb = b_max_A * sqrt(bt2);
+        double c = chi_quad<double>(P, q, gl, bb, half_m_over_k * g * g);
+        if (c != c) {
+            if (st) {
+                atomicAdd(&st->root_fail, 1);
+                atomicOr(&st->flags, (uint32_t)DSMC_ST_ROOT_FAIL);
+            }
+        }
+        const double xv[3] = {x0, x1, x2};
+        perp_dir<double>(xv, vh, e);
+        const double cc = cos(c), sc = sin(c);
+        for (int d = 0; d < 3; ++d) tgt[3 * r + d] = (float)(g * (cc * vh[d] + sc * e[d]));
+        float* xo = x_out + 8 * r;
+        xo[0] = (float)(v0 * inv_sv); xo[1] = (float)(v1 * inv_sv); xo[2] = (float)(v2 * inv_sv);
+        xo[3] = (float)x0; xo[4] = (float)x1; xo[5] = (float)x2;
+        xo[6] = (float)z0; xo[7] = (float)z1;
+        g_out[r] = (float)g;
+        if (chi_out) chi_out[r] = c;
+    }
+}
+
+}  // namespace dsmc
+
+using namespace dsmc;
+
+extern "C" int dsmc_deflect_jager(int64_t n, int32_t dtype, const void* b, const void* g,
+                                  void* chi, double m_red, const dsmc_potential* pot,
+                                  dsmc_quad quad, int32_t fold, dsmc_status* st,
+                                  dsmc_stream_t stream)
+{
+    if (n < 0) return arg_error("dsmc_deflect_jager: n < 0");
+    if (n > 0 && (!b || !g || !chi)) return arg_error("dsmc_deflect_jager: null pointer");
+    if (!(m_red > 0)) return arg_error("dsmc_deflect_jager: m_red must be > 0");
+    Pot P;
+    int rc = get_pot(pot, &P);
+    if (rc) return rc;
+    QuadCfg q;
+    GLRule gl;
+    rc = make_cfg(quad, &q, &gl);
+    if (rc) return rc;
+    if (n == 0) return DSMC_OK;
+    const double hmk = 0.5 * m_red / KB;
+    hipStream_t s = as_stream(stream);
+    int blocks = (int)((n + 255) / 256);
+    const int pb = persistent_blocks(256);
+    if (blocks > pb) blocks = pb;
+    if (dtype == DSMC_F64) {
+        k_deflect<double><<<blocks, 256, 0, s>>>(n, (const double*)b, (const double*)g,
+                                                 (double*)chi, hmk, P, q, gl, fold, st);
+    } else if (dtype == DSMC_F32) {
+        k_deflect<float><<<blocks, 256, 0, s>>>(n, (const float*)b, (const float*)g, (float*)chi,
+                                                (float)hmk, P, q, gl, fold, st);
+    } else {
+        return arg_error("dsmc_deflect_jager: dtype %d", dtype);
+    }
+    DSMC_LAUNCH_CHECK("deflect_jager");
+    return DSMC_OK;
+}
+
+extern "C" int dsmc_collide_jager(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pairs,
+                                  dsmc_rng rng, double m_red, double b_max,
+                                  const dsmc_potential* pot, dsmc_quad quad, int32_t schedule,
+                                  void* ws, size_t ws_bytes, dsmc_status* st,
+                                  dsmc_stream_t stream)
+{
+    int rc = check_pairs("dsmc_collide_jager", n_cells, v, pairs, dtype, ws, ws_bytes);
+    if (rc) return rc;
+    if (!(m_red > 0) || !(b_max > 0)) return arg_error("dsmc_collide_jager: m_red, b_max > 0");
+    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_BLOCK)
+        return arg_error("dsmc_collide_jager: schedule %d", schedule);
+    Pot P;
+    rc = get_pot(pot, &P);
+    if (rc) return rc;
+    QuadCfg q;
+    GLRule gl;
+    rc = make_cfg(quad, &q, &gl);
+    if (rc) return rc;
+    hipStream_t s = as_stream(stream);
+    const PairsView pr = PairsView::of(pairs);
+    const int pb = persistent_blocks(256);
+    const double hmk = 0.5 * m_red / KB;
+    if (dtype == DSMC_F64) {
+        k_phaseA_jager<double><<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const double>(v), hmk,
+                                                 b_max * 1e10, P, q, gl,
+                                                 PairBuf<double>::of(ws, pairs.cap), st);
+    } else {
+        k_phaseA_jager<float><<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const float>(v), (float)hmk,
+                                                (float)(b_max * 1e10), P, q, gl,
+                                                PairBuf<float>::of(ws, pairs.cap), st);
+    }
+    DSMC_LAUNCH_CHECK("collide_jager:phaseA");
+    return phase_b(RULE_CHI, dtype, n_cells, nullptr, v, pairs, ws, pairs.cap, schedule, s);
+}
+
+extern "C" int dsmc_harvest_rows(int64_t B, const double* vr, const double* xi, const double* z,
+                                 double sigma_v, double b_max, double m_red,
+                                 const dsmc_potential* pot, dsmc_quad quad, float* x_out,
+                                 float* g_out, float* target_out, double* chi_out,
+                                 dsmc_status* st, dsmc_stream_t stream)
+{
+    if (B < 0) return arg_error("dsmc_harvest_rows: B < 0");
+    if (B > 0 && (!vr || !xi || !z || !x_out || !g_out || !target_out))
+        return arg_error("dsmc_harvest_rows: null pointer");
+    if (!(sigma_v > 0) || !(b_max > 0) || !(m_red > 0))
+        return arg_error("dsmc_harvest_rows: sigma_v, b_max, m_red must be > 0");
+    Pot P;
+    int rc = get_pot(pot, &P);
+    if (rc) return rc;
+    QuadCfg q;
+    GLRule gl;
+    rc = make_cfg(quad, &q, &gl);
+    if (rc) return rc;
+    if (B == 0) return DSMC_OK;
+    int blocks = (int)((B + 255) / 256);
+    const int pb = persistent_blocks(256);
+    if (blocks > pb) blocks = pb;
+    k_harvest<<<blocks, 256, 0, as_stream(stream)>>>(B, vr, xi, z, 1.0 / sigma_v, b_max * 1e10,
+                                                     0.5 * m_red / KB, P, q, gl, x_out, g_out,
+                                                     target_out, chi_out, st);
+    DSMC_LAUNCH_CHECK("harvest_rows");
+    return DSMC_OK;
+}

@@ -1,0 +1,943 @@
+// Neural collision operator (sections "Cell-Based Neural Collision Operator"
+// and "Hard Conservation via Projection and Pair Update").
+//
+// BF16 path: one fused kernel evaluates the whole MLP on the matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation) for 32-row tiles per wave.
+// Each layer is computed transposed, D = W * H^T, so a wave's accumulators
+// hold, for its 32 rows, the layer's outputs in the MFMA result layout; after
+// the activation they are converted to bf16 and used directly as the B operand
+// of the next layer.  The weights are staged once per workgroup in LDS in
+// "fragment-major" order (the 64 lanes' 16-byte A fragments contiguous) with
+// the columns permuted to match the register layout of the previous layer's
+// outputs, so no LDS round trip of activations is needed.
+//
+// FP64 (and FP32) reference path: plain per-element kernels, used for parity
+// with the FP64 oracle and for finite-difference gradient checks.
+#include <math.h>
+
+#include "collide.hpp"
+
+namespace dsmc {
+
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float floatx16 __attribute__((__vector_size__(16 * sizeof(float))));
+
+constexpr int MLP_MAX_LAYERS = 6;
+
+struct MlpDev {
+    int L;
+    int dims[MLP_MAX_LAYERS + 1];
+    int act;
+    const void* W[MLP_MAX_LAYERS];
+    const void* b[MLP_MAX_LAYERS];
+    double inv_sigma_v;
+};
+
+static int check_mlp(const dsmc_mlp* net, MlpDev* d)
+{
+    if (!net) return arg_error("dsmc_mlp: null");
+    if (net->n_layers < 1 || net->n_layers > MLP_MAX_LAYERS)
+        return arg_error("dsmc_mlp: n_layers %d not in [1, %d]", net->n_layers, MLP_MAX_LAYERS);
+    if (net->act != DSMC_ACT_SILU && net->act != DSMC_ACT_RELU)
+        return arg_error("dsmc_mlp: act %d", net->act);
+    if (net->wdtype != DSMC_BF16 && net->wdtype != DSMC_F64 && net->wdtype != DSMC_F32)
+        return arg_error("dsmc_mlp: wdtype %d", net->wdtype);
+    d->L = net->n_layers;
+    for (int l = 0; l <= net->n_layers; ++l) {
+        if (net->dims[l] < 1 || net->dims[l] > 256)
+            return arg_error("dsmc_mlp: dims[%d] = %d not in [1, 256]", l, net->dims[l]);
+        d->dims[l] = net->dims[l];
+    }
+    for (int l = 0; l < net->n_layers; ++l) {
+        if (!net->W[l] || !net->b[l]) return arg_error("dsmc_mlp: null W/b of layer %d", l);
+        d->W[l] = net->W[l];
+        d->b[l] = net->b[l];
+    }
+    if (!(net->sigma_v > 0)) return arg_error("dsmc_mlp: sigma_v must be > 0");
+    d->inv_sigma_v = 1.0 / net->sigma_v;
+    d->act = net->act;
+    return DSMC_OK;
+}
+
+// Shape the fused MFMA kernel supports.
+static bool mfma_shape_ok(const MlpDev& d, int* H)
+{
+    if (d.L < 2) return false;
+    const int h = d.dims[1];
+    if (h != 64 && h != 128 && h != 256) return false;
+    for (int l = 1; l < d.L; ++l)
+        if (d.dims[l] != h) return false;
+    if (d.dims[0] > 32 || d.dims[d.L] > 32) return false;
+    *H = h;
+    return true;
+}
+
+__device__ __forceinline__ float act_f(float z, int act)
+{
+    if (act == DSMC_ACT_RELU) return z > 0.f ? z : 0.f;
+    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+
+template <typename T>
+__device__ __forceinline__ T act_t(T z, int act)
+{
+    if (act == DSMC_ACT_RELU) return z > T(0) ? z : T(0);
+    return z / (T(1) + exp(-z));
+}
+template <typename T>
+__device__ __forceinline__ T act_grad_t(T z, int act)
+{
+    if (act == DSMC_ACT_RELU) return z > T(0) ? T(1) : T(0);
+    const T s = T(1) / (T(1) + exp(-z));
+    return s * (T(1) + z * (T(1) - s));
+}
+
+// ------------------------------------------------------------------------
+// Fused BF16 MFMA forward
+// ------------------------------------------------------------------------
+struct FragLayout {
+    int off[MLP_MAX_LAYERS];   // element offset of each layer's fragments in LDS
+    int nb[MLP_MAX_LAYERS];    // 32-row output blocks
+    int ks[MLP_MAX_LAYERS];    // 16-wide k steps
+    int bias_off[MLP_MAX_LAYERS];
+    int total_bf16;
+    int total_bias;
+    size_t bytes;
+};
+
+static FragLayout frag_layout(const MlpDev& d)
+{
+    FragLayout f{};
+    int o = 0, bo = 0;
+    for (int l = 0; l < d.L; ++l) {
+        f.nb[l] = (d.dims[l + 1] + 31) / 32;
+        f.ks[l] = (l == 0) ? ((d.dims[0] + 15) / 16) : (d.dims[l] / 16);
+        f.off[l] = o;
+        o += f.nb[l] * f.ks[l] * 64 * 8;
+        f.bias_off[l] = bo;
+        bo += f.nb[l] * 32;
+    }
+    f.total_bf16 = o;
+    f.total_bias = bo;
+    f.bytes = (size_t)o * 2 + (size_t)bo * 4;
+    return f;
+}
+
+// Column of W feeding element e of lane-half h in k step ks.
+__device__ __forceinline__ int frag_col(int layer, int ks, int h, int e)
+{
+    if (layer == 0) return 16 * ks + 8 * h + e;
+    const int pb = ks >> 1, jp = ks & 1;
+    return pb * 32 + 16 * jp + 8 * (e >> 2) + 4 * h + (e & 3);
+}
+
+__device__ void stage_weights(const MlpDev& d, const FragLayout& f, __bf16* wl, float* bl)
+{
+    for (int l = 0; l < d.L; ++l) {
+        const __bf16* W = static_cast<const __bf16*>(d.W[l]);
+        const float* B = static_cast<const float*>(d.b[l]);
+        const int out = d.dims[l + 1], in = d.dims[l];
+        const int n_el = f.nb[l] * f.ks[l] * 64 * 8;
+        for (int q = threadIdx.x; q < n_el; q += blockDim.x) {
+            const int e = q & 7, lane = (q >> 3) & 63, frag = q >> 9;
+            const int nb = frag / f.ks[l], ks = frag % f.ks[l];
+            const int row = nb * 32 + (lane & 31);
+            const int col = frag_col(l, ks, lane >> 5, e);
+            wl[f.off[l] + q] = (row < out && col < in) ? W[(size_t)row * in + col] : (__bf16)0.0f;
+        }
+        for (int q = threadIdx.x; q < f.nb[l] * 32; q += blockDim.x)
+            bl[f.bias_off[l] + q] = q < out ? B[q] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ bf16x8 lds_frag(const __bf16* wl, int off, int frag, int lane)
+{
+    return *reinterpret_cast<const bf16x8*>(wl + off + (frag * 64 + lane) * 8);
+}
+
+// Row mapping of accumulator register r for lane-half h.
+__device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+__device__ __forceinline__ floatx16 bias_init(const float* bl, int boff, int nb, int h)
+{
+    floatx16 a;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = bl[boff + nb * 32 + acc_row(r, h)];
+    return a;
+}
+
+__device__ __forceinline__ bf16x8 to_frag(const floatx16& a, int jp, int act)
+{
+    bf16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = (__bf16)act_f(a[8 * jp + e], act);
+    return o;
+}
+
+struct RowsIO {
+    const float* x;   // [B][dims0]
+    const float* g;   // [B]
+    float* y_raw;     // [B][dout]
+    float* vr_out;    // [B][3]
+    float* zsave;     // [L-1][B][H] pre-activations, or null
+    int64_t B;
+};
+
+template <typename VT> struct PairsIO {
+    PairsView pr;
+    int32_t n_cells;
+    V3<const VT> v;
+    dsmc_rng rng;
+    PairBuf<VT> out;
+};
+
+// Input fragments of one 32-row tile: lane (row, h) supplies features
+// 16 ks + 8 h + e.  PAIRS mode builds x = [v_r / sigma_v, xi, z] in the
+// lane-half-0 lanes (dims[0] == 8).
+template <int H, bool PAIRS, typename VT>
+__global__ void __launch_bounds__(512)
+k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
+{
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    __bf16* wl = reinterpret_cast<__bf16*>(smem);
+    float* bl = reinterpret_cast<float*>(smem + (size_t)f.total_bf16 * 2);
+    stage_weights(d, f, wl, bl);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
+    const int waves = blockDim.x >> 6;
+    const int64_t nrows = PAIRS ? pio.pr.total(pio.n_cells) : rio.B;
+    const int L = d.L, act = d.act, dout = d.dims[L];
+    constexpr int NB = H / 32, KS = H / 16;
+
+    for (int64_t tile = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); tile * 32 < nrows;
+         tile += (int64_t)gridDim.x * waves) {
+        const int64_t row = tile * 32 + col;
+        const bool valid = row < nrows;
+        bf16x8 bin[2];
+        VT keep_vh[3] = {1, 0, 0}, keep_xi[3] = {0, 0, 0}, keep_u4 = 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bin[q][e] = (__bf16)0.0f;
+        if (PAIRS) {
+            if (h == 0 && valid) {
+                const int32_t k = pio.pr.cell[row];
+                const uint32_t a = (uint32_t)(row - pio.pr.off[k]);
+                VT xi[3], z[2], u4;
+                pair_latents(pio.rng, a, (uint32_t)k, xi, z, u4);
+                const int32_t i = pio.pr.i[row], j = pio.pr.j[row];
+                const VT rx = pio.v.x[i] - pio.v.x[j], ry = pio.v.y[i] - pio.v.y[j],
+                         rz = pio.v.z[i] - pio.v.z[j];
+                unit3<VT>(rx, ry, rz, keep_vh);
+                keep_xi[0] = xi[0]; keep_xi[1] = xi[1]; keep_xi[2] = xi[2];
+                keep_u4 = u4;
+                const VT isv = (VT)d.inv_sigma_v;
+                bin[0][0] = (__bf16)(float)(rx * isv);
+                bin[0][1] = (__bf16)(float)(ry * isv);
+                bin[0][2] = (__bf16)(float)(rz * isv);
+                bin[0][3] = (__bf16)(float)xi[0];
+                bin[0][4] = (__bf16)(float)xi[1];
+                bin[0][5] = (__bf16)(float)xi[2];
+                bin[0][6] = (__bf16)(float)z[0];
+                bin[0][7] = (__bf16)(float)z[1];
+            }
+        } else if (valid) {
+            const int din = d.dims[0];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int c = 16 * q + 8 * h + e;
+                    if (c < din) bin[q][e] = (__bf16)rio.x[row * din + c];
+                }
+        }
+
+        floatx16 acc[NB];
+        bf16x8 bfr[KS];
+        // input layer
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = bias_init(bl, f.bias_off[0], nb, h);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            if (ks >= f.ks[0]) break;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    lds_frag(wl, f.off[0], nb * f.ks[0] + ks, lane), bin[ks], acc[nb], 0, 0, 0);
+        }
+        // hidden layers
+        for (int l = 1; l < L; ++l) {
+            if (rio.zsave && valid) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        rio.zsave[((size_t)(l - 1) * rio.B + row) * H + nb * 32 + acc_row(r, h)] =
+                            acc[nb][r];
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                bfr[2 * nb] = to_frag(acc[nb], 0, act);
+                bfr[2 * nb + 1] = to_frag(acc[nb], 1, act);
+            }
+            if (l == L - 1) break;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[nb] = bias_init(bl, f.bias_off[l], nb, h);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        lds_frag(wl, f.off[l], nb * KS + ks, lane), bfr[ks], acc[nb], 0, 0, 0);
+        }
+        // output layer (<= 32 outputs: one block)
+        floatx16 ao = bias_init(bl, f.bias_off[L - 1], 0, h);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            ao = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lds_frag(wl, f.off[L - 1], ks, lane),
+                                                         bfr[ks], ao, 0, 0, 0);
+        if (!valid) continue;
+        if (!PAIRS) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int n = acc_row(r, h);
+                if (n < dout) rio.y_raw[row * dout + n] = ao[r];
+            }
+        }
+        if (h == 0) {
+            // outputs 0..2 sit in registers 0..2 of lane-half 0
+            const float y0 = ao[0], y1 = ao[1], y2 = ao[2];
+            const float nrm = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+            if (PAIRS) {
+                VT u[3];
+                if (nrm > 1e-30f) {
+                    u[0] = (VT)(y0 / nrm); u[1] = (VT)(y1 / nrm); u[2] = (VT)(y2 / nrm);
+                } else {
+                    // degenerate output: the isotropic direction of this pair
+                    VT e[3];
+                    const VT cc = VT(2) * keep_u4 - VT(1);
+                    const VT sc = VT(2) * dev_sqrt<VT>(keep_u4 * (VT(1) - keep_u4));
+                    perp_dir<VT>(keep_xi, keep_vh, e);
+                    for (int q = 0; q < 3; ++q) u[q] = cc * keep_vh[q] + sc * e[q];
+                }
+                pio.out.a[row] = u[0];
+                pio.out.b[row] = u[1];
+                pio.out.c[row] = u[2];
+            } else if (rio.vr_out && dout == 3) {
+                const float gg = rio.g[row];
+                const float s = nrm > 1e-30f ? gg / nrm : 0.0f;
+                rio.vr_out[3 * row + 0] = y0 * s;
+                rio.vr_out[3 * row + 1] = y1 * s;
+                rio.vr_out[3 * row + 2] = y2 * s;
+            }
+        }
+    }
+}
+
+template <int H, bool PAIRS, typename VT>
+static int launch_mlp_bf16(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
+                           int64_t max_rows, hipStream_t s)
+{
+    auto kern = k_mlp_bf16<H, PAIRS, VT>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return hip_check(e, "mlp: set LDS attribute");
+        attr_set = true;
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    int64_t tiles = (max_rows + 31) / 32;
+    int64_t blocks = (tiles + 7) / 8;
+    if (blocks > cus) blocks = cus;
+    if (blocks < 1) blocks = 1;
+    kern<<<(int)blocks, 512, f.bytes, s>>>(d, f, rio, pio);
+    DSMC_LAUNCH_CHECK("mlp_bf16");
+    return DSMC_OK;
+}
+
+// ------------------------------------------------------------------------
+// Reference path (FP64 / FP32): per-element layer kernels
+// ------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_x_from_pairs(int32_t n_cells, PairsView pr, dsmc_rng rng, V3<const T> v, T inv_sv, T* X)
+{
+    const int64_t np = pr.total(n_cells);
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = pr.cell[p];
+        const uint32_t a = (uint32_t)(p - pr.off[k]);
+        T xi[3], z[2], u4;
+        pair_latents(rng, a, (uint32_t)k, xi, z, u4);
+        const int32_t i = pr.i[p], j = pr.j[p];
+        T* x = X + 8 * p;
+        x[0] = (v.x[i] - v.x[j]) * inv_sv;
+        x[1] = (v.y[i] - v.y[j]) * inv_sv;
+        x[2] = (v.z[i] - v.z[j]) * inv_sv;
+        x[3] = xi[0]; x[4] = xi[1]; x[5] = xi[2];
+        x[6] = z[0]; x[7] = z[1];
+    }
+}
+
+// z = h W^T + b (one thread per output element); h_out = act(z) if hidden.
+template <typename T, typename WT>
+__global__ void __launch_bounds__(256)
+k_layer(const T* __restrict__ hin, int64_t B, const int64_t* nrows_dev, int in, int out,
+        const WT* __restrict__ W, const WT* __restrict__ bias, int act, int hidden,
+        T* __restrict__ z, T* __restrict__ hout)
+{
+    const int64_t nrows = nrows_dev ? *nrows_dev : B;
+    const int64_t n_el = nrows * out;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_el;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = q / out;
+        const int n = (int)(q % out);
+        T acc = (T)bias[n];
+        const T* hr = hin + r * in;
+        const WT* wr = W + (size_t)n * in;
+        for (int k = 0; k < in; ++k) acc += (T)wr[k] * hr[k];
+        if (z) z[q] = acc;
+        if (hidden) hout[q] = act_t<T>(acc, act);
+        else hout[q] = acc;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_project_pairs(int32_t n_cells, PairsView pr, dsmc_rng rng, V3<const T> v, const T* Y, int dout,
+                PairBuf<T> out)
+{
+    const int64_t np = pr.total(n_cells);
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const T y0 = Y[p * dout], y1 = Y[p * dout + 1], y2 = Y[p * dout + 2];
+        const T n = dev_sqrt<T>(y0 * y0 + y1 * y1 + y2 * y2);
+        T u[3];
+        if (n > T(1e-30)) {
+            u[0] = y0 / n; u[1] = y1 / n; u[2] = y2 / n;
+        } else {
+            const int32_t k = pr.cell[p];
+            const uint32_t a = (uint32_t)(p - pr.off[k]);
+            T xi[3], z[2], u4, vh[3], e[3];
+            pair_latents(rng, a, (uint32_t)k, xi, z, u4);
+            const int32_t i = pr.i[p], j = pr.j[p];
+            unit3<T>(v.x[i] - v.x[j], v.y[i] - v.y[j], v.z[i] - v.z[j], vh);
+            const T cc = T(2) * u4 - T(1);
+            const T sc = T(2) * dev_sqrt<T>(u4 * (T(1) - u4));
+            perp_dir<T>(xi, vh, e);
+            for (int q = 0; q < 3; ++q) u[q] = cc * vh[q] + sc * e[q];
+        }
+        out.a[p] = u[0]; out.b[p] = u[1]; out.c[p] = u[2];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_project_rows(int64_t B, const T* __restrict__ Y, int dout, const T* __restrict__ g,
+               T* __restrict__ vr)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < B;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const T y0 = Y[r * dout], y1 = Y[r * dout + 1], y2 = Y[r * dout + 2];
+        const T n = dev_sqrt<T>(y0 * y0 + y1 * y1 + y2 * y2);
+        const T s = n > T(1e-30) ? g[r] / n : T(0);
+        vr[3 * r] = y0 * s; vr[3 * r + 1] = y1 * s; vr[3 * r + 2] = y2 * s;
+    }
+}
+
+__global__ void k_pairs_total(int32_t n_cells, PairsView pr, int64_t* out)
+{
+    *out = pr.total(n_cells);
+}
+
+// Workspace of the reference path: X and two activation buffers.
+static size_t ref_ws_bytes(const MlpDev& d, int64_t rows, size_t es)
+{
+    int wmax = 8;
+    for (int l = 0; l <= d.L; ++l) wmax = wmax > d.dims[l] ? wmax : d.dims[l];
+    return 256 + 3 * align_up(es * (size_t)(rows + 1) * wmax);
+}
+
+template <typename T>
+static int ref_forward(const MlpDev& d, const T* X, int64_t B, const int64_t* nrows_dev, T* buf0,
+                       T* buf1, T* zsave, T* Yout, hipStream_t s)
+{
+    const T* hin = X;
+    T* bufs[2] = {buf0, buf1};
+    int64_t zoff = 0;
+    for (int l = 0; l < d.L; ++l) {
+        const bool hidden = l < d.L - 1;
+        T* hout = hidden ? bufs[l & 1] : Yout;
+        T* z = (hidden && zsave) ? zsave + zoff : nullptr;
+        const int64_t n_el = B * d.dims[l + 1];
+        int blocks = (int)((n_el + 255) / 256);
+        const int pb = persistent_blocks(256);
+        if (blocks > pb) blocks = pb;
+        if (blocks < 1) blocks = 1;
+        k_layer<T, T><<<blocks, 256, 0, s>>>(hin, B, nrows_dev, d.dims[l], d.dims[l + 1],
+                                             static_cast<const T*>(d.W[l]),
+                                             static_cast<const T*>(d.b[l]), d.act, hidden, z, hout);
+        DSMC_LAUNCH_CHECK("mlp_ref:layer");
+        if (hidden) zoff += B * d.dims[l + 1];
+        hin = hout;
+    }
+    return DSMC_OK;
+}
+
+// ------------------------------------------------------------------------
+// Backward (reference arithmetic in T; for the BF16 network T = float and
+// the activations are rounded to bf16 exactly as the forward used them)
+// ------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_project_backward(int64_t B, const T* __restrict__ Y, int dout, const T* __restrict__ g,
+                   const T* __restrict__ G, T* __restrict__ dY)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < B;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const T y0 = Y[r * dout], y1 = Y[r * dout + 1], y2 = Y[r * dout + 2];
+        const T n = dev_sqrt<T>(y0 * y0 + y1 * y1 + y2 * y2);
+        T* o = dY + r * dout;
+        for (int q = 0; q < dout; ++q) o[q] = T(0);
+        if (!(n > T(1e-30))) continue;
+        const T u0 = y0 / n, u1 = y1 / n, u2 = y2 / n;
+        const T G0 = G[3 * r], G1 = G[3 * r + 1], G2 = G[3 * r + 2];
+        const T Gu = G0 * u0 + G1 * u1 + G2 * u2;
+        const T f = g[r] / n;
+        o[0] = f * (G0 - Gu * u0);
+        o[1] = f * (G1 - Gu * u1);
+        o[2] = f * (G2 - Gu * u2);
+    }
+}
+
+// h_{l-1} for layer l's weight gradient: x for l == 0, act(z) otherwise
+// (rounded to bf16 when the network is bf16).
+template <typename T>
+__device__ __forceinline__ T hprev(const T* X, const T* Zp, int64_t r, int k, int in, int l,
+                                   int act, bool bf16)
+{
+    if (l == 0) {
+        const T x = X[r * in + k];
+        return bf16 ? (T)(float)(__bf16)(float)x : x;
+    }
+    const T a = act_t<T>(Zp[r * in + k], act);
+    return bf16 ? (T)(float)(__bf16)(float)a : a;
+}
+
+// Partial sums over row chunks: part[c][n][k] = sum_{r in chunk c} dY[r][n] h[r][k],
+// partb[c][n] = sum dY[r][n].  One thread per (n, k) of one chunk.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_dw_partial(int64_t B, int64_t chunk, const T* __restrict__ dY, int out, const T* __restrict__ X,
+             const T* __restrict__ Zp, int in, int l, int act, int bf16, T* __restrict__ part,
+             T* __restrict__ partb)
+{
+    const int64_t c = blockIdx.y;
+    const int64_t r0 = c * chunk, r1 = (r0 + chunk < B) ? r0 + chunk : B;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < out * (in + 1);
+         q += gridDim.x * blockDim.x) {
+        const int n = q / (in + 1), k = q % (in + 1);
+        T acc = T(0);
+        if (k < in) {
+            for (int64_t r = r0; r < r1; ++r)
+                acc += dY[r * out + n] * hprev<T>(X, Zp, r, k, in, l, act, bf16 != 0);
+            part[(c * out + n) * (size_t)in + k] = acc;
+        } else {
+            for (int64_t r = r0; r < r1; ++r) acc += dY[r * out + n];
+            partb[c * out + n] = acc;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_dw_reduce(int64_t n_chunks, const T* __restrict__ part, const T* __restrict__ partb, int out,
+            int in, T* __restrict__ dW, T* __restrict__ db, int accumulate)
+{
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < out * (in + 1);
+         q += gridDim.x * blockDim.x) {
+        const int n = q / (in + 1), k = q % (in + 1);
+        T acc = T(0);
+        if (k < in) {
+            for (int64_t c = 0; c < n_chunks; ++c) acc += part[(c * out + n) * (size_t)in + k];
+            const size_t o = (size_t)n * in + k;
+            dW[o] = accumulate ? dW[o] + acc : acc;
+        } else {
+            for (int64_t c = 0; c < n_chunks; ++c) acc += partb[c * out + n];
+            db[n] = accumulate ? db[n] + acc : acc;
+        }
+    }
+}
+
+// dH[r][k] = sum_n dY[r][n] W[n][k] (times act'(z) for hidden layers).
+template <typename T, typename WT>
+__global__ void __launch_bounds__(256)
+k_delta_prev(int64_t B, const T* __restrict__ dY, int out, const WT* __restrict__ W, int in,
+             const T* __restrict__ Zp, int act, int apply_act, T* __restrict__ dH)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < B * in;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = q / in;
+        const int k = (int)(q % in);
+        T acc = T(0);
+        for (int n = 0; n < out; ++n) acc += dY[r * out + n] * (T)W[(size_t)n * in + k];
+        if (apply_act) acc *= act_grad_t<T>(Zp[q], act);
+        dH[q] = acc;
+    }
+}
+
+template <typename T, typename WT>
+static int backward_impl(const MlpDev& d, int64_t B, const T* X, const T* Z, const T* Y,
+                         const T* g, const T* G, T* const* dW, T* const* db, T* dx, int accumulate,
+                         bool bf16, void* ws, hipStream_t s)
+{
+    int wmax = 8;
+    for (int l = 0; l <= d.L; ++l) wmax = wmax > d.dims[l] ? wmax : d.dims[l];
+    const int64_t chunk = 2048;
+    const int64_t n_chunks = (B + chunk - 1) / chunk;
+    uint8_t* w = static_cast<uint8_t*>(ws);
+    T* dA = reinterpret_cast<T*>(w);
+    w += align_up(sizeof(T) * (size_t)B * wmax);
+    T* dB = reinterpret_cast<T*>(w);
+    w += align_up(sizeof(T) * (size_t)B * wmax);
+    T* part = reinterpret_cast<T*>(w);
+    w += align_up(sizeof(T) * (size_t)n_chunks * wmax * wmax);
+    T* partb = reinterpret_cast<T*>(w);
+    const int pb = persistent_blocks(256);
+    auto grid1 = [&](int64_t n) {
+        int64_t b = (n + 255) / 256;
+        return (int)(b < 1 ? 1 : (b > pb ? pb : b));
+    };
+    const int dout = d.dims[d.L];
+    k_project_backward<T><<<grid1(B), 256, 0, s>>>(B, Y, dout, g, G, dA);
+    DSMC_LAUNCH_CHECK("mlp_bwd:project");
+    // z offsets of hidden layers
+    int64_t zoff[MLP_MAX_LAYERS] = {0};
+    for (int l = 1; l < d.L; ++l) zoff[l] = zoff[l - 1] + B * d.dims[l];
+    T* cur = dA;
+    T* nxt = dB;
+    for (int l = d.L - 1; l >= 0; --l) {
+        const int out = d.dims[l + 1], in = d.dims[l];
+        const T* Zp = (l > 0) ? Z + zoff[l - 1] : nullptr;
+        dim3 gp((unsigned)((out * (in + 1) + 255) / 256), (unsigned)n_chunks);
+        k_dw_partial<T><<<gp, 256, 0, s>>>(B, chunk, cur, out, X, Zp, in, l, d.act, bf16, part,
+                                           partb);
+        DSMC_LAUNCH_CHECK("mlp_bwd:dw_partial");
+        k_dw_reduce<T><<<grid1(out * (in + 1)), 256, 0, s>>>(n_chunks, part, partb, out, in, dW[l],
+                                                             db[l], accumulate);
+        DSMC_LAUNCH_CHECK("mlp_bwd:dw_reduce");
+        if (l > 0 || dx) {
+            T* target = (l > 0) ? nxt : dx;
+            k_delta_prev<T, WT><<<grid1(B * in), 256, 0, s>>>(
+                B, cur, out, static_cast<const WT*>(d.W[l]), in, Zp, d.act, l > 0, target);
+            DSMC_LAUNCH_CHECK("mlp_bwd:delta");
+            if (l > 0) {
+                T* t = cur;
+                cur = nxt;
+                nxt = t;
+            }
+        }
+    }
+    return DSMC_OK;
+}
+
+static size_t backward_ws_bytes(const MlpDev& d, int64_t B, size_t es)
+{
+    int wmax = 8;
+    for (int l = 0; l <= d.L; ++l) wmax = wmax > d.dims[l] ? wmax : d.dims[l];
+    const int64_t n_chunks = (B + 2047) / 2048;
+    return 256 + 2 * align_up(es * (size_t)B * wmax) + align_up(es * (size_t)n_chunks * wmax * wmax) +
+           align_up(es * (size_t)n_chunks * wmax);
+}
+
+// ------------------------------------------------------------------------
+// Training helpers
+// ------------------------------------------------------------------------
+// Single workgroup: gradient and the loss sum in a fixed order (deterministic).
+__global__ void __launch_bounds__(1024)
+k_mse(int64_t B, const float* __restrict__ a, const float* __restrict__ t, double scale,
+      float* __restrict__ grad, double* loss)
+{
+    __shared__ double red[16];
+    double acc = 0.0;
+    for (int64_t q = threadIdx.x; q < 3 * B; q += blockDim.x) {
+        const double dd = (double)a[q] - (double)t[q];
+        acc += dd * dd;
+        grad[q] = (float)(2.0 * scale * dd);
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
+        *loss += sum * scale;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_adam(int64_t n, float* __restrict__ p, __bf16* __restrict__ pb, const float* __restrict__ g,
+       float* __restrict__ m, float* __restrict__ v, float b1, float b2, float lr_c, float eps_c,
+       float bc2_sqrt)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const float gg = g[q];
+        const float mm = b1 * m[q] + (1.0f - b1) * gg;
+        const float vv = b2 * v[q] + (1.0f - b2) * gg * gg;
+        m[q] = mm;
+        v[q] = vv;
+        // bias-corrected step: lr m_hat / (sqrt(v_hat) + eps), folded as
+        // (lr / (1-b1^t)) m / (sqrt(v) / sqrt(1-b2^t) + eps)
+        const float np = p[q] - lr_c * mm / (sqrtf(vv) / bc2_sqrt + eps_c);
+        p[q] = np;
+        if (pb) pb[q] = (__bf16)np;
+    }
+}
+
+}  // namespace dsmc
+
+using namespace dsmc;
+
+// ------------------------------------------------------------------------
+// C-ABI
+// ------------------------------------------------------------------------
+static size_t neural_ws_extra(const MlpDev& d, int64_t cap, int dtype)
+{
+    return 256 + ref_ws_bytes(d, cap, dtype == DSMC_F64 ? 8 : 4);
+}
+
+extern "C" int dsmc_neural_collide(const dsmc_mlp* net, int32_t n_cells, int32_t dtype,
+                                   dsmc_vec3 v, dsmc_pairs pairs, dsmc_rng rng, int32_t schedule,
+                                   void* ws, size_t ws_bytes, dsmc_status* st,
+                                   dsmc_stream_t stream)
+{
+    (void)st;
+    MlpDev d;
+    int rc = check_mlp(net, &d);
+    if (rc) return rc;
+    rc = check_pairs("dsmc_neural_collide", n_cells, v, pairs, dtype, ws, ws_bytes);
+    if (rc) return rc;
+    if (d.dims[0] != 8 || d.dims[d.L] != 3)
+        return arg_error("dsmc_neural_collide: network must map 8 inputs to 3 outputs");
+    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_BLOCK)
+        return arg_error("dsmc_neural_collide: schedule %d", schedule);
+    hipStream_t s = as_stream(stream);
+    const PairsView pr = PairsView::of(pairs);
+    const size_t dir_bytes = dsmc_collide_ws(pairs.cap, dtype);
+    if (net->wdtype == DSMC_BF16) {
+        int H;
+        if (!mfma_shape_ok(d, &H))
+            return DSMC_E_UNSUPPORTED + 0 * arg_error("dsmc_neural_collide: bf16 shape unsupported");
+        const FragLayout f = frag_layout(d);
+        RowsIO rio{};
+        if (dtype == DSMC_F64) {
+            PairsIO<double> pio{pr, n_cells, v3<const double>(v), rng, PairBuf<double>::of(ws, pairs.cap)};
+            if (H == 128) rc = launch_mlp_bf16<128, true, double>(d, f, rio, pio, pairs.cap, s);
+            else if (H == 64) rc = launch_mlp_bf16<64, true, double>(d, f, rio, pio, pairs.cap, s);
+            else rc = launch_mlp_bf16<256, true, double>(d, f, rio, pio, pairs.cap, s);
+        } else {
+            PairsIO<float> pio{pr, n_cells, v3<const float>(v), rng, PairBuf<float>::of(ws, pairs.cap)};
+            if (H == 128) rc = launch_mlp_bf16<128, true, float>(d, f, rio, pio, pairs.cap, s);
+            else if (H == 64) rc = launch_mlp_bf16<64, true, float>(d, f, rio, pio, pairs.cap, s);
+            else rc = launch_mlp_bf16<256, true, float>(d, f, rio, pio, pairs.cap, s);
+        }
+        if (rc) return rc;
+    } else {
+        // reference path in the velocity dtype (weights must match it)
+        if ((dtype == DSMC_F64) != (net->wdtype == DSMC_F64))
+            return arg_error("dsmc_neural_collide: reference path needs wdtype == dtype");
+        if (ws_bytes < dir_bytes + neural_ws_extra(d, pairs.cap, dtype))
+            return arg_error("dsmc_neural_collide: workspace too small for the reference path "
+                             "(need dsmc_collide_ws + dsmc_neural_act_bytes(net, cap))");
+        uint8_t* w = static_cast<uint8_t*>(ws) + dir_bytes;
+        int wmax = 8;
+        for (int l = 0; l <= d.L; ++l) wmax = wmax > d.dims[l] ? wmax : d.dims[l];
+        const size_t es = dtype == DSMC_F64 ? 8 : 4;
+        int64_t* nrows = reinterpret_cast<int64_t*>(w);
+        w += 256;
+        void* X = w;
+        w += align_up(es * (size_t)(pairs.cap + 1) * wmax);
+        void* b0 = w;
+        w += align_up(es * (size_t)(pairs.cap + 1) * wmax);
+        void* b1 = w;
+        const int pb = persistent_blocks(256);
+        k_pairs_total<<<1, 1, 0, s>>>(n_cells, pr, nrows);
+        DSMC_LAUNCH_CHECK("neural:total");
+        if (dtype == DSMC_F64) {
+            k_x_from_pairs<double><<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const double>(v),
+                                                      d.inv_sigma_v, (double*)X);
+            DSMC_LAUNCH_CHECK("neural:x");
+            rc = ref_forward<double>(d, (double*)X, pairs.cap, nrows, (double*)b0, (double*)b1,
+                                     nullptr, (double*)X, s);
+            if (rc) return rc;
+            k_project_pairs<double><<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const double>(v),
+                                                       (double*)X, 3,
+                                                       PairBuf<double>::of(ws, pairs.cap));
+        } else {
+            k_x_from_pairs<float><<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const float>(v),
+                                                     (float)d.inv_sigma_v, (float*)X);
+            DSMC_LAUNCH_CHECK("neural:x");
+            rc = ref_forward<float>(d, (float*)X, pairs.cap, nrows, (float*)b0, (float*)b1, nullptr,
+                                    (float*)X, s);
+            if (rc) return rc;
+            k_project_pairs<float><<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const float>(v),
+                                                      (float*)X, 3, PairBuf<float>::of(ws, pairs.cap));
+        }
+        DSMC_LAUNCH_CHECK("neural:project");
+    }
+    return phase_b(RULE_DIR, dtype, n_cells, nullptr, v, pairs, ws, pairs.cap, schedule, s);
+}
+
+extern "C" size_t dsmc_neural_act_bytes(const dsmc_mlp* net, int64_t B)
+{
+    MlpDev d;
+    if (check_mlp(net, &d) != DSMC_OK || B < 0) return 0;
+    size_t n = 0;
+    for (int l = 1; l < d.L; ++l) n += (size_t)B * d.dims[l];
+    const size_t es = net->wdtype == DSMC_F64 ? 8 : 4;
+    // hidden pre-activations, plus (reference path) X copy and two buffers
+    return 256 + align_up(es * n) + ref_ws_bytes(d, B, es);
+}
+
+extern "C" int dsmc_neural_forward_rows(const dsmc_mlp* net, int64_t B, const void* x,
+                                        const void* g, void* y_raw, void* vr_out, void* act_save,
+                                        size_t act_bytes, dsmc_stream_t stream)
+{
+    MlpDev d;
+    int rc = check_mlp(net, &d);
+    if (rc) return rc;
+    if (B < 0 || (B > 0 && (!x || !g || !y_raw)))
+        return arg_error("dsmc_neural_forward_rows: bad arguments");
+    if (B == 0) return DSMC_OK;
+    hipStream_t s = as_stream(stream);
+    size_t nz = 0;
+    for (int l = 1; l < d.L; ++l) nz += (size_t)B * d.dims[l];
+    if (net->wdtype == DSMC_BF16) {
+        int H;
+        if (!mfma_shape_ok(d, &H)) return DSMC_E_UNSUPPORTED + 0 * arg_error("bf16 shape unsupported");
+        if (act_save && act_bytes < dsmc_neural_act_bytes(net, B))
+            return arg_error("dsmc_neural_forward_rows: act_save too small");
+        const FragLayout f = frag_layout(d);
+        RowsIO rio{(const float*)x, (const float*)g, (float*)y_raw, (float*)vr_out,
+                   act_save ? (float*)act_save : nullptr, B};
+        PairsIO<float> pio{};
+        if (H == 128) rc = launch_mlp_bf16<128, false, float>(d, f, rio, pio, B, s);
+        else if (H == 64) rc = launch_mlp_bf16<64, false, float>(d, f, rio, pio, B, s);
+        else rc = launch_mlp_bf16<256, false, float>(d, f, rio, pio, B, s);
+        return rc;
+    }
+    // reference path: needs act_save as scratch
+    if (!act_save || act_bytes < dsmc_neural_act_bytes(net, B))
+        return arg_error("dsmc_neural_forward_rows: reference path needs act_save of "
+                         "dsmc_neural_act_bytes(net, B)");
+    const size_t es = net->wdtype == DSMC_F64 ? 8 : 4;
+    uint8_t* w = static_cast<uint8_t*>(act_save);
+    void* Z = w;
+    w += align_up(es * nz) + 256;
+    int wmax = 8;
+    for (int l = 0; l <= d.L; ++l) wmax = wmax > d.dims[l] ? wmax : d.dims[l];
+    void* b0 = w + 256;
+    void* b1 = (uint8_t*)b0 + align_up(es * (size_t)(B + 1) * wmax);
+    const int pb = persistent_blocks(256);
+    int blocks = (int)((B + 255) / 256);
+    blocks = blocks > pb ? pb : blocks;
+    if (net->wdtype == DSMC_F64) {
+        rc = ref_forward<double>(d, (const double*)x, B, nullptr, (double*)b0, (double*)b1,
+                                 (double*)Z, (double*)y_raw, s);
+        if (rc) return rc;
+        if (vr_out && d.dims[d.L] == 3) {
+            k_project_rows<double><<<blocks, 256, 0, s>>>(B, (const double*)y_raw, 3,
+                                                          (const double*)g, (double*)vr_out);
+            DSMC_LAUNCH_CHECK("forward_rows:project");
+        }
+    } else {
+        rc = ref_forward<float>(d, (const float*)x, B, nullptr, (float*)b0, (float*)b1, (float*)Z,
+                                (float*)y_raw, s);
+        if (rc) return rc;
+        if (vr_out && d.dims[d.L] == 3) {
+            k_project_rows<float><<<blocks, 256, 0, s>>>(B, (const float*)y_raw, 3,
+                                                         (const float*)g, (float*)vr_out);
+            DSMC_LAUNCH_CHECK("forward_rows:project");
+        }
+    }
+    return DSMC_OK;
+}
+
+extern "C" size_t dsmc_neural_backward_ws(const dsmc_mlp* net, int64_t B)
+{
+    MlpDev d;
+    if (check_mlp(net, &d) != DSMC_OK || B < 0) return 0;
+    return backward_ws_bytes(d, B, net->wdtype == DSMC_F64 ? 8 : 4);
+}
+
+extern "C" int dsmc_neural_backward(const dsmc_mlp* net, int64_t B, const void* x,
+                                    const void* act_save, const void* y_raw, const void* g,
+                                    const void* dL_dvr, void* const* dW, void* const* db, void* dx,
+                                    int32_t accumulate, void* ws, size_t ws_bytes,
+                                    dsmc_stream_t stream)
+{
+    MlpDev d;
+    int rc = check_mlp(net, &d);
+    if (rc) return rc;
+    if (B < 1 || !x || !act_save || !y_raw || !g || !dL_dvr || !dW || !db || !ws)
+        return arg_error("dsmc_neural_backward: bad arguments");
+    if (d.dims[d.L] != 3) return arg_error("dsmc_neural_backward: network must have 3 outputs");
+    for (int l = 0; l < d.L; ++l)
+        if (!dW[l] || !db[l]) return arg_error("dsmc_neural_backward: null dW/db %d", l);
+    if (ws_bytes < dsmc_neural_backward_ws(net, B))
+        return arg_error("dsmc_neural_backward: workspace too small");
+    hipStream_t s = as_stream(stream);
+    if (net->wdtype == DSMC_F64) {
+        return backward_impl<double, double>(d, B, (const double*)x, (const double*)act_save,
+                                             (const double*)y_raw, (const double*)g,
+                                             (const double*)dL_dvr, (double* const*)dW,
+                                             (double* const*)db, (double*)dx, accumulate, false, ws,
+                                             s);
+    }
+    if (net->wdtype == DSMC_BF16) {
+        return backward_impl<float, __bf16>(d, B, (const float*)x, (const float*)act_save,
+                                            (const float*)y_raw, (const float*)g,
+                                            (const float*)dL_dvr, (float* const*)dW,
+                                            (float* const*)db, (float*)dx, accumulate, true, ws, s);
+    }
+    return backward_impl<float, float>(d, B, (const float*)x, (const float*)act_save,
+                                       (const float*)y_raw, (const float*)g, (const float*)dL_dvr,
+                                       (float* const*)dW, (float* const*)db, (float*)dx, accumulate,
+                                       false, ws, s);
+}
+
+extern "C" int dsmc_mse_loss(int64_t B, const float* vr_new, const float* vr_target,
+                             double sigma_v, float* dL_dvr, double* loss, dsmc_stream_t stream)
+{
+    if (B < 1 || !vr_new || !vr_target || !dL_dvr || !loss || !(sigma_v > 0))
+        return arg_error("dsmc_mse_loss: bad arguments");
+    const double scale = 1.0 / (4.0 * sigma_v * sigma_v * (double)B);
+    k_mse<<<1, 1024, 0, as_stream(stream)>>>(B, vr_new, vr_target, scale, dL_dvr, loss);
+    DSMC_LAUNCH_CHECK("mse");
+    return DSMC_OK;
+}
+
+extern "C" int dsmc_adam_step(int64_t n, float* param, void* param_bf16, const float* grad,
+                              float* m, float* v, int64_t t, double lr, double beta1, double beta2,
+                              double eps, dsmc_stream_t stream)
+{
+    if (n < 0 || (n > 0 && (!param || !grad || !m || !v)) || t < 1)
+        return arg_error("dsmc_adam_step: bad arguments");
+    if (n == 0) return DSMC_OK;
+    const double bc1 = 1.0 - pow(beta1, (double)t);
+    const double bc2 = 1.0 - pow(beta2, (double)t);
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    k_adam<<<blocks, 256, 0, as_stream(stream)>>>(n, param, (__bf16*)param_bf16, grad, m, v,
+                                                  (float)beta1, (float)beta2, (float)(lr / bc1),
+                                                  (float)eps, (float)sqrt(bc2));
+    DSMC_LAUNCH_CHECK("adam");
+    return DSMC_OK;
+}

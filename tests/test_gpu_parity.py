@@ -1,0 +1,475 @@
+"""GPU parity of the HIP path against the CPU FP64 oracle, through the C-ABI.
+
+Integer outputs (sort permutation, cell offsets, pair lists) must be
+bit-exact; FP64 velocities agree to 1e-12 and FP32 to 1e-5, relative to the
+thermal scale; the BF16 surrogate agrees with FP64 inference of the same
+weights to a chi RMS <= 1e-2 rad.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_21244_amd import _lib
+    _lib.load()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def api(dev):
+    from paper_2602_21244_amd import api as A
+    return A
+
+
+def _gpu_sort(api, dev, pop, dtype=torch.float64):
+    cell_of = torch.as_tensor(pop.cell_of, device=dev)
+    v = torch.as_tensor(pop.v, dtype=dtype, device=dev).contiguous()
+    st = api.new_status(dev)
+    cs, perm, vs = api.sort_cells(cell_of, pop.n_cells, v, st=st)
+    return cs, perm, vs, st
+
+
+def _thermal(T=300.0):
+    return math.sqrt(W.KB * T / W.AR_MASS)
+
+
+# ---------------------------------------------------------------------------
+# sort
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["c1", "ragged", "bigcells", "empty_tail", "bad_ids", "f32"])
+def test_sort_bitexact(orc, dev, api, case):
+    say("sort case", case)
+    dtype = torch.float64
+    if case == "c1":
+        pop = W.vhs_argon_1d(seed=1)
+    elif case == "ragged":
+        pop = W.ragged_population(3, 500, 90)
+    elif case == "bigcells":
+        # cells above the one-wave LDS limit (1024) and several thousand
+        pop = W.ragged_population(4, 6, 5000, empty_frac=0.0)
+    elif case == "empty_tail":
+        pop = W.ragged_population(5, 300, 40)
+        pop.cell_of = np.minimum(pop.cell_of, 150).astype(np.int32)
+    elif case == "bad_ids":
+        pop = W.ragged_population(6, 100, 40)
+        pop.cell_of = pop.cell_of.copy()
+        pop.cell_of[::97] = -3
+        pop.cell_of[5::211] = pop.n_cells + 7
+    else:
+        pop = W.cavity_grid(seed=3, nx=60, ny=50)
+        dtype = torch.float32
+    cs, perm, vs, st = _gpu_sort(api, dev, pop, dtype)
+    ocs, operm, bad = orc.sort_cells(pop.cell_of, pop.n_cells)
+    kept = int(ocs[-1])
+    assert np.array_equal(cs.cpu().numpy(), ocs)
+    assert np.array_equal(perm[:kept].cpu().numpy(), operm)
+    vnp = pop.v.astype(np.float32 if dtype == torch.float32 else np.float64)
+    assert np.array_equal(vs[:, :kept].cpu().numpy(), vnp[:, operm])
+    s = api.read_status(st)
+    assert s.bad_cell == bad
+    assert bool(s.flags & api.L.ST_BAD_CELL) == (bad > 0)
+
+
+# ---------------------------------------------------------------------------
+# moments, selection
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_moments_capture(orc, dev, api, dtype):
+    say("moments capture", dtype)
+    pop = W.ragged_population(7, 400, 120)
+    cs, perm, vs, _ = _gpu_sort(api, dev, pop, dtype)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, vs, mom, api.L.MM_CAPTURE)
+    ref = orc.moments(cs.cpu().numpy(), vs.cpu().numpy().astype(np.float64))
+    got = mom.cpu().numpy().reshape(-1, 6)
+    scale = np.maximum(np.abs(ref), 1.0)
+    assert np.max(np.abs(got - ref) / scale) < 1e-12
+
+
+def _select_case(orc, dev, api, pop, dtype, seed=11, step=3, cap=None):
+    cs, perm, vs, st = _gpu_sort(api, dev, pop, dtype)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, vs, mom, api.L.MM_CAPTURE)
+    lam = torch.as_tensor(pop.lam, device=dev)
+    v64 = vs.cpu().numpy().astype(np.float64)
+    ocs = cs.cpu().numpy()
+    omom = mom.cpu().numpy().reshape(-1, 6)
+    sel = orc.select_ntc(ocs, v64, pop.xs, pop.lam, omom, seed, step)
+    if cap is None:
+        cap = int(sel["n_cand"]) + 64
+    pairs = api.PairList(pop.n_cells, cap, dev)
+    api.select_pairs_ntc(cs, vs, pop.xs, lam, mom, seed, step, pairs, st=st)
+    return cs, vs, mom, pairs, st, sel, v64
+
+
+@pytest.mark.parametrize("case", ["vhs64", "vhs32", "const64", "cavity32"])
+def test_select_bitexact(orc, dev, api, case):
+    say("select case", case)
+    if case == "vhs64":
+        pop, dt = W.vhs_argon_1d(seed=1), torch.float64
+    elif case == "vhs32":
+        pop, dt = W.ragged_population(8, 300, 150), torch.float32
+    elif case == "const64":
+        pop, dt = W.ragged_population(9, 200, 200, xs="const"), torch.float64
+    else:
+        pop, dt = W.cavity_grid(seed=3, nx=80, ny=80), torch.float32
+    cs, vs, mom, pairs, st, sel, _ = _select_case(orc, dev, api, pop, dt)
+    s = api.read_status(st)
+    n = int(sel["pair_cnt"].sum())
+    assert s.n_cand == sel["n_cand"] and s.n_pairs == n
+    assert np.array_equal(pairs.cnt.cpu().numpy(), sel["pair_cnt"])
+    assert np.array_equal(pairs.off.cpu().numpy(), sel["pair_off"])
+    for name in ("i", "j", "cell"):
+        assert np.array_equal(getattr(pairs, name)[:n].cpu().numpy(), sel["pair_" + name]), name
+
+
+def test_select_overflow(orc, dev, api):
+    say("select overflow")
+    pop = W.ragged_population(10, 100, 60)
+    cs, vs, mom, pairs, st, sel, _ = _select_case(orc, dev, api, pop, torch.float64, cap=10)
+    s = api.read_status(st)
+    assert s.flags & api.L.ST_PAIR_OVERFLOW
+    assert s.n_cand == sel["n_cand"] and s.n_pairs == 0
+    assert int(pairs.cnt.sum()) == 0
+
+
+# ---------------------------------------------------------------------------
+# isotropic collide + moment matching
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("sched", ["auto", "lane", "block"])
+def test_collide_vhs_parity(orc, dev, api, dtype, sched):
+    say("collide_vhs", dtype, sched)
+    pop = W.ragged_population(12, 300, 260)
+    cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, dtype, seed=5, step=1)
+    code = {"auto": api.L.SCHED_AUTO, "lane": api.L.SCHED_LANE, "block": api.L.SCHED_BLOCK}[sched]
+    vn = vs.clone()
+    api.collide_vhs(vn, pairs, 5, 1, schedule=code)
+    ocs = cs.cpu().numpy()
+    lowp = dtype == torch.float32
+    ref, info = orc.step(ocs, v64, pop.xs, pop.lam, 5, 1, rule="vhs", lowp=lowp, match=False)
+    got = vn.cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(got - ref)) / _thermal()
+    tol = 1e-5 if lowp else 1e-12
+    assert err < tol, err
+    # moment matching on top (conserving step -> alpha = 1 to round-off)
+    api.moment_match(cs, vn, mom, api.L.MM_APPLY, pair_cnt=pairs.cnt, st=st)
+    ref2, _ = orc.moment_match(ocs, mom.cpu().numpy().reshape(-1, 6), sel["pair_cnt"], ref)
+    err2 = np.max(np.abs(vn.cpu().numpy().astype(np.float64) - ref2)) / _thermal()
+    assert err2 < tol, err2
+
+
+def test_schedules_bit_identical(dev, api):
+    say("schedules bit-identical")
+    pop = W.ragged_population(13, 200, 900, empty_frac=0.1)
+    out = []
+    for code in (api.L.SCHED_LANE, api.L.SCHED_BLOCK, api.L.SCHED_AUTO):
+        cell_of = torch.as_tensor(pop.cell_of, device=dev)
+        v = torch.as_tensor(pop.v, device=dev).contiguous()
+        cs, perm, vs = api.sort_cells(cell_of, pop.n_cells, v)
+        mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+        api.moment_match(cs, vs, mom, api.L.MM_CAPTURE)
+        pairs = api.PairList(pop.n_cells, 1 << 20, dev)
+        api.select_pairs_ntc(cs, vs, pop.xs, torch.as_tensor(pop.lam, device=dev), mom, 3, 9, pairs)
+        api.collide_vhs(vs, pairs, 3, 9, schedule=code)
+        out.append(vs.cpu().numpy())
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_moment_match_apply_modes(orc, dev, api, dtype):
+    say("moment match modes", dtype)
+    pop = W.ragged_population(14, 200, 80)
+    cs, perm, vs, st = _gpu_sort(api, dev, pop, dtype)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, vs, mom, api.L.MM_CAPTURE)
+    rng = np.random.default_rng(1)
+    pert = rng.uniform(0.8, 1.2, size=tuple(vs.shape))
+    vp = (vs.double().cpu().numpy() * pert + 5.0)
+    cnt = np.ones(pop.n_cells, np.int32)
+    cnt[::5] = 0
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    for mode, centred in ((api.L.MM_APPLY, True), (api.L.MM_APPLY_LITERAL, False)):
+        vt = torch.as_tensor(vp, dtype=dtype, device=dev).contiguous()
+        api.moment_match(cs, vt, mom, mode, pair_cnt=torch.as_tensor(cnt, device=dev), st=st)
+        ref, _ = orc.moment_match(cs.cpu().numpy(), mom.cpu().numpy().reshape(-1, 6), cnt,
+                                  vt.new_tensor(vp).cpu().numpy().astype(np.float64), centred)
+        err = np.max(np.abs(vt.cpu().numpy().astype(np.float64) - ref)) / _thermal()
+        assert err < tol, (mode, err)
+
+
+# ---------------------------------------------------------------------------
+# deflection angle
+# ---------------------------------------------------------------------------
+def test_deflect_closed_forms(dev, api):
+    say("deflect closed forms")
+    b = torch.linspace(0.0, 6e-10, 257, dtype=torch.float64, device=dev)
+    g = torch.full_like(b, 700.0)
+    chi = api.deflect_jager(b, g, W.AR_MASS / 2, api.potential_hs(3.0))
+    ref = 2 * np.arccos(np.minimum(b.cpu().numpy() * 1e10 / 3.0, 1.0))
+    assert np.max(np.abs(chi.cpu().numpy() - ref)) < 1e-12
+    E = 0.5 * (W.AR_MASS / 2) * 700.0 ** 2 / W.KB
+    bb = torch.linspace(0.05e-10, 9e-10, 101, dtype=torch.float64, device=dev)
+    gg = torch.full_like(bb, 700.0)
+    ba = bb.cpu().numpy() * 1e10
+    c2 = api.deflect_jager(bb, gg, W.AR_MASS / 2, api.potential_invpow(500.0, 2)).cpu().numpy()
+    assert np.max(np.abs(c2 - np.pi * (1 - ba / np.sqrt(ba * ba + 500.0 / E)))) < 1e-11
+    c1 = api.deflect_jager(bb, gg, W.AR_MASS / 2, api.potential_invpow(800.0, 1)).cpu().numpy()
+    assert np.max(np.abs(c1 - 2 * np.arctan(800.0 / (2 * E * ba)))) < 1e-11
+
+
+def _chi_stats(got, ref):
+    d = np.abs(np.arccos(np.clip(np.cos(got), -1, 1)) - np.arccos(np.clip(np.cos(ref), -1, 1)))
+    return d
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_deflect_jager_against_oracle(orc, dev, api, dtype):
+    say("deflect jager", dtype)
+    b, g, mr = W.deflection_batch(seed=21, n=4096)
+    P = orc.potential_jager(W.JAGER_PLACEHOLDER)
+    ref, ost = orc.chi_batch(P, b, g, mr, n_threads=8)
+    st = api.new_status(dev)
+    chi = api.deflect_jager(torch.as_tensor(b, dtype=dtype, device=dev),
+                            torch.as_tensor(g, dtype=dtype, device=dev), mr,
+                            api.potential_jager(W.JAGER_PLACEHOLDER), st=st)
+    got = chi.double().cpu().numpy()
+    s = api.read_status(st)
+    assert s.root_fail == 0 and np.all(np.isfinite(got))
+    d = _chi_stats(got, ref)
+    E = 0.5 * mr * g * g / W.KB
+    hi = E > 300.0  # above the orbiting range: single turning point, smooth integrand
+    say(f"  theta err all: rms={np.sqrt(np.mean(d*d)):.3e} max={d.max():.3e} "
+        f"p99.9={np.percentile(d, 99.9):.3e}; E>300K max={d[hi].max():.3e}")
+    if dtype == torch.float64:
+        assert d[hi].max() < 1e-9
+        assert np.sqrt(np.mean(d * d)) < 1e-3
+    else:
+        assert d[hi].max() < 2e-4
+        assert np.sqrt(np.mean(d * d)) < 2e-3
+
+
+def test_collide_jager_step(orc, dev, api):
+    say("collide jager in-step")
+    pop = W.ragged_population(15, 120, 120, xs="const", T=2000.0)
+    cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, torch.float64, seed=4, step=2)
+    vn = vs.clone()
+    pot = api.potential_jager(W.JAGER_PLACEHOLDER)
+    api.collide_jager(vn, pairs, 4, 2, W.AR_MASS / 2, W.B_MAX, pot, st=st)
+    P = orc.potential_jager(W.JAGER_PLACEHOLDER)
+    ref, info = orc.step(cs.cpu().numpy(), v64, pop.xs, pop.lam, 4, 2, rule="jager", pot=P,
+                         b_max=W.B_MAX, m_red=W.AR_MASS / 2)
+    err = np.abs(vn.cpu().numpy() - ref) / _thermal(2000.0)
+    say(f"  jager step: max rel dv {err.max():.3e}")
+    assert err.max() < 1e-6
+    # conservation per cell
+    got = vn.cpu().numpy()
+    ocs = cs.cpu().numpy()
+    for k in range(pop.n_cells):
+        a, b_ = ocs[k], ocs[k + 1]
+        np.testing.assert_allclose(np.sum(got[:, a:b_] ** 2), np.sum(v64[:, a:b_] ** 2), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# neural operator
+# ---------------------------------------------------------------------------
+def _net_params(seed, dims, scale=1.0):
+    return W.mlp_init(seed, dims, scale)
+
+
+def test_neural_fp64_reference_parity(orc, dev, api):
+    say("neural fp64 reference")
+    pop = W.ragged_population(16, 200, 100)
+    cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, torch.float64, seed=8, step=0)
+    Ws, bs = _net_params(2, W.FD_DIMS)
+    net = api.Net(Ws, bs, act="silu", wdtype="f64", sigma_v=600.0, device=dev)
+    vn = vs.clone()
+    api.neural_collide(net, vn, pairs, 8, 0, st=st)
+    api.moment_match(cs, vn, mom, api.L.MM_APPLY, pair_cnt=pairs.cnt, st=st)
+    ref, _ = orc.step(cs.cpu().numpy(), v64, pop.xs, pop.lam, 8, 0, rule="neural",
+                      net={"Ws": Ws, "bs": bs, "act": "silu", "sigma_v": 600.0})
+    err = np.max(np.abs(vn.cpu().numpy() - ref)) / _thermal()
+    assert err < 1e-12, err
+
+
+def _angle(a, b):
+    c = np.sum(a * b, axis=1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
+    return np.arccos(np.clip(c, -1, 1))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_neural_bf16_chi_rms(orc, dev, api, dtype):
+    say("neural bf16 mfma", dtype)
+    pop = W.cavity_grid(seed=3, nx=40, ny=40)
+    cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, dtype, seed=9, step=1)
+    Ws, bs = _net_params(4, W.SURROGATE_DIMS)
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev)
+    ws = api.neural_ws(net, pairs, vs)
+    vn = vs.clone()
+    api.neural_collide(net, vn, pairs, 9, 1, ws=ws, st=st)
+    n = int(sel["pair_cnt"].sum())
+    es = 8 if dtype == torch.float64 else 4
+    u_gpu = ws[: 3 * (pairs.cap + 1) * es].view(dtype).view(3, pairs.cap + 1)[:, :n].T.double().cpu().numpy()
+    U, xi, z = orc.pair_latents(sel, 9, 1, lowp=dtype == torch.float32)
+    vr = (v64[:, sel["pair_i"]] - v64[:, sel["pair_j"]]).T
+    x = orc.network_input(vr, xi, z, 500.0)
+    y = orc.mlp_forward(Ws, bs, x, "silu")
+    ang = _angle(u_gpu, y)
+    rms = float(np.sqrt(np.mean(ang ** 2)))
+    say(f"  bf16 direction error: rms={rms:.3e} max={ang.max():.3e}")
+    assert rms <= 1e-2
+    # Phase B kept exact pair conservation
+    got = vn.double().cpu().numpy()
+    ocs = cs.cpu().numpy()
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    for k in range(0, pop.n_cells, 7):
+        a, b_ = ocs[k], ocs[k + 1]
+        e0 = np.sum(v64[:, a:b_] ** 2)
+        if e0 > 0:
+            assert abs(np.sum(got[:, a:b_] ** 2) / e0 - 1) < 10 * tol
+
+
+def test_neural_rows_bf16(orc, dev, api):
+    say("neural rows bf16")
+    rows = W.training_rows(seed=3, n=3000)
+    Ws, bs = _net_params(5, W.SURROGATE_DIMS)
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=rows["sigma_v"], device=dev)
+    x = orc.network_input(rows["vr"], rows["xi"], rows["z"], rows["sigma_v"])
+    xt = torch.as_tensor(x, dtype=torch.float32, device=dev)
+    gt = torch.as_tensor(rows["g"], dtype=torch.float32, device=dev)
+    y, vr = api.neural_forward_rows(net, xt, gt)
+    yref = orc.mlp_forward(Ws, bs, x, "silu")
+    yg = y.double().cpu().numpy()
+    rel = np.linalg.norm(yg - yref) / np.linalg.norm(yref)
+    ang = _angle(yg, yref)
+    say(f"  rows: rel err {rel:.3e}, angle rms {np.sqrt(np.mean(ang**2)):.3e}")
+    assert rel < 2e-2 and np.sqrt(np.mean(ang ** 2)) < 1e-2
+    np.testing.assert_allclose(np.linalg.norm(vr.double().cpu().numpy(), axis=1), rows["g"], rtol=1e-5)
+
+
+def test_backward_fp64_against_oracle(orc, dev, api):
+    say("backward fp64")
+    rows = W.training_rows(seed=7, n=700)
+    Ws, bs = _net_params(6, W.FD_DIMS)
+    net = api.Net(Ws, bs, act="silu", wdtype="f64", sigma_v=rows["sigma_v"], device=dev)
+    x = orc.network_input(rows["vr"], rows["xi"], rows["z"], rows["sigma_v"])
+    rng = np.random.default_rng(3)
+    target = rng.normal(size=(700, 3)) * rows["g"][:, None]
+    xt = torch.as_tensor(x, device=dev)
+    gt = torch.as_tensor(rows["g"], device=dev)
+    act = api.workspace(api.neural_act_bytes(net, 700), dev)
+    y, vr = api.neural_forward_rows(net, xt, gt, act_save=act)
+    yref = orc.mlp_forward(Ws, bs, x, "silu")
+    assert np.max(np.abs(y.cpu().numpy() - yref)) < 1e-12 * max(1.0, np.abs(yref).max())
+    G = orc.surrogate_loss_grad(vr.cpu().numpy(), target, rows["sigma_v"])
+    dW = [torch.zeros_like(w) for w in net.W]
+    db = [torch.zeros_like(b) for b in net.b]
+    dx = torch.zeros_like(xt)
+    api.neural_backward(net, xt, act, y, gt, torch.as_tensor(G, device=dev), dW, db, dx=dx)
+    dy = orc.project_backward(G, yref, rows["g"])
+    rW, rb, rx = orc.mlp_backward(Ws, bs, x, dy, "silu")
+    for l in range(len(Ws)):
+        for a, r in ((dW[l].cpu().numpy(), rW[l]), (db[l].cpu().numpy(), rb[l])):
+            assert np.max(np.abs(a - r)) <= 1e-10 * max(np.abs(r).max(), 1e-300)
+    assert np.max(np.abs(dx.cpu().numpy() - rx)) <= 1e-10 * np.abs(rx).max()
+
+
+def test_backward_bf16_bound(orc, dev, api):
+    say("backward bf16")
+    rows = W.training_rows(seed=8, n=4096)
+    Ws, bs = _net_params(7, W.SURROGATE_DIMS)
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=rows["sigma_v"], device=dev)
+    x = orc.network_input(rows["vr"], rows["xi"], rows["z"], rows["sigma_v"])
+    rng = np.random.default_rng(4)
+    target = rng.normal(size=(4096, 3)) * rows["g"][:, None]
+    xt = torch.as_tensor(x, dtype=torch.float32, device=dev)
+    gt = torch.as_tensor(rows["g"], dtype=torch.float32, device=dev)
+    act = api.workspace(api.neural_act_bytes(net, 4096), dev)
+    y, vr = api.neural_forward_rows(net, xt, gt, act_save=act)
+    G = orc.surrogate_loss_grad(vr.double().cpu().numpy(), target, rows["sigma_v"])
+    dW = [torch.zeros(w.shape, dtype=torch.float32, device=dev) for w in net.W]
+    db = [torch.zeros_like(b) for b in net.b]
+    api.neural_backward(net, xt, act, y, gt, torch.as_tensor(G, dtype=torch.float32, device=dev), dW, db)
+    Wr = [w.float().double().cpu().numpy() for w in net.W]  # the bf16-rounded weights
+    yref = orc.mlp_forward(Wr, bs, x, "silu")
+    dy = orc.project_backward(G, yref, rows["g"])
+    rW, rb, _ = orc.mlp_backward(Wr, bs, x, dy, "silu")
+    for l in range(len(Ws)):
+        e = np.linalg.norm(dW[l].cpu().numpy() - rW[l]) / np.linalg.norm(rW[l])
+        say(f"  layer {l}: rel Frobenius error {e:.3e}")
+        assert e < 5e-2
+
+
+def test_training_helpers(orc, dev, api):
+    say("mse, adam, moment-match adjoint, harvest")
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=(1000, 3))
+    t = rng.normal(size=(1000, 3))
+    grad = torch.zeros(1000, 3, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    api.mse_loss(torch.as_tensor(a, dtype=torch.float32, device=dev),
+                 torch.as_tensor(t, dtype=torch.float32, device=dev), 2.0, grad, loss)
+    af, tf = a.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
+    np.testing.assert_allclose(loss.item(), orc.surrogate_loss(af, tf, 2.0), rtol=1e-12)
+    np.testing.assert_allclose(grad.cpu().numpy(), orc.surrogate_loss_grad(af, tf, 2.0), rtol=1e-6)
+    p = rng.normal(size=500)
+    gr = rng.normal(size=500)
+    pt = torch.as_tensor(p, dtype=torch.float32, device=dev)
+    m = torch.zeros_like(pt)
+    v = torch.zeros_like(pt)
+    for step in (1, 2, 3):
+        api.adam_step(pt, torch.as_tensor(gr * step, dtype=torch.float32, device=dev), m, v, step, 1e-2)
+    P = [p.copy()]
+    M = [np.zeros(500)]
+    S = [np.zeros(500)]
+    for step in (1, 2, 3):
+        orc.adam_step(P, [gr * step], M, S, step, 1e-2)
+    np.testing.assert_allclose(pt.cpu().numpy(), P[0], rtol=1e-5, atol=1e-6)
+    # moment-match adjoint per cell
+    pop = W.ragged_population(17, 30, 40)
+    cs, perm, vs, _ = _gpu_sort(api, dev, pop)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, vs, mom, api.L.MM_CAPTURE)
+    vpost = vs + torch.randn_like(vs) * 30.0
+    Gt = torch.randn_like(vs)
+    out = api.moment_match_backward(cs, mom, vpost, Gt).cpu().numpy()
+    ocs = cs.cpu().numpy()
+    vp, vq, Gn = vs.cpu().numpy(), vpost.cpu().numpy(), Gt.cpu().numpy()
+    for k in range(pop.n_cells):
+        a_, b_ = ocs[k], ocs[k + 1]
+        if b_ - a_ < 2:
+            continue
+        ref = orc.moment_match_group_backward(Gn[:, a_:b_].T, vq[:, a_:b_].T, vp[:, a_:b_].T).T
+        np.testing.assert_allclose(out[:, a_:b_], ref, rtol=1e-10, atol=1e-12)
+    # harvested rows: chi from the quadrature against the oracle
+    rows = W.training_rows(seed=9, n=512)
+    P_ = orc.potential_jager(W.JAGER_PLACEHOLDER)
+    x_, g_, tgt, chi = api.harvest_rows(torch.as_tensor(rows["vr"], device=dev),
+                                        torch.as_tensor(rows["xi"], device=dev),
+                                        torch.as_tensor(rows["z"], device=dev), rows["sigma_v"],
+                                        W.B_MAX, W.AR_MASS / 2, api.potential_jager(W.JAGER_PLACEHOLDER))
+    bb = orc.impact_from_z(rows["z"], W.B_MAX)
+    ref, _ = orc.chi_batch(P_, bb, rows["g"], W.AR_MASS / 2, n_threads=8)
+    d = _chi_stats(chi.cpu().numpy(), ref)
+    say(f"  harvest chi: rms {np.sqrt(np.mean(d*d)):.3e}, max {d.max():.3e}")
+    assert np.sqrt(np.mean(d * d)) < 1e-3
+    tref = orc.rotate(rows["vr"], ref, rows["xi"])
+    ok = d < 1e-9
+    np.testing.assert_allclose(tgt.double().cpu().numpy()[ok], tref[ok], rtol=1e-5, atol=1e-3)
