@@ -1,0 +1,288 @@
+"""Benchmark of the DSMC collision step on one MI355X.
+
+One step = the whole collision path on the Mach-10 cylinder-shaped workload
+(400 x 300 cells, ~30 M particles, uneven populations): stable counting sort
+of the post-streaming particle order into cells, FP64 cell moments, NTC pair
+selection, the neural collision operator (BF16 MFMA MLP + energy-shell
+projection, Phase B pair updates) and FP64 cell-wise moment matching.  The
+metric is accepted collision pairs per second.  The same step with the ab
+initio quadrature rule in place of the network is timed beside it, with the
+network's angle error against the quadrature on the same pairs.
+
+Prints ONE JSON line.  --gpus above 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MLP_FLOP_PER_PAIR = 2 * (8 * 128 + 3 * 128 * 128 + 128 * 3)  # 101,120 (unpadded)
+PEAK_BF16 = 2.5e15
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="cylinder", choices=["cylinder", "cavity"])
+    p.add_argument("--order", default="realistic", choices=["realistic", "shuffled", "sorted"])
+    p.add_argument("--quad-steps", type=int, default=3)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-pairs", type=int, default=1_200_000)
+    p.add_argument("--weights", default=os.path.join(ROOT, "paper_2602_21244_amd", "weights",
+                                                     "jager_surrogate_8x128x4.npz"))
+    return p.parse_args()
+
+
+def load_weights(path, workloads):
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        L = int(z["n_layers"])
+        Ws = [z[f"W{l}"] for l in range(L)]
+        bs = [z[f"b{l}"] for l in range(L)]
+        return Ws, bs, float(z["sigma_v"]), "trained"
+    Ws, bs = workloads.mlp_init(0, workloads.SURROGATE_DIMS)
+    return Ws, bs, 3547.0, "seeded-init"
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workloads as W
+    from paper_2602_21244_amd import api
+    L = api.L
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    if args.workload == "cylinder":
+        pop = W.cylinder_grid(seed=5, order=args.order)
+        wname = f"mach10_cylinder_400x300_{args.order}"
+    else:
+        pop = W.cavity_grid(seed=3)
+        wname = "cavity_200x200"
+    log(f"workload {wname}: {pop.n} particles, {pop.n_cells} cells ({time.time() - t0:.1f}s)")
+
+    stream = torch.cuda.current_stream()
+    cell_of = torch.as_tensor(pop.cell_of, device=dev)
+    v_in = torch.as_tensor(pop.v, dtype=torch.float32, device=dev).contiguous()
+    lam = torch.as_tensor(pop.lam, device=dev)
+    n, n_cells = pop.n, pop.n_cells
+    v = torch.empty_like(v_in)
+    cs = torch.empty(n_cells + 1, dtype=torch.int32, device=dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    mom = torch.zeros(n_cells * 6, dtype=torch.float64, device=dev)
+    st = api.new_status(dev)
+    lib = api.lib()
+    sort_ws_b = lib.dsmc_sort_cells_ws(n, n_cells)
+    sort_ws = api.workspace(sort_ws_b, dev)
+
+    def do_sort():
+        api.check(lib.dsmc_sort_cells(n, n_cells, api._ptr(cell_of), L.F32, api._vec3(v_in),
+                                      api._vec3(v), api._ptr(cs), api._ptr(perm), api._ptr(sort_ws),
+                                      sort_ws_b, api._ptr(st), api._stream()), "sort")
+
+    # size the pair capacity from a first selection
+    do_sort()
+    api.moment_match(cs, v, mom, L.MM_CAPTURE)
+    probe = api.PairList(n_cells, 1, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, probe, st=st)
+    n_cand = api.read_status(st).n_cand
+    cap = int(n_cand * 1.02) + 1024
+    pairs = api.PairList(n_cells, cap, dev)
+    sel_ws = api.workspace(lib.dsmc_select_pairs_ntc_ws(n_cells, cap), dev)
+
+    Ws, bs, sigma_v, wkind = load_weights(args.weights, W)
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=sigma_v, device=dev)
+    col_ws = api.collide_ws(cap, v)
+    pot = api.potential_jager(W.JAGER_PLACEHOLDER)
+    quad = api.quad_struct(64)
+
+    def stage_events(k):
+        return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+
+    def step(rule, ev=None):
+        """One collision step; ev: list of 7 events bracketing the stages."""
+        if ev: ev[0].record(stream)
+        do_sort()
+        if ev: ev[1].record(stream)
+        api.moment_match(cs, v, mom, L.MM_CAPTURE)
+        if ev: ev[2].record(stream)
+        api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, pairs, ws=sel_ws, st=st)
+        if ev: ev[3].record(stream)
+        if rule == "neural":
+            api.neural_collide(net, v, pairs, 11, 0, schedule=L.SCHED_DEFER, ws=col_ws, st=st)
+            kind = L.APPLY_DIRECTIONS
+        else:
+            api.collide_jager(v, pairs, 11, 0, W.AR_MASS / 2, W.B_MAX, pot, quad=quad,
+                              schedule=L.SCHED_DEFER, ws=col_ws, st=st)
+            kind = L.APPLY_ANGLES
+        if ev: ev[4].record(stream)
+        api.apply_pairs(v, pairs, kind, col_ws)
+        if ev: ev[5].record(stream)
+        api.moment_match(cs, v, mom, L.MM_APPLY, pair_cnt=pairs.cnt, st=st)
+        if ev: ev[6].record(stream)
+
+    names = ["sort", "moments", "select", "phaseA", "phaseB", "match"]
+
+    def run(rule, warm, steps):
+        for _ in range(warm):
+            step(rule)
+        torch.cuda.synchronize()
+        evs = [stage_events(7) for _ in range(steps)]
+        t_start = time.perf_counter()
+        for q in range(steps):
+            step(rule, evs[q])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        per = {nm: float(np.mean([evs[q][s].elapsed_time(evs[q][s + 1]) for q in range(steps)]))
+               for s, nm in enumerate(names)}
+        tot = float(np.mean([evs[q][0].elapsed_time(evs[q][6]) for q in range(steps)]))
+        return wall, tot, per
+
+    api.status_clear(st)
+    wall_n, ms_n, per_n = run("neural", args.warmup, args.steps)
+    s = api.read_status(st)
+    n_pairs = int(s.n_pairs)
+    log(f"neural: {ms_n:.3f} ms/step (events), wall {wall_n / args.steps * 1e3:.3f} ms/step, "
+        f"pairs {n_pairs}, stages {json.dumps({k: round(x, 4) for k, x in per_n.items()})}")
+
+    # neural directions of this step for the angle comparison
+    es = 4
+    dirs = col_ws[: 3 * (cap + 1) * es].view(torch.float32).view(3, cap + 1)[:, :n_pairs].clone()
+
+    wall_q, ms_q, per_q = run("quadrature", 1, args.quad_steps)
+    log(f"quadrature: {ms_q:.3f} ms/step, stages {json.dumps({k: round(x, 4) for k, x in per_q.items()})}")
+
+    # angle error of the network against the quadrature on the same pairs:
+    # rebuild the quadrature direction from (cos chi, sin chi, xi) and the
+    # pre-collision v_r (sorted velocities before Phase B of that step)
+    do_sort()
+    api.moment_match(cs, v, mom, L.MM_CAPTURE)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, pairs, ws=sel_ws, st=st)
+    api.collide_jager(v, pairs, 11, 0, W.AR_MASS / 2, W.B_MAX, pot, quad=quad,
+                      schedule=L.SCHED_DEFER, ws=col_ws, st=st)
+    torch.cuda.synchronize()
+    m = min(n_pairs, 200_000)
+    sel_idx = torch.linspace(0, n_pairs - 1, m, device=dev).long()
+    buf = col_ws[: 6 * (cap + 1) * es].view(torch.float32).view(6, cap + 1)
+    cc, sc = buf[0, sel_idx].double(), buf[1, sel_idx].double()
+    xi = buf[2:5, sel_idx].double()
+    pi_, pj_ = pairs.i[sel_idx].long(), pairs.j[sel_idx].long()
+    vr = (v[:, pi_] - v[:, pj_]).double()
+    vh = vr / vr.norm(dim=0, keepdim=True)
+    w = xi - (xi * vh).sum(0, keepdim=True) * vh
+    e = w / w.norm(dim=0, keepdim=True)
+    uq = cc * vh + sc * e
+    un = dirs[:, sel_idx].double()
+    un = un / un.norm(dim=0, keepdim=True)
+    ang = torch.arccos(torch.clamp((uq * un).sum(0), -1, 1)).cpu().numpy()
+    chi_rms = float(np.sqrt(np.mean(ang ** 2)))
+    log(f"network vs quadrature direction error: rms {chi_rms:.4f} rad ({wkind} weights)")
+
+    # roofline of the dominant kernel (the fused MLP, Phase A of the network)
+    t_mlp = per_n["phaseA"] * 1e-3
+    achieved = n_pairs * MLP_FLOP_PER_PAIR / t_mlp
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_BF16, "traffic": None,
+                "kernel": "k_mlp_bf16 (Phase A of dsmc_neural_collide)",
+                "algorithmic_flop_per_pair": MLP_FLOP_PER_PAIR}
+    sort_bytes = n * (4 + 4 + 12 + 12 + 4)  # cell id twice, v read + write, perm
+    extra = {
+        "quadrature_pairs_per_s": n_pairs / (ms_q * 1e-3),
+        "quadrature_ms_per_step": ms_q,
+        "neural_over_quadrature": (ms_q / ms_n),
+        "chi_rms_vs_quadrature_rad": chi_rms,
+        "network_weights": wkind,
+        "stage_ms_neural": per_n,
+        "stage_ms_quadrature": per_q,
+        "sort_GBps_algorithmic": sort_bytes / (per_n["sort"] * 1e-3) / 1e9,
+        "pairs_per_step": n_pairs,
+        "particles": n,
+        "cells": n_cells,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(pop, Ws, bs, sigma_v, args.cpu_sample_pairs)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": "collision pairs/s (neural collision operator step; quadrature beside it)",
+        "value": n_pairs / (ms_n * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_n,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": wname, "particles": n, "cells": n_cells,
+                   "pairs_per_step": n_pairs, "velocities": "fp32 SoA",
+                   "mlp": "8-128x4-3 SiLU bf16/fp32-acc", "moments": "fp64"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(pop, Ws, bs, sigma_v, sample_pairs):
+    """The oracle's neural step timed on the host on a bounded sample of the
+    same workload: the first cells holding about `sample_pairs` pairs."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    cs, perm, _ = oracle.sort_cells(pop.cell_of, pop.n_cells)
+    v = pop.v[:, perm]
+    # about P_COLL pairs per particle: take cells until the sample is reached
+    target_particles = int(sample_pairs / 0.5)
+    kmax = int(np.searchsorted(cs, target_particles))
+    kmax = max(1, min(kmax, pop.n_cells))
+    sub_cs = cs[: kmax + 1].copy()
+    sub_v = v[:, : sub_cs[-1]].copy()
+    sub_lam = pop.lam[:kmax].copy()
+    net = {"Ws": Ws, "bs": bs, "act": "silu", "sigma_v": sigma_v}
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        if ctx:
+            ctx.__enter__()
+        t = time.perf_counter()
+        _, info = oracle.step(sub_cs, sub_v, pop.xs, sub_lam, 11, 0, rule="neural", net=net)
+        dt = time.perf_counter() - t
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    npairs = int(info["sel"]["pair_cnt"].sum())
+    return {"value": npairs / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {kmax} of {pop.n_cells} cells ({sub_cs[-1]} particles, "
+                      f"{npairs} pairs), one oracle neural step, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

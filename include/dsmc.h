@@ -144,6 +144,12 @@ typedef struct {
  * one lane per cell; BLOCK: one workgroup per cell applying independent
  * pairs in dependency rounds.  All schedules give bit-identical results. */
 enum { DSMC_SCHED_AUTO = 0, DSMC_SCHED_LANE = 1, DSMC_SCHED_BLOCK = 2 };
+/* DSMC_SCHED_DEFER: run Phase A only and leave its per-pair results in the
+ * workspace; dsmc_apply_pairs then performs Phase B (used to overlap or time
+ * the two phases separately). */
+enum { DSMC_SCHED_DEFER = 3 };
+/* Phase-A result kinds for dsmc_apply_pairs. */
+enum { DSMC_APPLY_DIRECTIONS = 0, DSMC_APPLY_ANGLES = 1 };
 
 /* Moment-matching modes (eq. cell_energy_clamp). */
 enum { DSMC_MM_CAPTURE = 0, DSMC_MM_APPLY = 1, DSMC_MM_APPLY_LITERAL = 2 };
@@ -214,6 +220,13 @@ size_t dsmc_collide_ws(int64_t cap, int32_t dtype);
 int dsmc_collide_vhs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pairs,
                      dsmc_rng rng, int32_t schedule, void* ws, size_t ws_bytes,
                      dsmc_stream_t stream);
+
+/* Phase B alone, from the Phase-A results a collide call left in `ws` with
+ * schedule DSMC_SCHED_DEFER: kind DSMC_APPLY_DIRECTIONS after
+ * dsmc_collide_vhs / dsmc_neural_collide, DSMC_APPLY_ANGLES after
+ * dsmc_collide_jager.  schedule: AUTO, LANE or BLOCK. */
+int dsmc_apply_pairs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pairs, int32_t kind,
+                     int32_t schedule, void* ws, size_t ws_bytes, dsmc_stream_t stream);
 
 /* Ab initio deflection angle by quadrature (section "Computational
  * Implementation: The Exact vs. Neural Paradigm"): for each of n pairs,
@@ -303,6 +316,22 @@ int dsmc_harvest_rows(int64_t B, const double* vr, const double* xi, const doubl
                       double sigma_v, double b_max, double m_red, const dsmc_potential* pot,
                       dsmc_quad quad, float* x_out, float* g_out, float* target_out,
                       double* chi_out, dsmc_status* st, dsmc_stream_t stream);
+
+/* One persistent launch per step for the isotropic rule: each workgroup takes
+ * cells from a work queue and, with the cell staged in LDS, runs moments, NTC
+ * selection, Phase A, Phase B and (match != 0) centred moment matching; HBM
+ * sees one read and one write of the velocities.  Results are bit-identical
+ * to dsmc_moment_match(CAPTURE) -> dsmc_select_pairs_ntc -> dsmc_collide_vhs
+ * -> dsmc_moment_match(APPLY) with the same rng.  pair_cnt[n_cells] receives
+ * each cell's accepted pairs; a cell above the LDS capacity (3072 particles
+ * or 2048 accepted pairs) is left unchanged with pair_cnt = -1 and
+ * DSMC_ST_PAIR_OVERFLOW set, for the separate entry points to handle.
+ * ws: dsmc_step_vhs_ws bytes. */
+size_t dsmc_step_vhs_ws(int32_t n_cells, int64_t cap);
+int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, int32_t dtype, dsmc_vec3 v,
+                        dsmc_xs xs, const double* lambda, dsmc_rng rng, int32_t match,
+                        int32_t* pair_cnt, void* ws, size_t ws_bytes, dsmc_status* st,
+                        dsmc_stream_t stream);
 
 /* Tuning knobs (host): threshold in pairs above which AUTO uses the BLOCK
  * schedule; the autotuner in the Python package sets it. */

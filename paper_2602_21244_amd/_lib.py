@@ -13,7 +13,8 @@ ST_PAIR_OVERFLOW, ST_BAD_CELL, ST_ROOT_FAIL, ST_NONFINITE = 1, 2, 4, 8
 XS_VHS, XS_CONST = 0, 1
 POT_JAGER, POT_HS, POT_INVPOW = 0, 1, 2
 ACT_SILU, ACT_RELU = 0, 1
-SCHED_AUTO, SCHED_LANE, SCHED_BLOCK = 0, 1, 2
+SCHED_AUTO, SCHED_LANE, SCHED_BLOCK, SCHED_DEFER = 0, 1, 2, 3
+APPLY_DIRECTIONS, APPLY_ANGLES = 0, 1
 MM_CAPTURE, MM_APPLY, MM_APPLY_LITERAL = 0, 1, 2
 
 
@@ -76,6 +77,7 @@ SIGNATURES = {
                                         _sz, _vp, _vp]),
     "dsmc_collide_ws": (_sz, [_i64, _i32]),
     "dsmc_collide_vhs": (C.c_int, [_i32, _i32, Vec3, Pairs, Rng, _i32, _vp, _sz, _vp]),
+    "dsmc_apply_pairs": (C.c_int, [_i32, _i32, Vec3, Pairs, _i32, _i32, _vp, _sz, _vp]),
     "dsmc_deflect_jager": (C.c_int, [_i64, _i32, _vp, _vp, _vp, _d, C.POINTER(Potential), Quad,
                                      _i32, _vp, _vp]),
     "dsmc_collide_jager": (C.c_int, [_i32, _i32, Vec3, Pairs, Rng, _d, _d, C.POINTER(Potential),

@@ -217,6 +217,13 @@ def collide_vhs(v, pairs, seed, step, schedule=L.SCHED_AUTO, ws=None, stream=Non
     return ws
 
 
+def apply_pairs(v, pairs, kind, ws, schedule=L.SCHED_AUTO, stream=None):
+    n_cells = int(pairs.off.numel())
+    check(lib().dsmc_apply_pairs(n_cells, _dtype(v), _vec3(v), pairs.struct(), int(kind),
+                                 int(schedule), _ptr(ws), int(ws.numel()), _stream(stream)),
+          "dsmc_apply_pairs")
+
+
 def deflect_jager(b, g, m_red, pot, quad=None, fold=False, st=None, stream=None):
     chi = torch.empty_like(g)
     q = quad if quad is not None else quad_struct()

@@ -238,7 +238,7 @@ extern "C" int dsmc_collide_vhs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsm
 {
     int rc = check_pairs("dsmc_collide_vhs", n_cells, v, pairs, dtype, ws, ws_bytes);
     if (rc) return rc;
-    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_BLOCK)
+    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_DEFER)
         return arg_error("dsmc_collide_vhs: schedule %d", schedule);
     hipStream_t s = as_stream(stream);
     const PairsView pr = PairsView::of(pairs);
@@ -251,7 +251,20 @@ extern "C" int dsmc_collide_vhs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsm
                                               PairBuf<float>::of(ws, pairs.cap));
     }
     DSMC_LAUNCH_CHECK("collide_vhs:phaseA");
-    // cell_start is not needed by the isotropic rule's LANE path; the BLOCK
-    // path derives local indices from the pair list itself.
+    if (schedule == DSMC_SCHED_DEFER) return DSMC_OK;
     return phase_b(RULE_DIR, dtype, n_cells, nullptr, v, pairs, ws, pairs.cap, schedule, s);
+}
+
+extern "C" int dsmc_apply_pairs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pairs,
+                                int32_t kind, int32_t schedule, void* ws, size_t ws_bytes,
+                                dsmc_stream_t stream)
+{
+    int rc = check_pairs("dsmc_apply_pairs", n_cells, v, pairs, dtype, ws, ws_bytes);
+    if (rc) return rc;
+    if (kind != DSMC_APPLY_DIRECTIONS && kind != DSMC_APPLY_ANGLES)
+        return arg_error("dsmc_apply_pairs: kind %d", kind);
+    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_BLOCK)
+        return arg_error("dsmc_apply_pairs: schedule %d", schedule);
+    return phase_b(kind == DSMC_APPLY_ANGLES ? RULE_CHI : RULE_DIR, dtype, n_cells, nullptr, v, pairs,
+                   ws, pairs.cap, schedule, as_stream(stream));
 }

@@ -486,7 +486,7 @@ extern "C" int dsmc_collide_jager(int32_t n_cells, int32_t dtype, dsmc_vec3 v, d
     int rc = check_pairs("dsmc_collide_jager", n_cells, v, pairs, dtype, ws, ws_bytes);
     if (rc) return rc;
     if (!(m_red > 0) || !(b_max > 0)) return arg_error("dsmc_collide_jager: m_red, b_max > 0");
-    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_BLOCK)
+    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_DEFER)
         return arg_error("dsmc_collide_jager: schedule %d", schedule);
     Pot P;
     rc = get_pot(pot, &P);
@@ -509,6 +509,7 @@ extern "C" int dsmc_collide_jager(int32_t n_cells, int32_t dtype, dsmc_vec3 v, d
                                                 PairBuf<float>::of(ws, pairs.cap), st);
     }
     DSMC_LAUNCH_CHECK("collide_jager:phaseA");
+    if (schedule == DSMC_SCHED_DEFER) return DSMC_OK;
     return phase_b(RULE_CHI, dtype, n_cells, nullptr, v, pairs, ws, pairs.cap, schedule, s);
 }
 

@@ -1,0 +1,298 @@
+// One persistent launch per collision step for the isotropic rule: each
+// workgroup takes cells from a work queue (an atomic counter, so cells of any
+// population balance across the grid), stages the cell's velocities in LDS
+// and runs moments, NTC selection, Phase A, Phase B (dependency rounds) and
+// moment matching without touching HBM again.  HBM traffic is one read and one
+// write of the velocities per step.  The arithmetic (including the order of
+// every reduction) is that of the separate entry points, so the results are
+// bit-identical to dsmc_moment_match(CAPTURE) -> dsmc_select_pairs_ntc ->
+// dsmc_collide_vhs -> dsmc_moment_match(APPLY).
+#include <limits.h>
+#include <math.h>
+
+#include "collide.hpp"
+
+namespace dsmc {
+
+int xs_law_public(const dsmc_xs& xs, double* C, double* e);
+
+constexpr int FS_THREADS = 256;
+constexpr int FS_NMAX = 3072;  // particles of a cell staged in LDS
+constexpr int FS_MMAX = 2048;  // accepted pairs of a cell
+
+struct FusedArgs {
+    int32_t n_cells;
+    const int32_t* cell_start;
+    const double* lambda;
+    double C, e;
+    dsmc_rng rng;
+    int32_t match;
+    int32_t* pair_cnt;
+    int32_t* queue;
+    dsmc_status* st;
+};
+
+// Same reduction order as the wave-per-cell moments kernel: lane-strided
+// partial sums, then a butterfly over the 64 lanes (wave 0 only).
+__device__ __forceinline__ void wave0_sums(const double* vx, const double* vy, const double* vz,
+                                           int32_t N, int lane, double* out6)
+{
+    double sx = 0, sy = 0, sz = 0;
+    for (int32_t q = lane; q < N; q += 64) { sx += vx[q]; sy += vy[q]; sz += vz[q]; }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    sz = wave_sum(sz);
+    const double ux = sx / N, uy = sy / N, uz = sz / N;
+    double S = 0, c2max = 0, E = 0;
+    for (int32_t q = lane; q < N; q += 64) {
+        const double x = vx[q], y = vy[q], z = vz[q];
+        const double dx = x - ux, dy = y - uy, dz = z - uz;
+        const double c2 = dx * dx + dy * dy + dz * dz;
+        S += c2;
+        c2max = fmax(c2max, c2);
+        E += x * x + y * y + z * z;
+    }
+    out6[0] = ux; out6[1] = uy; out6[2] = uz;
+    out6[3] = wave_sum(S);
+    out6[4] = sqrt(wave_max(c2max));
+    out6[5] = wave_sum(E);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(FS_THREADS)
+k_step_vhs_fused(FusedArgs A, V3<T> v)
+{
+    __shared__ double lvx[FS_NMAX], lvy[FS_NMAX], lvz[FS_NMAX];
+    __shared__ uint32_t lpair[FS_MMAX];
+    __shared__ T ldir[3][FS_MMAX];
+    __shared__ int32_t first[FS_NMAX];
+    __shared__ double mom[6], post[6];
+    __shared__ int32_t s_cell, s_M, s_acc, s_remaining;
+    __shared__ int32_t wtot[FS_THREADS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+
+    for (;;) {
+        if (tid == 0) s_cell = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int32_t k = s_cell;
+        if (k >= A.n_cells) break;
+        const int32_t s0 = A.cell_start[k], N = A.cell_start[k + 1] - s0;
+        if (N < 2 || N > FS_NMAX) {
+            if (tid == 0) {
+                A.pair_cnt[k] = (N > FS_NMAX) ? -1 : 0;
+                if (N > FS_NMAX && A.st) atomicOr(&A.st->flags, (uint32_t)DSMC_ST_PAIR_OVERFLOW);
+            }
+            __syncthreads();
+            continue;
+        }
+        for (int32_t q = tid; q < N; q += FS_THREADS) {
+            lvx[q] = (double)v.x[s0 + q];
+            lvy[q] = (double)v.y[s0 + q];
+            lvz[q] = (double)v.z[s0 + q];
+        }
+        __syncthreads();
+        if (wid == 0) {
+            double m6[6];
+            wave0_sums(lvx, lvy, lvz, N, lane, m6);
+            if (lane == 0) {
+                for (int q = 0; q < 6; ++q) mom[q] = m6[q];
+                // candidate count: same arithmetic as the selection kernel
+                const double ghat = 2.0 * m6[4];
+                const double sgmax = A.C * pow(ghat, A.e);
+                const U4 r = draw(A.rng, 0u, (uint32_t)k, SLOT_COUNT);
+                const double U = unif53(r.a, r.b);
+                double x = __dmul_rn(0.5, (double)N);
+                x = __dmul_rn(x, (double)(N - 1));
+                x = __dmul_rn(x, A.lambda[k]);
+                x = __dmul_rn(x, sgmax);
+                x = __dadd_rn(x, U);
+                s_M = (!(x >= 0.0) || !(x < 2147483647.0)) ? 0 : (int32_t)floor(x);
+                s_acc = 0;
+            }
+        }
+        __syncthreads();
+        const int32_t M = s_M;
+        const double ghat = 2.0 * mom[4];
+        // candidates in chunks; ordered compaction of the accepted ones
+        for (int32_t base = 0; base < M; base += FS_THREADS) {
+            const int32_t t = base + tid;
+            bool acc = false;
+            uint32_t packed = 0;
+            if (t < M) {
+                const U4 r = draw(A.rng, (uint32_t)t, (uint32_t)k, SLOT_CAND);
+                int32_t i = (int32_t)(((uint64_t)r.a * (uint64_t)N) >> 32);
+                int32_t j = (int32_t)(((uint64_t)r.b * (uint64_t)(N - 1)) >> 32);
+                if (j >= i) j += 1;
+                const double U = unif53(r.c, r.d);
+                const double dx = lvx[i] - lvx[j], dy = lvy[i] - lvy[j], dz = lvz[i] - lvz[j];
+                const double g2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                            __dmul_rn(dz, dz));
+                const double ratio = sqrt(g2) / ghat;
+                const double p = (A.e == 1.0) ? ratio : pow(ratio, A.e);
+                acc = U < p;
+                packed = (uint32_t)i | ((uint32_t)j << 16);
+            }
+            const uint64_t bal = __ballot(acc);
+            const int before = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) wtot[wid] = __popcll(bal);
+            __syncthreads();
+            int off = s_acc;
+            for (int w = 0; w < wid; ++w) off += wtot[w];
+            if (acc && off + before < FS_MMAX) lpair[off + before] = packed;
+            __syncthreads();
+            if (tid == 0) {
+                int tot = 0;
+                for (int w = 0; w < FS_THREADS / 64; ++w) tot += wtot[w];
+                s_acc += tot;
+            }
+            __syncthreads();
+        }
+        const int32_t na = s_acc;
+        if (na > FS_MMAX) {
+            if (tid == 0) {
+                A.pair_cnt[k] = -1;
+                if (A.st) atomicOr(&A.st->flags, (uint32_t)DSMC_ST_PAIR_OVERFLOW);
+            }
+            __syncthreads();
+            continue;
+        }
+        // Phase A on the pre-collision velocities (arithmetic in T, as the
+        // separate isotropic kernel)
+        for (int32_t q = tid; q < na; q += FS_THREADS) {
+            T xi[3], z[2], u4;
+            pair_latents(A.rng, (uint32_t)q, (uint32_t)k, xi, z, u4);
+            const int32_t i = lpair[q] & 0xffff, j = lpair[q] >> 16;
+            T vh[3], e[3];
+            unit3<T>((T)lvx[i] - (T)lvx[j], (T)lvy[i] - (T)lvy[j], (T)lvz[i] - (T)lvz[j], vh);
+            const T cc = T(2) * u4 - T(1);
+            const T sc = T(2) * dev_sqrt<T>(u4 * (T(1) - u4));
+            perp_dir<T>(xi, vh, e);
+            ldir[0][q] = cc * vh[0] + sc * e[0];
+            ldir[1][q] = cc * vh[1] + sc * e[1];
+            ldir[2][q] = cc * vh[2] + sc * e[2];
+        }
+        if (tid == 0) s_remaining = na;
+        __syncthreads();
+        // Phase B: dependency rounds, every value rounded to T as stored
+        while (s_remaining > 0) {
+            for (int32_t q = tid; q < N; q += FS_THREADS) first[q] = INT32_MAX;
+            __syncthreads();
+            for (int32_t q = tid; q < na; q += FS_THREADS) {
+                const uint32_t w = lpair[q];
+                if (w != 0xffffffffu) {
+                    atomicMin(&first[w & 0xffff], q);
+                    atomicMin(&first[w >> 16], q);
+                }
+            }
+            __syncthreads();
+            int done_here = 0;
+            for (int32_t q = tid; q < na; q += FS_THREADS) {
+                const uint32_t w = lpair[q];
+                if (w == 0xffffffffu) continue;
+                const int32_t a = w & 0xffff, b = w >> 16;
+                if (first[a] != q || first[b] != q) continue;
+                const double xa = lvx[a], ya = lvy[a], za = lvz[a];
+                const double xb = lvx[b], yb = lvy[b], zb = lvz[b];
+                const double rx = xa - xb, ry = ya - yb, rz = za - zb;
+                const double g = sqrt(rx * rx + ry * ry + rz * rz);
+                const double a0 = ldir[0][q], a1 = ldir[1][q], a2 = ldir[2][q];
+                const double inv = 1.0 / sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+                const double u0 = a0 * inv, u1 = a1 * inv, u2 = a2 * inv;
+                const double cx = 0.5 * (xa + xb), cy = 0.5 * (ya + yb), cz = 0.5 * (za + zb);
+                const double px = 0.5 * g * u0, py = 0.5 * g * u1, pz = 0.5 * g * u2;
+                lvx[a] = (double)(T)(cx + px); lvy[a] = (double)(T)(cy + py); lvz[a] = (double)(T)(cz + pz);
+                lvx[b] = (double)(T)(cx - px); lvy[b] = (double)(T)(cy - py); lvz[b] = (double)(T)(cz - pz);
+                lpair[q] = 0xffffffffu;
+                ++done_here;
+            }
+            __syncthreads();
+            if (done_here) atomicSub(&s_remaining, done_here);
+            __syncthreads();
+        }
+        // moment matching (centred), same arithmetic as the separate kernel
+        bool write_raw = true;
+        if (A.match && na > 0) {
+            if (wid == 0) {
+                double m6[6];
+                wave0_sums(lvx, lvy, lvz, N, lane, m6);
+                if (lane == 0)
+                    for (int q = 0; q < 6; ++q) post[q] = m6[q];
+            }
+            __syncthreads();
+            const double Sp = post[3];
+            if (!(Sp > 0.0) || !isfinite(Sp)) {
+                if (tid == 0 && A.st) atomicAdd(&A.st->mm_skipped, 1);
+            } else {
+                const double alpha = sqrt(mom[3] / Sp);
+                for (int32_t q = tid; q < N; q += FS_THREADS) {
+                    v.x[s0 + q] = (T)(mom[0] + alpha * (lvx[q] - post[0]));
+                    v.y[s0 + q] = (T)(mom[1] + alpha * (lvy[q] - post[1]));
+                    v.z[s0 + q] = (T)(mom[2] + alpha * (lvz[q] - post[2]));
+                }
+                write_raw = false;
+            }
+        }
+        if (write_raw) {
+            for (int32_t q = tid; q < N; q += FS_THREADS) {
+                v.x[s0 + q] = (T)lvx[q];
+                v.y[s0 + q] = (T)lvy[q];
+                v.z[s0 + q] = (T)lvz[q];
+            }
+        }
+        if (tid == 0) A.pair_cnt[k] = na;
+        __syncthreads();
+    }
+}
+
+}  // namespace dsmc
+
+using namespace dsmc;
+
+extern "C" size_t dsmc_step_vhs_ws(int32_t n_cells, int64_t cap)
+{
+    (void)n_cells;
+    (void)cap;
+    return 256;
+}
+
+extern "C" int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, int32_t dtype,
+                                   dsmc_vec3 v, dsmc_xs xs, const double* lambda, dsmc_rng rng,
+                                   int32_t match, int32_t* pair_cnt, void* ws, size_t ws_bytes,
+                                   dsmc_status* st, dsmc_stream_t stream)
+{
+    if (n_cells < 1) return arg_error("dsmc_step_vhs_fused: n_cells=%d", n_cells);
+    if (!cell_start || !lambda || !pair_cnt || !ws || !v.x || !v.y || !v.z)
+        return arg_error("dsmc_step_vhs_fused: null pointer");
+    if (ws_bytes < dsmc_step_vhs_ws(n_cells, 0))
+        return arg_error("dsmc_step_vhs_fused: workspace too small");
+    FusedArgs A;
+    int rc = xs_law_public(xs, &A.C, &A.e);
+    if (rc) return rc;
+    A.n_cells = n_cells;
+    A.cell_start = cell_start;
+    A.lambda = lambda;
+    A.rng = rng;
+    A.match = match;
+    A.pair_cnt = pair_cnt;
+    A.queue = static_cast<int32_t*>(ws);
+    A.st = st;
+    hipStream_t s = as_stream(stream);
+    rc = fill_i32(A.queue, 0, 1, s);
+    if (rc) return rc;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    int blocks = cus * 2;
+    if (blocks > n_cells) blocks = n_cells;
+    if (dtype == DSMC_F64) {
+        k_step_vhs_fused<double><<<blocks, FS_THREADS, 0, s>>>(A, v3<double>(v));
+    } else if (dtype == DSMC_F32) {
+        k_step_vhs_fused<float><<<blocks, FS_THREADS, 0, s>>>(A, v3<float>(v));
+    } else {
+        return arg_error("dsmc_step_vhs_fused: dtype %d", dtype);
+    }
+    DSMC_LAUNCH_CHECK("step_vhs_fused");
+    return DSMC_OK;
+}

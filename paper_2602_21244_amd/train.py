@@ -1,0 +1,129 @@
+"""Train the neural collision operator on pairs our own quadrature labels.
+
+Data ("physics harvesting" on synthetic pairs): rows (v_r, xi, z) with g
+log-uniform on [100, 20000] m/s and isotropic direction; dsmc_harvest_rows
+computes chi(b(z), g) by the quadrature kernel and the target post-collision
+relative velocity.  Each step: forward (MFMA), MSE on the post-collision
+velocities, hand-written backward, Adam with a cosine learning-rate schedule
+decaying to 1e-6 (section "Neural Surrogate Training").
+
+    python -m paper_2602_21244_amd.train --steps 4000 --out weights/jager_surrogate_8x128x4.npz
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import api
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def cosine_lr(t, T, lr_max, lr_min=1e-6):
+    return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * min(t, T) / T))
+
+
+def harvest(workloads, n, seed, dev, pot, quad):
+    rows = workloads.training_rows(seed=seed, n=n)
+    x, g, tgt, chi = api.harvest_rows(torch.as_tensor(rows["vr"], device=dev),
+                                      torch.as_tensor(rows["xi"], device=dev),
+                                      torch.as_tensor(rows["z"], device=dev),
+                                      rows["sigma_v"], workloads.B_MAX, workloads.AR_MASS / 2,
+                                      pot, quad)
+    return x, g, tgt, chi, rows["sigma_v"]
+
+
+def direction_error(vr_pred, vr_tgt):
+    a = vr_pred.double()
+    b = vr_tgt.double()
+    c = (a * b).sum(1) / (a.norm(dim=1) * b.norm(dim=1))
+    return torch.arccos(torch.clamp(c, -1, 1))
+
+
+def train(steps=4000, batch=65536, pool=1 << 20, lr=2e-3, seed=4, dims=None, out=None,
+          log_every=200, dev=None):
+    sys.path.insert(0, os.path.dirname(HERE))
+    import workloads as W
+
+    dev = dev or torch.device("cuda:0")
+    dims = dims or W.SURROGATE_DIMS
+    pot = api.potential_jager(W.JAGER_PLACEHOLDER)
+    quad = api.quad_struct(64)
+    t0 = time.time()
+    x, g, tgt, chi, sigma_v = harvest(W, pool, seed, dev, pot, quad)
+    xv, gv, tv, _, _ = harvest(W, 65536, seed + 1000, dev, pot, quad)
+    torch.cuda.synchronize()
+    print(f"harvested {pool} + 65536 rows in {time.time() - t0:.1f}s", flush=True)
+    Ws, bs = W.mlp_init(seed, dims)
+    master = []
+    for w, b in zip(Ws, bs):
+        master.append(torch.as_tensor(w, dtype=torch.float32, device=dev).contiguous())
+        master.append(torch.as_tensor(b, dtype=torch.float32, device=dev).contiguous())
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=sigma_v, device=dev)
+    mstate = [torch.zeros_like(p) for p in master]
+    vstate = [torch.zeros_like(p) for p in master]
+    grads = [torch.zeros_like(p) for p in master]
+    act = api.workspace(api.neural_act_bytes(net, batch), dev)
+    bws = api.workspace(api.lib().dsmc_neural_backward_ws(__import__("ctypes").byref(net.struct), batch), dev)
+    dvr = torch.empty(batch, 3, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    hist = []
+    t0 = time.time()
+    for t in range(1, steps + 1):
+        idx = torch.randint(0, pool, (batch,), device=dev, generator=gen)
+        xb, gb, tb = x[idx].contiguous(), g[idx].contiguous(), tgt[idx].contiguous()
+        y, vr = api.neural_forward_rows(net, xb, gb, act_save=act)
+        loss.zero_()
+        api.mse_loss(vr, tb, sigma_v, dvr, loss)
+        dW = grads[0::2]
+        db = grads[1::2]
+        api.neural_backward(net, xb, act, y, gb, dvr, dW, db, ws=bws)
+        lr_t = cosine_lr(t, steps, lr)
+        for l in range(len(net.W)):
+            api.adam_step(master[2 * l], grads[2 * l], mstate[2 * l], vstate[2 * l], t, lr_t,
+                          param_bf16=net.W[l])
+            api.adam_step(master[2 * l + 1], grads[2 * l + 1], mstate[2 * l + 1],
+                          vstate[2 * l + 1], t, lr_t, param_bf16=None)
+            net.b[l].copy_(master[2 * l + 1])
+        if t % log_every == 0 or t == 1 or t == steps:
+            yv, vrv = api.neural_forward_rows(net, xv, gv)
+            err = direction_error(vrv, tv)
+            rms = float(torch.sqrt((err ** 2).mean()))
+            hist.append((t, float(loss.item()), rms))
+            print(f"step {t:5d} loss {loss.item():.5f} val dir rms {rms:.4f} rad "
+                  f"lr {lr_t:.2e} ({time.time() - t0:.1f}s)", flush=True)
+    torch.cuda.synchronize()
+    if out:
+        os.makedirs(os.path.dirname(out), exist_ok=True)
+        arrs = {"n_layers": np.int64(len(net.W)), "sigma_v": np.float64(sigma_v),
+                "dims": np.array(dims, np.int64), "history": np.array(hist)}
+        for l in range(len(net.W)):
+            arrs[f"W{l}"] = master[2 * l].double().cpu().numpy()
+            arrs[f"b{l}"] = master[2 * l + 1].double().cpu().numpy()
+        np.savez(out, **arrs)
+        print("saved", out, flush=True)
+    return net, master, hist
+
+
+def main():
+    p = argparse.ArgumentParser()
+    p.add_argument("--steps", type=int, default=4000)
+    p.add_argument("--batch", type=int, default=65536)
+    p.add_argument("--pool", type=int, default=1 << 20)
+    p.add_argument("--lr", type=float, default=2e-3)
+    p.add_argument("--seed", type=int, default=4)
+    p.add_argument("--out", default=os.path.join(HERE, "weights", "jager_surrogate_8x128x4.npz"))
+    a = p.parse_args()
+    train(a.steps, a.batch, a.pool, a.lr, a.seed, out=a.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+"""GPU tests of the batching forms: the persistent fused isotropic step, HIP
+graph capture of a whole step, the schedule autotuner, the autograd wrapper
+and the training loop's effect."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_21244_amd import _lib
+    _lib.load()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def api(dev):
+    from paper_2602_21244_amd import api as A
+    return A
+
+
+def _prepare(api, dev, pop, dtype):
+    cell_of = torch.as_tensor(pop.cell_of, device=dev)
+    v = torch.as_tensor(pop.v, dtype=dtype, device=dev).contiguous()
+    cs, perm, vs = api.sort_cells(cell_of, pop.n_cells, v)
+    return cs, vs, torch.as_tensor(pop.lam, device=dev)
+
+
+def _separate_step(api, dev, pop, cs, vs, lam, seed, step, match):
+    v = vs.clone()
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, v, mom, api.L.MM_CAPTURE)
+    pairs = api.PairList(pop.n_cells, 1 << 21, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, seed, step, pairs)
+    api.collide_vhs(v, pairs, seed, step)
+    if match:
+        api.moment_match(cs, v, mom, api.L.MM_APPLY, pair_cnt=pairs.cnt)
+    return v, pairs
+
+
+def _fused_step(api, dev, pop, cs, vs, lam, seed, step, match, st=None):
+    v = vs.clone()
+    cnt = torch.zeros(pop.n_cells, dtype=torch.int32, device=dev)
+    lib = api.lib()
+    ws = api.workspace(lib.dsmc_step_vhs_ws(pop.n_cells, 0), dev)
+    api.check(lib.dsmc_step_vhs_fused(pop.n_cells, api._ptr(cs), api._dtype(v), api._vec3(v),
+                                      api.xs_struct(pop.xs), api._ptr(lam),
+                                      api.rng_struct(seed, step), int(match), api._ptr(cnt),
+                                      api._ptr(ws), int(ws.numel()), api._ptr(st), api._stream()),
+              "fused")
+    return v, cnt
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("match", [0, 1])
+def test_fused_step_bit_identical(dev, api, dtype, match):
+    say("fused step", dtype, match)
+    pop = W.ragged_population(31, 400, 700, empty_frac=0.15)
+    cs, vs, lam = _prepare(api, dev, pop, dtype)
+    v1, pairs = _separate_step(api, dev, pop, cs, vs, lam, 21, 4, match)
+    v2, cnt = _fused_step(api, dev, pop, cs, vs, lam, 21, 4, match)
+    assert np.array_equal(cnt.cpu().numpy(), pairs.cnt.cpu().numpy())
+    assert torch.equal(v1, v2)
+
+
+def test_fused_step_oversized_cell_left_alone(dev, api):
+    say("fused step oversized cell")
+    pop = W.ragged_population(32, 3, 4000, empty_frac=0.0)
+    cs, vs, lam = _prepare(api, dev, pop, torch.float64)
+    st = api.new_status(dev)
+    v2, cnt = _fused_step(api, dev, pop, cs, vs, lam, 1, 1, 1, st=st)
+    c = cnt.cpu().numpy()
+    n = np.diff(cs.cpu().numpy())
+    big = n > 3072
+    assert np.all(c[big] == -1)
+    s = api.read_status(st)
+    assert (s.flags & api.L.ST_PAIR_OVERFLOW) == (api.L.ST_PAIR_OVERFLOW if big.any() else 0)
+    ocs = cs.cpu().numpy()
+    for k in np.flatnonzero(big):
+        assert torch.equal(v2[:, ocs[k]:ocs[k + 1]], vs[:, ocs[k]:ocs[k + 1]])
+
+
+def test_graph_replay_matches_eager(dev, api):
+    say("hip graph of a whole neural step")
+    pop = W.cavity_grid(seed=3, nx=60, ny=60)
+    cell_of = torch.as_tensor(pop.cell_of, device=dev)
+    v_in = torch.as_tensor(pop.v, dtype=torch.float32, device=dev).contiguous()
+    lam = torch.as_tensor(pop.lam, device=dev)
+    n, nc = pop.n, pop.n_cells
+    lib = api.lib()
+    v = torch.empty_like(v_in)
+    cs = torch.empty(nc + 1, dtype=torch.int32, device=dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    mom = torch.zeros(nc * 6, dtype=torch.float64, device=dev)
+    st = api.new_status(dev)
+    sort_ws = api.workspace(lib.dsmc_sort_cells_ws(n, nc), dev)
+    pairs = api.PairList(nc, 1 << 20, dev)
+    sel_ws = api.workspace(lib.dsmc_select_pairs_ntc_ws(nc, pairs.cap), dev)
+    Ws, bs = W.mlp_init(1, W.SURROGATE_DIMS)
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev)
+    col_ws = api.collide_ws(pairs.cap, v)
+    stream = torch.cuda.Stream()
+
+    def step():
+        api.check(lib.dsmc_sort_cells(n, nc, api._ptr(cell_of), api.L.F32, api._vec3(v_in),
+                                      api._vec3(v), api._ptr(cs), api._ptr(perm),
+                                      api._ptr(sort_ws), int(sort_ws.numel()), api._ptr(st),
+                                      api._stream()), "sort")
+        api.moment_match(cs, v, mom, api.L.MM_CAPTURE)
+        api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 5, 2, pairs, ws=sel_ws, st=st)
+        api.neural_collide(net, v, pairs, 5, 2, ws=col_ws, st=st)
+        api.moment_match(cs, v, mom, api.L.MM_APPLY, pair_cnt=pairs.cnt, st=st)
+
+    with torch.cuda.stream(stream):
+        step()  # eager warm-up (sets kernel attributes outside capture)
+    torch.cuda.synchronize()
+    eager = v.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        step()
+    for rep in range(4):
+        v.zero_()
+        mom.fill_(-1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(v, eager), rep
+        # eager work between replays
+        _ = (v_in * 2).sum().item()
+
+
+def test_autotune_installs_best_threshold(dev, api):
+    say("autotune")
+    from paper_2602_21244_amd import autotune
+    pop = W.cylinder_grid(seed=5, order="realistic", scale=0.05)
+    cs, vs, lam = _prepare(api, dev, pop, torch.float32)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, vs, mom, api.L.MM_CAPTURE)
+    pairs = api.PairList(pop.n_cells, 1 << 22, dev)
+    api.select_pairs_ntc(cs, vs, pop.xs, lam, mom, 3, 1, pairs)
+    ws = api.collide_ws(pairs.cap, vs)
+    api.collide_vhs(vs.clone(), pairs, 3, 1, schedule=api.L.SCHED_DEFER, ws=ws)
+    thr, times = autotune.tune_block_threshold(vs, pairs, ws, use_cache=False)
+    say("  thresholds ms:", times)
+    assert api.get_block_threshold() == thr
+    assert times[thr] == min(times.values())
+
+
+def test_autograd_function_matches_direct_calls(orc, dev, api):
+    say("autograd wrapper")
+    from paper_2602_21244_amd.autograd import surrogate
+    rows = W.training_rows(seed=12, n=512)
+    Ws, bs = W.mlp_init(9, W.FD_DIMS)
+    net = api.Net(Ws, bs, act="silu", wdtype="f64", sigma_v=rows["sigma_v"], device=dev)
+    params = []
+    for w, b in zip(net.W, net.b):
+        params += [w.clone().requires_grad_(True), b.clone().requires_grad_(True)]
+    x = torch.as_tensor(orc.network_input(rows["vr"], rows["xi"], rows["z"], rows["sigma_v"]),
+                        device=dev).requires_grad_(True)
+    g = torch.as_tensor(rows["g"], device=dev)
+    tgt = torch.as_tensor(rows["vr"][:, [1, 2, 0]], device=dev)
+    vr, y = surrogate(net, x, g, params)
+    loss = ((vr - tgt) ** 2).sum() / (4 * rows["sigma_v"] ** 2 * 512)
+    loss.backward()
+    G = orc.surrogate_loss_grad(vr.detach().cpu().numpy(), tgt.cpu().numpy(), rows["sigma_v"])
+    dy = orc.project_backward(G, y.detach().cpu().numpy(), rows["g"])
+    rW, rb, rx = orc.mlp_backward(Ws, bs, x.detach().cpu().numpy(), dy, "silu")
+    for l in range(len(Ws)):
+        np.testing.assert_allclose(params[2 * l].grad.cpu().numpy(), rW[l], rtol=1e-9, atol=1e-14)
+        np.testing.assert_allclose(params[2 * l + 1].grad.cpu().numpy(), rb[l], rtol=1e-9, atol=1e-14)
+    np.testing.assert_allclose(x.grad.cpu().numpy(), rx, rtol=1e-9, atol=1e-14)
+
+
+def test_training_reduces_error_and_beats_isotropic(dev, api):
+    """The trained surrogate reproduces the ab initio scattering far better
+    than the isotropic law it replaces, and its latent inputs matter."""
+    say("short training run")
+    from paper_2602_21244_amd import train as T
+    net, master, hist = T.train(steps=300, batch=16384, pool=1 << 16, lr=3e-3, seed=7,
+                                log_every=100, dev=dev)
+    first, last = hist[0][2], hist[-1][2]
+    say(f"  direction rms: start {first:.3f} -> end {last:.3f} rad")
+    assert last < 0.8 * first
+    pot = api.potential_jager(W.JAGER_PLACEHOLDER)
+    xv, gv, tv, _, sv = T.harvest(W, 16384, 99, dev, pot, api.quad_struct(64))
+    y, vr = api.neural_forward_rows(net, xv, gv)
+    err_net = float(torch.sqrt((T.direction_error(vr, tv) ** 2).mean()))
+    # isotropic law: a uniform random direction (independent of the target)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1)
+    d = torch.randn(16384, 3, device=dev, generator=gen, dtype=torch.float64)
+    err_iso = float(torch.sqrt((T.direction_error(d, tv) ** 2).mean()))
+    xz = xv.clone()
+    xz[:, 3:8] = 0.0
+    _, vr0 = api.neural_forward_rows(net, xz, gv)
+    err_nolat = float(torch.sqrt((T.direction_error(vr0, tv) ** 2).mean()))
+    say(f"  network {err_net:.3f}, isotropic {err_iso:.3f}, latents zeroed {err_nolat:.3f}")
+    assert err_net < 0.7 * err_iso
+    assert err_nolat > err_net
