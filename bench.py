@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--order", default="realistic", choices=["realistic", "shuffled", "sorted"])
     p.add_argument("--quad-steps", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run a plain 1 GiB device copy first (reference for counter scaling)")
     p.add_argument("--cpu-sample-pairs", type=int, default=1_200_000)
     p.add_argument("--weights", default=os.path.join(ROOT, "paper_2602_21244_amd", "weights",
                                                      "jager_surrogate_8x128x4.npz"))
@@ -84,6 +86,14 @@ def main():
     log(f"workload {wname}: {pop.n} particles, {pop.n_cells} cells ({time.time() - t0:.1f}s)")
 
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     cell_of = torch.as_tensor(pop.cell_of, device=dev)
     v_in = torch.as_tensor(pop.v, dtype=torch.float32, device=dev).contiguous()
     lam = torch.as_tensor(pop.lam, device=dev)
@@ -222,6 +232,12 @@ def main():
         "cells": n_cells,
     }
 
+    # surrogate training step (batch 65 536 harvested rows): forward (MFMA),
+    # MSE, hand-written backward, Adam on every parameter
+    train = train_step_timing(api, W, dev, net, sigma_v)
+    extra["train_step"] = train
+    log(f"training step: {train}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pop, Ws, bs, sigma_v, args.cpu_sample_pairs)
@@ -248,6 +264,59 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def train_step_timing(api, W, dev, net, sigma_v, B=65536, steps=5):
+    import ctypes
+
+    import torch
+    rows = W.training_rows(seed=4, n=B)
+    pot = api.potential_jager(W.JAGER_PLACEHOLDER)
+    x, g, tgt, chi = api.harvest_rows(torch.as_tensor(rows["vr"], device=dev),
+                                      torch.as_tensor(rows["xi"], device=dev),
+                                      torch.as_tensor(rows["z"], device=dev), rows["sigma_v"],
+                                      W.B_MAX, W.AR_MASS / 2, pot, api.quad_struct(64))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    api.harvest_rows(torch.as_tensor(rows["vr"], device=dev), torch.as_tensor(rows["xi"], device=dev),
+                     torch.as_tensor(rows["z"], device=dev), rows["sigma_v"], W.B_MAX,
+                     W.AR_MASS / 2, pot, api.quad_struct(64))
+    e1.record()
+    torch.cuda.synchronize()
+    harvest_ms = e0.elapsed_time(e1)
+    master = []
+    for w, b in zip(net.W, net.b):
+        master += [w.float().clone(), b.clone()]
+    ms_ = [torch.zeros_like(p) for p in master]
+    vs_ = [torch.zeros_like(p) for p in master]
+    grads = [torch.zeros_like(p) for p in master]
+    act = api.workspace(api.neural_act_bytes(net, B), dev)
+    bws = api.workspace(api.lib().dsmc_neural_backward_ws(ctypes.byref(net.struct), B), dev)
+    dvr = torch.empty(B, 3, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    evs = []
+
+    def one(t):
+        y, vr = api.neural_forward_rows(net, x, g, act_save=act)
+        api.mse_loss(vr, tgt, sigma_v, dvr, loss)
+        api.neural_backward(net, x, act, y, g, dvr, grads[0::2], grads[1::2], ws=bws)
+        for l in range(len(net.W)):
+            api.adam_step(master[2 * l], grads[2 * l], ms_[2 * l], vs_[2 * l], t, 1e-4,
+                          param_bf16=net.W[l])
+            api.adam_step(master[2 * l + 1], grads[2 * l + 1], ms_[2 * l + 1], vs_[2 * l + 1], t, 1e-4)
+
+    one(1)
+    torch.cuda.synchronize()
+    a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for t in range(steps):
+        one(t + 2)
+    b_.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b_) / steps
+    flop = 3 * MLP_FLOP_PER_PAIR * B
+    return {"batch": B, "ms_per_step": ms, "algorithmic_TFLOPs": flop / (ms * 1e-3) / 1e12,
+            "harvest_ms_65536_rows": harvest_ms}
 
 
 def cpu_baseline(pop, Ws, bs, sigma_v, sample_pairs):

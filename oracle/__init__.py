@@ -71,12 +71,12 @@ def _declare(L):
     L.orc_sort_cells.restype = C.c_int
     L.orc_moments.argtypes = [C.c_int32, _i32p, _f64p, _f64p, _f64p, _f64p]
     L.orc_select_ntc.argtypes = [C.c_int32, _i32p, _f64p, _f64p, _f64p, C.c_double,
-                                 C.c_double, _f64p, _f64p, C.c_uint64, C.c_uint32,
+                                 C.c_double, _f64p, _f64p, C.c_uint64, C.c_uint32, C.c_int32,
                                  _i32p, _i32p, _i32p, _i32p, _i32p, C.c_int64,
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.orc_select_ntc.restype = C.c_int
     L.orc_pair_latents.argtypes = [C.c_int64, _i32p, _i32p, C.c_uint64, C.c_uint32,
-                                   C.c_int, _f64p, _f64p, _f64p]
+                                   C.c_int32, C.c_int, _f64p, _f64p, _f64p]
     L.orc_vhs_dirs.argtypes = [C.c_int64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p,
                                _f64p, _f64p]
     L.orc_apply_dirs.argtypes = [C.c_int32, _i32p, _i32p, _i32p, _i32p, _f64p, _f64p,
@@ -156,9 +156,10 @@ def sigma_g_law(xs):
     raise ValueError(xs["kind"])
 
 
-def select_ntc(cell_start, v, xs, lam, mom, seed, step, cap=None):
+def select_ntc(cell_start, v, xs, lam, mom, seed, step, cap=None, cell_base=0):
     """NTC selection; returns dict with pair_off, pair_cnt, pair_i, pair_j,
-    pair_cell (dense, cell-major, candidate order), n_cand, overflow."""
+    pair_cell (dense, cell-major, candidate order), n_cand, overflow.
+    cell_base: global id of the first cell (keys the random numbers)."""
     cs = _c(cell_start, np.int32)
     n_cells = len(cs) - 1
     Cc, e = sigma_g_law(xs)
@@ -172,26 +173,28 @@ def select_ntc(cell_start, v, xs, lam, mom, seed, step, cap=None):
     probe = np.zeros(1, np.int32)
     rc = lib().orc_select_ntc(n_cells, cs, _c(v[0], np.float64), _c(v[1], np.float64),
                               _c(v[2], np.float64), Cc, e, _c(lam, np.float64),
-                              _c(mom, np.float64).reshape(-1), int(seed), int(step), off,
-                              cnt, probe, probe, probe, -1, C.byref(nc), C.byref(npair))
+                              _c(mom, np.float64).reshape(-1), int(seed), int(step),
+                              int(cell_base), off, cnt, probe, probe, probe, -1, C.byref(nc),
+                              C.byref(npair))
     total = nc.value
     if total > cap:
         return {"overflow": True, "n_cand": total, "pair_off": np.zeros(n_cells, np.int32),
                 "pair_cnt": np.zeros(n_cells, np.int32),
                 "pair_i": np.zeros(0, np.int32), "pair_j": np.zeros(0, np.int32),
-                "pair_cell": np.zeros(0, np.int32)}
+                "pair_cell": np.zeros(0, np.int32), "cell_base": int(cell_base)}
     pi = np.zeros(max(total, 1), np.int32)
     pj = np.zeros(max(total, 1), np.int32)
     pc = np.zeros(max(total, 1), np.int32)
     rc = lib().orc_select_ntc(n_cells, cs, _c(v[0], np.float64), _c(v[1], np.float64),
                               _c(v[2], np.float64), Cc, e, _c(lam, np.float64),
-                              _c(mom, np.float64).reshape(-1), int(seed), int(step), off,
-                              cnt, pi, pj, pc, total, C.byref(nc), C.byref(npair))
+                              _c(mom, np.float64).reshape(-1), int(seed), int(step),
+                              int(cell_base), off, cnt, pi, pj, pc, total, C.byref(nc),
+                              C.byref(npair))
     assert rc == 0
     m = npair.value
     return {"overflow": False, "n_cand": total, "pair_off": off[:n_cells],
             "pair_cnt": cnt[:n_cells], "pair_i": pi[:m], "pair_j": pj[:m],
-            "pair_cell": pc[:m]}
+            "pair_cell": pc[:m], "cell_base": int(cell_base)}
 
 
 def pair_latents(sel, seed, step, lowp=False):
@@ -204,7 +207,8 @@ def pair_latents(sel, seed, step, lowp=False):
     if len(off) == 0:
         off = np.zeros(1, np.int32)
     lib().orc_pair_latents(m, _c(sel["pair_cell"], np.int32) if m else np.zeros(1, np.int32),
-                           off, int(seed), int(step), int(bool(lowp)), U, xi, z)
+                           off, int(seed), int(step), int(sel.get("cell_base", 0)),
+                           int(bool(lowp)), U, xi, z)
     return U[: 6 * m].reshape(m, 6), xi[: 3 * m].reshape(m, 3), z[: 2 * m].reshape(m, 2)
 
 
@@ -474,17 +478,20 @@ def cosine_lr(t, T, lr_max, lr_min=1e-6):
 # Whole-step compositions (sorted arrays in, sorted arrays out)
 # ---------------------------------------------------------------------------
 def step(cell_start, v, xs, lam, seed, step_no, rule="vhs", lowp=False,
-         match=None, net=None, pot=None, b_max=1e-9, m_red=None, cap=None):
+         match=None, net=None, pot=None, b_max=1e-9, m_red=None, cap=None, cell_base=0):
     """One collision step on sorted velocities: select (pre-step velocities),
     Phase A per pair, Phase B in candidate order per cell, then moment matching.
 
     rule: "vhs" | "jager" | "neural".  net: dict(Ws, bs, act, sigma_v) for
     the neural rule.  match: None -> on for "neural", off otherwise.
+    cell_base: global id of cell 0 of these arrays (a contiguous range of a
+    larger population can be stepped on its own: the random numbers are keyed
+    by the global cell id).
     Returns (v_new, info dict).
     """
     v = np.asarray(v, np.float64)
     mom = moments(cell_start, v)
-    sel = select_ntc(cell_start, v, xs, lam, mom, seed, step_no, cap=cap)
+    sel = select_ntc(cell_start, v, xs, lam, mom, seed, step_no, cap=cap, cell_base=cell_base)
     if sel["overflow"]:
         return v.copy(), {"sel": sel, "mom": mom}
     U, xi, z = pair_latents(sel, seed, step_no, lowp=lowp)

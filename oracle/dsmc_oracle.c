@@ -190,14 +190,15 @@ static int32_t cell_select(int32_t s0, int32_t N, int32_t M, double xs_e, const 
 int orc_select_ntc(int32_t n_cells, const int32_t* cell_start, const double* vx,
                    const double* vy, const double* vz, double xs_C, double xs_e,
                    const double* lambda, const double* mom, uint64_t seed,
-                   uint32_t step, int32_t* pair_off, int32_t* pair_cnt,
+                   uint32_t step, int32_t cell_base, int32_t* pair_off, int32_t* pair_cnt,
                    int32_t* pair_i, int32_t* pair_j, int32_t* pair_cell,
                    int64_t cap, int64_t* n_cand_total, int64_t* n_pairs_total)
 {
     int64_t total = 0;
     for (int32_t k = 0; k < n_cells; ++k) {
         int32_t N = cell_start[k + 1] - cell_start[k];
-        total += cell_candidates(N, lambda[k], xs_C, xs_e, mom + 6 * (size_t)k, seed, step, k);
+        total += cell_candidates(N, lambda[k], xs_C, xs_e, mom + 6 * (size_t)k, seed, step,
+                                 cell_base + k);
     }
     *n_cand_total = total;
     if (total > cap) {
@@ -211,14 +212,15 @@ int orc_select_ntc(int32_t n_cells, const int32_t* cell_start, const double* vx,
     int32_t lcap = 0;
     for (int32_t k = 0; k < n_cells; ++k) {
         int32_t s0 = cell_start[k], N = cell_start[k + 1] - s0;
-        int32_t M = cell_candidates(N, lambda[k], xs_C, xs_e, mom + 6 * (size_t)k, seed, step, k);
+        int32_t M = cell_candidates(N, lambda[k], xs_C, xs_e, mom + 6 * (size_t)k, seed, step,
+                                    cell_base + k);
         if (M > lcap) {
             lcap = M;
             li = (int32_t*)realloc(li, sizeof(int32_t) * (size_t)lcap);
             lj = (int32_t*)realloc(lj, sizeof(int32_t) * (size_t)lcap);
         }
         int32_t a = cell_select(s0, N, M, xs_e, mom + 6 * (size_t)k, vx, vy, vz, seed, step,
-                                k, li, lj);
+                                cell_base + k, li, lj);
         pair_off[k] = (int32_t)np;
         pair_cnt[k] = a;
         for (int32_t q = 0; q < a; ++q) {
@@ -274,13 +276,13 @@ static void latents_from_uniforms(const double U[6], double xi[3], double z[2])
 }
 
 void orc_pair_latents(int64_t np, const int32_t* pair_cell, const int32_t* pair_off,
-                      uint64_t seed, uint32_t step, int lowp, double* U, double* xi,
-                      double* z)
+                      uint64_t seed, uint32_t step, int32_t cell_base, int lowp, double* U,
+                      double* xi, double* z)
 {
     for (int64_t p = 0; p < np; ++p) {
         int32_t k = pair_cell[p];
         uint32_t a = (uint32_t)(p - pair_off[k]);
-        pair_uniforms(seed, step, a, (uint32_t)k, lowp, U + 6 * p);
+        pair_uniforms(seed, step, a, (uint32_t)(cell_base + k), lowp, U + 6 * p);
         latents_from_uniforms(U + 6 * p, xi + 3 * p, z + 2 * p);
     }
 }

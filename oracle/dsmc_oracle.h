@@ -36,20 +36,22 @@ void orc_moments(int32_t n_cells, const int32_t* cell_start, const double* vx,
                  const double* vy, const double* vz, double* mom);
 
 /* NTC selection (section "Cell partition and collision-pair selection").
- * sigma*g = xs_C * g^xs_e.  Returns 0, or 1 on pair-capacity overflow (then
+ * sigma*g = xs_C * g^xs_e.  Cell k of the arrays is global cell cell_base + k
+ * (the id that keys the random numbers), so a contiguous range of cells can
+ * be checked on its own.  Returns 0, or 1 on pair-capacity overflow (then
  * *n_cand_total holds the required capacity and no pair is written). */
 int orc_select_ntc(int32_t n_cells, const int32_t* cell_start, const double* vx,
                    const double* vy, const double* vz, double xs_C, double xs_e,
                    const double* lambda, const double* mom, uint64_t seed,
-                   uint32_t step, int32_t* pair_off, int32_t* pair_cnt,
+                   uint32_t step, int32_t cell_base, int32_t* pair_off, int32_t* pair_cnt,
                    int32_t* pair_i, int32_t* pair_j, int32_t* pair_cell,
                    int64_t cap, int64_t* n_cand_total, int64_t* n_pairs_total);
 
 /* Per-pair latent draws.  U[6p..6p+5] uniforms, xi[3p..] and z[2p..] normals.
  * lowp = 1 selects the 24-bit uniform construction used for FP32 velocities. */
 void orc_pair_latents(int64_t np, const int32_t* pair_cell, const int32_t* pair_off,
-                      uint64_t seed, uint32_t step, int lowp, double* U, double* xi,
-                      double* z);
+                      uint64_t seed, uint32_t step, int32_t cell_base, int lowp, double* U,
+                      double* xi, double* z);
 
 /* Isotropic (VHS/HS) post-collision direction from pre-step velocities. */
 void orc_vhs_dirs(int64_t np, const int32_t* pair_i, const int32_t* pair_j,

@@ -14,6 +14,7 @@
 // FP64 (and FP32) reference path: plain per-element kernels, used for parity
 // with the FP64 oracle and for finite-difference gradient checks.
 #include <math.h>
+#include <stdlib.h>
 
 #include "collide.hpp"
 
@@ -72,10 +73,12 @@ static bool mfma_shape_ok(const MlpDev& d, int* H)
     return true;
 }
 
-__device__ __forceinline__ float act_f(float z, int act)
+template <int ACT>
+__device__ __forceinline__ float act_f(float z)
 {
-    if (act == DSMC_ACT_RELU) return z > 0.f ? z : 0.f;
-    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+    if (ACT == DSMC_ACT_RELU) return z > 0.f ? z : 0.f;
+    // SiLU: z * sigmoid(z) with the hardware exp2 and reciprocal
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
 
 template <typename T>
@@ -166,11 +169,12 @@ __device__ __forceinline__ floatx16 bias_init(const float* bl, int boff, int nb,
     return a;
 }
 
-__device__ __forceinline__ bf16x8 to_frag(const floatx16& a, int jp, int act)
+template <int ACT>
+__device__ __forceinline__ bf16x8 to_frag(const floatx16& a, int jp)
 {
     bf16x8 o;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) o[e] = (__bf16)act_f(a[8 * jp + e], act);
+    for (int e = 0; e < 8; ++e) o[e] = (__bf16)act_f<ACT>(a[8 * jp + e]);
     return o;
 }
 
@@ -191,11 +195,12 @@ template <typename VT> struct PairsIO {
     PairBuf<VT> out;
 };
 
-// Input fragments of one 32-row tile: lane (row, h) supplies features
+// Each wave processes NT tiles of 32 rows; every A fragment read from LDS
+// feeds NT MFMAs.  Input fragments of a tile: lane (row, h) supplies features
 // 16 ks + 8 h + e.  PAIRS mode builds x = [v_r / sigma_v, xi, z] in the
 // lane-half-0 lanes (dims[0] == 8).
-template <int H, bool PAIRS, typename VT>
-__global__ void __launch_bounds__(512)
+template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT>
+__global__ void __launch_bounds__(NT == 1 ? 512 : 256)
 k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -207,107 +212,147 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
     const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
     const int waves = blockDim.x >> 6;
     const int64_t nrows = PAIRS ? pio.pr.total(pio.n_cells) : rio.B;
-    const int L = d.L, act = d.act, dout = d.dims[L];
+    const int L = d.L, dout = d.dims[L];
     constexpr int NB = H / 32, KS = H / 16;
 
-    for (int64_t tile = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); tile * 32 < nrows;
-         tile += (int64_t)gridDim.x * waves) {
-        const int64_t row = tile * 32 + col;
-        const bool valid = row < nrows;
-        bf16x8 bin[2];
-        VT keep_vh[3] = {1, 0, 0}, keep_xi[3] = {0, 0, 0}, keep_u4 = 0;
+    for (int64_t grp = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); grp * 32 * NT < nrows;
+         grp += (int64_t)gridDim.x * waves) {
+        int64_t row[NT];
+        bool valid[NT];
+        bf16x8 bin[NT][2];
+        VT keep_vh[NT][3], keep_xi[NT][3], keep_u4[NT];
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) bin[q][e] = (__bf16)0.0f;
-        if (PAIRS) {
-            if (h == 0 && valid) {
-                const int32_t k = pio.pr.cell[row];
-                const uint32_t a = (uint32_t)(row - pio.pr.off[k]);
-                VT xi[3], z[2], u4;
-                pair_latents(pio.rng, a, (uint32_t)k, xi, z, u4);
-                const int32_t i = pio.pr.i[row], j = pio.pr.j[row];
-                const VT rx = pio.v.x[i] - pio.v.x[j], ry = pio.v.y[i] - pio.v.y[j],
-                         rz = pio.v.z[i] - pio.v.z[j];
-                unit3<VT>(rx, ry, rz, keep_vh);
-                keep_xi[0] = xi[0]; keep_xi[1] = xi[1]; keep_xi[2] = xi[2];
-                keep_u4 = u4;
-                const VT isv = (VT)d.inv_sigma_v;
-                bin[0][0] = (__bf16)(float)(rx * isv);
-                bin[0][1] = (__bf16)(float)(ry * isv);
-                bin[0][2] = (__bf16)(float)(rz * isv);
-                bin[0][3] = (__bf16)(float)xi[0];
-                bin[0][4] = (__bf16)(float)xi[1];
-                bin[0][5] = (__bf16)(float)xi[2];
-                bin[0][6] = (__bf16)(float)z[0];
-                bin[0][7] = (__bf16)(float)z[1];
-            }
-        } else if (valid) {
-            const int din = d.dims[0];
+        for (int t = 0; t < NT; ++t) {
+            row[t] = (grp * NT + t) * 32 + col;
+            valid[t] = row[t] < nrows;
+            keep_vh[t][0] = 1; keep_vh[t][1] = 0; keep_vh[t][2] = 0;
+            keep_xi[t][0] = 0; keep_xi[t][1] = 0; keep_xi[t][2] = 0;
+            keep_u4[t] = 0;
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int c = 16 * q + 8 * h + e;
-                    if (c < din) bin[q][e] = (__bf16)rio.x[row * din + c];
+                for (int e = 0; e < 8; ++e) bin[t][q][e] = (__bf16)0.0f;
+            if (PAIRS) {
+                if (h == 0 && valid[t]) {
+                    const int64_t r = row[t];
+                    const int32_t k = pio.pr.cell[r];
+                    const uint32_t a = (uint32_t)(r - pio.pr.off[k]);
+                    VT xi[3], z[2], u4;
+                    pair_latents(pio.rng, a, (uint32_t)k, xi, z, u4);
+                    const int32_t i = pio.pr.i[r], j = pio.pr.j[r];
+                    const VT rx = pio.v.x[i] - pio.v.x[j], ry = pio.v.y[i] - pio.v.y[j],
+                             rz = pio.v.z[i] - pio.v.z[j];
+                    unit3<VT>(rx, ry, rz, keep_vh[t]);
+                    keep_xi[t][0] = xi[0]; keep_xi[t][1] = xi[1]; keep_xi[t][2] = xi[2];
+                    keep_u4[t] = u4;
+                    const VT isv = (VT)d.inv_sigma_v;
+                    bin[t][0][0] = (__bf16)(float)(rx * isv);
+                    bin[t][0][1] = (__bf16)(float)(ry * isv);
+                    bin[t][0][2] = (__bf16)(float)(rz * isv);
+                    bin[t][0][3] = (__bf16)(float)xi[0];
+                    bin[t][0][4] = (__bf16)(float)xi[1];
+                    bin[t][0][5] = (__bf16)(float)xi[2];
+                    bin[t][0][6] = (__bf16)(float)z[0];
+                    bin[t][0][7] = (__bf16)(float)z[1];
                 }
+            } else if (valid[t]) {
+                const int din = d.dims[0];
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int c = 16 * q + 8 * h + e;
+                        if (c < din) bin[t][q][e] = (__bf16)rio.x[row[t] * din + c];
+                    }
+            }
         }
 
-        floatx16 acc[NB];
-        bf16x8 bfr[KS];
+        floatx16 acc[NT][NB];
+        bf16x8 bfr[NT][KS];
         // input layer
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = bias_init(bl, f.bias_off[0], nb, h);
+        for (int nb = 0; nb < NB; ++nb) {
+            const floatx16 b0 = bias_init(bl, f.bias_off[0], nb, h);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t][nb] = b0;
+        }
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             if (ks >= f.ks[0]) break;
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    lds_frag(wl, f.off[0], nb * f.ks[0] + ks, lane), bin[ks], acc[nb], 0, 0, 0);
+            for (int nb = 0; nb < NB; ++nb) {
+                const bf16x8 a = lds_frag(wl, f.off[0], nb * f.ks[0] + ks, lane);
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bin[t][ks], acc[t][nb], 0, 0, 0);
+            }
         }
         // hidden layers
         for (int l = 1; l < L; ++l) {
-            if (rio.zsave && valid) {
+            if (SAVE) {
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
+                for (int t = 0; t < NT; ++t) {
+                    if (!valid[t]) continue;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        rio.zsave[((size_t)(l - 1) * rio.B + row) * H + nb * 32 + acc_row(r, h)] =
-                            acc[nb][r];
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            rio.zsave[((size_t)(l - 1) * rio.B + row[t]) * H + nb * 32 + acc_row(r, h)] =
+                                acc[t][nb][r];
+                }
             }
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                bfr[2 * nb] = to_frag(acc[nb], 0, act);
-                bfr[2 * nb + 1] = to_frag(acc[nb], 1, act);
-            }
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    bfr[t][2 * nb] = to_frag<ACT>(acc[t][nb], 0);
+                    bfr[t][2 * nb + 1] = to_frag<ACT>(acc[t][nb], 1);
+                }
             if (l == L - 1) break;
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[nb] = bias_init(bl, f.bias_off[l], nb, h);
+            for (int nb = 0; nb < NB; ++nb) {
+                const floatx16 b0 = bias_init(bl, f.bias_off[l], nb, h);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t][nb] = b0;
+            }
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        lds_frag(wl, f.off[l], nb * KS + ks, lane), bfr[ks], acc[nb], 0, 0, 0);
+                for (int nb = 0; nb < NB; ++nb) {
+                    const bf16x8 a = lds_frag(wl, f.off[l], nb * KS + ks, lane);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[t][ks], acc[t][nb], 0, 0, 0);
+                }
         }
         // output layer (<= 32 outputs: one block)
-        floatx16 ao = bias_init(bl, f.bias_off[L - 1], 0, h);
+        floatx16 ao[NT];
+        {
+            const floatx16 b0 = bias_init(bl, f.bias_off[L - 1], 0, h);
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            ao = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lds_frag(wl, f.off[L - 1], ks, lane),
-                                                         bfr[ks], ao, 0, 0, 0);
-        if (!valid) continue;
-        if (!PAIRS) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int n = acc_row(r, h);
-                if (n < dout) rio.y_raw[row * dout + n] = ao[r];
-            }
+            for (int t = 0; t < NT; ++t) ao[t] = b0;
         }
-        if (h == 0) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf16x8 a = lds_frag(wl, f.off[L - 1], ks, lane);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                ao[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[t][ks], ao[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (!valid[t]) continue;
+            const int64_t r0 = row[t];
+            if (!PAIRS) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int n = acc_row(r, h);
+                    if (n < dout) rio.y_raw[r0 * dout + n] = ao[t][r];
+                }
+            }
+            if (h != 0) continue;
             // outputs 0..2 sit in registers 0..2 of lane-half 0
-            const float y0 = ao[0], y1 = ao[1], y2 = ao[2];
+            const float y0 = ao[t][0], y1 = ao[t][1], y2 = ao[t][2];
             const float nrm = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
             if (PAIRS) {
                 VT u[3];
@@ -316,30 +361,40 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                 } else {
                     // degenerate output: the isotropic direction of this pair
                     VT e[3];
-                    const VT cc = VT(2) * keep_u4 - VT(1);
-                    const VT sc = VT(2) * dev_sqrt<VT>(keep_u4 * (VT(1) - keep_u4));
-                    perp_dir<VT>(keep_xi, keep_vh, e);
-                    for (int q = 0; q < 3; ++q) u[q] = cc * keep_vh[q] + sc * e[q];
+                    const VT cc = VT(2) * keep_u4[t] - VT(1);
+                    const VT sc = VT(2) * dev_sqrt<VT>(keep_u4[t] * (VT(1) - keep_u4[t]));
+                    perp_dir<VT>(keep_xi[t], keep_vh[t], e);
+                    for (int q = 0; q < 3; ++q) u[q] = cc * keep_vh[t][q] + sc * e[q];
                 }
-                pio.out.a[row] = u[0];
-                pio.out.b[row] = u[1];
-                pio.out.c[row] = u[2];
+                pio.out.a[r0] = u[0];
+                pio.out.b[r0] = u[1];
+                pio.out.c[r0] = u[2];
             } else if (rio.vr_out && dout == 3) {
-                const float gg = rio.g[row];
-                const float s = nrm > 1e-30f ? gg / nrm : 0.0f;
-                rio.vr_out[3 * row + 0] = y0 * s;
-                rio.vr_out[3 * row + 1] = y1 * s;
-                rio.vr_out[3 * row + 2] = y2 * s;
+                const float gg = rio.g[r0];
+                const float sg = nrm > 1e-30f ? gg / nrm : 0.0f;
+                rio.vr_out[3 * r0 + 0] = y0 * sg;
+                rio.vr_out[3 * r0 + 1] = y1 * sg;
+                rio.vr_out[3 * r0 + 2] = y2 * sg;
             }
         }
     }
 }
 
-template <int H, bool PAIRS, typename VT>
-static int launch_mlp_bf16(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
-                           int64_t max_rows, hipStream_t s)
+static int mlp_tiles_per_wave()
 {
-    auto kern = k_mlp_bf16<H, PAIRS, VT>;
+    static int nt = -1;
+    if (nt < 0) {
+        const char* e = getenv("DSMC_MLP_TILES_PER_WAVE");
+        nt = (e && atoi(e) == 2) ? 2 : 1;
+    }
+    return nt;
+}
+
+template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT>
+static int launch_one(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
+                      int64_t max_rows, hipStream_t s)
+{
+    auto kern = k_mlp_bf16<H, PAIRS, VT, ACT, SAVE, NT>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -352,13 +407,36 @@ static int launch_mlp_bf16(const MlpDev& d, const FragLayout& f, RowsIO rio, Pai
         hipDeviceProp_t p;
         if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
     }
-    int64_t tiles = (max_rows + 31) / 32;
-    int64_t blocks = (tiles + 7) / 8;
+    const int threads = NT == 1 ? 512 : 256;
+    const int64_t groups = (max_rows + 32 * NT - 1) / (32 * NT);
+    int64_t blocks = (groups + threads / 64 - 1) / (threads / 64);
     if (blocks > cus) blocks = cus;
     if (blocks < 1) blocks = 1;
-    kern<<<(int)blocks, 512, f.bytes, s>>>(d, f, rio, pio);
+    kern<<<(int)blocks, threads, f.bytes, s>>>(d, f, rio, pio);
     DSMC_LAUNCH_CHECK("mlp_bf16");
     return DSMC_OK;
+}
+
+template <int H, bool PAIRS, typename VT, int ACT, bool SAVE>
+static int launch_nt(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
+                     int64_t max_rows, hipStream_t s)
+{
+    if (mlp_tiles_per_wave() == 2)
+        return launch_one<H, PAIRS, VT, ACT, SAVE, 2>(d, f, rio, pio, max_rows, s);
+    return launch_one<H, PAIRS, VT, ACT, SAVE, 1>(d, f, rio, pio, max_rows, s);
+}
+
+template <int H, bool PAIRS, typename VT>
+static int launch_mlp_bf16(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
+                           int64_t max_rows, hipStream_t s)
+{
+    const bool save = !PAIRS && rio.zsave != nullptr;
+    if (d.act == DSMC_ACT_SILU) {
+        if (save) return launch_nt<H, PAIRS, VT, DSMC_ACT_SILU, true>(d, f, rio, pio, max_rows, s);
+        return launch_nt<H, PAIRS, VT, DSMC_ACT_SILU, false>(d, f, rio, pio, max_rows, s);
+    }
+    if (save) return launch_nt<H, PAIRS, VT, DSMC_ACT_RELU, true>(d, f, rio, pio, max_rows, s);
+    return launch_nt<H, PAIRS, VT, DSMC_ACT_RELU, false>(d, f, rio, pio, max_rows, s);
 }
 
 // ------------------------------------------------------------------------
@@ -517,26 +595,26 @@ k_project_backward(int64_t B, const T* __restrict__ Y, int dout, const T* __rest
 }
 
 // h_{l-1} for layer l's weight gradient: x for l == 0, act(z) otherwise
-// (rounded to bf16 when the network is bf16).
-template <typename T>
-__device__ __forceinline__ T hprev(const T* X, const T* Zp, int64_t r, int k, int in, int l,
-                                   int act, bool bf16)
-{
-    if (l == 0) {
-        const T x = X[r * in + k];
-        return bf16 ? (T)(float)(__bf16)(float)x : x;
-    }
-    const T a = act_t<T>(Zp[r * in + k], act);
-    return bf16 ? (T)(float)(__bf16)(float)a : a;
-}
-
-// Partial sums over row chunks: part[c][n][k] = sum_{r in chunk c} dY[r][n] h[r][k],
-// partb[c][n] = sum dY[r][n].  One thread per (n, k) of one chunk.
+// (rounded to bf16 when the network is bf16, as the forward used it).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_dw_partial(int64_t B, int64_t chunk, const T* __restrict__ dY, int out, const T* __restrict__ X,
-             const T* __restrict__ Zp, int in, int l, int act, int bf16, T* __restrict__ part,
-             T* __restrict__ partb)
+k_hprev(int64_t n_el, const T* __restrict__ X, const T* __restrict__ Zp, int l, int act, int bf16,
+        T* __restrict__ H)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_el;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const T a = (l == 0) ? X[q] : act_t<T>(Zp[q], act);
+        H[q] = bf16 ? (T)(float)(__bf16)(float)a : a;
+    }
+}
+
+// Partial sums over row chunks: part[c][n][k] = sum_{r in chunk c} dY[r][n] H[r][k],
+// partb[c][n] = sum dY[r][n].  One thread per (n, k) of one chunk; threads of
+// a block share n and read consecutive k (coalesced H, broadcast dY).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_dw_partial(int64_t B, int64_t chunk, const T* __restrict__ dY, int out, const T* __restrict__ H,
+             int in, T* __restrict__ part, T* __restrict__ partb)
 {
     const int64_t c = blockIdx.y;
     const int64_t r0 = c * chunk, r1 = (r0 + chunk < B) ? r0 + chunk : B;
@@ -545,8 +623,7 @@ k_dw_partial(int64_t B, int64_t chunk, const T* __restrict__ dY, int out, const 
         const int n = q / (in + 1), k = q % (in + 1);
         T acc = T(0);
         if (k < in) {
-            for (int64_t r = r0; r < r1; ++r)
-                acc += dY[r * out + n] * hprev<T>(X, Zp, r, k, in, l, act, bf16 != 0);
+            for (int64_t r = r0; r < r1; ++r) acc += dY[r * out + n] * H[r * in + k];
             part[(c * out + n) * (size_t)in + k] = acc;
         } else {
             for (int64_t r = r0; r < r1; ++r) acc += dY[r * out + n];
@@ -609,6 +686,8 @@ static int backward_impl(const MlpDev& d, int64_t B, const T* X, const T* Z, con
     T* part = reinterpret_cast<T*>(w);
     w += align_up(sizeof(T) * (size_t)n_chunks * wmax * wmax);
     T* partb = reinterpret_cast<T*>(w);
+    w += align_up(sizeof(T) * (size_t)n_chunks * wmax);
+    T* H = reinterpret_cast<T*>(w);
     const int pb = persistent_blocks(256);
     auto grid1 = [&](int64_t n) {
         int64_t b = (n + 255) / 256;
@@ -625,9 +704,10 @@ static int backward_impl(const MlpDev& d, int64_t B, const T* X, const T* Z, con
     for (int l = d.L - 1; l >= 0; --l) {
         const int out = d.dims[l + 1], in = d.dims[l];
         const T* Zp = (l > 0) ? Z + zoff[l - 1] : nullptr;
+        k_hprev<T><<<grid1(B * in), 256, 0, s>>>(B * in, X, Zp, l, d.act, bf16, H);
+        DSMC_LAUNCH_CHECK("mlp_bwd:hprev");
         dim3 gp((unsigned)((out * (in + 1) + 255) / 256), (unsigned)n_chunks);
-        k_dw_partial<T><<<gp, 256, 0, s>>>(B, chunk, cur, out, X, Zp, in, l, d.act, bf16, part,
-                                           partb);
+        k_dw_partial<T><<<gp, 256, 0, s>>>(B, chunk, cur, out, H, in, part, partb);
         DSMC_LAUNCH_CHECK("mlp_bwd:dw_partial");
         k_dw_reduce<T><<<grid1(out * (in + 1)), 256, 0, s>>>(n_chunks, part, partb, out, in, dW[l],
                                                              db[l], accumulate);
@@ -652,7 +732,7 @@ static size_t backward_ws_bytes(const MlpDev& d, int64_t B, size_t es)
     int wmax = 8;
     for (int l = 0; l <= d.L; ++l) wmax = wmax > d.dims[l] ? wmax : d.dims[l];
     const int64_t n_chunks = (B + 2047) / 2048;
-    return 256 + 2 * align_up(es * (size_t)B * wmax) + align_up(es * (size_t)n_chunks * wmax * wmax) +
+    return 256 + 3 * align_up(es * (size_t)B * wmax) + align_up(es * (size_t)n_chunks * wmax * wmax) +
            align_up(es * (size_t)n_chunks * wmax);
 }
 
