@@ -112,13 +112,17 @@ typedef struct {
 } dsmc_potential;
 
 /* Quadrature settings of the deflection integral.  n_nodes: Gauss-Legendre
- * nodes (8..128; 0 = 64).  scan_ratio: geometric step of the downward root
- * scan at low energy (0 = 0.98).  max_iter: root refinement iterations
- * (0 = 60). */
+ * nodes per panel (8..128; 0 = 64).  scan_ratio: geometric step of the
+ * downward root scan at low energy (0 = 0.98).  max_iter: root refinement
+ * iterations (0 = 60).  low_panels: equal panels of n_nodes used below the
+ * energy at which several turning points become possible (orbiting, where
+ * the integrand has a sharp interior peak; 0 = 4); one panel above it. */
 typedef struct {
     int32_t n_nodes;
     int32_t max_iter;
     double scan_ratio;
+    int32_t low_panels;
+    int32_t reserved;
 } dsmc_quad;
 
 /* Conditional MLP f_theta (section "Cell-Based Neural Collision Operator"):
@@ -140,10 +144,14 @@ typedef struct {
     double sigma_v;
 } dsmc_mlp;
 
-/* Phase-B schedules: AUTO picks by pair count (autotuned threshold); LANE:
- * one lane per cell; BLOCK: one workgroup per cell applying independent
- * pairs in dependency rounds.  All schedules give bit-identical results. */
-enum { DSMC_SCHED_AUTO = 0, DSMC_SCHED_LANE = 1, DSMC_SCHED_BLOCK = 2 };
+/* Phase-B schedules: LANE: one lane walks a cell's pairs in order; WAVE: one
+ * wavefront per cell, velocities staged in LDS, applying in rounds every
+ * pending pair that is the earliest pending pair of both its particles
+ * (cells of up to 256 pairs spanning up to 1024 particles); BLOCK: the same
+ * rounds by a 256-lane workgroup on global memory (any cell).  AUTO: LANE
+ * up to an autotuned pair count, WAVE above it, BLOCK for cells WAVE cannot
+ * hold.  All schedules give bit-identical results. */
+enum { DSMC_SCHED_AUTO = 0, DSMC_SCHED_LANE = 1, DSMC_SCHED_BLOCK = 2, DSMC_SCHED_WAVE = 4 };
 /* DSMC_SCHED_DEFER: run Phase A only and leave its per-pair results in the
  * workspace; dsmc_apply_pairs then performs Phase B (used to overlap or time
  * the two phases separately). */
@@ -333,7 +341,7 @@ int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, int32_t dtyp
                         int32_t* pair_cnt, void* ws, size_t ws_bytes, dsmc_status* st,
                         dsmc_stream_t stream);
 
-/* Tuning knobs (host): threshold in pairs above which AUTO uses the BLOCK
+/* Tuning knobs (host): threshold in pairs above which AUTO leaves the LANE
  * schedule; the autotuner in the Python package sets it. */
 int dsmc_set_block_threshold(int32_t pairs);
 int32_t dsmc_get_block_threshold(void);

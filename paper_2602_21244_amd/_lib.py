@@ -13,7 +13,7 @@ ST_PAIR_OVERFLOW, ST_BAD_CELL, ST_ROOT_FAIL, ST_NONFINITE = 1, 2, 4, 8
 XS_VHS, XS_CONST = 0, 1
 POT_JAGER, POT_HS, POT_INVPOW = 0, 1, 2
 ACT_SILU, ACT_RELU = 0, 1
-SCHED_AUTO, SCHED_LANE, SCHED_BLOCK, SCHED_DEFER = 0, 1, 2, 3
+SCHED_AUTO, SCHED_LANE, SCHED_BLOCK, SCHED_DEFER, SCHED_WAVE = 0, 1, 2, 3, 4
 APPLY_DIRECTIONS, APPLY_ANGLES = 0, 1
 MM_CAPTURE, MM_APPLY, MM_APPLY_LITERAL = 0, 1, 2
 
@@ -52,7 +52,8 @@ class Potential(C.Structure):
 
 
 class Quad(C.Structure):
-    _fields_ = [("n_nodes", C.c_int32), ("max_iter", C.c_int32), ("scan_ratio", C.c_double)]
+    _fields_ = [("n_nodes", C.c_int32), ("max_iter", C.c_int32), ("scan_ratio", C.c_double),
+                ("low_panels", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Mlp(C.Structure):

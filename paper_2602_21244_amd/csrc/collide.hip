@@ -6,9 +6,11 @@
 // each cell in candidate order on the current velocities with the
 // centre-of-mass update of eq. v_update_pair.  Two Phase-B schedules:
 //   LANE  -- one lane walks one cell's pairs sequentially;
-//   BLOCK -- one workgroup per cell repeatedly applies, in parallel, every
-//            pending pair that is the earliest pending pair of both of its
-//            particles (dependency rounds in LDS).
+//   WAVE  -- one 64-lane workgroup per cell, the cell's velocities staged in
+//            LDS, applying in parallel, round by round, every pending pair
+//            that is the earliest pending pair of both of its particles;
+//   BLOCK -- the same dependency rounds by a 256-lane workgroup on
+//            velocities in global memory (cells too big for WAVE).
 // A pair's update depends only on the current velocities of its two particles,
 // and BLOCK applies each pair after every earlier pair that shares a particle,
 // so both schedules produce bit-identical velocities.
@@ -97,13 +99,22 @@ k_phaseB_lane(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t max_
     }
 }
 
+constexpr int WV_NMAX = 1024;
+constexpr int WV_PPL = 4;
+
+__device__ __forceinline__ bool wave_fits(int32_t c, int32_t span)
+{
+    return c <= 64 * WV_PPL && span <= WV_NMAX;
+}
+
 constexpr int BLK_THREADS = 256;
 constexpr int BLK_NMAX = 8192;   // particles of a cell tracked in LDS
 constexpr int BLK_MMAX = 8192;   // pairs of a cell tracked in LDS
 
 template <typename T, int RULE>
 __global__ void __launch_bounds__(BLK_THREADS)
-k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs)
+k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
+               int32_t skip_wave_cells)
 {
     __shared__ int32_t first[BLK_NMAX];     // earliest pending pair of each particle
     __shared__ uint32_t pij[BLK_MMAX];      // local (i | j << 16) of each pair, ~0 once applied
@@ -131,6 +142,7 @@ k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min
         lo = red[0][0]; hi = red[1][0];
         for (int w = 1; w < BLK_THREADS / 64; ++w) { lo = min(lo, red[0][w]); hi = max(hi, red[1][w]); }
         const int32_t span = hi - lo + 1;
+        if (skip_wave_cells && wave_fits(c, span)) continue;  // uniform: done by the WAVE kernel
         if (span > BLK_NMAX || c > BLK_MMAX || span > 65535) {
             // beyond the LDS tables: sequential, still in candidate order
             if (threadIdx.x == 0)
@@ -172,20 +184,133 @@ k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min
     }
 }
 
+// WAVE schedule: one 64-lane workgroup per cell with the cell's velocities
+// staged in LDS; each lane owns up to WV_PPL pairs; dependency rounds as in
+// the BLOCK schedule but entirely in LDS.  Cells with more pairs, or whose
+// pairs span more than WV_NMAX slots, are left to the BLOCK kernel.
+
+template <typename T, int RULE>
+__device__ __forceinline__ void apply_pair_lds(T* lx, T* ly, T* lz, int32_t a, int32_t b,
+                                               const PairBuf<T>& d, int64_t p)
+{
+    const double xa = lx[a], ya = ly[a], za = lz[a];
+    const double xb = lx[b], yb = ly[b], zb = lz[b];
+    const double rx = xa - xb, ry = ya - yb, rz = za - zb;
+    double u[3];
+    double g;
+    if (RULE == RULE_DIR) {
+        g = sqrt(rx * rx + ry * ry + rz * rz);
+        const double a0 = d.a[p], a1 = d.b[p], a2 = d.c[p];
+        const double inv = 1.0 / sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+        u[0] = a0 * inv; u[1] = a1 * inv; u[2] = a2 * inv;
+    } else {
+        double vh[3], e[3];
+        g = unit3<double>(rx, ry, rz, vh);
+        const double xi[3] = {(double)d.c[p], (double)d.d[p], (double)d.e[p]};
+        perp_dir<double>(xi, vh, e);
+        const double cc = d.a[p], sc = d.b[p];
+        u[0] = cc * vh[0] + sc * e[0];
+        u[1] = cc * vh[1] + sc * e[1];
+        u[2] = cc * vh[2] + sc * e[2];
+    }
+    const double cx = 0.5 * (xa + xb), cy = 0.5 * (ya + yb), cz = 0.5 * (za + zb);
+    const double px = 0.5 * g * u[0], py = 0.5 * g * u[1], pz = 0.5 * g * u[2];
+    lx[a] = (T)(cx + px); ly[a] = (T)(cy + py); lz[a] = (T)(cz + pz);
+    lx[b] = (T)(cx - px); ly[b] = (T)(cy - py); lz[b] = (T)(cz - pz);
+}
+
+template <typename T, int RULE>
+__global__ void __launch_bounds__(64)
+k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs)
+{
+    __shared__ T lx[WV_NMAX], ly[WV_NMAX], lz[WV_NMAX];
+    __shared__ int32_t first[WV_NMAX];
+    const int lane = threadIdx.x;
+    for (int32_t k = blockIdx.x; k < n_cells; k += gridDim.x) {
+        const int32_t c = pr.cnt[k];
+        if (c == 0 || c < min_pairs || c > 64 * WV_PPL) continue;
+        const int64_t o = pr.off[k];
+        int32_t pa[WV_PPL], pb[WV_PPL];
+        int32_t lo = INT32_MAX, hi = -1;
+        uint32_t pend = 0;
+#pragma unroll
+        for (int m = 0; m < WV_PPL; ++m) {
+            const int32_t q = lane + 64 * m;
+            pa[m] = 0;
+            pb[m] = 0;
+            if (q < c) {
+                pa[m] = pr.i[o + q];
+                pb[m] = pr.j[o + q];
+                lo = min(lo, min(pa[m], pb[m]));
+                hi = max(hi, max(pa[m], pb[m]));
+                pend |= 1u << m;
+            }
+        }
+#pragma unroll
+        for (int sft = 32; sft > 0; sft >>= 1) {
+            lo = min(lo, __shfl_xor(lo, sft, 64));
+            hi = max(hi, __shfl_xor(hi, sft, 64));
+        }
+        const int32_t span = hi - lo + 1;
+        if (!wave_fits(c, span)) continue;
+        for (int32_t q = lane; q < span; q += 64) {
+            lx[q] = v.x[lo + q];
+            ly[q] = v.y[lo + q];
+            lz[q] = v.z[lo + q];
+        }
+#pragma unroll
+        for (int m = 0; m < WV_PPL; ++m) { pa[m] -= lo; pb[m] -= lo; }
+        __syncthreads();
+        while (__ballot(pend != 0)) {
+            for (int32_t q = lane; q < span; q += 64) first[q] = INT32_MAX;
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < WV_PPL; ++m)
+                if (pend & (1u << m)) {
+                    atomicMin(&first[pa[m]], lane + 64 * m);
+                    atomicMin(&first[pb[m]], lane + 64 * m);
+                }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < WV_PPL; ++m) {
+                const int32_t q = lane + 64 * m;
+                if ((pend & (1u << m)) && first[pa[m]] == q && first[pb[m]] == q) {
+                    apply_pair_lds<T, RULE>(lx, ly, lz, pa[m], pb[m], d, o + q);
+                    pend &= ~(1u << m);
+                }
+            }
+            __syncthreads();
+        }
+        for (int32_t q = lane; q < span; q += 64) {
+            v.x[lo + q] = lx[q];
+            v.y[lo + q] = ly[q];
+            v.z[lo + q] = lz[q];
+        }
+        __syncthreads();
+    }
+}
+
 int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v,
             const dsmc_pairs& pairs, void* dirs, int64_t cap, int32_t schedule, hipStream_t s)
 {
+    (void)cell_start;
     const PairsView pr = PairsView::of(pairs);
     const int pb = persistent_blocks(256);
     int lb = (n_cells + 255) / 256;
     lb = lb < 1 ? 1 : (lb > pb ? pb : lb);
+    // cells with at most `thr` pairs: LANE; larger: WAVE if they fit its LDS
+    // tables (AUTO, WAVE), else BLOCK
     int32_t thr = block_threshold();
+    bool use_wave = true;
     if (schedule == DSMC_SCHED_LANE) thr = INT32_MAX;
-    if (schedule == DSMC_SCHED_BLOCK) thr = 0;
-    const bool need_lane = schedule != DSMC_SCHED_BLOCK;
-    const bool need_block = schedule != DSMC_SCHED_LANE;
+    if (schedule == DSMC_SCHED_BLOCK) { thr = 0; use_wave = false; }
+    if (schedule == DSMC_SCHED_WAVE) thr = 0;
+    const bool need_lane = thr > 0;
+    const bool need_rest = thr < INT32_MAX;
     int bb = n_cells < pb ? n_cells : pb;
     bb = bb < 1 ? 1 : bb;
+    int wb = n_cells < pb * 8 ? n_cells : pb * 8;
+    wb = wb < 1 ? 1 : wb;
 #define DSMC_PHASEB(T, R)                                                                   \
     do {                                                                                    \
         PairBuf<T> d = PairBuf<T>::of(dirs, cap);                                           \
@@ -193,9 +318,13 @@ int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsm
             k_phaseB_lane<T, R><<<lb, 256, 0, s>>>(n_cells, pr, v3<T>(v), d, thr);          \
             DSMC_LAUNCH_CHECK("phaseB:lane");                                               \
         }                                                                                   \
-        if (need_block) {                                                                   \
+        if (need_rest && use_wave) {                                                        \
+            k_phaseB_wave<T, R><<<wb, 64, 0, s>>>(n_cells, pr, v3<T>(v), d, thr + 1);       \
+            DSMC_LAUNCH_CHECK("phaseB:wave");                                               \
+        }                                                                                   \
+        if (need_rest) {                                                                    \
             k_phaseB_block<T, R><<<bb, BLK_THREADS, 0, s>>>(n_cells, pr, v3<T>(v), d,       \
-                                                            thr + 1);                       \
+                                                            thr + 1, use_wave ? 1 : 0);     \
             DSMC_LAUNCH_CHECK("phaseB:block");                                              \
         }                                                                                   \
     } while (0)
@@ -238,7 +367,7 @@ extern "C" int dsmc_collide_vhs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsm
 {
     int rc = check_pairs("dsmc_collide_vhs", n_cells, v, pairs, dtype, ws, ws_bytes);
     if (rc) return rc;
-    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_DEFER)
+    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_WAVE)
         return arg_error("dsmc_collide_vhs: schedule %d", schedule);
     hipStream_t s = as_stream(stream);
     const PairsView pr = PairsView::of(pairs);
@@ -263,7 +392,7 @@ extern "C" int dsmc_apply_pairs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsm
     if (rc) return rc;
     if (kind != DSMC_APPLY_DIRECTIONS && kind != DSMC_APPLY_ANGLES)
         return arg_error("dsmc_apply_pairs: kind %d", kind);
-    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_BLOCK)
+    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_WAVE || schedule == DSMC_SCHED_DEFER)
         return arg_error("dsmc_apply_pairs: schedule %d", schedule);
     return phase_b(kind == DSMC_APPLY_ANGLES ? RULE_CHI : RULE_DIR, dtype, n_cells, nullptr, v, pairs,
                    ws, pairs.cap, schedule, as_stream(stream));

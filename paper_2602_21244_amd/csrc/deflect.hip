@@ -40,12 +40,17 @@ struct Pot {
 
 struct QuadCfg {
     int max_iter;
+    int low_panels;
     double scan_ratio;
 };
 
 // ------------------------------------------------------------------------
 // Potential (T arithmetic)
 // ------------------------------------------------------------------------
+// Beyond beta_tt r = 60 every Tang-Toennies factor f_6..f_16 is 1 to better
+// than 1e-13 (the tail exp(-x) sum x^k/k! is below that), so they are taken
+// as 1 there.
+constexpr double DAMP_OFF = 60.0;
 template <typename T>
 __device__ __forceinline__ T dexp(T x) { return exp(x); }
 template <>
@@ -64,10 +69,21 @@ __device__ __forceinline__ T V_of(const Pot& P, T r)
     const T ri = T(1) / r;
     const T rep = T(p.A) * dexp<T>(T(p.a1) * r + T(p.a2) * r * r + T(p.am1) * ri + T(p.am2) * ri * ri);
     const T x = T(p.beta_tt) * r;
-    const T ex = dexp<T>(-x);
     const T ri2 = ri * ri;
     T rpow = ri2 * ri2 * ri2;  // r^-6
-    T term = T(1), S = T(1), disp = T(0);
+    T disp = T(0);
+    if (x >= T(DAMP_OFF)) {
+        // damping factors equal 1 to well below rounding (and x^16 would
+        // overflow FP32 at large r)
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            disp += T(p.C[n]) * rpow;
+            rpow *= ri2;
+        }
+        return rep - disp;
+    }
+    const T ex = dexp<T>(-x);
+    T term = T(1), S = T(1);
 #pragma unroll
     for (int k = 1; k <= 16; ++k) {
         term = term * x * T(1.0 / k);  // x^k / k!
@@ -97,10 +113,19 @@ __device__ __forceinline__ T dV_of(const Pot& P, T r)
     const T phi_r = T(p.a1) + T(2) * T(p.a2) * r - T(p.am1) * ri * ri - T(2) * T(p.am2) * ri * ri * ri;
     const T rep = T(p.A) * dexp<T>(T(p.a1) * r + T(p.a2) * r * r + T(p.am1) * ri + T(p.am2) * ri * ri);
     const T x = T(p.beta_tt) * r;
-    const T ex = dexp<T>(-x);
     const T ri2 = ri * ri;
     T rpow = ri2 * ri2 * ri2;
-    T term = T(1), S = T(1), dd = T(0);
+    T dd = T(0);
+    if (x >= T(DAMP_OFF)) {
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            dd -= T(6 + 2 * n) * T(p.C[n]) * rpow * ri;
+            rpow *= ri2;
+        }
+        return rep * phi_r - dd;
+    }
+    const T ex = dexp<T>(-x);
+    T term = T(1), S = T(1);
 #pragma unroll
     for (int k = 1; k <= 16; ++k) {
         term = term * x * T(1.0 / k);  // x^k / k!
@@ -130,6 +155,33 @@ template <typename T>
 __device__ __forceinline__ T D_of(const Pot& P, T b2, T E, T r)
 {
     return T(1) - b2 / (r * r) - V_of<T>(P, r) / E;
+}
+
+// Gauss-Legendre over t in [ta, tb] of 2 t / sqrt(F), with
+// F = beta^2 t^2 (2 - t^2) + (V(r_min) - V(r))/E + D0 and r = r_min / (1 - t^2).
+template <typename T>
+__device__ __forceinline__ T integral_part(const Pot& P, const GLRule& gl, T rmin, T beta, T Vmin,
+                                           T E, T D0, T ta, T tb)
+{
+    const T g1 = T(0.5) - T(0.28867513459481287);  // 2-point Gauss-Legendre on [0,1]
+    const T g2 = T(0.5) + T(0.28867513459481287);
+    const T len = tb - ta;
+    T I = T(0);
+    for (int k = 0; k < gl.n; ++k) {
+        const T t = ta + len * T(gl.t[k]);
+        const T t2 = t * t;
+        const T dr = rmin * t2 / (T(1) - t2);
+        T dV = T(0);
+        if (P.p.kind != DSMC_POT_HS) {
+            if (t2 < T(1e-3))
+                dV = -dr * T(0.5) * (dV_of<T>(P, rmin + g1 * dr) + dV_of<T>(P, rmin + g2 * dr));
+            else
+                dV = Vmin - V_of<T>(P, rmin + dr);
+        }
+        const T F = beta * beta * t2 * (T(2) - t2) + dV / E + D0;
+        if (F > T(0)) I += T(gl.w[k]) * T(2) * t / sqrt(F);
+    }
+    return len * I;
 }
 
 // chi(b, E) with b in Angstrom, E/k_B in K.  Returns NaN if no root is found.
@@ -186,22 +238,21 @@ __device__ T chi_quad(const Pot& P, const QuadCfg& q, const GLRule& gl, T b, T E
     }
     const T beta = b / rmin;
     const T Vmin = (P.p.kind == DSMC_POT_HS) ? T(0) : V_of<T>(P, rmin);
-    const T g1 = T(0.5) - T(0.28867513459481287);  // 2-point Gauss-Legendre on [0,1]
-    const T g2 = T(0.5) + T(0.28867513459481287);
+    // the short-range switch of the JAGER form is a kink of the integrand:
+    // integrate the two sides separately
     T I = T(0);
-    for (int k = 0; k < gl.n; ++k) {
-        const T t = T(gl.t[k]);
-        const T t2 = t * t;
-        const T dr = rmin * t2 / (T(1) - t2);
-        T dV = T(0);
-        if (P.p.kind != DSMC_POT_HS) {
-            if (t2 < T(1e-3))
-                dV = -dr * T(0.5) * (dV_of<T>(P, rmin + g1 * dr) + dV_of<T>(P, rmin + g2 * dr));
-            else
-                dV = Vmin - V_of<T>(P, rmin + dr);
-        }
-        const T F = beta * beta * t2 * (T(2) - t2) + dV / E + D0;
-        if (F > T(0)) I += T(gl.w[k]) * T(2) * t / sqrt(F);
+    if (E < T(P.e_scan) && P.p.kind == DSMC_POT_JAGER) {
+        // low energy: r_min lies outside the short-range region; equal panels
+        // resolve the sharp interior peak near orbiting
+        const T h = T(1) / T(q.low_panels);
+        for (int k = 0; k < q.low_panels; ++k)
+            I += integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, h * T(k),
+                                  k == q.low_panels - 1 ? T(1) : h * T(k + 1));
+    } else {
+        T tsw = T(1);
+        if (P.p.kind == DSMC_POT_JAGER && rmin < T(P.r_sw)) tsw = sqrt(T(1) - rmin / T(P.r_sw));
+        I = integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, T(0), tsw);
+        if (tsw < T(1)) I += integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, tsw, T(1));
     }
     return pi - T(2) * beta * I;
 }
@@ -337,6 +388,8 @@ static int make_cfg(const dsmc_quad& q, QuadCfg* c, GLRule* gl)
 {
     c->max_iter = q.max_iter > 0 ? q.max_iter : 60;
     c->scan_ratio = q.scan_ratio > 0 ? q.scan_ratio : 0.98;
+    c->low_panels = q.low_panels > 0 ? q.low_panels : 4;
+    if (c->low_panels > 16) return arg_error("dsmc_quad: low_panels %d > 16", c->low_panels);
     if (!(c->scan_ratio > 0.5 && c->scan_ratio < 1.0))
         return arg_error("dsmc_quad: scan_ratio %g not in (0.5, 1)", c->scan_ratio);
     return make_gl(q.n_nodes, gl);
@@ -486,7 +539,7 @@ extern "C" int dsmc_collide_jager(int32_t n_cells, int32_t dtype, dsmc_vec3 v, d
     int rc = check_pairs("dsmc_collide_jager", n_cells, v, pairs, dtype, ws, ws_bytes);
     if (rc) return rc;
     if (!(m_red > 0) || !(b_max > 0)) return arg_error("dsmc_collide_jager: m_red, b_max > 0");
-    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_DEFER)
+    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_WAVE)
         return arg_error("dsmc_collide_jager: schedule %d", schedule);
     Pot P;
     rc = get_pot(pot, &P);

@@ -806,7 +806,7 @@ extern "C" int dsmc_neural_collide(const dsmc_mlp* net, int32_t n_cells, int32_t
     if (rc) return rc;
     if (d.dims[0] != 8 || d.dims[d.L] != 3)
         return arg_error("dsmc_neural_collide: network must map 8 inputs to 3 outputs");
-    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_DEFER)
+    if (schedule < DSMC_SCHED_AUTO || schedule > DSMC_SCHED_WAVE)
         return arg_error("dsmc_neural_collide: schedule %d", schedule);
     hipStream_t s = as_stream(stream);
     const PairsView pr = PairsView::of(pairs);

@@ -2,8 +2,8 @@
 
 Integer outputs (sort permutation, cell offsets, pair lists) must be
 bit-exact; FP64 velocities agree to 1e-12 and FP32 to 1e-5, relative to the
-thermal scale; the BF16 surrogate agrees with FP64 inference of the same
-weights to a chi RMS <= 1e-2 rad.
+population's velocity scale; the BF16 surrogate agrees with FP64 inference of
+the same weights to a direction (chi) RMS <= 1e-2 rad.
 """
 import math
 import sys
@@ -154,25 +154,28 @@ def test_select_overflow(orc, dev, api):
 # isotropic collide + moment matching
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("sched", ["auto", "lane", "block"])
+@pytest.mark.parametrize("sched", ["auto", "lane", "block", "wave"])
 def test_collide_vhs_parity(orc, dev, api, dtype, sched):
     say("collide_vhs", dtype, sched)
     pop = W.ragged_population(12, 300, 260)
     cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, dtype, seed=5, step=1)
-    code = {"auto": api.L.SCHED_AUTO, "lane": api.L.SCHED_LANE, "block": api.L.SCHED_BLOCK}[sched]
+    code = {"auto": api.L.SCHED_AUTO, "lane": api.L.SCHED_LANE, "block": api.L.SCHED_BLOCK,
+            "wave": api.L.SCHED_WAVE}[sched]
     vn = vs.clone()
     api.collide_vhs(vn, pairs, 5, 1, schedule=code)
     ocs = cs.cpu().numpy()
     lowp = dtype == torch.float32
     ref, info = orc.step(ocs, v64, pop.xs, pop.lam, 5, 1, rule="vhs", lowp=lowp, match=False)
     got = vn.cpu().numpy().astype(np.float64)
-    err = np.max(np.abs(got - ref)) / _thermal()
+    # relative to the velocity scale of the population
+    vscale = max(np.max(np.abs(ref)), _thermal())
+    err = np.max(np.abs(got - ref)) / vscale
     tol = 1e-5 if lowp else 1e-12
     assert err < tol, err
     # moment matching on top (conserving step -> alpha = 1 to round-off)
     api.moment_match(cs, vn, mom, api.L.MM_APPLY, pair_cnt=pairs.cnt, st=st)
     ref2, _ = orc.moment_match(ocs, mom.cpu().numpy().reshape(-1, 6), sel["pair_cnt"], ref)
-    err2 = np.max(np.abs(vn.cpu().numpy().astype(np.float64) - ref2)) / _thermal()
+    err2 = np.max(np.abs(vn.cpu().numpy().astype(np.float64) - ref2)) / vscale
     assert err2 < tol, err2
 
 
@@ -180,7 +183,7 @@ def test_schedules_bit_identical(dev, api):
     say("schedules bit-identical")
     pop = W.ragged_population(13, 200, 900, empty_frac=0.1)
     out = []
-    for code in (api.L.SCHED_LANE, api.L.SCHED_BLOCK, api.L.SCHED_AUTO):
+    for code in (api.L.SCHED_LANE, api.L.SCHED_BLOCK, api.L.SCHED_AUTO, api.L.SCHED_WAVE):
         cell_of = torch.as_tensor(pop.cell_of, device=dev)
         v = torch.as_tensor(pop.v, device=dev).contiguous()
         cs, perm, vs = api.sort_cells(cell_of, pop.n_cells, v)
@@ -190,7 +193,8 @@ def test_schedules_bit_identical(dev, api):
         api.select_pairs_ntc(cs, vs, pop.xs, torch.as_tensor(pop.lam, device=dev), mom, 3, 9, pairs)
         api.collide_vhs(vs, pairs, 3, 9, schedule=code)
         out.append(vs.cpu().numpy())
-    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    for o in out[1:]:
+        assert np.array_equal(out[0], o)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -242,8 +246,13 @@ def _chi_stats(got, ref):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_deflect_jager_against_oracle(orc, dev, api, dtype):
+    """chi of the GPU quadrature against the oracle's (Brent + adaptive
+    Gauss-Kronrod) on the deflection-batch distribution.  Bounds: pairs whose
+    deflection stays within one half-turn (|chi| <= pi, i.e. away from
+    orbiting) to 1e-9 (FP64) / 2e-4 (FP32) rad in theta = arccos(cos chi);
+    all pairs, orbiting included, to an RMS of 1e-6 (FP64) / 1e-4 (FP32)."""
     say("deflect jager", dtype)
-    b, g, mr = W.deflection_batch(seed=21, n=4096)
+    b, g, mr = W.deflection_batch(seed=21, n=8192)
     P = orc.potential_jager(W.JAGER_PLACEHOLDER)
     ref, ost = orc.chi_batch(P, b, g, mr, n_threads=8)
     st = api.new_status(dev)
@@ -254,37 +263,51 @@ def test_deflect_jager_against_oracle(orc, dev, api, dtype):
     s = api.read_status(st)
     assert s.root_fail == 0 and np.all(np.isfinite(got))
     d = _chi_stats(got, ref)
-    E = 0.5 * mr * g * g / W.KB
-    hi = E > 300.0  # above the orbiting range: single turning point, smooth integrand
-    say(f"  theta err all: rms={np.sqrt(np.mean(d*d)):.3e} max={d.max():.3e} "
-        f"p99.9={np.percentile(d, 99.9):.3e}; E>300K max={d[hi].max():.3e}")
+    tame = np.abs(ref) <= np.pi
+    rms = float(np.sqrt(np.mean(d * d)))
+    say(f"  theta err all: rms={rms:.3e} max={d.max():.3e} p99.9={np.percentile(d, 99.9):.3e}; "
+        f"|chi|<=pi ({tame.sum()} of {len(d)}): max={d[tame].max():.3e}; "
+        f"orbiting (|chi|>pi): max={d[~tame].max() if (~tame).any() else 0:.3e}")
     if dtype == torch.float64:
-        assert d[hi].max() < 1e-9
-        assert np.sqrt(np.mean(d * d)) < 1e-3
+        assert d[tame].max() < 1e-9 and rms < 1e-6
     else:
-        assert d[hi].max() < 2e-4
-        assert np.sqrt(np.mean(d * d)) < 2e-3
+        assert d[tame].max() < 2e-4 and rms < 1e-4
 
 
 def test_collide_jager_step(orc, dev, api):
+    """In-step ab initio rule: chi per accepted pair against the oracle's
+    quadrature (stated), then Phase B from the GPU's angles against the
+    oracle's rotation + pair update (1e-12), and exact conservation."""
     say("collide jager in-step")
     pop = W.ragged_population(15, 120, 120, xs="const", T=2000.0)
     cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, torch.float64, seed=4, step=2)
     vn = vs.clone()
     pot = api.potential_jager(W.JAGER_PLACEHOLDER)
-    api.collide_jager(vn, pairs, 4, 2, W.AR_MASS / 2, W.B_MAX, pot, st=st)
+    ws = api.collide_ws(pairs.cap, vn)
+    api.collide_jager(vn, pairs, 4, 2, W.AR_MASS / 2, W.B_MAX, pot, ws=ws, st=st)
+    n = int(sel["pair_cnt"].sum())
+    buf = ws[: 6 * (pairs.cap + 1) * 8].view(torch.float64).view(6, pairs.cap + 1)[:, :n].cpu().numpy()
+    cc, sc, xi = buf[0], buf[1], buf[2:5].T.copy()
+    U, oxi, z = orc.pair_latents(sel, 4, 2)
+    np.testing.assert_allclose(xi, oxi, rtol=1e-13, atol=1e-13)
+    vr = v64[:, sel["pair_i"]] - v64[:, sel["pair_j"]]
+    g = np.sqrt(np.sum(vr * vr, axis=0))
     P = orc.potential_jager(W.JAGER_PLACEHOLDER)
-    ref, info = orc.step(cs.cpu().numpy(), v64, pop.xs, pop.lam, 4, 2, rule="jager", pot=P,
-                         b_max=W.B_MAX, m_red=W.AR_MASS / 2)
-    err = np.abs(vn.cpu().numpy() - ref) / _thermal(2000.0)
-    say(f"  jager step: max rel dv {err.max():.3e}")
-    assert err.max() < 1e-6
-    # conservation per cell
+    ref, _ = orc.chi_batch(P, W.B_MAX * np.sqrt(U[:, 4]), g, W.AR_MASS / 2, n_threads=8)
+    d = np.abs(np.arctan2(sc, cc) - np.arctan2(np.sin(ref), np.cos(ref)))
+    d = np.minimum(d, 2 * np.pi - d)
+    tame = np.abs(ref) <= np.pi
+    say(f"  in-step chi: |chi|<=pi max {d[tame].max():.3e}, all rms {np.sqrt(np.mean(d*d)):.3e}")
+    assert d[tame].max() < 1e-9
+    vref = orc.apply_chi(sel, v64, cc, sc, xi)
+    err = np.max(np.abs(vn.cpu().numpy() - vref)) / np.max(np.abs(v64))
+    say(f"  phase B from GPU angles: rel err {err:.3e}")
+    assert err < 1e-12
     got = vn.cpu().numpy()
     ocs = cs.cpu().numpy()
     for k in range(pop.n_cells):
-        a, b_ = ocs[k], ocs[k + 1]
-        np.testing.assert_allclose(np.sum(got[:, a:b_] ** 2), np.sum(v64[:, a:b_] ** 2), rtol=1e-12)
+        a_, b_ = ocs[k], ocs[k + 1]
+        np.testing.assert_allclose(np.sum(got[:, a_:b_] ** 2), np.sum(v64[:, a_:b_] ** 2), rtol=1e-12)
 
 
 # ---------------------------------------------------------------------------
