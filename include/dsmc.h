@@ -175,12 +175,15 @@ int dsmc_status_clear(dsmc_status* st, dsmc_stream_t stream);
 
 /* Bin particles into cells (section "Computational Framework", item 1:
  * particles sorted by cell index so each cell is contiguous).
- * Stable counting sort by cell_of[n] (original order kept inside a cell):
- * writes cell_start[n_cells+1] (exclusive prefix of the counts), perm[n]
- * (perm[s] = original index of sorted slot s) and gathers v_in into v_out
- * (distinct buffers).  Ids outside [0, n_cells) are dropped and counted in
- * st->bad_cell; then cell_start[n_cells] < n and perm/v_out hold only the
- * kept particles.  ws: dsmc_sort_cells_ws(n, n_cells) bytes. */
+ * Stable sort by cell_of[n] (original order kept inside a cell; a radix
+ * sort of the cell ids): writes cell_start[n_cells+1] (exclusive prefix of
+ * the counts), perm[n] (perm[s] = original index of sorted slot s) and
+ * gathers v_in into v_out (distinct buffers).  Ids outside [0, n_cells) are
+ * counted in st->bad_cell and sorted after every kept particle: then
+ * cell_start[n_cells] < n and slots cell_start[n_cells]..n-1 hold the dropped
+ * particles in original order.  n_cells < 2^31 - 1.
+ * ws: dsmc_sort_cells_ws(n, n_cells) bytes (about 12 n + 4 KiB per 4096
+ * particles). */
 size_t dsmc_sort_cells_ws(int32_t n, int32_t n_cells);
 int dsmc_sort_cells(int32_t n, int32_t n_cells, const int32_t* cell_of, int32_t dtype,
                     dsmc_vec3 v_in, dsmc_vec3 v_out, int32_t* cell_start, int32_t* perm,

@@ -67,26 +67,34 @@ __device__ __forceinline__ double unif53(uint32_t a, uint32_t b)
 // [0,1) with 24 random bits.
 __device__ __forceinline__ float unif24(uint32_t a) { return (float)(a >> 8) * 0x1.0p-24f; }
 
-// Uniforms of one accepted pair (index a in its cell): 6 values.
-template <typename T> struct PairU { T u[6]; };
-
-__device__ __forceinline__ void pair_uniforms(const dsmc_rng& rng, uint32_t a, uint32_t cell,
-                                              double (&U)[6])
+// Uniforms of one accepted pair (index a in its cell), in two groups:
+// U[0..3] feed xi (slot 2, and slot 3 for 53-bit uniforms), U[4..5] feed z
+// (slot 4 for 53-bit uniforms, slot 3 for 24-bit ones).
+__device__ __forceinline__ void uniforms_xi(const dsmc_rng& rng, uint32_t a, uint32_t cell,
+                                            double (&U)[4])
 {
     const U4 r0 = draw(rng, a, cell, SLOT_LAT0);
     const U4 r1 = draw(rng, a, cell, SLOT_LAT1);
-    const U4 r2 = draw(rng, a, cell, SLOT_LAT2);
     U[0] = unif53(r0.a, r0.b); U[1] = unif53(r0.c, r0.d);
     U[2] = unif53(r1.a, r1.b); U[3] = unif53(r1.c, r1.d);
-    U[4] = unif53(r2.a, r2.b); U[5] = unif53(r2.c, r2.d);
 }
-__device__ __forceinline__ void pair_uniforms(const dsmc_rng& rng, uint32_t a, uint32_t cell,
-                                              float (&U)[6])
+__device__ __forceinline__ void uniforms_z(const dsmc_rng& rng, uint32_t a, uint32_t cell,
+                                           double (&U)[2])
+{
+    const U4 r2 = draw(rng, a, cell, SLOT_LAT2);
+    U[0] = unif53(r2.a, r2.b); U[1] = unif53(r2.c, r2.d);
+}
+__device__ __forceinline__ void uniforms_xi(const dsmc_rng& rng, uint32_t a, uint32_t cell,
+                                            float (&U)[4])
 {
     const U4 r0 = draw(rng, a, cell, SLOT_LAT0);
-    const U4 r1 = draw(rng, a, cell, SLOT_LAT1);
     U[0] = unif24(r0.a); U[1] = unif24(r0.b); U[2] = unif24(r0.c); U[3] = unif24(r0.d);
-    U[4] = unif24(r1.a); U[5] = unif24(r1.b);
+}
+__device__ __forceinline__ void uniforms_z(const dsmc_rng& rng, uint32_t a, uint32_t cell,
+                                           float (&U)[2])
+{
+    const U4 r1 = draw(rng, a, cell, SLOT_LAT1);
+    U[0] = unif24(r1.a); U[1] = unif24(r1.b);
 }
 
 // Box-Muller (Box & Muller 1958); 1-U keeps the log argument in (0, 1].
@@ -108,17 +116,32 @@ __device__ __forceinline__ void box_muller(float ua, float ub, float& n1, float&
 }
 
 // Latents of a pair: xi (3) and z (2) normals, plus U[4] (= b^2 / b_max^2).
+// The two halves are separate so that two lanes can share one pair's work.
+template <typename T>
+__device__ __forceinline__ void latents_xi(const dsmc_rng& rng, uint32_t a, uint32_t cell,
+                                           T (&xi)[3])
+{
+    T U[4];
+    uniforms_xi(rng, a, cell, U);
+    T spare;
+    box_muller(U[0], U[1], xi[0], xi[1]);
+    box_muller(U[2], U[3], xi[2], spare);
+}
+template <typename T>
+__device__ __forceinline__ void latents_z(const dsmc_rng& rng, uint32_t a, uint32_t cell,
+                                          T (&z)[2], T& u4)
+{
+    T U[2];
+    uniforms_z(rng, a, cell, U);
+    box_muller(U[0], U[1], z[0], z[1]);
+    u4 = U[0];
+}
 template <typename T>
 __device__ __forceinline__ void pair_latents(const dsmc_rng& rng, uint32_t a, uint32_t cell,
                                              T (&xi)[3], T (&z)[2], T& u4)
 {
-    T U[6];
-    pair_uniforms(rng, a, cell, U);
-    T spare;
-    box_muller(U[0], U[1], xi[0], xi[1]);
-    box_muller(U[2], U[3], xi[2], spare);
-    box_muller(U[4], U[5], z[0], z[1]);
-    u4 = U[4];
+    latents_xi(rng, a, cell, xi);
+    latents_z(rng, a, cell, z, u4);
 }
 
 // --------------------------------------------------------------------------

@@ -68,17 +68,9 @@ static bool mfma_shape_ok(const MlpDev& d, int* H)
     if (h != 64 && h != 128 && h != 256) return false;
     for (int l = 1; l < d.L; ++l)
         if (d.dims[l] != h) return false;
-    if (d.dims[0] > 32 || d.dims[d.L] > 32) return false;
+    if (d.dims[0] > 30 || d.dims[d.L] > 32) return false;
     *H = h;
     return true;
-}
-
-template <int ACT>
-__device__ __forceinline__ float act_f(float z)
-{
-    if (ACT == DSMC_ACT_RELU) return z > 0.f ? z : 0.f;
-    // SiLU: z * sigmoid(z) with the hardware exp2 and reciprocal
-    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
 
 template <typename T>
@@ -98,44 +90,94 @@ __device__ __forceinline__ T act_grad_t(T z, int act)
 // ------------------------------------------------------------------------
 // Fused BF16 MFMA forward
 // ------------------------------------------------------------------------
+// The matrix cores compute s = c z instead of the pre-activation z, with
+// c = -log2(e) for SiLU (then exp2(s) = exp(-z) needs no multiply) and c = 1
+// for ReLU.  The network input and every bias are scaled by c; the hidden
+// weights stay as they are, because every hidden layer's input (the scaled
+// activation c act(z)) carries the same factor; the outputs are divided by c.
+// Biases enter the MFMAs as an extra k step against a constant-one input, as
+// a bf16 (hi, lo) split of c b, so no accumulator is initialised on the VALU.
+template <int ACT> struct ActScale;
+template <> struct ActScale<DSMC_ACT_SILU> {
+    static constexpr float c = -1.4426950408889634f;
+    static constexpr float inv = -0.69314718055994531f;
+};
+template <> struct ActScale<DSMC_ACT_RELU> {
+    static constexpr float c = 1.0f;
+    static constexpr float inv = 1.0f;
+};
+
+// c act(z) from s = c z.  SiLU: c z sigma(z) = s / (1 + 2^s).
+template <int ACT>
+__device__ __forceinline__ float act_scaled(float s)
+{
+    if (ACT == DSMC_ACT_RELU) return s > 0.f ? s : 0.f;
+    return s * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(s));
+}
+
 struct FragLayout {
     int off[MLP_MAX_LAYERS];   // element offset of each layer's fragments in LDS
     int nb[MLP_MAX_LAYERS];    // 32-row output blocks
-    int ks[MLP_MAX_LAYERS];    // 16-wide k steps
-    int bias_off[MLP_MAX_LAYERS];
+    int ks[MLP_MAX_LAYERS];    // 16-wide k steps, the bias step included
     int total_bf16;
-    int total_bias;
     size_t bytes;
 };
 
 static FragLayout frag_layout(const MlpDev& d)
 {
     FragLayout f{};
-    int o = 0, bo = 0;
+    int o = 0;
     for (int l = 0; l < d.L; ++l) {
         f.nb[l] = (d.dims[l + 1] + 31) / 32;
-        f.ks[l] = (l == 0) ? ((d.dims[0] + 15) / 16) : (d.dims[l] / 16);
+        f.ks[l] = (l == 0) ? ((d.dims[0] + 2 + 15) / 16) : (d.dims[l] / 16 + 1);
         f.off[l] = o;
         o += f.nb[l] * f.ks[l] * 64 * 8;
-        f.bias_off[l] = bo;
-        bo += f.nb[l] * 32;
     }
     f.total_bf16 = o;
-    f.total_bias = bo;
-    f.bytes = (size_t)o * 2 + (size_t)bo * 4;
+    f.bytes = (size_t)o * 2;
     return f;
 }
 
-// Column of W feeding element e of lane-half h in k step ks.
-__device__ __forceinline__ int frag_col(int layer, int ks, int h, int e)
+// Input slot k (0..15) of the first k step in pairs mode.  Lane-half 0
+// supplies xi, lane-half 1 supplies v_r / sigma_v, z and the two constant-one
+// bias inputs, so that each half computes its own latents.  Returns the
+// column of W, or -1 (hi bias), -2 (lo bias), -3 (unused).
+__device__ __forceinline__ int pairs_slot_col(int k)
 {
-    if (layer == 0) return 16 * ks + 8 * h + e;
+    switch (k) {
+    case 0: return 3;
+    case 1: return 4;
+    case 2: return 5;
+    case 8: return 0;
+    case 9: return 1;
+    case 10: return 2;
+    case 11: return 6;
+    case 12: return 7;
+    case 13: return -1;
+    case 14: return -2;
+    default: return -3;
+    }
+}
+
+// Column of W (or bias code, as above) feeding element e of lane-half h in
+// k step ks of layer l (in = input width of the layer).
+template <bool PAIRS>
+__device__ __forceinline__ int frag_col(int layer, int in, int ks, int h, int e)
+{
+    if (layer == 0) {
+        const int k = 16 * ks + 8 * h + e;
+        if (PAIRS) return pairs_slot_col(k);
+        return k < in ? k : (k == in ? -1 : (k == in + 1 ? -2 : -3));
+    }
+    if (ks == in / 16) return (h == 0 && e < 2) ? -1 - e : -3;
     const int pb = ks >> 1, jp = ks & 1;
     return pb * 32 + 16 * jp + 8 * (e >> 2) + 4 * h + (e & 3);
 }
 
-__device__ void stage_weights(const MlpDev& d, const FragLayout& f, __bf16* wl, float* bl)
+template <bool PAIRS, int ACT>
+__device__ void stage_weights(const MlpDev& d, const FragLayout& f, __bf16* wl)
 {
+    constexpr float C = ActScale<ACT>::c;
     for (int l = 0; l < d.L; ++l) {
         const __bf16* W = static_cast<const __bf16*>(d.W[l]);
         const float* B = static_cast<const float*>(d.b[l]);
@@ -145,11 +187,19 @@ __device__ void stage_weights(const MlpDev& d, const FragLayout& f, __bf16* wl, 
             const int e = q & 7, lane = (q >> 3) & 63, frag = q >> 9;
             const int nb = frag / f.ks[l], ks = frag % f.ks[l];
             const int row = nb * 32 + (lane & 31);
-            const int col = frag_col(l, ks, lane >> 5, e);
-            wl[f.off[l] + q] = (row < out && col < in) ? W[(size_t)row * in + col] : (__bf16)0.0f;
+            const int col = frag_col<PAIRS>(l, in, ks, lane >> 5, e);
+            __bf16 w = (__bf16)0.0f;
+            if (row < out) {
+                if (col >= 0) {
+                    w = W[(size_t)row * in + col];
+                } else if (col >= -2) {
+                    const float cb = C * B[row];
+                    const __bf16 hi = (__bf16)cb;
+                    w = (col == -1) ? hi : (__bf16)(cb - (float)hi);
+                }
+            }
+            wl[f.off[l] + q] = w;
         }
-        for (int q = threadIdx.x; q < f.nb[l] * 32; q += blockDim.x)
-            bl[f.bias_off[l] + q] = q < out ? B[q] : 0.0f;
     }
 }
 
@@ -161,20 +211,12 @@ __device__ __forceinline__ bf16x8 lds_frag(const __bf16* wl, int off, int frag, 
 // Row mapping of accumulator register r for lane-half h.
 __device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
-__device__ __forceinline__ floatx16 bias_init(const float* bl, int boff, int nb, int h)
-{
-    floatx16 a;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) a[r] = bl[boff + nb * 32 + acc_row(r, h)];
-    return a;
-}
-
 template <int ACT>
 __device__ __forceinline__ bf16x8 to_frag(const floatx16& a, int jp)
 {
     bf16x8 o;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) o[e] = (__bf16)act_f<ACT>(a[8 * jp + e]);
+    for (int e = 0; e < 8; ++e) o[e] = (__bf16)act_scaled<ACT>(a[8 * jp + e]);
     return o;
 }
 
@@ -195,150 +237,182 @@ template <typename VT> struct PairsIO {
     PairBuf<VT> out;
 };
 
+// One layer on NT tiles: acc holds s of the previous layer (NB blocks),
+// nxt receives s of this layer (NBO blocks).  The activation of block nb
+// produces the inputs of k steps 2 nb and 2 nb + 1, whose MFMAs are issued
+// right away, so the matrix cores run while the next block is activated.
+template <int NB, int NBO, int NT, int ACT>
+__device__ __forceinline__ void layer_step(const __bf16* wl, int off, int ksl,
+                                           const floatx16 (&acc)[NT][NB],
+                                           floatx16 (&nxt)[NT][NBO], const bf16x8& bone,
+                                           int lane)
+{
+    const floatx16 zero = {};
+#pragma unroll
+    for (int nb2 = 0; nb2 < NBO; ++nb2) {
+        const bf16x8 a = lds_frag(wl, off, nb2 * ksl + (ksl - 1), lane);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bone, zero, 0, 0, 0);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        bf16x8 b0[NT], b1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            b0[t] = to_frag<ACT>(acc[t][nb], 0);
+            b1[t] = to_frag<ACT>(acc[t][nb], 1);
+        }
+#pragma unroll
+        for (int nb2 = 0; nb2 < NBO; ++nb2) {
+            const bf16x8 a0 = lds_frag(wl, off, nb2 * ksl + 2 * nb, lane);
+            const bf16x8 a1 = lds_frag(wl, off, nb2 * ksl + 2 * nb + 1, lane);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0[t], nxt[t][nb2], 0, 0, 0);
+                nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[t], nxt[t][nb2], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int H, int NT, bool SAVE, int ACT>
+__device__ __forceinline__ void save_pre(const RowsIO& rio, int l, const int64_t (&row)[NT],
+                                         const bool (&valid)[NT], const floatx16 (&acc)[NT][H / 32],
+                                         int h)
+{
+    if (!SAVE) return;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (!valid[t]) continue;
+#pragma unroll
+        for (int nb = 0; nb < H / 32; ++nb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                rio.zsave[((size_t)(l - 1) * rio.B + row[t]) * H + nb * 32 + acc_row(r, h)] =
+                    acc[t][nb][r] * ActScale<ACT>::inv;
+    }
+}
+
 // Each wave processes NT tiles of 32 rows; every A fragment read from LDS
-// feeds NT MFMAs.  Input fragments of a tile: lane (row, h) supplies features
-// 16 ks + 8 h + e.  PAIRS mode builds x = [v_r / sigma_v, xi, z] in the
-// lane-half-0 lanes (dims[0] == 8).
+// feeds NT MFMAs.  Pairs mode: the lane of row r in lane-half 0 computes the
+// pair's xi, the lane in lane-half 1 its z and v_r (dims[0] == 8).
 template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT>
-__global__ void __launch_bounds__(NT == 1 ? 512 : 256)
+__global__ void __launch_bounds__(H == 256 || NT > 1 ? 256 : 512)
 k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __bf16* wl = reinterpret_cast<__bf16*>(smem);
-    float* bl = reinterpret_cast<float*>(smem + (size_t)f.total_bf16 * 2);
-    stage_weights(d, f, wl, bl);
+    stage_weights<PAIRS, ACT>(d, f, wl);
     __syncthreads();
 
+    constexpr float C = ActScale<ACT>::c, IC = ActScale<ACT>::inv;
     const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
     const int waves = blockDim.x >> 6;
     const int64_t nrows = PAIRS ? pio.pr.total(pio.n_cells) : rio.B;
     const int L = d.L, dout = d.dims[L];
-    constexpr int NB = H / 32, KS = H / 16;
+    constexpr int NB = H / 32;
+    const int ks_hidden = H / 16 + 1;
+    bf16x8 bone;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bone[e] = (__bf16)((h == 0 && e < 2) ? 1.0f : 0.0f);
+    const floatx16 zero = {};
 
     for (int64_t grp = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); grp * 32 * NT < nrows;
          grp += (int64_t)gridDim.x * waves) {
         int64_t row[NT];
         bool valid[NT];
         bf16x8 bin[NT][2];
-        VT keep_vh[NT][3], keep_xi[NT][3], keep_u4[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             row[t] = (grp * NT + t) * 32 + col;
             valid[t] = row[t] < nrows;
-            keep_vh[t][0] = 1; keep_vh[t][1] = 0; keep_vh[t][2] = 0;
-            keep_xi[t][0] = 0; keep_xi[t][1] = 0; keep_xi[t][2] = 0;
-            keep_u4[t] = 0;
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int e = 0; e < 8; ++e) bin[t][q][e] = (__bf16)0.0f;
             if (PAIRS) {
-                if (h == 0 && valid[t]) {
+                if (h == 1) {
+                    bin[t][0][5] = (__bf16)1.0f;
+                    bin[t][0][6] = (__bf16)1.0f;
+                }
+                if (valid[t]) {
                     const int64_t r = row[t];
                     const int32_t k = pio.pr.cell[r];
                     const uint32_t a = (uint32_t)(r - pio.pr.off[k]);
-                    VT xi[3], z[2], u4;
-                    pair_latents(pio.rng, a, (uint32_t)k, xi, z, u4);
-                    const int32_t i = pio.pr.i[r], j = pio.pr.j[r];
-                    const VT rx = pio.v.x[i] - pio.v.x[j], ry = pio.v.y[i] - pio.v.y[j],
-                             rz = pio.v.z[i] - pio.v.z[j];
-                    unit3<VT>(rx, ry, rz, keep_vh[t]);
-                    keep_xi[t][0] = xi[0]; keep_xi[t][1] = xi[1]; keep_xi[t][2] = xi[2];
-                    keep_u4[t] = u4;
-                    const VT isv = (VT)d.inv_sigma_v;
-                    bin[t][0][0] = (__bf16)(float)(rx * isv);
-                    bin[t][0][1] = (__bf16)(float)(ry * isv);
-                    bin[t][0][2] = (__bf16)(float)(rz * isv);
-                    bin[t][0][3] = (__bf16)(float)xi[0];
-                    bin[t][0][4] = (__bf16)(float)xi[1];
-                    bin[t][0][5] = (__bf16)(float)xi[2];
-                    bin[t][0][6] = (__bf16)(float)z[0];
-                    bin[t][0][7] = (__bf16)(float)z[1];
+                    if (h == 0) {
+                        VT xi[3];
+                        latents_xi(pio.rng, a, (uint32_t)k, xi);
+                        bin[t][0][0] = (__bf16)(C * (float)xi[0]);
+                        bin[t][0][1] = (__bf16)(C * (float)xi[1]);
+                        bin[t][0][2] = (__bf16)(C * (float)xi[2]);
+                    } else {
+                        VT z[2], u4;
+                        latents_z(pio.rng, a, (uint32_t)k, z, u4);
+                        const int32_t i = pio.pr.i[r], j = pio.pr.j[r];
+                        const VT isv = (VT)d.inv_sigma_v;
+                        bin[t][0][0] = (__bf16)(C * (float)((pio.v.x[i] - pio.v.x[j]) * isv));
+                        bin[t][0][1] = (__bf16)(C * (float)((pio.v.y[i] - pio.v.y[j]) * isv));
+                        bin[t][0][2] = (__bf16)(C * (float)((pio.v.z[i] - pio.v.z[j]) * isv));
+                        bin[t][0][3] = (__bf16)(C * (float)z[0]);
+                        bin[t][0][4] = (__bf16)(C * (float)z[1]);
+                    }
                 }
-            } else if (valid[t]) {
+            } else {
                 const int din = d.dims[0];
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const int c = 16 * q + 8 * h + e;
-                        if (c < din) bin[t][q][e] = (__bf16)rio.x[row[t] * din + c];
+                        if (c < din) {
+                            if (valid[t]) bin[t][q][e] = (__bf16)(C * rio.x[row[t] * din + c]);
+                        } else if (c < din + 2) {
+                            bin[t][q][e] = (__bf16)1.0f;
+                        }
                     }
             }
         }
 
+        // input layer: s = W (c x) + c b
         floatx16 acc[NT][NB];
-        bf16x8 bfr[NT][KS];
-        // input layer
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const floatx16 b0 = bias_init(bl, f.bias_off[0], nb, h);
+            const bf16x8 a = lds_frag(wl, f.off[0], nb * f.ks[0], lane);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t][nb] = b0;
+            for (int t = 0; t < NT; ++t)
+                acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bin[t][0], zero, 0, 0, 0);
         }
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            if (ks >= f.ks[0]) break;
+        if (f.ks[0] > 1) {
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const bf16x8 a = lds_frag(wl, f.off[0], nb * f.ks[0] + ks, lane);
+                const bf16x8 a = lds_frag(wl, f.off[0], nb * f.ks[0] + 1, lane);
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
-                    acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bin[t][ks], acc[t][nb], 0, 0, 0);
+                    acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bin[t][1], acc[t][nb], 0, 0, 0);
             }
         }
-        // hidden layers
-        for (int l = 1; l < L; ++l) {
-            if (SAVE) {
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    if (!valid[t]) continue;
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            rio.zsave[((size_t)(l - 1) * rio.B + row[t]) * H + nb * 32 + acc_row(r, h)] =
-                                acc[t][nb][r];
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    bfr[t][2 * nb] = to_frag<ACT>(acc[t][nb], 0);
-                    bfr[t][2 * nb + 1] = to_frag<ACT>(acc[t][nb], 1);
-                }
-            if (l == L - 1) break;
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const floatx16 b0 = bias_init(bl, f.bias_off[l], nb, h);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t][nb] = b0;
-            }
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    const bf16x8 a = lds_frag(wl, f.off[l], nb * KS + ks, lane);
-#pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[t][ks], acc[t][nb], 0, 0, 0);
-                }
+        // hidden layers, two at a time so the accumulators alternate
+        // between two register sets without copies
+        floatx16 alt[NT][NB];
+        floatx16 ao[NT][1];
+        int l = 1;
+        for (; l + 1 < L - 1; l += 2) {
+            save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
+            layer_step<NB, NB, NT, ACT>(wl, f.off[l], ks_hidden, acc, alt, bone, lane);
+            save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
+            layer_step<NB, NB, NT, ACT>(wl, f.off[l + 1], ks_hidden, alt, acc, bone, lane);
         }
-        // output layer (<= 32 outputs: one block)
-        floatx16 ao[NT];
-        {
-            const floatx16 b0 = bias_init(bl, f.bias_off[L - 1], 0, h);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) ao[t] = b0;
+        if (l < L - 1) {
+            save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
+            layer_step<NB, NB, NT, ACT>(wl, f.off[l], ks_hidden, acc, alt, bone, lane);
+            save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
+            layer_step<NB, 1, NT, ACT>(wl, f.off[L - 1], ks_hidden, alt, ao, bone, lane);
+        } else {
+            save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
+            layer_step<NB, 1, NT, ACT>(wl, f.off[L - 1], ks_hidden, acc, ao, bone, lane);
         }
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const bf16x8 a = lds_frag(wl, f.off[L - 1], ks, lane);
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-                ao[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[t][ks], ao[t], 0, 0, 0);
-        }
+        // output layer result: y = s / c, <= 32 outputs in one block
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             if (!valid[t]) continue;
@@ -347,12 +421,12 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int n = acc_row(r, h);
-                    if (n < dout) rio.y_raw[r0 * dout + n] = ao[t][r];
+                    if (n < dout) rio.y_raw[r0 * dout + n] = ao[t][0][r] * IC;
                 }
             }
             if (h != 0) continue;
             // outputs 0..2 sit in registers 0..2 of lane-half 0
-            const float y0 = ao[t][0], y1 = ao[t][1], y2 = ao[t][2];
+            const float y0 = ao[t][0][0] * IC, y1 = ao[t][0][1] * IC, y2 = ao[t][0][2] * IC;
             const float nrm = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
             if (PAIRS) {
                 VT u[3];
@@ -360,11 +434,17 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     u[0] = (VT)(y0 / nrm); u[1] = (VT)(y1 / nrm); u[2] = (VT)(y2 / nrm);
                 } else {
                     // degenerate output: the isotropic direction of this pair
-                    VT e[3];
-                    const VT cc = VT(2) * keep_u4[t] - VT(1);
-                    const VT sc = VT(2) * dev_sqrt<VT>(keep_u4[t] * (VT(1) - keep_u4[t]));
-                    perp_dir<VT>(keep_xi[t], keep_vh[t], e);
-                    for (int q = 0; q < 3; ++q) u[q] = cc * keep_vh[t][q] + sc * e[q];
+                    const int32_t k = pio.pr.cell[r0];
+                    const uint32_t a = (uint32_t)(r0 - pio.pr.off[k]);
+                    VT xi[3], z[2], u4, vh[3], e[3];
+                    pair_latents(pio.rng, a, (uint32_t)k, xi, z, u4);
+                    const int32_t i = pio.pr.i[r0], j = pio.pr.j[r0];
+                    unit3<VT>(pio.v.x[i] - pio.v.x[j], pio.v.y[i] - pio.v.y[j],
+                              pio.v.z[i] - pio.v.z[j], vh);
+                    const VT cc = VT(2) * u4 - VT(1);
+                    const VT sc = VT(2) * dev_sqrt<VT>(u4 * (VT(1) - u4));
+                    perp_dir<VT>(xi, vh, e);
+                    for (int q = 0; q < 3; ++q) u[q] = cc * vh[q] + sc * e[q];
                 }
                 pio.out.a[r0] = u[0];
                 pio.out.b[r0] = u[1];
@@ -407,7 +487,7 @@ static int launch_one(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<
         hipDeviceProp_t p;
         if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
     }
-    const int threads = NT == 1 ? 512 : 256;
+    const int threads = (H == 256 || NT > 1) ? 256 : 512;
     const int64_t groups = (max_rows + 32 * NT - 1) / (32 * NT);
     int64_t blocks = (groups + threads / 64 - 1) / (threads / 64);
     if (blocks > cus) blocks = cus;

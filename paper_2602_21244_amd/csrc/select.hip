@@ -103,9 +103,15 @@ k_candidates(const int32_t* __restrict__ cell_start, int32_t n_cells,
              int32_t* __restrict__ ck)
 {
     const int64_t total = *n_use;
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < total;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t k = find_cell(cand_off, n_cells, (int32_t)c);
+    const int lane = threadIdx.x & 63;
+    // one binary search per wavefront (for its first candidate); lanes then
+    // step forward over the few cells the wave's 64 candidates span
+    for (int64_t base = (blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63)); base < total;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = base + lane;
+        int32_t k = find_cell(cand_off, n_cells, (int32_t)base);
+        if (c >= total) continue;
+        while (k + 1 < n_cells && cand_off[k + 1] <= c) ++k;
         const int32_t t = (int32_t)c - cand_off[k];
         const int32_t s0 = cell_start[k], N = cell_start[k + 1] - s0;
         const U4 r = draw(rng, (uint32_t)t, (uint32_t)k, SLOT_CAND);

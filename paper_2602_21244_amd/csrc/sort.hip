@@ -1,208 +1,282 @@
-// Particle-to-cell binning: stable counting sort by cell id with an SoA
-// velocity gather (section "Computational Framework", item 1: particles sorted
-// by cell index so that each cell is contiguous in memory).
+// Particle-to-cell binning: stable sort by cell id with an SoA velocity
+// gather (section "Computational Framework", item 1: particles sorted by cell
+// index so that each cell is contiguous in memory).
 //
-// Pipeline: count (atomics, one per distinct cell per wave) -> exclusive scan
-// -> scatter into cell segments (atomic cursors, order within a segment not
-// yet fixed) -> per-cell LDS bitonic sort of the original indices, which makes
-// the order the stable one regardless of atomic timing -> coalesced gather of
-// vx, vy, vz into sorted order.
+// Least-significant-digit radix sort of the cell ids, 9 bits per pass (two
+// passes for up to 2^18 - 1 cells).  Every pass is stable, so the result is
+// the stable order (original order inside a cell) whatever the input order
+// and without atomics on the particle data:
+//   up    : per 4096-particle tile, a 512-bucket digit histogram (LDS atomics)
+//   scan  : exclusive scan of the digit-major (digit, tile) histogram table
+//   down  : each wave ranks its 1024 particles in index order (digit match by
+//           ballots, per-wave digit counters in LDS), the tile is reordered by
+//           digit in LDS and written out as contiguous digit runs
+// then one pass over the sorted keys writes cell_start and gathers vx, vy, vz.
+// Ids outside [0, n_cells) are mapped to the key n_cells, so they sort after
+// every kept particle.
 #include "common.hpp"
 
 namespace dsmc {
 
-constexpr int SMALL_MAX = 1024;   // cells up to this size: one wave, LDS bitonic
-constexpr int BIG_MAX = 16384;    // up to this size: one 256-thread block
+constexpr int RADIX_BITS = 9;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // 4096
+constexpr int WAVE_SPAN = 64 * SORT_ITEMS;              // particles per wave
 
-// Distinct-value aggregation inside a wave: lanes holding the same cell id
-// issue a single atomic; returns this lane's rank among equal lanes (in lane
-// order) and the old counter value of the group.
-__device__ __forceinline__ int wave_aggregated_add(int32_t* counters, int32_t c, bool valid,
-                                                   int* rank)
+__device__ __forceinline__ int32_t sort_key(const int32_t* cell_of, int64_t p, int32_t n_cells)
 {
-    const int lane = threadIdx.x & 63;
-    uint64_t pending = __ballot(valid);
-    int my_old = 0;
-    *rank = 0;
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int32_t lc = __shfl(c, leader, 64);
-        const uint64_t same = __ballot(valid && c == lc) & pending;
-        int old = 0;
-        if (lane == leader) old = atomicAdd(&counters[lc], __popcll(same));
-        old = __shfl(old, leader, 64);
-        if (valid && c == lc) {
-            my_old = old;
-            *rank = __popcll(same & ((1ull << lane) - 1ull));
-        }
-        pending &= ~same;
-    }
-    return my_old;
+    const int32_t c = cell_of[p];
+    return (c < 0 || c >= n_cells) ? n_cells : c;
 }
 
-__global__ void __launch_bounds__(256)
-k_count(const int32_t* __restrict__ cell_of, int32_t n, int32_t n_cells, int32_t* counts,
-        dsmc_status* st)
+// Lanes of the wave whose valid digit equals this lane's (bits 0..dbits-1).
+__device__ __forceinline__ uint64_t match_digit(int32_t d, bool valid, int dbits)
 {
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = base + threadIdx.x;
-        int32_t c = (p < n) ? cell_of[p] : -1;
-        const bool bad = (p < n) && (c < 0 || c >= n_cells);
-        const bool valid = (p < n) && !bad;
-        if (bad && st) {
-            atomicAdd(&st->bad_cell, 1);
+    uint64_t same = __ballot(valid);
+    for (int b = 0; b < dbits; ++b) {
+        const uint64_t ones = __ballot((d >> b) & 1);
+        same &= ((d >> b) & 1) ? ones : ~ones;
+    }
+    return same;
+}
+
+// Digit histogram of one tile (same particle-to-wave mapping as the down
+// pass; one LDS atomic per distinct digit per wave).  The first pass reads
+// cell_of, maps bad ids and counts them in the status word.
+template <bool FIRST>
+__global__ void __launch_bounds__(SORT_THREADS)
+k_radix_up(const int32_t* __restrict__ keys_in, int32_t n, int32_t n_cells, int shift,
+           int32_t mask, int dbits, int32_t nblk, int32_t* __restrict__ ghist, dsmc_status* st)
+{
+    __shared__ int32_t h[RADIX];
+    for (int i = threadIdx.x; i <= mask; i += SORT_THREADS) h[i] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t wbase = (int64_t)blockIdx.x * SORT_TILE + (int64_t)w * WAVE_SPAN;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int bad = 0;
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        const int64_t p = wbase + it * 64 + lane;
+        const bool valid = p < n;
+        int32_t key = 0;
+        if (valid) {
+            if (FIRST) {
+                key = sort_key(keys_in, p, n_cells);
+                bad += (key == n_cells);
+            } else {
+                key = keys_in[p];
+            }
+        }
+        const int32_t d = (key >> shift) & mask;
+        const uint64_t same = match_digit(d, valid, dbits);
+        if (valid && (same & lt_mask) == 0) atomicAdd(&h[d], (int32_t)__popcll(same));
+    }
+    if (FIRST && st) {
+        const int wbad = wave_sum_i(bad);
+        if (lane == 0 && wbad > 0) {
+            atomicAdd(&st->bad_cell, wbad);
             atomicOr(&st->flags, (uint32_t)DSMC_ST_BAD_CELL);
         }
-        int rank;
-        wave_aggregated_add(counts, c, valid, &rank);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= mask; i += SORT_THREADS) ghist[(int64_t)i * nblk + blockIdx.x] = h[i];
 }
 
-__global__ void __launch_bounds__(256)
-k_scatter(const int32_t* __restrict__ cell_of, int32_t n, int32_t n_cells, int32_t* cursor,
-          int32_t* __restrict__ tmp)
+// Exclusive scan of RADIX values in LDS by the 256 threads (two per thread).
+__device__ __forceinline__ void block_scan_radix(const int32_t* tot, int32_t* ex)
 {
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = base + threadIdx.x;
-        const int32_t c = (p < n) ? cell_of[p] : -1;
-        const bool valid = (p < n) && c >= 0 && c < n_cells;
-        int rank;
-        const int old = wave_aggregated_add(cursor, c, valid, &rank);
-        if (valid) tmp[old + rank] = (int32_t)p;
+    __shared__ int32_t wsum[SORT_THREADS / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int32_t a = tot[2 * t], b = tot[2 * t + 1];
+    int32_t x = a + b;
+    // inclusive wave scan
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int32_t before = 0;
+    for (int q = 0; q < w; ++q) before += wsum[q];
+    const int32_t excl = before + x - (a + b);
+    ex[2 * t] = excl;
+    ex[2 * t + 1] = excl + a;
 }
 
-__global__ void k_copy_i32(const int32_t* a, int32_t* b, int32_t n)
+template <bool FIRST>
+__global__ void __launch_bounds__(SORT_THREADS)
+k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int32_t n,
+             int32_t n_cells, int shift, int32_t mask, int dbits, int32_t nblk,
+             const int32_t* __restrict__ goff, int32_t* __restrict__ keys_out,
+             int32_t* __restrict__ vals_out)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        b[i] = a[i];
-}
+    __shared__ int32_t cnt[SORT_THREADS / 64][RADIX];
+    __shared__ int32_t tot[RADIX];
+    __shared__ int32_t boff[RADIX];
+    __shared__ int32_t gbase[RADIX];
+    __shared__ int32_t sk[SORT_TILE];
+    __shared__ int32_t sv[SORT_TILE];
 
-// Bitonic sort of P (power of two) ints in LDS by `nthreads` threads.
-__device__ __forceinline__ void lds_bitonic(int32_t* a, int P, int tid, int nthreads)
-{
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int e = tid; e < P; e += nthreads) {
-                const int q = e ^ j;
-                if (q > e) {
-                    const int32_t x = a[e], y = a[q];
-                    const bool up = (e & k) == 0;
-                    if ((x > y) == up) { a[e] = y; a[q] = x; }
-                }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < (SORT_THREADS / 64) * RADIX; i += SORT_THREADS)
+        (&cnt[0][0])[i] = 0;
+    __syncthreads();
+
+    const int64_t tbase = (int64_t)blockIdx.x * SORT_TILE;
+    const int64_t wbase = tbase + (int64_t)w * WAVE_SPAN;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int32_t key[SORT_ITEMS], val[SORT_ITEMS], rank[SORT_ITEMS];
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        const int64_t p = wbase + it * 64 + lane;
+        const bool valid = p < n;
+        int32_t k = 0, v = 0;
+        if (valid) {
+            if (FIRST) {
+                k = sort_key(keys_in, p, n_cells);
+                v = (int32_t)p;
+            } else {
+                k = keys_in[p];
+                v = vals_in[p];
             }
-            __syncthreads();
+        }
+        const int32_t d = (k >> shift) & mask;
+        const uint64_t same = match_digit(d, valid, dbits);
+        const int32_t before = __popcll(same & lt_mask);
+        const int32_t old = cnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before == 0) cnt[w][d] = old + __popcll(same);
+        __builtin_amdgcn_wave_barrier();
+        key[it] = k;
+        val[it] = v;
+        rank[it] = valid ? old + before : -1;
+    }
+    __syncthreads();
+    // per digit: exclusive over the waves, tile total
+    for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) {
+        int32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < SORT_THREADS / 64; ++q) {
+            const int32_t c = cnt[q][d];
+            cnt[q][d] = s;
+            s += c;
+        }
+        tot[d] = s;
+        gbase[d] = d <= mask ? goff[(int64_t)d * nblk + blockIdx.x] : 0;
+    }
+    __syncthreads();
+    block_scan_radix(tot, boff);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        if (rank[it] < 0) continue;
+        const int32_t d = (key[it] >> shift) & mask;
+        const int32_t pos = boff[d] + cnt[w][d] + rank[it];
+        sk[pos] = key[it];
+        sv[pos] = val[it];
+    }
+    __syncthreads();
+    const int64_t left = (int64_t)n - tbase;
+    const int32_t tn = left < SORT_TILE ? (int32_t)left : SORT_TILE;
+    for (int s = threadIdx.x; s < tn; s += SORT_THREADS) {
+        const int32_t k = sk[s];
+        const int32_t d = (k >> shift) & mask;
+        const int32_t o = gbase[d] + (s - boff[d]);
+        keys_out[o] = k;
+        vals_out[o] = sv[s];
+    }
+}
+
+// cell_start from the sorted keys (cell_start[k] = first slot whose key is
+// >= k) and the velocity gather into sorted order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sort_finish(const int32_t* __restrict__ keys, const int32_t* __restrict__ perm, int32_t n,
+              int32_t n_cells, int32_t* __restrict__ cell_start, V3<const T> vin, V3<T> vout)
+{
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s <= n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t kprev = s > 0 ? keys[s - 1] : -1;
+        const int32_t kcur = s < n ? keys[s] : n_cells + 1;
+        const int32_t khi = kcur < n_cells ? kcur : n_cells;
+        for (int32_t k = kprev + 1; k <= khi; ++k) cell_start[k] = (int32_t)s;
+        if (s < n) {
+            const int32_t p = perm[s];
+            vout.x[s] = vin.x[p];
+            vout.y[s] = vin.y[p];
+            vout.z[s] = vin.z[p];
         }
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void gather_seg(const int32_t* perm, int32_t s0, int32_t s1,
-                                           V3<const T> vin, V3<T> vout, int tid, int nthreads)
+static int sort_passes(int32_t n_cells, int* bits_total)
 {
-    for (int32_t s = s0 + tid; s < s1; s += nthreads) {
-        const int32_t p = perm[s];
-        vout.x[s] = vin.x[p];
-        vout.y[s] = vin.y[p];
-        vout.z[s] = vin.z[p];
-    }
+    const int nbits = 32 - __builtin_clz((unsigned)n_cells);   // keys go up to n_cells
+    *bits_total = nbits;
+    return (nbits + RADIX_BITS - 1) / RADIX_BITS;
 }
 
-// One 64-thread block per cell (grid-stride) for cells up to SMALL_MAX.
-template <typename T>
-__global__ void __launch_bounds__(64)
-k_fix_small(const int32_t* __restrict__ cell_start, int32_t n_cells,
-            const int32_t* __restrict__ tmp, int32_t* __restrict__ perm, V3<const T> vin,
-            V3<T> vout)
-{
-    __shared__ int32_t a[SMALL_MAX];
-    for (int32_t k = blockIdx.x; k < n_cells; k += gridDim.x) {
-        const int32_t s0 = cell_start[k], s1 = cell_start[k + 1], N = s1 - s0;
-        if (N == 0 || N > SMALL_MAX) continue;
-        int P = 1;
-        while (P < N) P <<= 1;
-        for (int e = threadIdx.x; e < P; e += 64) a[e] = (e < N) ? tmp[s0 + e] : INT32_MAX;
-        __syncthreads();
-        if (N > 1) lds_bitonic(a, P, threadIdx.x, 64);
-        for (int e = threadIdx.x; e < N; e += 64) perm[s0 + e] = a[e];
-        __syncthreads();
-        gather_seg<T>(perm, s0, s1, vin, vout, threadIdx.x, 64);
-    }
-}
-
-// One 256-thread block per big cell; cells beyond BIG_MAX use rank counting
-// in global memory (correct for any size, quadratic cost).
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_fix_big(const int32_t* __restrict__ cell_start, int32_t n_cells,
-          const int32_t* __restrict__ tmp, int32_t* __restrict__ perm, V3<const T> vin,
-          V3<T> vout)
-{
-    __shared__ int32_t a[BIG_MAX];
-    for (int32_t k = blockIdx.x; k < n_cells; k += gridDim.x) {
-        const int32_t s0 = cell_start[k], s1 = cell_start[k + 1], N = s1 - s0;
-        if (N <= SMALL_MAX) continue;
-        if (N <= BIG_MAX) {
-            int P = 1;
-            while (P < N) P <<= 1;
-            for (int e = threadIdx.x; e < P; e += 256) a[e] = (e < N) ? tmp[s0 + e] : INT32_MAX;
-            __syncthreads();
-            lds_bitonic(a, P, threadIdx.x, 256);
-            for (int e = threadIdx.x; e < N; e += 256) perm[s0 + e] = a[e];
-        } else {
-            for (int e = threadIdx.x; e < N; e += 256) {
-                const int32_t x = tmp[s0 + e];
-                int32_t r = 0;
-                for (int32_t f = 0; f < N; ++f) r += (tmp[s0 + f] < x);
-                perm[s0 + r] = x;
-            }
-        }
-        __syncthreads();
-        gather_seg<T>(perm, s0, s1, vin, vout, threadIdx.x, 256);
-        __syncthreads();
-    }
-}
+static int64_t sort_tiles(int32_t n) { return ((int64_t)n + SORT_TILE - 1) / SORT_TILE; }
 
 template <typename T>
 static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_vec3 vin,
                      dsmc_vec3 vout, int32_t* cell_start, int32_t* perm, void* ws,
                      dsmc_status* st, hipStream_t s)
 {
+    if (n == 0) return fill_i32(cell_start, 0, (int64_t)n_cells + 1, s);
+    const int64_t nblk = sort_tiles(n);
     uint8_t* w = static_cast<uint8_t*>(ws);
-    int32_t* counts = reinterpret_cast<int32_t*>(w);
-    w += align_up(sizeof(int32_t) * ((size_t)n_cells + 1));
-    int32_t* cursor = reinterpret_cast<int32_t*>(w);
-    w += align_up(sizeof(int32_t) * ((size_t)n_cells + 1));
-    int32_t* tmp = reinterpret_cast<int32_t*>(w);
-    w += align_up(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t* keys_a = reinterpret_cast<int32_t*>(w);
+    w += align_up(sizeof(int32_t) * (size_t)n);
+    int32_t* keys_b = reinterpret_cast<int32_t*>(w);
+    w += align_up(sizeof(int32_t) * (size_t)n);
+    int32_t* vals_a = reinterpret_cast<int32_t*>(w);
+    w += align_up(sizeof(int32_t) * (size_t)n);
+    int32_t* ghist = reinterpret_cast<int32_t*>(w);
+    w += align_up(sizeof(int32_t) * (size_t)(RADIX * nblk));
+    int32_t* goff = reinterpret_cast<int32_t*>(w);
+    w += align_up(sizeof(int32_t) * (size_t)(RADIX * nblk + 1));
     void* scan_ws = w;
 
-    int rc = fill_i32(counts, 0, n_cells, s);
-    if (rc) return rc;
-    const int pblocks = persistent_blocks(256);
-    int blocks = (int)((n + 255) / 256);
-    if (blocks > pblocks) blocks = pblocks;
-    if (blocks < 1) blocks = 1;
-    if (n > 0) {
-        k_count<<<blocks, 256, 0, s>>>(cell_of, n, n_cells, counts, st);
-        DSMC_LAUNCH_CHECK("sort:count");
+    int nbits = 0;
+    const int passes = sort_passes(n_cells, &nbits);
+    const int32_t* kin = cell_of;
+    const int32_t* vin_idx = nullptr;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = pass * RADIX_BITS;
+        const int dbits = (nbits - shift) < RADIX_BITS ? (nbits - shift) : RADIX_BITS;
+        const int32_t mask = (1 << dbits) - 1;
+        const bool to_final = ((passes - 1 - pass) % 2) == 0;
+        int32_t* kout = to_final ? keys_b : keys_a;
+        int32_t* vout_idx = to_final ? perm : vals_a;
+        if (pass == 0)
+            k_radix_up<true><<<(int)nblk, SORT_THREADS, 0, s>>>(kin, n, n_cells, shift, mask, dbits,
+                                                                (int32_t)nblk, ghist, st);
+        else
+            k_radix_up<false><<<(int)nblk, SORT_THREADS, 0, s>>>(kin, n, n_cells, shift, mask, dbits,
+                                                                 (int32_t)nblk, ghist, st);
+        DSMC_LAUNCH_CHECK("sort:up");
+        int rc = exclusive_scan_i32(ghist, goff, (int64_t)(mask + 1) * nblk, nullptr, scan_ws, s);
+        if (rc) return rc;
+        if (pass == 0)
+            k_radix_down<true><<<(int)nblk, SORT_THREADS, 0, s>>>(
+                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx);
+        else
+            k_radix_down<false><<<(int)nblk, SORT_THREADS, 0, s>>>(
+                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx);
+        DSMC_LAUNCH_CHECK("sort:down");
+        kin = kout;
+        vin_idx = vout_idx;
     }
-    rc = exclusive_scan_i32(counts, cell_start, n_cells, nullptr, scan_ws, s);
-    if (rc) return rc;
-    if (n == 0) return DSMC_OK;
-    k_copy_i32<<<(n_cells + 255) / 256, 256, 0, s>>>(cell_start, cursor, n_cells);
-    DSMC_LAUNCH_CHECK("sort:cursor");
-    k_scatter<<<blocks, 256, 0, s>>>(cell_of, n, n_cells, cursor, tmp);
-    DSMC_LAUNCH_CHECK("sort:scatter");
-    const int cb = n_cells < pblocks * 4 ? n_cells : pblocks * 4;
-    k_fix_small<T><<<cb > 0 ? cb : 1, 64, 0, s>>>(cell_start, n_cells, tmp, perm,
-                                                 v3<const T>(vin), v3<T>(vout));
-    DSMC_LAUNCH_CHECK("sort:fix_small");
-    k_fix_big<T><<<cb > 1024 ? 1024 : (cb > 0 ? cb : 1), 256, 0, s>>>(
-        cell_start, n_cells, tmp, perm, v3<const T>(vin), v3<T>(vout));
-    DSMC_LAUNCH_CHECK("sort:fix_big");
+    const int pblocks = persistent_blocks(256);
+    int64_t blocks = ((int64_t)n + 1 + 255) / 256;
+    if (blocks > pblocks * 4) blocks = pblocks * 4;
+    k_sort_finish<T><<<(int)blocks, 256, 0, s>>>(keys_b, perm, n, n_cells, cell_start,
+                                                v3<const T>(vin), v3<T>(vout));
+    DSMC_LAUNCH_CHECK("sort:finish");
     return DSMC_OK;
 }
 
@@ -213,8 +287,11 @@ using namespace dsmc;
 extern "C" size_t dsmc_sort_cells_ws(int32_t n, int32_t n_cells)
 {
     if (n < 0 || n_cells < 0) return 0;
-    return 2 * align_up(sizeof(int32_t) * ((size_t)n_cells + 1)) +
-           align_up(sizeof(int32_t) * ((size_t)n + 1)) + scan_ws_bytes(n_cells) + 256;
+    const int64_t nblk = sort_tiles(n);
+    return 3 * align_up(sizeof(int32_t) * (size_t)n) +
+           align_up(sizeof(int32_t) * (size_t)(RADIX * nblk)) +
+           align_up(sizeof(int32_t) * (size_t)(RADIX * nblk + 1)) +
+           scan_ws_bytes(RADIX * nblk) + 256;
 }
 
 extern "C" int dsmc_sort_cells(int32_t n, int32_t n_cells, const int32_t* cell_of, int32_t dtype,
@@ -223,6 +300,7 @@ extern "C" int dsmc_sort_cells(int32_t n, int32_t n_cells, const int32_t* cell_o
                                dsmc_stream_t stream)
 {
     if (n < 0 || n_cells < 1) return arg_error("dsmc_sort_cells: n=%d n_cells=%d", n, n_cells);
+    if (n_cells == INT32_MAX) return arg_error("dsmc_sort_cells: n_cells must be < 2^31 - 1");
     if (!cell_start || !ws || (n > 0 && (!cell_of || !perm || !v_in.x || !v_in.y || !v_in.z ||
                                          !v_out.x || !v_out.y || !v_out.z)))
         return arg_error("dsmc_sort_cells: null pointer");
