@@ -35,13 +35,25 @@ int hip_check(hipError_t e, const char* what)
     return DSMC_E_HIP;
 }
 
+// Compute units of the current device (queried once per device).
+int device_cus()
+{
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
 int persistent_blocks(int threads_per_block)
 {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
-    }
+    const int cus = device_cus();
     const int waves_per_block = (threads_per_block + 63) / 64;
     return cus * (32 / waves_per_block > 0 ? 32 / waves_per_block : 1);
 }

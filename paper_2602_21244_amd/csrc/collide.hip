@@ -4,16 +4,17 @@
 // the pair's latents into a post-collision direction (isotropic rule) or, for
 // the other rules, is done by their own kernels.  Phase B applies the pairs of
 // each cell in candidate order on the current velocities with the
-// centre-of-mass update of eq. v_update_pair.  Two Phase-B schedules:
+// centre-of-mass update of eq. v_update_pair.  Schedules:
 //   LANE  -- one lane walks one cell's pairs sequentially;
-//   WAVE  -- one 64-lane workgroup per cell, the cell's velocities staged in
-//            LDS, applying in parallel, round by round, every pending pair
-//            that is the earliest pending pair of both of its particles;
-//   BLOCK -- the same dependency rounds by a 256-lane workgroup on
-//            velocities in global memory (cells too big for WAVE).
-// A pair's update depends only on the current velocities of its two particles,
-// and BLOCK applies each pair after every earlier pair that shares a particle,
-// so both schedules produce bit-identical velocities.
+//   WAVE  -- one 64-lane workgroup per cell (up to 256 pairs), the cell's
+//            velocities staged in LDS, applying in parallel, round by round,
+//            every pending pair that is the earliest pending pair of both of
+//            its particles;
+//   BLOCK -- the same dependency rounds by a 256-lane workgroup (up to 2048
+//            pairs in LDS, larger cells on velocities in global memory).
+// A pair's update depends only on the current velocities of its two
+// particles, and every schedule applies each pair after every earlier pair
+// that shares a particle, so all schedules produce bit-identical velocities.
 #include "collide.hpp"
 
 #include <limits.h>
@@ -99,99 +100,29 @@ k_phaseB_lane(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t max_
     }
 }
 
-constexpr int WV_NMAX = 1024;
-constexpr int WV_PPL = 4;
-
-__device__ __forceinline__ bool wave_fits(int32_t c, int32_t span)
-{
-    return c <= 64 * WV_PPL && span <= WV_NMAX;
-}
-
-constexpr int BLK_THREADS = 256;
-constexpr int BLK_NMAX = 8192;   // particles of a cell tracked in LDS
-constexpr int BLK_MMAX = 8192;   // pairs of a cell tracked in LDS
+// ------------------------------------------------------------------------
+// Dependency rounds with the cell's velocities staged in LDS.  Each thread
+// owns up to PPL pairs (pair q = thread + NT m) with their Phase-A results
+// prefetched into registers.  In round r every pending pair offers the key
+// ((R - r) << 16 | q) to both of its particles (LDS atomicMin; keys of later
+// rounds are smaller, so the table never needs clearing); a pair whose key
+// wins at both particles is the earliest pending pair of both and is applied.
+// ------------------------------------------------------------------------
+constexpr int32_t ROUND_MAX = 32767;
 
 template <typename T, int RULE>
-__global__ void __launch_bounds__(BLK_THREADS)
-k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
-               int32_t skip_wave_cells)
-{
-    __shared__ int32_t first[BLK_NMAX];     // earliest pending pair of each particle
-    __shared__ uint32_t pij[BLK_MMAX];      // local (i | j << 16) of each pair, ~0 once applied
-    __shared__ int32_t red[2][BLK_THREADS / 64];
-    __shared__ int32_t remaining;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int32_t k = blockIdx.x; k < n_cells; k += gridDim.x) {
-        const int32_t c = pr.cnt[k];
-        if (c == 0 || c < min_pairs) continue;
-        const int64_t o = pr.off[k];
-        // local frame: the span of sorted slots the cell's pairs touch
-        int32_t lo = INT32_MAX, hi = -1;
-        for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS) {
-            const int32_t a = pr.i[o + q], b = pr.j[o + q];
-            lo = min(lo, min(a, b));
-            hi = max(hi, max(a, b));
-        }
-#pragma unroll
-        for (int s = 32; s > 0; s >>= 1) {
-            lo = min(lo, __shfl_xor(lo, s, 64));
-            hi = max(hi, __shfl_xor(hi, s, 64));
-        }
-        if (lane == 0) { red[0][wid] = lo; red[1][wid] = hi; }
-        __syncthreads();
-        lo = red[0][0]; hi = red[1][0];
-        for (int w = 1; w < BLK_THREADS / 64; ++w) { lo = min(lo, red[0][w]); hi = max(hi, red[1][w]); }
-        const int32_t span = hi - lo + 1;
-        if (skip_wave_cells && wave_fits(c, span)) continue;  // uniform: done by the WAVE kernel
-        if (span > BLK_NMAX || c > BLK_MMAX || span > 65535) {
-            // beyond the LDS tables: sequential, still in candidate order
-            if (threadIdx.x == 0)
-                for (int32_t q = 0; q < c; ++q)
-                    apply_pair<T, RULE>(v, pr.i[o + q], pr.j[o + q], d, o + q);
-            __syncthreads();
-            continue;
-        }
-        for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS)
-            pij[q] = (uint32_t)(pr.i[o + q] - lo) | ((uint32_t)(pr.j[o + q] - lo) << 16);
-        if (threadIdx.x == 0) remaining = c;
-        __syncthreads();
-        while (remaining > 0) {
-            for (int32_t q = threadIdx.x; q < span; q += BLK_THREADS) first[q] = INT32_MAX;
-            __syncthreads();
-            for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS) {
-                const uint32_t w = pij[q];
-                if (w != 0xffffffffu) {
-                    atomicMin(&first[w & 0xffff], q);
-                    atomicMin(&first[w >> 16], q);
-                }
-            }
-            __syncthreads();
-            int done_here = 0;
-            for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS) {
-                const uint32_t w = pij[q];
-                if (w == 0xffffffffu) continue;
-                const int32_t li = w & 0xffff, lj = w >> 16;
-                if (first[li] == q && first[lj] == q) {
-                    apply_pair<T, RULE>(v, lo + li, lo + lj, d, o + q);
-                    pij[q] = 0xffffffffu;
-                    ++done_here;
-                }
-            }
-            __syncthreads();
-            if (done_here) atomicSub(&remaining, done_here);
-            __syncthreads();
-        }
+struct Payload {
+    T a, b, c, d, e;
+    __device__ __forceinline__ void load(const PairBuf<T>& buf, int64_t p)
+    {
+        a = buf.a[p]; b = buf.b[p]; c = buf.c[p];
+        if (RULE == RULE_CHI) { d = buf.d[p]; e = buf.e[p]; }
     }
-}
-
-// WAVE schedule: one 64-lane workgroup per cell with the cell's velocities
-// staged in LDS; each lane owns up to WV_PPL pairs; dependency rounds as in
-// the BLOCK schedule but entirely in LDS.  Cells with more pairs, or whose
-// pairs span more than WV_NMAX slots, are left to the BLOCK kernel.
+};
 
 template <typename T, int RULE>
 __device__ __forceinline__ void apply_pair_lds(T* lx, T* ly, T* lz, int32_t a, int32_t b,
-                                               const PairBuf<T>& d, int64_t p)
+                                               const Payload<T, RULE>& pl)
 {
     const double xa = lx[a], ya = ly[a], za = lz[a];
     const double xb = lx[b], yb = ly[b], zb = lz[b];
@@ -200,15 +131,15 @@ __device__ __forceinline__ void apply_pair_lds(T* lx, T* ly, T* lz, int32_t a, i
     double g;
     if (RULE == RULE_DIR) {
         g = sqrt(rx * rx + ry * ry + rz * rz);
-        const double a0 = d.a[p], a1 = d.b[p], a2 = d.c[p];
+        const double a0 = pl.a, a1 = pl.b, a2 = pl.c;
         const double inv = 1.0 / sqrt(a0 * a0 + a1 * a1 + a2 * a2);
         u[0] = a0 * inv; u[1] = a1 * inv; u[2] = a2 * inv;
     } else {
         double vh[3], e[3];
         g = unit3<double>(rx, ry, rz, vh);
-        const double xi[3] = {(double)d.c[p], (double)d.d[p], (double)d.e[p]};
+        const double xi[3] = {(double)pl.c, (double)pl.d, (double)pl.e};
         perp_dir<double>(xi, vh, e);
-        const double cc = d.a[p], sc = d.b[p];
+        const double cc = pl.a, sc = pl.b;
         u[0] = cc * vh[0] + sc * e[0];
         u[1] = cc * vh[1] + sc * e[1];
         u[2] = cc * vh[2] + sc * e[2];
@@ -219,9 +150,104 @@ __device__ __forceinline__ void apply_pair_lds(T* lx, T* ly, T* lz, int32_t a, i
     lx[b] = (T)(cx - px); ly[b] = (T)(cy - py); lz[b] = (T)(cz - pz);
 }
 
+// Any thread of the workgroup with a pending pair (also a barrier).
+template <int NT>
+__device__ __forceinline__ bool any_pending(uint32_t pend)
+{
+    if (NT == 64) {
+        __syncthreads();
+        return __ballot(pend != 0) != 0;
+    }
+    return __syncthreads_or(pend != 0) != 0;
+}
+
+// One cell (c pairs from offset o; pair slots within [lo, lo + span)) on NT
+// threads with LDS tables lx/ly/lz/first of at least span entries.
+template <typename T, int RULE, int NT, int PPL>
+__device__ __forceinline__ void cell_rounds_lds(const PairsView& pr, V3<T> v, const PairBuf<T>& d,
+                                                int32_t c, int64_t o, int32_t lo, int32_t span,
+                                                const int32_t (&pa_g)[PPL],
+                                                const int32_t (&pb_g)[PPL], T* lx, T* ly, T* lz,
+                                                int32_t* first)
+{
+    const int t = threadIdx.x;
+    int32_t pa[PPL], pb[PPL];
+    Payload<T, RULE> pl[PPL];
+    uint32_t pend = 0;
+#pragma unroll
+    for (int m = 0; m < PPL; ++m) {
+        const int32_t q = t + NT * m;
+        pa[m] = pa_g[m] - lo;
+        pb[m] = pb_g[m] - lo;
+        if (q < c) {
+            pl[m].load(d, o + q);
+            pend |= 1u << m;
+        }
+    }
+    for (int32_t q = t; q < span; q += NT) {
+        lx[q] = v.x[lo + q];
+        ly[q] = v.y[lo + q];
+        lz[q] = v.z[lo + q];
+        first[q] = INT32_MAX;
+    }
+    int32_t r = 0;
+    while (any_pending<NT>(pend)) {
+        const int32_t kb = (ROUND_MAX - r) << 16;
+#pragma unroll
+        for (int m = 0; m < PPL; ++m)
+            if (pend & (1u << m)) {
+                const int32_t key = kb | (t + NT * m);
+                atomicMin(&first[pa[m]], key);
+                atomicMin(&first[pb[m]], key);
+            }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PPL; ++m) {
+            const int32_t key = kb | (t + NT * m);
+            if ((pend & (1u << m)) && first[pa[m]] == key && first[pb[m]] == key) {
+                apply_pair_lds<T, RULE>(lx, ly, lz, pa[m], pb[m], pl[m]);
+                pend &= ~(1u << m);
+            }
+        }
+        ++r;
+    }
+    for (int32_t q = t; q < span; q += NT) {
+        v.x[lo + q] = lx[q];
+        v.y[lo + q] = ly[q];
+        v.z[lo + q] = lz[q];
+    }
+    __syncthreads();
+}
+
+// Min / max of the cell's pair slots over the workgroup.
+template <int NT>
+__device__ __forceinline__ void group_minmax(int32_t& lo, int32_t& hi, int32_t* red)
+{
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+        lo = min(lo, __shfl_xor(lo, s, 64));
+        hi = max(hi, __shfl_xor(hi, s, 64));
+    }
+    if (NT == 64) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { red[wid] = lo; red[NT / 64 + wid] = hi; }
+    __syncthreads();
+    lo = red[0];
+    hi = red[NT / 64];
+    for (int w = 1; w < NT / 64; ++w) { lo = min(lo, red[w]); hi = max(hi, red[NT / 64 + w]); }
+    __syncthreads();
+}
+
+// WAVE schedule: one 64-lane workgroup per cell with thr < pairs <= 256 whose
+// pairs span at most 1024 slots; a cell that does not fit is appended to the
+// list handled by the BLOCK kernel (list[0] = length, list[1..] = cells).
+constexpr int WV_NMAX = 1024;
+constexpr int WV_PPL = 4;
+
 template <typename T, int RULE>
 __global__ void __launch_bounds__(64)
-k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs)
+k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
+              int32_t* list)
 {
     __shared__ T lx[WV_NMAX], ly[WV_NMAX], lz[WV_NMAX];
     __shared__ int32_t first[WV_NMAX];
@@ -232,7 +258,6 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
         const int64_t o = pr.off[k];
         int32_t pa[WV_PPL], pb[WV_PPL];
         int32_t lo = INT32_MAX, hi = -1;
-        uint32_t pend = 0;
 #pragma unroll
         for (int m = 0; m < WV_PPL; ++m) {
             const int32_t q = lane + 64 * m;
@@ -243,52 +268,144 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
                 pb[m] = pr.j[o + q];
                 lo = min(lo, min(pa[m], pb[m]));
                 hi = max(hi, max(pa[m], pb[m]));
-                pend |= 1u << m;
             }
         }
-#pragma unroll
-        for (int sft = 32; sft > 0; sft >>= 1) {
-            lo = min(lo, __shfl_xor(lo, sft, 64));
-            hi = max(hi, __shfl_xor(hi, sft, 64));
-        }
+        group_minmax<64>(lo, hi, nullptr);
         const int32_t span = hi - lo + 1;
-        if (!wave_fits(c, span)) continue;
-        for (int32_t q = lane; q < span; q += 64) {
-            lx[q] = v.x[lo + q];
-            ly[q] = v.y[lo + q];
-            lz[q] = v.z[lo + q];
-        }
-#pragma unroll
-        for (int m = 0; m < WV_PPL; ++m) { pa[m] -= lo; pb[m] -= lo; }
-        __syncthreads();
-        while (__ballot(pend != 0)) {
-            for (int32_t q = lane; q < span; q += 64) first[q] = INT32_MAX;
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < WV_PPL; ++m)
-                if (pend & (1u << m)) {
-                    atomicMin(&first[pa[m]], lane + 64 * m);
-                    atomicMin(&first[pb[m]], lane + 64 * m);
-                }
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < WV_PPL; ++m) {
-                const int32_t q = lane + 64 * m;
-                if ((pend & (1u << m)) && first[pa[m]] == q && first[pb[m]] == q) {
-                    apply_pair_lds<T, RULE>(lx, ly, lz, pa[m], pb[m], d, o + q);
-                    pend &= ~(1u << m);
-                }
+        if (span > WV_NMAX) {
+            if (lane == 0) {
+                const int32_t at = atomicAdd(&list[0], 1);
+                list[1 + at] = k;
             }
-            __syncthreads();
+            continue;
         }
-        for (int32_t q = lane; q < span; q += 64) {
-            v.x[lo + q] = lx[q];
-            v.y[lo + q] = ly[q];
-            v.z[lo + q] = lz[q];
+#pragma unroll
+        for (int m = 0; m < WV_PPL; ++m)
+            if (lane + 64 * m >= c) { pa[m] = lo; pb[m] = lo; }
+        cell_rounds_lds<T, RULE, 64, WV_PPL>(pr, v, d, c, o, lo, span, pa, pb, lx, ly, lz, first);
+    }
+}
+
+// BLOCK schedule: 256 threads per cell.  Cells with up to 2048 pairs spanning
+// up to 4096 slots run the LDS rounds; larger ones (up to 8192) run the same
+// rounds on velocities in global memory with the tables in LDS; beyond that
+// one thread applies the pairs in order.  Handles the cells with at least
+// min_pairs pairs not taken by the WAVE kernel (wave_max: its pair limit, or
+// 0 when it did not run) and the cells in `list`.
+constexpr int BLK_THREADS = 256;
+constexpr int BLK_PPL = 8;
+constexpr int BLK_NMAX = 4096;      // LDS rounds
+constexpr int BLK_GMAX = 8192;      // global-memory rounds
+
+template <typename T>
+struct BlkLds {
+    static constexpr size_t lds = (size_t)BLK_NMAX * (3 * sizeof(T) + sizeof(int32_t));
+    static constexpr size_t glb = (size_t)BLK_GMAX * 2 * sizeof(int32_t);
+    static constexpr size_t bytes = lds > glb ? lds : glb;
+};
+
+template <typename T, int RULE>
+__device__ void cell_rounds_global(V3<T> v, const PairBuf<T>& d, const PairsView& pr, int32_t c,
+                                   int64_t o, int32_t lo, int32_t span, int32_t* first,
+                                   uint32_t* pij)
+{
+    __shared__ int32_t remaining;
+    for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS)
+        pij[q] = (uint32_t)(pr.i[o + q] - lo) | ((uint32_t)(pr.j[o + q] - lo) << 16);
+    if (threadIdx.x == 0) remaining = c;
+    __syncthreads();
+    while (remaining > 0) {
+        for (int32_t q = threadIdx.x; q < span; q += BLK_THREADS) first[q] = INT32_MAX;
+        __syncthreads();
+        for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS) {
+            const uint32_t w = pij[q];
+            if (w != 0xffffffffu) {
+                atomicMin(&first[w & 0xffff], q);
+                atomicMin(&first[w >> 16], q);
+            }
         }
+        __syncthreads();
+        int done_here = 0;
+        for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS) {
+            const uint32_t w = pij[q];
+            if (w == 0xffffffffu) continue;
+            const int32_t li = w & 0xffff, lj = w >> 16;
+            if (first[li] == q && first[lj] == q) {
+                apply_pair<T, RULE>(v, lo + li, lo + lj, d, o + q);
+                pij[q] = 0xffffffffu;
+                ++done_here;
+            }
+        }
+        __syncthreads();
+        if (done_here) atomicSub(&remaining, done_here);
         __syncthreads();
     }
 }
+
+template <typename T, int RULE>
+__global__ void __launch_bounds__(BLK_THREADS)
+k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
+               int32_t wave_max, const int32_t* list)
+{
+    __shared__ __attribute__((aligned(16))) char smem[BlkLds<T>::bytes];
+    __shared__ int32_t red[2 * (BLK_THREADS / 64)];
+    T* lx = reinterpret_cast<T*>(smem);
+    T* ly = lx + BLK_NMAX;
+    T* lz = ly + BLK_NMAX;
+    int32_t* first = reinterpret_cast<int32_t*>(lz + BLK_NMAX);
+    const int64_t n_listed = list ? list[0] : 0;
+    for (int64_t idx = blockIdx.x; idx < (int64_t)n_cells + n_listed; idx += gridDim.x) {
+        int32_t k;
+        if (idx < n_cells) {
+            k = (int32_t)idx;
+            const int32_t c = pr.cnt[k];
+            if (c == 0 || c < min_pairs || c <= wave_max) continue;
+        } else {
+            k = list[1 + (idx - n_cells)];
+        }
+        const int32_t c = pr.cnt[k];
+        const int64_t o = pr.off[k];
+        int32_t pa[BLK_PPL], pb[BLK_PPL];
+        int32_t lo = INT32_MAX, hi = -1;
+#pragma unroll
+        for (int m = 0; m < BLK_PPL; ++m) {
+            const int32_t q = threadIdx.x + BLK_THREADS * m;
+            pa[m] = 0;
+            pb[m] = 0;
+            if (q < c) {
+                pa[m] = pr.i[o + q];
+                pb[m] = pr.j[o + q];
+                lo = min(lo, min(pa[m], pb[m]));
+                hi = max(hi, max(pa[m], pb[m]));
+            }
+        }
+        for (int32_t q = threadIdx.x + BLK_THREADS * BLK_PPL; q < c; q += BLK_THREADS) {
+            lo = min(lo, min(pr.i[o + q], pr.j[o + q]));
+            hi = max(hi, max(pr.i[o + q], pr.j[o + q]));
+        }
+        group_minmax<BLK_THREADS>(lo, hi, red);
+        const int32_t span = hi - lo + 1;
+        if (c <= BLK_THREADS * BLK_PPL && span <= BLK_NMAX) {
+#pragma unroll
+            for (int m = 0; m < BLK_PPL; ++m)
+                if (threadIdx.x + BLK_THREADS * m >= c) { pa[m] = lo; pb[m] = lo; }
+            cell_rounds_lds<T, RULE, BLK_THREADS, BLK_PPL>(pr, v, d, c, o, lo, span, pa, pb, lx, ly,
+                                                           lz, first);
+        } else if (c <= BLK_GMAX && span <= BLK_GMAX) {
+            int32_t* gfirst = reinterpret_cast<int32_t*>(smem);
+            uint32_t* pij = reinterpret_cast<uint32_t*>(gfirst + BLK_GMAX);
+            cell_rounds_global<T, RULE>(v, d, pr, c, o, lo, span, gfirst, pij);
+        } else {
+            // beyond the LDS tables: sequential, still in candidate order
+            if (threadIdx.x == 0)
+                for (int32_t q = 0; q < c; ++q)
+                    apply_pair<T, RULE>(v, pr.i[o + q], pr.j[o + q], d, o + q);
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_zero_i32(int32_t* p) { *p = 0; }
 
 int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v,
             const dsmc_pairs& pairs, void* dirs, int64_t cap, int32_t schedule, hipStream_t s)
@@ -298,8 +415,8 @@ int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsm
     const int pb = persistent_blocks(256);
     int lb = (n_cells + 255) / 256;
     lb = lb < 1 ? 1 : (lb > pb ? pb : lb);
-    // cells with at most `thr` pairs: LANE; larger: WAVE if they fit its LDS
-    // tables (AUTO, WAVE), else BLOCK
+    // cells with at most `thr` pairs: LANE; larger: WAVE when they fit its
+    // LDS tables (AUTO, WAVE), else BLOCK
     int32_t thr = block_threshold();
     bool use_wave = true;
     if (schedule == DSMC_SCHED_LANE) thr = INT32_MAX;
@@ -307,24 +424,29 @@ int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsm
     if (schedule == DSMC_SCHED_WAVE) thr = 0;
     const bool need_lane = thr > 0;
     const bool need_rest = thr < INT32_MAX;
-    int bb = n_cells < pb ? n_cells : pb;
-    bb = bb < 1 ? 1 : bb;
-    int wb = n_cells < pb * 8 ? n_cells : pb * 8;
+    const int cus = device_cus();
+    int wb = n_cells < cus * 40 ? n_cells : cus * 40;
     wb = wb < 1 ? 1 : wb;
+    int bb = n_cells < cus * 2 ? n_cells : cus * 2;
+    bb = bb < 1 ? 1 : bb;
 #define DSMC_PHASEB(T, R)                                                                   \
     do {                                                                                    \
         PairBuf<T> d = PairBuf<T>::of(dirs, cap);                                           \
+        int32_t* list = reinterpret_cast<int32_t*>(d.f);                                    \
         if (need_lane) {                                                                    \
             k_phaseB_lane<T, R><<<lb, 256, 0, s>>>(n_cells, pr, v3<T>(v), d, thr);          \
             DSMC_LAUNCH_CHECK("phaseB:lane");                                               \
         }                                                                                   \
         if (need_rest && use_wave) {                                                        \
-            k_phaseB_wave<T, R><<<wb, 64, 0, s>>>(n_cells, pr, v3<T>(v), d, thr + 1);       \
+            k_zero_i32<<<1, 1, 0, s>>>(list);                                               \
+            DSMC_LAUNCH_CHECK("phaseB:list");                                               \
+            k_phaseB_wave<T, R><<<wb, 64, 0, s>>>(n_cells, pr, v3<T>(v), d, thr + 1, list); \
             DSMC_LAUNCH_CHECK("phaseB:wave");                                               \
         }                                                                                   \
         if (need_rest) {                                                                    \
-            k_phaseB_block<T, R><<<bb, BLK_THREADS, 0, s>>>(n_cells, pr, v3<T>(v), d,       \
-                                                            thr + 1, use_wave ? 1 : 0);     \
+            k_phaseB_block<T, R><<<bb, BLK_THREADS, 0, s>>>(                                \
+                n_cells, pr, v3<T>(v), d, thr + 1, use_wave ? 64 * WV_PPL : 0,              \
+                use_wave ? list : nullptr);                                                 \
             DSMC_LAUNCH_CHECK("phaseB:block");                                              \
         }                                                                                   \
     } while (0)

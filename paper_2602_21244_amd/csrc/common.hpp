@@ -23,6 +23,8 @@ int hip_check(hipError_t e, const char* what);
 
 // Persistent grid for data-dependent sizes (pair counts live on the device).
 int persistent_blocks(int threads_per_block);
+// Compute units of the current device.
+int device_cus();
 
 inline hipStream_t as_stream(dsmc_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 

@@ -482,11 +482,7 @@ static int launch_one(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<
         if (e != hipSuccess) return hip_check(e, "mlp: set LDS attribute");
         attr_set = true;
     }
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
-    }
+    const int cus = device_cus();
     const int threads = (H == 256 || NT > 1) ? 256 : 512;
     const int64_t groups = (max_rows + 32 * NT - 1) / (32 * NT);
     int64_t blocks = (groups + threads / 64 - 1) / (threads / 64);

@@ -1,11 +1,17 @@
 // No-Time-Counter pair selection (section "Cell partition and collision-pair
 // selection").  Candidates are generated for all cells at once, one lane per
 // candidate, so the work is balanced however uneven the cell populations are:
-//   count M_k per cell -> scan (candidate offsets) -> draw + accept per
-//   candidate -> scan of the accept flags -> scatter accepted pairs densely
-//   (cell-major, candidate order) -> per-cell offsets and counts.
-// The decision arithmetic (g, the candidate count) uses explicitly rounded
-// FP64 operations so it is the same on every launch shape.
+//   count M_k per cell -> scan (candidate offsets) -> accept pass: each wave
+//   takes a chunk of 1024 consecutive candidates (one binary search for the
+//   chunk's first cell, then a forward walk), draws and decides them and
+//   counts the accepted ones -> scan of the chunk counts -> emit pass: the
+//   same decisions again, accepted pairs written densely (cell-major,
+//   candidate order) at the chunk's offset, with each cell's pair offset ->
+//   per-cell counts.
+// Deciding twice costs arithmetic and L2-resident velocity reads, and saves
+// writing and re-reading every candidate.  The decision arithmetic (g, the
+// candidate count) uses explicitly rounded FP64 operations so it is the same
+// on every launch shape and in both passes.
 #include <math.h>
 
 #include "common.hpp"
@@ -68,14 +74,18 @@ k_cand_count(const int32_t* __restrict__ cell_start, int32_t n_cells,
     }
 }
 
-// Overflow decision: total candidates vs capacity.
+constexpr int CAND_ROUNDS = 16;
+constexpr int CAND_CHUNK = 64 * CAND_ROUNDS;
+
+// Overflow decision: total candidates vs capacity; number of chunks.
 __global__ void k_cand_check(const int64_t* total, int64_t cap, int32_t* ok, int64_t* n_use,
-                             dsmc_status* st)
+                             int64_t* n_chunks, dsmc_status* st)
 {
     const int64_t t = *total;
     const bool fits = t <= cap;
     *ok = fits ? 1 : 0;
     *n_use = fits ? t : 0;
+    *n_chunks = fits ? (t + CAND_CHUNK - 1) / CAND_CHUNK : 0;
     if (st) {
         st->n_cand = t;
         if (!fits) atomicOr(&st->flags, (uint32_t)DSMC_ST_PAIR_OVERFLOW);
@@ -94,102 +104,133 @@ __device__ __forceinline__ int32_t find_cell(const int32_t* __restrict__ off, in
     return lo;
 }
 
+// Candidate t of cell k: indices (Lemire multiply-shift, j != i) and the
+// acceptance test U < (g / g_hat)^e.
 template <typename T>
+__device__ __forceinline__ bool cand_decide(const int32_t* __restrict__ cell_start, int32_t k,
+                                            int32_t t, const double* __restrict__ mom, double e,
+                                            const dsmc_rng& rng, const V3<const T>& v,
+                                            int32_t& pi, int32_t& pj)
+{
+    const int32_t s0 = cell_start[k], N = cell_start[k + 1] - s0;
+    const U4 r = draw(rng, (uint32_t)t, (uint32_t)k, SLOT_CAND);
+    int32_t i = (int32_t)(((uint64_t)r.a * (uint64_t)N) >> 32);
+    int32_t j = (int32_t)(((uint64_t)r.b * (uint64_t)(N - 1)) >> 32);
+    if (j >= i) j += 1;
+    const double U = unif53(r.c, r.d);
+    const double dx = (double)v.x[s0 + i] - (double)v.x[s0 + j];
+    const double dy = (double)v.y[s0 + i] - (double)v.y[s0 + j];
+    const double dz = (double)v.z[s0 + i] - (double)v.z[s0 + j];
+    const double g2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                __dmul_rn(dz, dz));
+    const double g = sqrt(g2);
+    const double ghat = 2.0 * mom[6 * (size_t)k + 4];
+    const double ratio = g / ghat;
+    const double p = (e == 1.0) ? ratio : pow(ratio, e);
+    pi = s0 + i;
+    pj = s0 + j;
+    return U < p;
+}
+
+// EMIT = false: accepted candidates per chunk.  EMIT = true: write the
+// accepted pairs from the chunk offsets, and pair_off[k] for every cell whose
+// candidates start inside the chunk (empty cells get the offset of the next
+// candidate).
+template <typename T, bool EMIT>
 __global__ void __launch_bounds__(256)
-k_candidates(const int32_t* __restrict__ cell_start, int32_t n_cells,
-             const int32_t* __restrict__ cand_off, const int64_t* __restrict__ n_use,
-             const double* __restrict__ mom, double e, dsmc_rng rng, V3<const T> v,
-             int32_t* __restrict__ flag, int32_t* __restrict__ ci, int32_t* __restrict__ cj,
-             int32_t* __restrict__ ck)
+k_cand_chunks(const int32_t* __restrict__ cell_start, int32_t n_cells,
+              const int32_t* __restrict__ cand_off, const int64_t* __restrict__ n_use,
+              const double* __restrict__ mom, double e, dsmc_rng rng, V3<const T> v,
+              int32_t* __restrict__ chunk_cnt, const int32_t* __restrict__ chunk_off,
+              int32_t* __restrict__ pi, int32_t* __restrict__ pj, int32_t* __restrict__ pc,
+              int32_t* __restrict__ pair_off)
 {
     const int64_t total = *n_use;
+    const int64_t nch = (total + CAND_CHUNK - 1) / CAND_CHUNK;
     const int lane = threadIdx.x & 63;
-    // one binary search per wavefront (for its first candidate); lanes then
-    // step forward over the few cells the wave's 64 candidates span
-    for (int64_t base = (blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63)); base < total;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = base + lane;
-        int32_t k = find_cell(cand_off, n_cells, (int32_t)base);
-        if (c >= total) continue;
-        while (k + 1 < n_cells && cand_off[k + 1] <= c) ++k;
-        const int32_t t = (int32_t)c - cand_off[k];
-        const int32_t s0 = cell_start[k], N = cell_start[k + 1] - s0;
-        const U4 r = draw(rng, (uint32_t)t, (uint32_t)k, SLOT_CAND);
-        int32_t i = (int32_t)(((uint64_t)r.a * (uint64_t)N) >> 32);
-        int32_t j = (int32_t)(((uint64_t)r.b * (uint64_t)(N - 1)) >> 32);
-        if (j >= i) j += 1;
-        const double U = unif53(r.c, r.d);
-        const double dx = (double)v.x[s0 + i] - (double)v.x[s0 + j];
-        const double dy = (double)v.y[s0 + i] - (double)v.y[s0 + j];
-        const double dz = (double)v.z[s0 + i] - (double)v.z[s0 + j];
-        const double g2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                                    __dmul_rn(dz, dz));
-        const double g = sqrt(g2);
-        const double ghat = 2.0 * mom[6 * (size_t)k + 4];
-        const double ratio = g / ghat;
-        const double p = (e == 1.0) ? ratio : pow(ratio, e);
-        flag[c] = (U < p) ? 1 : 0;
-        ci[c] = s0 + i;
-        cj[c] = s0 + j;
-        ck[c] = k;
-    }
-}
-
-__global__ void __launch_bounds__(256)
-k_pairs_scatter(const int64_t* __restrict__ n_use, const int32_t* __restrict__ flag,
-                const int32_t* __restrict__ pos, const int32_t* __restrict__ ci,
-                const int32_t* __restrict__ cj, const int32_t* __restrict__ ck,
-                int32_t* __restrict__ pi, int32_t* __restrict__ pj, int32_t* __restrict__ pc)
-{
-    const int64_t total = *n_use;
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < total;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        if (flag[c]) {
-            const int32_t p = pos[c];
-            pi[p] = ci[c];
-            pj[p] = cj[c];
-            pc[p] = ck[c];
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t ch = wave; ch < nch; ch += nwaves) {
+        const int64_t cbase = ch * CAND_CHUNK;
+        int32_t kw = find_cell(cand_off, n_cells, (int32_t)cbase);
+        int32_t pos = EMIT ? chunk_off[ch] : 0;
+        int32_t acc = 0;
+        for (int r = 0; r < CAND_ROUNDS; ++r) {
+            const int64_t base = cbase + r * 64;
+            if (base >= total) break;
+            const int64_t c = base + lane;
+            const bool valid = c < total;
+            int32_t k = kw, i = 0, j = 0;
+            bool take = false;
+            if (valid) {
+                while (k + 1 < n_cells && cand_off[k + 1] <= c) ++k;
+                take = cand_decide<T>(cell_start, k, (int32_t)(c - cand_off[k]), mom, e, rng, v,
+                                      i, j);
+            }
+            const uint64_t ab = __ballot(take);
+            if (EMIT) {
+                const int32_t p = pos + (int32_t)__popcll(ab & lt);
+                if (take) {
+                    pi[p] = i;
+                    pj[p] = j;
+                    pc[p] = k;
+                }
+                if (valid && c == cand_off[k]) {
+                    pair_off[k] = p;
+                    for (int32_t q = k - 1; q >= 0 && cand_off[q] == c; --q) pair_off[q] = p;
+                }
+                pos += (int32_t)__popcll(ab);
+            } else {
+                acc += (int32_t)__popcll(ab);
+            }
+            kw = __shfl(k, 63, 64);
         }
+        if (!EMIT && lane == 0) chunk_cnt[ch] = acc;
     }
 }
 
+// Pair counts per cell; cells whose candidates would start at or after the
+// last candidate (none left) get the total as offset.
 __global__ void __launch_bounds__(256)
-k_pair_offsets(int32_t n_cells, const int32_t* __restrict__ cand_off,
-               const int32_t* __restrict__ pos, const int32_t* __restrict__ ok,
-               const int64_t* __restrict__ n_use, int32_t* __restrict__ off,
-               int32_t* __restrict__ cnt, dsmc_status* st)
+k_pair_counts(int32_t n_cells, const int32_t* __restrict__ cand_off,
+              const int32_t* __restrict__ ok, const int64_t* __restrict__ n_use,
+              const int64_t* __restrict__ n_chunks, const int32_t* __restrict__ chunk_off,
+              int32_t* __restrict__ off, int32_t* __restrict__ cnt, dsmc_status* st)
 {
     const bool fits = *ok != 0;
+    const int64_t total = *n_use;
+    const int32_t npairs = fits ? chunk_off[*n_chunks] : 0;
     for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_cells;
          k += gridDim.x * blockDim.x) {
-        if (fits) {
-            const int32_t a = pos[cand_off[k]], b = pos[cand_off[k + 1]];
-            off[k] = a;
-            cnt[k] = b - a;
-        } else {
+        if (!fits) {
             off[k] = 0;
             cnt[k] = 0;
+            continue;
         }
+        const bool tail = cand_off[k] >= total;
+        const int32_t a = tail ? npairs : off[k];
+        const int32_t b = (k + 1 == n_cells || cand_off[k + 1] >= total) ? npairs : off[k + 1];
+        if (tail) off[k] = a;
+        cnt[k] = b - a;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && st) {
-        st->n_pairs = fits ? (int64_t)pos[*n_use] : 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && st) st->n_pairs = npairs;
 }
 
 struct SelectWs {
-    int32_t* cand_cnt;  // [n_cells]
-    int32_t* cand_off;  // [n_cells + 1]
-    int64_t* total;     // candidates
-    int64_t* n_use;     // candidates processed (0 on overflow)
+    int32_t* cand_cnt;   // [n_cells]
+    int32_t* cand_off;   // [n_cells + 1]
+    int64_t* total;      // candidates
+    int64_t* n_use;      // candidates processed (0 on overflow)
+    int64_t* n_chunks;
     int32_t* ok;
-    int32_t* flag;      // [cap]
-    int32_t* pos;       // [cap + 1]
-    int32_t* ci;        // [cap]
-    int32_t* cj;        // [cap]
-    int32_t* ck;        // [cap]
+    int32_t* chunk_cnt;  // [max chunks]
+    int32_t* chunk_off;  // [max chunks + 1]
     void* scan;
     size_t bytes;
 };
+
+static int64_t max_chunks(int64_t cap) { return (cap + CAND_CHUNK - 1) / CAND_CHUNK + 1; }
 
 static SelectWs select_ws_layout(void* base, int32_t n_cells, int64_t cap)
 {
@@ -197,17 +238,16 @@ static SelectWs select_ws_layout(void* base, int32_t n_cells, int64_t cap)
     uint8_t* p = static_cast<uint8_t*>(base);
     size_t o = 0;
     auto take = [&](size_t b) { uint8_t* r = p ? p + o : nullptr; o += align_up(b); return r; };
+    const int64_t mc = max_chunks(cap);
     w.cand_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)n_cells + 1)));
     w.cand_off = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)n_cells + 2)));
     w.total = reinterpret_cast<int64_t*>(take(sizeof(int64_t)));
     w.n_use = reinterpret_cast<int64_t*>(take(sizeof(int64_t)));
+    w.n_chunks = reinterpret_cast<int64_t*>(take(sizeof(int64_t)));
     w.ok = reinterpret_cast<int32_t*>(take(sizeof(int32_t)));
-    w.flag = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)cap + 1)));
-    w.pos = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)cap + 2)));
-    w.ci = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)cap + 1)));
-    w.cj = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)cap + 1)));
-    w.ck = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)cap + 1)));
-    const size_t sb = scan_ws_bytes((int64_t)(cap > n_cells ? cap : n_cells) + 1);
+    w.chunk_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)mc));
+    w.chunk_off = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)mc + 1)));
+    const size_t sb = scan_ws_bytes((int64_t)(mc > n_cells ? mc : n_cells) + 1);
     w.scan = take(sb);
     w.bytes = o;
     return w;
@@ -226,19 +266,23 @@ static int select_impl(int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v, 
     DSMC_LAUNCH_CHECK("select:count");
     int rc = exclusive_scan_i32(w.cand_cnt, w.cand_off, n_cells, w.total, w.scan, s);
     if (rc) return rc;
-    k_cand_check<<<1, 1, 0, s>>>(w.total, pairs.cap, w.ok, w.n_use, st);
+    k_cand_check<<<1, 1, 0, s>>>(w.total, pairs.cap, w.ok, w.n_use, w.n_chunks, st);
     DSMC_LAUNCH_CHECK("select:check");
-    k_candidates<T><<<pb, 256, 0, s>>>(cell_start, n_cells, w.cand_off, w.n_use, mom, law.e, rng,
-                                       v3<const T>(v), w.flag, w.ci, w.cj, w.ck);
-    DSMC_LAUNCH_CHECK("select:candidates");
-    rc = exclusive_scan_i32_dev(w.flag, w.pos, w.n_use, pairs.cap, w.scan, s);
+    const V3<const T> vv = v3<const T>(v);
+    k_cand_chunks<T, false><<<pb, 256, 0, s>>>(cell_start, n_cells, w.cand_off, w.n_use, mom,
+                                               law.e, rng, vv, w.chunk_cnt, nullptr, nullptr,
+                                               nullptr, nullptr, nullptr);
+    DSMC_LAUNCH_CHECK("select:accept");
+    rc = exclusive_scan_i32_dev(w.chunk_cnt, w.chunk_off, w.n_chunks, max_chunks(pairs.cap),
+                                w.scan, s);
     if (rc) return rc;
-    k_pairs_scatter<<<pb, 256, 0, s>>>(w.n_use, w.flag, w.pos, w.ci, w.cj, w.ck, pairs.i,
-                                       pairs.j, pairs.cell);
-    DSMC_LAUNCH_CHECK("select:scatter");
-    k_pair_offsets<<<cb, 256, 0, s>>>(n_cells, w.cand_off, w.pos, w.ok, w.n_use, pairs.off,
-                                      pairs.cnt, st);
-    DSMC_LAUNCH_CHECK("select:offsets");
+    k_cand_chunks<T, true><<<pb, 256, 0, s>>>(cell_start, n_cells, w.cand_off, w.n_use, mom,
+                                              law.e, rng, vv, nullptr, w.chunk_off, pairs.i,
+                                              pairs.j, pairs.cell, pairs.off);
+    DSMC_LAUNCH_CHECK("select:emit");
+    k_pair_counts<<<cb, 256, 0, s>>>(n_cells, w.cand_off, w.ok, w.n_use, w.n_chunks, w.chunk_off,
+                                     pairs.off, pairs.cnt, st);
+    DSMC_LAUNCH_CHECK("select:counts");
     return DSMC_OK;
 }
 

@@ -279,11 +279,7 @@ extern "C" int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, i
     hipStream_t s = as_stream(stream);
     rc = fill_i32(A.queue, 0, 1, s);
     if (rc) return rc;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
-    }
+    const int cus = device_cus();
     int blocks = cus * 2;
     if (blocks > n_cells) blocks = n_cells;
     if (dtype == DSMC_F64) {
