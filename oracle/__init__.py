@@ -475,15 +475,149 @@ def cosine_lr(t, T, lr_max, lr_min=1e-6):
 
 
 # ---------------------------------------------------------------------------
+# Angle network and deflection-angle table (sections "Neural Network
+# Architecture", "Neural Surrogate Training" and "Runtime Acceleration via
+# Neural Table Look-up").  The network maps (normalised ln E_r, b / b_max) to
+# a prediction of ln(1 + theta), theta the folded deflection angle; hidden
+# layers SiLU, output Softplus.
+# ---------------------------------------------------------------------------
+def softplus(zz):
+    """ln(1 + e^z), evaluated without overflow."""
+    return np.logaddexp(0.0, np.asarray(zz, np.float64))
+
+
+def sigmoid(zz):
+    """1 / (1 + e^-z), with e^z / (1 + e^z) for z < 0 (no overflow)."""
+    zz = np.asarray(zz, np.float64)
+    ez = np.exp(-np.abs(zz))
+    return np.where(zz >= 0, 1.0 / (1.0 + ez), ez / (1.0 + ez))
+
+
+def angle_net_input(E_kelvin, b_rel, lne_lo, lne_hi):
+    """x = [2 (ln E - lnE_lo) / (lnE_hi - lnE_lo) - 1, b / b_max]."""
+    lnE = np.log(np.asarray(E_kelvin, np.float64))
+    x0 = 2.0 * (lnE - lne_lo) / (lne_hi - lne_lo) - 1.0
+    return np.stack([x0, np.asarray(b_rel, np.float64)], axis=1)
+
+
+def angle_net_forward(Ws, bs, x, keep=False):
+    """SiLU hidden layers, Softplus output; returns y[B] (= predicted
+    ln(1 + theta))."""
+    h = np.asarray(x, np.float64)
+    zs, hs = [], [h]
+    L = len(Ws)
+    for l in range(L):
+        zz = h @ np.asarray(Ws[l], np.float64).T + np.asarray(bs[l], np.float64)
+        zs.append(zz)
+        if l < L - 1:
+            h = act_fn("silu", zz)
+            hs.append(h)
+        else:
+            h = softplus(zz)
+    y = h[:, 0]
+    return (y, zs, hs) if keep else y
+
+
+def angle_net_backward(Ws, bs, x, dy):
+    """Gradients (dW list, db list, dx) of sum(dy * angle_net(x)) in FP64."""
+    _, zs, hs = angle_net_forward(Ws, bs, x, keep=True)
+    L = len(Ws)
+    dW = [None] * L
+    db = [None] * L
+    delta = np.asarray(dy, np.float64)[:, None] * sigmoid(zs[L - 1])
+    dx = None
+    for l in range(L - 1, -1, -1):
+        dW[l] = delta.T @ hs[l]
+        db[l] = delta.sum(axis=0)
+        dh = delta @ np.asarray(Ws[l], np.float64)
+        if l > 0:
+            delta = dh * act_grad("silu", zs[l - 1])
+        else:
+            dx = dh
+    return dW, db, dx
+
+
+def huber_loss(yhat, y):
+    """Mean smooth-L1 (Huber, threshold 1) loss of eq. huber_loss."""
+    d = np.asarray(yhat, np.float64) - np.asarray(y, np.float64)
+    a = np.abs(d)
+    return float(np.mean(np.where(a < 1.0, 0.5 * d * d, a - 0.5)))
+
+
+def huber_grad(yhat, y):
+    """d huber_loss / d yhat."""
+    d = np.asarray(yhat, np.float64) - np.asarray(y, np.float64)
+    return np.clip(d, -1.0, 1.0) / d.shape[0]
+
+
+def angle_rows(b, g, chi_, m_red, lne_lo, lne_hi, b_max):
+    """Training rows from quadrature results: x (angle_net_input) and the
+    target ln(1 + theta), theta = fold(chi)."""
+    E = 0.5 * m_red * np.asarray(g, np.float64) ** 2 / KB
+    x = angle_net_input(E, np.asarray(b, np.float64) / b_max, lne_lo, lne_hi)
+    return x, np.log1p(fold(chi_))
+
+
+def table_grid(n_e, n_b, lne_lo, lne_hi):
+    """Grid node coordinates: ln E_i = lnE_lo + i (lnE_hi - lnE_lo)/(n_e - 1),
+    b_j / b_max = j / (n_b - 1)."""
+    lnE = lne_lo + (lne_hi - lne_lo) * np.arange(n_e) / (n_e - 1)
+    brel = np.arange(n_b) / (n_b - 1)
+    return lnE, brel
+
+
+def chi_table(Ws, bs, n_e, n_b, lne_lo, lne_hi):
+    """theta[n_e, n_b] = clip(exp(y) - 1, 0, pi) of the angle network at the
+    grid nodes."""
+    lnE, brel = table_grid(n_e, n_b, lne_lo, lne_hi)
+    E = np.repeat(np.exp(lnE), n_b)
+    B = np.tile(brel, n_e)
+    y = angle_net_forward(Ws, bs, angle_net_input(E, B, lne_lo, lne_hi))
+    return np.clip(np.expm1(y), 0.0, math.pi).reshape(n_e, n_b)
+
+
+def table_lookup(theta, lne_lo, lne_hi, E_kelvin, b_rel):
+    """Bilinear interpolation of the table in (ln E, b / b_max), with both
+    coordinates clamped to the grid."""
+    theta = np.asarray(theta, np.float64)
+    n_e, n_b = theta.shape
+    fe = (np.log(np.asarray(E_kelvin, np.float64)) - lne_lo) / (lne_hi - lne_lo) * (n_e - 1)
+    fb = np.asarray(b_rel, np.float64) * (n_b - 1)
+    fe = np.clip(fe, 0.0, n_e - 1)
+    fb = np.clip(fb, 0.0, n_b - 1)
+    i0 = np.minimum(np.floor(fe).astype(np.int64), n_e - 2)
+    j0 = np.minimum(np.floor(fb).astype(np.int64), n_b - 2)
+    te = fe - i0
+    tb = fb - j0
+    t00 = theta[i0, j0]
+    t01 = theta[i0, j0 + 1]
+    t10 = theta[i0 + 1, j0]
+    t11 = theta[i0 + 1, j0 + 1]
+    return (1 - te) * ((1 - tb) * t00 + tb * t01) + te * ((1 - tb) * t10 + tb * t11)
+
+
+def table_angles(sel, v, U, table, b_max, m_red):
+    """Phase A of the table rule: theta per accepted pair from the pre-step
+    relative speed (E = m_r g^2 / 2) and b = b_max sqrt(U4)."""
+    vr = v[:, sel["pair_i"]] - v[:, sel["pair_j"]]
+    g = np.sqrt(np.sum(vr * vr, axis=0))
+    E = 0.5 * m_red * g * g / KB
+    b_rel = np.sqrt(U[:, 4])
+    return table_lookup(table["theta"], table["lne_lo"], table["lne_hi"], E, b_rel)
+
+
+# ---------------------------------------------------------------------------
 # Whole-step compositions (sorted arrays in, sorted arrays out)
 # ---------------------------------------------------------------------------
 def step(cell_start, v, xs, lam, seed, step_no, rule="vhs", lowp=False,
-         match=None, net=None, pot=None, b_max=1e-9, m_red=None, cap=None, cell_base=0):
+         match=None, net=None, pot=None, b_max=1e-9, m_red=None, cap=None, cell_base=0,
+         table=None):
     """One collision step on sorted velocities: select (pre-step velocities),
     Phase A per pair, Phase B in candidate order per cell, then moment matching.
 
-    rule: "vhs" | "jager" | "neural".  net: dict(Ws, bs, act, sigma_v) for
-    the neural rule.  match: None -> on for "neural", off otherwise.
+    rule: "vhs" | "jager" | "neural" | "table".  net: dict(Ws, bs, act,
+    sigma_v) for the neural rule; table: dict(theta, lne_lo, lne_hi) for the
+    table rule.  match: None -> on for "neural", off otherwise.
     cell_base: global id of cell 0 of these arrays (a contiguous range of a
     larger population can be stepped on its own: the random numbers are keyed
     by the global cell id).
@@ -524,6 +658,10 @@ def step(cell_start, v, xs, lam, seed, step_no, rule="vhs", lowp=False,
         info["u"] = u
         info["y"] = y
         vn = apply_dirs(sel, v, u)
+    elif rule == "table":
+        th = table_angles(sel, v, U, table, b_max, m_red)
+        info["theta"] = th
+        vn = apply_chi(sel, v, np.cos(th), np.sin(th), xi)
     else:
         raise ValueError(rule)
     if match:
