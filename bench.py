@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--cpu-sample-pairs", type=int, default=4_000_000)
     p.add_argument("--weights", default=os.path.join(ROOT, "paper_2602_21244_amd", "weights",
                                                      "jager_surrogate_8x128x4.npz"))
+    p.add_argument("--anet-weights", default=os.path.join(ROOT, "paper_2602_21244_amd", "weights",
+                                                          "jager_anet.npz"))
+    p.add_argument("--table-steps", type=int, default=5)
     return p.parse_args()
 
 
@@ -128,6 +131,20 @@ def main():
     pot = api.potential_jager(W.JAGER_PLACEHOLDER)
     quad = api.quad_struct(64)
 
+    # neural deflection-angle table: angle network -> 512 x 512 table
+    anet, lne_lo, lne_hi, akind = load_anet(args.anet_weights, W, api, dev)
+    tab = api.ChiTable(512, 512, lne_lo, lne_hi, device=dev)
+    tab_ws = api.chi_table_build(anet, tab)
+    torch.cuda.synchronize()
+    tb0, tb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tb0.record(stream)
+    for _ in range(3):
+        api.chi_table_build(anet, tab, ws=tab_ws)
+    tb1.record(stream)
+    torch.cuda.synchronize()
+    table_build_ms = tb0.elapsed_time(tb1) / 3
+    log(f"chi table 512x512 build: {table_build_ms:.3f} ms ({akind} angle network)")
+
     def stage_events(k):
         return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
 
@@ -143,6 +160,10 @@ def main():
         if rule == "neural":
             api.neural_collide(net, v, pairs, 11, 0, schedule=L.SCHED_DEFER, ws=col_ws, st=st)
             kind = L.APPLY_DIRECTIONS
+        elif rule == "table":
+            api.collide_table(tab, v, pairs, 11, 0, W.AR_MASS / 2, schedule=L.SCHED_DEFER,
+                              ws=col_ws)
+            kind = L.APPLY_ANGLES
         else:
             api.collide_jager(v, pairs, 11, 0, W.AR_MASS / 2, W.B_MAX, pot, quad=quad,
                               schedule=L.SCHED_DEFER, ws=col_ws, st=st)
@@ -210,6 +231,22 @@ def main():
     chi_rms = float(np.sqrt(np.mean(ang ** 2)))
     log(f"network vs quadrature direction error: rms {chi_rms:.4f} rad ({wkind} weights)")
 
+    # the table rule on the same step, and its angle error against the
+    # quadrature on the same pairs (folded angles)
+    wall_t, ms_t, per_t = run("table", 1, args.table_steps)
+    log(f"table: {ms_t:.3f} ms/step, stages {json.dumps({k: round(x, 4) for k, x in per_t.items()})}")
+    th_q = torch.arccos(torch.clamp(cc, -1, 1))
+    do_sort()
+    api.moment_match(cs, v, mom, L.MM_CAPTURE)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, pairs, ws=sel_ws, st=st)
+    api.collide_table(tab, v, pairs, 11, 0, W.AR_MASS / 2, schedule=L.SCHED_DEFER, ws=col_ws)
+    torch.cuda.synchronize()
+    th_t = torch.arccos(torch.clamp(buf[0, sel_idx].double(), -1, 1))
+    dth = (th_t - th_q).cpu().numpy()
+    table_rms = float(np.sqrt(np.mean(dth ** 2)))
+    log(f"table vs quadrature folded-angle error: rms {table_rms:.4f} rad ({akind} angle network)")
+    table_flop = 512 * 512 * anet_flop_per_row(anet.dims)
+
     # roofline of the dominant kernel (the fused MLP, Phase A of the network)
     t_mlp = per_n["phaseA"] * 1e-3
     achieved = n_pairs * MLP_FLOP_PER_PAIR / t_mlp
@@ -227,6 +264,13 @@ def main():
         "stage_ms_neural": per_n,
         "stage_ms_quadrature": per_q,
         "sort_GBps_algorithmic": sort_bytes / (per_n["sort"] * 1e-3) / 1e9,
+        "table_pairs_per_s": n_pairs / (ms_t * 1e-3),
+        "table_ms_per_step": ms_t,
+        "stage_ms_table": per_t,
+        "table_theta_rms_vs_quadrature_rad": table_rms,
+        "angle_network_weights": akind,
+        "table_build_ms_512x512": table_build_ms,
+        "table_build_TFLOPs": table_flop / (table_build_ms * 1e-3) / 1e12,
         "pairs_per_step": n_pairs,
         "particles": n,
         "cells": n_cells,
@@ -257,13 +301,36 @@ def main():
         "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": wname, "particles": n, "cells": n_cells,
-                   "pairs_per_step": n_pairs, "velocities": "fp32 SoA",
+                   "table_pairs_per_s": n_pairs / (ms_t * 1e-3),
+        "table_ms_per_step": ms_t,
+        "stage_ms_table": per_t,
+        "table_theta_rms_vs_quadrature_rad": table_rms,
+        "angle_network_weights": akind,
+        "table_build_ms_512x512": table_build_ms,
+        "table_build_TFLOPs": table_flop / (table_build_ms * 1e-3) / 1e12,
+        "pairs_per_step": n_pairs, "velocities": "fp32 SoA",
                    "mlp": "8-128x4-3 SiLU bf16/fp32-acc", "moments": "fp64"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def anet_flop_per_row(dims):
+    return 2 * sum(dims[l] * dims[l + 1] for l in range(len(dims) - 1))
+
+
+def load_anet(path, workloads, api, dev):
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        L = int(z["n_layers"])
+        Ws = [z[f"W{l}"] for l in range(L)]
+        bs = [z[f"b{l}"] for l in range(L)]
+        return (api.AngleNet(Ws, bs, device=dev), float(z["lne_lo"]), float(z["lne_hi"]),
+                "trained")
+    Ws, bs = workloads.mlp_init(11, api.ANGLE_DIMS)
+    return api.AngleNet(Ws, bs, device=dev), math.log(5.0), math.log(5.0e5), "seeded-init"
 
 
 def train_step_timing(api, W, dev, net, sigma_v, B=65536, steps=5):

@@ -349,6 +349,64 @@ int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, int32_t dtyp
 int dsmc_set_block_threshold(int32_t pairs);
 int32_t dsmc_get_block_threshold(void);
 
+/* ---------------------------------------------------------------------- */
+/* Neural deflection-angle table (sections "Neural Network Architecture",
+ * "Neural Surrogate Training" and "Runtime Acceleration via Neural Table
+ * Look-up"): an angle network maps x = [2 (ln E - lne_lo)/(lne_hi - lne_lo)
+ * - 1, b / b_max] (E = E_r / k_B in K) through SiLU hidden layers and a
+ * Softplus output to a prediction y of ln(1 + theta), theta the folded
+ * deflection angle arccos(cos chi) in [0, pi].  The network synthesises an
+ * n_e x n_b table of theta on the grid ln E_i = lne_lo + i (lne_hi -
+ * lne_lo)/(n_e - 1), b_j / b_max = j / (n_b - 1); a collision rule looks
+ * theta up by bilinear interpolation (coordinates clamped to the grid). */
+enum { DSMC_ANET_MAX_LAYERS = 8 };
+typedef struct {
+    int32_t n_layers;                       /* weight layers, 2..8 */
+    int32_t dims[DSMC_ANET_MAX_LAYERS + 1]; /* dims[0] = 2, dims[n_layers] = 1, each <= 1024 */
+    const void* W[DSMC_ANET_MAX_LAYERS];    /* bf16 [dims[l+1]][dims[l]] row-major (device) */
+    const float* b[DSMC_ANET_MAX_LAYERS];   /* fp32 [dims[l+1]] (device) */
+} dsmc_anet;
+
+typedef struct {
+    int32_t n_e, n_b;        /* grid nodes along ln E and b / b_max, each >= 2 */
+    double lne_lo, lne_hi;   /* ln(E / K) range of the grid, lne_lo < lne_hi */
+    float* theta;            /* [n_e][n_b] folded angle in rad (device) */
+} dsmc_chi_table;
+
+/* Workspace for dsmc_anet_forward / dsmc_anet_backward on `rows` rows
+ * (activations of every layer are kept for the backward). */
+size_t dsmc_anet_ws(const dsmc_anet* net, int64_t rows);
+/* y[rows] = network(x[rows][2]) (BF16 matrix cores, FP32 accumulation).
+ * The activations stay in ws for a following dsmc_anet_backward. */
+int dsmc_anet_forward(const dsmc_anet* net, int64_t rows, const float* x, float* y, void* ws,
+                      size_t ws_bytes, dsmc_stream_t stream);
+/* Gradients of sum_r dy[r] y[r] for the rows of the preceding forward on the
+ * same ws: dW[l] fp32 [dims[l+1]][dims[l]], db[l] fp32 [dims[l+1]]
+ * (overwritten; reductions in a fixed order). */
+int dsmc_anet_backward(const dsmc_anet* net, int64_t rows, const float* dy, float* const* dW,
+                       float* const* db, void* ws, size_t ws_bytes, dsmc_stream_t stream);
+/* Mean Huber loss (threshold 1) of yhat against y (eq. huber_loss) into
+ * *loss (FP64, device) and its gradient dy = clip(yhat - y, -1, 1) / n. */
+int dsmc_huber_loss(int64_t n, const float* yhat, const float* y, float* dy, double* loss,
+                    dsmc_stream_t stream);
+/* Training rows from quadrature results (b in m, g in m/s, chi in rad, FP64):
+ * x[n][2] as above with E = m_red g^2 / (2 k_B), y[n] = ln(1 + theta). */
+int dsmc_anet_rows(int64_t n, const double* b, const double* g, const double* chi,
+                   double m_red, double lne_lo, double lne_hi, double b_max, float* x,
+                   float* y, dsmc_stream_t stream);
+/* Synthesise tab->theta from the network: theta = clip(exp(y) - 1, 0, pi).
+ * ws: dsmc_chi_table_ws bytes. */
+size_t dsmc_chi_table_ws(const dsmc_anet* net, const dsmc_chi_table* tab);
+int dsmc_chi_table_build(const dsmc_anet* net, const dsmc_chi_table* tab, void* ws,
+                         size_t ws_bytes, dsmc_stream_t stream);
+/* Table rule: Phase A per accepted pair looks theta up at E = m_red g_pre^2 /
+ * (2 k_B) and b / b_max = sqrt(U4) (the latent impact parameter of
+ * dsmc_collide_jager); Phase B rotates the current v_r by theta about the
+ * azimuth direction of xi.  ws: dsmc_collide_ws(cap, dtype) bytes. */
+int dsmc_collide_table(const dsmc_chi_table* tab, int32_t n_cells, int32_t dtype, dsmc_vec3 v,
+                       dsmc_pairs pairs, dsmc_rng rng, double m_red, int32_t schedule, void* ws,
+                       size_t ws_bytes, dsmc_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

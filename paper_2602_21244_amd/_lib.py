@@ -62,6 +62,19 @@ class Mlp(C.Structure):
                 ("sigma_v", C.c_double)]
 
 
+ANET_MAX_LAYERS = 8
+
+
+class Anet(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("dims", C.c_int32 * (ANET_MAX_LAYERS + 1)),
+                ("W", C.c_void_p * ANET_MAX_LAYERS), ("b", C.c_void_p * ANET_MAX_LAYERS)]
+
+
+class ChiTable(C.Structure):
+    _fields_ = [("n_e", C.c_int32), ("n_b", C.c_int32), ("lne_lo", C.c_double),
+                ("lne_hi", C.c_double), ("theta", C.c_void_p)]
+
+
 _vp, _i32, _i64, _u64, _sz, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t, C.c_double
 
 # name: (restype, argtypes)
@@ -100,6 +113,16 @@ SIGNATURES = {
     "dsmc_step_vhs_ws": (_sz, [_i32, _i64]),
     "dsmc_step_vhs_fused": (C.c_int, [_i32, _vp, _i32, Vec3, Xs, _vp, Rng, _i32, _vp, _vp, _sz,
                                       _vp, _vp]),
+    "dsmc_anet_ws": (_sz, [C.POINTER(Anet), _i64]),
+    "dsmc_anet_forward": (C.c_int, [C.POINTER(Anet), _i64, _vp, _vp, _vp, _sz, _vp]),
+    "dsmc_anet_backward": (C.c_int, [C.POINTER(Anet), _i64, _vp, C.POINTER(_vp), C.POINTER(_vp),
+                                     _vp, _sz, _vp]),
+    "dsmc_huber_loss": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp]),
+    "dsmc_anet_rows": (C.c_int, [_i64, _vp, _vp, _vp, _d, _d, _d, _d, _vp, _vp, _vp]),
+    "dsmc_chi_table_ws": (_sz, [C.POINTER(Anet), C.POINTER(ChiTable)]),
+    "dsmc_chi_table_build": (C.c_int, [C.POINTER(Anet), C.POINTER(ChiTable), _vp, _sz, _vp]),
+    "dsmc_collide_table": (C.c_int, [C.POINTER(ChiTable), _i32, _i32, Vec3, Pairs, Rng, _d, _i32,
+                                     _vp, _sz, _vp]),
     "dsmc_set_block_threshold": (C.c_int, [_i32]),
     "dsmc_get_block_threshold": (_i32, []),
 }

@@ -346,3 +346,103 @@ def set_block_threshold(pairs):
 
 def get_block_threshold():
     return int(lib().dsmc_get_block_threshold())
+
+
+# ---------------------------------------------------------------------------
+# Angle network and deflection-angle table
+# ---------------------------------------------------------------------------
+ANGLE_DIMS = (2, 512, 512, 512, 256, 128, 1)
+
+
+class AngleNet:
+    """Device copy of the angle network (bf16 weights for the matrix cores,
+    fp32 biases; FP32 master copies for training)."""
+
+    def __init__(self, Ws, bs, device="cuda"):
+        self.dims = [int(Ws[0].shape[1])] + [int(w.shape[0]) for w in Ws]
+        self.master_W = [torch.as_tensor(w, dtype=torch.float32).to(device).contiguous() for w in Ws]
+        self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for b in bs]
+        self.W = [w.to(torch.bfloat16).contiguous() for w in self.master_W]
+        self.refresh()
+
+    def refresh(self):
+        a = L.Anet()
+        a.n_layers = len(self.W)
+        for q, d in enumerate(self.dims):
+            a.dims[q] = d
+        for q in range(len(self.W)):
+            a.W[q] = self.W[q].data_ptr()
+            a.b[q] = self.b[q].data_ptr()
+        self.struct = a
+        return a
+
+
+def anet_ws(net, rows, device):
+    return workspace(lib().dsmc_anet_ws(C.byref(net.struct), int(rows)), device)
+
+
+def anet_forward(net, x, y=None, ws=None, stream=None):
+    R = int(x.shape[0])
+    if y is None:
+        y = torch.empty(R, dtype=torch.float32, device=x.device)
+    if ws is None:
+        ws = anet_ws(net, R, x.device)
+    check(lib().dsmc_anet_forward(C.byref(net.struct), R, _ptr(x), _ptr(y), _ptr(ws),
+                                  int(ws.numel()), _stream(stream)),
+          "dsmc_anet_forward")
+    return y, ws
+
+
+def anet_backward(net, dy, dW, db, ws, stream=None):
+    R = int(dy.shape[0])
+    pw = (C.c_void_p * len(dW))(*[t.data_ptr() for t in dW])
+    pb = (C.c_void_p * len(db))(*[t.data_ptr() for t in db])
+    check(lib().dsmc_anet_backward(C.byref(net.struct), R, _ptr(dy), pw, pb, _ptr(ws),
+                                   int(ws.numel()), _stream(stream)),
+          "dsmc_anet_backward")
+
+
+def huber_loss(yhat, y, dy, loss, stream=None):
+    check(lib().dsmc_huber_loss(int(yhat.numel()), _ptr(yhat), _ptr(y), _ptr(dy), _ptr(loss),
+                                _stream(stream)),
+          "dsmc_huber_loss")
+
+
+def anet_rows(b, g, chi, m_red, lne_lo, lne_hi, b_max, stream=None):
+    n = int(b.numel())
+    x = torch.empty(n, 2, dtype=torch.float32, device=b.device)
+    y = torch.empty(n, dtype=torch.float32, device=b.device)
+    check(lib().dsmc_anet_rows(n, _ptr(b), _ptr(g), _ptr(chi), float(m_red), float(lne_lo),
+                               float(lne_hi), float(b_max), _ptr(x), _ptr(y), _stream(stream)),
+          "dsmc_anet_rows")
+    return x, y
+
+
+class ChiTable:
+    """theta[n_e][n_b] on the (ln E, b / b_max) grid (device)."""
+
+    def __init__(self, n_e, n_b, lne_lo, lne_hi, device="cuda", theta=None):
+        self.theta = (torch.zeros(n_e, n_b, dtype=torch.float32, device=device) if theta is None
+                      else torch.as_tensor(theta, dtype=torch.float32).to(device).contiguous())
+        self.struct = L.ChiTable(int(n_e), int(n_b), float(lne_lo), float(lne_hi),
+                                 self.theta.data_ptr())
+
+
+def chi_table_build(net, tab, ws=None, stream=None):
+    if ws is None:
+        ws = workspace(lib().dsmc_chi_table_ws(C.byref(net.struct), C.byref(tab.struct)),
+                       tab.theta.device)
+    check(lib().dsmc_chi_table_build(C.byref(net.struct), C.byref(tab.struct), _ptr(ws),
+                                     int(ws.numel()), _stream(stream)),
+          "dsmc_chi_table_build")
+    return ws
+
+
+def collide_table(tab, v, pairs, seed, step, m_red, schedule=L.SCHED_AUTO, ws=None, stream=None):
+    if ws is None:
+        ws = collide_ws(pairs.cap, v)
+    check(lib().dsmc_collide_table(C.byref(tab.struct), int(pairs.off.numel()), _dtype(v), _vec3(v),
+                                   pairs.struct(), rng_struct(seed, step), float(m_red),
+                                   int(schedule), _ptr(ws), int(ws.numel()), _stream(stream)),
+          "dsmc_collide_table")
+    return ws

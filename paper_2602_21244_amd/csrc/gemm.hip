@@ -1,0 +1,210 @@
+// Tiled BF16 matrix-core GEMM with fused epilogues, for networks whose layers
+// do not fit the fused in-LDS MLP kernel (the angle network of section
+// "Neural Network Architecture": 2 -> 512 -> 512 -> 512 -> 256 -> 128 -> 1).
+//
+//   C[m][n] = epilogue( sum_k A(m, k) B(k, n) ),   A, B bf16, FP32 accumulate
+//   A(m, k) = TA ? a[k lda + m] : a[m lda + k]
+//   B(k, n) = TB ? b[n ldb + k] : b[k ldb + n]
+//
+// A 256-thread workgroup computes a 128 x 128 tile: each wave a 64 x 64 block
+// as 2 x 2 v_mfma_f32_32x32x16_bf16 accumulators.  Operand tiles (128 x 32)
+// are staged in LDS with k contiguous (row stride 40 bf16 to spread banks);
+// operands that are k-contiguous in memory are copied with 16-byte loads, the
+// transposed ones are scattered into that layout element by element.  A
+// split of K across blockIdx.z writes FP32 partials that a second kernel sums
+// in a fixed order, so results do not depend on timing.
+#include "gemm.hpp"
+
+namespace dsmc {
+
+typedef __bf16 bf16x8g __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float floatx16g __attribute__((__vector_size__(16 * sizeof(float))));
+
+constexpr int GM = 128, GN = 128, GK = 32, GLD = GK + 8;
+constexpr int G_THREADS = 256;
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+__device__ __forceinline__ float act_apply(int act, float z)
+{
+    switch (act) {
+    case GEMM_ACT_SILU: return z * sigm(z);
+    case GEMM_ACT_SOFTPLUS: return z > 20.0f ? z : log1pf(expf(z));
+    default: return z;
+    }
+}
+
+__device__ __forceinline__ float act_deriv(int act, float z)
+{
+    switch (act) {
+    case GEMM_ACT_SILU: {
+        const float s = sigm(z);
+        return s * (1.0f + z * (1.0f - s));
+    }
+    case GEMM_ACT_SOFTPLUS: return sigm(z);
+    default: return 1.0f;
+    }
+}
+
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m, int64_t n, float v)
+{
+    if (g.bias) v += g.bias[n];
+    if (g.z_out) g.z_out[m * g.ldz + n] = v;
+    if (g.dact_z) v *= act_deriv(g.act, g.dact_z[m * g.ldz + n]);
+    else v = act_apply(g.act, v);
+    if (g.accumulate && g.out_f32) v += g.out_f32[m * g.ldo + n];
+    if (g.out_f32) g.out_f32[m * g.ldo + n] = v;
+    if (g.out_bf16) g.out_bf16[m * g.ldo + n] = (__bf16)v;
+}
+
+// Stage rows [r0, r0 + 128) x k [k0, k0 + 32) of an operand into LDS as
+// tile[row][k].  kcontig: element (row, k) at p[row * ld + k]; otherwise at
+// p[k * ld + row].  Out-of-range elements are zero.
+__device__ __forceinline__ void stage_tile(const __bf16* __restrict__ p, int64_t ld, int64_t rows,
+                                           int64_t K, int64_t r0, int64_t k0, bool kcontig,
+                                           __bf16* tile)
+{
+    const int t = threadIdx.x;
+    if (kcontig) {
+        // 128 rows x 4 chunks of 8
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = t + G_THREADS * q;
+            const int row = c >> 2, kc = (c & 3) * 8;
+            const int64_t gr = r0 + row, gk = k0 + kc;
+            bf16x8g v;
+            const __bf16* src = p + gr * ld + gk;
+            if (gr < rows && gk + 8 <= K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+                v = *reinterpret_cast<const bf16x8g*>(src);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    v[e] = (gr < rows && gk + e < K) ? src[e] : (__bf16)0.0f;
+            }
+            *reinterpret_cast<bf16x8g*>(tile + row * GLD + kc) = v;
+        }
+    } else {
+        // 32 k x 16 chunks of 8 rows
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = t + G_THREADS * q;
+            const int kk = c >> 4, rc = (c & 15) * 8;
+            const int64_t gk = k0 + kk, gr = r0 + rc;
+            const __bf16* src = p + gk * ld + gr;
+            bf16x8g v;
+            if (gk < K && gr + 8 <= rows && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+                v = *reinterpret_cast<const bf16x8g*>(src);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    v[e] = (gk < K && gr + e < rows) ? src[e] : (__bf16)0.0f;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) tile[(rc + e) * GLD + kk] = v[e];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(G_THREADS)
+k_gemm_bf16(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 As[GM * GLD];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[GN * GLD];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t m0 = (int64_t)blockIdx.x * GM, n0 = (int64_t)blockIdx.y * GN;
+    const int64_t kc = (g.K + gridDim.z - 1) / gridDim.z;
+    const int64_t kbeg = (int64_t)blockIdx.z * kc;
+    const int64_t kend = kbeg + kc < g.K ? kbeg + kc : g.K;
+
+    floatx16g acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
+        __syncthreads();
+        stage_tile(g.a, g.lda, g.M, kend, m0, k0, !g.ta, As);
+        stage_tile(g.b, g.ldb, g.N, kend, n0, k0, g.tb, Bs);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GK / 16; ++ks) {
+            bf16x8g fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                fa[i] = *reinterpret_cast<const bf16x8g*>(
+                    As + (wm * 64 + i * 32 + col) * GLD + ks * 16 + 8 * h);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                fb[j] = *reinterpret_cast<const bf16x8g*>(
+                    Bs + (wn * 64 + j * 32 + col) * GLD + ks * 16 + 8 * h);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j],
+                                                                        0, 0, 0);
+        }
+    }
+
+    // epilogue: register r of lane (h, col) holds row 8 (r / 4) + 4 h + r % 4, column col
+    float* part = g.partial ? g.partial + (int64_t)blockIdx.z * g.M * g.N : nullptr;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int64_t n = n0 + wn * 64 + j * 32 + col;
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][j][r];
+                if (part) {
+                    part[m * g.N + n] = v;
+                    continue;
+                }
+                gemm_epilogue(g, m, n, v);
+            }
+}
+
+// Sum of the K-split partials in split order, then the epilogue.
+__global__ void __launch_bounds__(256)
+k_gemm_reduce(GemmArgs g, int splits)
+{
+    const int64_t total = g.M * g.N;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.0f;
+        for (int s = 0; s < splits; ++s) v += g.partial[(int64_t)s * total + q];
+        gemm_epilogue(g, q / g.N, q % g.N, v);
+    }
+}
+
+int gemm_bf16(const GemmArgs& g0, int splits, hipStream_t s)
+{
+    GemmArgs g = g0;
+    if (g.M <= 0 || g.N <= 0) return DSMC_OK;
+    if (splits < 1) splits = 1;
+    const int64_t gx = (g.M + GM - 1) / GM, gy = (g.N + GN - 1) / GN;
+    if (gx > 2147483647 || gy > 65535 || splits > 65535) return arg_error("gemm: grid too large");
+    if (splits > 1 && !g.partial) return arg_error("gemm: split-K needs a partial buffer");
+    if (splits == 1) g.partial = nullptr;
+    dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)splits);
+    k_gemm_bf16<<<grid, G_THREADS, 0, s>>>(g);
+    DSMC_LAUNCH_CHECK("gemm_bf16");
+    if (splits > 1) {
+        const int64_t total = g.M * g.N;
+        int64_t blocks = (total + 255) / 256;
+        const int pb = persistent_blocks(256);
+        if (blocks > pb) blocks = pb;
+        k_gemm_reduce<<<(int)blocks, 256, 0, s>>>(g, splits);
+        DSMC_LAUNCH_CHECK("gemm_reduce");
+    }
+    return DSMC_OK;
+}
+
+}  // namespace dsmc

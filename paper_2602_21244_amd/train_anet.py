@@ -1,0 +1,135 @@
+"""Training of the angle network on deflection angles from the library's own
+quadrature (section "Neural Surrogate Training: The Physics Harvesting
+Strategy"): ln E log-uniform over the table range, b biased towards head-on
+collisions, target ln(1 + theta); Huber loss, Adam, cosine learning rate to
+1e-6.  Every arithmetic step runs in the library's kernels; this module only
+orders the calls.
+
+    python -m paper_2602_21244_amd.train_anet --steps 4000 --out weights/jager_anet.npz
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import api
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+E_LO_K, E_HI_K = 5.0, 5.0e5          # table / training range of E_r / k_B
+
+
+def cosine_lr(t, T, lr_max, lr_min=1e-6):
+    return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * min(t, T) / T))
+
+
+def harvest(workloads, n, seed, dev, pot, quad, lne_lo=None, lne_hi=None):
+    """n training rows: (x[n,2], y[n]) with y = ln(1 + theta) from quadrature."""
+    lne_lo = math.log(E_LO_K) if lne_lo is None else lne_lo
+    lne_hi = math.log(E_HI_K) if lne_hi is None else lne_hi
+    s = workloads.angle_samples(seed=seed, n=n, lne_lo=lne_lo, lne_hi=lne_hi)
+    b = torch.as_tensor(s["b"], device=dev)
+    g = torch.as_tensor(s["g"], device=dev)
+    chi = api.deflect_jager(b, g, workloads.AR_MASS / 2, pot, quad)
+    x, y = api.anet_rows(b, g, chi, workloads.AR_MASS / 2, lne_lo, lne_hi, workloads.B_MAX)
+    return x, y, chi, b, g
+
+
+def train(steps=4000, batch=4096, pool=1 << 20, lr=1e-3, seed=11, dims=None, out=None,
+          log_every=500, dev=None):
+    sys.path.insert(0, os.path.dirname(HERE))
+    import workloads as W
+
+    dev = dev or torch.device("cuda:0")
+    dims = dims or api.ANGLE_DIMS
+    pot = api.potential_jager(W.JAGER_PLACEHOLDER)
+    quad = api.quad_struct(64)
+    t0 = time.time()
+    x, y, _, _, _ = harvest(W, pool, seed, dev, pot, quad)
+    xv, yv, _, _, _ = harvest(W, 65536, seed + 1000, dev, pot, quad)
+    torch.cuda.synchronize()
+    print(f"harvested {pool} + 65536 rows in {time.time() - t0:.1f}s", flush=True)
+    Ws, bs = W.mlp_init(seed, dims)
+    net = api.AngleNet(Ws, bs, device=dev)
+    params = []
+    for l in range(len(net.W)):
+        params.append((net.master_W[l], net.W[l]))
+        params.append((net.b[l], None))
+    mst = [torch.zeros_like(p) for p, _ in params]
+    vst = [torch.zeros_like(p) for p, _ in params]
+    dW = [torch.zeros_like(w) for w in net.master_W]
+    db = [torch.zeros_like(b) for b in net.b]
+    grads = []
+    for l in range(len(net.W)):
+        grads += [dW[l], db[l]]
+    ws = api.anet_ws(net, batch, dev)
+    wsv = api.anet_ws(net, xv.shape[0], dev)
+    yhat = torch.empty(batch, dtype=torch.float32, device=dev)
+    dy = torch.empty(batch, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    yvh = torch.empty(xv.shape[0], dtype=torch.float32, device=dev)
+    dyv = torch.empty_like(yvh)
+    lossv = torch.zeros(1, dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    hist = []
+    t0 = time.time()
+    for t in range(1, steps + 1):
+        idx = torch.randint(0, pool, (batch,), device=dev, generator=gen)
+        xb, yb = x[idx].contiguous(), y[idx].contiguous()
+        api.anet_forward(net, xb, yhat, ws)
+        api.huber_loss(yhat, yb, dy, loss)
+        api.anet_backward(net, dy, dW, db, ws)
+        lr_t = cosine_lr(t, steps, lr)
+        for q, (p, pbf) in enumerate(params):
+            api.adam_step(p, grads[q], mst[q], vst[q], t, lr_t, param_bf16=pbf)
+        if t % log_every == 0 or t == 1 or t == steps:
+            api.anet_forward(net, xv, yvh, wsv)
+            api.huber_loss(yvh, yv, dyv, lossv)
+            th_err = torch.expm1(yvh.double()).clamp(0, math.pi) - torch.expm1(yv.double())
+            rms = float(torch.sqrt((th_err ** 2).mean()))
+            hist.append((t, float(loss.item()), float(lossv.item()), rms))
+            print(f"step {t:5d} huber {loss.item():.3e} val {lossv.item():.3e} "
+                  f"theta rms {rms:.4f} rad lr {lr_t:.2e} ({time.time() - t0:.1f}s)", flush=True)
+    torch.cuda.synchronize()
+    if out:
+        os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+        arrs = {"n_layers": np.int64(len(net.W)), "dims": np.array(dims, np.int64),
+                "lne_lo": np.float64(math.log(E_LO_K)), "lne_hi": np.float64(math.log(E_HI_K)),
+                "history": np.array(hist)}
+        for l in range(len(net.W)):
+            arrs[f"W{l}"] = net.master_W[l].double().cpu().numpy()
+            arrs[f"b{l}"] = net.b[l].double().cpu().numpy()
+        np.savez(out, **arrs)
+        print("saved", out, flush=True)
+    return net, hist
+
+
+def load(path, dev):
+    z = np.load(path)
+    L = int(z["n_layers"])
+    Ws = [z[f"W{l}"] for l in range(L)]
+    bs = [z[f"b{l}"] for l in range(L)]
+    return api.AngleNet(Ws, bs, device=dev), float(z["lne_lo"]), float(z["lne_hi"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--pool", type=int, default=1 << 20)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=11)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "weights",
+                                                  "jager_anet.npz"))
+    a = ap.parse_args()
+    train(a.steps, a.batch, a.pool, a.lr, a.seed, out=a.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -47,7 +47,8 @@ def test_struct_layout_matches_header():
     from paper_2602_21244_amd import _lib as L
     structs = {"dsmc_vec3": L.Vec3, "dsmc_rng": L.Rng, "dsmc_status": L.Status,
                "dsmc_pairs": L.Pairs, "dsmc_xs": L.Xs, "dsmc_potential": L.Potential,
-               "dsmc_quad": L.Quad, "dsmc_mlp": L.Mlp}
+               "dsmc_quad": L.Quad, "dsmc_mlp": L.Mlp, "dsmc_anet": L.Anet,
+               "dsmc_chi_table": L.ChiTable}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -77,7 +78,17 @@ def test_host_argument_errors(lib):
     assert lib.dsmc_set_block_threshold(0) == L.DSMC_E_ARG
     assert lib.dsmc_set_block_threshold(40) == L.DSMC_OK
     assert lib.dsmc_get_block_threshold() == 40
-    assert lib.dsmc_select_pairs_ntc_ws(100, 1000) > 4 * 1000
+    assert lib.dsmc_select_pairs_ntc_ws(100, 1000) > 4 * 100
+    # angle network / table: null structs and bad shapes
+    assert lib.dsmc_anet_forward(None, 10, None, None, None, 0, None) == L.DSMC_E_ARG
+    a = L.Anet()
+    a.n_layers = 2
+    a.dims[0], a.dims[1], a.dims[2] = 3, 8, 1     # dims[0] must be 2
+    assert lib.dsmc_anet_ws(C.byref(a), 10) == 0
+    assert lib.dsmc_huber_loss(0, None, None, None, None, None) == L.DSMC_E_ARG
+    t = L.ChiTable(1, 4, 0.0, 1.0, None)
+    assert lib.dsmc_collide_table(C.byref(t), 4, L.F64, L.Vec3(), L.Pairs(), L.Rng(), 1.0, 0,
+                                  None, 0, None) == L.DSMC_E_ARG
 
 
 def test_product_package_does_not_use_the_oracle():

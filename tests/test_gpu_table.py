@@ -1,0 +1,177 @@
+"""GPU parity of the neural deflection-angle table path: angle network forward
+and backward (BF16 matrix cores) against the FP64 oracle, Huber loss, training
+rows, table synthesis, the table collision rule, and a short training run."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_21244_amd import _lib
+    _lib.load()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def api(dev):
+    from paper_2602_21244_amd import api as A
+    return A
+
+
+def _bf16_round(a):
+    t = torch.as_tensor(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64)
+    return t.numpy()
+
+
+def _net(api, dev, seed, dims):
+    Ws, bs = W.mlp_init(seed, dims)
+    net = api.AngleNet(Ws, bs, device=dev)
+    # the oracle evaluates the same bf16-rounded weights in FP64
+    Wr = [_bf16_round(w) for w in Ws]
+    br = [np.asarray(b, np.float32).astype(np.float64) for b in bs]
+    return net, Wr, br
+
+
+@pytest.mark.parametrize("rows", [1, 37, 300, 4100])
+@pytest.mark.parametrize("dims", [(2, 64, 48, 1), (2, 512, 512, 512, 256, 128, 1)])
+def test_anet_forward_matches_fp64(orc, dev, api, rows, dims):
+    say("anet forward", rows, dims)
+    net, Wr, br = _net(api, dev, 3, dims)
+    rng = np.random.default_rng(rows)
+    x = np.stack([rng.uniform(-1, 1, rows), rng.uniform(0, 1, rows)], axis=1).astype(np.float32)
+    y, _ = api.anet_forward(net, torch.as_tensor(x, device=dev))
+    ref = orc.angle_net_forward(Wr, br, x.astype(np.float64))
+    err = np.abs(y.double().cpu().numpy() - ref)
+    rel = float(np.sqrt(np.mean(err ** 2)) / max(np.sqrt(np.mean(ref ** 2)), 1e-3))
+    say(f"  y rms rel err {rel:.2e} (max abs {err.max():.2e})")
+    assert rel < 1e-2
+
+
+def test_anet_backward_matches_fp64(orc, dev, api):
+    dims = (2, 512, 512, 512, 256, 128, 1)
+    say("anet backward", dims)
+    net, Wr, br = _net(api, dev, 4, dims)
+    rows = 3000
+    rng = np.random.default_rng(1)
+    x = np.stack([rng.uniform(-1, 1, rows), rng.uniform(0, 1, rows)], axis=1).astype(np.float32)
+    dy = rng.normal(0, 1.0 / rows, rows).astype(np.float32)
+    xt = torch.as_tensor(x, device=dev)
+    _, ws = api.anet_forward(net, xt)
+    dW = [torch.zeros_like(w) for w in net.master_W]
+    db = [torch.zeros_like(b) for b in net.b]
+    api.anet_backward(net, torch.as_tensor(dy, device=dev), dW, db, ws)
+    rW, rb, _ = orc.angle_net_backward(Wr, br, x.astype(np.float64), dy.astype(np.float64))
+    for l in range(len(dims) - 1):
+        gW = dW[l].double().cpu().numpy()
+        gb = db[l].double().cpu().numpy()
+        eW = np.linalg.norm(gW - rW[l]) / np.linalg.norm(rW[l])
+        eb = np.linalg.norm(gb - rb[l]) / np.linalg.norm(rb[l])
+        say(f"  layer {l}: dW rel {eW:.2e}, db rel {eb:.2e}")
+        assert eW < 3e-2 and eb < 3e-2
+
+
+def test_huber_loss_matches_oracle(orc, dev, api):
+    say("huber loss")
+    rng = np.random.default_rng(2)
+    n = 70001
+    yh = rng.normal(0, 1.5, n).astype(np.float32)
+    y = rng.normal(0, 1.5, n).astype(np.float32)
+    dy = torch.empty(n, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    api.huber_loss(torch.as_tensor(yh, device=dev), torch.as_tensor(y, device=dev), dy, loss)
+    ref = orc.huber_loss(yh.astype(np.float64), y.astype(np.float64))
+    assert float(loss.item()) == pytest.approx(ref, rel=1e-12)
+    np.testing.assert_allclose(dy.double().cpu().numpy(),
+                               orc.huber_grad(yh.astype(np.float64), y.astype(np.float64)),
+                               rtol=1e-6, atol=1e-13)
+
+
+def test_anet_rows_match_oracle(orc, dev, api):
+    say("anet rows")
+    s = W.angle_samples(seed=3, n=5000)
+    chi = np.random.default_rng(5).uniform(-6, 3, 5000)
+    lo, hi = math.log(5.0), math.log(5e5)
+    x, y = api.anet_rows(torch.as_tensor(s["b"], device=dev), torch.as_tensor(s["g"], device=dev),
+                         torch.as_tensor(chi, device=dev), W.AR_MASS / 2, lo, hi, W.B_MAX)
+    rx, ry = orc.angle_rows(s["b"], s["g"], chi, W.AR_MASS / 2, lo, hi, W.B_MAX)
+    np.testing.assert_allclose(x.double().cpu().numpy(), rx, rtol=0, atol=2e-7)
+    np.testing.assert_allclose(y.double().cpu().numpy(), ry, rtol=2e-7, atol=2e-7)
+
+
+@pytest.mark.parametrize("shape", [(17, 9), (512, 512)])
+def test_chi_table_build_matches_fp64(orc, dev, api, shape):
+    say("chi table build", shape)
+    dims = (2, 512, 512, 512, 256, 128, 1)
+    net, Wr, br = _net(api, dev, 6, dims)
+    lo, hi = math.log(5.0), math.log(5e5)
+    tab = api.ChiTable(shape[0], shape[1], lo, hi, device=dev)
+    api.chi_table_build(net, tab)
+    got = tab.theta.double().cpu().numpy()
+    if shape == (512, 512):
+        # sampled rows (the FP64 oracle on all 262 144 nodes takes too long)
+        rows = [0, 1, 255, 400, 511]
+        lnE, brel = orc.table_grid(*shape, lo, hi)
+        E = np.repeat(np.exp(lnE[rows]), shape[1])
+        B = np.tile(brel, len(rows))
+        y = orc.angle_net_forward(Wr, br, orc.angle_net_input(E, B, lo, hi))
+        ref = np.clip(np.expm1(y), 0, math.pi).reshape(len(rows), shape[1])
+        got = got[rows]
+    else:
+        ref = orc.chi_table(Wr, br, shape[0], shape[1], lo, hi)
+    err = np.abs(got - ref)
+    say(f"  theta rms err {np.sqrt(np.mean(err ** 2)):.2e} rad, max {err.max():.2e}")
+    assert np.sqrt(np.mean(err ** 2)) < 1e-2 and err.max() < 5e-2
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_collide_table_step_matches_oracle(orc, dev, api, dtype):
+    say("collide table step", dtype)
+    pop = W.ragged_population(21, 300, 120, empty_frac=0.1)
+    cs_np, perm, _ = orc.sort_cells(pop.cell_of, pop.n_cells)
+    v_np = pop.v[:, perm]
+    lo, hi = math.log(5.0), math.log(5e5)
+    # an arbitrary smooth table of the right shape and range
+    lnE, brel = orc.table_grid(64, 33, lo, hi)
+    theta = (math.pi * (1 - brel[None, :]) ** 2 * (0.3 + 0.7 / (1 + np.exp(lnE[:, None] - 6)))
+             ).astype(np.float32)
+    tab = api.ChiTable(64, 33, lo, hi, device=dev, theta=theta)
+    cs = torch.as_tensor(cs_np, device=dev)
+    v = torch.as_tensor(v_np, dtype=dtype, device=dev).contiguous()
+    lam = torch.as_tensor(pop.lam, device=dev)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, v, mom, api.L.MM_CAPTURE)
+    pairs = api.PairList(pop.n_cells, 1 << 20, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 9, 2, pairs)
+    api.collide_table(tab, v, pairs, 9, 2, W.AR_MASS / 2)
+    table = {"theta": theta.astype(np.float64), "lne_lo": lo, "lne_hi": hi}
+    vin = v_np.astype(np.float32).astype(np.float64) if dtype == torch.float32 else v_np
+    ref, info = orc.step(cs_np, vin, pop.xs, pop.lam, 9, 2, rule="table", table=table,
+                         m_red=W.AR_MASS / 2, lowp=dtype == torch.float32, match=False)
+    scale = max(float(np.max(np.abs(vin))), math.sqrt(W.KB * 300 / W.AR_MASS))
+    err = float(np.max(np.abs(v.double().cpu().numpy() - ref))) / scale
+    say(f"  {int(info['sel']['pair_cnt'].sum())} pairs, velocity rel err {err:.2e}")
+    assert err < (1e-12 if dtype == torch.float64 else 2e-5)
+
+
+def test_anet_training_reduces_loss(dev, api):
+    say("angle network short training run")
+    from paper_2602_21244_amd import train_anet as T
+    net, hist = T.train(steps=200, batch=2048, pool=1 << 16, lr=1e-3, seed=5, log_every=100,
+                        dev=dev)
+    first, last = hist[0], hist[-1]
+    say(f"  val huber {first[2]:.3e} -> {last[2]:.3e}, theta rms {first[3]:.3f} -> {last[3]:.3f}")
+    assert last[2] < 0.5 * first[2]
+    assert last[3] < first[3]

@@ -296,6 +296,24 @@ def training_rows(seed: int = 4, n: int = 65536, g_lo: float = 100.0,
     return {"vr": vr, "xi": xi, "z": z, "g": g, "sigma_v": sigma_v}
 
 
+def angle_samples(seed: int = 11, n: int = 1 << 20, lne_lo: float = math.log(5.0),
+                  lne_hi: float = math.log(5.0e5), m_red: float = AR_MASS / 2,
+                  b_max: float = B_MAX):
+    """Collision parameters for the angle network's training set.
+
+    E_r / k_B log-uniform on [exp(lne_lo), exp(lne_hi)] K; b / b_max uniform
+    for one half of the rows and U^2 (biased towards head-on collisions) for
+    the other half; g = sqrt(2 E_r / m_red).
+    """
+    rng = np.random.default_rng(seed)
+    lnE = rng.uniform(lne_lo, lne_hi, n)
+    E = np.exp(lnE) * KB
+    u = rng.random(n)
+    b_rel = np.where(np.arange(n) % 2 == 0, u, u * u)
+    g = np.sqrt(2.0 * E / m_red)
+    return {"b": b_rel * b_max, "g": g, "E_kelvin": np.exp(lnE), "b_rel": b_rel}
+
+
 # --------------------------------------------------------------------------
 # Network parameters
 # --------------------------------------------------------------------------
