@@ -251,7 +251,8 @@ def main():
     t_mlp = per_n["phaseA"] * 1e-3
     achieved = n_pairs * MLP_FLOP_PER_PAIR / t_mlp
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_BF16, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_BF16,
+                "traffic": counter_traffic("k_mlp_bf16<128, true, float, 0, false, 1>"),
                 "kernel": "k_mlp_bf16 (Phase A of dsmc_neural_collide)",
                 "algorithmic_flop_per_pair": MLP_FLOP_PER_PAIR}
     sort_bytes = n * (4 + 4 + 12 + 12 + 4)  # cell id twice, v read + write, perm
@@ -315,6 +316,25 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def counter_traffic(kernel, source="mlp.hip"):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy), or None when the
+    summary is missing or was taken on a different build of the kernel."""
+    from paper_2602_21244_amd.build import compile_signature
+    path = os.path.join(ROOT, "profiles", "hbm_counters_mach10_cylinder_400x300_bench.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    try:
+        blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+        k = blob["kernels"][kernel]
+    except (IndexError, KeyError, ValueError):
+        return None
+    if k.get("compile_signature") != compile_signature(source):
+        return None
+    return k["hbm_bytes"]
 
 
 def anet_flop_per_row(dims):

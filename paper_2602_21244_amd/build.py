@@ -19,9 +19,36 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-munsafe-fp-atomics", "-Wno-unused-result"]
 
 
+# Files whose FP64 results must be bit-identical across kernels that compute
+# the same update (Phase-B schedules, the fused step, moment matching): no
+# FMA contraction, so every expression rounds the same way in every kernel.
+EXACT = {"collide.hip", "step_fused.hip", "moments.hip"}
+
+
+def flags_for(src):
+    return CFLAGS + (["-ffp-contract=off"] if os.path.basename(src) in EXACT else [])
+
+
+def compile_signature(name):
+    """sha256 of what one source's object depends on: the .hip file, every
+    header in csrc/ and include/, and its compile flags (profiles record it
+    so a stale counter reading can be recognised)."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(CSRC, name)
+    h.update(open(src, "rb").read())
+    hdrs = sorted(glob.glob(os.path.join(CSRC, "*.hpp")) +
+                  glob.glob(os.path.join(os.path.dirname(HERE), "include", "*.h")))
+    for f in hdrs:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    h.update(" ".join(flags_for(src)).encode())
+    return h.hexdigest()
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + flags_for(src) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

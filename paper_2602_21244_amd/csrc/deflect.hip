@@ -157,39 +157,66 @@ __device__ __forceinline__ T D_of(const Pot& P, T b2, T E, T r)
     return T(1) - b2 / (r * r) - V_of<T>(P, r) / E;
 }
 
-// Gauss-Legendre over t in [ta, tb] of 2 t / sqrt(F), with
-// F = beta^2 t^2 (2 - t^2) + (V(r_min) - V(r))/E + D0 and r = r_min / (1 - t^2).
+// One node of the t integral: 2 t / sqrt(F) with
+// F = beta^2 t^2 (2 - t^2) + (V(r_min) - V(r))/E + D0 and r = r_min / (1 - t^2);
+// also F / t^2 (for the peak indicator).
 template <typename T>
-__device__ __forceinline__ T integral_part(const Pot& P, const GLRule& gl, T rmin, T beta, T Vmin,
-                                           T E, T D0, T ta, T tb)
+__device__ __forceinline__ T node_term(const Pot& P, T rmin, T beta, T Vmin, T E, T D0, T t,
+                                       T& f_over_t2)
 {
     const T g1 = T(0.5) - T(0.28867513459481287);  // 2-point Gauss-Legendre on [0,1]
     const T g2 = T(0.5) + T(0.28867513459481287);
+    const T t2 = t * t;
+    const T dr = rmin * t2 / (T(1) - t2);
+    T dV = T(0);
+    if (P.p.kind != DSMC_POT_HS) {
+        if (t2 < T(1e-3))
+            dV = -dr * T(0.5) * (dV_of<T>(P, rmin + g1 * dr) + dV_of<T>(P, rmin + g2 * dr));
+        else
+            dV = Vmin - V_of<T>(P, rmin + dr);
+    }
+    const T F = beta * beta * t2 * (T(2) - t2) + dV / E + D0;
+    f_over_t2 = F / t2;
+    return F > T(0) ? T(2) * t / sqrt(F) : T(0);
+}
+
+// Gauss-Legendre over t in [ta, tb]; qmin tracks min F / t^2 over the nodes.
+template <typename T>
+__device__ __forceinline__ T integral_part(const Pot& P, const GLRule& gl, T rmin, T beta, T Vmin,
+                                           T E, T D0, T ta, T tb, T& qmin)
+{
     const T len = tb - ta;
     T I = T(0);
     for (int k = 0; k < gl.n; ++k) {
-        const T t = ta + len * T(gl.t[k]);
-        const T t2 = t * t;
-        const T dr = rmin * t2 / (T(1) - t2);
-        T dV = T(0);
-        if (P.p.kind != DSMC_POT_HS) {
-            if (t2 < T(1e-3))
-                dV = -dr * T(0.5) * (dV_of<T>(P, rmin + g1 * dr) + dV_of<T>(P, rmin + g2 * dr));
-            else
-                dV = Vmin - V_of<T>(P, rmin + dr);
-        }
-        const T F = beta * beta * t2 * (T(2) - t2) + dV / E + D0;
-        if (F > T(0)) I += T(gl.w[k]) * T(2) * t / sqrt(F);
+        T fq;
+        I += T(gl.w[k]) * node_term<T>(P, rmin, beta, Vmin, E, D0, ta + len * T(gl.t[k]), fq);
+        qmin = fq < qmin ? fq : qmin;
     }
     return len * I;
 }
 
-// chi(b, E) with b in Angstrom, E/k_B in K.  Returns NaN if no root is found.
+// Peak indicator threshold: below the scan energy, F / t^2 (which is
+// r_min D'(r_min) at t = 0 and 1 at t = 1) dipping under this value marks an
+// integrand with a sharp interior peak (near orbiting), for which one
+// Gauss-Legendre panel is not enough; such pairs are re-integrated on
+// low_panels equal panels.
+constexpr double Q_REFINE = 0.6;
+
 template <typename T>
-__device__ T chi_quad(const Pot& P, const QuadCfg& q, const GLRule& gl, T b, T E)
+struct QuadState {
+    T rmin, beta, Vmin, E, D0;
+    bool refine;
+};
+
+// chi(b, E) with b in Angstrom, E/k_B in K, by the one-panel rule; returns
+// NaN if no root is found.  s receives what a panel refinement needs.
+template <typename T>
+__device__ T chi_quad_std(const Pot& P, const QuadCfg& q, const GLRule& gl, T b, T E,
+                          QuadState<T>& s)
 {
     const T pi = Consts<T>::pi;
     const T b2 = b * b;
+    s.refine = false;
     T rmin, D0 = T(0);
     if (P.p.kind == DSMC_POT_HS) {
         const T d = T(P.p.d);
@@ -238,23 +265,63 @@ __device__ T chi_quad(const Pot& P, const QuadCfg& q, const GLRule& gl, T b, T E
     }
     const T beta = b / rmin;
     const T Vmin = (P.p.kind == DSMC_POT_HS) ? T(0) : V_of<T>(P, rmin);
-    // the short-range switch of the JAGER form is a kink of the integrand:
-    // integrate the two sides separately
+    s.rmin = rmin;
+    s.beta = beta;
+    s.Vmin = Vmin;
+    s.E = E;
+    s.D0 = D0;
     T I = T(0);
+    T qmin = T(1e30);
     if (E < T(P.e_scan) && P.p.kind == DSMC_POT_JAGER) {
-        // low energy: r_min lies outside the short-range region; equal panels
-        // resolve the sharp interior peak near orbiting
-        const T h = T(1) / T(q.low_panels);
-        for (int k = 0; k < q.low_panels; ++k)
-            I += integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, h * T(k),
-                                  k == q.low_panels - 1 ? T(1) : h * T(k + 1));
+        // low energy: r_min lies outside the short-range region
+        I = integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, T(0), T(1), qmin);
+        s.refine = q.low_panels > 1 && qmin < T(Q_REFINE);
     } else {
+        // the short-range switch of the JAGER form is a kink of the
+        // integrand: integrate the two sides separately
         T tsw = T(1);
         if (P.p.kind == DSMC_POT_JAGER && rmin < T(P.r_sw)) tsw = sqrt(T(1) - rmin / T(P.r_sw));
-        I = integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, T(0), tsw);
-        if (tsw < T(1)) I += integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, tsw, T(1));
+        I = integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, T(0), tsw, qmin);
+        if (tsw < T(1)) I += integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, tsw, T(1), qmin);
     }
     return pi - T(2) * beta * I;
+}
+
+// chi for the lanes of a wave (all 64 lanes call it; inactive lanes pass
+// active = false).  Pairs flagged for refinement are re-integrated one at a
+// time by the whole wave: the low_panels x n nodes are spread over the lanes
+// and summed by a fixed butterfly, so the cost of a flagged pair is a few
+// node evaluations per lane.
+template <typename T>
+__device__ T chi_quad_wave(const Pot& P, const QuadCfg& q, const GLRule& gl, T b, T E,
+                           bool active)
+{
+    QuadState<T> s{};
+    T c = T(0);
+    if (active) c = chi_quad_std<T>(P, q, gl, b, E, s);
+    const bool flag = active && s.refine && c == c;
+    uint64_t pend = __ballot(flag);
+    const int lane = threadIdx.x & 63;
+    const int n = gl.n, np = q.low_panels, total = n * np;
+    const T inv_np = T(1) / T(np);
+    while (pend) {
+        const int src = __ffsll((unsigned long long)pend) - 1;
+        const T rmin = __shfl(s.rmin, src, 64), beta = __shfl(s.beta, src, 64);
+        const T Vmin = __shfl(s.Vmin, src, 64), Ee = __shfl(s.E, src, 64);
+        const T D0 = __shfl(s.D0, src, 64);
+        T I = T(0);
+        for (int m = lane; m < total; m += 64) {
+            const int k = m / n, j = m - k * n;
+            T fq;
+            I += T(gl.w[j]) * inv_np *
+                 node_term<T>(P, rmin, beta, Vmin, Ee, D0, (T(k) + T(gl.t[j])) * inv_np, fq);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) I += __shfl_xor(I, o, 64);
+        if (lane == src) c = Consts<T>::pi - T(2) * beta * I;
+        pend &= pend - 1;
+    }
+    return c;
 }
 
 // ------------------------------------------------------------------------
@@ -405,11 +472,14 @@ __global__ void __launch_bounds__(256)
 k_deflect(int64_t n, const T* __restrict__ b, const T* __restrict__ g, T* __restrict__ chi,
           T half_m_over_k, Pot P, QuadCfg q, GLRule gl, int fold, dsmc_status* st)
 {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const T gg = g[p];
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < n;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = base + (threadIdx.x & 63);
+        const bool active = p < n;
+        const T gg = active ? g[p] : T(1);
         const T E = half_m_over_k * gg * gg;
-        T c = chi_quad<T>(P, q, gl, b[p] * T(1e10), E);
+        T c = chi_quad_wave<T>(P, q, gl, active ? b[p] * T(1e10) : T(1), E, active);
+        if (!active) continue;
         if (c != c) {
             if (st) {
                 atomicAdd(&st->root_fail, 1);
@@ -429,18 +499,24 @@ k_phaseA_jager(int32_t n_cells, PairsView pr, dsmc_rng rng, V3<const T> v, T hal
                T b_max_A, Pot P, QuadCfg q, GLRule gl, PairBuf<T> out, dsmc_status* st)
 {
     const int64_t np = pr.total(n_cells);
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t k = pr.cell[p];
-        const uint32_t a = (uint32_t)(p - pr.off[k]);
-        T xi[3], z[2], u4;
-        pair_latents(rng, a, (uint32_t)k, xi, z, u4);
-        const int32_t i = pr.i[p], j = pr.j[p];
-        const T rx = v.x[i] - v.x[j], ry = v.y[i] - v.y[j], rz = v.z[i] - v.z[j];
-        const T g2 = rx * rx + ry * ry + rz * rz;
-        const T E = half_m_over_k * g2;
-        const T bb = b_max_A * sqrt(u4);  // b^2 / b_max^2 = 1 - exp(-|z|^2/2) = U4
-        T c = chi_quad<T>(P, q, gl, bb, E);
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < np;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = base + (threadIdx.x & 63);
+        const bool active = p < np;
+        T xi[3] = {T(0), T(0), T(0)}, z[2], u4 = T(0);
+        T E = T(1), bb = T(1);
+        if (active) {
+            const int32_t k = pr.cell[p];
+            const uint32_t a = (uint32_t)(p - pr.off[k]);
+            pair_latents(rng, a, (uint32_t)k, xi, z, u4);
+            const int32_t i = pr.i[p], j = pr.j[p];
+            const T rx = v.x[i] - v.x[j], ry = v.y[i] - v.y[j], rz = v.z[i] - v.z[j];
+            const T g2 = rx * rx + ry * ry + rz * rz;
+            E = half_m_over_k * g2;
+            bb = b_max_A * sqrt(u4);  // b^2 / b_max^2 = 1 - exp(-|z|^2/2) = U4
+        }
+        T c = chi_quad_wave<T>(P, q, gl, bb, E, active);
+        if (!active) continue;
         if (c != c) {
             if (st) {
                 atomicAdd(&st->root_fail, 1);
@@ -463,16 +539,20 @@ k_harvest(int64_t B, const double* __restrict__ vr, const double* __restrict__ x
           Pot P, QuadCfg q, GLRule gl, float* __restrict__ x_out, float* __restrict__ g_out,
           float* __restrict__ tgt, double* __restrict__ chi_out, dsmc_status* st)
 {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < B;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const double v0 = vr[3 * r], v1 = vr[3 * r + 1], v2 = vr[3 * r + 2];
-        const double x0 = xi[3 * r], x1 = xi[3 * r + 1], x2 = xi[3 * r + 2];
-        const double z0 = z[2 * r], z1 = z[2 * r + 1];
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < B;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = base + (threadIdx.x & 63);
+        const bool active = r < B;
+        const int64_t rr = active ? r : 0;
+        const double v0 = vr[3 * rr], v1 = vr[3 * rr + 1], v2 = vr[3 * rr + 2];
+        const double x0 = xi[3 * rr], x1 = xi[3 * rr + 1], x2 = xi[3 * rr + 2];
+        const double z0 = z[2 * rr], z1 = z[2 * rr + 1];
         double vh[3], e[3];
         const double g = unit3<double>(v0, v1, v2, vh);
         const double bt2 = -expm1(-0.5 * (z0 * z0 + z1 * z1));
         const double bb = b_max_A * sqrt(bt2);
-        double c = chi_quad<double>(P, q, gl, bb, half_m_over_k * g * g);
+        double c = chi_quad_wave<double>(P, q, gl, bb, half_m_over_k * g * g, active);
+        if (!active) continue;
         if (c != c) {
             if (st) {
                 atomicAdd(&st->root_fail, 1);
