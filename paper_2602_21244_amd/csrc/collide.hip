@@ -239,9 +239,12 @@ __device__ __forceinline__ void group_minmax(int32_t& lo, int32_t& hi, int32_t* 
 }
 
 // WAVE schedule: one 64-lane workgroup per cell with thr < pairs <= 256 whose
-// pairs span at most 1024 slots; a cell that does not fit is appended to the
-// list handled by the BLOCK kernel (list[0] = length, list[1..] = cells).
-constexpr int WV_NMAX = 1024;
+// pairs span at most 512 slots (small LDS tables, so many workgroups stay
+// resident to hide the cell loads); every other cell with more than thr
+// pairs is appended to the list the BLOCK kernel works through (list[0] =
+// length, list[1..] = cells).  The next cell's count and offset are loaded
+// while the current cell runs.
+constexpr int WV_NMAX = 512;
 constexpr int WV_PPL = 4;
 
 template <typename T, int RULE>
@@ -252,10 +255,26 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
     __shared__ T lx[WV_NMAX], ly[WV_NMAX], lz[WV_NMAX];
     __shared__ int32_t first[WV_NMAX];
     const int lane = threadIdx.x;
-    for (int32_t k = blockIdx.x; k < n_cells; k += gridDim.x) {
-        const int32_t c = pr.cnt[k];
-        if (c == 0 || c < min_pairs || c > 64 * WV_PPL) continue;
-        const int64_t o = pr.off[k];
+    int64_t k = blockIdx.x;
+    int32_t c = k < n_cells ? pr.cnt[k] : 0;
+    int32_t o32 = k < n_cells ? pr.off[k] : 0;
+    for (; k < n_cells; k += gridDim.x) {
+        const int64_t kn = k + gridDim.x;
+        const int32_t c_next = kn < n_cells ? pr.cnt[kn] : 0;
+        const int32_t o_next = kn < n_cells ? pr.off[kn] : 0;
+        const int64_t o = o32;
+        const int32_t cc = c;
+        c = c_next;
+        o32 = o_next;
+        if (cc == 0 || cc < min_pairs) continue;
+        if (cc > 64 * WV_PPL) {
+            if (lane == 0) {
+                const int32_t at = atomicAdd(&list[0], 1);
+                list[1 + at] = (int32_t)k;
+            }
+            continue;
+        }
+        const int32_t c_ = cc;
         int32_t pa[WV_PPL], pb[WV_PPL];
         int32_t lo = INT32_MAX, hi = -1;
 #pragma unroll
@@ -263,7 +282,7 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
             const int32_t q = lane + 64 * m;
             pa[m] = 0;
             pb[m] = 0;
-            if (q < c) {
+            if (q < c_) {
                 pa[m] = pr.i[o + q];
                 pb[m] = pr.j[o + q];
                 lo = min(lo, min(pa[m], pb[m]));
@@ -275,23 +294,23 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
         if (span > WV_NMAX) {
             if (lane == 0) {
                 const int32_t at = atomicAdd(&list[0], 1);
-                list[1 + at] = k;
+                list[1 + at] = (int32_t)k;
             }
             continue;
         }
 #pragma unroll
         for (int m = 0; m < WV_PPL; ++m)
-            if (lane + 64 * m >= c) { pa[m] = lo; pb[m] = lo; }
-        cell_rounds_lds<T, RULE, 64, WV_PPL>(pr, v, d, c, o, lo, span, pa, pb, lx, ly, lz, first);
+            if (lane + 64 * m >= c_) { pa[m] = lo; pb[m] = lo; }
+        cell_rounds_lds<T, RULE, 64, WV_PPL>(pr, v, d, c_, o, lo, span, pa, pb, lx, ly, lz, first);
     }
 }
 
 // BLOCK schedule: 256 threads per cell.  Cells with up to 2048 pairs spanning
 // up to 4096 slots run the LDS rounds; larger ones (up to 8192) run the same
 // rounds on velocities in global memory with the tables in LDS; beyond that
-// one thread applies the pairs in order.  Handles the cells with at least
-// min_pairs pairs not taken by the WAVE kernel (wave_max: its pair limit, or
-// 0 when it did not run) and the cells in `list`.
+// one thread applies the pairs in order.  Works through the cells in `list`
+// after the WAVE kernel, or (list == nullptr) every cell with at least
+// min_pairs pairs.
 constexpr int BLK_THREADS = 256;
 constexpr int BLK_PPL = 8;
 constexpr int BLK_NMAX = 4096;      // LDS rounds
@@ -345,7 +364,7 @@ __device__ void cell_rounds_global(V3<T> v, const PairBuf<T>& d, const PairsView
 template <typename T, int RULE>
 __global__ void __launch_bounds__(BLK_THREADS)
 k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
-               int32_t wave_max, const int32_t* list)
+               const int32_t* list)
 {
     __shared__ __attribute__((aligned(16))) char smem[BlkLds<T>::bytes];
     __shared__ int32_t red[2 * (BLK_THREADS / 64)];
@@ -353,15 +372,15 @@ k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min
     T* ly = lx + BLK_NMAX;
     T* lz = ly + BLK_NMAX;
     int32_t* first = reinterpret_cast<int32_t*>(lz + BLK_NMAX);
-    const int64_t n_listed = list ? list[0] : 0;
-    for (int64_t idx = blockIdx.x; idx < (int64_t)n_cells + n_listed; idx += gridDim.x) {
+    const int64_t n_items = list ? (int64_t)list[0] : (int64_t)n_cells;
+    for (int64_t idx = blockIdx.x; idx < n_items; idx += gridDim.x) {
         int32_t k;
-        if (idx < n_cells) {
+        if (list) {
+            k = list[1 + idx];
+        } else {
             k = (int32_t)idx;
             const int32_t c = pr.cnt[k];
-            if (c == 0 || c < min_pairs || c <= wave_max) continue;
-        } else {
-            k = list[1 + (idx - n_cells)];
+            if (c == 0 || c < min_pairs) continue;
         }
         const int32_t c = pr.cnt[k];
         const int64_t o = pr.off[k];
@@ -445,8 +464,7 @@ int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsm
         }                                                                                   \
         if (need_rest) {                                                                    \
             k_phaseB_block<T, R><<<bb, BLK_THREADS, 0, s>>>(                                \
-                n_cells, pr, v3<T>(v), d, thr + 1, use_wave ? 64 * WV_PPL : 0,              \
-                use_wave ? list : nullptr);                                                 \
+                n_cells, pr, v3<T>(v), d, thr + 1, use_wave ? list : nullptr);              \
             DSMC_LAUNCH_CHECK("phaseB:block");                                              \
         }                                                                                   \
     } while (0)

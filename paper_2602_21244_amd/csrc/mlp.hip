@@ -297,8 +297,8 @@ __device__ __forceinline__ void save_pre(const RowsIO& rio, int l, const int64_t
 // Each wave processes NT tiles of 32 rows; every A fragment read from LDS
 // feeds NT MFMAs.  Pairs mode: the lane of row r in lane-half 0 computes the
 // pair's xi, the lane in lane-half 1 its z and v_r (dims[0] == 8).
-template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT>
-__global__ void __launch_bounds__(H == 256 || NT > 1 ? 256 : 512)
+template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT, int TPB>
+__global__ void __launch_bounds__(TPB)
 k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -460,21 +460,27 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
     }
 }
 
-static int mlp_tiles_per_wave()
+// Launch shape of the fused kernel: 1 = one 32-row tile per wave, 512-thread
+// workgroups (two waves per SIMD share the LDS copy of the weights); 2 = two
+// tiles per wave (each weight fragment read from LDS feeds two MFMAs),
+// 256 threads; 3 = one tile per wave, 256 threads (one wave per SIMD with the
+// whole register file).  DSMC_MLP_CONFIG selects it (default 1).
+static int mlp_config()
 {
-    static int nt = -1;
-    if (nt < 0) {
-        const char* e = getenv("DSMC_MLP_TILES_PER_WAVE");
-        nt = (e && atoi(e) == 2) ? 2 : 1;
+    static int cfg = -1;
+    if (cfg < 0) {
+        const char* e = getenv("DSMC_MLP_CONFIG");
+        const int v = e ? atoi(e) : 1;
+        cfg = (v == 2 || v == 3) ? v : 1;
     }
-    return nt;
+    return cfg;
 }
 
-template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT>
+template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT, int TPB>
 static int launch_one(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
                       int64_t max_rows, hipStream_t s)
 {
-    auto kern = k_mlp_bf16<H, PAIRS, VT, ACT, SAVE, NT>;
+    auto kern = k_mlp_bf16<H, PAIRS, VT, ACT, SAVE, NT, TPB>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -483,12 +489,11 @@ static int launch_one(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<
         attr_set = true;
     }
     const int cus = device_cus();
-    const int threads = (H == 256 || NT > 1) ? 256 : 512;
     const int64_t groups = (max_rows + 32 * NT - 1) / (32 * NT);
-    int64_t blocks = (groups + threads / 64 - 1) / (threads / 64);
+    int64_t blocks = (groups + TPB / 64 - 1) / (TPB / 64);
     if (blocks > cus) blocks = cus;
     if (blocks < 1) blocks = 1;
-    kern<<<(int)blocks, threads, f.bytes, s>>>(d, f, rio, pio);
+    kern<<<(int)blocks, TPB, f.bytes, s>>>(d, f, rio, pio);
     DSMC_LAUNCH_CHECK("mlp_bf16");
     return DSMC_OK;
 }
@@ -497,9 +502,10 @@ template <int H, bool PAIRS, typename VT, int ACT, bool SAVE>
 static int launch_nt(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
                      int64_t max_rows, hipStream_t s)
 {
-    if (mlp_tiles_per_wave() == 2)
-        return launch_one<H, PAIRS, VT, ACT, SAVE, 2>(d, f, rio, pio, max_rows, s);
-    return launch_one<H, PAIRS, VT, ACT, SAVE, 1>(d, f, rio, pio, max_rows, s);
+    const int cfg = H == 256 ? 3 : mlp_config();
+    if (cfg == 2) return launch_one<H, PAIRS, VT, ACT, SAVE, 2, 256>(d, f, rio, pio, max_rows, s);
+    if (cfg == 3) return launch_one<H, PAIRS, VT, ACT, SAVE, 1, 256>(d, f, rio, pio, max_rows, s);
+    return launch_one<H, PAIRS, VT, ACT, SAVE, 1, 512>(d, f, rio, pio, max_rows, s);
 }
 
 template <int H, bool PAIRS, typename VT>
