@@ -19,7 +19,6 @@ namespace dsmc {
 
 constexpr double KB_SI = 1.380649e-23;
 constexpr int ANET_SPLITS = 16;        // K split of the dW GEMMs
-constexpr int RED_ROWS = 256;          // rows per partial of the column reductions
 constexpr int64_t TABLE_CHUNK = 65536; // rows per table-synthesis pass
 
 struct AnetDims {
@@ -84,9 +83,7 @@ static AnetWs anet_layout(void* base, const AnetDims& a, int64_t R)
         if (x > dd) dd = x;
     }
     w.partial = reinterpret_cast<float*>(take(sizeof(float) * ANET_SPLITS * dd));
-    const int64_t chunks = (R + RED_ROWS - 1) / RED_ROWS;
-    w.red = reinterpret_cast<float*>(take(sizeof(float) * (size_t)(chunks > 0 ? chunks : 1) *
-                                          a.dmax * 3));
+    w.red = reinterpret_cast<float*>(take(sizeof(float) * colsum_ws_floats(R, a.dmax)));
     w.bytes = o;
     return w;
 }
@@ -128,50 +125,6 @@ k_anet_first(int64_t R, int n, const float* __restrict__ x, const __bf16* __rest
         const float zz = (float)W0[2 * c] * x0 + (float)W0[2 * c + 1] * x1 + b0[c];
         if (z0) z0[r * n + c] = zz;
         h0[r * n + c] = (__bf16)silu_f(zz);
-    }
-}
-
-// Per row chunk and column: sums of dz, dz x0, dz x1 (x optional).
-__global__ void __launch_bounds__(256)
-k_col_partial(const float* __restrict__ dz, int64_t R, int n, const float* __restrict__ x,
-              float* __restrict__ red)
-{
-    const int c = blockIdx.y * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    const int64_t r0 = (int64_t)blockIdx.x * RED_ROWS;
-    const int64_t r1 = r0 + RED_ROWS < R ? r0 + RED_ROWS : R;
-    float s = 0.f, s0 = 0.f, s1 = 0.f;
-    for (int64_t r = r0; r < r1; ++r) {
-        const float d = dz[r * n + c];
-        s += d;
-        if (x) {
-            s0 += d * x[2 * r];
-            s1 += d * x[2 * r + 1];
-        }
-    }
-    float* o = red + ((int64_t)blockIdx.x * n + c) * 3;
-    o[0] = s;
-    o[1] = s0;
-    o[2] = s1;
-}
-
-__global__ void __launch_bounds__(256)
-k_col_final(const float* __restrict__ red, int64_t chunks, int n, float* __restrict__ db,
-            float* __restrict__ dW0)
-{
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    float s = 0.f, s0 = 0.f, s1 = 0.f;
-    for (int64_t q = 0; q < chunks; ++q) {
-        const float* o = red + (q * n + c) * 3;
-        s += o[0];
-        s0 += o[1];
-        s1 += o[2];
-    }
-    db[c] = s;
-    if (dW0) {
-        dW0[2 * c] = s0;
-        dW0[2 * c + 1] = s1;
     }
 }
 
@@ -390,7 +343,6 @@ extern "C" int dsmc_anet_backward(const dsmc_anet* net, int64_t rows, const floa
                          dsmc_anet_ws(net, rows));
     hipStream_t s = as_stream(stream);
     const AnetWs w = anet_layout(ws, a, rows);
-    const int64_t chunks = (rows + RED_ROWS - 1) / RED_ROWS;
     int cur = 0;
     const int L = a.L;
     k_out_delta<<<grid_for(rows), 256, 0, s>>>(rows, dy, w.z[L - 1], w.dz32[cur], w.dz16[cur]);
@@ -415,11 +367,8 @@ extern "C" int dsmc_anet_backward(const dsmc_anet* net, int64_t rows, const floa
         rc = gemm_bf16(g, ANET_SPLITS, s);
         if (rc) return rc;
         // db_l
-        dim3 pg((unsigned)chunks, (unsigned)((n_out + 255) / 256));
-        k_col_partial<<<pg, 256, 0, s>>>(w.dz32[cur], rows, n_out, nullptr, w.red);
-        DSMC_LAUNCH_CHECK("anet:col_partial");
-        k_col_final<<<(n_out + 255) / 256, 256, 0, s>>>(w.red, chunks, n_out, db[l], nullptr);
-        DSMC_LAUNCH_CHECK("anet:col_final");
+        rc = colsum_f32(w.dz32[cur], rows, n_out, nullptr, w.red, db[l], nullptr, 0, s);
+        if (rc) return rc;
         // dz_{l-1} = (dz_l W_l) * SiLU'(z_{l-1})
         GemmArgs d{};
         d.a = w.dz16[cur];
@@ -442,13 +391,7 @@ extern "C" int dsmc_anet_backward(const dsmc_anet* net, int64_t rows, const floa
         cur = 1 - cur;
     }
     // layer 0: db_0 = sum dz_0, dW_0 = dz_0^T x
-    const int n1 = a.d[1];
-    dim3 pg((unsigned)chunks, (unsigned)((n1 + 255) / 256));
-    k_col_partial<<<pg, 256, 0, s>>>(w.dz32[cur], rows, n1, w.x, w.red);
-    DSMC_LAUNCH_CHECK("anet:col_partial0");
-    k_col_final<<<(n1 + 255) / 256, 256, 0, s>>>(w.red, chunks, n1, db[0], dW[0]);
-    DSMC_LAUNCH_CHECK("anet:col_final0");
-    return DSMC_OK;
+    return colsum_f32(w.dz32[cur], rows, a.d[1], w.x, w.red, db[0], dW[0], 0, s);
 }
 
 extern "C" int dsmc_huber_loss(int64_t n, const float* yhat, const float* y, float* dy,

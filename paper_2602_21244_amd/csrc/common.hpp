@@ -41,13 +41,12 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        // one 32 x 32 -> 64-bit product gives both halves (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -158,8 +157,12 @@ template <typename T>
 __device__ __forceinline__ T unit3(T a, T b, T c, T (&o)[3])
 {
     const T n = dev_sqrt<T>(a * a + b * b + c * c);
-    if (n > T(0)) { o[0] = a / n; o[1] = b / n; o[2] = c / n; }
-    else { o[0] = T(1); o[1] = T(0); o[2] = T(0); }
+    if (n > T(0)) {
+        const T inv = T(1) / n;
+        o[0] = a * inv; o[1] = b * inv; o[2] = c * inv;
+    } else {
+        o[0] = T(1); o[1] = T(0); o[2] = T(0);
+    }
     return n;
 }
 
@@ -180,7 +183,8 @@ __device__ __forceinline__ void perp_dir(const T (&xi)[3], const T (&vh)[3], T (
         w2 = vh[0] * t1 - vh[1] * t0;
         n = dev_sqrt<T>(w0 * w0 + w1 * w1 + w2 * w2);
     }
-    e[0] = w0 / n; e[1] = w1 / n; e[2] = w2 / n;
+    const T inv = T(1) / n;
+    e[0] = w0 * inv; e[1] = w1 * inv; e[2] = w2 * inv;
 }
 
 // Status word updates (device).

@@ -30,6 +30,7 @@ __device__ __forceinline__ float act_apply(int act, float z)
     switch (act) {
     case GEMM_ACT_SILU: return z * sigm(z);
     case GEMM_ACT_SOFTPLUS: return z > 20.0f ? z : log1pf(expf(z));
+    case GEMM_ACT_RELU: return z > 0.0f ? z : 0.0f;
     default: return z;
     }
 }
@@ -42,6 +43,7 @@ __device__ __forceinline__ float act_deriv(int act, float z)
         return s * (1.0f + z * (1.0f - s));
     }
     case GEMM_ACT_SOFTPLUS: return sigm(z);
+    case GEMM_ACT_RELU: return z > 0.0f ? 1.0f : 0.0f;
     default: return 1.0f;
     }
 }
@@ -182,6 +184,63 @@ k_gemm_reduce(GemmArgs g, int splits)
         for (int s = 0; s < splits; ++s) v += g.partial[(int64_t)s * total + q];
         gemm_epilogue(g, q / g.N, q % g.N, v);
     }
+}
+
+// Per row chunk and column: sums of a, a x0, a x1 (x optional).
+__global__ void __launch_bounds__(256)
+k_col_partial(const float* __restrict__ a, int64_t R, int n, const float* __restrict__ x,
+              float* __restrict__ red)
+{
+    const int c = blockIdx.y * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int64_t r0 = (int64_t)blockIdx.x * COLSUM_ROWS;
+    const int64_t r1 = r0 + COLSUM_ROWS < R ? r0 + COLSUM_ROWS : R;
+    float s = 0.f, s0 = 0.f, s1 = 0.f;
+    for (int64_t r = r0; r < r1; ++r) {
+        const float d = a[r * n + c];
+        s += d;
+        if (x) {
+            s0 += d * x[2 * r];
+            s1 += d * x[2 * r + 1];
+        }
+    }
+    float* o = red + ((int64_t)blockIdx.x * n + c) * 3;
+    o[0] = s;
+    o[1] = s0;
+    o[2] = s1;
+}
+
+__global__ void __launch_bounds__(256)
+k_col_final(const float* __restrict__ red, int64_t chunks, int n, float* __restrict__ out,
+            float* __restrict__ out2, int accumulate)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    float s = 0.f, s0 = 0.f, s1 = 0.f;
+    for (int64_t q = 0; q < chunks; ++q) {
+        const float* o = red + (q * n + c) * 3;
+        s += o[0];
+        s0 += o[1];
+        s1 += o[2];
+    }
+    out[c] = accumulate ? out[c] + s : s;
+    if (out2) {
+        out2[2 * c] = accumulate ? out2[2 * c] + s0 : s0;
+        out2[2 * c + 1] = accumulate ? out2[2 * c + 1] + s1 : s1;
+    }
+}
+
+int colsum_f32(const float* a, int64_t R, int n, const float* x2, float* red, float* out,
+               float* out2, int accumulate, hipStream_t s)
+{
+    if (R <= 0 || n <= 0) return DSMC_OK;
+    const int64_t chunks = (R + COLSUM_ROWS - 1) / COLSUM_ROWS;
+    dim3 pg((unsigned)chunks, (unsigned)((n + 255) / 256));
+    k_col_partial<<<pg, 256, 0, s>>>(a, R, n, x2, red);
+    DSMC_LAUNCH_CHECK("colsum:partial");
+    k_col_final<<<(n + 255) / 256, 256, 0, s>>>(red, chunks, n, out, out2, accumulate);
+    DSMC_LAUNCH_CHECK("colsum:final");
+    return DSMC_OK;
 }
 
 int gemm_bf16(const GemmArgs& g0, int splits, hipStream_t s)

@@ -5,7 +5,7 @@
 
 namespace dsmc {
 
-enum { GEMM_ACT_NONE = 0, GEMM_ACT_SILU = 1, GEMM_ACT_SOFTPLUS = 2 };
+enum { GEMM_ACT_NONE = 0, GEMM_ACT_SILU = 1, GEMM_ACT_SOFTPLUS = 2, GEMM_ACT_RELU = 3 };
 
 struct GemmArgs {
     const __bf16* a;
@@ -28,5 +28,17 @@ struct GemmArgs {
 // Launch on stream s; splits > 1 divides K over workgroups (FP32 partials
 // summed in a fixed order).
 int gemm_bf16(const GemmArgs& g, int splits, hipStream_t s);
+
+// Column sums of a[R][n] (FP32) in a fixed order: out[c] = sum_r a[r][c]
+// (+= when accumulate); with x2 != null also out2[2c + q] = sum_r a[r][c] x2[r][q].
+// red: colsum_ws_floats(R, n) floats of workspace.
+constexpr int COLSUM_ROWS = 256;
+inline size_t colsum_ws_floats(int64_t R, int n)
+{
+    const int64_t chunks = (R + COLSUM_ROWS - 1) / COLSUM_ROWS;
+    return (size_t)(chunks > 0 ? chunks : 1) * (size_t)n * 3;
+}
+int colsum_f32(const float* a, int64_t R, int n, const float* x2, float* red, float* out,
+               float* out2, int accumulate, hipStream_t s);
 
 }  // namespace dsmc

@@ -17,6 +17,7 @@
 #include <stdlib.h>
 
 #include "collide.hpp"
+#include "gemm.hpp"
 
 namespace dsmc {
 
@@ -809,13 +810,140 @@ static int backward_impl(const MlpDev& d, int64_t B, const T* X, const T* Z, con
     return DSMC_OK;
 }
 
-static size_t backward_ws_bytes(const MlpDev& d, int64_t B, size_t es)
+// BF16 network: the weight and input gradients on the matrix cores.
+// dW_l = delta_l^T h_{l-1} (K = B split over workgroups, fixed-order sum),
+// delta_{l-1} = (delta_l W_l) * act'(z_{l-1}) with the derivative fused in the
+// GEMM epilogue; db_l by a fixed-order column sum.  delta is kept in FP32 (for
+// db) and bf16 (the GEMM operand); h_{l-1} is the bf16 activation the forward
+// used.
+struct Bf16BwdWs {
+    float* d32[2];
+    __bf16* d16[2];
+    __bf16* h16;
+    float* part;
+    float* red;
+    size_t bytes;
+};
+
+constexpr int BWD_SPLITS_MAX = 32;
+
+static Bf16BwdWs bf16_bwd_layout(void* base, const MlpDev& d, int64_t B)
 {
     int wmax = 8;
     for (int l = 0; l <= d.L; ++l) wmax = wmax > d.dims[l] ? wmax : d.dims[l];
+    Bf16BwdWs w{};
+    uint8_t* p = static_cast<uint8_t*>(base);
+    size_t o = 0;
+    auto take = [&](size_t b) { uint8_t* r = p ? p + o : nullptr; o += align_up(b); return r; };
+    for (int q = 0; q < 2; ++q) {
+        w.d32[q] = reinterpret_cast<float*>(take(sizeof(float) * (size_t)B * wmax));
+        w.d16[q] = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * (size_t)B * wmax));
+    }
+    w.h16 = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * (size_t)B * wmax));
+    w.part = reinterpret_cast<float*>(take(sizeof(float) * BWD_SPLITS_MAX * (size_t)wmax * wmax));
+    w.red = reinterpret_cast<float*>(take(sizeof(float) * colsum_ws_floats(B, wmax)));
+    w.bytes = o;
+    return w;
+}
+
+__global__ void __launch_bounds__(256)
+k_to_bf16(int64_t n, const float* __restrict__ a, __bf16* __restrict__ b)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        b[q] = (__bf16)a[q];
+}
+
+// h_{l-1} in bf16: x for l == 0, act(z) otherwise.
+__global__ void __launch_bounds__(256)
+k_hprev16(int64_t n_el, const float* __restrict__ X, const float* __restrict__ Zp, int l, int act,
+          __bf16* __restrict__ H)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_el;
+         q += (int64_t)gridDim.x * blockDim.x)
+        H[q] = (__bf16)((l == 0) ? X[q] : act_t<float>(Zp[q], act));
+}
+
+static int backward_bf16(const MlpDev& d, int64_t B, const float* X, const float* Z,
+                         const float* Y, const float* g, const float* G, float* const* dW,
+                         float* const* db, float* dx, int accumulate, void* ws, hipStream_t s)
+{
+    const Bf16BwdWs w = bf16_bwd_layout(ws, d, B);
+    const int pb = persistent_blocks(256);
+    auto grid1 = [&](int64_t n) {
+        int64_t b = (n + 255) / 256;
+        return (int)(b < 1 ? 1 : (b > pb ? pb : b));
+    };
+    int splits = (int)(B / 2048);
+    splits = splits < 1 ? 1 : (splits > BWD_SPLITS_MAX ? BWD_SPLITS_MAX : splits);
+    const int dout = d.dims[d.L];
+    int cur = 0;
+    k_project_backward<float><<<grid1(B), 256, 0, s>>>(B, Y, dout, g, G, w.d32[cur]);
+    DSMC_LAUNCH_CHECK("mlp_bwd16:project");
+    k_to_bf16<<<grid1(B * dout), 256, 0, s>>>(B * dout, w.d32[cur], w.d16[cur]);
+    DSMC_LAUNCH_CHECK("mlp_bwd16:to_bf16");
+    int64_t zoff[MLP_MAX_LAYERS] = {0};
+    for (int l = 1; l < d.L; ++l) zoff[l] = zoff[l - 1] + B * d.dims[l];
+    const int gact = d.act == DSMC_ACT_RELU ? GEMM_ACT_RELU : GEMM_ACT_SILU;
+    for (int l = d.L - 1; l >= 0; --l) {
+        const int out = d.dims[l + 1], in = d.dims[l];
+        const float* Zp = (l > 0) ? Z + zoff[l - 1] : nullptr;
+        k_hprev16<<<grid1(B * in), 256, 0, s>>>(B * in, X, Zp, l, d.act, w.h16);
+        DSMC_LAUNCH_CHECK("mlp_bwd16:hprev");
+        GemmArgs gw{};
+        gw.a = w.d16[cur];
+        gw.lda = out;
+        gw.ta = 1;
+        gw.b = w.h16;
+        gw.ldb = in;
+        gw.tb = 0;
+        gw.M = out;
+        gw.N = in;
+        gw.K = B;
+        gw.act = GEMM_ACT_NONE;
+        gw.accumulate = accumulate;
+        gw.out_f32 = dW[l];
+        gw.ldo = in;
+        gw.partial = w.part;
+        int rc = gemm_bf16(gw, splits, s);
+        if (rc) return rc;
+        rc = colsum_f32(w.d32[cur], B, out, nullptr, w.red, db[l], nullptr, accumulate, s);
+        if (rc) return rc;
+        if (l > 0 || dx) {
+            GemmArgs gd{};
+            gd.a = w.d16[cur];
+            gd.lda = out;
+            gd.ta = 0;
+            gd.b = static_cast<const __bf16*>(d.W[l]);
+            gd.ldb = in;
+            gd.tb = 0;
+            gd.M = B;
+            gd.N = in;
+            gd.K = out;
+            gd.dact_z = Zp;
+            gd.ldz = in;
+            gd.act = l > 0 ? gact : GEMM_ACT_NONE;
+            gd.out_f32 = (l > 0) ? w.d32[1 - cur] : dx;
+            gd.out_bf16 = (l > 0) ? w.d16[1 - cur] : nullptr;
+            gd.ldo = in;
+            rc = gemm_bf16(gd, 1, s);
+            if (rc) return rc;
+            cur = 1 - cur;
+        }
+    }
+    return DSMC_OK;
+}
+
+static size_t backward_ws_bytes(const MlpDev& d, int64_t B, size_t es)
+{
+    const size_t b16 = bf16_bwd_layout(nullptr, d, B).bytes + 256;
+    int wmax = 8;
+    for (int l = 0; l <= d.L; ++l) wmax = wmax > d.dims[l] ? wmax : d.dims[l];
     const int64_t n_chunks = (B + 2047) / 2048;
-    return 256 + 3 * align_up(es * (size_t)B * wmax) + align_up(es * (size_t)n_chunks * wmax * wmax) +
-           align_up(es * (size_t)n_chunks * wmax);
+    const size_t gen = 256 + 3 * align_up(es * (size_t)B * wmax) +
+                       align_up(es * (size_t)n_chunks * wmax * wmax) +
+                       align_up(es * (size_t)n_chunks * wmax);
+    return gen > b16 ? gen : b16;
 }
 
 // ------------------------------------------------------------------------
@@ -1065,10 +1193,9 @@ extern "C" int dsmc_neural_backward(const dsmc_mlp* net, int64_t B, const void* 
                                              s);
     }
     if (net->wdtype == DSMC_BF16) {
-        return backward_impl<float, __bf16>(d, B, (const float*)x, (const float*)act_save,
-                                            (const float*)y_raw, (const float*)g,
-                                            (const float*)dL_dvr, (float* const*)dW,
-                                            (float* const*)db, (float*)dx, accumulate, true, ws, s);
+        return backward_bf16(d, B, (const float*)x, (const float*)act_save, (const float*)y_raw,
+                             (const float*)g, (const float*)dL_dvr, (float* const*)dW,
+                             (float* const*)db, (float*)dx, accumulate, ws, s);
     }
     return backward_impl<float, float>(d, B, (const float*)x, (const float*)act_save,
                                        (const float*)y_raw, (const float*)g, (const float*)dL_dvr,

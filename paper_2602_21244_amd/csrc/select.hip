@@ -1,17 +1,15 @@
 // No-Time-Counter pair selection (section "Cell partition and collision-pair
 // selection").  Candidates are generated for all cells at once, one lane per
 // candidate, so the work is balanced however uneven the cell populations are:
-//   count M_k per cell -> scan (candidate offsets) -> accept pass: each wave
-//   takes a chunk of 1024 consecutive candidates (one binary search for the
-//   chunk's first cell, then a forward walk), draws and decides them and
-//   counts the accepted ones -> scan of the chunk counts -> emit pass: the
-//   same decisions again, accepted pairs written densely (cell-major,
-//   candidate order) at the chunk's offset, with each cell's pair offset ->
-//   per-cell counts.
-// Deciding twice costs arithmetic and L2-resident velocity reads, and saves
-// writing and re-reading every candidate.  The decision arithmetic (g, the
-// candidate count) uses explicitly rounded FP64 operations so it is the same
-// on every launch shape and in both passes.
+//   count M_k per cell -> scan (candidate offsets) -> the cell of each
+//   1024-candidate chunk's first candidate -> decide pass: each wave takes a
+//   chunk, walks its cells forward, draws and decides the candidates and
+//   stages the accepted pairs compactly in the chunk's own slots, with each
+//   cell's offset inside the chunk -> scan of the chunk counts -> copy pass:
+//   the staged pairs of every chunk to their dense, cell-major place -> per
+//   cell offsets and counts.
+// The decision arithmetic (g, the candidate count) uses explicitly rounded
+// FP64 operations so it is the same on every launch shape.
 #include <math.h>
 
 #include "common.hpp"
@@ -76,6 +74,7 @@ k_cand_count(const int32_t* __restrict__ cell_start, int32_t n_cells,
 
 constexpr int CAND_ROUNDS = 16;
 constexpr int CAND_CHUNK = 64 * CAND_ROUNDS;
+constexpr int CAND_GROUP = 4;
 
 // Overflow decision: total candidates vs capacity; number of chunks.
 __global__ void k_cand_check(const int64_t* total, int64_t cap, int32_t* ok, int64_t* n_use,
@@ -92,58 +91,68 @@ __global__ void k_cand_check(const int64_t* total, int64_t cap, int32_t* ok, int
     }
 }
 
-// Largest k with off[k] <= c (off non-decreasing, off[0] = 0).
-__device__ __forceinline__ int32_t find_cell(const int32_t* __restrict__ off, int32_t n_cells,
-                                             int32_t c)
-{
-    int32_t lo = 0, hi = n_cells;  // answer in [lo, hi)
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= c) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 // Candidate t of cell k: indices (Lemire multiply-shift, j != i) and the
-// acceptance test U < (g / g_hat)^e.
-template <typename T>
-__device__ __forceinline__ bool cand_decide(const int32_t* __restrict__ cell_start, int32_t k,
-                                            int32_t t, const double* __restrict__ mom, double e,
-                                            const dsmc_rng& rng, const V3<const T>& v,
-                                            int32_t& pi, int32_t& pj)
+// acceptance uniform.
+struct CandDraw {
+    int32_t i, j;   // sorted slots
+    double U;
+};
+
+__device__ __forceinline__ CandDraw cand_draw(const int32_t* __restrict__ cell_start, int32_t k,
+                                              int32_t t, const dsmc_rng& rng)
 {
     const int32_t s0 = cell_start[k], N = cell_start[k + 1] - s0;
     const U4 r = draw(rng, (uint32_t)t, (uint32_t)k, SLOT_CAND);
     int32_t i = (int32_t)(((uint64_t)r.a * (uint64_t)N) >> 32);
     int32_t j = (int32_t)(((uint64_t)r.b * (uint64_t)(N - 1)) >> 32);
     if (j >= i) j += 1;
-    const double U = unif53(r.c, r.d);
-    const double dx = (double)v.x[s0 + i] - (double)v.x[s0 + j];
-    const double dy = (double)v.y[s0 + i] - (double)v.y[s0 + j];
-    const double dz = (double)v.z[s0 + i] - (double)v.z[s0 + j];
+    return CandDraw{s0 + i, s0 + j, unif53(r.c, r.d)};
+}
+
+// Acceptance test U < (g / g_hat)^e on the pre-step velocities.
+template <typename T>
+__device__ __forceinline__ bool cand_accept(const CandDraw& d, const V3<const T>& v, double ghat,
+                                            double e)
+{
+    const double dx = (double)v.x[d.i] - (double)v.x[d.j];
+    const double dy = (double)v.y[d.i] - (double)v.y[d.j];
+    const double dz = (double)v.z[d.i] - (double)v.z[d.j];
     const double g2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
                                 __dmul_rn(dz, dz));
     const double g = sqrt(g2);
-    const double ghat = 2.0 * mom[6 * (size_t)k + 4];
     const double ratio = g / ghat;
     const double p = (e == 1.0) ? ratio : pow(ratio, e);
-    pi = s0 + i;
-    pj = s0 + j;
-    return U < p;
+    return d.U < p;
 }
 
-// EMIT = false: accepted candidates per chunk.  EMIT = true: write the
-// accepted pairs from the chunk offsets, and pair_off[k] for every cell whose
-// candidates start inside the chunk (empty cells get the offset of the next
-// candidate).
-template <typename T, bool EMIT>
+// Cell owning the first candidate of each chunk (one thread per cell).
 __global__ void __launch_bounds__(256)
-k_cand_chunks(const int32_t* __restrict__ cell_start, int32_t n_cells,
+k_chunk_cells(int32_t n_cells, const int32_t* __restrict__ cand_off,
+              const int64_t* __restrict__ n_use, int32_t* __restrict__ chunk_cell)
+{
+    const int64_t total = *n_use;
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_cells;
+         k += gridDim.x * blockDim.x) {
+        const int64_t a = cand_off[k];
+        const int64_t b = cand_off[k + 1] < total ? cand_off[k + 1] : total;
+        for (int64_t ch = (a + CAND_CHUNK - 1) / CAND_CHUNK; ch * CAND_CHUNK < b; ++ch)
+            chunk_cell[ch] = k;
+    }
+}
+
+// Decide every candidate of a chunk; accepted pairs go to the chunk's slots
+// [ch * 1024, ...) of the staging arrays in candidate order; loc[k] = number
+// of accepted pairs of the chunk before cell k's first candidate (for every
+// cell whose candidates start inside the chunk; empty cells take the value of
+// the next candidate).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cand_decide(const int32_t* __restrict__ cell_start, int32_t n_cells,
               const int32_t* __restrict__ cand_off, const int64_t* __restrict__ n_use,
-              const double* __restrict__ mom, double e, dsmc_rng rng, V3<const T> v,
-              int32_t* __restrict__ chunk_cnt, const int32_t* __restrict__ chunk_off,
-              int32_t* __restrict__ pi, int32_t* __restrict__ pj, int32_t* __restrict__ pc,
-              int32_t* __restrict__ pair_off)
+              const int32_t* __restrict__ chunk_cell, const double* __restrict__ mom, double e,
+              dsmc_rng rng, V3<const T> v, int32_t* __restrict__ chunk_cnt,
+              int32_t* __restrict__ si, int32_t* __restrict__ sj, int32_t* __restrict__ sc,
+              int32_t* __restrict__ loc)
 {
     const int64_t total = *n_use;
     const int64_t nch = (total + CAND_CHUNK - 1) / CAND_CHUNK;
@@ -153,50 +162,84 @@ k_cand_chunks(const int32_t* __restrict__ cell_start, int32_t n_cells,
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t ch = wave; ch < nch; ch += nwaves) {
         const int64_t cbase = ch * CAND_CHUNK;
-        int32_t kw = find_cell(cand_off, n_cells, (int32_t)cbase);
-        int32_t pos = EMIT ? chunk_off[ch] : 0;
+        int32_t kw = chunk_cell[ch];
         int32_t acc = 0;
-        for (int r = 0; r < CAND_ROUNDS; ++r) {
-            const int64_t base = cbase + r * 64;
-            if (base >= total) break;
-            const int64_t c = base + lane;
-            const bool valid = c < total;
-            int32_t k = kw, i = 0, j = 0;
-            bool take = false;
-            if (valid) {
-                while (k + 1 < n_cells && cand_off[k + 1] <= c) ++k;
-                take = cand_decide<T>(cell_start, k, (int32_t)(c - cand_off[k]), mom, e, rng, v,
-                                      i, j);
+        // CAND_GROUP rounds at a time: cells, draws and velocity gathers of
+        // the group are independent, so their loads overlap
+        for (int r0 = 0; r0 < CAND_ROUNDS; r0 += CAND_GROUP) {
+            if (cbase + r0 * 64 >= total) break;
+            int32_t kk[CAND_GROUP];
+            bool val[CAND_GROUP];
+            int64_t cc[CAND_GROUP];
+            int32_t k = kw;
+#pragma unroll
+            for (int u = 0; u < CAND_GROUP; ++u) {
+                cc[u] = cbase + (r0 + u) * 64 + lane;
+                val[u] = cc[u] < total;
+                if (val[u])
+                    while (k + 1 < n_cells && cand_off[k + 1] <= cc[u]) ++k;
+                kk[u] = k;
             }
-            const uint64_t ab = __ballot(take);
-            if (EMIT) {
-                const int32_t p = pos + (int32_t)__popcll(ab & lt);
-                if (take) {
-                    pi[p] = i;
-                    pj[p] = j;
-                    pc[p] = k;
+            CandDraw dr[CAND_GROUP];
+#pragma unroll
+            for (int u = 0; u < CAND_GROUP; ++u)
+                dr[u] = val[u] ? cand_draw(cell_start, kk[u], (int32_t)(cc[u] - cand_off[kk[u]]), rng)
+                               : CandDraw{0, 0, 1.0};
+            bool take[CAND_GROUP];
+#pragma unroll
+            for (int u = 0; u < CAND_GROUP; ++u)
+                take[u] = val[u] && cand_accept<T>(dr[u], v, 2.0 * mom[6 * (size_t)kk[u] + 4], e);
+#pragma unroll
+            for (int u = 0; u < CAND_GROUP; ++u) {
+                const uint64_t ab = __ballot(take[u]);
+                const int32_t p = acc + (int32_t)__popcll(ab & lt);
+                if (take[u]) {
+                    si[cbase + p] = dr[u].i;
+                    sj[cbase + p] = dr[u].j;
+                    sc[cbase + p] = kk[u];
                 }
-                if (valid && c == cand_off[k]) {
-                    pair_off[k] = p;
-                    for (int32_t q = k - 1; q >= 0 && cand_off[q] == c; --q) pair_off[q] = p;
+                if (val[u] && cc[u] == cand_off[kk[u]]) {
+                    loc[kk[u]] = p;
+                    for (int32_t q = kk[u] - 1; q >= 0 && cand_off[q] == cc[u]; --q) loc[q] = p;
                 }
-                pos += (int32_t)__popcll(ab);
-            } else {
                 acc += (int32_t)__popcll(ab);
             }
-            kw = __shfl(k, 63, 64);
+            kw = __shfl(kk[CAND_GROUP - 1], 63, 64);
         }
-        if (!EMIT && lane == 0) chunk_cnt[ch] = acc;
+        if (lane == 0) chunk_cnt[ch] = acc;
     }
 }
 
-// Pair counts per cell; cells whose candidates would start at or after the
-// last candidate (none left) get the total as offset.
+// Staged pairs of each chunk to their dense place (one wave per chunk).
+__global__ void __launch_bounds__(256)
+k_stage_copy(const int64_t* __restrict__ n_chunks, const int32_t* __restrict__ chunk_cnt,
+             const int32_t* __restrict__ chunk_off, const int32_t* __restrict__ si,
+             const int32_t* __restrict__ sj, const int32_t* __restrict__ sc,
+             int32_t* __restrict__ pi, int32_t* __restrict__ pj, int32_t* __restrict__ pc)
+{
+    const int64_t nch = *n_chunks;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t ch = wave; ch < nch; ch += nwaves) {
+        const int32_t n = chunk_cnt[ch], o = chunk_off[ch];
+        const int64_t src = ch * CAND_CHUNK;
+        for (int32_t q = lane; q < n; q += 64) {
+            pi[o + q] = si[src + q];
+            pj[o + q] = sj[src + q];
+            pc[o + q] = sc[src + q];
+        }
+    }
+}
+
+// Pair offsets and counts per cell; cells whose candidates would start at or
+// after the last candidate (none left) get the total as offset.
 __global__ void __launch_bounds__(256)
 k_pair_counts(int32_t n_cells, const int32_t* __restrict__ cand_off,
               const int32_t* __restrict__ ok, const int64_t* __restrict__ n_use,
               const int64_t* __restrict__ n_chunks, const int32_t* __restrict__ chunk_off,
-              int32_t* __restrict__ off, int32_t* __restrict__ cnt, dsmc_status* st)
+              const int32_t* __restrict__ loc, int32_t* __restrict__ off,
+              int32_t* __restrict__ cnt, dsmc_status* st)
 {
     const bool fits = *ok != 0;
     const int64_t total = *n_use;
@@ -208,24 +251,33 @@ k_pair_counts(int32_t n_cells, const int32_t* __restrict__ cand_off,
             cnt[k] = 0;
             continue;
         }
-        const bool tail = cand_off[k] >= total;
-        const int32_t a = tail ? npairs : off[k];
-        const int32_t b = (k + 1 == n_cells || cand_off[k + 1] >= total) ? npairs : off[k + 1];
-        if (tail) off[k] = a;
+        const int64_t ca = cand_off[k];
+        const int32_t a = ca >= total ? npairs : chunk_off[ca / CAND_CHUNK] + loc[k];
+        int32_t b = npairs;
+        if (k + 1 < n_cells) {
+            const int64_t cb = cand_off[k + 1];
+            b = cb >= total ? npairs : chunk_off[cb / CAND_CHUNK] + loc[k + 1];
+        }
+        off[k] = a;
         cnt[k] = b - a;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && st) st->n_pairs = npairs;
 }
 
 struct SelectWs {
-    int32_t* cand_cnt;   // [n_cells]
-    int32_t* cand_off;   // [n_cells + 1]
-    int64_t* total;      // candidates
-    int64_t* n_use;      // candidates processed (0 on overflow)
+    int32_t* cand_cnt;    // [n_cells]
+    int32_t* cand_off;    // [n_cells + 1]
+    int32_t* loc;         // [n_cells]
+    int64_t* total;       // candidates
+    int64_t* n_use;       // candidates processed (0 on overflow)
     int64_t* n_chunks;
     int32_t* ok;
-    int32_t* chunk_cnt;  // [max chunks]
-    int32_t* chunk_off;  // [max chunks + 1]
+    int32_t* chunk_cell;  // [max chunks]
+    int32_t* chunk_cnt;   // [max chunks]
+    int32_t* chunk_off;   // [max chunks + 1]
+    int32_t* si;          // staging [max chunks * 1024]
+    int32_t* sj;
+    int32_t* sc;
     void* scan;
     size_t bytes;
 };
@@ -241,12 +293,18 @@ static SelectWs select_ws_layout(void* base, int32_t n_cells, int64_t cap)
     const int64_t mc = max_chunks(cap);
     w.cand_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)n_cells + 1)));
     w.cand_off = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)n_cells + 2)));
+    w.loc = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)n_cells + 1)));
     w.total = reinterpret_cast<int64_t*>(take(sizeof(int64_t)));
     w.n_use = reinterpret_cast<int64_t*>(take(sizeof(int64_t)));
     w.n_chunks = reinterpret_cast<int64_t*>(take(sizeof(int64_t)));
     w.ok = reinterpret_cast<int32_t*>(take(sizeof(int32_t)));
+    w.chunk_cell = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)mc));
     w.chunk_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)mc));
     w.chunk_off = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)mc + 1)));
+    const size_t stage = sizeof(int32_t) * (size_t)mc * CAND_CHUNK;
+    w.si = reinterpret_cast<int32_t*>(take(stage));
+    w.sj = reinterpret_cast<int32_t*>(take(stage));
+    w.sc = reinterpret_cast<int32_t*>(take(stage));
     const size_t sb = scan_ws_bytes((int64_t)(mc > n_cells ? mc : n_cells) + 1);
     w.scan = take(sb);
     w.bytes = o;
@@ -268,20 +326,20 @@ static int select_impl(int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v, 
     if (rc) return rc;
     k_cand_check<<<1, 1, 0, s>>>(w.total, pairs.cap, w.ok, w.n_use, w.n_chunks, st);
     DSMC_LAUNCH_CHECK("select:check");
-    const V3<const T> vv = v3<const T>(v);
-    k_cand_chunks<T, false><<<pb, 256, 0, s>>>(cell_start, n_cells, w.cand_off, w.n_use, mom,
-                                               law.e, rng, vv, w.chunk_cnt, nullptr, nullptr,
-                                               nullptr, nullptr, nullptr);
-    DSMC_LAUNCH_CHECK("select:accept");
+    k_chunk_cells<<<cb, 256, 0, s>>>(n_cells, w.cand_off, w.n_use, w.chunk_cell);
+    DSMC_LAUNCH_CHECK("select:chunk_cells");
+    k_cand_decide<T><<<pb, 256, 0, s>>>(cell_start, n_cells, w.cand_off, w.n_use, w.chunk_cell,
+                                        mom, law.e, rng, v3<const T>(v), w.chunk_cnt, w.si, w.sj,
+                                        w.sc, w.loc);
+    DSMC_LAUNCH_CHECK("select:decide");
     rc = exclusive_scan_i32_dev(w.chunk_cnt, w.chunk_off, w.n_chunks, max_chunks(pairs.cap),
                                 w.scan, s);
     if (rc) return rc;
-    k_cand_chunks<T, true><<<pb, 256, 0, s>>>(cell_start, n_cells, w.cand_off, w.n_use, mom,
-                                              law.e, rng, vv, nullptr, w.chunk_off, pairs.i,
-                                              pairs.j, pairs.cell, pairs.off);
-    DSMC_LAUNCH_CHECK("select:emit");
+    k_stage_copy<<<pb, 256, 0, s>>>(w.n_chunks, w.chunk_cnt, w.chunk_off, w.si, w.sj, w.sc,
+                                    pairs.i, pairs.j, pairs.cell);
+    DSMC_LAUNCH_CHECK("select:copy");
     k_pair_counts<<<cb, 256, 0, s>>>(n_cells, w.cand_off, w.ok, w.n_use, w.n_chunks, w.chunk_off,
-                                     pairs.off, pairs.cnt, st);
+                                     w.loc, pairs.off, pairs.cnt, st);
     DSMC_LAUNCH_CHECK("select:counts");
     return DSMC_OK;
 }

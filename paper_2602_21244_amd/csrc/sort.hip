@@ -42,40 +42,57 @@ __device__ __forceinline__ uint64_t match_digit(int32_t d, bool valid, int dbits
     return same;
 }
 
-// Digit histogram of one tile (same particle-to-wave mapping as the down
-// pass; one LDS atomic per distinct digit per wave).  The first pass reads
-// cell_of, maps bad ids and counts them in the status word.
+// Digit histogram of one tile: each thread counts 16 consecutive keys
+// (16-byte loads) and adds runs of equal digits with one LDS atomic each, so
+// the cell-sorted-with-movers order typical after streaming costs a few
+// atomics per thread.  The first pass reads cell_of, maps bad ids and counts
+// them in the status word.
 template <bool FIRST>
 __global__ void __launch_bounds__(SORT_THREADS)
 k_radix_up(const int32_t* __restrict__ keys_in, int32_t n, int32_t n_cells, int shift,
            int32_t mask, int dbits, int32_t nblk, int32_t* __restrict__ ghist, dsmc_status* st)
 {
+    (void)dbits;
     __shared__ int32_t h[RADIX];
     for (int i = threadIdx.x; i <= mask; i += SORT_THREADS) h[i] = 0;
     __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t wbase = (int64_t)blockIdx.x * SORT_TILE + (int64_t)w * WAVE_SPAN;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int bad = 0;
-    for (int it = 0; it < SORT_ITEMS; ++it) {
-        const int64_t p = wbase + it * 64 + lane;
-        const bool valid = p < n;
-        int32_t key = 0;
-        if (valid) {
-            if (FIRST) {
-                key = sort_key(keys_in, p, n_cells);
-                bad += (key == n_cells);
-            } else {
-                key = keys_in[p];
-            }
+    const int64_t p0 = (int64_t)blockIdx.x * SORT_TILE + (int64_t)threadIdx.x * SORT_ITEMS;
+    int32_t key[SORT_ITEMS];
+    const bool full = p0 + SORT_ITEMS <= n;
+    if (full && ((reinterpret_cast<uintptr_t>(keys_in + p0) & 15) == 0)) {
+        const int4* src = reinterpret_cast<const int4*>(keys_in + p0);
+#pragma unroll
+        for (int q = 0; q < SORT_ITEMS / 4; ++q) {
+            const int4 x = src[q];
+            key[4 * q] = x.x; key[4 * q + 1] = x.y; key[4 * q + 2] = x.z; key[4 * q + 3] = x.w;
         }
-        const int32_t d = (key >> shift) & mask;
-        const uint64_t same = match_digit(d, valid, dbits);
-        if (valid && (same & lt_mask) == 0) atomicAdd(&h[d], (int32_t)__popcll(same));
+    } else {
+#pragma unroll
+        for (int q = 0; q < SORT_ITEMS; ++q) key[q] = (p0 + q < n) ? keys_in[p0 + q] : -1;
     }
+    int bad = 0;
+    int32_t run_d = -1, run_n = 0;
+#pragma unroll
+    for (int q = 0; q < SORT_ITEMS; ++q) {
+        if (p0 + q >= n) break;
+        int32_t kk = key[q];
+        if (FIRST && (kk < 0 || kk >= n_cells)) {
+            kk = n_cells;
+            ++bad;
+        }
+        const int32_t d = (kk >> shift) & mask;
+        if (d == run_d) {
+            ++run_n;
+        } else {
+            if (run_n) atomicAdd(&h[run_d], run_n);
+            run_d = d;
+            run_n = 1;
+        }
+    }
+    if (run_n) atomicAdd(&h[run_d], run_n);
     if (FIRST && st) {
         const int wbad = wave_sum_i(bad);
-        if (lane == 0 && wbad > 0) {
+        if ((threadIdx.x & 63) == 0 && wbad > 0) {
             atomicAdd(&st->bad_cell, wbad);
             atomicOr(&st->flags, (uint32_t)DSMC_ST_BAD_CELL);
         }
