@@ -75,6 +75,12 @@ def _declare(L):
                                  _i32p, _i32p, _i32p, _i32p, _i32p, C.c_int64,
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.orc_select_ntc.restype = C.c_int
+    L.orc_select_sbt.argtypes = [C.c_int32, _i32p, _f64p, _f64p, _f64p, C.c_double,
+                                 C.c_double, _f64p, C.c_uint64, C.c_uint32, C.c_int32,
+                                 _i32p, _i32p, _i32p, _i32p, _i32p, C.c_int64,
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int32)]
+    L.orc_select_sbt.restype = C.c_int
     L.orc_pair_latents.argtypes = [C.c_int64, _i32p, _i32p, C.c_uint64, C.c_uint32,
                                    C.c_int32, C.c_int, _f64p, _f64p, _f64p]
     L.orc_vhs_dirs.argtypes = [C.c_int64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p,
@@ -195,6 +201,34 @@ def select_ntc(cell_start, v, xs, lam, mom, seed, step, cap=None, cell_base=0):
     return {"overflow": False, "n_cand": total, "pair_off": off[:n_cells],
             "pair_cnt": cnt[:n_cells], "pair_i": pi[:m], "pair_j": pj[:m],
             "pair_cell": pc[:m], "cell_base": int(cell_base)}
+
+
+def select_sbt(cell_start, v, xs, lam, seed, step, cap=None, cell_base=0):
+    """Simplified Bernoulli Trials selection (same dict as select_ntc, with
+    n_cand = trials and n_clamped = trials whose probability exceeded 1)."""
+    cs = _c(cell_start, np.int32)
+    n_cells = len(cs) - 1
+    Cc, e = sigma_g_law(xs)
+    v = _c(v, np.float64)
+    counts = np.diff(cs)
+    total = int(np.sum(np.maximum(counts - 1, 0)))
+    if cap is None:
+        cap = 1 << 26
+    m = max(total, 1)
+    off = np.zeros(max(n_cells, 1), np.int32)
+    cnt = np.zeros(max(n_cells, 1), np.int32)
+    pi = np.zeros(m, np.int32)
+    pj = np.zeros(m, np.int32)
+    pc = np.zeros(m, np.int32)
+    nt, npair, ncl = C.c_int64(0), C.c_int64(0), C.c_int32(0)
+    rc = lib().orc_select_sbt(n_cells, cs, _c(v[0], np.float64), _c(v[1], np.float64),
+                              _c(v[2], np.float64), Cc, e, _c(lam, np.float64), int(seed),
+                              int(step), int(cell_base), off, cnt, pi, pj, pc, int(cap),
+                              C.byref(nt), C.byref(npair), C.byref(ncl))
+    k = npair.value
+    return {"overflow": rc != 0, "n_cand": nt.value, "n_clamped": ncl.value,
+            "pair_off": off[:n_cells], "pair_cnt": cnt[:n_cells], "pair_i": pi[:k],
+            "pair_j": pj[:k], "pair_cell": pc[:k], "cell_base": int(cell_base)}
 
 
 def pair_latents(sel, seed, step, lowp=False):
@@ -611,13 +645,14 @@ def table_angles(sel, v, U, table, b_max, m_red):
 # ---------------------------------------------------------------------------
 def step(cell_start, v, xs, lam, seed, step_no, rule="vhs", lowp=False,
          match=None, net=None, pot=None, b_max=1e-9, m_red=None, cap=None, cell_base=0,
-         table=None):
+         table=None, selection="ntc"):
     """One collision step on sorted velocities: select (pre-step velocities),
     Phase A per pair, Phase B in candidate order per cell, then moment matching.
 
     rule: "vhs" | "jager" | "neural" | "table".  net: dict(Ws, bs, act,
     sigma_v) for the neural rule; table: dict(theta, lne_lo, lne_hi) for the
     table rule.  match: None -> on for "neural", off otherwise.
+    selection: "ntc" | "sbt" (Simplified Bernoulli Trials).
     cell_base: global id of cell 0 of these arrays (a contiguous range of a
     larger population can be stepped on its own: the random numbers are keyed
     by the global cell id).
@@ -625,7 +660,10 @@ def step(cell_start, v, xs, lam, seed, step_no, rule="vhs", lowp=False,
     """
     v = np.asarray(v, np.float64)
     mom = moments(cell_start, v)
-    sel = select_ntc(cell_start, v, xs, lam, mom, seed, step_no, cap=cap, cell_base=cell_base)
+    if selection == "sbt":
+        sel = select_sbt(cell_start, v, xs, lam, seed, step_no, cap=cap, cell_base=cell_base)
+    else:
+        sel = select_ntc(cell_start, v, xs, lam, mom, seed, step_no, cap=cap, cell_base=cell_base)
     if sel["overflow"]:
         return v.copy(), {"sel": sel, "mom": mom}
     U, xi, z = pair_latents(sel, seed, step_no, lowp=lowp)

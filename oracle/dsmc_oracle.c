@@ -70,7 +70,7 @@ static double u24(uint32_t a)
 }
 
 /* RNG slot numbers of the step's counter layout. */
-enum { SLOT_CAND = 0, SLOT_COUNT = 1, SLOT_LAT0 = 2, SLOT_LAT1 = 3, SLOT_LAT2 = 4 };
+enum { SLOT_CAND = 0, SLOT_COUNT = 1, SLOT_LAT0 = 2, SLOT_LAT1 = 3, SLOT_LAT2 = 4, SLOT_SBT = 5 };
 
 /* ------------------------------------------------------------------------
  * Stable counting sort by cell id.
@@ -232,6 +232,65 @@ int orc_select_ntc(int32_t n_cells, const int32_t* cell_start, const double* vx,
     }
     free(li);
     free(lj);
+    *n_pairs_total = np;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Simplified Bernoulli Trials (Stefanov 2011), the rate control the paper
+ * names beside NTC: particle i (slot order, i = 0 .. N-2) gets one partner j
+ * drawn uniformly from the m = N-1-i particles after it, and the pair
+ * collides with probability m * lambda * sigma(g) g, so each unordered pair
+ * {i, j} collides with probability lambda sigma(g_ij) g_ij -- the same
+ * expectation as NTC.  Probabilities above 1 act as 1 and are counted.
+ * ---------------------------------------------------------------------- */
+int orc_select_sbt(int32_t n_cells, const int32_t* cell_start, const double* vx,
+                   const double* vy, const double* vz, double xs_C, double xs_e,
+                   const double* lambda, uint64_t seed, uint32_t step, int32_t cell_base,
+                   int32_t* pair_off, int32_t* pair_cnt, int32_t* pair_i, int32_t* pair_j,
+                   int32_t* pair_cell, int64_t cap, int64_t* n_trials_total,
+                   int64_t* n_pairs_total, int32_t* n_clamped)
+{
+    int64_t total = 0;
+    for (int32_t k = 0; k < n_cells; ++k) {
+        int32_t N = cell_start[k + 1] - cell_start[k];
+        if (N >= 2) total += N - 1;
+    }
+    *n_trials_total = total;
+    *n_clamped = 0;
+    if (total > cap) {
+        for (int32_t k = 0; k < n_cells; ++k) { pair_off[k] = 0; pair_cnt[k] = 0; }
+        *n_pairs_total = 0;
+        return 1;
+    }
+    int64_t np = 0;
+    for (int32_t k = 0; k < n_cells; ++k) {
+        int32_t s0 = cell_start[k], N = cell_start[k + 1] - s0;
+        int32_t a = 0;
+        pair_off[k] = (int32_t)np;
+        for (int32_t i = 0; i + 1 < N; ++i) {
+            int32_t m = N - 1 - i;
+            uint32_t r[4];
+            orc_draw(seed, step, (uint32_t)i, (uint32_t)(cell_base + k), SLOT_SBT, r);
+            int32_t j = i + 1 + (int32_t)(((uint64_t)r[0] * (uint64_t)m) >> 32);
+            double U = u53(r[2], r[3]);
+            double dx = vx[s0 + i] - vx[s0 + j];
+            double dy = vy[s0 + i] - vy[s0 + j];
+            double dz = vz[s0 + i] - vz[s0 + j];
+            double g = sqrt(dx * dx + dy * dy + dz * dz);
+            double sg = xs_C * ((xs_e == 1.0) ? g : pow(g, xs_e));
+            double P = (double)m * lambda[k] * sg;
+            if (P > 1.0) *n_clamped += 1;
+            if (U < P) {
+                pair_i[np + a] = s0 + i;
+                pair_j[np + a] = s0 + j;
+                pair_cell[np + a] = k;
+                ++a;
+            }
+        }
+        pair_cnt[k] = a;
+        np += a;
+    }
     *n_pairs_total = np;
     return 0;
 }

@@ -46,6 +46,12 @@ int orc_select_ntc(int32_t n_cells, const int32_t* cell_start, const double* vx,
                    uint32_t step, int32_t cell_base, int32_t* pair_off, int32_t* pair_cnt,
                    int32_t* pair_i, int32_t* pair_j, int32_t* pair_cell,
                    int64_t cap, int64_t* n_cand_total, int64_t* n_pairs_total);
+int orc_select_sbt(int32_t n_cells, const int32_t* cell_start, const double* vx,
+                   const double* vy, const double* vz, double xs_C, double xs_e,
+                   const double* lambda, uint64_t seed, uint32_t step, int32_t cell_base,
+                   int32_t* pair_off, int32_t* pair_cnt, int32_t* pair_i, int32_t* pair_j,
+                   int32_t* pair_cell, int64_t cap, int64_t* n_trials_total,
+                   int64_t* n_pairs_total, int32_t* n_clamped);
 
 /* Per-pair latent draws.  U[6p..6p+5] uniforms, xi[3p..] and z[2p..] normals.
  * lowp = 1 selects the 24-bit uniform construction used for FP32 velocities. */

@@ -165,6 +165,68 @@ def test_ntc_small_cells_and_overflow(orc):
     assert np.all(over["pair_cnt"] == 0)
 
 
+def test_sbt_partner_uniform_and_pair_rate(orc):
+    # Trial i draws its partner uniformly among the later slots and accepts
+    # with probability m * lambda * sigma g, so each unordered pair {i, j}
+    # collides with probability lambda sigma g_ij: with constant sigma and
+    # v_x = 0,100,..,400 the count of pair (i, j), i < j, is proportional to
+    # j - i; and j > i always.
+    from scipy import stats
+    N = 5
+    cs = np.array([0, N], np.int32)
+    v = np.zeros((3, N))
+    v[0] = np.arange(N) * 100.0
+    xs = {"kind": "const", "sigma": 1.0}
+    lam = np.array([1.0 / (4 * 400.0 * 1.01)])     # max P = m lam g < 1
+    counts = np.zeros((N, N))
+    trials = 0
+    for seed in range(3000):
+        sel = orc.select_sbt(cs, v, xs, lam, seed, 0)
+        assert sel["n_clamped"] == 0 and sel["n_cand"] == N - 1
+        assert np.all(sel["pair_j"] > sel["pair_i"])
+        np.add.at(counts, (sel["pair_i"], sel["pair_j"]), 1)
+        trials += 1
+    i, j = np.triu_indices(N, 1)
+    p = lam[0] * (j - i) * 100.0                        # lambda sigma g_ij
+    obs = counts[i, j]
+    exp = trials * p
+    chi2 = np.sum((obs - exp) ** 2 / exp)
+    assert stats.chi2.sf(chi2, len(obs)) > 1e-4, (obs, exp)
+
+
+def test_sbt_accepted_count_matches_rate(orc):
+    # E[accepted in cell] = lambda * sum_{i<j} sigma(g_ij) g_ij, as for NTC.
+    N = 60
+    cs, v = _one_cell(N, 1)
+    xs = {"kind": "vhs", "m": W.AR_MASS, "d_ref": W.AR_D_REF, "omega": W.AR_OMEGA,
+          "T_ref": W.AR_T_REF}
+    Cc, e = orc.sigma_g_law(xs)
+    lam = np.array([0.2 / ((N - 1) * W.vhs_mean_sigma_g(273.0))])
+    diff = v[:, :, None] - v[:, None, :]
+    g = np.sqrt(np.sum(diff ** 2, axis=0))
+    iu = np.triu_indices(N, 1)
+    expect = lam[0] * np.sum(Cc * g[iu] ** e)
+    sels = [orc.select_sbt(cs, v, xs, lam, s, 3) for s in range(400)]
+    assert all(sl["n_clamped"] == 0 for sl in sels)
+    cnt = np.array([len(sl["pair_i"]) for sl in sels])
+    z = (cnt.mean() - expect) / (cnt.std() / math.sqrt(cnt.size))
+    assert abs(z) < 4.0, (cnt.mean(), expect)
+
+
+def test_sbt_two_particles_clamp_and_overflow(orc):
+    # N = 2: one trial, P = lambda sigma g; P > 1 collides and is counted
+    cs = np.array([0, 0, 1, 3], np.int32)
+    v = np.array([[1.0, 2.0, 5.0], [0, 0, 0], [0, 0, 0]])
+    xs = {"kind": "const", "sigma": 1.0}
+    lam = np.array([1e9, 1e9, 0.1])                      # P = 0.1 * 3 = 0.3
+    acc = [len(orc.select_sbt(cs, v, xs, lam, s, 0)["pair_i"]) for s in range(4000)]
+    assert abs(np.mean(acc) - 0.3) < 4 * math.sqrt(0.3 * 0.7 / 4000)
+    big = orc.select_sbt(cs, v, xs, np.array([1.0, 1.0, 10.0]), 1, 0)
+    assert big["n_clamped"] == 1 and list(big["pair_cnt"]) == [0, 0, 1]
+    over = orc.select_sbt(cs, v, xs, lam, 5, 0, cap=0)
+    assert over["overflow"] and over["n_cand"] == 1 and np.all(over["pair_cnt"] == 0)
+
+
 def _sorted_pop(orc, pop):
     cs, perm, _ = orc.sort_cells(pop.cell_of, pop.n_cells)
     return cs, pop.v[:, perm]
