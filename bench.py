@@ -247,6 +247,11 @@ def main():
     log(f"table vs quadrature folded-angle error: rms {table_rms:.4f} rad ({akind} angle network)")
     table_flop = 512 * 512 * anet_flop_per_row(anet.dims)
 
+    # deflection batch (2^20 pairs, g log-uniform 100-20 000 m/s, b^2 uniform):
+    # quadrature FP64 / FP32 against the angle network evaluated per pair
+    batch = deflection_batch_timing(api, W, dev, pot, quad, anet, lne_lo, lne_hi)
+    log(f"deflection batch: {batch}")
+
     # roofline of the dominant kernel (the fused MLP, Phase A of the network)
     t_mlp = per_n["phaseA"] * 1e-3
     achieved = n_pairs * MLP_FLOP_PER_PAIR / t_mlp
@@ -275,6 +280,7 @@ def main():
         "pairs_per_step": n_pairs,
         "particles": n,
         "cells": n_cells,
+        "deflection_batch_2p20": batch,
     }
 
     # surrogate training step (batch 65 536 harvested rows): forward (MFMA),
@@ -289,7 +295,8 @@ def main():
         log(f"cpu baseline: {cpu}")
 
     out = {
-        "metric": "collision pairs/s (neural collision operator step; quadrature beside it)",
+        "metric": "collision pairs/s: neural vs quadrature \u03c7 at stated angle error; "
+                  "% HBM/MFMA peak",
         "value": n_pairs / (ms_n * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -302,14 +309,7 @@ def main():
         "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": wname, "particles": n, "cells": n_cells,
-                   "table_pairs_per_s": n_pairs / (ms_t * 1e-3),
-        "table_ms_per_step": ms_t,
-        "stage_ms_table": per_t,
-        "table_theta_rms_vs_quadrature_rad": table_rms,
-        "angle_network_weights": akind,
-        "table_build_ms_512x512": table_build_ms,
-        "table_build_TFLOPs": table_flop / (table_build_ms * 1e-3) / 1e12,
-        "pairs_per_step": n_pairs, "velocities": "fp32 SoA",
+                   "pairs_per_step": n_pairs, "velocities": "fp32 SoA",
                    "mlp": "8-128x4-3 SiLU bf16/fp32-acc", "moments": "fp64"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -335,6 +335,44 @@ def counter_traffic(kernel, source="mlp.hip"):
     if k.get("compile_signature") != compile_signature(source):
         return None
     return k["hbm_bytes"]
+
+
+def deflection_batch_timing(api, W, dev, pot, quad, anet, lne_lo, lne_hi, reps=3):
+    import torch
+    b, g, mr = W.deflection_batch(seed=2, n=1 << 20)
+    out = {"pairs": int(b.size)}
+    th = {}
+    for name, dt in (("quadrature_fp64", torch.float64), ("quadrature_fp32", torch.float32)):
+        bt = torch.as_tensor(b, dtype=dt, device=dev)
+        gt = torch.as_tensor(g, dtype=dt, device=dev)
+        chi = api.deflect_jager(bt, gt, mr, pot, quad)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            chi = api.deflect_jager(bt, gt, mr, pot, quad)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "pairs_per_s": b.size / (ms * 1e-3)}
+        th[name] = torch.arccos(torch.clamp(torch.cos(chi.double()), -1, 1))
+    b64 = torch.as_tensor(b, device=dev)
+    g64 = torch.as_tensor(g, device=dev)
+    chi64 = torch.as_tensor(th["quadrature_fp64"], device=dev)
+    x, _ = api.anet_rows(b64, g64, chi64, mr, lne_lo, lne_hi, W.B_MAX)
+    y, ws = api.anet_forward(anet, x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        api.anet_forward(anet, x, y, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["angle_network_per_pair"] = {"ms": ms, "pairs_per_s": b.size / (ms * 1e-3)}
+    th_net = torch.clamp(torch.expm1(y.double()), 0, math.pi)
+    ref = th["quadrature_fp64"]
+    out["theta_rms_fp32_vs_fp64_rad"] = float(torch.sqrt(((th["quadrature_fp32"] - ref) ** 2).mean()))
+    out["theta_rms_network_vs_fp64_rad"] = float(torch.sqrt(((th_net - ref) ** 2).mean()))
+    return out
 
 
 def anet_flop_per_row(dims):

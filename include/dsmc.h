@@ -62,13 +62,14 @@ typedef struct {
     int32_t root_fail;  /* deflection evaluations whose root search failed */
     int32_t nonfinite;  /* non-finite values met (results left unchanged) */
     int32_t mm_skipped; /* cells that moment matching left alone (S_post <= 0) */
-    int32_t reserved;
+    int32_t prob_clamped; /* SBT trials whose collision probability exceeded 1 */
 } dsmc_status;
 enum {
     DSMC_ST_PAIR_OVERFLOW = 1u, /* candidates exceeded the pair capacity */
     DSMC_ST_BAD_CELL = 2u,
     DSMC_ST_ROOT_FAIL = 4u,
-    DSMC_ST_NONFINITE = 8u
+    DSMC_ST_NONFINITE = 8u,
+    DSMC_ST_PROB_CLAMP = 16u    /* an SBT probability exceeded 1 (time step too large) */
 };
 
 /* Accepted-pair list, dense and cell-major: the pairs of cell k are entries
@@ -218,6 +219,23 @@ int dsmc_select_pairs_ntc(int32_t n_cells, const int32_t* cell_start, int32_t dt
                           dsmc_vec3 v, dsmc_xs xs, const double* lambda, const double* mom,
                           dsmc_rng rng, dsmc_pairs pairs, void* ws, size_t ws_bytes,
                           dsmc_status* st, dsmc_stream_t stream);
+
+/* Simplified Bernoulli Trials selection (Stefanov 2011), the alternative rate
+ * control the paper names beside NTC (section "Cell partition and
+ * collision-pair selection"): per cell with N >= 2, trial t = 0 .. N-2 takes
+ * the particle in slot t, draws its partner uniformly among the m = N-1-t
+ * later slots (Philox slot 5, Lemire multiply-shift) and accepts with
+ * probability P = m lambda_k sigma(g) g on the velocities as passed
+ * (P > 1 acts as 1; counted in st->prob_clamped with DSMC_ST_PROB_CLAMP).
+ * Same pair-list output as dsmc_select_pairs_ntc (trial order = candidate
+ * order); expected pairs per cell lambda_k sum_{i<j} sigma g_ij, as NTC.
+ * More than pairs.cap trials: nothing written, DSMC_ST_PAIR_OVERFLOW.
+ * ws: dsmc_select_pairs_sbt_ws(n_cells, cap) bytes. */
+size_t dsmc_select_pairs_sbt_ws(int32_t n_cells, int64_t cap);
+int dsmc_select_pairs_sbt(int32_t n_cells, const int32_t* cell_start, int32_t dtype,
+                          dsmc_vec3 v, dsmc_xs xs, const double* lambda, dsmc_rng rng,
+                          dsmc_pairs pairs, void* ws, size_t ws_bytes, dsmc_status* st,
+                          dsmc_stream_t stream);
 
 /* Workspace of the collide entry points below (per-pair Phase-A results). */
 size_t dsmc_collide_ws(int64_t cap, int32_t dtype);

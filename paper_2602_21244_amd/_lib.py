@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libdsmc.so")
 
 DSMC_OK, DSMC_E_ARG, DSMC_E_HIP, DSMC_E_UNSUPPORTED = 0, -1, -2, -3
 F32, F64, BF16 = 0, 1, 2
-ST_PAIR_OVERFLOW, ST_BAD_CELL, ST_ROOT_FAIL, ST_NONFINITE = 1, 2, 4, 8
+ST_PAIR_OVERFLOW, ST_BAD_CELL, ST_ROOT_FAIL, ST_NONFINITE, ST_PROB_CLAMP = 1, 2, 4, 8, 16
 XS_VHS, XS_CONST = 0, 1
 POT_JAGER, POT_HS, POT_INVPOW = 0, 1, 2
 ACT_SILU, ACT_RELU = 0, 1
@@ -29,7 +29,7 @@ class Rng(C.Structure):
 class Status(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("bad_cell", C.c_int32), ("n_cand", C.c_int64),
                 ("n_pairs", C.c_int64), ("root_fail", C.c_int32), ("nonfinite", C.c_int32),
-                ("mm_skipped", C.c_int32), ("reserved", C.c_int32)]
+                ("mm_skipped", C.c_int32), ("prob_clamped", C.c_int32)]
 
 
 class Pairs(C.Structure):
@@ -89,6 +89,9 @@ SIGNATURES = {
     "dsmc_select_pairs_ntc_ws": (_sz, [_i32, _i64]),
     "dsmc_select_pairs_ntc": (C.c_int, [_i32, _vp, _i32, Vec3, Xs, _vp, _vp, Rng, Pairs, _vp,
                                         _sz, _vp, _vp]),
+    "dsmc_select_pairs_sbt_ws": (_sz, [_i32, _i64]),
+    "dsmc_select_pairs_sbt": (C.c_int, [_i32, _vp, _i32, Vec3, Xs, _vp, Rng, Pairs, _vp, _sz, _vp,
+                                        _vp]),
     "dsmc_collide_ws": (_sz, [_i64, _i32]),
     "dsmc_collide_vhs": (C.c_int, [_i32, _i32, Vec3, Pairs, Rng, _i32, _vp, _sz, _vp]),
     "dsmc_apply_pairs": (C.c_int, [_i32, _i32, Vec3, Pairs, _i32, _i32, _vp, _sz, _vp]),

@@ -202,6 +202,19 @@ def select_pairs_ntc(cell_start, v, xs, lam, mom, seed, step, pairs, ws=None, st
     return ws
 
 
+def select_pairs_sbt(cell_start, v, xs, lam, seed, step, pairs, ws=None, st=None, stream=None):
+    n_cells = int(cell_start.numel()) - 1
+    need = lib().dsmc_select_pairs_sbt_ws(n_cells, pairs.cap)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, v.device)
+    check(lib().dsmc_select_pairs_sbt(n_cells, _ptr(cell_start), _dtype(v), _vec3(v),
+                                      xs_struct(xs), _ptr(lam), rng_struct(seed, step),
+                                      pairs.struct(), _ptr(ws), int(ws.numel()), _ptr(st),
+                                      _stream(stream)),
+          "dsmc_select_pairs_sbt")
+    return ws
+
+
 def collide_ws(cap, v, extra=0):
     return workspace(lib().dsmc_collide_ws(int(cap), _dtype(v)) + int(extra), v.device)
 

@@ -53,7 +53,8 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     return U4{c0, c1, c2, c3};
 }
 
-enum : uint32_t { SLOT_CAND = 0, SLOT_COUNT = 1, SLOT_LAT0 = 2, SLOT_LAT1 = 3, SLOT_LAT2 = 4 };
+enum : uint32_t { SLOT_CAND = 0, SLOT_COUNT = 1, SLOT_LAT0 = 2, SLOT_LAT1 = 3, SLOT_LAT2 = 4,
+                  SLOT_SBT = 5 };
 
 __device__ __forceinline__ U4 draw(const dsmc_rng& rng, uint32_t c0, uint32_t cell, uint32_t slot)
 {

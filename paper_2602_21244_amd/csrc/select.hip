@@ -125,6 +125,49 @@ __device__ __forceinline__ bool cand_accept(const CandDraw& d, const V3<const T>
     return d.U < p;
 }
 
+// Simplified Bernoulli Trials (Stefanov 2011): trial t of cell k is the
+// particle in slot t; its partner is drawn uniformly among the m = N-1-t
+// later slots and the pair collides with probability P = m lambda_k sigma(g) g
+// (values above 1 act as 1 and are counted).
+__device__ __forceinline__ CandDraw sbt_draw(const int32_t* __restrict__ cell_start, int32_t k,
+                                             int32_t t, const dsmc_rng& rng, int32_t& m)
+{
+    const int32_t s0 = cell_start[k], N = cell_start[k + 1] - s0;
+    m = N - 1 - t;
+    const U4 r = draw(rng, (uint32_t)t, (uint32_t)k, SLOT_SBT);
+    const int32_t j = t + 1 + (int32_t)(((uint64_t)r.a * (uint64_t)m) >> 32);
+    return CandDraw{s0 + t, s0 + j, unif53(r.c, r.d)};
+}
+
+template <typename T>
+__device__ __forceinline__ bool sbt_accept(const CandDraw& d, int32_t m, const V3<const T>& v,
+                                           double lam, double C, double e, bool& clamped)
+{
+    const double dx = (double)v.x[d.i] - (double)v.x[d.j];
+    const double dy = (double)v.y[d.i] - (double)v.y[d.j];
+    const double dz = (double)v.z[d.i] - (double)v.z[d.j];
+    const double g2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                __dmul_rn(dz, dz));
+    const double g = sqrt(g2);
+    const double sg = __dmul_rn(C, (e == 1.0) ? g : pow(g, e));
+    const double P = __dmul_rn(__dmul_rn((double)m, lam), sg);
+    clamped = P > 1.0;
+    return d.U < P;
+}
+
+// Trials per cell of the SBT scheme: N - 1.
+__global__ void __launch_bounds__(256)
+k_trial_count(const int32_t* __restrict__ cell_start, int32_t n_cells, int32_t* __restrict__ cnt)
+{
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_cells;
+         k += gridDim.x * blockDim.x) {
+        const int32_t N = cell_start[k + 1] - cell_start[k];
+        cnt[k] = N >= 2 ? N - 1 : 0;
+    }
+}
+
+enum { SEL_NTC = 0, SEL_SBT = 1 };
+
 // Cell owning the first candidate of each chunk (one thread per cell).
 __global__ void __launch_bounds__(256)
 k_chunk_cells(int32_t n_cells, const int32_t* __restrict__ cand_off,
@@ -145,15 +188,17 @@ k_chunk_cells(int32_t n_cells, const int32_t* __restrict__ cand_off,
 // of accepted pairs of the chunk before cell k's first candidate (for every
 // cell whose candidates start inside the chunk; empty cells take the value of
 // the next candidate).
-template <typename T>
+template <typename T, int SEL>
 __global__ void __launch_bounds__(256)
 k_cand_decide(const int32_t* __restrict__ cell_start, int32_t n_cells,
               const int32_t* __restrict__ cand_off, const int64_t* __restrict__ n_use,
-              const int32_t* __restrict__ chunk_cell, const double* __restrict__ mom, double e,
-              dsmc_rng rng, V3<const T> v, int32_t* __restrict__ chunk_cnt,
-              int32_t* __restrict__ si, int32_t* __restrict__ sj, int32_t* __restrict__ sc,
-              int32_t* __restrict__ loc)
+              const int32_t* __restrict__ chunk_cell, const double* __restrict__ mom,
+              const double* __restrict__ lambda, double C, double e, dsmc_rng rng,
+              V3<const T> v, int32_t* __restrict__ chunk_cnt, int32_t* __restrict__ si,
+              int32_t* __restrict__ sj, int32_t* __restrict__ sc, int32_t* __restrict__ loc,
+              dsmc_status* st)
 {
+    int clamped_n = 0;
     const int64_t total = *n_use;
     const int64_t nch = (total + CAND_CHUNK - 1) / CAND_CHUNK;
     const int lane = threadIdx.x & 63;
@@ -181,14 +226,26 @@ k_cand_decide(const int32_t* __restrict__ cell_start, int32_t n_cells,
                 kk[u] = k;
             }
             CandDraw dr[CAND_GROUP];
+            int32_t mm[CAND_GROUP];
 #pragma unroll
-            for (int u = 0; u < CAND_GROUP; ++u)
-                dr[u] = val[u] ? cand_draw(cell_start, kk[u], (int32_t)(cc[u] - cand_off[kk[u]]), rng)
-                               : CandDraw{0, 0, 1.0};
+            for (int u = 0; u < CAND_GROUP; ++u) {
+                const int32_t t = (int32_t)(cc[u] - cand_off[kk[u]]);
+                mm[u] = 0;
+                if (!val[u]) dr[u] = CandDraw{0, 0, 1.0};
+                else if (SEL == SEL_NTC) dr[u] = cand_draw(cell_start, kk[u], t, rng);
+                else dr[u] = sbt_draw(cell_start, kk[u], t, rng, mm[u]);
+            }
             bool take[CAND_GROUP];
 #pragma unroll
-            for (int u = 0; u < CAND_GROUP; ++u)
-                take[u] = val[u] && cand_accept<T>(dr[u], v, 2.0 * mom[6 * (size_t)kk[u] + 4], e);
+            for (int u = 0; u < CAND_GROUP; ++u) {
+                if (SEL == SEL_NTC) {
+                    take[u] = val[u] && cand_accept<T>(dr[u], v, 2.0 * mom[6 * (size_t)kk[u] + 4], e);
+                } else {
+                    bool cl = false;
+                    take[u] = val[u] && sbt_accept<T>(dr[u], mm[u], v, lambda[kk[u]], C, e, cl);
+                    clamped_n += (val[u] && cl) ? 1 : 0;
+                }
+            }
 #pragma unroll
             for (int u = 0; u < CAND_GROUP; ++u) {
                 const uint64_t ab = __ballot(take[u]);
@@ -207,6 +264,13 @@ k_cand_decide(const int32_t* __restrict__ cell_start, int32_t n_cells,
             kw = __shfl(kk[CAND_GROUP - 1], 63, 64);
         }
         if (lane == 0) chunk_cnt[ch] = acc;
+    }
+    if (SEL == SEL_SBT && st) {
+        const int w = wave_sum_i(clamped_n);
+        if (lane == 0 && w > 0) {
+            atomicAdd(&st->prob_clamped, w);
+            atomicOr(&st->flags, (uint32_t)DSMC_ST_PROB_CLAMP);
+        }
     }
 }
 
@@ -311,7 +375,7 @@ static SelectWs select_ws_layout(void* base, int32_t n_cells, int64_t cap)
     return w;
 }
 
-template <typename T>
+template <typename T, int SEL>
 static int select_impl(int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v, XsLaw law,
                        const double* lambda, const double* mom, dsmc_rng rng,
                        dsmc_pairs pairs, void* ws, dsmc_status* st, hipStream_t s)
@@ -320,7 +384,10 @@ static int select_impl(int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v, 
     const int pb = persistent_blocks(256);
     int cb = (n_cells + 255) / 256;
     cb = cb < 1 ? 1 : (cb > pb ? pb : cb);
-    k_cand_count<<<cb, 256, 0, s>>>(cell_start, n_cells, lambda, mom, law, rng, w.cand_cnt);
+    if (SEL == SEL_NTC)
+        k_cand_count<<<cb, 256, 0, s>>>(cell_start, n_cells, lambda, mom, law, rng, w.cand_cnt);
+    else
+        k_trial_count<<<cb, 256, 0, s>>>(cell_start, n_cells, w.cand_cnt);
     DSMC_LAUNCH_CHECK("select:count");
     int rc = exclusive_scan_i32(w.cand_cnt, w.cand_off, n_cells, w.total, w.scan, s);
     if (rc) return rc;
@@ -328,9 +395,10 @@ static int select_impl(int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v, 
     DSMC_LAUNCH_CHECK("select:check");
     k_chunk_cells<<<cb, 256, 0, s>>>(n_cells, w.cand_off, w.n_use, w.chunk_cell);
     DSMC_LAUNCH_CHECK("select:chunk_cells");
-    k_cand_decide<T><<<pb, 256, 0, s>>>(cell_start, n_cells, w.cand_off, w.n_use, w.chunk_cell,
-                                        mom, law.e, rng, v3<const T>(v), w.chunk_cnt, w.si, w.sj,
-                                        w.sc, w.loc);
+    k_cand_decide<T, SEL><<<pb, 256, 0, s>>>(cell_start, n_cells, w.cand_off, w.n_use,
+                                             w.chunk_cell, mom, lambda, law.C, law.e, rng,
+                                             v3<const T>(v), w.chunk_cnt, w.si, w.sj, w.sc,
+                                             w.loc, st);
     DSMC_LAUNCH_CHECK("select:decide");
     rc = exclusive_scan_i32_dev(w.chunk_cnt, w.chunk_off, w.n_chunks, max_chunks(pairs.cap),
                                 w.scan, s);
@@ -374,10 +442,44 @@ extern "C" int dsmc_select_pairs_ntc(int32_t n_cells, const int32_t* cell_start,
     if (rc) return rc;
     hipStream_t s = as_stream(stream);
     if (dtype == DSMC_F64)
-        return select_impl<double>(n_cells, cell_start, v, law, lambda, mom, rng, pairs, ws, st, s);
+        return select_impl<double, SEL_NTC>(n_cells, cell_start, v, law, lambda, mom, rng, pairs,
+                                            ws, st, s);
     if (dtype == DSMC_F32)
-        return select_impl<float>(n_cells, cell_start, v, law, lambda, mom, rng, pairs, ws, st, s);
+        return select_impl<float, SEL_NTC>(n_cells, cell_start, v, law, lambda, mom, rng, pairs,
+                                           ws, st, s);
     return arg_error("dsmc_select_pairs_ntc: dtype %d", dtype);
+}
+
+extern "C" size_t dsmc_select_pairs_sbt_ws(int32_t n_cells, int64_t cap)
+{
+    return dsmc_select_pairs_ntc_ws(n_cells, cap);
+}
+
+extern "C" int dsmc_select_pairs_sbt(int32_t n_cells, const int32_t* cell_start, int32_t dtype,
+                                     dsmc_vec3 v, dsmc_xs xs, const double* lambda,
+                                     dsmc_rng rng, dsmc_pairs pairs, void* ws, size_t ws_bytes,
+                                     dsmc_status* st, dsmc_stream_t stream)
+{
+    if (n_cells < 1) return arg_error("dsmc_select_pairs_sbt: n_cells=%d", n_cells);
+    if (!cell_start || !lambda || !ws || !v.x || !v.y || !v.z || !pairs.off || !pairs.cnt ||
+        (pairs.cap > 0 && (!pairs.i || !pairs.j || !pairs.cell)))
+        return arg_error("dsmc_select_pairs_sbt: null pointer");
+    if (pairs.cap < 0 || pairs.cap >= (int64_t)INT32_MAX - 2)
+        return arg_error("dsmc_select_pairs_sbt: cap %lld out of range", (long long)pairs.cap);
+    if (ws_bytes < dsmc_select_pairs_sbt_ws(n_cells, pairs.cap))
+        return arg_error("dsmc_select_pairs_sbt: workspace %zu < %zu", ws_bytes,
+                         dsmc_select_pairs_sbt_ws(n_cells, pairs.cap));
+    XsLaw law;
+    int rc = xs_law(xs, &law);
+    if (rc) return rc;
+    hipStream_t s = as_stream(stream);
+    if (dtype == DSMC_F64)
+        return select_impl<double, SEL_SBT>(n_cells, cell_start, v, law, lambda, nullptr, rng,
+                                            pairs, ws, st, s);
+    if (dtype == DSMC_F32)
+        return select_impl<float, SEL_SBT>(n_cells, cell_start, v, law, lambda, nullptr, rng,
+                                           pairs, ws, st, s);
+    return arg_error("dsmc_select_pairs_sbt: dtype %d", dtype);
 }
 
 namespace dsmc {

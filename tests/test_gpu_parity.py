@@ -162,6 +162,60 @@ def test_select_overflow(orc, dev, api):
     assert int(pairs.cnt.sum()) == 0
 
 
+@pytest.mark.parametrize("case", ["vhs64", "vhs32", "const64_clamped", "cylinder32"])
+def test_select_sbt_bitexact(orc, dev, api, case):
+    """Simplified Bernoulli Trials: pair lists and the clamp count bit-exact."""
+    say("select sbt case", case)
+    scale = 0.25
+    if case == "vhs64":
+        pop, dt = W.vhs_argon_1d(seed=1), torch.float64
+    elif case == "vhs32":
+        pop, dt = W.ragged_population(8, 300, 150), torch.float32
+    elif case == "const64_clamped":
+        pop, dt, scale = W.ragged_population(9, 200, 200, xs="const"), torch.float64, 1.0
+    else:
+        pop, dt = W.cylinder_grid(seed=9, order="shuffled", scale=0.03), torch.float32
+    cs, perm, vs, st = _gpu_sort(api, dev, pop, dt)
+    lam_np = pop.lam * scale
+    v64 = vs.cpu().numpy().astype(np.float64)
+    sel = orc.select_sbt(cs.cpu().numpy(), v64, pop.xs, lam_np, 11, 3)
+    pairs = api.PairList(pop.n_cells, int(sel["n_cand"]) + 64, dev)
+    api.select_pairs_sbt(cs, vs, pop.xs, torch.as_tensor(lam_np, device=dev), 11, 3, pairs, st=st)
+    s = api.read_status(st)
+    n = int(sel["pair_cnt"].sum())
+    say(f"  {sel['n_cand']} trials, {n} pairs, {sel['n_clamped']} clamped")
+    assert s.n_cand == sel["n_cand"] and s.n_pairs == n
+    assert s.prob_clamped == sel["n_clamped"]
+    assert bool(s.flags & api.L.ST_PROB_CLAMP) == (sel["n_clamped"] > 0)
+    assert np.array_equal(pairs.cnt.cpu().numpy(), sel["pair_cnt"])
+    assert np.array_equal(pairs.off.cpu().numpy(), sel["pair_off"])
+    for name in ("i", "j", "cell"):
+        assert np.array_equal(getattr(pairs, name)[:n].cpu().numpy(), sel["pair_" + name]), name
+    if case == "const64_clamped":
+        assert sel["n_clamped"] > 0
+
+
+def test_sbt_step_and_overflow(orc, dev, api):
+    say("sbt step")
+    pop = W.ragged_population(15, 250, 120, empty_frac=0.1)
+    cs, perm, vs, st = _gpu_sort(api, dev, pop, torch.float64)
+    lam_np = pop.lam * 0.25
+    lam = torch.as_tensor(lam_np, device=dev)
+    v_np = vs.cpu().numpy()
+    small = api.PairList(pop.n_cells, 10, dev)
+    api.select_pairs_sbt(cs, vs, pop.xs, lam, 4, 2, small, st=st)
+    s = api.read_status(st)
+    assert s.flags & api.L.ST_PAIR_OVERFLOW and int(small.cnt.sum()) == 0
+    pairs = api.PairList(pop.n_cells, 1 << 20, dev)
+    api.select_pairs_sbt(cs, vs, pop.xs, lam, 4, 2, pairs)
+    api.collide_vhs(vs, pairs, 4, 2)
+    ref, info = orc.step(cs.cpu().numpy(), v_np, pop.xs, lam_np, 4, 2, rule="vhs",
+                         selection="sbt")
+    err = np.max(np.abs(vs.cpu().numpy() - ref)) / math.sqrt(W.KB * 300 / W.AR_MASS)
+    say(f"  {int(info['sel']['pair_cnt'].sum())} pairs, velocity rel err {err:.2e}")
+    assert err < 1e-12
+
+
 # ---------------------------------------------------------------------------
 # isotropic collide + moment matching
 # ---------------------------------------------------------------------------
