@@ -381,6 +381,50 @@ def rotate(vr, chi_, xi):
 
 
 # ---------------------------------------------------------------------------
+# Chapman-Enskog viscosity from the deflection angle (section "Macroscopic
+# Validation: Viscosity and Transport Coefficients").
+# ---------------------------------------------------------------------------
+def transport_q2(P, E_kelvin, b_cut, n_panels=256, n_gl=8, n_threads=8):
+    """Q2(E) = 2 pi int_0^b_cut (1 - cos^2 chi(b, E)) b db in m^2 (eq.
+    transport cross-section), composite Gauss-Legendre in b: n_panels equal
+    panels of n_gl nodes.  E in K (E_r / k_B), b_cut in m."""
+    x, w = np.polynomial.legendre.leggauss(n_gl)
+    edges = np.linspace(0.0, b_cut, n_panels + 1)
+    mid = 0.5 * (edges[:-1] + edges[1:])
+    half = 0.5 * np.diff(edges)
+    b = (mid[:, None] + half[:, None] * x[None, :]).ravel()
+    wb = (half[:, None] * w[None, :]).ravel()
+    m_red = 1.0          # chi depends on E only: any reduced mass with g = sqrt(2 E k / m_red)
+    out = []
+    for E in np.atleast_1d(E_kelvin):
+        g = np.full(b.shape, math.sqrt(2.0 * E * KB / m_red))
+        ch, _ = chi_batch(P, b, g, m_red, n_threads=n_threads)
+        out.append(2.0 * math.pi * np.sum(wb * (1.0 - np.cos(ch) ** 2) * b))
+    return np.array(out)
+
+
+def collision_integral(P, T, b_cut, n_lag=24, printed=False, **kw):
+    """Omega(T) in m^2.  Standard Chapman-Cowling average (reading of the
+    printed average): Omega = 1/(4 (kT)^4) int E^3 Q2(E) exp(-E/kT) dE
+    = 1/4 int x^3 e^-x Q2(x kT) dx (generalised Gauss-Laguerre, alpha = 3),
+    which makes the hard-sphere viscosity come out right.  printed=True:
+    the average as printed, 1/(2 (kT)^3) int E^2 Q2 exp(-E/kT) dE (alpha = 2)."""
+    from scipy.special import roots_genlaguerre
+    alpha, scale = (2, 0.5) if printed else (3, 0.25)
+    x, w = roots_genlaguerre(n_lag, alpha)
+    out = []
+    for t in np.atleast_1d(T):
+        q = transport_q2(P, x * t, b_cut, **kw)
+        out.append(scale * np.sum(w * q))
+    return np.array(out)
+
+
+def viscosity_ce(omega, T, m):
+    """mu = 5/16 sqrt(pi m k T) / Omega (eq. chapman_enskog), Pa s."""
+    return 5.0 / 16.0 * np.sqrt(math.pi * m * KB * np.asarray(T, np.float64)) / omega
+
+
+# ---------------------------------------------------------------------------
 # Conditional MLP, projection, loss and gradients (sections "Cell-Based
 # Neural Collision Operator" and "Hard Conservation via Projection").
 # ---------------------------------------------------------------------------
