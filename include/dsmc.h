@@ -367,6 +367,30 @@ int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, int32_t dtyp
 int dsmc_set_block_threshold(int32_t pairs);
 int32_t dsmc_get_block_threshold(void);
 
+/* Chapman-Enskog viscosity from the deflection angle (section "Macroscopic
+ * Validation: Viscosity and Transport Coefficients", eq. chapman_enskog):
+ *   Q2(E) = 2 pi int_0^b_cut (1 - cos^2 chi(b, E)) b db   [m^2]
+ * by composite Gauss-Legendre in b (n_panels equal panels of n_gl nodes, chi
+ * by the quadrature of dsmc_deflect_jager in FP64); E in K (E_r / k_B),
+ * b_cut in m.  ws: dsmc_transport_q2_ws bytes.  Root failures count in st. */
+size_t dsmc_transport_q2_ws(int64_t n_E, int32_t n_panels, int32_t n_gl);
+int dsmc_transport_q2(int64_t n_E, const double* E_kelvin, double b_cut, int32_t n_panels,
+                      int32_t n_gl, const dsmc_potential* pot, dsmc_quad quad, double* Q,
+                      void* ws, size_t ws_bytes, dsmc_status* st, dsmc_stream_t stream);
+/* Omega(T) and mu(T) = 5/16 sqrt(pi m k_B T) / Omega for n_T temperatures
+ * (device arrays, K; m the atomic mass in kg).  DSMC_CE_STANDARD:
+ * Omega = 1/(4 (kT)^4) int E^3 Q2 exp(-E/kT) dE, the Chapman-Cowling average
+ * (reading of the printed average; it gives the hard-sphere viscosity);
+ * DSMC_CE_AS_PRINTED: Omega = 1/(2 (kT)^3) int E^2 Q2 exp(-E/kT) dE.  The
+ * Maxwellian average by n_lag-point generalised Gauss-Laguerre in E/kT.
+ * ws: dsmc_viscosity_ce_ws bytes. */
+enum { DSMC_CE_STANDARD = 0, DSMC_CE_AS_PRINTED = 1 };
+size_t dsmc_viscosity_ce_ws(int32_t n_T, int32_t n_panels, int32_t n_gl, int32_t n_lag);
+int dsmc_viscosity_ce(int32_t n_T, const double* T, double m, double b_cut, int32_t n_panels,
+                      int32_t n_gl, int32_t n_lag, int32_t mode, const dsmc_potential* pot,
+                      dsmc_quad quad, double* omega, double* mu, void* ws, size_t ws_bytes,
+                      dsmc_status* st, dsmc_stream_t stream);
+
 /* ---------------------------------------------------------------------- */
 /* Neural deflection-angle table (sections "Neural Network Architecture",
  * "Neural Surrogate Training" and "Runtime Acceleration via Neural Table

@@ -16,6 +16,7 @@ ACT_SILU, ACT_RELU = 0, 1
 SCHED_AUTO, SCHED_LANE, SCHED_BLOCK, SCHED_DEFER, SCHED_WAVE = 0, 1, 2, 3, 4
 APPLY_DIRECTIONS, APPLY_ANGLES = 0, 1
 MM_CAPTURE, MM_APPLY, MM_APPLY_LITERAL = 0, 1, 2
+CE_STANDARD, CE_AS_PRINTED = 0, 1
 
 
 class Vec3(C.Structure):
@@ -126,6 +127,12 @@ SIGNATURES = {
     "dsmc_chi_table_build": (C.c_int, [C.POINTER(Anet), C.POINTER(ChiTable), _vp, _sz, _vp]),
     "dsmc_collide_table": (C.c_int, [C.POINTER(ChiTable), _i32, _i32, Vec3, Pairs, Rng, _d, _i32,
                                      _vp, _sz, _vp]),
+    "dsmc_transport_q2_ws": (_sz, [_i64, _i32, _i32]),
+    "dsmc_transport_q2": (C.c_int, [_i64, _vp, _d, _i32, _i32, C.POINTER(Potential), Quad, _vp,
+                                    _vp, _sz, _vp, _vp]),
+    "dsmc_viscosity_ce_ws": (_sz, [_i32, _i32, _i32, _i32]),
+    "dsmc_viscosity_ce": (C.c_int, [_i32, _vp, _d, _d, _i32, _i32, _i32, _i32,
+                                    C.POINTER(Potential), Quad, _vp, _vp, _vp, _sz, _vp, _vp]),
     "dsmc_set_block_threshold": (C.c_int, [_i32]),
     "dsmc_get_block_threshold": (_i32, []),
 }

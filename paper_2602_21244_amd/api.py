@@ -353,6 +353,32 @@ def harvest_rows(vr, xi, z, sigma_v, b_max, m_red, pot, quad=None, st=None, stre
     return x, g, tgt, chi
 
 
+def transport_q2(E_kelvin, b_cut, pot, n_panels=256, n_gl=8, quad=None, st=None, stream=None):
+    n = int(E_kelvin.numel())
+    Q = torch.empty(n, dtype=torch.float64, device=E_kelvin.device)
+    ws = workspace(lib().dsmc_transport_q2_ws(n, int(n_panels), int(n_gl)), E_kelvin.device)
+    q = quad if quad is not None else quad_struct()
+    check(lib().dsmc_transport_q2(n, _ptr(E_kelvin), float(b_cut), int(n_panels), int(n_gl),
+                                  C.byref(pot), q, _ptr(Q), _ptr(ws), int(ws.numel()), _ptr(st),
+                                  _stream(stream)),
+          "dsmc_transport_q2")
+    return Q
+
+
+def viscosity_ce(T, m, b_cut, pot, n_panels=256, n_gl=8, n_lag=16, mode=L.CE_STANDARD,
+                 quad=None, st=None, stream=None):
+    n = int(T.numel())
+    omega = torch.empty(n, dtype=torch.float64, device=T.device)
+    mu = torch.empty_like(omega)
+    ws = workspace(lib().dsmc_viscosity_ce_ws(n, int(n_panels), int(n_gl), int(n_lag)), T.device)
+    q = quad if quad is not None else quad_struct()
+    check(lib().dsmc_viscosity_ce(n, _ptr(T), float(m), float(b_cut), int(n_panels), int(n_gl),
+                                  int(n_lag), int(mode), C.byref(pot), q, _ptr(omega), _ptr(mu),
+                                  _ptr(ws), int(ws.numel()), _ptr(st), _stream(stream)),
+          "dsmc_viscosity_ce")
+    return omega, mu
+
+
 def set_block_threshold(pairs):
     check(lib().dsmc_set_block_threshold(int(pairs)), "dsmc_set_block_threshold")
 

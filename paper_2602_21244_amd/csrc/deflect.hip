@@ -674,3 +674,244 @@ extern "C" int dsmc_harvest_rows(int64_t B, const double* vr, const double* xi, 
     DSMC_LAUNCH_CHECK("harvest_rows");
     return DSMC_OK;
 }
+
+// ------------------------------------------------------------------------
+// Chapman-Enskog viscosity (section "Macroscopic Validation: Viscosity and
+// Transport Coefficients"): transport cross-section
+//   Q2(E) = 2 pi int_0^b_cut (1 - cos^2 chi) b db
+// by composite Gauss-Legendre in b (chi from the quadrature above, FP64, the
+// wave-cooperative refinement included), the Maxwellian average by
+// generalised Gauss-Laguerre in x = E / kT, and mu = 5/16 sqrt(pi m k T) / Omega.
+// ------------------------------------------------------------------------
+namespace dsmc {
+
+constexpr int LAG_MAX = 64;
+
+struct LagRule {
+    int n;
+    double x[LAG_MAX];
+    double w[LAG_MAX];
+};
+
+// Generalised Gauss-Laguerre nodes and weights (weight x^alpha e^-x): nodes
+// are the eigenvalues of the symmetric tridiagonal Jacobi matrix (diagonal
+// 2k + alpha + 1, off-diagonal sqrt(k (k + alpha))), found by cyclic Jacobi
+// rotations (Golub-Welsch); weights from the closed form in L_{n+1}.
+static int make_laguerre(int n, double alpha, LagRule* L)
+{
+    if (n < 1 || n > LAG_MAX) return arg_error("laguerre: n %d not in [1, %d]", n, LAG_MAX);
+    std::vector<double> A((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        A[(size_t)k * n + k] = 2.0 * k + alpha + 1.0;
+        if (k > 0) {
+            const double b = sqrt(k * (k + alpha));
+            A[(size_t)k * n + k - 1] = b;
+            A[(size_t)(k - 1) * n + k] = b;
+        }
+    }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += A[(size_t)p * n + q] * A[(size_t)p * n + q];
+        if (off < 1e-30) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (fabs(apq) < 1e-300) continue;
+                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                const double theta = 0.5 * (aqq - app) / apq;
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {  // columns p, q
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - s * akq;
+                    A[(size_t)k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, q
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - s * aqk;
+                    A[(size_t)q * n + k] = s * apk + c * aqk;
+                }
+            }
+    }
+    // weights from the closed form Gamma(n+alpha+1) x / (n! (n+1)^2 L_{n+1}(x)^2)
+    // (more accurate on the tiny weights than squared eigenvector components)
+    L->n = n;
+    const double lg = lgamma(n + alpha + 1.0) - lgamma(n + 1.0) - 2.0 * log(n + 1.0);
+    for (int k = 0; k < n; ++k) {
+        const double x = A[(size_t)k * n + k];
+        double p0 = 1.0, p1 = 1.0 + alpha - x;
+        for (int j = 2; j <= n + 1; ++j) {
+            const double p2 = ((2.0 * j - 1.0 + alpha - x) * p1 - (j - 1.0 + alpha) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        L->x[k] = x;
+        L->w[k] = exp(lg) * x / (p1 * p1);
+    }
+    return DSMC_OK;
+}
+
+// One term of the b integral: node j of energy i (b in Angstrom).
+__global__ void __launch_bounds__(256)
+k_q2_terms(int64_t n_items, int n_b, const double* __restrict__ E_kelvin, double b_cut_A,
+           int n_panels, GLRule bgl, Pot P, QuadCfg q, GLRule gl, double* __restrict__ terms,
+           dsmc_status* st)
+{
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < n_items;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t it = base + (threadIdx.x & 63);
+        const bool active = it < n_items;
+        const int64_t i = active ? it / n_b : 0;
+        const int j = active ? (int)(it % n_b) : 0;
+        const int pnl = j / bgl.n, node = j % bgl.n;
+        const double h = b_cut_A / n_panels;
+        const double b = h * (pnl + bgl.t[node]);
+        const double E = active ? E_kelvin[i] : 1.0;
+        double c = chi_quad_wave<double>(P, q, gl, b, E, active);
+        if (!active) continue;
+        if (c != c) {
+            if (st) {
+                atomicAdd(&st->root_fail, 1);
+                atomicOr(&st->flags, (uint32_t)DSMC_ST_ROOT_FAIL);
+            }
+            c = 0.0;
+        }
+        const double cc = cos(c);
+        terms[it] = h * bgl.w[node] * (1.0 - cc * cc) * b;
+    }
+}
+
+// Q2[i] = 2 pi sum_j terms[i][j] (fixed order), in m^2.
+__global__ void __launch_bounds__(256)
+k_q2_sum(int64_t n_E, int n_b, const double* __restrict__ terms, double* __restrict__ Q)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_E;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < n_b; ++j) s += terms[i * n_b + j];
+        Q[i] = 2.0 * 3.14159265358979323846 * s * 1e-20;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_ce_energies(int n_T, const double* __restrict__ T, LagRule lag, double* __restrict__ E)
+{
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_T * lag.n;
+         q += gridDim.x * blockDim.x)
+        E[q] = lag.x[q % lag.n] * T[q / lag.n];
+}
+
+__global__ void __launch_bounds__(256)
+k_ce_finish(int n_T, const double* __restrict__ T, LagRule lag, double scale, double m,
+            const double* __restrict__ Q, double* __restrict__ omega, double* __restrict__ mu)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_T; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < lag.n; ++k) s += lag.w[k] * Q[(int64_t)i * lag.n + k];
+        const double om = scale * s;
+        omega[i] = om;
+        mu[i] = 5.0 / 16.0 * sqrt(3.14159265358979323846 * m * KB * T[i]) / om;
+    }
+}
+
+static int q2_impl(int64_t n_E, const double* E, double b_cut, int n_panels, int n_gl,
+                   const dsmc_potential* pot, const dsmc_quad& quad, double* Q, void* ws,
+                   dsmc_status* st, hipStream_t s)
+{
+    Pot P;
+    int rc = get_pot(pot, &P);
+    if (rc) return rc;
+    QuadCfg q;
+    GLRule gl, bgl;
+    rc = make_cfg(quad, &q, &gl);
+    if (rc) return rc;
+    rc = make_gl(n_gl, &bgl);
+    if (rc) return rc;
+    const int n_b = n_panels * n_gl;
+    const int64_t items = n_E * (int64_t)n_b;
+    double* terms = static_cast<double*>(ws);
+    const int pb = persistent_blocks(256);
+    int64_t blocks = (items + 255) / 256;
+    if (blocks > pb) blocks = pb;
+    k_q2_terms<<<(int)(blocks < 1 ? 1 : blocks), 256, 0, s>>>(items, n_b, E, b_cut * 1e10,
+                                                              n_panels, bgl, P, q, gl, terms, st);
+    DSMC_LAUNCH_CHECK("q2:terms");
+    k_q2_sum<<<(int)((n_E + 255) / 256), 256, 0, s>>>(n_E, n_b, terms, Q);
+    DSMC_LAUNCH_CHECK("q2:sum");
+    return DSMC_OK;
+}
+
+static int check_q2_args(const char* who, double b_cut, int n_panels, int n_gl)
+{
+    if (!(b_cut > 0)) return arg_error("%s: b_cut must be > 0", who);
+    if (n_panels < 1 || n_panels > (1 << 20)) return arg_error("%s: n_panels %d", who, n_panels);
+    if (n_gl < 2 || n_gl > GL_MAX) return arg_error("%s: n_gl %d", who, n_gl);
+    return DSMC_OK;
+}
+
+}  // namespace dsmc
+
+extern "C" size_t dsmc_transport_q2_ws(int64_t n_E, int32_t n_panels, int32_t n_gl)
+{
+    if (n_E < 0 || n_panels < 1 || n_gl < 1) return 0;
+    return align_up(sizeof(double) * (size_t)n_E * n_panels * n_gl) + 256;
+}
+
+extern "C" int dsmc_transport_q2(int64_t n_E, const double* E_kelvin, double b_cut,
+                                 int32_t n_panels, int32_t n_gl, const dsmc_potential* pot,
+                                 dsmc_quad quad, double* Q, void* ws, size_t ws_bytes,
+                                 dsmc_status* st, dsmc_stream_t stream)
+{
+    int rc = check_q2_args("dsmc_transport_q2", b_cut, n_panels, n_gl);
+    if (rc) return rc;
+    if (n_E < 0) return arg_error("dsmc_transport_q2: n_E < 0");
+    if (n_E == 0) return DSMC_OK;
+    if (!E_kelvin || !Q || !ws) return arg_error("dsmc_transport_q2: null pointer");
+    if (ws_bytes < dsmc_transport_q2_ws(n_E, n_panels, n_gl))
+        return arg_error("dsmc_transport_q2: workspace too small");
+    return q2_impl(n_E, E_kelvin, b_cut, n_panels, n_gl, pot, quad, Q, ws, st, as_stream(stream));
+}
+
+extern "C" size_t dsmc_viscosity_ce_ws(int32_t n_T, int32_t n_panels, int32_t n_gl, int32_t n_lag)
+{
+    if (n_T < 0 || n_lag < 1) return 0;
+    const int64_t nE = (int64_t)n_T * n_lag;
+    return 2 * align_up(sizeof(double) * (size_t)nE) + dsmc_transport_q2_ws(nE, n_panels, n_gl);
+}
+
+extern "C" int dsmc_viscosity_ce(int32_t n_T, const double* T, double m, double b_cut,
+                                 int32_t n_panels, int32_t n_gl, int32_t n_lag, int32_t mode,
+                                 const dsmc_potential* pot, dsmc_quad quad, double* omega,
+                                 double* mu, void* ws, size_t ws_bytes, dsmc_status* st,
+                                 dsmc_stream_t stream)
+{
+    int rc = check_q2_args("dsmc_viscosity_ce", b_cut, n_panels, n_gl);
+    if (rc) return rc;
+    if (n_T < 0 || !(m > 0)) return arg_error("dsmc_viscosity_ce: n_T >= 0 and m > 0 required");
+    if (mode != DSMC_CE_STANDARD && mode != DSMC_CE_AS_PRINTED)
+        return arg_error("dsmc_viscosity_ce: mode %d", mode);
+    if (n_T == 0) return DSMC_OK;
+    if (!T || !omega || !mu || !ws) return arg_error("dsmc_viscosity_ce: null pointer");
+    if (ws_bytes < dsmc_viscosity_ce_ws(n_T, n_panels, n_gl, n_lag))
+        return arg_error("dsmc_viscosity_ce: workspace too small");
+    LagRule lag;
+    const bool printed = mode == DSMC_CE_AS_PRINTED;
+    rc = make_laguerre(n_lag, printed ? 2.0 : 3.0, &lag);
+    if (rc) return rc;
+    hipStream_t s = as_stream(stream);
+    const int64_t nE = (int64_t)n_T * n_lag;
+    uint8_t* w = static_cast<uint8_t*>(ws);
+    double* E = reinterpret_cast<double*>(w);
+    w += align_up(sizeof(double) * (size_t)nE);
+    double* Q = reinterpret_cast<double*>(w);
+    w += align_up(sizeof(double) * (size_t)nE);
+    k_ce_energies<<<(int)((nE + 255) / 256), 256, 0, s>>>(n_T, T, lag, E);
+    DSMC_LAUNCH_CHECK("ce:energies");
+    rc = q2_impl(nE, E, b_cut, n_panels, n_gl, pot, quad, Q, w, st, s);
+    if (rc) return rc;
+    k_ce_finish<<<(n_T + 255) / 256, 256, 0, s>>>(n_T, T, lag, printed ? 0.5 : 0.25, m, Q, omega,
+                                                  mu);
+    DSMC_LAUNCH_CHECK("ce:finish");
+    return DSMC_OK;
+}
