@@ -149,7 +149,7 @@ def main():
         return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
 
     def step(rule, ev=None):
-        """One collision step; ev: list of 7 events bracketing the stages."""
+        """One collision step; ev: list of 6 events bracketing the stages."""
         if ev: ev[0].record(stream)
         do_sort()
         if ev: ev[1].record(stream)
@@ -169,18 +169,17 @@ def main():
                               schedule=L.SCHED_DEFER, ws=col_ws, st=st)
             kind = L.APPLY_ANGLES
         if ev: ev[4].record(stream)
-        api.apply_pairs(v, pairs, kind, col_ws)
+        # Phase B and the cell-wise moment matching in one pass
+        api.apply_pairs_match(cs, v, pairs, kind, mom, col_ws, mode=L.MM_APPLY, st=st)
         if ev: ev[5].record(stream)
-        api.moment_match(cs, v, mom, L.MM_APPLY, pair_cnt=pairs.cnt, st=st)
-        if ev: ev[6].record(stream)
 
-    names = ["sort", "moments", "select", "phaseA", "phaseB", "match"]
+    names = ["sort", "moments", "select", "phaseA", "phaseB_match"]
 
     def run(rule, warm, steps):
         for _ in range(warm):
             step(rule)
         torch.cuda.synchronize()
-        evs = [stage_events(7) for _ in range(steps)]
+        evs = [stage_events(6) for _ in range(steps)]
         t_start = time.perf_counter()
         for q in range(steps):
             step(rule, evs[q])
@@ -188,7 +187,7 @@ def main():
         wall = time.perf_counter() - t_start
         per = {nm: float(np.mean([evs[q][s].elapsed_time(evs[q][s + 1]) for q in range(steps)]))
                for s, nm in enumerate(names)}
-        tot = float(np.mean([evs[q][0].elapsed_time(evs[q][6]) for q in range(steps)]))
+        tot = float(np.mean([evs[q][0].elapsed_time(evs[q][5]) for q in range(steps)]))
         return wall, tot, per
 
     api.status_clear(st)
@@ -257,7 +256,7 @@ def main():
     achieved = n_pairs * MLP_FLOP_PER_PAIR / t_mlp
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_BF16,
-                "traffic": counter_traffic("k_mlp_bf16<128, true, float, 0, false, 1>"),
+                "traffic": counter_traffic("k_mlp_bf16<128, true, float, 0, false, 1, 512>"),
                 "kernel": "k_mlp_bf16 (Phase A of dsmc_neural_collide)",
                 "algorithmic_flop_per_pair": MLP_FLOP_PER_PAIR}
     sort_bytes = n * (4 + 4 + 12 + 12 + 4)  # cell id twice, v read + write, perm

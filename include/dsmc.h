@@ -257,6 +257,22 @@ int dsmc_collide_vhs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pai
 int dsmc_apply_pairs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pairs, int32_t kind,
                      int32_t schedule, void* ws, size_t ws_bytes, dsmc_stream_t stream);
 
+/* Phase B fused with the cell-wise moment matching (section "Optional
+ * Cell-Wise Energy Drift Correction", eq. cell_energy_clamp): the same result,
+ * bit for bit, as dsmc_apply_pairs(kind, AUTO) followed by
+ * dsmc_moment_match(mode, pair_cnt = pairs.cnt), with one read and one write
+ * of each colliding cell's velocities.  cell_start[n_cells+1] as from
+ * dsmc_sort_cells (every pair of cell k lies in [cell_start[k],
+ * cell_start[k+1])); mom[6*n_cells] from dsmc_moment_match(CAPTURE) on the
+ * pre-collision velocities; mode DSMC_MM_APPLY or DSMC_MM_APPLY_LITERAL.
+ * Cells without pairs are left untouched; skipped cells (non-positive or
+ * non-finite post value) count in st->mm_skipped (st may be NULL).
+ * ws: the workspace the DEFER collide call filled (dsmc_collide_ws). */
+int dsmc_apply_pairs_match(int32_t n_cells, const int32_t* cell_start, int32_t dtype,
+                           dsmc_vec3 v, dsmc_pairs pairs, int32_t kind, const double* mom,
+                           int32_t mode, void* ws, size_t ws_bytes, dsmc_status* st,
+                           dsmc_stream_t stream);
+
 /* Ab initio deflection angle by quadrature (section "Computational
  * Implementation: The Exact vs. Neural Paradigm"): for each of n pairs,
  * E = m_red g^2 / 2, r_min = largest root of 1 - b^2/r^2 - V(r)/E, and

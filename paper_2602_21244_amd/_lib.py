@@ -96,6 +96,8 @@ SIGNATURES = {
     "dsmc_collide_ws": (_sz, [_i64, _i32]),
     "dsmc_collide_vhs": (C.c_int, [_i32, _i32, Vec3, Pairs, Rng, _i32, _vp, _sz, _vp]),
     "dsmc_apply_pairs": (C.c_int, [_i32, _i32, Vec3, Pairs, _i32, _i32, _vp, _sz, _vp]),
+    "dsmc_apply_pairs_match": (C.c_int, [_i32, _vp, _i32, Vec3, Pairs, _i32, _vp, _i32, _vp, _sz,
+                                         _vp, _vp]),
     "dsmc_deflect_jager": (C.c_int, [_i64, _i32, _vp, _vp, _vp, _d, C.POINTER(Potential), Quad,
                                      _i32, _vp, _vp]),
     "dsmc_collide_jager": (C.c_int, [_i32, _i32, Vec3, Pairs, Rng, _d, _d, C.POINTER(Potential),

@@ -237,6 +237,17 @@ def apply_pairs(v, pairs, kind, ws, schedule=L.SCHED_AUTO, stream=None):
           "dsmc_apply_pairs")
 
 
+def apply_pairs_match(cell_start, v, pairs, kind, mom, ws, mode=L.MM_APPLY, st=None,
+                      stream=None):
+    n_cells = int(cell_start.numel()) - 1
+    if n_cells != int(pairs.off.numel()):
+        raise ValueError("apply_pairs_match: cell_start and pairs cover different cell counts")
+    check(lib().dsmc_apply_pairs_match(n_cells, _ptr(cell_start), _dtype(v), _vec3(v),
+                                       pairs.struct(), int(kind), _ptr(mom), int(mode), _ptr(ws),
+                                       int(ws.numel()), _ptr(st), _stream(stream)),
+          "dsmc_apply_pairs_match")
+
+
 def deflect_jager(b, g, m_red, pot, quad=None, fold=False, st=None, stream=None):
     chi = torch.empty_like(g)
     q = quad if quad is not None else quad_struct()

@@ -163,7 +163,7 @@ __device__ __forceinline__ bool any_pending(uint32_t pend)
 
 // One cell (c pairs from offset o; pair slots within [lo, lo + span)) on NT
 // threads with LDS tables lx/ly/lz/first of at least span entries.
-template <typename T, int RULE, int NT, int PPL>
+template <typename T, int RULE, int NT, int PPL, bool WB = true>
 __device__ __forceinline__ void cell_rounds_lds(const PairsView& pr, V3<T> v, const PairBuf<T>& d,
                                                 int32_t c, int64_t o, int32_t lo, int32_t span,
                                                 const int32_t (&pa_g)[PPL],
@@ -211,10 +211,12 @@ __device__ __forceinline__ void cell_rounds_lds(const PairsView& pr, V3<T> v, co
         }
         ++r;
     }
-    for (int32_t q = t; q < span; q += NT) {
-        v.x[lo + q] = lx[q];
-        v.y[lo + q] = ly[q];
-        v.z[lo + q] = lz[q];
+    if (WB) {
+        for (int32_t q = t; q < span; q += NT) {
+            v.x[lo + q] = lx[q];
+            v.y[lo + q] = ly[q];
+            v.z[lo + q] = lz[q];
+        }
     }
     __syncthreads();
 }
@@ -424,6 +426,189 @@ k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min
     }
 }
 
+// ------------------------------------------------------------------------
+// Phase B fused with the cell-wise moment matching (eq. cell_energy_clamp):
+// the whole cell [s0, s0 + N) is staged in LDS, its pairs applied in
+// dependency rounds, then the first wave forms the cell's post-collision sums
+// with the same lane assignment, loop order and butterfly as the separate
+// matching kernel (so the result is bit-identical to Phase B followed by
+// dsmc_moment_match(APPLY)) and writes the matched velocities once.
+// ------------------------------------------------------------------------
+struct MatchArgs {
+    const int32_t* cell_start;
+    const double* mom;
+    int literal;
+    dsmc_status* st;
+};
+
+template <typename T, typename LD>
+__device__ __forceinline__ void match_cell(LD ld, int32_t N, const double* m, int literal,
+                                           V3<T> v, int32_t s0, dsmc_status* st)
+{
+    const int lane = threadIdx.x & 63;
+    double sx = 0, sy = 0, sz = 0;
+    for (int32_t q = lane; q < N; q += 64) {
+        sx += (double)ld.x(q);
+        sy += (double)ld.y(q);
+        sz += (double)ld.z(q);
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    sz = wave_sum(sz);
+    const double ux = sx / N, uy = sy / N, uz = sz / N;
+    double S = 0, E = 0;
+    for (int32_t q = lane; q < N; q += 64) {
+        const double x = ld.x(q), y = ld.y(q), z = ld.z(q);
+        const double dx = x - ux, dy = y - uy, dz = z - uz;
+        S += dx * dx + dy * dy + dz * dz;
+        E += x * x + y * y + z * z;
+    }
+    S = wave_sum(S);
+    E = wave_sum(E);
+    const double post = literal ? E : S;
+    if (!(post > 0.0) || !isfinite(post)) {
+        if (lane == 0 && st) atomicAdd(&st->mm_skipped, 1);
+        for (int32_t q = lane; q < N; q += 64) {
+            v.x[s0 + q] = ld.x(q);
+            v.y[s0 + q] = ld.y(q);
+            v.z[s0 + q] = ld.z(q);
+        }
+        return;
+    }
+    const double alpha = sqrt((literal ? m[5] : m[3]) / post);
+    for (int32_t q = lane; q < N; q += 64) {
+        const int32_t s = s0 + q;
+        if (literal) {
+            v.x[s] = (T)(alpha * (double)ld.x(q));
+            v.y[s] = (T)(alpha * (double)ld.y(q));
+            v.z[s] = (T)(alpha * (double)ld.z(q));
+        } else {
+            v.x[s] = (T)(m[0] + alpha * ((double)ld.x(q) - ux));
+            v.y[s] = (T)(m[1] + alpha * ((double)ld.y(q) - uy));
+            v.z[s] = (T)(m[2] + alpha * ((double)ld.z(q) - uz));
+        }
+    }
+}
+
+template <typename T> struct LdsCell {
+    const T *px, *py, *pz;
+    __device__ T x(int32_t q) const { return px[q]; }
+    __device__ T y(int32_t q) const { return py[q]; }
+    __device__ T z(int32_t q) const { return pz[q]; }
+};
+template <typename T> struct GlobalCell {
+    const T *px, *py, *pz;
+    __device__ T x(int32_t q) const { return px[q]; }
+    __device__ T y(int32_t q) const { return py[q]; }
+    __device__ T z(int32_t q) const { return pz[q]; }
+};
+
+// WAVE form: cells with <= 256 pairs and <= 512 particles; others go to the list.
+template <typename T, int RULE>
+__global__ void __launch_bounds__(64)
+k_phaseB_match_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchArgs ma,
+                    int32_t* list)
+{
+    __shared__ T lx[WV_NMAX], ly[WV_NMAX], lz[WV_NMAX];
+    __shared__ int32_t first[WV_NMAX];
+    const int lane = threadIdx.x;
+    int64_t k = blockIdx.x;
+    int32_t c = k < n_cells ? pr.cnt[k] : 0;
+    int32_t o32 = k < n_cells ? pr.off[k] : 0;
+    int32_t s0 = k < n_cells ? ma.cell_start[k] : 0;
+    int32_t s1 = k < n_cells ? ma.cell_start[k + 1] : 0;
+    for (; k < n_cells; k += gridDim.x) {
+        const int64_t kn = k + gridDim.x;
+        const int32_t c_next = kn < n_cells ? pr.cnt[kn] : 0;
+        const int32_t o_next = kn < n_cells ? pr.off[kn] : 0;
+        const int32_t s0_next = kn < n_cells ? ma.cell_start[kn] : 0;
+        const int32_t s1_next = kn < n_cells ? ma.cell_start[kn + 1] : 0;
+        const int32_t cc = c, N = s1 - s0, b0 = s0;
+        const int64_t o = o32;
+        c = c_next;
+        o32 = o_next;
+        s0 = s0_next;
+        s1 = s1_next;
+        if (cc == 0 || N < 2) continue;
+        if (cc > 64 * WV_PPL || N > WV_NMAX) {
+            if (lane == 0) {
+                const int32_t at = atomicAdd(&list[0], 1);
+                list[1 + at] = (int32_t)k;
+            }
+            continue;
+        }
+        int32_t pa[WV_PPL], pb[WV_PPL];
+#pragma unroll
+        for (int m = 0; m < WV_PPL; ++m) {
+            const int32_t q = lane + 64 * m;
+            pa[m] = b0;
+            pb[m] = b0;
+            if (q < cc) {
+                pa[m] = pr.i[o + q];
+                pb[m] = pr.j[o + q];
+            }
+        }
+        cell_rounds_lds<T, RULE, 64, WV_PPL, false>(pr, v, d, cc, o, b0, N, pa, pb, lx, ly, lz,
+                                                    first);
+        match_cell<T>(LdsCell<T>{lx, ly, lz}, N, ma.mom + 6 * (size_t)k, ma.literal, v, b0, ma.st);
+        __syncthreads();
+    }
+}
+
+// BLOCK form for the listed cells: LDS rounds when the cell fits, else the
+// global-memory rounds; the first wave matches.
+template <typename T, int RULE>
+__global__ void __launch_bounds__(BLK_THREADS)
+k_phaseB_match_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchArgs ma,
+                     const int32_t* list)
+{
+    __shared__ __attribute__((aligned(16))) char smem[BlkLds<T>::bytes];
+    T* lx = reinterpret_cast<T*>(smem);
+    T* ly = lx + BLK_NMAX;
+    T* lz = ly + BLK_NMAX;
+    int32_t* first = reinterpret_cast<int32_t*>(lz + BLK_NMAX);
+    const int64_t n_items = list[0];
+    for (int64_t idx = blockIdx.x; idx < n_items; idx += gridDim.x) {
+        const int32_t k = list[1 + idx];
+        const int32_t c = pr.cnt[k];
+        const int64_t o = pr.off[k];
+        const int32_t b0 = ma.cell_start[k], N = ma.cell_start[k + 1] - b0;
+        if (c <= BLK_THREADS * BLK_PPL && N <= BLK_NMAX) {
+            int32_t pa[BLK_PPL], pb[BLK_PPL];
+#pragma unroll
+            for (int m = 0; m < BLK_PPL; ++m) {
+                const int32_t q = threadIdx.x + BLK_THREADS * m;
+                pa[m] = b0;
+                pb[m] = b0;
+                if (q < c) {
+                    pa[m] = pr.i[o + q];
+                    pb[m] = pr.j[o + q];
+                }
+            }
+            cell_rounds_lds<T, RULE, BLK_THREADS, BLK_PPL, false>(pr, v, d, c, o, b0, N, pa, pb,
+                                                                  lx, ly, lz, first);
+            if (threadIdx.x < 64)
+                match_cell<T>(LdsCell<T>{lx, ly, lz}, N, ma.mom + 6 * (size_t)k, ma.literal, v,
+                              b0, ma.st);
+        } else {
+            if (c <= BLK_GMAX && N <= BLK_GMAX) {
+                int32_t* gfirst = reinterpret_cast<int32_t*>(smem);
+                uint32_t* pij = reinterpret_cast<uint32_t*>(gfirst + BLK_GMAX);
+                cell_rounds_global<T, RULE>(v, d, pr, c, o, b0, N, gfirst, pij);
+            } else {
+                if (threadIdx.x == 0)
+                    for (int32_t q = 0; q < c; ++q)
+                        apply_pair<T, RULE>(v, pr.i[o + q], pr.j[o + q], d, o + q);
+                __syncthreads();
+            }
+            if (threadIdx.x < 64)
+                match_cell<T>(GlobalCell<T>{v.x + b0, v.y + b0, v.z + b0}, N,
+                              ma.mom + 6 * (size_t)k, ma.literal, v, b0, ma.st);
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_zero_i32(int32_t* p) { *p = 0; }
 
 int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v,
@@ -522,6 +707,48 @@ extern "C" int dsmc_collide_vhs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsm
     DSMC_LAUNCH_CHECK("collide_vhs:phaseA");
     if (schedule == DSMC_SCHED_DEFER) return DSMC_OK;
     return phase_b(RULE_DIR, dtype, n_cells, nullptr, v, pairs, ws, pairs.cap, schedule, s);
+}
+
+extern "C" int dsmc_apply_pairs_match(int32_t n_cells, const int32_t* cell_start, int32_t dtype,
+                                      dsmc_vec3 v, dsmc_pairs pairs, int32_t kind,
+                                      const double* mom, int32_t mode, void* ws,
+                                      size_t ws_bytes, dsmc_status* st, dsmc_stream_t stream)
+{
+    int rc = check_pairs("dsmc_apply_pairs_match", n_cells, v, pairs, dtype, ws, ws_bytes);
+    if (rc) return rc;
+    if (!cell_start || !mom) return arg_error("dsmc_apply_pairs_match: null pointer");
+    if (kind != DSMC_APPLY_DIRECTIONS && kind != DSMC_APPLY_ANGLES)
+        return arg_error("dsmc_apply_pairs_match: kind %d", kind);
+    if (mode != DSMC_MM_APPLY && mode != DSMC_MM_APPLY_LITERAL)
+        return arg_error("dsmc_apply_pairs_match: mode %d", mode);
+    hipStream_t s = as_stream(stream);
+    const PairsView pr = PairsView::of(pairs);
+    const MatchArgs ma{cell_start, mom, mode == DSMC_MM_APPLY_LITERAL ? 1 : 0, st};
+    const int cus = device_cus();
+    int wb = n_cells < cus * 40 ? n_cells : cus * 40;
+    wb = wb < 1 ? 1 : wb;
+    int bb = n_cells < cus * 2 ? n_cells : cus * 2;
+    bb = bb < 1 ? 1 : bb;
+#define DSMC_PHASEB_MATCH(T, R)                                                              \
+    do {                                                                                     \
+        PairBuf<T> d = PairBuf<T>::of(ws, pairs.cap);                                        \
+        int32_t* list = reinterpret_cast<int32_t*>(d.f);                                     \
+        k_zero_i32<<<1, 1, 0, s>>>(list);                                                    \
+        DSMC_LAUNCH_CHECK("phaseB_match:list");                                              \
+        k_phaseB_match_wave<T, R><<<wb, 64, 0, s>>>(n_cells, pr, v3<T>(v), d, ma, list);     \
+        DSMC_LAUNCH_CHECK("phaseB_match:wave");                                              \
+        k_phaseB_match_block<T, R><<<bb, BLK_THREADS, 0, s>>>(n_cells, pr, v3<T>(v), d, ma,  \
+                                                              list);                         \
+        DSMC_LAUNCH_CHECK("phaseB_match:block");                                             \
+    } while (0)
+    const int rule = kind == DSMC_APPLY_ANGLES ? RULE_CHI : RULE_DIR;
+    if (dtype == DSMC_F64) {
+        if (rule == RULE_DIR) DSMC_PHASEB_MATCH(double, RULE_DIR); else DSMC_PHASEB_MATCH(double, RULE_CHI);
+    } else {
+        if (rule == RULE_DIR) DSMC_PHASEB_MATCH(float, RULE_DIR); else DSMC_PHASEB_MATCH(float, RULE_CHI);
+    }
+#undef DSMC_PHASEB_MATCH
+    return DSMC_OK;
 }
 
 extern "C" int dsmc_apply_pairs(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pairs,

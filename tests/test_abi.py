@@ -86,6 +86,8 @@ def test_host_argument_errors(lib):
     a.dims[0], a.dims[1], a.dims[2] = 3, 8, 1     # dims[0] must be 2
     assert lib.dsmc_anet_ws(C.byref(a), 10) == 0
     assert lib.dsmc_huber_loss(0, None, None, None, None, None) == L.DSMC_E_ARG
+    assert lib.dsmc_apply_pairs_match(4, None, L.F64, L.Vec3(), L.Pairs(), 0, None, L.MM_APPLY,
+                                      None, 0, None, None) == L.DSMC_E_ARG
     t = L.ChiTable(1, 4, 0.0, 1.0, None)
     assert lib.dsmc_collide_table(C.byref(t), 4, L.F64, L.Vec3(), L.Pairs(), L.Rng(), 1.0, 0,
                                   None, 0, None) == L.DSMC_E_ARG

@@ -72,8 +72,8 @@ def test_cylinder_fullsize_neural_step(orc, dev, api):
     net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=3547.0, device=dev)
     ws = api.collide_ws(cap, v)
     api.neural_collide(net, v, pairs, 11, 0, schedule=api.L.SCHED_DEFER, ws=ws, st=st)
-    api.apply_pairs(v, pairs, api.L.APPLY_DIRECTIONS, ws)
-    api.moment_match(cs, v, mom, api.L.MM_APPLY, pair_cnt=pairs.cnt, st=st)
+    # the fused Phase B + matching pass the timed step runs
+    api.apply_pairs_match(cs, v, pairs, api.L.APPLY_DIRECTIONS, mom, ws, st=st)
     torch.cuda.synchronize()
     say(f"  {n} particles, {int(api.read_status(st).n_pairs)} pairs")
 

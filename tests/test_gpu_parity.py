@@ -285,6 +285,67 @@ def test_moment_match_apply_modes(orc, dev, api, dtype):
         assert err < tol, (mode, err)
 
 
+@pytest.mark.parametrize("case", ["ragged", "big", "huge"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("rule", ["vhs", "table"])
+def test_apply_pairs_match_fused_bit_identical(dev, api, case, dtype, rule):
+    """Phase B fused with the moment matching against Phase B followed by the
+    matching kernel: bit-identical velocities and skip counts, both modes.
+    ragged: one-wave cells and LDS block cells; big: block cells up to 7000
+    particles (LDS and global-memory rounds); huge: one 9000-particle cell
+    (sequential rounds)."""
+    say("apply_pairs_match fused", case, dtype, rule)
+    pop = {"ragged": lambda: W.ragged_population(31, 400, 700, empty_frac=0.1),
+           "big": lambda: W.ragged_population(32, 6, 7000, empty_frac=0.0),
+           "huge": lambda: W.ragged_population(8, 1, 9000, empty_frac=0.0)}[case]()
+    cs, _, v0, _ = _gpu_sort(api, dev, pop, dtype)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, v0, mom, api.L.MM_CAPTURE)
+    pairs = api.PairList(pop.n_cells, 1 << 21, dev)
+    api.select_pairs_ntc(cs, v0, pop.xs, torch.as_tensor(pop.lam, device=dev), mom, 6, 3, pairs)
+    say(f"  {int(pairs.cnt.sum())} pairs, max per cell {int(pairs.cnt.max())}, "
+        f"max cell {int((cs[1:] - cs[:-1]).max())}")
+    if rule == "table":
+        lo, hi = math.log(5.0), math.log(5e5)
+        th = np.linspace(math.pi, 0.0, 33)[None, :] * np.linspace(0.2, 1.0, 16)[:, None]
+        tab = api.ChiTable(16, 33, lo, hi, device=dev, theta=th.astype(np.float32))
+        kind = api.L.APPLY_ANGLES
+    else:
+        kind = api.L.APPLY_DIRECTIONS
+    for mode in (api.L.MM_APPLY, api.L.MM_APPLY_LITERAL):
+        outs = []
+        for fused in (False, True):
+            v = v0.clone()
+            st = api.new_status(dev)
+            ws = api.collide_ws(pairs.cap, v)
+            if rule == "table":
+                api.collide_table(tab, v, pairs, 6, 3, W.AR_MASS / 2, schedule=api.L.SCHED_DEFER,
+                                  ws=ws)
+            else:
+                api.collide_vhs(v, pairs, 6, 3, schedule=api.L.SCHED_DEFER, ws=ws)
+            if fused:
+                api.apply_pairs_match(cs, v, pairs, kind, mom, ws, mode=mode, st=st)
+            else:
+                api.apply_pairs(v, pairs, kind, ws)
+                api.moment_match(cs, v, mom, mode, pair_cnt=pairs.cnt, st=st)
+            outs.append((v.cpu().numpy(), api.read_status(st).mm_skipped))
+        assert np.array_equal(outs[0][0], outs[1][0]), mode
+        assert outs[0][1] == outs[1][1]
+        assert not np.array_equal(outs[0][0], v0.cpu().numpy())
+
+
+def test_apply_pairs_match_rejects_bad_args(dev, api):
+    pop = W.ragged_population(33, 20, 30)
+    cs, _, v, _ = _gpu_sort(api, dev, pop)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    pairs = api.PairList(pop.n_cells, 4096, dev)
+    ws = api.collide_ws(pairs.cap, v)
+    with pytest.raises(RuntimeError):
+        api.apply_pairs_match(cs, v, pairs, 7, mom, ws)
+    with pytest.raises(RuntimeError):
+        api.apply_pairs_match(cs, v, pairs, api.L.APPLY_DIRECTIONS, mom, ws, mode=api.L.MM_CAPTURE)
+
+
 # ---------------------------------------------------------------------------
 # deflection angle
 # ---------------------------------------------------------------------------
