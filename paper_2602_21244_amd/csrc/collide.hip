@@ -103,20 +103,37 @@ k_phaseB_lane(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t max_
 // ------------------------------------------------------------------------
 // Dependency rounds with the cell's velocities staged in LDS.  Each thread
 // owns up to PPL pairs (pair q = thread + NT m) with their Phase-A results
-// prefetched into registers.  In round r every pending pair offers the key
-// ((R - r) << 16 | q) to both of its particles (LDS atomicMin; keys of later
-// rounds are smaller, so the table never needs clearing); a pair whose key
-// wins at both particles is the earliest pending pair of both and is applied.
+// prefetched into registers.  Round search: in round r every pending pair
+// offers the key ((R - r) << 16 | q) to both of its particles (LDS
+// atomicMin; keys of later rounds are smaller, so the table never needs
+// clearing); a pair whose key wins at both particles is the earliest pending
+// pair of both and belongs to round r.  Pairs of one round share no particle,
+// so they commute.  The pairs are then bucketed by round in LDS (record and
+// Phase-A result at a compact position) and applied round by round, each
+// round's pairs spread over all lanes: every pair costs one pass of the
+// update, however many rounds the cell needs.  The result is the sequential
+// application in candidate order, bit for bit.
 // ------------------------------------------------------------------------
 constexpr int32_t ROUND_MAX = 32767;
 
 template <typename T, int RULE>
 struct Payload {
+    static constexpr int W = RULE == RULE_CHI ? 5 : 3;
     T a, b, c, d, e;
     __device__ __forceinline__ void load(const PairBuf<T>& buf, int64_t p)
     {
         a = buf.a[p]; b = buf.b[p]; c = buf.c[p];
         if (RULE == RULE_CHI) { d = buf.d[p]; e = buf.e[p]; }
+    }
+    __device__ __forceinline__ void put(T* s) const
+    {
+        s[0] = a; s[1] = b; s[2] = c;
+        if (RULE == RULE_CHI) { s[3] = d; s[4] = e; }
+    }
+    __device__ __forceinline__ void get(const T* s)
+    {
+        a = s[0]; b = s[1]; c = s[2];
+        if (RULE == RULE_CHI) { d = s[3]; e = s[4]; }
     }
 };
 
@@ -161,17 +178,67 @@ __device__ __forceinline__ bool any_pending(uint32_t pend)
     return __syncthreads_or(pend != 0) != 0;
 }
 
-// One cell (c pairs from offset o; pair slots within [lo, lo + span)) on NT
-// threads with LDS tables lx/ly/lz/first of at least span entries.
-template <typename T, int RULE, int NT, int PPL, bool WB = true>
-__device__ __forceinline__ void cell_rounds_lds(const PairsView& pr, V3<T> v, const PairBuf<T>& d,
-                                                int32_t c, int64_t o, int32_t lo, int32_t span,
-                                                const int32_t (&pa_g)[PPL],
-                                                const int32_t (&pb_g)[PPL], T* lx, T* ly, T* lz,
-                                                int32_t* first)
+// LDS of one staged cell: velocities [3][NMAX]; a union of the round-search
+// table first[NMAX] and the bucketed Phase-A results pay[PMAX][W]; the
+// bucketed pair records rab[PMAX] (slot a | slot b << 16); the round table
+// rc[RMAX + 1] (counts, then starts).
+template <typename T, int RULE, int NT, int PPL, int NMAX, int RMAX>
+struct CellLds {
+    static constexpr int PMAX = NT * PPL;
+    static constexpr size_t v_bytes = (size_t)3 * NMAX * sizeof(T);
+    static constexpr size_t f_bytes = (size_t)NMAX * sizeof(int32_t);
+    static constexpr size_t p_bytes = (size_t)PMAX * Payload<T, RULE>::W * sizeof(T);
+    static constexpr size_t u_bytes = f_bytes > p_bytes ? f_bytes : p_bytes;
+    static constexpr size_t bytes = v_bytes + u_bytes + (size_t)PMAX * 4 + (size_t)(RMAX + 1) * 4;
+    T *lx, *ly, *lz, *pay;
+    int32_t *first, *rab, *rc;
+    __device__ __forceinline__ explicit CellLds(char* smem)
+    {
+        lx = reinterpret_cast<T*>(smem);
+        ly = lx + NMAX;
+        lz = ly + NMAX;
+        first = reinterpret_cast<int32_t*>(smem + v_bytes);
+        pay = reinterpret_cast<T*>(smem + v_bytes);
+        rab = reinterpret_cast<int32_t*>(smem + v_bytes + u_bytes);
+        rc = rab + PMAX;
+    }
+};
+
+// Exclusive scan of rc[0..R) in place by the first wave; rc[R] = total.
+__device__ __forceinline__ void round_scan(int32_t* rc, int32_t R)
 {
     const int t = threadIdx.x;
-    int32_t pa[PPL], pb[PPL];
+    if (t < 64) {
+        int32_t carry = 0;
+        for (int32_t base = 0; base < R; base += 64) {
+            const int32_t x = base + t < R ? rc[base + t] : 0;
+            int32_t y = x;
+#pragma unroll
+            for (int s = 1; s < 64; s <<= 1) {
+                const int32_t u = __shfl_up(y, s, 64);
+                if (t >= s) y += u;
+            }
+            if (base + t < R) rc[base + t] = carry + y - x;
+            carry += __shfl(y, 63, 64);
+        }
+        if (t == 0) rc[R] = carry;
+    }
+}
+
+// One cell: c pairs from offset o with slots in [lo, lo + span) (span <=
+// NMAX, c <= NT * PPL); pa_g / pb_g are this thread's pairs (global slots,
+// padded with lo).  On return the updated velocities are in LDS (and in v if
+// WB).
+template <typename T, int RULE, int NT, int PPL, int NMAX, int RMAX, bool WB>
+__device__ __forceinline__ void cell_rounds(const PairsView& pr, V3<T> v, const PairBuf<T>& d,
+                                            int32_t c, int64_t o, int32_t lo, int32_t span,
+                                            const int32_t (&pa_g)[PPL],
+                                            const int32_t (&pb_g)[PPL],
+                                            const CellLds<T, RULE, NT, PPL, NMAX, RMAX>& L)
+{
+    constexpr int W = Payload<T, RULE>::W;
+    const int t = threadIdx.x;
+    int32_t pa[PPL], pb[PPL], rnd[PPL];
     Payload<T, RULE> pl[PPL];
     uint32_t pend = 0;
 #pragma unroll
@@ -179,16 +246,17 @@ __device__ __forceinline__ void cell_rounds_lds(const PairsView& pr, V3<T> v, co
         const int32_t q = t + NT * m;
         pa[m] = pa_g[m] - lo;
         pb[m] = pb_g[m] - lo;
+        rnd[m] = -1;
         if (q < c) {
             pl[m].load(d, o + q);
             pend |= 1u << m;
         }
     }
     for (int32_t q = t; q < span; q += NT) {
-        lx[q] = v.x[lo + q];
-        ly[q] = v.y[lo + q];
-        lz[q] = v.z[lo + q];
-        first[q] = INT32_MAX;
+        L.lx[q] = v.x[lo + q];
+        L.ly[q] = v.y[lo + q];
+        L.lz[q] = v.z[lo + q];
+        L.first[q] = INT32_MAX;
     }
     int32_t r = 0;
     while (any_pending<NT>(pend)) {
@@ -197,28 +265,66 @@ __device__ __forceinline__ void cell_rounds_lds(const PairsView& pr, V3<T> v, co
         for (int m = 0; m < PPL; ++m)
             if (pend & (1u << m)) {
                 const int32_t key = kb | (t + NT * m);
-                atomicMin(&first[pa[m]], key);
-                atomicMin(&first[pb[m]], key);
+                atomicMin(&L.first[pa[m]], key);
+                atomicMin(&L.first[pb[m]], key);
             }
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < PPL; ++m) {
             const int32_t key = kb | (t + NT * m);
-            if ((pend & (1u << m)) && first[pa[m]] == key && first[pb[m]] == key) {
-                apply_pair_lds<T, RULE>(lx, ly, lz, pa[m], pb[m], pl[m]);
+            if ((pend & (1u << m)) && L.first[pa[m]] == key && L.first[pb[m]] == key) {
+                rnd[m] = r;
                 pend &= ~(1u << m);
             }
         }
         ++r;
     }
-    if (WB) {
-        for (int32_t q = t; q < span; q += NT) {
-            v.x[lo + q] = lx[q];
-            v.y[lo + q] = ly[q];
-            v.z[lo + q] = lz[q];
+    const int32_t R = r;
+    if (R <= RMAX) {
+        // bucket by round: position inside the round, round starts, records
+        for (int32_t q = t; q < R; q += NT) L.rc[q] = 0;
+        __syncthreads();
+        int32_t pos[PPL];
+#pragma unroll
+        for (int m = 0; m < PPL; ++m) pos[m] = rnd[m] >= 0 ? atomicAdd(&L.rc[rnd[m]], 1) : 0;
+        __syncthreads();
+        round_scan(L.rc, R);
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PPL; ++m)
+            if (rnd[m] >= 0) {
+                const int32_t s = L.rc[rnd[m]] + pos[m];
+                L.rab[s] = pa[m] | (pb[m] << 16);
+                pl[m].put(L.pay + (size_t)s * W);
+            }
+        __syncthreads();
+        for (int32_t rr = 0; rr < R; ++rr) {
+            const int32_t s1 = L.rc[rr + 1];
+            for (int32_t s = L.rc[rr] + t; s < s1; s += NT) {
+                const int32_t ab = L.rab[s];
+                Payload<T, RULE> p;
+                p.get(L.pay + (size_t)s * W);
+                apply_pair_lds<T, RULE>(L.lx, L.ly, L.lz, ab & 0xffff, ab >> 16, p);
+            }
+            __syncthreads();
+        }
+    } else {
+        // more rounds than the round table holds: apply from the registers
+        for (int32_t rr = 0; rr < R; ++rr) {
+#pragma unroll
+            for (int m = 0; m < PPL; ++m)
+                if (rnd[m] == rr) apply_pair_lds<T, RULE>(L.lx, L.ly, L.lz, pa[m], pb[m], pl[m]);
+            __syncthreads();
         }
     }
-    __syncthreads();
+    if (WB) {
+        for (int32_t q = t; q < span; q += NT) {
+            v.x[lo + q] = L.lx[q];
+            v.y[lo + q] = L.ly[q];
+            v.z[lo + q] = L.lz[q];
+        }
+        __syncthreads();
+    }
 }
 
 // Min / max of the cell's pair slots over the workgroup.
@@ -240,22 +346,24 @@ __device__ __forceinline__ void group_minmax(int32_t& lo, int32_t& hi, int32_t* 
     __syncthreads();
 }
 
-// WAVE schedule: one 64-lane workgroup per cell with thr < pairs <= 256 whose
-// pairs span at most 512 slots (small LDS tables, so many workgroups stay
-// resident to hide the cell loads); every other cell with more than thr
-// pairs is appended to the list the BLOCK kernel works through (list[0] =
-// length, list[1..] = cells).  The next cell's count and offset are loaded
-// while the current cell runs.
+// WAVE schedule: one 64-lane workgroup per cell with at most 256 pairs whose
+// slots span at most 512 (small LDS tables, so many workgroups stay resident
+// to hide the cell loads); every other cell goes to the list the BLOCK kernel
+// works through (list[0] = length, list[1..] = cells).  The next cell's count
+// and offset are loaded while the current cell runs.
 constexpr int WV_NMAX = 512;
 constexpr int WV_PPL = 4;
+constexpr int WV_RMAX = 64 * WV_PPL;
+template <typename T, int RULE>
+using WaveLds = CellLds<T, RULE, 64, WV_PPL, WV_NMAX, WV_RMAX>;
 
 template <typename T, int RULE>
 __global__ void __launch_bounds__(64)
 k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
               int32_t* list)
 {
-    __shared__ T lx[WV_NMAX], ly[WV_NMAX], lz[WV_NMAX];
-    __shared__ int32_t first[WV_NMAX];
+    __shared__ __attribute__((aligned(16))) char smem[WaveLds<T, RULE>::bytes];
+    const WaveLds<T, RULE> L(smem);
     const int lane = threadIdx.x;
     int64_t k = blockIdx.x;
     int32_t c = k < n_cells ? pr.cnt[k] : 0;
@@ -276,7 +384,6 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
             }
             continue;
         }
-        const int32_t c_ = cc;
         int32_t pa[WV_PPL], pb[WV_PPL];
         int32_t lo = INT32_MAX, hi = -1;
 #pragma unroll
@@ -284,7 +391,7 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
             const int32_t q = lane + 64 * m;
             pa[m] = 0;
             pb[m] = 0;
-            if (q < c_) {
+            if (q < cc) {
                 pa[m] = pr.i[o + q];
                 pb[m] = pr.j[o + q];
                 lo = min(lo, min(pa[m], pb[m]));
@@ -302,27 +409,32 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
         }
 #pragma unroll
         for (int m = 0; m < WV_PPL; ++m)
-            if (lane + 64 * m >= c_) { pa[m] = lo; pb[m] = lo; }
-        cell_rounds_lds<T, RULE, 64, WV_PPL>(pr, v, d, c_, o, lo, span, pa, pb, lx, ly, lz, first);
+            if (lane + 64 * m >= cc) { pa[m] = lo; pb[m] = lo; }
+        cell_rounds<T, RULE, 64, WV_PPL, WV_NMAX, WV_RMAX, true>(pr, v, d, cc, o, lo, span, pa, pb,
+                                                                 L);
     }
 }
 
-// BLOCK schedule: 256 threads per cell.  Cells with up to 2048 pairs spanning
-// up to 4096 slots run the LDS rounds; larger ones (up to 8192) run the same
-// rounds on velocities in global memory with the tables in LDS; beyond that
-// one thread applies the pairs in order.  Works through the cells in `list`
-// after the WAVE kernel, or (list == nullptr) every cell with at least
-// min_pairs pairs.
-constexpr int BLK_THREADS = 256;
-constexpr int BLK_PPL = 8;
-constexpr int BLK_NMAX = 4096;      // LDS rounds
+// BLOCK schedule: 512 threads per cell.  Cells with up to 4096 pairs (2048
+// for FP64 velocities) spanning up to 4096 slots (2048) run the LDS rounds;
+// larger ones (up to 8192) run the rounds on velocities in global memory with
+// the tables in LDS; beyond that one thread applies the pairs in order.
+// Works through the cells in `list` after the WAVE kernel, or (list ==
+// nullptr) every cell with at least min_pairs pairs.
+constexpr int BLK_THREADS = 512;
 constexpr int BLK_GMAX = 8192;      // global-memory rounds
+constexpr int BLK_RMAX = 1024;
+template <typename T> struct BlkShape;
+template <> struct BlkShape<float> { static constexpr int PPL = 8, NMAX = 4096; };
+template <> struct BlkShape<double> { static constexpr int PPL = 4, NMAX = 2048; };
+template <typename T, int RULE>
+using BlockLds = CellLds<T, RULE, BLK_THREADS, BlkShape<T>::PPL, BlkShape<T>::NMAX, BLK_RMAX>;
 
-template <typename T>
-struct BlkLds {
-    static constexpr size_t lds = (size_t)BLK_NMAX * (3 * sizeof(T) + sizeof(int32_t));
+template <typename T, int RULE>
+struct BlkSmem {
     static constexpr size_t glb = (size_t)BLK_GMAX * 2 * sizeof(int32_t);
-    static constexpr size_t bytes = lds > glb ? lds : glb;
+    static constexpr size_t bytes =
+        BlockLds<T, RULE>::bytes > glb ? BlockLds<T, RULE>::bytes : glb;
 };
 
 template <typename T, int RULE>
@@ -363,17 +475,52 @@ __device__ void cell_rounds_global(V3<T> v, const PairBuf<T>& d, const PairsView
     }
 }
 
+// One BLOCK cell (pairs [o, o + c), slots [lo, lo + span)); LDS: updated
+// velocities left in L when the LDS rounds ran (returns true), else in v.
+template <typename T, int RULE, bool WB>
+__device__ __forceinline__ bool block_cell(const PairsView& pr, V3<T> v, const PairBuf<T>& d,
+                                           int32_t c, int64_t o, int32_t lo, int32_t span,
+                                           char* smem)
+{
+    constexpr int PPL = BlkShape<T>::PPL, NMAX = BlkShape<T>::NMAX;
+    if (c <= BLK_THREADS * PPL && span <= NMAX) {
+        int32_t pa[PPL], pb[PPL];
+#pragma unroll
+        for (int m = 0; m < PPL; ++m) {
+            const int32_t q = threadIdx.x + BLK_THREADS * m;
+            pa[m] = lo;
+            pb[m] = lo;
+            if (q < c) {
+                pa[m] = pr.i[o + q];
+                pb[m] = pr.j[o + q];
+            }
+        }
+        const BlockLds<T, RULE> L(smem);
+        cell_rounds<T, RULE, BLK_THREADS, PPL, NMAX, BLK_RMAX, WB>(pr, v, d, c, o, lo, span, pa,
+                                                                   pb, L);
+        return true;
+    }
+    if (c <= BLK_GMAX && span <= BLK_GMAX) {
+        int32_t* gfirst = reinterpret_cast<int32_t*>(smem);
+        uint32_t* pij = reinterpret_cast<uint32_t*>(gfirst + BLK_GMAX);
+        cell_rounds_global<T, RULE>(v, d, pr, c, o, lo, span, gfirst, pij);
+    } else {
+        // beyond the LDS tables: sequential, still in candidate order
+        if (threadIdx.x == 0)
+            for (int32_t q = 0; q < c; ++q)
+                apply_pair<T, RULE>(v, pr.i[o + q], pr.j[o + q], d, o + q);
+        __syncthreads();
+    }
+    return false;
+}
+
 template <typename T, int RULE>
 __global__ void __launch_bounds__(BLK_THREADS)
 k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
                const int32_t* list)
 {
-    __shared__ __attribute__((aligned(16))) char smem[BlkLds<T>::bytes];
+    __shared__ __attribute__((aligned(16))) char smem[BlkSmem<T, RULE>::bytes];
     __shared__ int32_t red[2 * (BLK_THREADS / 64)];
-    T* lx = reinterpret_cast<T*>(smem);
-    T* ly = lx + BLK_NMAX;
-    T* lz = ly + BLK_NMAX;
-    int32_t* first = reinterpret_cast<int32_t*>(lz + BLK_NMAX);
     const int64_t n_items = list ? (int64_t)list[0] : (int64_t)n_cells;
     for (int64_t idx = blockIdx.x; idx < n_items; idx += gridDim.x) {
         int32_t k;
@@ -386,43 +533,14 @@ k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min
         }
         const int32_t c = pr.cnt[k];
         const int64_t o = pr.off[k];
-        int32_t pa[BLK_PPL], pb[BLK_PPL];
         int32_t lo = INT32_MAX, hi = -1;
-#pragma unroll
-        for (int m = 0; m < BLK_PPL; ++m) {
-            const int32_t q = threadIdx.x + BLK_THREADS * m;
-            pa[m] = 0;
-            pb[m] = 0;
-            if (q < c) {
-                pa[m] = pr.i[o + q];
-                pb[m] = pr.j[o + q];
-                lo = min(lo, min(pa[m], pb[m]));
-                hi = max(hi, max(pa[m], pb[m]));
-            }
-        }
-        for (int32_t q = threadIdx.x + BLK_THREADS * BLK_PPL; q < c; q += BLK_THREADS) {
+        for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS) {
             lo = min(lo, min(pr.i[o + q], pr.j[o + q]));
             hi = max(hi, max(pr.i[o + q], pr.j[o + q]));
         }
         group_minmax<BLK_THREADS>(lo, hi, red);
-        const int32_t span = hi - lo + 1;
-        if (c <= BLK_THREADS * BLK_PPL && span <= BLK_NMAX) {
-#pragma unroll
-            for (int m = 0; m < BLK_PPL; ++m)
-                if (threadIdx.x + BLK_THREADS * m >= c) { pa[m] = lo; pb[m] = lo; }
-            cell_rounds_lds<T, RULE, BLK_THREADS, BLK_PPL>(pr, v, d, c, o, lo, span, pa, pb, lx, ly,
-                                                           lz, first);
-        } else if (c <= BLK_GMAX && span <= BLK_GMAX) {
-            int32_t* gfirst = reinterpret_cast<int32_t*>(smem);
-            uint32_t* pij = reinterpret_cast<uint32_t*>(gfirst + BLK_GMAX);
-            cell_rounds_global<T, RULE>(v, d, pr, c, o, lo, span, gfirst, pij);
-        } else {
-            // beyond the LDS tables: sequential, still in candidate order
-            if (threadIdx.x == 0)
-                for (int32_t q = 0; q < c; ++q)
-                    apply_pair<T, RULE>(v, pr.i[o + q], pr.j[o + q], d, o + q);
-            __syncthreads();
-        }
+        block_cell<T, RULE, true>(pr, v, d, c, o, lo, hi - lo + 1, smem);
+        __syncthreads();
     }
 }
 
@@ -490,13 +608,7 @@ __device__ __forceinline__ void match_cell(LD ld, int32_t N, const double* m, in
     }
 }
 
-template <typename T> struct LdsCell {
-    const T *px, *py, *pz;
-    __device__ T x(int32_t q) const { return px[q]; }
-    __device__ T y(int32_t q) const { return py[q]; }
-    __device__ T z(int32_t q) const { return pz[q]; }
-};
-template <typename T> struct GlobalCell {
+template <typename T> struct CellView {
     const T *px, *py, *pz;
     __device__ T x(int32_t q) const { return px[q]; }
     __device__ T y(int32_t q) const { return py[q]; }
@@ -509,8 +621,8 @@ __global__ void __launch_bounds__(64)
 k_phaseB_match_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchArgs ma,
                     int32_t* list)
 {
-    __shared__ T lx[WV_NMAX], ly[WV_NMAX], lz[WV_NMAX];
-    __shared__ int32_t first[WV_NMAX];
+    __shared__ __attribute__((aligned(16))) char smem[WaveLds<T, RULE>::bytes];
+    const WaveLds<T, RULE> L(smem);
     const int lane = threadIdx.x;
     int64_t k = blockIdx.x;
     int32_t c = k < n_cells ? pr.cnt[k] : 0;
@@ -548,67 +660,41 @@ k_phaseB_match_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchA
                 pb[m] = pr.j[o + q];
             }
         }
-        cell_rounds_lds<T, RULE, 64, WV_PPL, false>(pr, v, d, cc, o, b0, N, pa, pb, lx, ly, lz,
-                                                    first);
-        match_cell<T>(LdsCell<T>{lx, ly, lz}, N, ma.mom + 6 * (size_t)k, ma.literal, v, b0, ma.st);
+        cell_rounds<T, RULE, 64, WV_PPL, WV_NMAX, WV_RMAX, false>(pr, v, d, cc, o, b0, N, pa, pb,
+                                                                  L);
+        match_cell<T>(CellView<T>{L.lx, L.ly, L.lz}, N, ma.mom + 6 * (size_t)k, ma.literal, v, b0,
+                      ma.st);
         __syncthreads();
     }
 }
 
-// BLOCK form for the listed cells: LDS rounds when the cell fits, else the
-// global-memory rounds; the first wave matches.
+// BLOCK form for the listed cells; the first wave matches.
 template <typename T, int RULE>
 __global__ void __launch_bounds__(BLK_THREADS)
 k_phaseB_match_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchArgs ma,
                      const int32_t* list)
 {
-    __shared__ __attribute__((aligned(16))) char smem[BlkLds<T>::bytes];
-    T* lx = reinterpret_cast<T*>(smem);
-    T* ly = lx + BLK_NMAX;
-    T* lz = ly + BLK_NMAX;
-    int32_t* first = reinterpret_cast<int32_t*>(lz + BLK_NMAX);
+    __shared__ __attribute__((aligned(16))) char smem[BlkSmem<T, RULE>::bytes];
     const int64_t n_items = list[0];
     for (int64_t idx = blockIdx.x; idx < n_items; idx += gridDim.x) {
         const int32_t k = list[1 + idx];
         const int32_t c = pr.cnt[k];
         const int64_t o = pr.off[k];
         const int32_t b0 = ma.cell_start[k], N = ma.cell_start[k + 1] - b0;
-        if (c <= BLK_THREADS * BLK_PPL && N <= BLK_NMAX) {
-            int32_t pa[BLK_PPL], pb[BLK_PPL];
-#pragma unroll
-            for (int m = 0; m < BLK_PPL; ++m) {
-                const int32_t q = threadIdx.x + BLK_THREADS * m;
-                pa[m] = b0;
-                pb[m] = b0;
-                if (q < c) {
-                    pa[m] = pr.i[o + q];
-                    pb[m] = pr.j[o + q];
-                }
-            }
-            cell_rounds_lds<T, RULE, BLK_THREADS, BLK_PPL, false>(pr, v, d, c, o, b0, N, pa, pb,
-                                                                  lx, ly, lz, first);
-            if (threadIdx.x < 64)
-                match_cell<T>(LdsCell<T>{lx, ly, lz}, N, ma.mom + 6 * (size_t)k, ma.literal, v,
-                              b0, ma.st);
-        } else {
-            if (c <= BLK_GMAX && N <= BLK_GMAX) {
-                int32_t* gfirst = reinterpret_cast<int32_t*>(smem);
-                uint32_t* pij = reinterpret_cast<uint32_t*>(gfirst + BLK_GMAX);
-                cell_rounds_global<T, RULE>(v, d, pr, c, o, b0, N, gfirst, pij);
+        const bool in_lds = block_cell<T, RULE, false>(pr, v, d, c, o, b0, N, smem);
+        if (threadIdx.x < 64) {
+            const double* m = ma.mom + 6 * (size_t)k;
+            if (in_lds) {
+                const BlockLds<T, RULE> L(smem);
+                match_cell<T>(CellView<T>{L.lx, L.ly, L.lz}, N, m, ma.literal, v, b0, ma.st);
             } else {
-                if (threadIdx.x == 0)
-                    for (int32_t q = 0; q < c; ++q)
-                        apply_pair<T, RULE>(v, pr.i[o + q], pr.j[o + q], d, o + q);
-                __syncthreads();
+                match_cell<T>(CellView<T>{v.x + b0, v.y + b0, v.z + b0}, N, m, ma.literal, v, b0,
+                              ma.st);
             }
-            if (threadIdx.x < 64)
-                match_cell<T>(GlobalCell<T>{v.x + b0, v.y + b0, v.z + b0}, N,
-                              ma.mom + 6 * (size_t)k, ma.literal, v, b0, ma.st);
         }
         __syncthreads();
     }
 }
-
 __global__ void k_zero_i32(int32_t* p) { *p = 0; }
 
 int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v,

@@ -337,7 +337,33 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     bin[t][0][5] = (__bf16)1.0f;
                     bin[t][0][6] = (__bf16)1.0f;
                 }
-                if (valid[t]) {
+                if (valid[t] && sizeof(VT) == 4) {
+                    // FP32 latents: the xi draw (slot 2) and the z draw
+                    // (slot 3) take the same instructions, so each lane-half
+                    // runs one Philox call and the same Box-Muller transforms
+                    // on its own slot without divergence (half 1 discards the
+                    // second transform).
+                    const int64_t r = row[t];
+                    const int32_t k = pio.pr.cell[r];
+                    const uint32_t a = (uint32_t)(r - pio.pr.off[k]);
+                    const U4 rr = draw(pio.rng, a, (uint32_t)k, SLOT_LAT0 + (uint32_t)h);
+                    float n0, n1, n2, spare;
+                    box_muller(unif24(rr.a), unif24(rr.b), n0, n1);
+                    box_muller(unif24(rr.c), unif24(rr.d), n2, spare);
+                    if (h == 0) {
+                        bin[t][0][0] = (__bf16)(C * n0);
+                        bin[t][0][1] = (__bf16)(C * n1);
+                        bin[t][0][2] = (__bf16)(C * n2);
+                    } else {
+                        const int32_t i = pio.pr.i[r], j = pio.pr.j[r];
+                        const VT isv = (VT)d.inv_sigma_v;
+                        bin[t][0][0] = (__bf16)(C * (float)((pio.v.x[i] - pio.v.x[j]) * isv));
+                        bin[t][0][1] = (__bf16)(C * (float)((pio.v.y[i] - pio.v.y[j]) * isv));
+                        bin[t][0][2] = (__bf16)(C * (float)((pio.v.z[i] - pio.v.z[j]) * isv));
+                        bin[t][0][3] = (__bf16)(C * n0);
+                        bin[t][0][4] = (__bf16)(C * n1);
+                    }
+                } else if (valid[t]) {
                     const int64_t r = row[t];
                     const int32_t k = pio.pr.cell[r];
                     const uint32_t a = (uint32_t)(r - pio.pr.off[k]);

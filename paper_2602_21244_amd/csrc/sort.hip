@@ -11,7 +11,8 @@
 //   down  : each wave ranks its 1024 particles in index order (digit match by
 //           ballots, per-wave digit counters in LDS), the tile is reordered by
 //           digit in LDS and written out as contiguous digit runs
-// then one pass over the sorted keys writes cell_start and gathers vx, vy, vz.
+// The last down pass also gathers vx, vy, vz into sorted order; one pass
+// over the sorted keys then writes cell_start.
 // Ids outside [0, n_cells) are mapped to the key n_cells, so they sort after
 // every kept particle.
 #include "common.hpp"
@@ -123,12 +124,14 @@ __device__ __forceinline__ void block_scan_radix(const int32_t* tot, int32_t* ex
     ex[2 * t + 1] = excl + a;
 }
 
-template <bool FIRST>
+// LAST: the final pass also gathers the velocities into sorted order
+// (vals are then the original indices, i.e. perm).
+template <bool FIRST, bool LAST, typename T>
 __global__ void __launch_bounds__(SORT_THREADS)
 k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int32_t n,
              int32_t n_cells, int shift, int32_t mask, int dbits, int32_t nblk,
              const int32_t* __restrict__ goff, int32_t* __restrict__ keys_out,
-             int32_t* __restrict__ vals_out)
+             int32_t* __restrict__ vals_out, V3<const T> vin, V3<T> vout)
 {
     __shared__ int32_t cnt[SORT_THREADS / 64][RADIX];
     __shared__ int32_t tot[RADIX];
@@ -146,20 +149,28 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
     const int64_t wbase = tbase + (int64_t)w * WAVE_SPAN;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int32_t key[SORT_ITEMS], val[SORT_ITEMS], rank[SORT_ITEMS];
+    // all loads of the wave's 1024 items first (independent, coalesced), so
+    // the ranking below does not wait on one load per item
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        const int64_t p = wbase + it * 64 + lane;
+        key[it] = 0;
+        val[it] = 0;
+        if (p < n) {
+            if (FIRST) {
+                key[it] = sort_key(keys_in, p, n_cells);
+                val[it] = (int32_t)p;
+            } else {
+                key[it] = keys_in[p];
+                val[it] = vals_in[p];
+            }
+        }
+    }
 #pragma unroll
     for (int it = 0; it < SORT_ITEMS; ++it) {
         const int64_t p = wbase + it * 64 + lane;
         const bool valid = p < n;
-        int32_t k = 0, v = 0;
-        if (valid) {
-            if (FIRST) {
-                k = sort_key(keys_in, p, n_cells);
-                v = (int32_t)p;
-            } else {
-                k = keys_in[p];
-                v = vals_in[p];
-            }
-        }
+        const int32_t k = key[it];
         const int32_t d = (k >> shift) & mask;
         const uint64_t same = match_digit(d, valid, dbits);
         const int32_t before = __popcll(same & lt_mask);
@@ -167,8 +178,6 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
         __builtin_amdgcn_wave_barrier();
         if (valid && before == 0) cnt[w][d] = old + __popcll(same);
         __builtin_amdgcn_wave_barrier();
-        key[it] = k;
-        val[it] = v;
         rank[it] = valid ? old + before : -1;
     }
     __syncthreads();
@@ -198,33 +207,70 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
     __syncthreads();
     const int64_t left = (int64_t)n - tbase;
     const int32_t tn = left < SORT_TILE ? (int32_t)left : SORT_TILE;
-    for (int s = threadIdx.x; s < tn; s += SORT_THREADS) {
-        const int32_t k = sk[s];
-        const int32_t d = (k >> shift) & mask;
-        const int32_t o = gbase[d] + (s - boff[d]);
-        keys_out[o] = k;
-        vals_out[o] = sv[s];
+    int32_t oo[SORT_ITEMS], vv[SORT_ITEMS];
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        const int s = threadIdx.x + it * SORT_THREADS;
+        oo[it] = -1;
+        vv[it] = 0;
+        if (s < tn) {
+            const int32_t k = sk[s];
+            const int32_t d = (k >> shift) & mask;
+            const int32_t o = gbase[d] + (s - boff[d]);
+            const int32_t v = sv[s];
+            keys_out[o] = k;
+            vals_out[o] = v;
+            oo[it] = o;
+            vv[it] = v;
+        }
+    }
+    if (LAST) {
+        // all gathers first, then all stores, so the loads overlap
+        T gx[SORT_ITEMS], gy[SORT_ITEMS], gz[SORT_ITEMS];
+#pragma unroll
+        for (int it = 0; it < SORT_ITEMS; ++it) {
+            if (oo[it] < 0) continue;
+            gx[it] = vin.x[vv[it]];
+            gy[it] = vin.y[vv[it]];
+            gz[it] = vin.z[vv[it]];
+        }
+#pragma unroll
+        for (int it = 0; it < SORT_ITEMS; ++it) {
+            if (oo[it] < 0) continue;
+            vout.x[oo[it]] = gx[it];
+            vout.y[oo[it]] = gy[it];
+            vout.z[oo[it]] = gz[it];
+        }
     }
 }
 
-// cell_start from the sorted keys (cell_start[k] = first slot whose key is
-// >= k) and the velocity gather into sorted order.
-template <typename T>
+// cell_start from the sorted keys: cell_start[k] = first slot whose key is
+// >= k.  Each thread covers 4 consecutive slots (one 16-byte load of keys
+// plus the key before them).
 __global__ void __launch_bounds__(256)
-k_sort_finish(const int32_t* __restrict__ keys, const int32_t* __restrict__ perm, int32_t n,
-              int32_t n_cells, int32_t* __restrict__ cell_start, V3<const T> vin, V3<T> vout)
+k_cell_start(const int32_t* __restrict__ keys, int32_t n, int32_t n_cells,
+             int32_t* __restrict__ cell_start)
 {
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s <= n;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t kprev = s > 0 ? keys[s - 1] : -1;
-        const int32_t kcur = s < n ? keys[s] : n_cells + 1;
-        const int32_t khi = kcur < n_cells ? kcur : n_cells;
-        for (int32_t k = kprev + 1; k <= khi; ++k) cell_start[k] = (int32_t)s;
-        if (s < n) {
-            const int32_t p = perm[s];
-            vout.x[s] = vin.x[p];
-            vout.y[s] = vin.y[p];
-            vout.z[s] = vin.z[p];
+    const int64_t n4 = ((int64_t)n + 4) / 4;      // slots 0..n inclusive
+    const bool aligned = (reinterpret_cast<uintptr_t>(keys) & 15) == 0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n4;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s0 = 4 * q;
+        int32_t k[5];
+        k[0] = s0 > 0 ? keys[s0 - 1] : -1;
+        if (s0 + 4 <= n && aligned) {
+            const int4 x = *reinterpret_cast<const int4*>(keys + s0);
+            k[1] = x.x; k[2] = x.y; k[3] = x.z; k[4] = x.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) k[e + 1] = s0 + e < n ? keys[s0 + e] : n_cells + 1;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t s = s0 + e;
+            if (s > n) break;
+            const int32_t khi = k[e + 1] < n_cells ? k[e + 1] : n_cells;
+            for (int32_t c = k[e] + 1; c <= khi; ++c) cell_start[c] = (int32_t)s;
         }
     }
 }
@@ -278,22 +324,35 @@ static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_ve
         DSMC_LAUNCH_CHECK("sort:up");
         int rc = exclusive_scan_i32(ghist, goff, (int64_t)(mask + 1) * nblk, nullptr, scan_ws, s);
         if (rc) return rc;
-        if (pass == 0)
-            k_radix_down<true><<<(int)nblk, SORT_THREADS, 0, s>>>(
-                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx);
+        const bool last = pass == passes - 1;
+        const V3<const T> vi = v3<const T>(vin);
+        const V3<T> vo = v3<T>(vout);
+        if (pass == 0 && last)
+            k_radix_down<true, true, T><<<(int)nblk, SORT_THREADS, 0, s>>>(
+                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
+                vi, vo);
+        else if (pass == 0)
+            k_radix_down<true, false, T><<<(int)nblk, SORT_THREADS, 0, s>>>(
+                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
+                vi, vo);
+        else if (last)
+            k_radix_down<false, true, T><<<(int)nblk, SORT_THREADS, 0, s>>>(
+                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
+                vi, vo);
         else
-            k_radix_down<false><<<(int)nblk, SORT_THREADS, 0, s>>>(
-                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx);
+            k_radix_down<false, false, T><<<(int)nblk, SORT_THREADS, 0, s>>>(
+                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
+                vi, vo);
         DSMC_LAUNCH_CHECK("sort:down");
         kin = kout;
         vin_idx = vout_idx;
     }
     const int pblocks = persistent_blocks(256);
-    int64_t blocks = ((int64_t)n + 1 + 255) / 256;
+    int64_t blocks = ((int64_t)n + 4) / 4;
+    blocks = (blocks + 255) / 256;
     if (blocks > pblocks * 4) blocks = pblocks * 4;
-    k_sort_finish<T><<<(int)blocks, 256, 0, s>>>(keys_b, perm, n, n_cells, cell_start,
-                                                v3<const T>(vin), v3<T>(vout));
-    DSMC_LAUNCH_CHECK("sort:finish");
+    k_cell_start<<<(int)blocks, 256, 0, s>>>(keys_b, n, n_cells, cell_start);
+    DSMC_LAUNCH_CHECK("sort:cell_start");
     return DSMC_OK;
 }
 
