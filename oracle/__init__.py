@@ -65,6 +65,15 @@ class Potential(C.Structure):
 POT_JAGER, POT_HS, POT_INVPOW = 0, 1, 2
 
 
+class Domain(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("Lx", C.c_double), ("Ly", C.c_double),
+                ("kind", C.c_int32 * 4), ("T_w", C.c_double * 4),
+                ("u_w", (C.c_double * 3) * 4), ("m", C.c_double)]
+
+
+WALL_PERIODIC, WALL_SPECULAR, WALL_DIFFUSE = 0, 1, 2
+
+
 def _declare(L):
     L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
     L.orc_sort_cells.argtypes = [C.c_int32, C.c_int32, _i32p, _i32p, _i32p]
@@ -103,6 +112,10 @@ def _declare(L):
                                C.c_double, _f64p, C.c_uint64, C.c_uint32, C.c_int, C.c_int,
                                C.c_int]
     L.orc_step_vhs.restype = C.c_int64
+    L.orc_move.argtypes = [C.c_int32, C.POINTER(Domain), C.c_double, C.c_uint64, C.c_uint32,
+                           _f64p, _f64p, _f64p, _f64p, _f64p, _i32p, C.POINTER(C.c_int64)]
+    L.orc_move.restype = C.c_int64
+    L.orc_sample.argtypes = [C.c_int32, _i32p, _f64p, _f64p, _f64p, _f64p]
 
 
 def _c(a, dt):
@@ -761,3 +774,99 @@ def step_vhs_fast(cell_start, v, xs, lam, seed, step_no, lowp=False, match=False
                                 Cc, e, _c(lam, np.float64), int(seed), int(step_no),
                                 int(bool(lowp)), int(bool(match)), int(n_threads))
     return np.stack([vx, vy, vz]), int(npairs)
+
+
+# ---------------------------------------------------------------------------
+# Flow loop around the collision step (section "Results and Discussion": the
+# Couette channel and the lid-driven cavity).  Move: free flight, wall events,
+# cell index (dsmc_oracle.c, orc_move); sampling of the macroscopic fields.
+# ---------------------------------------------------------------------------
+def domain(nx, ny, Lx, Ly, kinds, T_w, u_w, m):
+    """kinds / T_w / u_w per side (x = 0, x = Lx, y = 0, y = Ly)."""
+    d = Domain()
+    d.nx, d.ny, d.Lx, d.Ly, d.m = int(nx), int(ny), float(Lx), float(Ly), float(m)
+    for q in range(4):
+        d.kind[q] = int(kinds[q])
+        d.T_w[q] = float(T_w[q])
+        for c in range(3):
+            d.u_w[q][c] = float(u_w[q][c])
+    return d
+
+
+def move(dom, pos, v, dt, seed, step_no):
+    """Free flight over dt with wall events (FP64).  pos[2, n], v[3, n] are
+    copied; returns (pos', v', cell_of, n_at_event_limit, n_wall_events)."""
+    pos = np.array(pos, np.float64)
+    v = np.array(v, np.float64)
+    px, py = [np.ascontiguousarray(pos[q]) for q in range(2)]
+    vx, vy, vz = [np.ascontiguousarray(v[q]) for q in range(3)]
+    n = px.size
+    cell = np.zeros(max(n, 1), np.int32)
+    hits = C.c_int64(0)
+    stuck = lib().orc_move(n, C.byref(dom), float(dt), int(seed), int(step_no),
+                           px if n else np.zeros(1), py if n else np.zeros(1),
+                           vx if n else np.zeros(1), vy if n else np.zeros(1),
+                           vz if n else np.zeros(1), cell, C.byref(hits))
+    return np.stack([px, py]), np.stack([vx, vy, vz]), cell[:n], int(stuck), int(hits.value)
+
+
+def sample(cell_start, v, acc=None):
+    """Accumulate the 13 raw moment sums per cell (orc_sample): count, v_i,
+    v_i v_j (xx, yy, zz, xy, xz, yz), |v|^2 v_i."""
+    n_cells = len(cell_start) - 1
+    if acc is None:
+        acc = np.zeros((n_cells, 13))
+    a = np.ascontiguousarray(acc, np.float64).reshape(-1)
+    v = np.asarray(v, np.float64)
+    lib().orc_sample(n_cells, _c(cell_start, np.int32), _c(v[0], np.float64),
+                     _c(v[1], np.float64), _c(v[2], np.float64), a)
+    return a.reshape(n_cells, 13)
+
+
+def fields(acc, n_samples, m, fnum_per_volume):
+    """Macroscopic fields from the raw sums: number density, mean velocity,
+    temperature T = m <|c|^2> / (3 k), shear stress tau_xy = -rho <c_x c_y>,
+    heat flux q_i = rho <|c|^2 c_i> / 2 (c = v - u, rho = n m); per cell,
+    columns (n, ux, uy, uz, T, tau_xy, qx, qy, qz).  fnum_per_volume =
+    F_N / V_cell.  Cells never sampled give zeros."""
+    acc = np.asarray(acc, np.float64)
+    N = acc[:, 0]
+    out = np.zeros((acc.shape[0], 9))
+    ok = N > 0
+    Nn = np.where(ok, N, 1.0)
+    u = acc[:, 1:4] / Nn[:, None]
+    vv = {"xx": acc[:, 4], "yy": acc[:, 5], "zz": acc[:, 6], "xy": acc[:, 7], "xz": acc[:, 8],
+          "yz": acc[:, 9]}
+    m2 = {k: x / Nn for k, x in vv.items()}
+    e2 = m2["xx"] + m2["yy"] + m2["zz"]
+    cc = e2 - np.sum(u * u, axis=1)
+    dens = N / n_samples * fnum_per_volume
+    rho = dens * m
+    # <|c|^2 c_i> = <|v|^2 v_i> - u_i <|v|^2> - 2 u_j <v_j v_i> + 2 |u|^2 u_i
+    vij = np.stack([np.stack([m2["xx"], m2["xy"], m2["xz"]], 1),
+                    np.stack([m2["xy"], m2["yy"], m2["yz"]], 1),
+                    np.stack([m2["xz"], m2["yz"], m2["zz"]], 1)], 1)
+    e3 = acc[:, 10:13] / Nn[:, None]
+    uu = np.sum(u * u, axis=1)
+    c3 = e3 - u * e2[:, None] - 2.0 * np.einsum("kj,kji->ki", u, vij) + 2.0 * uu[:, None] * u
+    out[:, 0] = dens
+    out[:, 1:4] = u
+    out[:, 4] = m * cc / (3.0 * KB)
+    out[:, 5] = -rho * (m2["xy"] - u[:, 0] * u[:, 1])
+    out[:, 6:9] = 0.5 * rho[:, None] * c3
+    out[~ok] = 0.0
+    return out
+
+
+def flow_step(dom, pos, v, xs, lam, dt, seed, step_no, rule="vhs", **kw):
+    """One DSMC step of the flow cases: move (wall events), bin by cell with
+    positions and velocities gathered into cell order, then the collision
+    step of `step` on the sorted velocities.  Returns (pos, v, cell_start,
+    info)."""
+    pos2, v2, cell_of, stuck, hits = move(dom, pos, v, dt, seed, step_no)
+    cs, perm, bad = sort_cells(cell_of, dom.nx * dom.ny)
+    pos3 = pos2[:, perm]
+    v3 = v2[:, perm]
+    vn, info = step(cs, v3, xs, lam, seed, step_no, rule=rule, **kw)
+    info.update({"stuck": stuck, "hits": hits, "perm": perm})
+    return pos3, vn, cs, info

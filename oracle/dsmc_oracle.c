@@ -863,3 +863,143 @@ int64_t orc_step_vhs(int32_t n_cells, const int32_t* cell_start, double* vx,
     }
     return total;
 }
+
+/* ------------------------------------------------------------------------
+ * Free flight, wall interaction and cell index: the DSMC move step around the
+ * collision step (the flow cases of section "Results and Discussion": the
+ * Couette channel between two diffuse walls and the lid-driven cavity with
+ * diffuse walls).  The paper gives no formulas for this part; the standard
+ * method (Bird 1994, ch. 11-12) is followed:
+ *   - ballistic motion over dt, the earliest wall crossing handled first and
+ *     the remaining time flown with the new velocity (at most ORC_MAX_HITS
+ *     wall events per particle and step);
+ *   - periodic sides shift the position by the period, specular sides flip
+ *     the normal velocity, diffuse sides draw the velocity from the wall
+ *     Maxwellian: normal component sigma_w sqrt(-2 ln(1 - U1)) (the flux
+ *     weighted half-range Maxwellian), tangential components u_w + sigma_w n
+ *     with n a Box-Muller pair of (U2, U3), sigma_w = sqrt(k T_w / m);
+ *   - cell index ix = floor(x nx / Lx), clamped to the grid.
+ * Random numbers: the wall event h of the particle in slot s draws
+ * Philox(c0 = s, c1 = h, step, slot 6) -> (U1, U2) and (.., slot 7) -> U3,
+ * 53-bit uniforms.  All arithmetic is FP64.
+ * ---------------------------------------------------------------------- */
+enum { SLOT_WALL0 = 6, SLOT_WALL1 = 7 };
+#define ORC_MAX_HITS 8
+
+static void wall_velocity(const orc_domain* dom, int side, uint64_t seed, uint32_t step,
+                          uint32_t s, uint32_t h, double* vx, double* vy, double* vz)
+{
+    uint32_t r0[4], r1[4];
+    orc_draw(seed, step, s, h, SLOT_WALL0, r0);
+    orc_draw(seed, step, s, h, SLOT_WALL1, r1);
+    const double U1 = u53(r0[0], r0[1]), U2 = u53(r0[2], r0[3]), U3 = u53(r1[0], r1[1]);
+    const double sw = sqrt(ORC_KB * dom->T_w[side] / dom->m);
+    const double vn = sw * sqrt(-2.0 * log(1.0 - U1));
+    double n1, n2;
+    box_muller(U2, U3, &n1, &n2);
+    const double* uw = dom->u_w[side];
+    /* sides 0/1: x = 0 / x = Lx (normal x); 2/3: y = 0 / y = Ly (normal y) */
+    if (side < 2) {
+        *vx = side == 0 ? vn : -vn;
+        *vy = uw[1] + sw * n1;
+        *vz = uw[2] + sw * n2;
+    } else {
+        *vy = side == 2 ? vn : -vn;
+        *vx = uw[0] + sw * n1;
+        *vz = uw[2] + sw * n2;
+    }
+}
+
+int64_t orc_move(int32_t n, const orc_domain* dom, double dt, uint64_t seed, uint32_t step,
+                 double* px, double* py, double* vx, double* vy, double* vz,
+                 int32_t* cell_of, int64_t* n_hits)
+{
+    int64_t stuck = 0, hits = 0;
+    const double Lx = dom->Lx, Ly = dom->Ly;
+    for (int32_t s = 0; s < n; ++s) {
+        double x = px[s], y = py[s], ux = vx[s], uy = vy[s], uz = vz[s];
+        double t = dt;
+        int h = 0;
+        for (;;) {
+            double tx = INFINITY, ty = INFINITY;
+            if (ux > 0.0) tx = (Lx - x) / ux;
+            else if (ux < 0.0) tx = -x / ux;
+            if (uy > 0.0) ty = (Ly - y) / uy;
+            else if (uy < 0.0) ty = -y / uy;
+            if (tx >= t && ty >= t) {
+                x = x + ux * t;
+                y = y + uy * t;
+                break;
+            }
+            if (h == ORC_MAX_HITS) {
+                ++stuck;
+                x = x + ux * t;
+                y = y + uy * t;
+                break;
+            }
+            int side;
+            double th;
+            if (tx <= ty) {
+                side = ux > 0.0 ? 1 : 0;
+                th = tx > 0.0 ? tx : 0.0;
+                y = y + uy * th;
+                x = side == 1 ? Lx : 0.0;
+            } else {
+                side = uy > 0.0 ? 3 : 2;
+                th = ty > 0.0 ? ty : 0.0;
+                x = x + ux * th;
+                y = side == 3 ? Ly : 0.0;
+            }
+            t = t - th;
+            const int kind = dom->kind[side];
+            if (kind == ORC_WALL_PERIODIC) {
+                if (side == 0) x = Lx;
+                else if (side == 1) x = 0.0;
+                else if (side == 2) y = Ly;
+                else y = 0.0;
+            } else if (kind == ORC_WALL_SPECULAR) {
+                if (side < 2) ux = -ux; else uy = -uy;
+            } else {
+                wall_velocity(dom, side, seed, step, (uint32_t)s, (uint32_t)h, &ux, &uy, &uz);
+            }
+            ++h;
+            ++hits;
+        }
+        /* keep the position inside the box (rounding at the walls) */
+        if (x < 0.0) x = 0.0;
+        if (x > Lx) x = Lx;
+        if (y < 0.0) y = 0.0;
+        if (y > Ly) y = Ly;
+        px[s] = x; py[s] = y; vx[s] = ux; vy[s] = uy; vz[s] = uz;
+        int32_t ix = (int32_t)(x * ((double)dom->nx / Lx));
+        int32_t iy = (int32_t)(y * ((double)dom->ny / Ly));
+        ix = ix < 0 ? 0 : (ix >= dom->nx ? dom->nx - 1 : ix);
+        iy = iy < 0 ? 0 : (iy >= dom->ny ? dom->ny - 1 : iy);
+        cell_of[s] = iy * dom->nx + ix;
+    }
+    if (n_hits) *n_hits = hits;
+    return stuck;
+}
+
+/* ------------------------------------------------------------------------
+ * Cell sampling for the macroscopic fields (velocity, temperature, shear
+ * stress and heat flux of the flow results): per cell, raw moment sums
+ * acc[13k + ...] += (1, vx, vy, vz, vx^2, vy^2, vz^2, vx vy, vx vz, vy vz,
+ * |v|^2 vx, |v|^2 vy, |v|^2 vz), in slot order.
+ * ---------------------------------------------------------------------- */
+void orc_sample(int32_t n_cells, const int32_t* cell_start, const double* vx,
+                const double* vy, const double* vz, double* acc)
+{
+    for (int32_t k = 0; k < n_cells; ++k) {
+        double* a = acc + 13 * (size_t)k;
+        for (int32_t s = cell_start[k]; s < cell_start[k + 1]; ++s) {
+            const double x = vx[s], y = vy[s], z = vz[s];
+            const double e = x * x + y * y + z * z;
+            a[0] += 1.0;
+            a[1] += x; a[2] += y; a[3] += z;
+            a[4] += x * x; a[5] += y * y; a[6] += z * z;
+            a[7] += x * y; a[8] += x * z; a[9] += y * z;
+            a[10] += e * x; a[11] += e * y; a[12] += e * z;
+        }
+    }
+}

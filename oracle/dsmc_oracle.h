@@ -116,6 +116,31 @@ int64_t orc_step_vhs(int32_t n_cells, const int32_t* cell_start, double* vx,
                      const double* lambda, uint64_t seed, uint32_t step,
                      int lowp, int moment_match, int n_threads);
 
+/* Domain of the move step: nx x ny uniform cells over [0, Lx] x [0, Ly];
+ * sides 0..3 = x = 0, x = Lx, y = 0, y = Ly, each periodic, specular or
+ * diffuse (wall temperature T_w, wall velocity u_w); m = particle mass. */
+enum { ORC_WALL_PERIODIC = 0, ORC_WALL_SPECULAR = 1, ORC_WALL_DIFFUSE = 2 };
+typedef struct {
+    int32_t nx, ny;
+    double Lx, Ly;
+    int32_t kind[4];
+    double T_w[4];
+    double u_w[4][3];
+    double m;
+} orc_domain;
+
+/* Move step: free flight over dt with wall events; positions and velocities
+ * updated in place, cell_of[n] written.  Returns the number of particles that
+ * reached the wall-event limit; *n_hits = wall events. */
+int64_t orc_move(int32_t n, const orc_domain* dom, double dt, uint64_t seed, uint32_t step,
+                 double* px, double* py, double* vx, double* vy, double* vz,
+                 int32_t* cell_of, int64_t* n_hits);
+
+/* Raw per-cell moment sums for the macroscopic fields (13 per cell,
+ * accumulated into acc). */
+void orc_sample(int32_t n_cells, const int32_t* cell_start, const double* vx,
+                const double* vy, const double* vz, double* acc);
+
 #ifdef __cplusplus
 }
 #endif

@@ -330,3 +330,102 @@ def mlp_init(seed: int, dims, scale: float = 1.0):
 
 SURROGATE_DIMS = (8, 128, 128, 128, 128, 3)
 FD_DIMS = (8, 16, 3)
+
+
+# --------------------------------------------------------------------------
+# Flow cases around the collision step (section "Results and Discussion")
+# --------------------------------------------------------------------------
+WALL_PERIODIC, WALL_SPECULAR, WALL_DIFFUSE = 0, 1, 2
+
+
+@dataclass
+class Flow:
+    """A gas in a box of nx x ny cells over [0, Lx] x [0, Ly] (unit depth in
+    z): positions pos[2, N], velocities v[3, N], per-side wall description
+    (x = 0, x = Lx, y = 0, y = Ly), time step and collision-rate parameter
+    lam = F_N dt / V_c per cell."""
+    nx: int
+    ny: int
+    Lx: float
+    Ly: float
+    kinds: tuple
+    T_w: tuple
+    u_w: tuple
+    pos: np.ndarray
+    v: np.ndarray
+    dt: float
+    lam: np.ndarray
+    xs: dict
+    n_density: float
+    fnum_per_volume: float      # F_N / V_c
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[1])
+
+    @property
+    def n_cells(self) -> int:
+        return self.nx * self.ny
+
+
+def _hs_mean_free_path_density(kn_length: float) -> float:
+    """Number density whose hard-sphere mean free path 1/(sqrt(2) pi d^2 n),
+    with the argon VHS reference diameter, equals kn_length (the reading of
+    the paper's Knudsen numbers: Kn = lambda / L)."""
+    return 1.0 / (math.sqrt(2.0) * math.pi * AR_D_REF ** 2 * kn_length)
+
+
+def _fill(rng, n, Lx, Ly, T, u):
+    pos = np.stack([rng.uniform(0.0, Lx, n), rng.uniform(0.0, Ly, n)])
+    v = rng.normal(0.0, maxwell_sigma(T), size=(3, n))
+    v[0] += u[0]
+    v[1] += u[1]
+    return pos, v
+
+
+def _time_step(n_density, dx, u_max, T):
+    """A fifth of the hard-sphere mean collision time, and no more than a
+    third of a cell crossed at u_max + 3 most-probable speeds."""
+    c_mean = math.sqrt(8.0 * KB * T / (math.pi * AR_MASS))
+    lam_mfp = 1.0 / (math.sqrt(2.0) * math.pi * AR_D_REF ** 2 * n_density)
+    c_mp = math.sqrt(2.0 * KB * T / AR_MASS)
+    return min(0.2 * lam_mfp / c_mean, dx / (3.0 * (u_max + 3.0 * c_mp)))
+
+
+def couette_flow(seed: int = 7, ny: int = 50, ppc: int = 100, L: float = 1.0e-3,
+                 kn: float = 0.2, u_wall: float = 500.0, T_wall: float = 273.0) -> Flow:
+    """Planar Couette flow of argon (the paper's rarefied Couette case): walls
+    at y = 0 and y = L moving at -u_wall and +u_wall in x, diffuse at T_wall;
+    periodic in x over one cell width; gas initially at rest at T_wall."""
+    rng = np.random.default_rng(seed)
+    n_cells = ny
+    n = ppc * n_cells
+    dy = L / ny
+    Lx = dy
+    pos, v = _fill(rng, n, Lx, L, T_wall, (0.0, 0.0))
+    nd = _hs_mean_free_path_density(kn * L)
+    dt = _time_step(nd, dy, u_wall, T_wall)
+    lam = np.full(n_cells, nd * dt / ppc)
+    return Flow(1, ny, Lx, L, (WALL_PERIODIC, WALL_PERIODIC, WALL_DIFFUSE, WALL_DIFFUSE),
+                (T_wall,) * 4,
+                ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (-u_wall, 0.0, 0.0), (u_wall, 0.0, 0.0)),
+                pos, v, dt, lam, _vhs_xs(), nd, nd / ppc, name="couette")
+
+
+def cavity_flow(seed: int = 8, nx: int = 50, ny: int = 50, ppc: int = 100,
+                L: float = 1.0e-3, kn: float = 0.1, u_lid: float = 100.0,
+                T_wall: float = 273.15) -> Flow:
+    """Lid-driven cavity of argon (the paper's generalisation test: side L =
+    1 mm, 50 x 50 cells, 100 particles per cell, Kn = 0.1, lid at y = L moving
+    at u_lid in x, all walls diffuse at T_wall); gas initially at rest."""
+    rng = np.random.default_rng(seed)
+    n_cells = nx * ny
+    n = ppc * n_cells
+    pos, v = _fill(rng, n, L, L, T_wall, (0.0, 0.0))
+    nd = _hs_mean_free_path_density(kn * L)
+    dt = _time_step(nd, L / max(nx, ny), u_lid, T_wall)
+    lam = np.full(n_cells, nd * dt / ppc)
+    return Flow(nx, ny, L, L, (WALL_DIFFUSE,) * 4, (T_wall,) * 4,
+                ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (u_lid, 0.0, 0.0)),
+                pos, v, dt, lam, _vhs_xs(), nd, nd / ppc, name="cavity")
