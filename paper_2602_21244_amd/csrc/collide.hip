@@ -179,14 +179,16 @@ __device__ __forceinline__ bool any_pending(uint32_t pend)
 }
 
 // LDS of one staged cell: velocities [3][NMAX]; a union of the round-search
-// table first[NMAX] and the bucketed Phase-A results pay[PMAX][W]; the
+// tables first[TABLES][NMAX] (two for multi-wave workgroups, see pair_batch)
+// and the bucketed Phase-A results pay[PMAX][W]; the
 // bucketed pair records rab[PMAX] (slot a | slot b << 16); the round table
 // rc[RMAX + 1] (counts, then starts).
 template <typename T, int RULE, int NT, int PPL, int NMAX, int RMAX>
 struct CellLds {
     static constexpr int PMAX = NT * PPL;
+    static constexpr int TABLES = NT > 64 ? 2 : 1;
     static constexpr size_t v_bytes = (size_t)3 * NMAX * sizeof(T);
-    static constexpr size_t f_bytes = (size_t)NMAX * sizeof(int32_t);
+    static constexpr size_t f_bytes = (size_t)TABLES * NMAX * sizeof(int32_t);
     static constexpr size_t p_bytes = (size_t)PMAX * Payload<T, RULE>::W * sizeof(T);
     static constexpr size_t u_bytes = f_bytes > p_bytes ? f_bytes : p_bytes;
     static constexpr size_t bytes = v_bytes + u_bytes + (size_t)PMAX * 4 + (size_t)(RMAX + 1) * 4;
@@ -225,18 +227,19 @@ __device__ __forceinline__ void round_scan(int32_t* rc, int32_t R)
     }
 }
 
-// One cell: c pairs from offset o with slots in [lo, lo + span) (span <=
-// NMAX, c <= NT * PPL); pa_g / pb_g are this thread's pairs (global slots,
-// padded with lo).  On return the updated velocities are in LDS (and in v if
-// WB).
-template <typename T, int RULE, int NT, int PPL, int NMAX, int RMAX, bool WB>
-__device__ __forceinline__ void cell_rounds(const PairsView& pr, V3<T> v, const PairBuf<T>& d,
-                                            int32_t c, int64_t o, int32_t lo, int32_t span,
-                                            const int32_t (&pa_g)[PPL],
-                                            const int32_t (&pb_g)[PPL],
-                                            const CellLds<T, RULE, NT, PPL, NMAX, RMAX>& L)
+// One batch of c <= NT * PPL pairs (from offset o) of a cell whose
+// velocities (slots [lo, lo + span), span <= NMAX) are staged in L; pa_g /
+// pb_g are this thread's pairs (global slots, padded with lo).  Applies the
+// batch in candidate order and ends with a barrier.  A cell with more pairs
+// than one batch holds runs its batches one after another in candidate order.
+template <typename T, int RULE, int NT, int PPL, int NMAX, int RMAX>
+__device__ __forceinline__ void pair_batch(const PairBuf<T>& d, int32_t c, int64_t o, int32_t lo,
+                                           int32_t span, const int32_t (&pa_g)[PPL],
+                                           const int32_t (&pb_g)[PPL],
+                                           const CellLds<T, RULE, NT, PPL, NMAX, RMAX>& L)
 {
     constexpr int W = Payload<T, RULE>::W;
+    constexpr bool DUAL = CellLds<T, RULE, NT, PPL, NMAX, RMAX>::TABLES == 2;
     const int t = threadIdx.x;
     int32_t pa[PPL], pb[PPL], rnd[PPL];
     Payload<T, RULE> pl[PPL];
@@ -253,31 +256,58 @@ __device__ __forceinline__ void cell_rounds(const PairsView& pr, V3<T> v, const 
         }
     }
     for (int32_t q = t; q < span; q += NT) {
-        L.lx[q] = v.x[lo + q];
-        L.ly[q] = v.y[lo + q];
-        L.lz[q] = v.z[lo + q];
         L.first[q] = INT32_MAX;
+        if (DUAL) L.first[NMAX + q] = INT32_MAX;
     }
     int32_t r = 0;
-    while (any_pending<NT>(pend)) {
-        const int32_t kb = (ROUND_MAX - r) << 16;
-#pragma unroll
-        for (int m = 0; m < PPL; ++m)
-            if (pend & (1u << m)) {
-                const int32_t key = kb | (t + NT * m);
-                atomicMin(&L.first[pa[m]], key);
-                atomicMin(&L.first[pb[m]], key);
-            }
+    if (DUAL) {
+        // Rounds alternate between two tables, so one barrier per round
+        // suffices: a wave may offer round r + 1's keys while others still
+        // read round r's table, and a table is written again only after every
+        // wave has passed the barrier that follows the reads of it.
         __syncthreads();
+        for (;;) {
+            int32_t* tb = L.first + (r & 1) * NMAX;
+            const int32_t kb = (ROUND_MAX - r) << 16;
 #pragma unroll
-        for (int m = 0; m < PPL; ++m) {
-            const int32_t key = kb | (t + NT * m);
-            if ((pend & (1u << m)) && L.first[pa[m]] == key && L.first[pb[m]] == key) {
-                rnd[m] = r;
-                pend &= ~(1u << m);
+            for (int m = 0; m < PPL; ++m)
+                if (pend & (1u << m)) {
+                    const int32_t key = kb | (t + NT * m);
+                    atomicMin(&tb[pa[m]], key);
+                    atomicMin(&tb[pb[m]], key);
+                }
+            if (!any_pending<NT>(pend)) break;
+#pragma unroll
+            for (int m = 0; m < PPL; ++m) {
+                const int32_t key = kb | (t + NT * m);
+                if ((pend & (1u << m)) && tb[pa[m]] == key && tb[pb[m]] == key) {
+                    rnd[m] = r;
+                    pend &= ~(1u << m);
+                }
             }
+            ++r;
         }
-        ++r;
+    } else {
+        while (any_pending<NT>(pend)) {
+            const int32_t kb = (ROUND_MAX - r) << 16;
+#pragma unroll
+            for (int m = 0; m < PPL; ++m)
+                if (pend & (1u << m)) {
+                    const int32_t key = kb | (t + NT * m);
+                    atomicMin(&L.first[pa[m]], key);
+                    atomicMin(&L.first[pb[m]], key);
+                }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < PPL; ++m) {
+                const int32_t key = kb | (t + NT * m);
+                if ((pend & (1u << m)) && L.first[pa[m]] == key && L.first[pb[m]] == key) {
+                    rnd[m] = r;
+                    pend &= ~(1u << m);
+                }
+            }
+            ++r;
+        }
     }
     const int32_t R = r;
     if (R <= RMAX) {
@@ -317,14 +347,43 @@ __device__ __forceinline__ void cell_rounds(const PairsView& pr, V3<T> v, const 
             __syncthreads();
         }
     }
-    if (WB) {
-        for (int32_t q = t; q < span; q += NT) {
-            v.x[lo + q] = L.lx[q];
-            v.y[lo + q] = L.ly[q];
-            v.z[lo + q] = L.lz[q];
-        }
-        __syncthreads();
+}
+
+template <typename T, int RULE, int NT, int PPL, int NMAX, int RMAX>
+__device__ __forceinline__ void stage_cell(V3<T> v, int32_t lo, int32_t span,
+                                           const CellLds<T, RULE, NT, PPL, NMAX, RMAX>& L)
+{
+    for (int32_t q = threadIdx.x; q < span; q += NT) {
+        L.lx[q] = v.x[lo + q];
+        L.ly[q] = v.y[lo + q];
+        L.lz[q] = v.z[lo + q];
     }
+}
+
+template <typename T, int RULE, int NT, int PPL, int NMAX, int RMAX>
+__device__ __forceinline__ void unstage_cell(V3<T> v, int32_t lo, int32_t span,
+                                             const CellLds<T, RULE, NT, PPL, NMAX, RMAX>& L)
+{
+    for (int32_t q = threadIdx.x; q < span; q += NT) {
+        v.x[lo + q] = L.lx[q];
+        v.y[lo + q] = L.ly[q];
+        v.z[lo + q] = L.lz[q];
+    }
+    __syncthreads();
+}
+
+// One cell of at most NT * PPL pairs: stage, apply, and (WB) write back.
+template <typename T, int RULE, int NT, int PPL, int NMAX, int RMAX, bool WB>
+__device__ __forceinline__ void cell_rounds(const PairsView& pr, V3<T> v, const PairBuf<T>& d,
+                                            int32_t c, int64_t o, int32_t lo, int32_t span,
+                                            const int32_t (&pa_g)[PPL],
+                                            const int32_t (&pb_g)[PPL],
+                                            const CellLds<T, RULE, NT, PPL, NMAX, RMAX>& L)
+{
+    (void)pr;
+    stage_cell(v, lo, span, L);
+    pair_batch(d, c, o, lo, span, pa_g, pb_g, L);
+    if (WB) unstage_cell(v, lo, span, L);
 }
 
 // Min / max of the cell's pair slots over the workgroup.
@@ -346,6 +405,81 @@ __device__ __forceinline__ void group_minmax(int32_t& lo, int32_t& hi, int32_t* 
     __syncthreads();
 }
 
+// BLOCK schedule, in two size classes so that the common large cells keep two
+// workgroups per CU:
+//   medium: 256 threads, cells whose pairs span up to 2496 slots (1280 for
+//           FP64 velocities), LDS rounds on batches of 2048 pairs (1024);
+//   big:    512 threads, spans up to 4096 slots (2048) in LDS, batches of
+//           4096 pairs (2048); larger cells (up to 8192 pairs and slots) run
+//           the rounds on velocities in global memory with the tables in LDS;
+//           beyond that one thread applies the pairs in order.
+// The WAVE kernel lists the cells it cannot hold (list[0] = length, then k
+// for a medium cell or -1 - k for a big one); each class kernel works through
+// the list and takes its own entries.  Without a list every cell with at
+// least min_pairs pairs is classified in the kernel.
+constexpr int BLK_GMAX = 8192;      // global-memory rounds
+template <typename T, bool BIG> struct BlkShape;
+template <> struct BlkShape<float, false> {
+    static constexpr int NT = 256, PPL = 8, NMAX = 2496, RMAX = 512;
+};
+template <> struct BlkShape<float, true> {
+    static constexpr int NT = 512, PPL = 8, NMAX = 4096, RMAX = 1024;
+};
+template <> struct BlkShape<double, false> {
+    static constexpr int NT = 256, PPL = 4, NMAX = 1280, RMAX = 512;
+};
+template <> struct BlkShape<double, true> {
+    static constexpr int NT = 512, PPL = 4, NMAX = 2048, RMAX = 1024;
+};
+template <typename T, int RULE, bool BIG>
+using BlockLds = CellLds<T, RULE, BlkShape<T, BIG>::NT, BlkShape<T, BIG>::PPL,
+                         BlkShape<T, BIG>::NMAX, BlkShape<T, BIG>::RMAX>;
+
+template <typename T, int RULE, bool BIG>
+struct BlkSmem {
+    static constexpr size_t glb = BIG ? (size_t)BLK_GMAX * 2 * sizeof(int32_t) : 0;
+    static constexpr size_t bytes =
+        BlockLds<T, RULE, BIG>::bytes > glb ? BlockLds<T, RULE, BIG>::bytes : glb;
+};
+
+// Size class of a cell whose pairs span `span` slots (any pair count: the
+// pairs run in batches of NT * PPL).
+template <typename T>
+__host__ __device__ __forceinline__ bool is_big_cell(int32_t c, int32_t span)
+{
+    (void)c;
+    return span > BlkShape<T, false>::NMAX;
+}
+
+// Work list of the cells the WAVE kernel cannot hold, in the sixth Phase-A
+// field: p[0] = number of heavy cells (more pairs than one medium batch),
+// stored from p[2] upward; p[1] = number of the others, stored from p[top]
+// downward, top = the first int32 past the field (inside the workspace's
+// 256-byte tail).  Heavy cells are handed out first, which balances the block
+// kernels' long cells.  An entry is k (medium class) or -1 - k (big class).
+// Every listed cell holds a pair, so the entries number at most cap < top - 1
+// and the two ends never meet or reach the counters.
+struct CellList {
+    int32_t* p;
+    int64_t top;
+};
+
+template <typename T>
+__device__ __forceinline__ void list_cell(const CellList& L, int32_t k, int32_t c, int32_t span)
+{
+    using M = BlkShape<T, false>;
+    const int32_t e = is_big_cell<T>(c, span) ? -1 - k : k;
+    if (c > M::NT * M::PPL) {
+        const int32_t at = atomicAdd(&L.p[0], 1);
+        L.p[2 + at] = e;
+    } else {
+        const int32_t at = atomicAdd(&L.p[1], 1);
+        L.p[L.top - at] = e;
+    }
+}
+
+__device__ __forceinline__ int64_t list_items(const CellList& L) { return (int64_t)L.p[0] + L.p[1]; }
+
 // WAVE schedule: one 64-lane workgroup per cell with at most 256 pairs whose
 // slots span at most 512 (small LDS tables, so many workgroups stay resident
 // to hide the cell loads); every other cell goes to the list the BLOCK kernel
@@ -360,7 +494,7 @@ using WaveLds = CellLds<T, RULE, 64, WV_PPL, WV_NMAX, WV_RMAX>;
 template <typename T, int RULE>
 __global__ void __launch_bounds__(64)
 k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
-              int32_t* list)
+              CellList list)
 {
     __shared__ __attribute__((aligned(16))) char smem[WaveLds<T, RULE>::bytes];
     const WaveLds<T, RULE> L(smem);
@@ -378,10 +512,13 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
         o32 = o_next;
         if (cc == 0 || cc < min_pairs) continue;
         if (cc > 64 * WV_PPL) {
-            if (lane == 0) {
-                const int32_t at = atomicAdd(&list[0], 1);
-                list[1 + at] = (int32_t)k;
+            int32_t lo = INT32_MAX, hi = -1;
+            for (int32_t q = lane; q < cc; q += 64) {
+                lo = min(lo, min(pr.i[o + q], pr.j[o + q]));
+                hi = max(hi, max(pr.i[o + q], pr.j[o + q]));
             }
+            group_minmax<64>(lo, hi, nullptr);
+            if (lane == 0) list_cell<T>(list, (int32_t)k, cc, hi - lo + 1);
             continue;
         }
         int32_t pa[WV_PPL], pb[WV_PPL];
@@ -401,10 +538,7 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
         group_minmax<64>(lo, hi, nullptr);
         const int32_t span = hi - lo + 1;
         if (span > WV_NMAX) {
-            if (lane == 0) {
-                const int32_t at = atomicAdd(&list[0], 1);
-                list[1 + at] = (int32_t)k;
-            }
+            if (lane == 0) list_cell<T>(list, (int32_t)k, cc, span);
             continue;
         }
 #pragma unroll
@@ -415,42 +549,20 @@ k_phaseB_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_
     }
 }
 
-// BLOCK schedule: 512 threads per cell.  Cells with up to 4096 pairs (2048
-// for FP64 velocities) spanning up to 4096 slots (2048) run the LDS rounds;
-// larger ones (up to 8192) run the rounds on velocities in global memory with
-// the tables in LDS; beyond that one thread applies the pairs in order.
-// Works through the cells in `list` after the WAVE kernel, or (list ==
-// nullptr) every cell with at least min_pairs pairs.
-constexpr int BLK_THREADS = 512;
-constexpr int BLK_GMAX = 8192;      // global-memory rounds
-constexpr int BLK_RMAX = 1024;
-template <typename T> struct BlkShape;
-template <> struct BlkShape<float> { static constexpr int PPL = 8, NMAX = 4096; };
-template <> struct BlkShape<double> { static constexpr int PPL = 4, NMAX = 2048; };
-template <typename T, int RULE>
-using BlockLds = CellLds<T, RULE, BLK_THREADS, BlkShape<T>::PPL, BlkShape<T>::NMAX, BLK_RMAX>;
-
-template <typename T, int RULE>
-struct BlkSmem {
-    static constexpr size_t glb = (size_t)BLK_GMAX * 2 * sizeof(int32_t);
-    static constexpr size_t bytes =
-        BlockLds<T, RULE>::bytes > glb ? BlockLds<T, RULE>::bytes : glb;
-};
-
-template <typename T, int RULE>
+template <typename T, int RULE, int NT>
 __device__ void cell_rounds_global(V3<T> v, const PairBuf<T>& d, const PairsView& pr, int32_t c,
                                    int64_t o, int32_t lo, int32_t span, int32_t* first,
                                    uint32_t* pij)
 {
     __shared__ int32_t remaining;
-    for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS)
+    for (int32_t q = threadIdx.x; q < c; q += NT)
         pij[q] = (uint32_t)(pr.i[o + q] - lo) | ((uint32_t)(pr.j[o + q] - lo) << 16);
     if (threadIdx.x == 0) remaining = c;
     __syncthreads();
     while (remaining > 0) {
-        for (int32_t q = threadIdx.x; q < span; q += BLK_THREADS) first[q] = INT32_MAX;
+        for (int32_t q = threadIdx.x; q < span; q += NT) first[q] = INT32_MAX;
         __syncthreads();
-        for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS) {
+        for (int32_t q = threadIdx.x; q < c; q += NT) {
             const uint32_t w = pij[q];
             if (w != 0xffffffffu) {
                 atomicMin(&first[w & 0xffff], q);
@@ -459,7 +571,7 @@ __device__ void cell_rounds_global(V3<T> v, const PairBuf<T>& d, const PairsView
         }
         __syncthreads();
         int done_here = 0;
-        for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS) {
+        for (int32_t q = threadIdx.x; q < c; q += NT) {
             const uint32_t w = pij[q];
             if (w == 0xffffffffu) continue;
             const int32_t li = w & 0xffff, lj = w >> 16;
@@ -475,35 +587,40 @@ __device__ void cell_rounds_global(V3<T> v, const PairBuf<T>& d, const PairsView
     }
 }
 
-// One BLOCK cell (pairs [o, o + c), slots [lo, lo + span)); LDS: updated
-// velocities left in L when the LDS rounds ran (returns true), else in v.
-template <typename T, int RULE, bool WB>
+// One BLOCK cell (pairs [o, o + c), slots [lo, lo + span)); the updated
+// velocities are left in LDS when the LDS rounds ran (returns true), else in
+// v.  The medium class is only given cells that fit its LDS tables.
+template <typename T, int RULE, bool BIG, bool WB>
 __device__ __forceinline__ bool block_cell(const PairsView& pr, V3<T> v, const PairBuf<T>& d,
                                            int32_t c, int64_t o, int32_t lo, int32_t span,
                                            char* smem)
 {
-    constexpr int PPL = BlkShape<T>::PPL, NMAX = BlkShape<T>::NMAX;
-    if (c <= BLK_THREADS * PPL && span <= NMAX) {
-        int32_t pa[PPL], pb[PPL];
+    using S = BlkShape<T, BIG>;
+    if (span <= S::NMAX) {
+        const BlockLds<T, RULE, BIG> L(smem);
+        stage_cell(v, lo, span, L);
+        for (int32_t b = 0; b < c; b += S::NT * S::PPL) {
+            const int32_t cb = c - b < S::NT * S::PPL ? c - b : S::NT * S::PPL;
+            int32_t pa[S::PPL], pb[S::PPL];
 #pragma unroll
-        for (int m = 0; m < PPL; ++m) {
-            const int32_t q = threadIdx.x + BLK_THREADS * m;
-            pa[m] = lo;
-            pb[m] = lo;
-            if (q < c) {
-                pa[m] = pr.i[o + q];
-                pb[m] = pr.j[o + q];
+            for (int m = 0; m < S::PPL; ++m) {
+                const int32_t q = threadIdx.x + S::NT * m;
+                pa[m] = lo;
+                pb[m] = lo;
+                if (q < cb) {
+                    pa[m] = pr.i[o + b + q];
+                    pb[m] = pr.j[o + b + q];
+                }
             }
+            pair_batch(d, cb, o + b, lo, span, pa, pb, L);
         }
-        const BlockLds<T, RULE> L(smem);
-        cell_rounds<T, RULE, BLK_THREADS, PPL, NMAX, BLK_RMAX, WB>(pr, v, d, c, o, lo, span, pa,
-                                                                   pb, L);
+        if (WB) unstage_cell(v, lo, span, L);
         return true;
     }
-    if (c <= BLK_GMAX && span <= BLK_GMAX) {
+    if (BIG && c <= BLK_GMAX && span <= BLK_GMAX) {
         int32_t* gfirst = reinterpret_cast<int32_t*>(smem);
         uint32_t* pij = reinterpret_cast<uint32_t*>(gfirst + BLK_GMAX);
-        cell_rounds_global<T, RULE>(v, d, pr, c, o, lo, span, gfirst, pij);
+        cell_rounds_global<T, RULE, S::NT>(v, d, pr, c, o, lo, span, gfirst, pij);
     } else {
         // beyond the LDS tables: sequential, still in candidate order
         if (threadIdx.x == 0)
@@ -514,18 +631,30 @@ __device__ __forceinline__ bool block_cell(const PairsView& pr, V3<T> v, const P
     return false;
 }
 
-template <typename T, int RULE>
-__global__ void __launch_bounds__(BLK_THREADS)
-k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
-               const int32_t* list)
+// Entry idx of the work list, or -1 when it belongs to the other class.
+template <bool BIG>
+__device__ __forceinline__ int32_t class_cell(const CellList& L, int64_t idx)
 {
-    __shared__ __attribute__((aligned(16))) char smem[BlkSmem<T, RULE>::bytes];
-    __shared__ int32_t red[2 * (BLK_THREADS / 64)];
-    const int64_t n_items = list ? (int64_t)list[0] : (int64_t)n_cells;
+    const int32_t a = L.p[0];
+    const int32_t e = idx < a ? L.p[2 + idx] : L.p[L.top - (idx - a)];
+    if (BIG) return e < 0 ? -1 - e : -1;
+    return e >= 0 ? e : -1;
+}
+
+template <typename T, int RULE, bool BIG>
+__global__ void __launch_bounds__((BlkShape<T, BIG>::NT))
+k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min_pairs,
+               CellList list, bool use_list)
+{
+    constexpr int NT = BlkShape<T, BIG>::NT;
+    __shared__ __attribute__((aligned(16))) char smem[BlkSmem<T, RULE, BIG>::bytes];
+    __shared__ int32_t red[2 * (NT / 64)];
+    const int64_t n_items = use_list ? list_items(list) : (int64_t)n_cells;
     for (int64_t idx = blockIdx.x; idx < n_items; idx += gridDim.x) {
         int32_t k;
-        if (list) {
-            k = list[1 + idx];
+        if (use_list) {
+            k = class_cell<BIG>(list, idx);
+            if (k < 0) continue;
         } else {
             k = (int32_t)idx;
             const int32_t c = pr.cnt[k];
@@ -534,12 +663,14 @@ k_phaseB_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, int32_t min
         const int32_t c = pr.cnt[k];
         const int64_t o = pr.off[k];
         int32_t lo = INT32_MAX, hi = -1;
-        for (int32_t q = threadIdx.x; q < c; q += BLK_THREADS) {
+        for (int32_t q = threadIdx.x; q < c; q += NT) {
             lo = min(lo, min(pr.i[o + q], pr.j[o + q]));
             hi = max(hi, max(pr.i[o + q], pr.j[o + q]));
         }
-        group_minmax<BLK_THREADS>(lo, hi, red);
-        block_cell<T, RULE, true>(pr, v, d, c, o, lo, hi - lo + 1, smem);
+        group_minmax<NT>(lo, hi, red);
+        const int32_t span = hi - lo + 1;
+        if (!use_list && is_big_cell<T>(c, span) != BIG) continue;
+        block_cell<T, RULE, BIG, true>(pr, v, d, c, o, lo, span, smem);
         __syncthreads();
     }
 }
@@ -619,7 +750,7 @@ template <typename T> struct CellView {
 template <typename T, int RULE>
 __global__ void __launch_bounds__(64)
 k_phaseB_match_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchArgs ma,
-                    int32_t* list)
+                    CellList list)
 {
     __shared__ __attribute__((aligned(16))) char smem[WaveLds<T, RULE>::bytes];
     const WaveLds<T, RULE> L(smem);
@@ -643,10 +774,7 @@ k_phaseB_match_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchA
         s1 = s1_next;
         if (cc == 0 || N < 2) continue;
         if (cc > 64 * WV_PPL || N > WV_NMAX) {
-            if (lane == 0) {
-                const int32_t at = atomicAdd(&list[0], 1);
-                list[1 + at] = (int32_t)k;
-            }
+            if (lane == 0) list_cell<T>(list, (int32_t)k, cc, N);
             continue;
         }
         int32_t pa[WV_PPL], pb[WV_PPL];
@@ -668,24 +796,25 @@ k_phaseB_match_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchA
     }
 }
 
-// BLOCK form for the listed cells; the first wave matches.
-template <typename T, int RULE>
-__global__ void __launch_bounds__(BLK_THREADS)
+// BLOCK forms (medium, big) for the listed cells; the first wave matches.
+template <typename T, int RULE, bool BIG>
+__global__ void __launch_bounds__((BlkShape<T, BIG>::NT))
 k_phaseB_match_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchArgs ma,
-                     const int32_t* list)
+                     CellList list)
 {
-    __shared__ __attribute__((aligned(16))) char smem[BlkSmem<T, RULE>::bytes];
-    const int64_t n_items = list[0];
+    __shared__ __attribute__((aligned(16))) char smem[BlkSmem<T, RULE, BIG>::bytes];
+    const int64_t n_items = list_items(list);
     for (int64_t idx = blockIdx.x; idx < n_items; idx += gridDim.x) {
-        const int32_t k = list[1 + idx];
+        const int32_t k = class_cell<BIG>(list, idx);
+        if (k < 0) continue;
         const int32_t c = pr.cnt[k];
         const int64_t o = pr.off[k];
         const int32_t b0 = ma.cell_start[k], N = ma.cell_start[k + 1] - b0;
-        const bool in_lds = block_cell<T, RULE, false>(pr, v, d, c, o, b0, N, smem);
+        const bool in_lds = block_cell<T, RULE, BIG, false>(pr, v, d, c, o, b0, N, smem);
         if (threadIdx.x < 64) {
             const double* m = ma.mom + 6 * (size_t)k;
             if (in_lds) {
-                const BlockLds<T, RULE> L(smem);
+                const BlockLds<T, RULE, BIG> L(smem);
                 match_cell<T>(CellView<T>{L.lx, L.ly, L.lz}, N, m, ma.literal, v, b0, ma.st);
             } else {
                 match_cell<T>(CellView<T>{v.x + b0, v.y + b0, v.z + b0}, N, m, ma.literal, v, b0,
@@ -695,7 +824,8 @@ k_phaseB_match_block(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, Match
         __syncthreads();
     }
 }
-__global__ void k_zero_i32(int32_t* p) { *p = 0; }
+
+__global__ void k_zero_list(int32_t* p) { p[0] = 0; p[1] = 0; }
 
 int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v,
             const dsmc_pairs& pairs, void* dirs, int64_t cap, int32_t schedule, hipStream_t s)
@@ -719,24 +849,29 @@ int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsm
     wb = wb < 1 ? 1 : wb;
     int bb = n_cells < cus * 2 ? n_cells : cus * 2;
     bb = bb < 1 ? 1 : bb;
+    const int bg = n_cells < cus ? n_cells : cus;
 #define DSMC_PHASEB(T, R)                                                                   \
     do {                                                                                    \
         PairBuf<T> d = PairBuf<T>::of(dirs, cap);                                           \
-        int32_t* list = reinterpret_cast<int32_t*>(d.f);                                    \
+        const CellList list{reinterpret_cast<int32_t*>(d.f),                                \
+                            (cap + 1) * (int64_t)sizeof(T) / 4};                            \
         if (need_lane) {                                                                    \
             k_phaseB_lane<T, R><<<lb, 256, 0, s>>>(n_cells, pr, v3<T>(v), d, thr);          \
             DSMC_LAUNCH_CHECK("phaseB:lane");                                               \
         }                                                                                   \
         if (need_rest && use_wave) {                                                        \
-            k_zero_i32<<<1, 1, 0, s>>>(list);                                               \
+            k_zero_list<<<1, 1, 0, s>>>(list.p);                                            \
             DSMC_LAUNCH_CHECK("phaseB:list");                                               \
             k_phaseB_wave<T, R><<<wb, 64, 0, s>>>(n_cells, pr, v3<T>(v), d, thr + 1, list); \
             DSMC_LAUNCH_CHECK("phaseB:wave");                                               \
         }                                                                                   \
         if (need_rest) {                                                                    \
-            k_phaseB_block<T, R><<<bb, BLK_THREADS, 0, s>>>(                                \
-                n_cells, pr, v3<T>(v), d, thr + 1, use_wave ? list : nullptr);              \
+            k_phaseB_block<T, R, false><<<bb, BlkShape<T, false>::NT, 0, s>>>(              \
+                n_cells, pr, v3<T>(v), d, thr + 1, list, use_wave);                         \
             DSMC_LAUNCH_CHECK("phaseB:block");                                              \
+            k_phaseB_block<T, R, true><<<bg, BlkShape<T, true>::NT, 0, s>>>(                \
+                n_cells, pr, v3<T>(v), d, thr + 1, list, use_wave);                         \
+            DSMC_LAUNCH_CHECK("phaseB:block_big");                                          \
         }                                                                                   \
     } while (0)
     if (dtype == DSMC_F64) {
@@ -815,16 +950,21 @@ extern "C" int dsmc_apply_pairs_match(int32_t n_cells, const int32_t* cell_start
     wb = wb < 1 ? 1 : wb;
     int bb = n_cells < cus * 2 ? n_cells : cus * 2;
     bb = bb < 1 ? 1 : bb;
+    const int bg = n_cells < cus ? n_cells : cus;
 #define DSMC_PHASEB_MATCH(T, R)                                                              \
     do {                                                                                     \
         PairBuf<T> d = PairBuf<T>::of(ws, pairs.cap);                                        \
-        int32_t* list = reinterpret_cast<int32_t*>(d.f);                                     \
-        k_zero_i32<<<1, 1, 0, s>>>(list);                                                    \
+        const CellList list{reinterpret_cast<int32_t*>(d.f),                                 \
+                            (pairs.cap + 1) * (int64_t)sizeof(T) / 4};                       \
+        k_zero_list<<<1, 1, 0, s>>>(list.p);                                                 \
         DSMC_LAUNCH_CHECK("phaseB_match:list");                                              \
         k_phaseB_match_wave<T, R><<<wb, 64, 0, s>>>(n_cells, pr, v3<T>(v), d, ma, list);     \
         DSMC_LAUNCH_CHECK("phaseB_match:wave");                                              \
-        k_phaseB_match_block<T, R><<<bb, BLK_THREADS, 0, s>>>(n_cells, pr, v3<T>(v), d, ma,  \
-                                                              list);                         \
+        k_phaseB_match_block<T, R, false><<<bb, BlkShape<T, false>::NT, 0, s>>>(              \
+            n_cells, pr, v3<T>(v), d, ma, list);                                             \
+        DSMC_LAUNCH_CHECK("phaseB_match:block");                                             \
+        k_phaseB_match_block<T, R, true><<<bg, BlkShape<T, true>::NT, 0, s>>>(               \
+            n_cells, pr, v3<T>(v), d, ma, list);                                             \
         DSMC_LAUNCH_CHECK("phaseB_match:block");                                             \
     } while (0)
     const int rule = kind == DSMC_APPLY_ANGLES ? RULE_CHI : RULE_DIR;

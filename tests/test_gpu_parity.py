@@ -245,9 +245,13 @@ def test_collide_vhs_parity(orc, dev, api, dtype, sched):
     assert err2 < tol, err2
 
 
-def test_schedules_bit_identical(dev, api):
-    say("schedules bit-identical")
-    pop = W.ragged_population(13, 200, 900, empty_frac=0.1)
+@pytest.mark.parametrize("case", ["ragged", "dense"])
+def test_schedules_bit_identical(dev, api, case):
+    say("schedules bit-identical", case)
+    if case == "ragged":
+        pop = W.ragged_population(13, 200, 900, empty_frac=0.1)
+    else:
+        pop = W.ragged_population(35, 60, 1500, empty_frac=0.0, lam_scale=6.0)
     out = []
     for code in (api.L.SCHED_LANE, api.L.SCHED_BLOCK, api.L.SCHED_AUTO, api.L.SCHED_WAVE):
         cell_of = torch.as_tensor(pop.cell_of, device=dev)
@@ -285,17 +289,19 @@ def test_moment_match_apply_modes(orc, dev, api, dtype):
         assert err < tol, (mode, err)
 
 
-@pytest.mark.parametrize("case", ["ragged", "big", "huge"])
+@pytest.mark.parametrize("case", ["ragged", "dense", "big", "huge"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("rule", ["vhs", "table"])
 def test_apply_pairs_match_fused_bit_identical(dev, api, case, dtype, rule):
     """Phase B fused with the moment matching against Phase B followed by the
     matching kernel: bit-identical velocities and skip counts, both modes.
-    ragged: one-wave cells and LDS block cells; big: block cells up to 7000
-    particles (LDS and global-memory rounds); huge: one 9000-particle cell
-    (sequential rounds)."""
+    ragged: one-wave cells and medium block cells; dense: cells of up to 900
+    particles with up to ~3600 pairs (big block cells by pair count, long
+    dependency chains); big: block cells up to 7000 particles (LDS and
+    global-memory rounds); huge: one 9000-particle cell (sequential rounds)."""
     say("apply_pairs_match fused", case, dtype, rule)
     pop = {"ragged": lambda: W.ragged_population(31, 400, 700, empty_frac=0.1),
+           "dense": lambda: W.ragged_population(34, 40, 900, empty_frac=0.0, lam_scale=8.0),
            "big": lambda: W.ragged_population(32, 6, 7000, empty_frac=0.0),
            "huge": lambda: W.ragged_population(8, 1, 9000, empty_frac=0.0)}[case]()
     cs, _, v0, _ = _gpu_sort(api, dev, pop, dtype)
