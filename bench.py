@@ -288,6 +288,14 @@ def main():
     extra["train_step"] = train
     log(f"training step: {train}")
 
+    # the flow loop around the step on the paper's lid-driven cavity (50 x 50
+    # cells, 250 000 particles, Kn = 0.1, lid 100 m/s): move with diffuse
+    # walls, binning, selection, the per-pair network, fused Phase B + moment
+    # matching and sampling every step
+    cav = cavity_loop_timing(W, dev, net)
+    extra["cavity_loop"] = cav
+    log(f"cavity loop: {cav}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pop, Ws, bs, sigma_v, args.cpu_sample_pairs)
@@ -388,6 +396,28 @@ def load_anet(path, workloads, api, dev):
                 "trained")
     Ws, bs = workloads.mlp_init(11, api.ANGLE_DIMS)
     return api.AngleNet(Ws, bs, device=dev), math.log(5.0), math.log(5.0e5), "seeded-init"
+
+
+def cavity_loop_timing(W, dev, net, warm=20, steps=200):
+    import torch
+    from paper_2602_21244_amd.flow import FlowSim
+    fl = W.cavity_flow()
+    sim = FlowSim(fl, dtype=torch.float32, rule="neural", net=net, seed=5, device=dev)
+    sim.run(warm, sample_from=0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.run(steps, sample_from=0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = sim.status()
+    f = sim.fields().cpu().numpy()
+    return {"particles": fl.n, "cells": fl.n_cells, "ms_per_step": ms,
+            "particle_steps_per_s": fl.n / (ms * 1e-3),
+            "pairs_per_step": float(st.n_pairs), "wall_events_per_step":
+            float(st.wall_events) / (warm + steps),
+            "lid_row_mean_ux": float(f[-fl.nx:, 1].mean()), "mean_T": float(f[:, 4].mean())}
 
 
 def train_step_timing(api, W, dev, net, sigma_v, B=65536, steps=5):

@@ -63,13 +63,17 @@ typedef struct {
     int32_t nonfinite;  /* non-finite values met (results left unchanged) */
     int32_t mm_skipped; /* cells that moment matching left alone (S_post <= 0) */
     int32_t prob_clamped; /* SBT trials whose collision probability exceeded 1 */
+    int64_t wall_events;  /* wall crossings handled by dsmc_move */
+    int32_t wall_limit;   /* particles that met the wall-event limit of one move */
+    int32_t reserved;
 } dsmc_status;
 enum {
     DSMC_ST_PAIR_OVERFLOW = 1u, /* candidates exceeded the pair capacity */
     DSMC_ST_BAD_CELL = 2u,
     DSMC_ST_ROOT_FAIL = 4u,
     DSMC_ST_NONFINITE = 8u,
-    DSMC_ST_PROB_CLAMP = 16u    /* an SBT probability exceeded 1 (time step too large) */
+    DSMC_ST_PROB_CLAMP = 16u,   /* an SBT probability exceeded 1 (time step too large) */
+    DSMC_ST_WALL_LIMIT = 32u    /* a particle met 8 wall events in one move */
 };
 
 /* Accepted-pair list, dense and cell-major: the pairs of cell k are entries
@@ -464,6 +468,62 @@ int dsmc_chi_table_build(const dsmc_anet* net, const dsmc_chi_table* tab, void* 
 int dsmc_collide_table(const dsmc_chi_table* tab, int32_t n_cells, int32_t dtype, dsmc_vec3 v,
                        dsmc_pairs pairs, dsmc_rng rng, double m_red, int32_t schedule, void* ws,
                        size_t ws_bytes, dsmc_stream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* The flow loop around the collision step (section "Results and
+ * Discussion": the Couette channel and the lid-driven cavity).  The paper
+ * gives no formulas for it; the standard DSMC method is used (Bird 1994).  */
+
+/* Box of nx x ny uniform cells over [0, Lx] x [0, Ly] (unit depth in z).
+ * Sides 0..3 are x = 0, x = Lx, y = 0, y = Ly, each periodic (the opposite
+ * side must be periodic too), specular, or diffuse with wall temperature
+ * T_w[side] (K) and wall velocity u_w[side] (m/s; its tangential components
+ * are used).  m: particle mass (kg).  Passed by host pointer, read at call. */
+enum { DSMC_WALL_PERIODIC = 0, DSMC_WALL_SPECULAR = 1, DSMC_WALL_DIFFUSE = 2 };
+typedef struct {
+    int32_t nx, ny;
+    double Lx, Ly;
+    int32_t kind[4];
+    double T_w[4];
+    double u_w[4][3];
+    double m;
+} dsmc_domain;
+
+/* Move step: every particle flies dt ballistically; when it reaches a side
+ * first, the remaining time continues after the side's rule: periodic shifts
+ * by the period, specular flips the normal velocity, diffuse re-emits from
+ * the wall Maxwellian (normal speed sigma_w sqrt(-2 ln(1 - U1)), tangential
+ * u_w + sigma_w n, n a Box-Muller pair of (U2, U3), sigma_w = sqrt(k T_w/m)),
+ * with U1, U2 from Philox(slot s, event h, step, 6) and U3 from (.., 7), s
+ * the particle's index in the arrays.  At most 8 wall events per particle and
+ * call (more: the flight is finished without further events, counted in
+ * st->wall_limit with DSMC_ST_WALL_LIMIT); st->wall_events counts events.
+ * Positions are clamped to the box, then cell_of[s] = iy nx + ix with
+ * ix = floor(x nx / Lx) (of the stored position), clamped to the grid.
+ * pos.x, pos.y: positions (pos.z unused); v: velocities; both in place, of
+ * `dtype`; arithmetic in FP64.  st may be NULL. */
+int dsmc_move(int32_t n, int32_t dtype, dsmc_vec3 pos, dsmc_vec3 v, const dsmc_domain* dom,
+              double dt, dsmc_rng rng, int32_t* cell_of, dsmc_status* st,
+              dsmc_stream_t stream);
+
+/* out.c[s] = in.c[perm[s]] for each component c whose pointers are both
+ * non-NULL (the positions into the cell order of dsmc_sort_cells). */
+int dsmc_gather(int32_t n, int32_t dtype, const int32_t* perm, dsmc_vec3 in, dsmc_vec3 out,
+                dsmc_stream_t stream);
+
+/* Sampling of the macroscopic fields: per cell k, acc[13k .. 13k+12] +=
+ * (N, sum v_x, v_y, v_z, sum v_x^2, v_y^2, v_z^2, v_x v_y, v_x v_z, v_y v_z,
+ * sum |v|^2 v_x, |v|^2 v_y, |v|^2 v_z) over the cell's sorted slots, FP64. */
+int dsmc_sample(int32_t n_cells, const int32_t* cell_start, int32_t dtype, dsmc_vec3 v,
+                double* acc, dsmc_stream_t stream);
+
+/* Fields from n_samples accumulated samples: fields[9k ..] = (number
+ * density, u_x, u_y, u_z, T = m <|c|^2> / (3 k), tau_xy = -rho <c_x c_y>,
+ * q_x, q_y, q_z with q = rho <|c|^2 c> / 2), c = v - u, rho = n m, number
+ * density = N / n_samples * fnum_per_volume (F_N / V_cell).  Cells never
+ * sampled give zeros. */
+int dsmc_sample_fields(int32_t n_cells, const double* acc, double n_samples, double mass,
+                       double fnum_per_volume, double* fields, dsmc_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -10,6 +10,8 @@ LIB_PATH = os.path.join(HERE, "libdsmc.so")
 DSMC_OK, DSMC_E_ARG, DSMC_E_HIP, DSMC_E_UNSUPPORTED = 0, -1, -2, -3
 F32, F64, BF16 = 0, 1, 2
 ST_PAIR_OVERFLOW, ST_BAD_CELL, ST_ROOT_FAIL, ST_NONFINITE, ST_PROB_CLAMP = 1, 2, 4, 8, 16
+ST_WALL_LIMIT = 32
+WALL_PERIODIC, WALL_SPECULAR, WALL_DIFFUSE = 0, 1, 2
 XS_VHS, XS_CONST = 0, 1
 POT_JAGER, POT_HS, POT_INVPOW = 0, 1, 2
 ACT_SILU, ACT_RELU = 0, 1
@@ -30,7 +32,14 @@ class Rng(C.Structure):
 class Status(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("bad_cell", C.c_int32), ("n_cand", C.c_int64),
                 ("n_pairs", C.c_int64), ("root_fail", C.c_int32), ("nonfinite", C.c_int32),
-                ("mm_skipped", C.c_int32), ("prob_clamped", C.c_int32)]
+                ("mm_skipped", C.c_int32), ("prob_clamped", C.c_int32),
+                ("wall_events", C.c_int64), ("wall_limit", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Domain(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("Lx", C.c_double), ("Ly", C.c_double),
+                ("kind", C.c_int32 * 4), ("T_w", C.c_double * 4),
+                ("u_w", (C.c_double * 3) * 4), ("m", C.c_double)]
 
 
 class Pairs(C.Structure):
@@ -96,6 +105,10 @@ SIGNATURES = {
     "dsmc_collide_ws": (_sz, [_i64, _i32]),
     "dsmc_collide_vhs": (C.c_int, [_i32, _i32, Vec3, Pairs, Rng, _i32, _vp, _sz, _vp]),
     "dsmc_apply_pairs": (C.c_int, [_i32, _i32, Vec3, Pairs, _i32, _i32, _vp, _sz, _vp]),
+    "dsmc_move": (C.c_int, [_i32, _i32, Vec3, Vec3, _vp, C.c_double, Rng, _vp, _vp, _vp]),
+    "dsmc_gather": (C.c_int, [_i32, _i32, _vp, Vec3, Vec3, _vp]),
+    "dsmc_sample": (C.c_int, [_i32, _vp, _i32, Vec3, _vp, _vp]),
+    "dsmc_sample_fields": (C.c_int, [_i32, _vp, C.c_double, C.c_double, C.c_double, _vp, _vp]),
     "dsmc_apply_pairs_match": (C.c_int, [_i32, _vp, _i32, Vec3, Pairs, _i32, _vp, _i32, _vp, _sz,
                                          _vp, _vp]),
     "dsmc_deflect_jager": (C.c_int, [_i64, _i32, _vp, _vp, _vp, _d, C.POINTER(Potential), Quad,

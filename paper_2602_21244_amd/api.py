@@ -496,3 +496,72 @@ def collide_table(tab, v, pairs, seed, step, m_red, schedule=L.SCHED_AUTO, ws=No
                                    int(schedule), _ptr(ws), int(ws.numel()), _stream(stream)),
           "dsmc_collide_table")
     return ws
+
+
+# ---------------------------------------------------------------------------
+# Flow loop around the collision step: move, gather, sampling, fields
+# ---------------------------------------------------------------------------
+def domain(nx, ny, Lx, Ly, kinds, T_w, u_w, m):
+    """dsmc_domain; kinds / T_w / u_w per side (x = 0, x = Lx, y = 0, y = Ly)."""
+    d = L.Domain()
+    d.nx, d.ny, d.Lx, d.Ly, d.m = int(nx), int(ny), float(Lx), float(Ly), float(m)
+    for q in range(4):
+        d.kind[q] = int(kinds[q])
+        d.T_w[q] = float(T_w[q])
+        for c in range(3):
+            d.u_w[q][c] = float(u_w[q][c])
+    return d
+
+
+def _vec2(p):
+    assert p.dim() == 2 and p.shape[0] == 2 and p.is_contiguous()
+    return L.Vec3(p[0].data_ptr(), p[1].data_ptr(), None)
+
+
+def move(pos, v, dom, dt, seed, step, cell_of=None, st=None, stream=None):
+    """Free flight over dt with wall events, in place on pos[2, n] and
+    v[3, n] (same dtype); returns cell_of[n] (int32)."""
+    n = int(v.shape[1])
+    if pos.dtype != v.dtype or int(pos.shape[1]) != n:
+        raise ValueError("move: positions and velocities must match in dtype and count")
+    if cell_of is None:
+        cell_of = torch.empty(n, dtype=torch.int32, device=v.device)
+    check(lib().dsmc_move(n, _dtype(v), _vec2(pos), _vec3(v), C.byref(dom), float(dt),
+                          rng_struct(seed, step), _ptr(cell_of), _ptr(st), _stream(stream)),
+          "dsmc_move")
+    return cell_of
+
+
+def gather(perm, src, out=None, stream=None):
+    """out[:, s] = src[:, perm[s]] for a [2, n] or [3, n] array."""
+    if out is None:
+        out = torch.empty_like(src)
+    rows = int(src.shape[0])
+    if rows not in (2, 3):
+        raise ValueError("gather: 2 or 3 rows")
+    vin = _vec2(src) if rows == 2 else _vec3(src)
+    vout = _vec2(out) if rows == 2 else _vec3(out)
+    check(lib().dsmc_gather(int(src.shape[1]), _dtype(src), _ptr(perm), vin, vout,
+                            _stream(stream)), "dsmc_gather")
+    return out
+
+
+def sample(cell_start, v, acc=None, stream=None):
+    """acc[n_cells, 13] += the raw per-cell moment sums of v (FP64)."""
+    n_cells = int(cell_start.numel()) - 1
+    if acc is None:
+        acc = torch.zeros(n_cells, 13, dtype=torch.float64, device=v.device)
+    check(lib().dsmc_sample(n_cells, _ptr(cell_start), _dtype(v), _vec3(v), _ptr(acc),
+                            _stream(stream)), "dsmc_sample")
+    return acc
+
+
+def sample_fields(acc, n_samples, mass, fnum_per_volume, out=None, stream=None):
+    """Fields [n_cells, 9]: n, ux, uy, uz, T, tau_xy, qx, qy, qz."""
+    n_cells = int(acc.shape[0])
+    if out is None:
+        out = torch.empty(n_cells, 9, dtype=torch.float64, device=acc.device)
+    check(lib().dsmc_sample_fields(n_cells, _ptr(acc), float(n_samples), float(mass),
+                                   float(fnum_per_volume), _ptr(out), _stream(stream)),
+          "dsmc_sample_fields")
+    return out

@@ -22,7 +22,7 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # Files whose FP64 results must be bit-identical across kernels that compute
 # the same update (Phase-B schedules, the fused step, moment matching): no
 # FMA contraction, so every expression rounds the same way in every kernel.
-EXACT = {"collide.hip", "step_fused.hip", "moments.hip"}
+EXACT = {"collide.hip", "step_fused.hip", "moments.hip", "flow.hip"}
 
 
 def flags_for(src):

@@ -75,6 +75,7 @@ k_cand_count(const int32_t* __restrict__ cell_start, int32_t n_cells,
 constexpr int CAND_ROUNDS = 16;
 constexpr int CAND_CHUNK = 64 * CAND_ROUNDS;
 constexpr int CAND_GROUP = 4;
+constexpr int CAND_WIN = 4;      // cell window of a group (see k_cand_decide)
 
 // Overflow decision: total candidates vs capacity; number of chunks.
 __global__ void k_cand_check(const int64_t* total, int64_t cap, int32_t* ok, int64_t* n_use,
@@ -97,6 +98,16 @@ struct CandDraw {
     int32_t i, j;   // sorted slots
     double U;
 };
+
+__device__ __forceinline__ CandDraw cand_draw_sn(int32_t s0, int32_t N, int32_t k, int32_t t,
+                                                 const dsmc_rng& rng)
+{
+    const U4 r = draw(rng, (uint32_t)t, (uint32_t)k, SLOT_CAND);
+    int32_t i = (int32_t)(((uint64_t)r.a * (uint64_t)N) >> 32);
+    int32_t j = (int32_t)(((uint64_t)r.b * (uint64_t)(N - 1)) >> 32);
+    if (j >= i) j += 1;
+    return CandDraw{s0 + i, s0 + j, unif53(r.c, r.d)};
+}
 
 __device__ __forceinline__ CandDraw cand_draw(const int32_t* __restrict__ cell_start, int32_t k,
                                               int32_t t, const dsmc_rng& rng)
@@ -129,6 +140,15 @@ __device__ __forceinline__ bool cand_accept(const CandDraw& d, const V3<const T>
 // particle in slot t; its partner is drawn uniformly among the m = N-1-t
 // later slots and the pair collides with probability P = m lambda_k sigma(g) g
 // (values above 1 act as 1 and are counted).
+__device__ __forceinline__ CandDraw sbt_draw_sn(int32_t s0, int32_t N, int32_t k, int32_t t,
+                                                const dsmc_rng& rng, int32_t& m)
+{
+    m = N - 1 - t;
+    const U4 r = draw(rng, (uint32_t)t, (uint32_t)k, SLOT_SBT);
+    const int32_t j = t + 1 + (int32_t)(((uint64_t)r.a * (uint64_t)m) >> 32);
+    return CandDraw{s0 + t, s0 + j, unif53(r.c, r.d)};
+}
+
 __device__ __forceinline__ CandDraw sbt_draw(const int32_t* __restrict__ cell_start, int32_t k,
                                              int32_t t, const dsmc_rng& rng, int32_t& m)
 {
@@ -207,42 +227,79 @@ k_cand_decide(const int32_t* __restrict__ cell_start, int32_t n_cells,
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t ch = wave; ch < nch; ch += nwaves) {
         const int64_t cbase = ch * CAND_CHUNK;
-        int32_t kw = chunk_cell[ch];
+        int32_t kw = __builtin_amdgcn_readfirstlane(chunk_cell[ch]);
         int32_t acc = 0;
-        // CAND_GROUP rounds at a time: cells, draws and velocity gathers of
-        // the group are independent, so their loads overlap
+        // CAND_GROUP rounds at a time.  The cells of a group are read once
+        // per wave from a window of CAND_WIN + 1 cells starting at kw (scalar
+        // loads: kw is uniform); a candidate's cell is kw plus the number of
+        // window boundaries at or below it.  Candidates beyond the window
+        // (groups that cross many small cells) walk on from its last cell.
         for (int r0 = 0; r0 < CAND_ROUNDS; r0 += CAND_GROUP) {
             if (cbase + r0 * 64 >= total) break;
-            int32_t kk[CAND_GROUP];
+            int32_t wb[CAND_WIN], ws0[CAND_WIN + 2];
+            double wg[CAND_WIN + 1];
+            const int32_t wa0 = cand_off[kw];
+#pragma unroll
+            for (int q = 0; q < CAND_WIN; ++q)
+                wb[q] = kw + 1 + q < n_cells ? cand_off[kw + 1 + q] : INT32_MAX;
+#pragma unroll
+            for (int q = 0; q < CAND_WIN + 2; ++q)
+                ws0[q] = cell_start[kw + q <= n_cells ? kw + q : n_cells];
+#pragma unroll
+            for (int q = 0; q < CAND_WIN + 1; ++q) {
+                const int32_t kq = kw + q < n_cells ? kw + q : n_cells - 1;
+                wg[q] = SEL == SEL_NTC ? 2.0 * mom[6 * (size_t)kq + 4] : lambda[kq];
+            }
+            int32_t kk[CAND_GROUP], s0u[CAND_GROUP], nu[CAND_GROUP], au[CAND_GROUP];
+            double gu[CAND_GROUP];
             bool val[CAND_GROUP];
             int64_t cc[CAND_GROUP];
-            int32_t k = kw;
 #pragma unroll
             for (int u = 0; u < CAND_GROUP; ++u) {
                 cc[u] = cbase + (r0 + u) * 64 + lane;
                 val[u] = cc[u] < total;
-                if (val[u])
+                int32_t w = 0;
+#pragma unroll
+                for (int q = 0; q < CAND_WIN; ++q) w += cc[u] >= wb[q] ? 1 : 0;
+                int32_t k = kw + w;
+                int32_t s0 = ws0[0], s1 = ws0[1], a = wa0;
+                double g = wg[0];
+#pragma unroll
+                for (int q = 1; q <= CAND_WIN; ++q)
+                    if (w == q) { s0 = ws0[q]; s1 = ws0[q + 1]; g = wg[q]; a = wb[q - 1]; }
+                if (w == CAND_WIN && val[u]) {
                     while (k + 1 < n_cells && cand_off[k + 1] <= cc[u]) ++k;
+                    if (k != kw + CAND_WIN) {
+                        s0 = cell_start[k];
+                        s1 = cell_start[k + 1];
+                        g = SEL == SEL_NTC ? 2.0 * mom[6 * (size_t)k + 4] : lambda[k];
+                        a = cand_off[k];
+                    }
+                }
                 kk[u] = k;
+                au[u] = a;
+                s0u[u] = s0;
+                nu[u] = s1 - s0;
+                gu[u] = g;
             }
             CandDraw dr[CAND_GROUP];
             int32_t mm[CAND_GROUP];
 #pragma unroll
             for (int u = 0; u < CAND_GROUP; ++u) {
-                const int32_t t = (int32_t)(cc[u] - cand_off[kk[u]]);
+                const int32_t t = (int32_t)(cc[u] - au[u]);
                 mm[u] = 0;
                 if (!val[u]) dr[u] = CandDraw{0, 0, 1.0};
-                else if (SEL == SEL_NTC) dr[u] = cand_draw(cell_start, kk[u], t, rng);
-                else dr[u] = sbt_draw(cell_start, kk[u], t, rng, mm[u]);
+                else if (SEL == SEL_NTC) dr[u] = cand_draw_sn(s0u[u], nu[u], kk[u], t, rng);
+                else dr[u] = sbt_draw_sn(s0u[u], nu[u], kk[u], t, rng, mm[u]);
             }
             bool take[CAND_GROUP];
 #pragma unroll
             for (int u = 0; u < CAND_GROUP; ++u) {
                 if (SEL == SEL_NTC) {
-                    take[u] = val[u] && cand_accept<T>(dr[u], v, 2.0 * mom[6 * (size_t)kk[u] + 4], e);
+                    take[u] = val[u] && cand_accept<T>(dr[u], v, gu[u], e);
                 } else {
                     bool cl = false;
-                    take[u] = val[u] && sbt_accept<T>(dr[u], mm[u], v, lambda[kk[u]], C, e, cl);
+                    take[u] = val[u] && sbt_accept<T>(dr[u], mm[u], v, gu[u], C, e, cl);
                     clamped_n += (val[u] && cl) ? 1 : 0;
                 }
             }
@@ -255,13 +312,13 @@ k_cand_decide(const int32_t* __restrict__ cell_start, int32_t n_cells,
                     sj[cbase + p] = dr[u].j;
                     sc[cbase + p] = kk[u];
                 }
-                if (val[u] && cc[u] == cand_off[kk[u]]) {
+                if (val[u] && cc[u] == au[u]) {
                     loc[kk[u]] = p;
                     for (int32_t q = kk[u] - 1; q >= 0 && cand_off[q] == cc[u]; --q) loc[q] = p;
                 }
                 acc += (int32_t)__popcll(ab);
             }
-            kw = __shfl(kk[CAND_GROUP - 1], 63, 64);
+            kw = __builtin_amdgcn_readfirstlane(__shfl(kk[CAND_GROUP - 1], 63, 64));
         }
         if (lane == 0) chunk_cnt[ch] = acc;
     }

@@ -48,7 +48,7 @@ def test_struct_layout_matches_header():
     structs = {"dsmc_vec3": L.Vec3, "dsmc_rng": L.Rng, "dsmc_status": L.Status,
                "dsmc_pairs": L.Pairs, "dsmc_xs": L.Xs, "dsmc_potential": L.Potential,
                "dsmc_quad": L.Quad, "dsmc_mlp": L.Mlp, "dsmc_anet": L.Anet,
-               "dsmc_chi_table": L.ChiTable}
+               "dsmc_chi_table": L.ChiTable, "dsmc_domain": L.Domain}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -88,6 +88,17 @@ def test_host_argument_errors(lib):
     assert lib.dsmc_huber_loss(0, None, None, None, None, None) == L.DSMC_E_ARG
     assert lib.dsmc_apply_pairs_match(4, None, L.F64, L.Vec3(), L.Pairs(), 0, None, L.MM_APPLY,
                                       None, 0, None, None) == L.DSMC_E_ARG
+    d = L.Domain()
+    d.nx, d.ny, d.Lx, d.Ly, d.m = 4, 4, 1.0, 1.0, 1.0
+    d.kind[0], d.kind[1], d.kind[2], d.kind[3] = 0, 1, 2, 2       # periodic side without partner
+    for q in range(4):
+        d.T_w[q] = 300.0
+    assert lib.dsmc_move(10, L.F64, L.Vec3(), L.Vec3(), C.byref(d), 1.0, L.Rng(), None, None,
+                         None) == L.DSMC_E_ARG
+    assert b"periodic" in lib.dsmc_last_error()
+    assert lib.dsmc_gather(5, L.F64, None, L.Vec3(), L.Vec3(), None) == L.DSMC_E_ARG
+    assert lib.dsmc_sample(0, None, L.F64, L.Vec3(), None, None) == L.DSMC_E_ARG
+    assert lib.dsmc_sample_fields(3, None, 1.0, 1.0, 1.0, None, None) == L.DSMC_E_ARG
     t = L.ChiTable(1, 4, 0.0, 1.0, None)
     assert lib.dsmc_collide_table(C.byref(t), 4, L.F64, L.Vec3(), L.Pairs(), L.Rng(), 1.0, 0,
                                   None, 0, None) == L.DSMC_E_ARG
