@@ -17,24 +17,47 @@ __device__ __forceinline__ CellSums cell_sums(V3<T> v, int32_t s0, int32_t N, in
 {
     CellSums r{0, 0, 0, 0, 0, 0};
     if (N <= 0) return r;
+    // each lane adds its slots lane, lane + 64, ... in order; the loads of
+    // SUM_BATCH consecutive terms are issued together
+    constexpr int SUM_BATCH = 4;
     double sx = 0, sy = 0, sz = 0;
-    for (int32_t q = lane; q < N; q += 64) {
-        sx += (double)v.x[s0 + q];
-        sy += (double)v.y[s0 + q];
-        sz += (double)v.z[s0 + q];
+    for (int32_t q0 = lane; q0 < N; q0 += 64 * SUM_BATCH) {
+        T x[SUM_BATCH], y[SUM_BATCH], z[SUM_BATCH];
+#pragma unroll
+        for (int b = 0; b < SUM_BATCH; ++b) {
+            const int32_t q = q0 + 64 * b;
+            if (q < N) { x[b] = v.x[s0 + q]; y[b] = v.y[s0 + q]; z[b] = v.z[s0 + q]; }
+        }
+#pragma unroll
+        for (int b = 0; b < SUM_BATCH; ++b)
+            if (q0 + 64 * b < N) {
+                sx += (double)x[b];
+                sy += (double)y[b];
+                sz += (double)z[b];
+            }
     }
     sx = wave_sum(sx);
     sy = wave_sum(sy);
     sz = wave_sum(sz);
     r.ux = sx / N; r.uy = sy / N; r.uz = sz / N;
     double S = 0, c2max = 0, E = 0;
-    for (int32_t q = lane; q < N; q += 64) {
-        const double x = v.x[s0 + q], y = v.y[s0 + q], z = v.z[s0 + q];
-        const double dx = x - r.ux, dy = y - r.uy, dz = z - r.uz;
-        const double c2 = dx * dx + dy * dy + dz * dz;
-        S += c2;
-        c2max = fmax(c2max, c2);
-        E += x * x + y * y + z * z;
+    for (int32_t q0 = lane; q0 < N; q0 += 64 * SUM_BATCH) {
+        T xb[SUM_BATCH], yb[SUM_BATCH], zb[SUM_BATCH];
+#pragma unroll
+        for (int b = 0; b < SUM_BATCH; ++b) {
+            const int32_t q = q0 + 64 * b;
+            if (q < N) { xb[b] = v.x[s0 + q]; yb[b] = v.y[s0 + q]; zb[b] = v.z[s0 + q]; }
+        }
+#pragma unroll
+        for (int b = 0; b < SUM_BATCH; ++b) {
+            if (q0 + 64 * b >= N) continue;
+            const double x = xb[b], y = yb[b], z = zb[b];
+            const double dx = x - r.ux, dy = y - r.uy, dz = z - r.uz;
+            const double c2 = dx * dx + dy * dy + dz * dz;
+            S += c2;
+            c2max = fmax(c2max, c2);
+            E += x * x + y * y + z * z;
+        }
     }
     r.S = wave_sum(S);
     r.cmax = sqrt(wave_max(c2max));

@@ -75,7 +75,7 @@ k_cand_count(const int32_t* __restrict__ cell_start, int32_t n_cells,
 constexpr int CAND_ROUNDS = 16;
 constexpr int CAND_CHUNK = 64 * CAND_ROUNDS;
 constexpr int CAND_GROUP = 4;
-constexpr int CAND_WIN = 4;      // cell window of a group (see k_cand_decide)
+constexpr int CAND_WIN = 4;      // scalar cell window of a group (see k_cand_decide)
 
 // Overflow decision: total candidates vs capacity; number of chunks.
 __global__ void k_cand_check(const int64_t* total, int64_t cap, int32_t* ok, int64_t* n_use,
@@ -188,18 +188,19 @@ k_trial_count(const int32_t* __restrict__ cell_start, int32_t n_cells, int32_t* 
 
 enum { SEL_NTC = 0, SEL_SBT = 1 };
 
-// Cell owning the first candidate of each chunk (one thread per cell).
+// Cell owning the first candidate of each 64-candidate round (one thread per
+// cell writes the rounds that start inside its candidate range).
 __global__ void __launch_bounds__(256)
-k_chunk_cells(int32_t n_cells, const int32_t* __restrict__ cand_off,
-              const int64_t* __restrict__ n_use, int32_t* __restrict__ chunk_cell)
+k_round_cells(int32_t n_cells, const int32_t* __restrict__ cand_off,
+              const int64_t* __restrict__ n_use, int32_t* __restrict__ round_cell)
 {
     const int64_t total = *n_use;
     for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_cells;
          k += gridDim.x * blockDim.x) {
         const int64_t a = cand_off[k];
-        const int64_t b = cand_off[k + 1] < total ? cand_off[k + 1] : total;
-        for (int64_t ch = (a + CAND_CHUNK - 1) / CAND_CHUNK; ch * CAND_CHUNK < b; ++ch)
-            chunk_cell[ch] = k;
+        const int64_t nxt = k + 1 < n_cells ? (int64_t)cand_off[k + 1] : total;
+        const int64_t b = nxt < total ? nxt : total;
+        for (int64_t r = (a + 63) / 64; r * 64 < b; ++r) round_cell[r] = k;
     }
 }
 
@@ -212,7 +213,7 @@ template <typename T, int SEL>
 __global__ void __launch_bounds__(256)
 k_cand_decide(const int32_t* __restrict__ cell_start, int32_t n_cells,
               const int32_t* __restrict__ cand_off, const int64_t* __restrict__ n_use,
-              const int32_t* __restrict__ chunk_cell, const double* __restrict__ mom,
+              const int32_t* __restrict__ round_cell, const double* __restrict__ mom,
               const double* __restrict__ lambda, double C, double e, dsmc_rng rng,
               V3<const T> v, int32_t* __restrict__ chunk_cnt, int32_t* __restrict__ si,
               int32_t* __restrict__ sj, int32_t* __restrict__ sc, int32_t* __restrict__ loc,
@@ -227,60 +228,105 @@ k_cand_decide(const int32_t* __restrict__ cell_start, int32_t n_cells,
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t ch = wave; ch < nch; ch += nwaves) {
         const int64_t cbase = ch * CAND_CHUNK;
-        int32_t kw = __builtin_amdgcn_readfirstlane(chunk_cell[ch]);
         int32_t acc = 0;
-        // CAND_GROUP rounds at a time.  The cells of a group are read once
-        // per wave from a window of CAND_WIN + 1 cells starting at kw (scalar
-        // loads: kw is uniform); a candidate's cell is kw plus the number of
-        // window boundaries at or below it.  Candidates beyond the window
-        // (groups that cross many small cells) walk on from its last cell.
+        // CAND_GROUP rounds at a time.  Cells are looked up in two ways:
+        //  - when the group's candidates lie in the CAND_WIN cells from the
+        //    cell of its first candidate (cells of many candidates), those
+        //    cells are read once by scalar loads and a lane's cell is the
+        //    number of their starts at or below its candidate;
+        //  - otherwise each round of 64 candidates reads a window of 64 cells
+        //    from the cell of its first candidate (one coalesced load per
+        //    lane and field), a lane finds its cell by a binary search over
+        //    the window's candidate offsets with lane shuffles, and a round
+        //    that crosses more than 63 cell starts (runs of cells without
+        //    candidates) walks on from the window's last cell.
         for (int r0 = 0; r0 < CAND_ROUNDS; r0 += CAND_GROUP) {
-            if (cbase + r0 * 64 >= total) break;
-            int32_t wb[CAND_WIN], ws0[CAND_WIN + 2];
-            double wg[CAND_WIN + 1];
-            const int32_t wa0 = cand_off[kw];
-#pragma unroll
-            for (int q = 0; q < CAND_WIN; ++q)
-                wb[q] = kw + 1 + q < n_cells ? cand_off[kw + 1 + q] : INT32_MAX;
-#pragma unroll
-            for (int q = 0; q < CAND_WIN + 2; ++q)
-                ws0[q] = cell_start[kw + q <= n_cells ? kw + q : n_cells];
-#pragma unroll
-            for (int q = 0; q < CAND_WIN + 1; ++q) {
-                const int32_t kq = kw + q < n_cells ? kw + q : n_cells - 1;
-                wg[q] = SEL == SEL_NTC ? 2.0 * mom[6 * (size_t)kq + 4] : lambda[kq];
-            }
+            const int64_t gfirst = cbase + r0 * 64;
+            if (gfirst >= total) break;
             int32_t kk[CAND_GROUP], s0u[CAND_GROUP], nu[CAND_GROUP], au[CAND_GROUP];
             double gu[CAND_GROUP];
             bool val[CAND_GROUP];
             int64_t cc[CAND_GROUP];
+            const int32_t kw = __builtin_amdgcn_readfirstlane(round_cell[gfirst >> 6]);
+            const int64_t glast = (gfirst + CAND_GROUP * 64 < total ? gfirst + CAND_GROUP * 64
+                                                                      : total) - 1;
+            int32_t wb[CAND_WIN];
 #pragma unroll
-            for (int u = 0; u < CAND_GROUP; ++u) {
-                cc[u] = cbase + (r0 + u) * 64 + lane;
-                val[u] = cc[u] < total;
-                int32_t w = 0;
+            for (int q = 0; q < CAND_WIN; ++q)
+                wb[q] = kw + 1 + q < n_cells ? cand_off[kw + 1 + q] : INT32_MAX;
+            if (glast < (int64_t)wb[CAND_WIN - 1]) {
+                int32_t ws0[CAND_WIN + 1];
+                double wg[CAND_WIN];
 #pragma unroll
-                for (int q = 0; q < CAND_WIN; ++q) w += cc[u] >= wb[q] ? 1 : 0;
-                int32_t k = kw + w;
-                int32_t s0 = ws0[0], s1 = ws0[1], a = wa0;
-                double g = wg[0];
+                for (int q = 0; q <= CAND_WIN; ++q)
+                    ws0[q] = cell_start[kw + q <= n_cells ? kw + q : n_cells];
 #pragma unroll
-                for (int q = 1; q <= CAND_WIN; ++q)
-                    if (w == q) { s0 = ws0[q]; s1 = ws0[q + 1]; g = wg[q]; a = wb[q - 1]; }
-                if (w == CAND_WIN && val[u]) {
-                    while (k + 1 < n_cells && cand_off[k + 1] <= cc[u]) ++k;
-                    if (k != kw + CAND_WIN) {
+                for (int q = 0; q < CAND_WIN; ++q) {
+                    const int32_t kq = kw + q < n_cells ? kw + q : n_cells - 1;
+                    wg[q] = SEL == SEL_NTC ? 2.0 * mom[6 * (size_t)kq + 4] : lambda[kq];
+                }
+                const int32_t wa0 = cand_off[kw];
+#pragma unroll
+                for (int u = 0; u < CAND_GROUP; ++u) {
+                    cc[u] = gfirst + u * 64 + lane;
+                    val[u] = cc[u] < total;
+                    int32_t w = 0;
+#pragma unroll
+                    for (int q = 0; q < CAND_WIN - 1; ++q) w += cc[u] >= wb[q] ? 1 : 0;
+                    int32_t s0 = ws0[0], s1 = ws0[1], a = wa0;
+                    double g = wg[0];
+#pragma unroll
+                    for (int q = 1; q < CAND_WIN; ++q)
+                        if (w == q) { s0 = ws0[q]; s1 = ws0[q + 1]; g = wg[q]; a = wb[q - 1]; }
+                    kk[u] = kw + w;
+                    au[u] = a;
+                    s0u[u] = s0;
+                    nu[u] = s1 - s0;
+                    gu[u] = g;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < CAND_GROUP; ++u) {
+                    cc[u] = gfirst + u * 64 + lane;
+                    val[u] = cc[u] < total;
+                    const int64_t rfirst = gfirst + u * 64;
+                    const int32_t kr =
+                        rfirst < total ? __builtin_amdgcn_readfirstlane(round_cell[rfirst >> 6])
+                                       : 0;
+                    const int32_t kl = kr + lane;
+                    const int32_t A = kl < n_cells ? cand_off[kl] : INT32_MAX;
+                    const int32_t An = kl + 1 < n_cells ? cand_off[kl + 1] : INT32_MAX;
+                    const int32_t S = cell_start[kl < n_cells ? kl : n_cells];
+                    const int32_t Sn = cell_start[kl < n_cells ? kl + 1 : n_cells];
+                    const int32_t kq = kl < n_cells ? kl : n_cells - 1;
+                    const double G = SEL == SEL_NTC ? 2.0 * mom[6 * (size_t)kq + 4] : lambda[kq];
+                    // largest window index l with A[l] <= cc (A[0] <= cc holds)
+                    int32_t l = 0;
+#pragma unroll
+                    for (int stp = 32; stp > 0; stp >>= 1) {
+                        const int32_t c = l + stp;
+                        const int32_t Ac = __shfl(A, c < 64 ? c : 63, 64);
+                        if (c < 64 && (int64_t)Ac <= cc[u]) l = c;
+                    }
+                    int32_t k = kr + l;
+                    int32_t a = __shfl(A, l, 64);
+                    int32_t s0 = __shfl(S, l, 64), s1 = __shfl(Sn, l, 64);
+                    double g = __shfl(G, l, 64);
+                    const int32_t an = __shfl(An, l, 64);
+                    if (val[u] && (int64_t)an <= cc[u]) {
+                        // beyond the window
+                        while (k + 1 < n_cells && cand_off[k + 1] <= cc[u]) ++k;
+                        a = cand_off[k];
                         s0 = cell_start[k];
                         s1 = cell_start[k + 1];
                         g = SEL == SEL_NTC ? 2.0 * mom[6 * (size_t)k + 4] : lambda[k];
-                        a = cand_off[k];
                     }
+                    kk[u] = k;
+                    au[u] = a;
+                    s0u[u] = s0;
+                    nu[u] = s1 - s0;
+                    gu[u] = g;
                 }
-                kk[u] = k;
-                au[u] = a;
-                s0u[u] = s0;
-                nu[u] = s1 - s0;
-                gu[u] = g;
             }
             CandDraw dr[CAND_GROUP];
             int32_t mm[CAND_GROUP];
@@ -318,7 +364,6 @@ k_cand_decide(const int32_t* __restrict__ cell_start, int32_t n_cells,
                 }
                 acc += (int32_t)__popcll(ab);
             }
-            kw = __builtin_amdgcn_readfirstlane(__shfl(kk[CAND_GROUP - 1], 63, 64));
         }
         if (lane == 0) chunk_cnt[ch] = acc;
     }
@@ -393,7 +438,7 @@ struct SelectWs {
     int64_t* n_use;       // candidates processed (0 on overflow)
     int64_t* n_chunks;
     int32_t* ok;
-    int32_t* chunk_cell;  // [max chunks]
+    int32_t* round_cell;  // [max chunks * 16]
     int32_t* chunk_cnt;   // [max chunks]
     int32_t* chunk_off;   // [max chunks + 1]
     int32_t* si;          // staging [max chunks * 1024]
@@ -419,7 +464,7 @@ static SelectWs select_ws_layout(void* base, int32_t n_cells, int64_t cap)
     w.n_use = reinterpret_cast<int64_t*>(take(sizeof(int64_t)));
     w.n_chunks = reinterpret_cast<int64_t*>(take(sizeof(int64_t)));
     w.ok = reinterpret_cast<int32_t*>(take(sizeof(int32_t)));
-    w.chunk_cell = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)mc));
+    w.round_cell = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)mc * CAND_ROUNDS));
     w.chunk_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)mc));
     w.chunk_off = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * ((size_t)mc + 1)));
     const size_t stage = sizeof(int32_t) * (size_t)mc * CAND_CHUNK;
@@ -450,10 +495,10 @@ static int select_impl(int32_t n_cells, const int32_t* cell_start, dsmc_vec3 v, 
     if (rc) return rc;
     k_cand_check<<<1, 1, 0, s>>>(w.total, pairs.cap, w.ok, w.n_use, w.n_chunks, st);
     DSMC_LAUNCH_CHECK("select:check");
-    k_chunk_cells<<<cb, 256, 0, s>>>(n_cells, w.cand_off, w.n_use, w.chunk_cell);
-    DSMC_LAUNCH_CHECK("select:chunk_cells");
+    k_round_cells<<<cb, 256, 0, s>>>(n_cells, w.cand_off, w.n_use, w.round_cell);
+    DSMC_LAUNCH_CHECK("select:round_cells");
     k_cand_decide<T, SEL><<<pb, 256, 0, s>>>(cell_start, n_cells, w.cand_off, w.n_use,
-                                             w.chunk_cell, mom, lambda, law.C, law.e, rng,
+                                             w.round_cell, mom, lambda, law.C, law.e, rng,
                                              v3<const T>(v), w.chunk_cnt, w.si, w.sj, w.sc,
                                              w.loc, st);
     DSMC_LAUNCH_CHECK("select:decide");
