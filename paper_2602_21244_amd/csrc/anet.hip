@@ -88,7 +88,10 @@ static AnetWs anet_layout(void* base, const AnetDims& a, int64_t R)
     return w;
 }
 
-__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float silu_f(float z)
+{
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
 
 // Layer 0 on the VALU: z0 = W0 x + b0 (FP32), h0 = bf16(SiLU(z0)).  With
 // grid != nullptr, x is the table grid node of row row0 + r.
@@ -106,7 +109,7 @@ k_anet_first(int64_t R, int n, const float* __restrict__ x, const __bf16* __rest
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = q / n;
-        const int c = (int)(q % n);
+        const int c = (int)(q - r * n);
         float x0, x1;
         if (use_grid) {
             const int64_t g = row0 + r;

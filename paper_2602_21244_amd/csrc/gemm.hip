@@ -7,8 +7,9 @@
 //   B(k, n) = TB ? b[n ldb + k] : b[k ldb + n]
 //
 // A 256-thread workgroup computes a 128 x 128 tile: each wave a 64 x 64 block
-// as 2 x 2 v_mfma_f32_32x32x16_bf16 accumulators.  Operand tiles (128 x 32)
-// are staged in LDS with k contiguous (row stride 40 bf16 to spread banks);
+// as 2 x 2 v_mfma_f32_32x32x16_bf16 accumulators.  Operand tiles (128 x 64)
+// are staged in LDS with k contiguous (row stride 72 bf16 to spread banks),
+// double-buffered: the next tile is loaded into registers during the MFMAs;
 // operands that are k-contiguous in memory are copied with 16-byte loads, the
 // transposed ones are scattered into that layout element by element.  A
 // split of K across blockIdx.z writes FP32 partials that a second kernel sums
@@ -20,16 +21,28 @@ namespace dsmc {
 typedef __bf16 bf16x8g __attribute__((__vector_size__(8 * sizeof(__bf16))));
 typedef float floatx16g __attribute__((__vector_size__(16 * sizeof(float))));
 
-constexpr int GM = 128, GN = 128, GK = 32, GLD = GK + 8;
+constexpr int GM = 128, GN = 128, GK = 64, GLD = GK + 8;
+constexpr int G_CHUNKS = GM * GK / 8 / 256;   // 8-element chunks per thread and operand
 constexpr int G_THREADS = 256;
 
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+// Activations of the epilogue with the hardware exp2 / log2 / reciprocal
+// (the results are rounded to bf16 for the next layer; the pre-activations
+// are kept in FP32 separately).
+__device__ __forceinline__ float sigm(float z)
+{
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
 
 __device__ __forceinline__ float act_apply(int act, float z)
 {
     switch (act) {
     case GEMM_ACT_SILU: return z * sigm(z);
-    case GEMM_ACT_SOFTPLUS: return z > 20.0f ? z : log1pf(expf(z));
+    case GEMM_ACT_SOFTPLUS:
+        // ln(1 + e^z) = max(z, 0) + ln(1 + e^-|z|)
+        return fmaxf(z, 0.0f) + 0.69314718055994531f *
+                                    __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(
+                                                                     -1.4426950408889634f *
+                                                                     fabsf(z)));
     case GEMM_ACT_RELU: return z > 0.0f ? z : 0.0f;
     default: return z;
     }
@@ -59,66 +72,89 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m, int6
     if (g.out_bf16) g.out_bf16[m * g.ldo + n] = (__bf16)v;
 }
 
-// Stage rows [r0, r0 + 128) x k [k0, k0 + 32) of an operand into LDS as
-// tile[row][k].  kcontig: element (row, k) at p[row * ld + k]; otherwise at
-// p[k * ld + row].  Out-of-range elements are zero.
-__device__ __forceinline__ void stage_tile(const __bf16* __restrict__ p, int64_t ld, int64_t rows,
-                                           int64_t K, int64_t r0, int64_t k0, bool kcontig,
-                                           __bf16* tile)
+// One operand tile (rows [r0, r0 + 128) x k [k0, k0 + GK)) in flight: each
+// thread holds G_CHUNKS 8-element chunks.  kcontig: element (row, k) at
+// p[row * ld + k], chunks run along k; otherwise at p[k * ld + row], chunks
+// run along rows and are scattered into the k-contiguous LDS layout.
+// Out-of-range elements are zero.
+struct TileRegs {
+    bf16x8g v[G_CHUNKS];
+};
+
+__device__ __forceinline__ void load_tile(const __bf16* __restrict__ p, int64_t ld, int64_t rows,
+                                          int64_t K, int64_t r0, int64_t k0, bool kcontig,
+                                          TileRegs& R)
 {
     const int t = threadIdx.x;
-    if (kcontig) {
-        // 128 rows x 4 chunks of 8
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = t + G_THREADS * q;
-            const int row = c >> 2, kc = (c & 3) * 8;
-            const int64_t gr = r0 + row, gk = k0 + kc;
-            bf16x8g v;
-            const __bf16* src = p + gr * ld + gk;
-            if (gr < rows && gk + 8 <= K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
-                v = *reinterpret_cast<const bf16x8g*>(src);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    v[e] = (gr < rows && gk + e < K) ? src[e] : (__bf16)0.0f;
-            }
-            *reinterpret_cast<bf16x8g*>(tile + row * GLD + kc) = v;
+    for (int q = 0; q < G_CHUNKS; ++q) {
+        const int c = t + G_THREADS * q;
+        int64_t gr, gk;
+        const __bf16* src;
+        bool full;
+        if (kcontig) {
+            gr = r0 + c / (GK / 8);
+            gk = k0 + (c % (GK / 8)) * 8;
+            src = p + gr * ld + gk;
+            full = gr < rows && gk + 8 <= K;
+        } else {
+            gk = k0 + (c >> 4);
+            gr = r0 + (c & 15) * 8;
+            src = p + gk * ld + gr;
+            full = gk < K && gr + 8 <= rows;
         }
-    } else {
-        // 32 k x 16 chunks of 8 rows
+        if (full && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+            R.v[q] = *reinterpret_cast<const bf16x8g*>(src);
+        } else {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = t + G_THREADS * q;
-            const int kk = c >> 4, rc = (c & 15) * 8;
-            const int64_t gk = k0 + kk, gr = r0 + rc;
-            const __bf16* src = p + gk * ld + gr;
-            bf16x8g v;
-            if (gk < K && gr + 8 <= rows && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
-                v = *reinterpret_cast<const bf16x8g*>(src);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    v[e] = (gk < K && gr + e < rows) ? src[e] : (__bf16)0.0f;
+            for (int e = 0; e < 8; ++e) {
+                const bool ok = kcontig ? (gr < rows && gk + e < K) : (gk < K && gr + e < rows);
+                R.v[q][e] = ok ? src[e] : (__bf16)0.0f;
             }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) tile[(rc + e) * GLD + kk] = v[e];
         }
     }
 }
 
+__device__ __forceinline__ void store_tile(const TileRegs& R, bool kcontig, __bf16* tile)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < G_CHUNKS; ++q) {
+        const int c = t + G_THREADS * q;
+        if (kcontig) {
+            *reinterpret_cast<bf16x8g*>(tile + (c / (GK / 8)) * GLD + (c % (GK / 8)) * 8) = R.v[q];
+        } else {
+            const int kk = c >> 4, rc = (c & 15) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) tile[(rc + e) * GLD + kk] = R.v[q][e];
+        }
+    }
+}
+
+// Double-buffered main loop: the next k tile is loaded into registers while
+// the current one is multiplied from LDS, then stored into the other buffer;
+// one barrier per k tile.
 __global__ void __launch_bounds__(G_THREADS)
 k_gemm_bf16(GemmArgs g)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 As[GM * GLD];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[GN * GLD];
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][GM * GLD];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][GN * GLD];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int h = lane >> 5, col = lane & 31;
-    const int64_t m0 = (int64_t)blockIdx.x * GM, n0 = (int64_t)blockIdx.y * GN;
+    // XCD-aware tile order: workgroups are dealt to the 8 XCDs in turn, so
+    // workgroup w runs on XCD w % 8; the n tiles of one m tile are given to
+    // consecutive workgroups of the same XCD and share its L2 copy of the A
+    // rows.
+    const int64_t m_tiles = (g.M + GM - 1) / GM, n_tiles = (g.N + GN - 1) / GN;
+    const int64_t wid = blockIdx.x, r8 = wid >> 3;
+    const int64_t mt = (r8 / n_tiles) * 8 + (wid & 7), nt = r8 % n_tiles;
+    if (mt >= m_tiles) return;
+    const int64_t m0 = mt * GM, n0 = nt * GN;
     const int64_t kc = (g.K + gridDim.z - 1) / gridDim.z;
     const int64_t kbeg = (int64_t)blockIdx.z * kc;
     const int64_t kend = kbeg + kc < g.K ? kbeg + kc : g.K;
+    const bool a_kc = !g.ta, b_kc = g.tb;
 
     floatx16g acc[2][2];
 #pragma unroll
@@ -128,22 +164,34 @@ k_gemm_bf16(GemmArgs g)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
+    TileRegs ra, rb;
+    if (kbeg < kend) {
+        load_tile(g.a, g.lda, g.M, kend, m0, kbeg, a_kc, ra);
+        load_tile(g.b, g.ldb, g.N, kend, n0, kbeg, b_kc, rb);
+        store_tile(ra, a_kc, As[0]);
+        store_tile(rb, b_kc, Bs[0]);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
-        __syncthreads();
-        stage_tile(g.a, g.lda, g.M, kend, m0, k0, !g.ta, As);
-        stage_tile(g.b, g.ldb, g.N, kend, n0, k0, g.tb, Bs);
-        __syncthreads();
+        const bool more = k0 + GK < kend;
+        if (more) {
+            load_tile(g.a, g.lda, g.M, kend, m0, k0 + GK, a_kc, ra);
+            load_tile(g.b, g.ldb, g.N, kend, n0, k0 + GK, b_kc, rb);
+        }
+        const __bf16* A_ = As[cur];
+        const __bf16* B_ = Bs[cur];
 #pragma unroll
         for (int ks = 0; ks < GK / 16; ++ks) {
             bf16x8g fa[2], fb[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
                 fa[i] = *reinterpret_cast<const bf16x8g*>(
-                    As + (wm * 64 + i * 32 + col) * GLD + ks * 16 + 8 * h);
+                    A_ + (wm * 64 + i * 32 + col) * GLD + ks * 16 + 8 * h);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
                 fb[j] = *reinterpret_cast<const bf16x8g*>(
-                    Bs + (wn * 64 + j * 32 + col) * GLD + ks * 16 + 8 * h);
+                    B_ + (wn * 64 + j * 32 + col) * GLD + ks * 16 + 8 * h);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -151,6 +199,12 @@ k_gemm_bf16(GemmArgs g)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j],
                                                                         0, 0, 0);
         }
+        if (more) {
+            store_tile(ra, a_kc, As[cur ^ 1]);
+            store_tile(rb, b_kc, Bs[cur ^ 1]);
+        }
+        __syncthreads();
+        cur ^= 1;
     }
 
     // epilogue: register r of lane (h, col) holds row 8 (r / 4) + 4 h + r % 4, column col
@@ -249,10 +303,11 @@ int gemm_bf16(const GemmArgs& g0, int splits, hipStream_t s)
     if (g.M <= 0 || g.N <= 0) return DSMC_OK;
     if (splits < 1) splits = 1;
     const int64_t gx = (g.M + GM - 1) / GM, gy = (g.N + GN - 1) / GN;
-    if (gx > 2147483647 || gy > 65535 || splits > 65535) return arg_error("gemm: grid too large");
+    const int64_t tiles = (gx + 7) / 8 * 8 * gy;
+    if (tiles > 2147483647 || splits > 65535) return arg_error("gemm: grid too large");
     if (splits > 1 && !g.partial) return arg_error("gemm: split-K needs a partial buffer");
     if (splits == 1) g.partial = nullptr;
-    dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)splits);
+    dim3 grid((unsigned)tiles, 1u, (unsigned)splits);
     k_gemm_bf16<<<grid, G_THREADS, 0, s>>>(g);
     DSMC_LAUNCH_CHECK("gemm_bf16");
     if (splits > 1) {
