@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--order", default="realistic", choices=["realistic", "shuffled", "sorted"])
     p.add_argument("--quad-steps", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-cavity-loop", action="store_true",
+                   help="skip the cavity flow-loop timing (profiling runs of the step kernels)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 1 GiB device copy first (reference for counter scaling)")
     p.add_argument("--cpu-sample-pairs", type=int, default=4_000_000)
@@ -292,9 +294,10 @@ def main():
     # cells, 250 000 particles, Kn = 0.1, lid 100 m/s): move with diffuse
     # walls, binning, selection, the per-pair network, fused Phase B + moment
     # matching and sampling every step
-    cav = cavity_loop_timing(W, dev, net)
-    extra["cavity_loop"] = cav
-    log(f"cavity loop: {cav}")
+    if not args.no_cavity_loop:
+        cav = cavity_loop_timing(W, dev, net)
+        extra["cavity_loop"] = cav
+        log(f"cavity loop: {cav}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -100,20 +100,32 @@ struct TableGrid {
     double lne_lo, lne_hi;
 };
 
+// One wave per row at a time: the row's two inputs are formed once (table
+// grid node or x), lane l computes outputs l, l + 64, ... with the layer-0
+// weights of those columns held in registers across rows (n <= 1024).
+constexpr int FIRST_COLS = 16;
+
 __global__ void __launch_bounds__(256)
 k_anet_first(int64_t R, int n, const float* __restrict__ x, const __bf16* __restrict__ W0,
              const float* __restrict__ b0, float* __restrict__ z0, __bf16* __restrict__ h0,
              float* __restrict__ xkeep, int64_t row0, TableGrid tg, int use_grid)
 {
-    const int64_t total = R * n;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = q / n;
-        const int c = (int)(q - r * n);
+    const int lane = threadIdx.x & 63;
+    float wa[FIRST_COLS], wb[FIRST_COLS], bb[FIRST_COLS];
+#pragma unroll
+    for (int e = 0; e < FIRST_COLS; ++e) {
+        const int c = lane + 64 * e;
+        wa[e] = c < n ? (float)W0[2 * c] : 0.0f;
+        wb[e] = c < n ? (float)W0[2 * c + 1] : 0.0f;
+        bb[e] = c < n ? b0[c] : 0.0f;
+    }
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < R; r += nwaves) {
         float x0, x1;
         if (use_grid) {
             const int64_t g = row0 + r;
-            const int64_t i = g / tg.n_b, j = g % tg.n_b;
+            const int64_t i = g / tg.n_b, j = g - i * tg.n_b;
             // normalised ln E of node i: 2 i / (n_e - 1) - 1; b / b_max = j / (n_b - 1)
             x0 = (float)(2.0 * (double)i / (double)(tg.n_e - 1) - 1.0);
             x1 = (float)((double)j / (double)(tg.n_b - 1));
@@ -121,13 +133,18 @@ k_anet_first(int64_t R, int n, const float* __restrict__ x, const __bf16* __rest
             x0 = x[2 * r];
             x1 = x[2 * r + 1];
         }
-        if (xkeep && c == 0) {
+        if (xkeep && lane == 0) {
             xkeep[2 * r] = x0;
             xkeep[2 * r + 1] = x1;
         }
-        const float zz = (float)W0[2 * c] * x0 + (float)W0[2 * c + 1] * x1 + b0[c];
-        if (z0) z0[r * n + c] = zz;
-        h0[r * n + c] = (__bf16)silu_f(zz);
+#pragma unroll
+        for (int e = 0; e < FIRST_COLS; ++e) {
+            const int c = lane + 64 * e;
+            if (c >= n) break;
+            const float zz = wa[e] * x0 + wb[e] * x1 + bb[e];
+            if (z0) z0[r * n + c] = zz;
+            h0[r * n + c] = (__bf16)silu_f(zz);
+        }
     }
 }
 

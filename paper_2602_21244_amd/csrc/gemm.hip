@@ -7,8 +7,8 @@
 //   B(k, n) = TB ? b[n ldb + k] : b[k ldb + n]
 //
 // A 256-thread workgroup computes a 128 x 128 tile: each wave a 64 x 64 block
-// as 2 x 2 v_mfma_f32_32x32x16_bf16 accumulators.  Operand tiles (128 x 64)
-// are staged in LDS with k contiguous (row stride 72 bf16 to spread banks),
+// as 2 x 2 v_mfma_f32_32x32x16_bf16 accumulators.  Operand tiles (128 x 32)
+// are staged in LDS with k contiguous (row stride 40 bf16 to spread banks),
 // double-buffered: the next tile is loaded into registers during the MFMAs;
 // operands that are k-contiguous in memory are copied with 16-byte loads, the
 // transposed ones are scattered into that layout element by element.  A
@@ -21,7 +21,7 @@ namespace dsmc {
 typedef __bf16 bf16x8g __attribute__((__vector_size__(8 * sizeof(__bf16))));
 typedef float floatx16g __attribute__((__vector_size__(16 * sizeof(float))));
 
-constexpr int GM = 128, GN = 128, GK = 64, GLD = GK + 8;
+constexpr int GM = 128, GN = 128, GK = 32, GLD = GK + 8;
 constexpr int G_CHUNKS = GM * GK / 8 / 256;   // 8-element chunks per thread and operand
 constexpr int G_THREADS = 256;
 
@@ -134,7 +134,7 @@ __device__ __forceinline__ void store_tile(const TileRegs& R, bool kcontig, __bf
 // Double-buffered main loop: the next k tile is loaded into registers while
 // the current one is multiplied from LDS, then stored into the other buffer;
 // one barrier per k tile.
-__global__ void __launch_bounds__(G_THREADS)
+__global__ void __launch_bounds__(G_THREADS, 4)
 k_gemm_bf16(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) __bf16 As[2][GM * GLD];
