@@ -24,8 +24,16 @@ struct DomainDev {
     double Lx, Ly, cx, cy;      // cx = nx / Lx, cy = ny / Ly
     int32_t kind[4];
     double sw[4];               // sqrt(k T_w / m)
-    double uw[4][3];
+    double uw0[4], uw1[4], uw2[4];   // wall velocity components per side
 };
+
+// Entry `side` of a per-side array of the by-value domain, by selects (a
+// dynamic index into a kernel argument would go through scratch memory).
+template <typename V>
+__device__ __forceinline__ V side_of(const V (&a)[4], int side)
+{
+    return side == 0 ? a[0] : side == 1 ? a[1] : side == 2 ? a[2] : a[3];
+}
 
 // Diffuse re-emission at `side` for wall event h of the particle in slot s:
 // Philox(s, h, step, slot 6) -> U1, U2 and (.., slot 7) -> U3.
@@ -36,18 +44,19 @@ __device__ __forceinline__ void wall_velocity(const DomainDev& D, int side, cons
     const U4 r0 = draw(rng, s, h, SLOT_WALL0);
     const U4 r1 = draw(rng, s, h, SLOT_WALL1);
     const double U1 = unif53(r0.a, r0.b), U2 = unif53(r0.c, r0.d), U3 = unif53(r1.a, r1.b);
-    const double sw = D.sw[side];
+    const double sw = side_of(D.sw, side);
     const double vn = sw * sqrt(-2.0 * log(1.0 - U1));
     double n1, n2;
     box_muller(U2, U3, n1, n2);
+    const double w0 = side_of(D.uw0, side), w1 = side_of(D.uw1, side), w2 = side_of(D.uw2, side);
     if (side < 2) {
         ux = side == 0 ? vn : -vn;
-        uy = D.uw[side][1] + sw * n1;
-        uz = D.uw[side][2] + sw * n2;
+        uy = w1 + sw * n1;
+        uz = w2 + sw * n2;
     } else {
         uy = side == 2 ? vn : -vn;
-        ux = D.uw[side][0] + sw * n1;
-        uz = D.uw[side][2] + sw * n2;
+        ux = w0 + sw * n1;
+        uz = w2 + sw * n2;
     }
 }
 
@@ -94,7 +103,7 @@ k_move(int32_t n, V3<T> pos, V3<T> v, DomainDev D, double dt, dsmc_rng rng,
                 y = side == 3 ? D.Ly : 0.0;
             }
             t = t - th;
-            const int kind = D.kind[side];
+            const int kind = side_of(D.kind, side);
             if (kind == DSMC_WALL_PERIODIC) {
                 if (side == 0) x = D.Lx;
                 else if (side == 1) x = 0.0;
@@ -114,8 +123,10 @@ k_move(int32_t n, V3<T> pos, V3<T> v, DomainDev D, double dt, dsmc_rng rng,
         if (y > D.Ly) y = D.Ly;
         // stored positions stay inside the box in the storage type too
         T xs = (T)x, ys = (T)y;
-        if ((double)xs > D.Lx) xs = nextafter(xs, (T)0);
-        if ((double)ys > D.Ly) ys = nextafter(ys, (T)0);
+        if constexpr (sizeof(T) == 4) {
+            if ((double)xs > D.Lx) xs = nextafterf(xs, 0.0f);
+            if ((double)ys > D.Ly) ys = nextafterf(ys, 0.0f);
+        }
         pos.x[p] = xs;
         pos.y[p] = ys;
         v.x[p] = (T)ux;
@@ -251,7 +262,9 @@ static int check_domain(const dsmc_domain* dom, DomainDev* D)
             return arg_error("dsmc_move: side %d wall temperature %g", q, dom->T_w[q]);
         D->kind[q] = k;
         D->sw[q] = k == DSMC_WALL_DIFFUSE ? sqrt(BOLTZMANN * dom->T_w[q] / dom->m) : 0.0;
-        for (int c = 0; c < 3; ++c) D->uw[q][c] = dom->u_w[q][c];
+        D->uw0[q] = dom->u_w[q][0];
+        D->uw1[q] = dom->u_w[q][1];
+        D->uw2[q] = dom->u_w[q][2];
     }
     if ((dom->kind[0] == DSMC_WALL_PERIODIC) != (dom->kind[1] == DSMC_WALL_PERIODIC) ||
         (dom->kind[2] == DSMC_WALL_PERIODIC) != (dom->kind[3] == DSMC_WALL_PERIODIC))

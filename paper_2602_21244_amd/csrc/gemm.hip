@@ -134,7 +134,7 @@ __device__ __forceinline__ void store_tile(const TileRegs& R, bool kcontig, __bf
 // Double-buffered main loop: the next k tile is loaded into registers while
 // the current one is multiplied from LDS, then stored into the other buffer;
 // one barrier per k tile.
-__global__ void __launch_bounds__(G_THREADS, 4)
+__global__ void __launch_bounds__(G_THREADS, 3)
 k_gemm_bf16(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) __bf16 As[2][GM * GLD];
