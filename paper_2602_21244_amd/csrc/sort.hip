@@ -6,11 +6,15 @@
 // passes for up to 2^18 - 1 cells).  Every pass is stable, so the result is
 // the stable order (original order inside a cell) whatever the input order
 // and without atomics on the particle data:
-//   up    : per 4096-particle tile, a 512-bucket digit histogram (LDS atomics)
-//   scan  : exclusive scan of the digit-major (digit, tile) histogram table
-//   down  : each wave ranks its 1024 particles in index order (digit match by
-//           ballots, per-wave digit counters in LDS), the tile is reordered by
-//           digit in LDS and written out as contiguous digit runs
+//   up    : per 4096-particle tile, a 512-bucket digit histogram (LDS
+//           atomics), stored tile-major so every store is a row segment
+//   scan  : offsets of the (tile, digit) table in digit-major order by three
+//           small kernels over chunks of tiles (column sums, a scan of those
+//           per digit, expansion of the chunk rows)
+//   down  : each wave ranks its 1024 particles in index order (digit groups
+//           split off by ballots, per-wave digit counters in LDS), the tile
+//           is reordered by digit through one LDS array (keys, then values)
+//           and written out as contiguous digit runs
 // The last down pass also gathers vx, vy, vz into sorted order; one pass
 // over the sorted keys then writes cell_start.
 // Ids outside [0, n_cells) are mapped to the key n_cells, so they sort after
@@ -30,17 +34,6 @@ __device__ __forceinline__ int32_t sort_key(const int32_t* cell_of, int64_t p, i
 {
     const int32_t c = cell_of[p];
     return (c < 0 || c >= n_cells) ? n_cells : c;
-}
-
-// Lanes of the wave whose valid digit equals this lane's (bits 0..dbits-1).
-__device__ __forceinline__ uint64_t match_digit(int32_t d, bool valid, int dbits)
-{
-    uint64_t same = __ballot(valid);
-    for (int b = 0; b < dbits; ++b) {
-        const uint64_t ones = __ballot((d >> b) & 1);
-        same &= ((d >> b) & 1) ? ones : ~ones;
-    }
-    return same;
 }
 
 // Digit histogram of one tile: each thread counts 16 consecutive keys
@@ -99,7 +92,8 @@ k_radix_up(const int32_t* __restrict__ keys_in, int32_t n, int32_t n_cells, int 
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i <= mask; i += SORT_THREADS) ghist[(int64_t)i * nblk + blockIdx.x] = h[i];
+    for (int i = threadIdx.x; i <= mask; i += SORT_THREADS)
+        ghist[(int64_t)blockIdx.x * (mask + 1) + i] = h[i];
 }
 
 // Exclusive scan of RADIX values in LDS by the 256 threads (two per thread).
@@ -124,6 +118,131 @@ __device__ __forceinline__ void block_scan_radix(const int32_t* tot, int32_t* ex
     ex[2 * t + 1] = excl + a;
 }
 
+// Offsets of the tile-major (tile, digit) count table H[nblk][R]:
+//   O[b][d] = sum_{d' < d} T[d'] + sum_{b' < b} H[b'][d],  T[d] = sum_b H[b][d]
+// in three small kernels over chunks of HCHUNK tiles (rows), every access a
+// coalesced row segment: chunk column sums, an exclusive scan of those over
+// the chunks per digit (with the digit totals), and the expansion of each
+// chunk's rows.
+constexpr int HCHUNK = 32;
+constexpr int HSEG = 16;        // chunk segments per digit in the chunk scan
+constexpr int HDIG = 256 / HSEG;
+
+__global__ void __launch_bounds__(256)
+k_hist_chunk_sum(const int32_t* __restrict__ h, int32_t nblk, int32_t R, int32_t* __restrict__ csum)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * HCHUNK;
+    const int nb = (int)((nblk - b0) < HCHUNK ? (nblk - b0) : HCHUNK);
+    for (int d = threadIdx.x; d < R; d += 256) {
+        int32_t v[HCHUNK];
+#pragma unroll
+        for (int r = 0; r < HCHUNK; ++r) v[r] = r < nb ? h[(b0 + r) * R + d] : 0;
+        int32_t s = 0;
+#pragma unroll
+        for (int r = 0; r < HCHUNK; ++r) s += v[r];
+        csum[(int64_t)blockIdx.x * R + d] = s;
+    }
+}
+
+// One workgroup per HDIG digits; HSEG threads per digit split the chunks.
+__global__ void __launch_bounds__(256)
+k_hist_chunk_scan(const int32_t* __restrict__ csum, int32_t nch, int32_t R,
+                  int32_t* __restrict__ cpre, int32_t* __restrict__ tot)
+{
+    __shared__ int32_t seg[HSEG][HDIG];
+    const int dl = threadIdx.x % HDIG, g = threadIdx.x / HDIG;
+    const int d = blockIdx.x * HDIG + dl;
+    const int per = (nch + HSEG - 1) / HSEG;
+    const int c0 = g * per, c1 = (c0 + per) < nch ? (c0 + per) : nch;
+    int32_t s = 0;
+    if (d < R) {
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) s += csum[(int64_t)c * R + d];
+    }
+    seg[g][dl] = s;
+    __syncthreads();
+    int32_t run = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < HSEG; ++q) {
+        const int32_t x = seg[q][dl];
+        run += q < g ? x : 0;
+        all += x;
+    }
+    if (d < R) {
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) {
+            const int32_t x = csum[(int64_t)c * R + d];
+            cpre[(int64_t)c * R + d] = run;
+            run += x;
+        }
+        if (g == 0) tot[d] = all;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_hist_expand(const int32_t* __restrict__ h, const int32_t* __restrict__ cpre,
+              const int32_t* __restrict__ tot, int32_t nblk, int32_t R, int32_t* __restrict__ goff)
+{
+    __shared__ int32_t t_s[RADIX];
+    __shared__ int32_t e_s[RADIX];
+    for (int d = threadIdx.x; d < RADIX; d += 256) t_s[d] = d < R ? tot[d] : 0;
+    __syncthreads();
+    block_scan_radix(t_s, e_s);
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * HCHUNK;
+    const int nb = (int)((nblk - b0) < HCHUNK ? (nblk - b0) : HCHUNK);
+    for (int d = threadIdx.x; d < R; d += 256) {
+        int32_t v[HCHUNK];
+#pragma unroll
+        for (int r = 0; r < HCHUNK; ++r) v[r] = r < nb ? h[(b0 + r) * R + d] : 0;
+        int32_t run = e_s[d] + cpre[(int64_t)blockIdx.x * R + d];
+#pragma unroll
+        for (int r = 0; r < HCHUNK; ++r) {
+            if (r < nb) goff[(b0 + r) * R + d] = run;
+            run += v[r];
+        }
+    }
+}
+
+constexpr int PEEL = 4;   // digit groups split off one at a time before the bit match
+
+// Rank of this lane's item among the wave's valid items with the same digit
+// (lanes in index order), and the size of that group.  Groups are split off
+// by the digit of their lowest lane, at most PEEL times (input close to
+// sorted has few distinct digits per wave); lanes left after that are
+// matched bit by bit among themselves.
+__device__ __forceinline__ void wave_rank(int32_t d, bool valid, int dbits, int lane,
+                                          int32_t& before, int32_t& count)
+{
+    uint64_t todo = __ballot(valid);
+    before = 0;
+    count = 0;
+    for (int it = 0; it < PEEL && todo; ++it) {
+        const int leader = __builtin_ctzll(todo);
+        const int32_t dl = __builtin_amdgcn_readlane(d, leader);
+        const uint64_t grp = __ballot(d == dl) & todo;
+        if ((grp >> lane) & 1) {
+            before = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(grp >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)grp, 0u));
+            count = __popcll(grp);
+        }
+        todo &= ~grp;
+    }
+    if (todo) {
+        uint64_t same = todo;
+        for (int b = 0; b < dbits; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t ones = __ballot(bit);
+            same &= bit ? ones : ~ones;
+        }
+        if ((todo >> lane) & 1) {
+            before = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+            count = __popcll(same);
+        }
+    }
+}
+
 // LAST: the final pass also gathers the velocities into sorted order
 // (vals are then the original indices, i.e. perm).
 template <bool FIRST, bool LAST, typename T>
@@ -133,95 +252,128 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
              const int32_t* __restrict__ goff, int32_t* __restrict__ keys_out,
              int32_t* __restrict__ vals_out, V3<const T> vin, V3<T> vout)
 {
-    __shared__ int32_t cnt[SORT_THREADS / 64][RADIX];
-    __shared__ int32_t tot[RADIX];
-    __shared__ int32_t boff[RADIX];
-    __shared__ int32_t gbase[RADIX];
-    __shared__ int32_t sk[SORT_TILE];
-    __shared__ int32_t sv[SORT_TILE];
+    __shared__ int32_t cnt[SORT_THREADS / 64][RADIX];   // per wave and digit
+    __shared__ int32_t gb[RADIX];                       // global slot of tile slot 0, per digit
+    __shared__ int32_t wsum[SORT_THREADS / 64];
+    __shared__ int32_t stage[SORT_TILE];               // keys, then values, in tile order
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < (SORT_THREADS / 64) * RADIX; i += SORT_THREADS)
         (&cnt[0][0])[i] = 0;
+    // this tile's global digit offsets (digits 2t, 2t+1), loaded early
+    int32_t g[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int d = 2 * threadIdx.x + e;
+        g[e] = d <= mask ? goff[(int64_t)blockIdx.x * (mask + 1) + d] : 0;
+    }
     __syncthreads();
 
     const int64_t tbase = (int64_t)blockIdx.x * SORT_TILE;
-    const int64_t wbase = tbase + (int64_t)w * WAVE_SPAN;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int32_t tn = (int32_t)(((int64_t)n - tbase) < SORT_TILE ? ((int64_t)n - tbase) : SORT_TILE);
+    const int32_t* kt = keys_in + tbase;
+    const int32_t* vt = FIRST ? nullptr : vals_in + tbase;
+    const int woff = w * WAVE_SPAN;
     int32_t key[SORT_ITEMS], val[SORT_ITEMS], rank[SORT_ITEMS];
-    // all loads of the wave's 1024 items first (independent, coalesced), so
-    // the ranking below does not wait on one load per item
+    // all loads of the wave's 1024 items first (independent, coalesced)
 #pragma unroll
     for (int it = 0; it < SORT_ITEMS; ++it) {
-        const int64_t p = wbase + it * 64 + lane;
+        const int q = woff + it * 64 + lane;
         key[it] = 0;
         val[it] = 0;
-        if (p < n) {
+        if (q < tn) {
             if (FIRST) {
-                key[it] = sort_key(keys_in, p, n_cells);
-                val[it] = (int32_t)p;
+                const int32_t c = kt[q];
+                key[it] = (c < 0 || c >= n_cells) ? n_cells : c;
+                val[it] = (int32_t)(tbase + q);
             } else {
-                key[it] = keys_in[p];
-                val[it] = vals_in[p];
+                key[it] = kt[q];
+                val[it] = vt[q];
             }
         }
     }
 #pragma unroll
     for (int it = 0; it < SORT_ITEMS; ++it) {
-        const int64_t p = wbase + it * 64 + lane;
-        const bool valid = p < n;
-        const int32_t k = key[it];
-        const int32_t d = (k >> shift) & mask;
-        const uint64_t same = match_digit(d, valid, dbits);
-        const int32_t before = __popcll(same & lt_mask);
+        const bool valid = woff + it * 64 + lane < tn;
+        const int32_t d = (key[it] >> shift) & mask;
+        int32_t before, count;
+        wave_rank(d, valid, dbits, lane, before, count);
         const int32_t old = cnt[w][d];
         __builtin_amdgcn_wave_barrier();
-        if (valid && before == 0) cnt[w][d] = old + __popcll(same);
+        if (valid && before == 0) cnt[w][d] = old + count;
         __builtin_amdgcn_wave_barrier();
         rank[it] = valid ? old + before : -1;
     }
     __syncthreads();
-    // per digit: exclusive over the waves, tile total
-    for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) {
-        int32_t s = 0;
+    // thread t owns digits 2t and 2t+1: exclusive over the waves, then the
+    // tile's exclusive scan over digits; cnt[w][d] becomes the tile slot of
+    // wave w's first item of digit d, gb[d] the global slot of tile slot 0
+    {
+        const int t = threadIdx.x;
+        int32_t c[2][SORT_THREADS / 64], tsum[2];
 #pragma unroll
-        for (int q = 0; q < SORT_THREADS / 64; ++q) {
-            const int32_t c = cnt[q][d];
-            cnt[q][d] = s;
-            s += c;
+        for (int e = 0; e < 2; ++e) {
+            const int d = 2 * t + e;
+            int32_t acc = 0;
+#pragma unroll
+            for (int q = 0; q < SORT_THREADS / 64; ++q) {
+                c[e][q] = acc;
+                acc += cnt[q][d];
+            }
+            tsum[e] = acc;
         }
-        tot[d] = s;
-        gbase[d] = d <= mask ? goff[(int64_t)d * nblk + blockIdx.x] : 0;
+        int32_t x = tsum[0] + tsum[1];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        int32_t excl = x - (tsum[0] + tsum[1]);
+        for (int q = 0; q < w; ++q) excl += wsum[q];
+        const int32_t be[2] = {excl, excl + tsum[0]};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int d = 2 * t + e;
+#pragma unroll
+            for (int q = 0; q < SORT_THREADS / 64; ++q) cnt[q][d] = c[e][q] + be[e];
+            gb[d] = g[e] - be[e];
+        }
     }
-    __syncthreads();
-    block_scan_radix(tot, boff);
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < SORT_ITEMS; ++it) {
         if (rank[it] < 0) continue;
         const int32_t d = (key[it] >> shift) & mask;
-        const int32_t pos = boff[d] + cnt[w][d] + rank[it];
-        sk[pos] = key[it];
-        sv[pos] = val[it];
+        rank[it] += cnt[w][d];                          // tile slot
+        stage[rank[it]] = key[it];
     }
     __syncthreads();
-    const int64_t left = (int64_t)n - tbase;
-    const int32_t tn = left < SORT_TILE ? (int32_t)left : SORT_TILE;
     int32_t oo[SORT_ITEMS], vv[SORT_ITEMS];
 #pragma unroll
     for (int it = 0; it < SORT_ITEMS; ++it) {
         const int s = threadIdx.x + it * SORT_THREADS;
         oo[it] = -1;
-        vv[it] = 0;
         if (s < tn) {
-            const int32_t k = sk[s];
-            const int32_t d = (k >> shift) & mask;
-            const int32_t o = gbase[d] + (s - boff[d]);
-            const int32_t v = sv[s];
+            const int32_t k = stage[s];
+            const int32_t o = gb[(k >> shift) & mask] + s;
             keys_out[o] = k;
-            vals_out[o] = v;
             oo[it] = o;
-            vv[it] = v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it)
+        if (rank[it] >= 0) stage[rank[it]] = val[it];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        const int s = threadIdx.x + it * SORT_THREADS;
+        vv[it] = 0;
+        if (oo[it] >= 0) {
+            vv[it] = stage[s];
+            vals_out[oo[it]] = vv[it];
         }
     }
     if (LAST) {
@@ -301,8 +453,13 @@ static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_ve
     int32_t* ghist = reinterpret_cast<int32_t*>(w);
     w += align_up(sizeof(int32_t) * (size_t)(RADIX * nblk));
     int32_t* goff = reinterpret_cast<int32_t*>(w);
-    w += align_up(sizeof(int32_t) * (size_t)(RADIX * nblk + 1));
-    void* scan_ws = w;
+    w += align_up(sizeof(int32_t) * (size_t)(RADIX * nblk));
+    const int64_t nch = (nblk + HCHUNK - 1) / HCHUNK;
+    int32_t* csum = reinterpret_cast<int32_t*>(w);
+    w += align_up(sizeof(int32_t) * (size_t)(RADIX * nch));
+    int32_t* cpre = reinterpret_cast<int32_t*>(w);
+    w += align_up(sizeof(int32_t) * (size_t)(RADIX * nch));
+    int32_t* dtot = reinterpret_cast<int32_t*>(w);
 
     int nbits = 0;
     const int passes = sort_passes(n_cells, &nbits);
@@ -322,8 +479,11 @@ static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_ve
             k_radix_up<false><<<(int)nblk, SORT_THREADS, 0, s>>>(kin, n, n_cells, shift, mask, dbits,
                                                                  (int32_t)nblk, ghist, st);
         DSMC_LAUNCH_CHECK("sort:up");
-        int rc = exclusive_scan_i32(ghist, goff, (int64_t)(mask + 1) * nblk, nullptr, scan_ws, s);
-        if (rc) return rc;
+        const int32_t R = mask + 1;
+        k_hist_chunk_sum<<<(int)nch, 256, 0, s>>>(ghist, (int32_t)nblk, R, csum);
+        k_hist_chunk_scan<<<(R + HDIG - 1) / HDIG, 256, 0, s>>>(csum, (int32_t)nch, R, cpre, dtot);
+        k_hist_expand<<<(int)nch, 256, 0, s>>>(ghist, cpre, dtot, (int32_t)nblk, R, goff);
+        DSMC_LAUNCH_CHECK("sort:scan");
         const bool last = pass == passes - 1;
         const V3<const T> vi = v3<const T>(vin);
         const V3<T> vo = v3<T>(vout);
@@ -364,10 +524,11 @@ extern "C" size_t dsmc_sort_cells_ws(int32_t n, int32_t n_cells)
 {
     if (n < 0 || n_cells < 0) return 0;
     const int64_t nblk = sort_tiles(n);
+    const int64_t nch = (nblk + HCHUNK - 1) / HCHUNK;
     return 3 * align_up(sizeof(int32_t) * (size_t)n) +
-           align_up(sizeof(int32_t) * (size_t)(RADIX * nblk)) +
-           align_up(sizeof(int32_t) * (size_t)(RADIX * nblk + 1)) +
-           scan_ws_bytes(RADIX * nblk) + 256;
+           2 * align_up(sizeof(int32_t) * (size_t)(RADIX * nblk)) +
+           2 * align_up(sizeof(int32_t) * (size_t)(RADIX * nch)) +
+           align_up(sizeof(int32_t) * (size_t)RADIX) + 256;
 }
 
 extern "C" int dsmc_sort_cells(int32_t n, int32_t n_cells, const int32_t* cell_of, int32_t dtype,
