@@ -11,10 +11,11 @@
 //   scan  : offsets of the (tile, digit) table in digit-major order by three
 //           small kernels over chunks of tiles (column sums, a scan of those
 //           per digit, expansion of the chunk rows)
-//   down  : each wave ranks its 1024 particles in index order (digit groups
-//           split off by ballots, per-wave digit counters in LDS), the tile
-//           is reordered by digit through one LDS array (keys, then values)
-//           and written out as contiguous digit runs
+//   down  : 512 threads per tile; each wave ranks its 512 particles in index
+//           order (digit groups split off by ballots, per-wave digit
+//           counters in LDS), the tile is reordered by digit through one LDS
+//           array (keys, then values) and written out as contiguous digit
+//           runs
 // The last down pass also gathers vx, vy, vz into sorted order; one pass
 // over the sorted keys then writes cell_start.
 // Ids outside [0, n_cells) are mapped to the key n_cells, so they sort after
@@ -28,7 +29,12 @@ constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SORT_THREADS = 256;
 constexpr int SORT_ITEMS = 16;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // 4096
-constexpr int WAVE_SPAN = 64 * SORT_ITEMS;              // particles per wave
+// down kernel: same tile, DN_THREADS threads of DN_ITEMS particles
+constexpr int DN_THREADS = 512;
+constexpr int DN_ITEMS = SORT_TILE / DN_THREADS;
+constexpr int DN_WAVES = DN_THREADS / 64;
+constexpr int DN_DPT = RADIX / DN_THREADS;               // digits owned per thread
+constexpr int WAVE_SPAN = 64 * DN_ITEMS;                // particles per wave
 
 __device__ __forceinline__ int32_t sort_key(const int32_t* cell_of, int64_t p, int32_t n_cells)
 {
@@ -246,25 +252,25 @@ __device__ __forceinline__ void wave_rank(int32_t d, bool valid, int dbits, int 
 // LAST: the final pass also gathers the velocities into sorted order
 // (vals are then the original indices, i.e. perm).
 template <bool FIRST, bool LAST, typename T>
-__global__ void __launch_bounds__(SORT_THREADS)
+__global__ void __launch_bounds__(DN_THREADS)
 k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int32_t n,
              int32_t n_cells, int shift, int32_t mask, int dbits, int32_t nblk,
              const int32_t* __restrict__ goff, int32_t* __restrict__ keys_out,
              int32_t* __restrict__ vals_out, V3<const T> vin, V3<T> vout)
 {
-    __shared__ int32_t cnt[SORT_THREADS / 64][RADIX];   // per wave and digit
+    __shared__ int32_t cnt[DN_WAVES][RADIX];   // per wave and digit
     __shared__ int32_t gb[RADIX];                       // global slot of tile slot 0, per digit
-    __shared__ int32_t wsum[SORT_THREADS / 64];
+    __shared__ int32_t wsum[DN_WAVES];
     __shared__ int32_t stage[SORT_TILE];               // keys, then values, in tile order
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < (SORT_THREADS / 64) * RADIX; i += SORT_THREADS)
+    for (int i = threadIdx.x; i < DN_WAVES * RADIX; i += DN_THREADS)
         (&cnt[0][0])[i] = 0;
     // this tile's global digit offsets (digits 2t, 2t+1), loaded early
-    int32_t g[2];
+    int32_t g[DN_DPT];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int d = 2 * threadIdx.x + e;
+    for (int e = 0; e < DN_DPT; ++e) {
+        const int d = DN_DPT * threadIdx.x + e;
         g[e] = d <= mask ? goff[(int64_t)blockIdx.x * (mask + 1) + d] : 0;
     }
     __syncthreads();
@@ -274,10 +280,10 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
     const int32_t* kt = keys_in + tbase;
     const int32_t* vt = FIRST ? nullptr : vals_in + tbase;
     const int woff = w * WAVE_SPAN;
-    int32_t key[SORT_ITEMS], val[SORT_ITEMS], rank[SORT_ITEMS];
+    int32_t key[DN_ITEMS], val[DN_ITEMS], rank[DN_ITEMS];
     // all loads of the wave's 1024 items first (independent, coalesced)
 #pragma unroll
-    for (int it = 0; it < SORT_ITEMS; ++it) {
+    for (int it = 0; it < DN_ITEMS; ++it) {
         const int q = woff + it * 64 + lane;
         key[it] = 0;
         val[it] = 0;
@@ -293,7 +299,7 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
         }
     }
 #pragma unroll
-    for (int it = 0; it < SORT_ITEMS; ++it) {
+    for (int it = 0; it < DN_ITEMS; ++it) {
         const bool valid = woff + it * 64 + lane < tn;
         const int32_t d = (key[it] >> shift) & mask;
         int32_t before, count;
@@ -305,24 +311,27 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
         rank[it] = valid ? old + before : -1;
     }
     __syncthreads();
-    // thread t owns digits 2t and 2t+1: exclusive over the waves, then the
-    // tile's exclusive scan over digits; cnt[w][d] becomes the tile slot of
-    // wave w's first item of digit d, gb[d] the global slot of tile slot 0
+    // thread t owns digits DN_DPT t .. DN_DPT t + DN_DPT - 1: exclusive over
+    // the waves, then the tile's exclusive scan over digits; cnt[w][d]
+    // becomes the tile slot of wave w's first item of digit d, gb[d] the
+    // global slot of tile slot 0
     {
         const int t = threadIdx.x;
-        int32_t c[2][SORT_THREADS / 64], tsum[2];
+        int32_t c[DN_DPT][DN_WAVES], tsum[DN_DPT];
+        int32_t x = 0;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int d = 2 * t + e;
+        for (int e = 0; e < DN_DPT; ++e) {
+            const int d = DN_DPT * t + e;
             int32_t acc = 0;
 #pragma unroll
-            for (int q = 0; q < SORT_THREADS / 64; ++q) {
+            for (int q = 0; q < DN_WAVES; ++q) {
                 c[e][q] = acc;
                 acc += cnt[q][d];
             }
             tsum[e] = acc;
+            x += acc;
         }
-        int32_t x = tsum[0] + tsum[1];
+        const int32_t own = x;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int32_t y = __shfl_up(x, o, 64);
@@ -330,30 +339,30 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
         }
         if (lane == 63) wsum[w] = x;
         __syncthreads();
-        int32_t excl = x - (tsum[0] + tsum[1]);
-        for (int q = 0; q < w; ++q) excl += wsum[q];
-        const int32_t be[2] = {excl, excl + tsum[0]};
+        int32_t be = x - own;
+        for (int q = 0; q < w; ++q) be += wsum[q];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int d = 2 * t + e;
+        for (int e = 0; e < DN_DPT; ++e) {
+            const int d = DN_DPT * t + e;
 #pragma unroll
-            for (int q = 0; q < SORT_THREADS / 64; ++q) cnt[q][d] = c[e][q] + be[e];
-            gb[d] = g[e] - be[e];
+            for (int q = 0; q < DN_WAVES; ++q) cnt[q][d] = c[e][q] + be;
+            gb[d] = g[e] - be;
+            be += tsum[e];
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < SORT_ITEMS; ++it) {
+    for (int it = 0; it < DN_ITEMS; ++it) {
         if (rank[it] < 0) continue;
         const int32_t d = (key[it] >> shift) & mask;
         rank[it] += cnt[w][d];                          // tile slot
         stage[rank[it]] = key[it];
     }
     __syncthreads();
-    int32_t oo[SORT_ITEMS], vv[SORT_ITEMS];
+    int32_t oo[DN_ITEMS], vv[DN_ITEMS];
 #pragma unroll
-    for (int it = 0; it < SORT_ITEMS; ++it) {
-        const int s = threadIdx.x + it * SORT_THREADS;
+    for (int it = 0; it < DN_ITEMS; ++it) {
+        const int s = threadIdx.x + it * DN_THREADS;
         oo[it] = -1;
         if (s < tn) {
             const int32_t k = stage[s];
@@ -364,12 +373,12 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < SORT_ITEMS; ++it)
+    for (int it = 0; it < DN_ITEMS; ++it)
         if (rank[it] >= 0) stage[rank[it]] = val[it];
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < SORT_ITEMS; ++it) {
-        const int s = threadIdx.x + it * SORT_THREADS;
+    for (int it = 0; it < DN_ITEMS; ++it) {
+        const int s = threadIdx.x + it * DN_THREADS;
         vv[it] = 0;
         if (oo[it] >= 0) {
             vv[it] = stage[s];
@@ -378,16 +387,16 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
     }
     if (LAST) {
         // all gathers first, then all stores, so the loads overlap
-        T gx[SORT_ITEMS], gy[SORT_ITEMS], gz[SORT_ITEMS];
+        T gx[DN_ITEMS], gy[DN_ITEMS], gz[DN_ITEMS];
 #pragma unroll
-        for (int it = 0; it < SORT_ITEMS; ++it) {
+        for (int it = 0; it < DN_ITEMS; ++it) {
             if (oo[it] < 0) continue;
             gx[it] = vin.x[vv[it]];
             gy[it] = vin.y[vv[it]];
             gz[it] = vin.z[vv[it]];
         }
 #pragma unroll
-        for (int it = 0; it < SORT_ITEMS; ++it) {
+        for (int it = 0; it < DN_ITEMS; ++it) {
             if (oo[it] < 0) continue;
             vout.x[oo[it]] = gx[it];
             vout.y[oo[it]] = gy[it];
@@ -488,19 +497,19 @@ static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_ve
         const V3<const T> vi = v3<const T>(vin);
         const V3<T> vo = v3<T>(vout);
         if (pass == 0 && last)
-            k_radix_down<true, true, T><<<(int)nblk, SORT_THREADS, 0, s>>>(
+            k_radix_down<true, true, T><<<(int)nblk, DN_THREADS, 0, s>>>(
                 kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
                 vi, vo);
         else if (pass == 0)
-            k_radix_down<true, false, T><<<(int)nblk, SORT_THREADS, 0, s>>>(
+            k_radix_down<true, false, T><<<(int)nblk, DN_THREADS, 0, s>>>(
                 kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
                 vi, vo);
         else if (last)
-            k_radix_down<false, true, T><<<(int)nblk, SORT_THREADS, 0, s>>>(
+            k_radix_down<false, true, T><<<(int)nblk, DN_THREADS, 0, s>>>(
                 kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
                 vi, vo);
         else
-            k_radix_down<false, false, T><<<(int)nblk, SORT_THREADS, 0, s>>>(
+            k_radix_down<false, false, T><<<(int)nblk, DN_THREADS, 0, s>>>(
                 kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
                 vi, vo);
         DSMC_LAUNCH_CHECK("sort:down");
