@@ -238,6 +238,16 @@ template <typename VT> struct PairsIO {
     PairBuf<VT> out;
 };
 
+// Box-Muller on the hardware transcendentals (v_log_f32 is log2, v_sin_f32
+// and v_cos_f32 take revolutions, so sin(2 pi u) needs no scaling): used for
+// the latents of the bf16 network only, whose inputs are rounded to bf16.
+__device__ __forceinline__ void box_muller_hw(float ua, float ub, float& n1, float& n2)
+{
+    const float R = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(1.0f - ua));
+    n1 = R * __builtin_amdgcn_cosf(ub);
+    n2 = R * __builtin_amdgcn_sinf(ub);
+}
+
 // One layer on NT tiles: acc holds s of the previous layer (NB blocks),
 // nxt receives s of this layer (NBO blocks).  The activation of block nb
 // produces the inputs of k steps 2 nb and 2 nb + 1, whose MFMAs are issued
@@ -348,8 +358,8 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     const uint32_t a = (uint32_t)(r - pio.pr.off[k]);
                     const U4 rr = draw(pio.rng, a, (uint32_t)k, SLOT_LAT0 + (uint32_t)h);
                     float n0, n1, n2, spare;
-                    box_muller(unif24(rr.a), unif24(rr.b), n0, n1);
-                    box_muller(unif24(rr.c), unif24(rr.d), n2, spare);
+                    box_muller_hw(unif24(rr.a), unif24(rr.b), n0, n1);
+                    box_muller_hw(unif24(rr.c), unif24(rr.d), n2, spare);
                     if (h == 0) {
                         bin[t][0][0] = (__bf16)(C * n0);
                         bin[t][0][1] = (__bf16)(C * n1);
@@ -458,7 +468,8 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
             if (PAIRS) {
                 VT u[3];
                 if (nrm > 1e-30f) {
-                    u[0] = (VT)(y0 / nrm); u[1] = (VT)(y1 / nrm); u[2] = (VT)(y2 / nrm);
+                    const float inv = 1.0f / nrm;
+                    u[0] = (VT)(y0 * inv); u[1] = (VT)(y1 * inv); u[2] = (VT)(y2 * inv);
                 } else {
                     // degenerate output: the isotropic direction of this pair
                     const int32_t k = pio.pr.cell[r0];
