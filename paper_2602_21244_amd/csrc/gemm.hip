@@ -12,8 +12,9 @@
 // double-buffered: the next tile is loaded into registers during the MFMAs;
 // operands that are k-contiguous in memory are copied with 16-byte loads, the
 // transposed ones are scattered into that layout element by element.  A
-// split of K across blockIdx.z writes FP32 partials that a second kernel sums
-// in a fixed order, so results do not depend on timing.
+// split of K (the split index fastest in the 1-D grid) writes FP32 partials
+// that a second kernel sums in a fixed order, so results do not depend on
+// timing.
 #include "gemm.hpp"
 
 namespace dsmc {
@@ -146,13 +147,27 @@ k_gemm_bf16(GemmArgs g)
     // workgroup w runs on XCD w % 8; the n tiles of one m tile are given to
     // consecutive workgroups of the same XCD and share its L2 copy of the A
     // rows.
+    // With a K split the grid is tiles x splits in one dimension, split
+    // fastest, so a few output tiles with many splits still spread over
+    // every XCD.
     const int64_t m_tiles = (g.M + GM - 1) / GM, n_tiles = (g.N + GN - 1) / GN;
-    const int64_t wid = blockIdx.x, r8 = wid >> 3;
-    const int64_t mt = (r8 / n_tiles) * 8 + (wid & 7), nt = r8 % n_tiles;
+    const int64_t wid = blockIdx.x;
+    int64_t mt, nt, split = 0;
+    const int64_t splits = g.ksplits > 1 ? g.ksplits : 1;
+    if (splits > 1) {
+        split = wid % splits;
+        const int64_t tile = wid / splits;
+        mt = tile / n_tiles;
+        nt = tile % n_tiles;
+    } else {
+        const int64_t r8 = wid >> 3;
+        mt = (r8 / n_tiles) * 8 + (wid & 7);
+        nt = r8 % n_tiles;
+    }
     if (mt >= m_tiles) return;
     const int64_t m0 = mt * GM, n0 = nt * GN;
-    const int64_t kc = (g.K + gridDim.z - 1) / gridDim.z;
-    const int64_t kbeg = (int64_t)blockIdx.z * kc;
+    const int64_t kc = (g.K + splits - 1) / splits;
+    const int64_t kbeg = split * kc;
     const int64_t kend = kbeg + kc < g.K ? kbeg + kc : g.K;
     const bool a_kc = !g.ta, b_kc = g.tb;
 
@@ -208,7 +223,7 @@ k_gemm_bf16(GemmArgs g)
     }
 
     // epilogue: register r of lane (h, col) holds row 8 (r / 4) + 4 h + r % 4, column col
-    float* part = g.partial ? g.partial + (int64_t)blockIdx.z * g.M * g.N : nullptr;
+    float* part = g.partial ? g.partial + split * g.M * g.N : nullptr;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -227,60 +242,124 @@ k_gemm_bf16(GemmArgs g)
             }
 }
 
-// Sum of the K-split partials in split order, then the epilogue.
+// Sum of the K-split partials, then the epilogue.  A workgroup takes 64
+// outputs; its four waves sum interleaved quarters of the splits (split
+// s to wave s % 4, in split order), and the four sums are added in wave
+// order: a fixed order whatever the launch.
 __global__ void __launch_bounds__(256)
 k_gemm_reduce(GemmArgs g, int splits)
 {
+    __shared__ float part[4][64];
     const int64_t total = g.M * g.N;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t q0 = (int64_t)blockIdx.x * 64; q0 < total; q0 += (int64_t)gridDim.x * 64) {
+        const int64_t q = q0 + lane;
         float v = 0.0f;
-        for (int s = 0; s < splits; ++s) v += g.partial[(int64_t)s * total + q];
-        gemm_epilogue(g, q / g.N, q % g.N, v);
+        if (q < total) {
+            int s = w;
+            for (; s + 12 < splits; s += 16) {
+                const float a0 = g.partial[(int64_t)s * total + q];
+                const float a1 = g.partial[(int64_t)(s + 4) * total + q];
+                const float a2 = g.partial[(int64_t)(s + 8) * total + q];
+                const float a3 = g.partial[(int64_t)(s + 12) * total + q];
+                v += a0; v += a1; v += a2; v += a3;
+            }
+            for (; s < splits; s += 4) v += g.partial[(int64_t)s * total + q];
+        }
+        part[w][lane] = v;
+        __syncthreads();
+        if (w == 0 && q < total) {
+            const float r = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+            gemm_epilogue(g, q / g.N, q % g.N, r);
+        }
+        __syncthreads();
     }
 }
 
-// Per row chunk and column: sums of a, a x0, a x1 (x optional).
+// Column sums in two fixed-order stages.  Partial: a workgroup takes
+// COLSUM_ROWS rows and 64 columns; wave w sums rows w, w + 4, ... of the
+// chunk and the four wave sums are added in wave order.  Final: a workgroup
+// takes 64 columns; its 16 waves sum chunks g, g + 16, ... and the sums are
+// added in wave order.
 __global__ void __launch_bounds__(256)
 k_col_partial(const float* __restrict__ a, int64_t R, int n, const float* __restrict__ x,
               float* __restrict__ red)
 {
-    const int c = blockIdx.y * blockDim.x + threadIdx.x;
-    if (c >= n) return;
+    __shared__ float ps[4][3][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.y * 64 + lane;
     const int64_t r0 = (int64_t)blockIdx.x * COLSUM_ROWS;
     const int64_t r1 = r0 + COLSUM_ROWS < R ? r0 + COLSUM_ROWS : R;
     float s = 0.f, s0 = 0.f, s1 = 0.f;
-    for (int64_t r = r0; r < r1; ++r) {
-        const float d = a[r * n + c];
-        s += d;
-        if (x) {
-            s0 += d * x[2 * r];
-            s1 += d * x[2 * r + 1];
+    if (c < n) {
+        int64_t r = r0 + w;
+        for (; r + 28 < r1; r += 32) {
+            float d[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) d[u] = a[(r + 4 * u) * n + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                s += d[u];
+                if (x) {
+                    s0 += d[u] * x[2 * (r + 4 * u)];
+                    s1 += d[u] * x[2 * (r + 4 * u) + 1];
+                }
+            }
+        }
+        for (; r < r1; r += 4) {
+            const float d = a[r * n + c];
+            s += d;
+            if (x) {
+                s0 += d * x[2 * r];
+                s1 += d * x[2 * r + 1];
+            }
         }
     }
-    float* o = red + ((int64_t)blockIdx.x * n + c) * 3;
-    o[0] = s;
-    o[1] = s0;
-    o[2] = s1;
+    ps[w][0][lane] = s;
+    ps[w][1][lane] = s0;
+    ps[w][2][lane] = s1;
+    __syncthreads();
+    if (w == 0 && c < n) {
+        float* o = red + ((int64_t)blockIdx.x * n + c) * 3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            o[k] = ((ps[0][k][lane] + ps[1][k][lane]) + ps[2][k][lane]) + ps[3][k][lane];
+    }
 }
 
-__global__ void __launch_bounds__(256)
+constexpr int COLSUM_FINAL_WAVES = 16;
+
+__global__ void __launch_bounds__(64 * COLSUM_FINAL_WAVES)
 k_col_final(const float* __restrict__ red, int64_t chunks, int n, float* __restrict__ out,
             float* __restrict__ out2, int accumulate)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
+    __shared__ float ps[COLSUM_FINAL_WAVES][3][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
     float s = 0.f, s0 = 0.f, s1 = 0.f;
-    for (int64_t q = 0; q < chunks; ++q) {
-        const float* o = red + (q * n + c) * 3;
-        s += o[0];
-        s0 += o[1];
-        s1 += o[2];
+    if (c < n) {
+        for (int64_t q = w; q < chunks; q += COLSUM_FINAL_WAVES) {
+            const float* o = red + (q * n + c) * 3;
+            s += o[0];
+            s0 += o[1];
+            s1 += o[2];
+        }
     }
-    out[c] = accumulate ? out[c] + s : s;
-    if (out2) {
-        out2[2 * c] = accumulate ? out2[2 * c] + s0 : s0;
-        out2[2 * c + 1] = accumulate ? out2[2 * c + 1] + s1 : s1;
+    ps[w][0][lane] = s;
+    ps[w][1][lane] = s0;
+    ps[w][2][lane] = s1;
+    __syncthreads();
+    if (w == 0 && c < n) {
+        float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < COLSUM_FINAL_WAVES; ++q)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) t[k] += ps[q][k][lane];
+        out[c] = accumulate ? out[c] + t[0] : t[0];
+        if (out2) {
+            out2[2 * c] = accumulate ? out2[2 * c] + t[1] : t[1];
+            out2[2 * c + 1] = accumulate ? out2[2 * c + 1] + t[2] : t[2];
+        }
     }
 }
 
@@ -289,10 +368,12 @@ int colsum_f32(const float* a, int64_t R, int n, const float* x2, float* red, fl
 {
     if (R <= 0 || n <= 0) return DSMC_OK;
     const int64_t chunks = (R + COLSUM_ROWS - 1) / COLSUM_ROWS;
-    dim3 pg((unsigned)chunks, (unsigned)((n + 255) / 256));
+    if (chunks > 2147483647) return arg_error("colsum: too many rows");
+    dim3 pg((unsigned)chunks, (unsigned)((n + 63) / 64));
     k_col_partial<<<pg, 256, 0, s>>>(a, R, n, x2, red);
     DSMC_LAUNCH_CHECK("colsum:partial");
-    k_col_final<<<(n + 255) / 256, 256, 0, s>>>(red, chunks, n, out, out2, accumulate);
+    k_col_final<<<(n + 63) / 64, 64 * COLSUM_FINAL_WAVES, 0, s>>>(red, chunks, n, out, out2,
+                                                                  accumulate);
     DSMC_LAUNCH_CHECK("colsum:final");
     return DSMC_OK;
 }
@@ -303,16 +384,17 @@ int gemm_bf16(const GemmArgs& g0, int splits, hipStream_t s)
     if (g.M <= 0 || g.N <= 0) return DSMC_OK;
     if (splits < 1) splits = 1;
     const int64_t gx = (g.M + GM - 1) / GM, gy = (g.N + GN - 1) / GN;
-    const int64_t tiles = (gx + 7) / 8 * 8 * gy;
+    const int64_t tiles = splits > 1 ? gx * gy * splits : (gx + 7) / 8 * 8 * gy;
     if (tiles > 2147483647 || splits > 65535) return arg_error("gemm: grid too large");
     if (splits > 1 && !g.partial) return arg_error("gemm: split-K needs a partial buffer");
     if (splits == 1) g.partial = nullptr;
-    dim3 grid((unsigned)tiles, 1u, (unsigned)splits);
+    g.ksplits = splits;
+    dim3 grid((unsigned)tiles, 1u, 1u);
     k_gemm_bf16<<<grid, G_THREADS, 0, s>>>(g);
     DSMC_LAUNCH_CHECK("gemm_bf16");
     if (splits > 1) {
         const int64_t total = g.M * g.N;
-        int64_t blocks = (total + 255) / 256;
+        int64_t blocks = (total + 63) / 64;
         const int pb = persistent_blocks(256);
         if (blocks > pb) blocks = pb;
         k_gemm_reduce<<<(int)blocks, 256, 0, s>>>(g, splits);

@@ -23,6 +23,7 @@ struct GemmArgs {
     __bf16* out_bf16;      // [M][ldo] or null
     int64_t ldo;
     float* partial;        // split-K partials [splits][M][N] (splits > 1)
+    int ksplits;           // set by gemm_bf16: K splits (one 1-D grid of tiles x splits)
 };
 
 // Launch on stream s; splits > 1 divides K over workgroups (FP32 partials

@@ -862,7 +862,7 @@ struct Bf16BwdWs {
     size_t bytes;
 };
 
-constexpr int BWD_SPLITS_MAX = 32;
+constexpr int BWD_SPLITS_MAX = 128;
 
 static Bf16BwdWs bf16_bwd_layout(void* base, const MlpDev& d, int64_t B)
 {
@@ -911,7 +911,7 @@ static int backward_bf16(const MlpDev& d, int64_t B, const float* X, const float
         int64_t b = (n + 255) / 256;
         return (int)(b < 1 ? 1 : (b > pb ? pb : b));
     };
-    int splits = (int)(B / 2048);
+    int splits = (int)(B / 512);
     splits = splits < 1 ? 1 : (splits > BWD_SPLITS_MAX ? BWD_SPLITS_MAX : splits);
     const int dout = d.dims[d.L];
     int cur = 0;
@@ -993,7 +993,24 @@ k_mse(int64_t B, const float* __restrict__ a, const float* __restrict__ t, doubl
 {
     __shared__ double red[16];
     double acc = 0.0;
-    for (int64_t q = threadIdx.x; q < 3 * B; q += blockDim.x) {
+    const int64_t n3 = 3 * B, step = blockDim.x;
+    int64_t q = threadIdx.x;
+    // eight elements per thread in flight; the sum keeps the thread's order
+    for (; q + 7 * step < n3; q += 8 * step) {
+        float av[8], tv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            av[u] = a[q + u * step];
+            tv[u] = t[q + u * step];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double dd = (double)av[u] - (double)tv[u];
+            acc += dd * dd;
+            grad[q + u * step] = (float)(2.0 * scale * dd);
+        }
+    }
+    for (; q < n3; q += step) {
         const double dd = (double)a[q] - (double)t[q];
         acc += dd * dd;
         grad[q] = (float)(2.0 * scale * dd);
