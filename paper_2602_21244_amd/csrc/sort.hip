@@ -16,8 +16,10 @@
 //           counters in LDS), the tile is reordered by digit through one LDS
 //           array (keys, then values) and written out as contiguous digit
 //           runs
-// The last down pass also gathers vx, vy, vz into sorted order; one pass
-// over the sorted keys then writes cell_start.
+// The last down pass also gathers vx, vy, vz into sorted order and adds the
+// cell counts (its tiles are sorted by the whole key, so a few integer
+// atomics per tile); an in-place exclusive scan of the counts gives
+// cell_start.
 // Ids outside [0, n_cells) are mapped to the key n_cells, so they sort after
 // every kept particle.
 #include "common.hpp"
@@ -249,6 +251,25 @@ __device__ __forceinline__ void wave_rank(int32_t d, bool valid, int dbits, int 
     }
 }
 
+// Cell counts from the last pass: its tile is sorted by the whole key, so a
+// wave's 64 consecutive slots hold a few runs of equal ids; the first lane of
+// each run adds the run length (integer atomics: the counts do not depend on
+// their order).  Dropped particles (key n_cells) are not counted.
+__device__ __forceinline__ void count_runs(int32_t k, bool ok, int s, int32_t tn, int lane,
+                                           int32_t* counts, int32_t n_cells)
+{
+    const int32_t kp = __shfl_up(k, 1, 64);
+    const bool start = ok && (lane == 0 || kp != k);
+    const uint64_t starts = __ballot(start);
+    if (start && k < n_cells) {
+        const uint64_t after = starts & ~((2ull << lane) - 1ull);
+        int end = after ? __builtin_ctzll(after) : 64;
+        const int nvalid = tn - (s - lane);
+        if (end > nvalid) end = nvalid;
+        atomicAdd(&counts[k], end - lane);
+    }
+}
+
 // LAST: the final pass also gathers the velocities into sorted order
 // (vals are then the original indices, i.e. perm).
 template <bool FIRST, bool LAST, typename T>
@@ -256,7 +277,8 @@ __global__ void __launch_bounds__(DN_THREADS)
 k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int32_t n,
              int32_t n_cells, int shift, int32_t mask, int dbits, int32_t nblk,
              const int32_t* __restrict__ goff, int32_t* __restrict__ keys_out,
-             int32_t* __restrict__ vals_out, V3<const T> vin, V3<T> vout)
+             int32_t* __restrict__ vals_out, V3<const T> vin, V3<T> vout,
+             int32_t* __restrict__ counts)
 {
     __shared__ int32_t cnt[DN_WAVES][RADIX];   // per wave and digit
     __shared__ int32_t gb[RADIX];                       // global slot of tile slot 0, per digit
@@ -363,13 +385,15 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
 #pragma unroll
     for (int it = 0; it < DN_ITEMS; ++it) {
         const int s = threadIdx.x + it * DN_THREADS;
+        const bool ok = s < tn;
+        const int32_t k = ok ? stage[s] : -1;
         oo[it] = -1;
-        if (s < tn) {
-            const int32_t k = stage[s];
+        if (ok) {
             const int32_t o = gb[(k >> shift) & mask] + s;
-            keys_out[o] = k;
+            if (!LAST) keys_out[o] = k;
             oo[it] = o;
         }
+        if (LAST) count_runs(k, ok, s, tn, lane, counts, n_cells);
     }
     __syncthreads();
 #pragma unroll
@@ -401,37 +425,6 @@ k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ va
             vout.x[oo[it]] = gx[it];
             vout.y[oo[it]] = gy[it];
             vout.z[oo[it]] = gz[it];
-        }
-    }
-}
-
-// cell_start from the sorted keys: cell_start[k] = first slot whose key is
-// >= k.  Each thread covers 4 consecutive slots (one 16-byte load of keys
-// plus the key before them).
-__global__ void __launch_bounds__(256)
-k_cell_start(const int32_t* __restrict__ keys, int32_t n, int32_t n_cells,
-             int32_t* __restrict__ cell_start)
-{
-    const int64_t n4 = ((int64_t)n + 4) / 4;      // slots 0..n inclusive
-    const bool aligned = (reinterpret_cast<uintptr_t>(keys) & 15) == 0;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n4;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t s0 = 4 * q;
-        int32_t k[5];
-        k[0] = s0 > 0 ? keys[s0 - 1] : -1;
-        if (s0 + 4 <= n && aligned) {
-            const int4 x = *reinterpret_cast<const int4*>(keys + s0);
-            k[1] = x.x; k[2] = x.y; k[3] = x.z; k[4] = x.w;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) k[e + 1] = s0 + e < n ? keys[s0 + e] : n_cells + 1;
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t s = s0 + e;
-            if (s > n) break;
-            const int32_t khi = k[e + 1] < n_cells ? k[e + 1] : n_cells;
-            for (int32_t c = k[e] + 1; c <= khi; ++c) cell_start[c] = (int32_t)s;
         }
     }
 }
@@ -469,6 +462,12 @@ static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_ve
     int32_t* cpre = reinterpret_cast<int32_t*>(w);
     w += align_up(sizeof(int32_t) * (size_t)(RADIX * nch));
     int32_t* dtot = reinterpret_cast<int32_t*>(w);
+    w += align_up(sizeof(int32_t) * (size_t)RADIX);
+    void* scan_ws = w;
+    {
+        const int rc = fill_i32(cell_start, 0, (int64_t)n_cells + 1, s);
+        if (rc) return rc;
+    }
 
     int nbits = 0;
     const int passes = sort_passes(n_cells, &nbits);
@@ -499,29 +498,26 @@ static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_ve
         if (pass == 0 && last)
             k_radix_down<true, true, T><<<(int)nblk, DN_THREADS, 0, s>>>(
                 kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
-                vi, vo);
+                vi, vo, cell_start);
         else if (pass == 0)
             k_radix_down<true, false, T><<<(int)nblk, DN_THREADS, 0, s>>>(
                 kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
-                vi, vo);
+                vi, vo, cell_start);
         else if (last)
             k_radix_down<false, true, T><<<(int)nblk, DN_THREADS, 0, s>>>(
                 kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
-                vi, vo);
+                vi, vo, cell_start);
         else
             k_radix_down<false, false, T><<<(int)nblk, DN_THREADS, 0, s>>>(
                 kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
-                vi, vo);
+                vi, vo, cell_start);
         DSMC_LAUNCH_CHECK("sort:down");
         kin = kout;
         vin_idx = vout_idx;
     }
-    const int pblocks = persistent_blocks(256);
-    int64_t blocks = ((int64_t)n + 4) / 4;
-    blocks = (blocks + 255) / 256;
-    if (blocks > pblocks * 4) blocks = pblocks * 4;
-    k_cell_start<<<(int)blocks, 256, 0, s>>>(keys_b, n, n_cells, cell_start);
-    DSMC_LAUNCH_CHECK("sort:cell_start");
+    // cell_start: exclusive scan, in place, of the counts the last pass added
+    int rc = exclusive_scan_i32(cell_start, cell_start, n_cells, nullptr, scan_ws, s);
+    if (rc) return rc;
     return DSMC_OK;
 }
 
@@ -537,7 +533,7 @@ extern "C" size_t dsmc_sort_cells_ws(int32_t n, int32_t n_cells)
     return 3 * align_up(sizeof(int32_t) * (size_t)n) +
            2 * align_up(sizeof(int32_t) * (size_t)(RADIX * nblk)) +
            2 * align_up(sizeof(int32_t) * (size_t)(RADIX * nch)) +
-           align_up(sizeof(int32_t) * (size_t)RADIX) + 256;
+           align_up(sizeof(int32_t) * (size_t)RADIX) + scan_ws_bytes(n_cells) + 256;
 }
 
 extern "C" int dsmc_sort_cells(int32_t n, int32_t n_cells, const int32_t* cell_of, int32_t dtype,
