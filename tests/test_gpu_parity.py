@@ -54,7 +54,8 @@ def _thermal(T=300.0):
 # sort
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("case", ["c1", "ragged", "bigcells", "empty_tail", "bad_ids", "f32",
-                                  "three_pass", "one_cell", "shuffled"])
+                                  "three_pass", "one_cell", "shuffled", "tiny", "all_bad",
+                                  "sorted_runs"])
 def test_sort_bitexact(orc, dev, api, case):
     say("sort case", case)
     dtype = torch.float64
@@ -81,6 +82,23 @@ def test_sort_bitexact(orc, dev, api, case):
     elif case == "shuffled":
         pop = W.cylinder_grid(seed=9, order="shuffled", scale=0.03)
         dtype = torch.float32
+    elif case == "tiny":
+        # fewer particles than one wave, a bad id among them
+        pop = W.ragged_population(10, 5, 40, empty_frac=0.0)
+        assert pop.cell_of.size >= 37
+        pop.cell_of = pop.cell_of[:37].copy()
+        pop.v = pop.v[:, :37].copy()
+        pop.cell_of[11] = -1
+    elif case == "all_bad":
+        pop = W.ragged_population(11, 50, 30)
+        pop.cell_of = np.full_like(pop.cell_of, pop.n_cells)
+    elif case == "sorted_runs":
+        # cell order already: runs of one id across wave and tile boundaries,
+        # a ragged last tile
+        pop = W.ragged_population(12, 700, 300, empty_frac=0.1)
+        order = np.argsort(pop.cell_of, kind="stable")
+        pop.cell_of = pop.cell_of[order].copy()
+        pop.v = pop.v[:, order].copy()
     else:
         pop = W.cavity_grid(seed=3, nx=60, ny=50)
         dtype = torch.float32
