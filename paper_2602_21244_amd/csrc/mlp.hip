@@ -856,7 +856,8 @@ static int backward_impl(const MlpDev& d, int64_t B, const T* X, const T* Z, con
 struct Bf16BwdWs {
     float* d32[2];
     __bf16* d16[2];
-    __bf16* h16;
+    __bf16* d16t;   // delta^T [out][B]: k-contiguous A of the weight-gradient GEMM
+    __bf16* h16t;   // h^T [in][B]: k-contiguous B of the weight-gradient GEMM
     float* part;
     float* red;
     size_t bytes;
@@ -876,7 +877,8 @@ static Bf16BwdWs bf16_bwd_layout(void* base, const MlpDev& d, int64_t B)
         w.d32[q] = reinterpret_cast<float*>(take(sizeof(float) * (size_t)B * wmax));
         w.d16[q] = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * (size_t)B * wmax));
     }
-    w.h16 = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * (size_t)B * wmax));
+    w.d16t = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * (size_t)B * wmax));
+    w.h16t = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * (size_t)B * wmax));
     w.part = reinterpret_cast<float*>(take(sizeof(float) * BWD_SPLITS_MAX * (size_t)wmax * wmax));
     w.red = reinterpret_cast<float*>(take(sizeof(float) * colsum_ws_floats(B, wmax)));
     w.bytes = o;
@@ -891,14 +893,49 @@ k_to_bf16(int64_t n, const float* __restrict__ a, __bf16* __restrict__ b)
         b[q] = (__bf16)a[q];
 }
 
-// h_{l-1} in bf16: x for l == 0, act(z) otherwise.
+// out[c][r] = in[r][c] for a rows x cols bf16 matrix, through 64 x 64 LDS
+// tiles (both sides coalesced).
+constexpr int TR_TILE = 64;
+
 __global__ void __launch_bounds__(256)
-k_hprev16(int64_t n_el, const float* __restrict__ X, const float* __restrict__ Zp, int l, int act,
-          __bf16* __restrict__ H)
+k_transpose16(const __bf16* __restrict__ in, int64_t rows, int64_t cols, __bf16* __restrict__ out)
 {
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_el;
-         q += (int64_t)gridDim.x * blockDim.x)
-        H[q] = (__bf16)((l == 0) ? X[q] : act_t<float>(Zp[q], act));
+    __shared__ __bf16 t[TR_TILE][TR_TILE + 2];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * TR_TILE, c0 = (int64_t)blockIdx.y * TR_TILE;
+    for (int r = ty; r < TR_TILE; r += 4)
+        if (r0 + r < rows && c0 + tx < cols) t[r][tx] = in[(r0 + r) * cols + c0 + tx];
+    __syncthreads();
+    for (int c = ty; c < TR_TILE; c += 4)
+        if (c0 + c < cols && r0 + tx < rows) out[(c0 + c) * rows + r0 + tx] = t[tx][c];
+}
+
+static int transpose16(const __bf16* in, int64_t rows, int64_t cols, __bf16* out, hipStream_t s)
+{
+    const int64_t gr = (rows + TR_TILE - 1) / TR_TILE, gc = (cols + TR_TILE - 1) / TR_TILE;
+    if (gr > 2147483647 || gc > 65535) return arg_error("transpose: matrix too large");
+    k_transpose16<<<dim3((unsigned)gr, (unsigned)gc), 256, 0, s>>>(in, rows, cols, out);
+    DSMC_LAUNCH_CHECK("mlp_bwd16:transpose");
+    return DSMC_OK;
+}
+
+// h_{l-1}^T in bf16, [in][B]: x for l == 0, act(z) otherwise, through the
+// same LDS tiles as k_transpose16.
+__global__ void __launch_bounds__(256)
+k_hprev16t(int64_t rows, int cols, const float* __restrict__ X, const float* __restrict__ Zp,
+           int l, int act, __bf16* __restrict__ Ht)
+{
+    __shared__ __bf16 t[TR_TILE][TR_TILE + 2];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * TR_TILE, c0 = (int64_t)blockIdx.y * TR_TILE;
+    for (int r = ty; r < TR_TILE; r += 4)
+        if (r0 + r < rows && c0 + tx < cols) {
+            const int64_t q = (r0 + r) * cols + c0 + tx;
+            t[r][tx] = (__bf16)((l == 0) ? X[q] : act_t<float>(Zp[q], act));
+        }
+    __syncthreads();
+    for (int c = ty; c < TR_TILE; c += 4)
+        if (c0 + c < cols && r0 + tx < rows) Ht[(c0 + c) * rows + r0 + tx] = t[tx][c];
 }
 
 static int backward_bf16(const MlpDev& d, int64_t B, const float* X, const float* Z,
@@ -925,15 +962,24 @@ static int backward_bf16(const MlpDev& d, int64_t B, const float* X, const float
     for (int l = d.L - 1; l >= 0; --l) {
         const int out = d.dims[l + 1], in = d.dims[l];
         const float* Zp = (l > 0) ? Z + zoff[l - 1] : nullptr;
-        k_hprev16<<<grid1(B * in), 256, 0, s>>>(B * in, X, Zp, l, d.act, w.h16);
-        DSMC_LAUNCH_CHECK("mlp_bwd16:hprev");
+        // both factors of dW have the batch as K: they are written transposed
+        // so that the GEMM stages them with vector loads
+        {
+            const int64_t gr = (B + TR_TILE - 1) / TR_TILE, gc = (in + TR_TILE - 1) / TR_TILE;
+            if (gr > 2147483647 || gc > 65535) return arg_error("mlp_backward: batch too large");
+            k_hprev16t<<<dim3((unsigned)gr, (unsigned)gc), 256, 0, s>>>(B, in, X, Zp, l, d.act,
+                                                                      w.h16t);
+            DSMC_LAUNCH_CHECK("mlp_bwd16:hprev");
+        }
+        int rc = transpose16(w.d16[cur], B, out, w.d16t, s);
+        if (rc) return rc;
         GemmArgs gw{};
-        gw.a = w.d16[cur];
-        gw.lda = out;
-        gw.ta = 1;
-        gw.b = w.h16;
-        gw.ldb = in;
-        gw.tb = 0;
+        gw.a = w.d16t;
+        gw.lda = B;
+        gw.ta = 0;
+        gw.b = w.h16t;
+        gw.ldb = B;
+        gw.tb = 1;
         gw.M = out;
         gw.N = in;
         gw.K = B;
@@ -942,7 +988,7 @@ static int backward_bf16(const MlpDev& d, int64_t B, const float* X, const float
         gw.out_f32 = dW[l];
         gw.ldo = in;
         gw.partial = w.part;
-        int rc = gemm_bf16(gw, splits, s);
+        rc = gemm_bf16(gw, splits, s);
         if (rc) return rc;
         rc = colsum_f32(w.d32[cur], B, out, nullptr, w.red, db[l], nullptr, accumulate, s);
         if (rc) return rc;
