@@ -162,6 +162,9 @@ def main():
         if rule == "neural":
             api.neural_collide(net, v, pairs, 11, 0, schedule=L.SCHED_DEFER, ws=col_ws, st=st)
             kind = L.APPLY_DIRECTIONS
+        elif rule == "vhs":
+            api.collide_vhs(v, pairs, 11, 0, schedule=L.SCHED_DEFER, ws=col_ws)
+            kind = L.APPLY_DIRECTIONS
         elif rule == "table":
             api.collide_table(tab, v, pairs, 11, 0, W.AR_MASS / 2, schedule=L.SCHED_DEFER,
                               ws=col_ws)
@@ -248,6 +251,11 @@ def main():
     log(f"table vs quadrature folded-angle error: rms {table_rms:.4f} rad ({akind} angle network)")
     table_flop = 512 * 512 * anet_flop_per_row(anet.dims)
 
+    # the isotropic VHS rule (the plain rule the network replaces) on the same
+    # step: its Phase A reads the pair list and writes one direction per pair
+    wall_v, ms_v, per_v = run("vhs", 1, args.table_steps)
+    log(f"vhs: {ms_v:.3f} ms/step, stages {json.dumps({k: round(x, 4) for k, x in per_v.items()})}")
+
     # deflection batch (2^20 pairs, g log-uniform 100-20 000 m/s, b^2 uniform):
     # quadrature FP64 / FP32 against the angle network evaluated per pair
     batch = deflection_batch_timing(api, W, dev, pot, quad, anet, lne_lo, lne_hi)
@@ -275,6 +283,9 @@ def main():
         "table_ms_per_step": ms_t,
         "stage_ms_table": per_t,
         "table_theta_rms_vs_quadrature_rad": table_rms,
+        "vhs_pairs_per_s": n_pairs / (ms_v * 1e-3),
+        "vhs_ms_per_step": ms_v,
+        "stage_ms_vhs": per_v,
         "angle_network_weights": akind,
         "table_build_ms_512x512": table_build_ms,
         "table_build_TFLOPs": table_flop / (table_build_ms * 1e-3) / 1e12,
