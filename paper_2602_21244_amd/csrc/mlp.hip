@@ -329,8 +329,30 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
     for (int e = 0; e < 8; ++e) bone[e] = (__bf16)((h == 0 && e < 2) ? 1.0f : 0.0f);
     const floatx16 zero = {};
 
+    // pairs mode: the next tile's pair record (cell, i, j) is loaded while the
+    // current tile runs through the network, so a tile's first loads wait on
+    // one round trip (offsets and velocities) instead of two
+    const int64_t gstride = (int64_t)gridDim.x * waves;
+    int32_t pf_k[NT], pf_i[NT], pf_j[NT];
+    auto prefetch = [&](int64_t g) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int64_t r = (g * NT + t) * 32 + col;
+            pf_k[t] = 0;
+            pf_i[t] = 0;
+            pf_j[t] = 0;
+            if (PAIRS && r < nrows) {
+                pf_k[t] = pio.pr.cell[r];
+                if (h == 1) {
+                    pf_i[t] = pio.pr.i[r];
+                    pf_j[t] = pio.pr.j[r];
+                }
+            }
+        }
+    };
+    if (PAIRS) prefetch((int64_t)blockIdx.x * waves + (threadIdx.x >> 6));
     for (int64_t grp = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); grp * 32 * NT < nrows;
-         grp += (int64_t)gridDim.x * waves) {
+         grp += gstride) {
         int64_t row[NT];
         bool valid[NT];
         bf16x8 bin[NT][2];
@@ -354,7 +376,7 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     // on its own slot without divergence (half 1 discards the
                     // second transform).
                     const int64_t r = row[t];
-                    const int32_t k = pio.pr.cell[r];
+                    const int32_t k = pf_k[t];
                     const uint32_t a = (uint32_t)(r - pio.pr.off[k]);
                     const U4 rr = draw(pio.rng, a, (uint32_t)k, SLOT_LAT0 + (uint32_t)h);
                     float n0, n1, n2, spare;
@@ -365,7 +387,7 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                         bin[t][0][1] = (__bf16)(C * n1);
                         bin[t][0][2] = (__bf16)(C * n2);
                     } else {
-                        const int32_t i = pio.pr.i[r], j = pio.pr.j[r];
+                        const int32_t i = pf_i[t], j = pf_j[t];
                         const VT isv = (VT)d.inv_sigma_v;
                         bin[t][0][0] = (__bf16)(C * (float)((pio.v.x[i] - pio.v.x[j]) * isv));
                         bin[t][0][1] = (__bf16)(C * (float)((pio.v.y[i] - pio.v.y[j]) * isv));
@@ -375,7 +397,7 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     }
                 } else if (valid[t]) {
                     const int64_t r = row[t];
-                    const int32_t k = pio.pr.cell[r];
+                    const int32_t k = pf_k[t];
                     const uint32_t a = (uint32_t)(r - pio.pr.off[k]);
                     if (h == 0) {
                         VT xi[3];
@@ -386,7 +408,7 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     } else {
                         VT z[2], u4;
                         latents_z(pio.rng, a, (uint32_t)k, z, u4);
-                        const int32_t i = pio.pr.i[r], j = pio.pr.j[r];
+                        const int32_t i = pf_i[t], j = pf_j[t];
                         const VT isv = (VT)d.inv_sigma_v;
                         bin[t][0][0] = (__bf16)(C * (float)((pio.v.x[i] - pio.v.x[j]) * isv));
                         bin[t][0][1] = (__bf16)(C * (float)((pio.v.y[i] - pio.v.y[j]) * isv));
@@ -410,6 +432,8 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     }
             }
         }
+
+        if (PAIRS) prefetch(grp + gstride);
 
         // input layer: s = W (c x) + c b
         floatx16 acc[NT][NB];
