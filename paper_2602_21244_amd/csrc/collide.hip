@@ -353,10 +353,29 @@ template <typename T, int RULE, int NT, int PPL, int NMAX, int RMAX>
 __device__ __forceinline__ void stage_cell(V3<T> v, int32_t lo, int32_t span,
                                            const CellLds<T, RULE, NT, PPL, NMAX, RMAX>& L)
 {
-    for (int32_t q = threadIdx.x; q < span; q += NT) {
-        L.lx[q] = v.x[lo + q];
-        L.ly[q] = v.y[lo + q];
-        L.lz[q] = v.z[lo + q];
+    // STAGE_BATCH slots per thread in flight: their loads are issued before
+    // any LDS store waits on them
+    constexpr int STAGE_BATCH = 4;
+    for (int32_t q0 = threadIdx.x; q0 < span; q0 += NT * STAGE_BATCH) {
+        T x[STAGE_BATCH], y[STAGE_BATCH], z[STAGE_BATCH];
+#pragma unroll
+        for (int b = 0; b < STAGE_BATCH; ++b) {
+            const int32_t q = q0 + NT * b;
+            if (q < span) {
+                x[b] = v.x[lo + q];
+                y[b] = v.y[lo + q];
+                z[b] = v.z[lo + q];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < STAGE_BATCH; ++b) {
+            const int32_t q = q0 + NT * b;
+            if (q < span) {
+                L.lx[q] = x[b];
+                L.ly[q] = y[b];
+                L.lz[q] = z[b];
+            }
+        }
     }
 }
 
@@ -695,6 +714,9 @@ __device__ __forceinline__ void match_cell(LD ld, int32_t N, const double* m, in
                                            V3<T> v, int32_t s0, dsmc_status* st)
 {
     const int lane = threadIdx.x & 63;
+    // the cell's captured moments are loaded first, their latency overlaps
+    // the sums
+    const double m0 = m[0], m1 = m[1], m2 = m[2], mt = literal ? m[5] : m[3];
     double sx = 0, sy = 0, sz = 0;
     for (int32_t q = lane; q < N; q += 64) {
         sx += (double)ld.x(q);
@@ -724,7 +746,7 @@ __device__ __forceinline__ void match_cell(LD ld, int32_t N, const double* m, in
         }
         return;
     }
-    const double alpha = sqrt((literal ? m[5] : m[3]) / post);
+    const double alpha = sqrt(mt / post);
     for (int32_t q = lane; q < N; q += 64) {
         const int32_t s = s0 + q;
         if (literal) {
@@ -732,9 +754,9 @@ __device__ __forceinline__ void match_cell(LD ld, int32_t N, const double* m, in
             v.y[s] = (T)(alpha * (double)ld.y(q));
             v.z[s] = (T)(alpha * (double)ld.z(q));
         } else {
-            v.x[s] = (T)(m[0] + alpha * ((double)ld.x(q) - ux));
-            v.y[s] = (T)(m[1] + alpha * ((double)ld.y(q) - uy));
-            v.z[s] = (T)(m[2] + alpha * ((double)ld.z(q) - uz));
+            v.x[s] = (T)(m0 + alpha * ((double)ld.x(q) - ux));
+            v.y[s] = (T)(m1 + alpha * ((double)ld.y(q) - uy));
+            v.z[s] = (T)(m2 + alpha * ((double)ld.z(q) - uz));
         }
     }
 }
