@@ -71,8 +71,15 @@ k_capture(const int32_t* __restrict__ cell_start, int32_t n_cells, V3<T> v, doub
 {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
-    for (int32_t k = blockIdx.x * wpb + (threadIdx.x >> 6); k < n_cells; k += gridDim.x * wpb) {
-        const int32_t s0 = cell_start[k], N = cell_start[k + 1] - s0;
+    const int64_t kstep = (int64_t)gridDim.x * wpb;
+    int64_t k = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    // the next cell's bounds are loaded while the current cell is summed
+    int32_t a0 = k < n_cells ? cell_start[k] : 0, a1 = k < n_cells ? cell_start[k + 1] : 0;
+    for (; k < n_cells; k += kstep) {
+        const int32_t s0 = a0, N = a1 - a0;
+        const int64_t kn = k + kstep;
+        a0 = kn < n_cells ? cell_start[kn] : 0;
+        a1 = kn < n_cells ? cell_start[kn + 1] : 0;
         const CellSums c = cell_sums(v, s0, N, lane);
         if (lane == 0) {
             double* m = mom + 6 * (size_t)k;
