@@ -188,7 +188,7 @@ int dsmc_status_clear(dsmc_status* st, dsmc_stream_t stream);
  * cell_start[n_cells] < n and slots cell_start[n_cells]..n-1 hold the dropped
  * particles in original order.  n_cells < 2^31 - 1.
  * ws: dsmc_sort_cells_ws(n, n_cells) bytes (about 12 n + 4 KiB per 4096
- * particles). */
+ * particles, plus a few bytes per thousand cells for the count scan). */
 size_t dsmc_sort_cells_ws(int32_t n, int32_t n_cells);
 int dsmc_sort_cells(int32_t n, int32_t n_cells, const int32_t* cell_of, int32_t dtype,
                     dsmc_vec3 v_in, dsmc_vec3 v_out, int32_t* cell_start, int32_t* perm,

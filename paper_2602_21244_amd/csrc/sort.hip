@@ -52,9 +52,8 @@ __device__ __forceinline__ int32_t sort_key(const int32_t* cell_of, int64_t p, i
 template <bool FIRST>
 __global__ void __launch_bounds__(SORT_THREADS)
 k_radix_up(const int32_t* __restrict__ keys_in, int32_t n, int32_t n_cells, int shift,
-           int32_t mask, int dbits, int32_t nblk, int32_t* __restrict__ ghist, dsmc_status* st)
+           int32_t mask, int32_t* __restrict__ ghist, dsmc_status* st)
 {
-    (void)dbits;
     __shared__ int32_t h[RADIX];
     for (int i = threadIdx.x; i <= mask; i += SORT_THREADS) h[i] = 0;
     __syncthreads();
@@ -275,7 +274,7 @@ __device__ __forceinline__ void count_runs(int32_t k, bool ok, int s, int32_t tn
 template <bool FIRST, bool LAST, typename T>
 __global__ void __launch_bounds__(DN_THREADS)
 k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int32_t n,
-             int32_t n_cells, int shift, int32_t mask, int dbits, int32_t nblk,
+             int32_t n_cells, int shift, int32_t mask, int dbits,
              const int32_t* __restrict__ goff, int32_t* __restrict__ keys_out,
              int32_t* __restrict__ vals_out, V3<const T> vin, V3<T> vout,
              int32_t* __restrict__ counts)
@@ -481,11 +480,11 @@ static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_ve
         int32_t* kout = to_final ? keys_b : keys_a;
         int32_t* vout_idx = to_final ? perm : vals_a;
         if (pass == 0)
-            k_radix_up<true><<<(int)nblk, SORT_THREADS, 0, s>>>(kin, n, n_cells, shift, mask, dbits,
-                                                                (int32_t)nblk, ghist, st);
+            k_radix_up<true><<<(int)nblk, SORT_THREADS, 0, s>>>(kin, n, n_cells, shift, mask, ghist,
+                                                                st);
         else
-            k_radix_up<false><<<(int)nblk, SORT_THREADS, 0, s>>>(kin, n, n_cells, shift, mask, dbits,
-                                                                 (int32_t)nblk, ghist, st);
+            k_radix_up<false><<<(int)nblk, SORT_THREADS, 0, s>>>(kin, n, n_cells, shift, mask, ghist,
+                                                                 st);
         DSMC_LAUNCH_CHECK("sort:up");
         const int32_t R = mask + 1;
         k_hist_chunk_sum<<<(int)nch, 256, 0, s>>>(ghist, (int32_t)nblk, R, csum);
@@ -497,19 +496,19 @@ static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_ve
         const V3<T> vo = v3<T>(vout);
         if (pass == 0 && last)
             k_radix_down<true, true, T><<<(int)nblk, DN_THREADS, 0, s>>>(
-                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
+                kin, vin_idx, n, n_cells, shift, mask, dbits, goff, kout, vout_idx,
                 vi, vo, cell_start);
         else if (pass == 0)
             k_radix_down<true, false, T><<<(int)nblk, DN_THREADS, 0, s>>>(
-                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
+                kin, vin_idx, n, n_cells, shift, mask, dbits, goff, kout, vout_idx,
                 vi, vo, cell_start);
         else if (last)
             k_radix_down<false, true, T><<<(int)nblk, DN_THREADS, 0, s>>>(
-                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
+                kin, vin_idx, n, n_cells, shift, mask, dbits, goff, kout, vout_idx,
                 vi, vo, cell_start);
         else
             k_radix_down<false, false, T><<<(int)nblk, DN_THREADS, 0, s>>>(
-                kin, vin_idx, n, n_cells, shift, mask, dbits, (int32_t)nblk, goff, kout, vout_idx,
+                kin, vin_idx, n, n_cells, shift, mask, dbits, goff, kout, vout_idx,
                 vi, vo, cell_start);
         DSMC_LAUNCH_CHECK("sort:down");
         kin = kout;
