@@ -281,33 +281,60 @@ k_phaseA_table(int32_t n_cells, PairsView pr, dsmc_rng rng, V3<const T> v, T hmk
 {
     const int64_t np = pr.total(n_cells);
     const T span = T(tv.lne_hi - tv.lne_lo);
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t k = pr.cell[p];
-        const uint32_t a = (uint32_t)(p - pr.off[k]);
-        T xi[3], z[2], u4;
-        pair_latents(rng, a, (uint32_t)k, xi, z, u4);
-        const int32_t i = pr.i[p], j = pr.j[p];
-        const T rx = v.x[i] - v.x[j], ry = v.y[i] - v.y[j], rz = v.z[i] - v.z[j];
-        const T E = hmk * (rx * rx + ry * ry + rz * rz);
-        T fe = (log(E) - T(tv.lne_lo)) / span * T(tv.n_e - 1);
-        T fb = sqrt(u4) * T(tv.n_b - 1);
-        fe = fe > T(0) ? (fe < T(tv.n_e - 1) ? fe : T(tv.n_e - 1)) : T(0);
-        fb = fb > T(0) ? (fb < T(tv.n_b - 1) ? fb : T(tv.n_b - 1)) : T(0);
-        int32_t i0 = (int32_t)floor(fe), j0 = (int32_t)floor(fb);
-        if (i0 > tv.n_e - 2) i0 = tv.n_e - 2;
-        if (j0 > tv.n_b - 2) j0 = tv.n_b - 2;
-        const T te = fe - T(i0), tb = fb - T(j0);
-        const float* row0 = tv.theta + (int64_t)i0 * tv.n_b + j0;
-        const float* row1 = row0 + tv.n_b;
-        const T t00 = row0[0], t01 = row0[1], t10 = row1[0], t11 = row1[1];
-        const T th = (T(1) - te) * ((T(1) - tb) * t00 + tb * t01) +
-                     te * ((T(1) - tb) * t10 + tb * t11);
-        out.a[p] = cos(th);
-        out.b[p] = sin(th);
-        out.c[p] = xi[0];
-        out.d[p] = xi[1];
-        out.e[p] = xi[2];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // two pairs per thread and iteration: the dependent loads of both (pair
+    // record, velocities, table corners) are in flight together
+    constexpr int U = 2;
+    for (int64_t p0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p0 < np; p0 += U * stride) {
+        int64_t pp[U];
+        bool ok[U];
+        int32_t kk[U], ii[U], jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            pp[u] = p0 + u * stride;
+            ok[u] = pp[u] < np;
+            const int64_t q = ok[u] ? pp[u] : p0;
+            kk[u] = pr.cell[q];
+            ii[u] = pr.i[q];
+            jj[u] = pr.j[q];
+        }
+        T rx[U], ry[U], rz[U];
+        uint32_t aa[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = ok[u] ? pp[u] : p0;
+            aa[u] = (uint32_t)(q - pr.off[kk[u]]);
+            rx[u] = v.x[ii[u]] - v.x[jj[u]];
+            ry[u] = v.y[ii[u]] - v.y[jj[u]];
+            rz[u] = v.z[ii[u]] - v.z[jj[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            T xi[3], z[2], u4;
+            pair_latents(rng, aa[u], (uint32_t)kk[u], xi, z, u4);
+            const T E = hmk * (rx[u] * rx[u] + ry[u] * ry[u] + rz[u] * rz[u]);
+            T fe = (log(E) - T(tv.lne_lo)) / span * T(tv.n_e - 1);
+            T fb = sqrt(u4) * T(tv.n_b - 1);
+            fe = fe > T(0) ? (fe < T(tv.n_e - 1) ? fe : T(tv.n_e - 1)) : T(0);
+            fb = fb > T(0) ? (fb < T(tv.n_b - 1) ? fb : T(tv.n_b - 1)) : T(0);
+            int32_t i0 = (int32_t)floor(fe), j0 = (int32_t)floor(fb);
+            if (i0 > tv.n_e - 2) i0 = tv.n_e - 2;
+            if (j0 > tv.n_b - 2) j0 = tv.n_b - 2;
+            const T te = fe - T(i0), tb = fb - T(j0);
+            const float* row0 = tv.theta + (int64_t)i0 * tv.n_b + j0;
+            const float* row1 = row0 + tv.n_b;
+            const T t00 = row0[0], t01 = row0[1], t10 = row1[0], t11 = row1[1];
+            const T th = (T(1) - te) * ((T(1) - tb) * t00 + tb * t01) +
+                         te * ((T(1) - tb) * t10 + tb * t11);
+            if (ok[u]) {
+                const int64_t p = pp[u];
+                out.a[p] = cos(th);
+                out.b[p] = sin(th);
+                out.c[p] = xi[0];
+                out.d[p] = xi[1];
+                out.e[p] = xi[2];
+            }
+        }
     }
 }
 
