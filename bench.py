@@ -9,7 +9,7 @@ metric is accepted collision pairs per second.  The same step with the ab
 initio quadrature rule in place of the network is timed beside it, with the
 network's angle error against the quadrature on the same pairs.
 
-Prints ONE JSON line.  --gpus above 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus above 1 exits: the path is measured on one GPU.
 """
 from __future__ import annotations
 
@@ -70,8 +70,9 @@ def load_weights(path, workloads):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        print(f"bench.py: the collision step is measured on one GPU only (asked for --gpus "
+              f"{args.gpus}); sharding it across GPUs is described, not implemented.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
