@@ -195,16 +195,43 @@ __device__ __forceinline__ void st_flag(dsmc_status* st, uint32_t f)
 }
 
 // Wave64 reductions with cross-lane shuffles.
+// Value of the partner lane under a DPP pattern inside each 16-lane row
+// (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror):
+// a VALU move instead of an LDS-crossbar permute.  Needs the whole wave
+// active, as every wave reduction here is called.
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const int l0 = (int)(uint32_t)b, h0 = (int)(uint32_t)(b >> 32);
+    const int lo = __builtin_amdgcn_update_dpp(l0, l0, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(h0, h0, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_HALF_MIRROR = 0x141,
+              DPP_ROW_MIRROR = 0x140;
+
+// Butterfly sum over the wave: pairs within quads, then quads and half-rows
+// by mirrors, then rows by lane shuffles.  Every pairing is symmetric, so
+// all lanes end with the same bits, and the order is fixed.
 __device__ __forceinline__ double wave_sum(double x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    x += dpp_partner<DPP_QUAD_XOR1>(x);
+    x += dpp_partner<DPP_QUAD_XOR2>(x);
+    x += dpp_partner<DPP_ROW_HALF_MIRROR>(x);
+    x += dpp_partner<DPP_ROW_MIRROR>(x);
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
     return x;
 }
 __device__ __forceinline__ double wave_max(double x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    x = fmax(x, dpp_partner<DPP_QUAD_XOR1>(x));
+    x = fmax(x, dpp_partner<DPP_QUAD_XOR2>(x));
+    x = fmax(x, dpp_partner<DPP_ROW_HALF_MIRROR>(x));
+    x = fmax(x, dpp_partner<DPP_ROW_MIRROR>(x));
+    x = fmax(x, __shfl_xor(x, 16, 64));
+    x = fmax(x, __shfl_xor(x, 32, 64));
     return x;
 }
 __device__ __forceinline__ int wave_sum_i(int x)
