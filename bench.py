@@ -257,6 +257,37 @@ def main():
     wall_v, ms_v, per_v = run("vhs", 1, args.table_steps)
     log(f"vhs: {ms_v:.3f} ms/step, stages {json.dumps({k: round(x, 4) for k, x in per_v.items()})}")
 
+    # SBT selection (the alternative rate control) on the same sorted input,
+    # beside the NTC selection's stage time
+    st_sbt = api.new_status(dev)
+    sbt_ws = api.workspace(lib.dsmc_select_pairs_sbt_ws(n_cells, cap), dev)
+    do_sort()
+    api.moment_match(cs, v, mom, L.MM_CAPTURE)
+    api.select_pairs_sbt(cs, v, pop.xs, lam, 11, 0, pairs, ws=sbt_ws, st=st_sbt)
+    torch.cuda.synchronize()
+    s0_, s1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0_.record(stream)
+    for _ in range(5):
+        api.select_pairs_sbt(cs, v, pop.xs, lam, 11, 0, pairs, ws=sbt_ws, st=st_sbt)
+    s1_.record(stream)
+    torch.cuda.synchronize()
+    sbt_ms = s0_.elapsed_time(s1_) / 5
+    sbt_pairs = int(pairs.cnt.sum())
+    log(f"sbt selection: {sbt_ms:.3f} ms, {sbt_pairs} pairs (NTC stage {per_n['select']:.3f} ms)")
+
+    # Chapman-Enskog viscosity from the quadrature chi: 64 temperatures
+    T_ce = torch.linspace(300.0, 3000.0, 64, dtype=torch.float64, device=dev)
+    api.viscosity_ce(T_ce, W.AR_MASS, 2.5e-9, pot)
+    torch.cuda.synchronize()
+    c0_, c1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0_.record(stream)
+    for _ in range(3):
+        api.viscosity_ce(T_ce, W.AR_MASS, 2.5e-9, pot)
+    c1_.record(stream)
+    torch.cuda.synchronize()
+    ce_ms = c0_.elapsed_time(c1_) / 3
+    log(f"Chapman-Enskog viscosity, 64 temperatures: {ce_ms:.3f} ms")
+
     # deflection batch (2^20 pairs, g log-uniform 100-20 000 m/s, b^2 uniform):
     # quadrature FP64 / FP32 against the angle network evaluated per pair
     batch = deflection_batch_timing(api, W, dev, pot, quad, anet, lne_lo, lne_hi)
@@ -284,6 +315,10 @@ def main():
         "table_ms_per_step": ms_t,
         "stage_ms_table": per_t,
         "table_theta_rms_vs_quadrature_rad": table_rms,
+        "sbt_select_ms": sbt_ms,
+        "sbt_pairs": sbt_pairs,
+        "ntc_select_ms": per_n["select"],
+        "ce_viscosity_ms_64_temperatures": ce_ms,
         "vhs_pairs_per_s": n_pairs / (ms_v * 1e-3),
         "vhs_ms_per_step": ms_v,
         "stage_ms_vhs": per_v,
