@@ -500,11 +500,11 @@ __device__ __forceinline__ void list_cell(const CellList& L, int32_t k, int32_t 
 __device__ __forceinline__ int64_t list_items(const CellList& L) { return (int64_t)L.p[0] + L.p[1]; }
 
 // WAVE schedule: one 64-lane workgroup per cell with at most 256 pairs whose
-// slots span at most 512 (small LDS tables, so many workgroups stay resident
-// to hide the cell loads); every other cell goes to the list the BLOCK kernel
+// slots span at most 320 (free-stream cells of a few hundred particles; small
+// LDS tables, so many workgroups stay resident to hide the cell loads); every other cell goes to the list the BLOCK kernel
 // works through (list[0] = length, list[1..] = cells).  The next cell's count
 // and offset are loaded while the current cell runs.
-constexpr int WV_NMAX = 512;
+constexpr int WV_NMAX = 320;
 constexpr int WV_PPL = 4;
 constexpr int WV_RMAX = 64 * WV_PPL;
 template <typename T, int RULE>
@@ -768,9 +768,10 @@ template <typename T> struct CellView {
     __device__ T z(int32_t q) const { return pz[q]; }
 };
 
-// WAVE form: cells with <= 256 pairs and <= 512 particles; others go to the list.
+// WAVE form: cells with <= 256 pairs and <= WV_NMAX particles; others go to the list.
+// At most four waves per SIMD: with the 320-slot LDS that is 14 cells per CU.
 template <typename T, int RULE>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, 4)
 k_phaseB_match_wave(int32_t n_cells, PairsView pr, V3<T> v, PairBuf<T> d, MatchArgs ma,
                     CellList list)
 {
