@@ -272,7 +272,7 @@ __device__ __forceinline__ void count_runs(int32_t k, bool ok, int s, int32_t tn
 // LAST: the final pass also gathers the velocities into sorted order
 // (vals are then the original indices, i.e. perm).
 template <bool FIRST, bool LAST, typename T>
-__global__ void __launch_bounds__(DN_THREADS)
+__global__ void __launch_bounds__(DN_THREADS, 8)
 k_radix_down(const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int32_t n,
              int32_t n_cells, int shift, int32_t mask, int dbits,
              const int32_t* __restrict__ goff, int32_t* __restrict__ keys_out,
