@@ -555,17 +555,35 @@ static double potential_dVdr(const orc_potential* p, double r)
     return 0.0;
 }
 
+/* -int_a^{a+h} V'(r) dr by 3-point Gauss-Legendre. */
+static double gauss3_minus_int_dV(const orc_potential* p, double a, double h)
+{
+    double half = 0.5 * h, mid = a + half, x = sqrt(0.6);
+    return -half * ((5.0 / 9.0) * potential_dVdr(p, mid - half * x) +
+                    (8.0 / 9.0) * potential_dVdr(p, mid) +
+                    (5.0 / 9.0) * potential_dVdr(p, mid + half * x));
+}
+
 /* V(a) - V(a + h).  For |h| small against a the direct difference loses
  * digits, so it is taken as -int_a^{a+h} V'(r) dr by 3-point Gauss-Legendre,
  * whose error is far below rounding for |h| < 1e-3 a.  Passing the step h
- * itself (not a + h) keeps it exact. */
+ * itself (not a + h) keeps it exact.  The Jager form has two branches that
+ * meet at 0.4 R_eps; a Gauss rule is exact only on one smooth branch, so an
+ * interval that contains the meeting point is split there, and the
+ * difference of the two branches at that point (V is continuous there only
+ * to the accuracy of the coefficients) is added. */
 double orc_potential_dV(const orc_potential* p, double a, double h)
 {
     if (fabs(h) < 1e-3 * fabs(a)) {
-        double half = 0.5 * h, mid = a + half, x = sqrt(0.6);
-        return -half * ((5.0 / 9.0) * potential_dVdr(p, mid - half * x) +
-                        (8.0 / 9.0) * potential_dVdr(p, mid) +
-                        (5.0 / 9.0) * potential_dVdr(p, mid + half * x));
+        if (p->kind == ORC_POT_JAGER) {
+            double rs = 0.4 * p->R_eps;
+            if (h > 0.0 && a < rs && a + h > rs) {
+                double inner = p->A_sr / rs * exp(-p->a_sr * rs);
+                return gauss3_minus_int_dV(p, a, rs - a) + (inner - orc_potential_V(p, rs)) +
+                       gauss3_minus_int_dV(p, rs, (a + h) - rs);
+            }
+        }
+        return gauss3_minus_int_dV(p, a, h);
     }
     return orc_potential_V(p, a) - orc_potential_V(p, a + h);
 }

@@ -133,8 +133,13 @@ def _mp_chi(b, E, dps=30, n_pan=32):
     return float(mp.pi - 2 * (b / rmin) * I)
 
 
+# The last two: high-energy pairs of the 2^20-pair batch of seed 2 whose
+# turning point lies just inside the switch between the two branches of the
+# potential (0.4 R_eps), so the integrand's first nodes straddle it.
 @pytest.mark.parametrize("g,b", [(2743.87, 9.472), (498.07, 5.2766), (120.81, 7.176),
-                                 (312.92, 4.003), (2567.27, 2.096), (19528.8, 0.7)])
+                                 (312.92, 4.003), (2567.27, 2.096), (19528.8, 0.7),
+                                 (15687.361230336597, 0.925757711954615),
+                                 (14749.692948604592, 0.8179355689506196)])
 def test_jager_against_mpmath(orc, g, b):
     P = orc.potential_jager(W.JAGER_PLACEHOLDER)
     E = 0.5 * (W.AR_MASS / 2) * g * g / W.KB
