@@ -118,15 +118,19 @@ typedef struct {
 
 /* Quadrature settings of the deflection integral.  n_nodes: Gauss-Legendre
  * nodes per panel (8..128; 0 = 64).  scan_ratio: geometric step of the
- * downward root scan at low energy (0 = 0.98).  max_iter: root refinement
- * iterations (0 = 60).  low_panels: equal panels of n_nodes used below the
- * energy at which several turning points become possible (orbiting, where
- * the integrand has a sharp interior peak; 0 = 4); one panel above it. */
+ * downward root scan below the energy at which D can have several roots
+ * (0 = 0.95; every local minimum the scan passes is checked, so a narrow
+ * negative dip of D is not stepped over).  max_iter: root refinement
+ * iterations (0 = 60).  refine: >= 0 (default): pairs whose integrand has a
+ * sharp peak near orbiting, or whose root is uncertain, are re-evaluated in
+ * FP64 by the whole wavefront (parallel root scan, polished local minimum
+ * and root, sinh substitution centred on the peak); -1: off, every pair
+ * keeps the one-rule result (for accuracy and timing comparison). */
 typedef struct {
     int32_t n_nodes;
     int32_t max_iter;
     double scan_ratio;
-    int32_t low_panels;
+    int32_t refine;
     int32_t reserved;
 } dsmc_quad;
 
@@ -283,7 +287,11 @@ int dsmc_apply_pairs_match(int32_t n_cells, const int32_t* cell_start, int32_t d
  *   chi = pi - 2 b int_{r_min}^inf dr / (r^2 sqrt(1 - b^2/r^2 - V/E)),
  * evaluated after u = r_min / r and u = 1 - t^2 with Gauss-Legendre in t.
  * b (m), g (m/s) and chi (rad) are arrays of `dtype` (FP64 or FP32: the
- * arithmetic precision).  fold = 1 returns theta = arccos(cos chi) in
+ * arithmetic precision of the per-pair rule; for FP32 the root and
+ * V(r_min) are finished in FP64 below the orbiting energy).  Pairs whose
+ * integrand has a sharp peak near orbiting, or whose root is uncertain, are
+ * re-evaluated in FP64 by a second pass (see dsmc_quad.refine); chi of such
+ * a pair is written twice.  fold = 1 returns theta = arccos(cos chi) in
  * [0, pi].  A failed root search gives NaN and counts in st->root_fail. */
 int dsmc_deflect_jager(int64_t n, int32_t dtype, const void* b, const void* g, void* chi,
                        double m_red, const dsmc_potential* pot, dsmc_quad quad, int32_t fold,

@@ -63,7 +63,7 @@ class Potential(C.Structure):
 
 class Quad(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("max_iter", C.c_int32), ("scan_ratio", C.c_double),
-                ("low_panels", C.c_int32), ("reserved", C.c_int32)]
+                ("refine", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Mlp(C.Structure):

@@ -106,8 +106,8 @@ def potential_invpow(K, n):
     return P
 
 
-def quad_struct(n_nodes=64, max_iter=60, scan_ratio=0.98, low_panels=4):
-    return L.Quad(int(n_nodes), int(max_iter), float(scan_ratio), int(low_panels), 0)
+def quad_struct(n_nodes=64, max_iter=60, scan_ratio=0.95, refine=0):
+    return L.Quad(int(n_nodes), int(max_iter), float(scan_ratio), int(refine), 0)
 
 
 class Net:

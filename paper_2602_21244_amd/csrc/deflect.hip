@@ -1,432 +1,176 @@
 // Ab initio deflection angle by quadrature of the classical deflection
 // integral (section "Computational Implementation: The Exact vs. Neural
-// Paradigm"), one lane per pair, no cross-lane traffic:
-//   1. E = m_red g^2 / 2; r_min = largest root of D(r) = 1 - b^2/r^2 - V(r)/E,
-//      bracketed by a downward geometric scan (fine steps at low energy, where
-//      D can have several roots) and refined by safeguarded Newton steps.
-//   2. u = r_min / r maps the range to [0, 1]; u = 1 - t^2 removes the
-//      inverse-square-root singularity at u = 1, leaving the smooth integrand
-//      2 t / sqrt(F) with F = beta^2 t^2 (2 - t^2) + (V(r_min) - V(r))/E,
-//      beta = b / r_min, which is integrated by fixed-order Gauss-Legendre.
-//   3. chi = pi - 2 beta * integral.
-// Near r_min the potential difference is formed as -int V' dr (2-point
-// Gauss-Legendre) to avoid cancellation.
+// Paradigm"): the batch entry point, Phase A of the in-step rule, the
+// training-row harvest and the Chapman-Enskog transport integrals.  The
+// per-pair arithmetic (root, substitution, Gauss-Legendre rule, peak
+// detection and the FP64 refinement pieces) is in chi_quad.hpp; this file
+// holds the wave-level driver -- every lane evaluates its pair, then the
+// wavefront re-evaluates each flagged pair in FP64 together -- and the
+// kernels.
 #include <math.h>
 
 #include <string.h>
 
 #include <vector>
 
+#include "chi_quad.hpp"
 #include "collide.hpp"
 
 namespace dsmc {
 
-constexpr int GL_MAX = 128;
-
-struct GLRule {
-    int n;
-    double t[GL_MAX];
-    double w[GL_MAX];
-};
-
-// Potential and the derived quantities a kernel needs.
-struct Pot {
-    dsmc_potential p;
-    double r_sw;     // short-range switch 0.4 R_eps (JAGER)
-    double r_zero;   // largest zero of V (JAGER); V < 0 beyond it
-    double e_scan;   // below this E (K), D may have several roots: fine scan
-    double fact[17]; // 1/k!
-};
-
-struct QuadCfg {
-    int max_iter;
-    int low_panels;
-    double scan_ratio;
-};
-
 // ------------------------------------------------------------------------
-// Potential (T arithmetic)
+// Wave level: the lane rule for every pair, then the FP64 refinement of the
+// flagged pairs, one pair at a time by the whole wavefront.
 // ------------------------------------------------------------------------
-// Beyond beta_tt r = 60 every Tang-Toennies factor f_6..f_16 is 1 to better
-// than 1e-13 (the tail exp(-x) sum x^k/k! is below that), so they are taken
-// as 1 there.
-constexpr double DAMP_OFF = 60.0;
-template <typename T>
-__device__ __forceinline__ T dexp(T x) { return exp(x); }
-template <>
-__device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
-
-template <typename T>
-__device__ __forceinline__ T V_of(const Pot& P, T r)
+// chi of one pair re-evaluated in FP64 by the 64 lanes of a wave (all lanes
+// call it with the same b, E), with uniform control flow:
+//  1. D at 64 geometric radii (one per lane) from max(b, r_zero) down past
+//     r_floor; the first sign change bounds the largest root from below.
+//  2. If the samples show a local minimum of D above it, D' is bracketed
+//     there by parallel rounds: a minimum D(r_m) <= 0 means a dip holding
+//     the largest root in (r_m, r_{k-1}); a positive one is the interior
+//     peak of the integrand.
+//  3. The root is bracketed by parallel rounds, the secant taken, and V, V'
+//     evaluated there; D'' at r_min by a central difference on two lanes.
+//  4. The sinh-mapped integral, its nodes spread over the lanes, summed by a
+//     fixed butterfly.
+__device__ double chi_refine_wave(const Pot& P, const QuadCfg& q, const GLRule& gl, double b,
+                                  double E)
 {
-    const dsmc_potential& p = P.p;
-    if (p.kind == DSMC_POT_INVPOW) {
-        T rn = r;
-        for (int q = 1; q < p.n; ++q) rn *= r;
-        return T(p.K) / rn;
-    }
-    if (r < T(P.r_sw)) return T(p.A_sr) / r * dexp<T>(-T(p.a_sr) * r);
-    const T ri = T(1) / r;
-    const T rep = T(p.A) * dexp<T>(T(p.a1) * r + T(p.a2) * r * r + T(p.am1) * ri + T(p.am2) * ri * ri);
-    const T x = T(p.beta_tt) * r;
-    const T ri2 = ri * ri;
-    T rpow = ri2 * ri2 * ri2;  // r^-6
-    T disp = T(0);
-    if (x >= T(DAMP_OFF)) {
-        // damping factors equal 1 to well below rounding (and x^16 would
-        // overflow FP32 at large r)
-#pragma unroll
-        for (int n = 0; n < 6; ++n) {
-            disp += T(p.C[n]) * rpow;
-            rpow *= ri2;
-        }
-        return rep - disp;
-    }
-    const T ex = dexp<T>(-x);
-    T term = T(1), S = T(1);
-#pragma unroll
-    for (int k = 1; k <= 16; ++k) {
-        term = term * x * T(1.0 / k);  // x^k / k!
-        S += term;
-        if (k >= 6 && (k & 1) == 0) {
-            disp += (T(1) - ex * S) * T(p.C[(k - 6) / 2]) * rpow;
-            rpow *= ri2;
-        }
-    }
-    return rep - disp;
-}
-
-template <typename T>
-__device__ __forceinline__ T dV_of(const Pot& P, T r)
-{
-    const dsmc_potential& p = P.p;
-    if (p.kind == DSMC_POT_INVPOW) {
-        T rn = r;
-        for (int q = 1; q < p.n; ++q) rn *= r;
-        return -T(p.n) * T(p.K) / (rn * r);
-    }
-    const T ri = T(1) / r;
-    if (r < T(P.r_sw)) {
-        const T v = T(p.A_sr) * ri * dexp<T>(-T(p.a_sr) * r);
-        return -v * (T(p.a_sr) + ri);
-    }
-    const T phi_r = T(p.a1) + T(2) * T(p.a2) * r - T(p.am1) * ri * ri - T(2) * T(p.am2) * ri * ri * ri;
-    const T rep = T(p.A) * dexp<T>(T(p.a1) * r + T(p.a2) * r * r + T(p.am1) * ri + T(p.am2) * ri * ri);
-    const T x = T(p.beta_tt) * r;
-    const T ri2 = ri * ri;
-    T rpow = ri2 * ri2 * ri2;
-    T dd = T(0);
-    if (x >= T(DAMP_OFF)) {
-#pragma unroll
-        for (int n = 0; n < 6; ++n) {
-            dd -= T(6 + 2 * n) * T(p.C[n]) * rpow * ri;
-            rpow *= ri2;
-        }
-        return rep * phi_r - dd;
-    }
-    const T ex = dexp<T>(-x);
-    T term = T(1), S = T(1);
-#pragma unroll
-    for (int k = 1; k <= 16; ++k) {
-        term = term * x * T(1.0 / k);  // x^k / k!
-        S += term;
-        if (k >= 6 && (k & 1) == 0) {
-            // d/dr [f_k(beta r) C_k r^-k], f_k'(x) = e^-x x^k / k!
-            dd += T(p.C[(k - 6) / 2]) * (T(p.beta_tt) * ex * term * rpow -
-                                        T(k) * (T(1) - ex * S) * rpow * ri);
-            rpow *= ri2;
-        }
-    }
-    return rep * phi_r - dd;
-}
-
-template <typename T> struct Consts;
-template <> struct Consts<double> {
-    static constexpr double pi = 3.14159265358979323846;
-    static constexpr double rtol = 4e-16;
-};
-template <> struct Consts<float> {
-    static constexpr float pi = 3.14159265358979f;
-    static constexpr float rtol = 2e-7f;
-};
-
-// D(r) = 1 - b^2/r^2 - V(r)/E
-template <typename T>
-__device__ __forceinline__ T D_of(const Pot& P, T b2, T E, T r)
-{
-    return T(1) - b2 / (r * r) - V_of<T>(P, r) / E;
-}
-
-// One node of the t integral: 2 t / sqrt(F) with
-// F = beta^2 t^2 (2 - t^2) + (V(r_min) - V(r))/E + D0 and r = r_min / (1 - t^2);
-// also F / t^2 (for the peak indicator).
-template <typename T>
-__device__ __forceinline__ T node_term(const Pot& P, T rmin, T beta, T Vmin, T E, T D0, T t,
-                                       T& f_over_t2)
-{
-    const T g1 = T(0.5) - T(0.28867513459481287);  // 2-point Gauss-Legendre on [0,1]
-    const T g2 = T(0.5) + T(0.28867513459481287);
-    const T t2 = t * t;
-    const T dr = rmin * t2 / (T(1) - t2);
-    T dV = T(0);
-    if (P.p.kind != DSMC_POT_HS) {
-        if (t2 < T(1e-3))
-            dV = -dr * T(0.5) * (dV_of<T>(P, rmin + g1 * dr) + dV_of<T>(P, rmin + g2 * dr));
-        else
-            dV = Vmin - V_of<T>(P, rmin + dr);
-    }
-    const T F = beta * beta * t2 * (T(2) - t2) + dV / E + D0;
-    f_over_t2 = F / t2;
-    return F > T(0) ? T(2) * t / sqrt(F) : T(0);
-}
-
-// Gauss-Legendre over t in [ta, tb]; qmin tracks min F / t^2 over the nodes.
-template <typename T>
-__device__ __forceinline__ T integral_part(const Pot& P, const GLRule& gl, T rmin, T beta, T Vmin,
-                                           T E, T D0, T ta, T tb, T& qmin)
-{
-    const T len = tb - ta;
-    T I = T(0);
-    for (int k = 0; k < gl.n; ++k) {
-        T fq;
-        I += T(gl.w[k]) * node_term<T>(P, rmin, beta, Vmin, E, D0, ta + len * T(gl.t[k]), fq);
-        qmin = fq < qmin ? fq : qmin;
-    }
-    return len * I;
-}
-
-// Peak indicator threshold: below the scan energy, F / t^2 (which is
-// r_min D'(r_min) at t = 0 and 1 at t = 1) dipping under this value marks an
-// integrand with a sharp interior peak (near orbiting), for which one
-// Gauss-Legendre panel is not enough; such pairs are re-integrated on
-// low_panels equal panels.
-constexpr double Q_REFINE = 0.6;
-
-template <typename T>
-struct QuadState {
-    T rmin, beta, Vmin, E, D0;
-    bool refine;
-};
-
-// chi(b, E) with b in Angstrom, E/k_B in K, by the one-panel rule; returns
-// NaN if no root is found.  s receives what a panel refinement needs.
-template <typename T>
-__device__ T chi_quad_std(const Pot& P, const QuadCfg& q, const GLRule& gl, T b, T E,
-                          QuadState<T>& s)
-{
-    const T pi = Consts<T>::pi;
-    const T b2 = b * b;
-    s.refine = false;
-    T rmin, D0 = T(0);
-    if (P.p.kind == DSMC_POT_HS) {
-        const T d = T(P.p.d);
-        rmin = b > d ? b : d;
-        const T beta = b / rmin;
-        D0 = b > d ? T(0) : T(1) - beta * beta;
-    } else {
-        T rhi;
-        if (P.p.kind == DSMC_POT_JAGER) {
-            rhi = b > T(P.r_zero) ? b : T(P.r_zero);
-        } else {
-            const T rk = pow(T(2) * T(P.p.K) / E, T(1) / T(P.p.n));
-            rhi = T(2) * b > rk ? T(2) * b : rk;
-            if (!(rhi > T(0))) rhi = T(1);
-        }
-        T fhi = D_of<T>(P, b2, E, rhi);
-        if (fhi <= T(0)) {
-            rmin = rhi;
-        } else {
-            const T ratio = (E < T(P.e_scan)) ? T(q.scan_ratio) : T(0.7);
-            T rlo = rhi, flo = fhi;
-            bool found = false;
-            for (int it = 0; it < 4000; ++it) {
-                rlo = rhi * ratio;
-                flo = D_of<T>(P, b2, E, rlo);
-                if (flo <= T(0)) { found = true; break; }
-                rhi = rlo;
-                fhi = flo;
-                if (rlo < T(1e-4)) break;
-            }
-            if (!found) return T(NAN);
-            // safeguarded Newton inside [rlo, rhi], D(rlo) <= 0 < D(rhi)
-            T r = rhi;
-            for (int it = 0; it < q.max_iter; ++it) {
-                const T f = D_of<T>(P, b2, E, r);
-                if (f > T(0)) rhi = r; else rlo = r;
-                const T fp = T(2) * b2 / (r * r * r) - dV_of<T>(P, r) / E;
-                T rn = r - f / fp;
-                if (!(rn > rlo && rn < rhi)) rn = T(0.5) * (rlo + rhi);
-                const T step = rn - r;
-                r = rn;
-                if (fabs(step) <= Consts<T>::rtol * r || rhi - rlo <= Consts<T>::rtol * r) break;
-            }
-            rmin = r;
-        }
-    }
-    const T beta = b / rmin;
-    const T Vmin = (P.p.kind == DSMC_POT_HS) ? T(0) : V_of<T>(P, rmin);
-    s.rmin = rmin;
-    s.beta = beta;
-    s.Vmin = Vmin;
-    s.E = E;
-    s.D0 = D0;
-    T I = T(0);
-    T qmin = T(1e30);
-    if (E < T(P.e_scan) && P.p.kind == DSMC_POT_JAGER) {
-        // low energy: r_min lies outside the short-range region
-        I = integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, T(0), T(1), qmin);
-        s.refine = q.low_panels > 1 && qmin < T(Q_REFINE);
-    } else {
-        // the short-range switch of the JAGER form is a kink of the
-        // integrand: integrate the two sides separately
-        T tsw = T(1);
-        if (P.p.kind == DSMC_POT_JAGER && rmin < T(P.r_sw)) tsw = sqrt(T(1) - rmin / T(P.r_sw));
-        I = integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, T(0), tsw, qmin);
-        if (tsw < T(1)) I += integral_part<T>(P, gl, rmin, beta, Vmin, E, D0, tsw, T(1), qmin);
-    }
-    return pi - T(2) * beta * I;
-}
-
-// chi for the lanes of a wave (all 64 lanes call it; inactive lanes pass
-// active = false).  Pairs flagged for refinement are re-integrated one at a
-// time by the whole wave: the low_panels x n nodes are spread over the lanes
-// and summed by a fixed butterfly, so the cost of a flagged pair is a few
-// node evaluations per lane.
-template <typename T>
-__device__ T chi_quad_wave(const Pot& P, const QuadCfg& q, const GLRule& gl, T b, T E,
-                           bool active)
-{
-    QuadState<T> s{};
-    T c = T(0);
-    if (active) c = chi_quad_std<T>(P, q, gl, b, E, s);
-    const bool flag = active && s.refine && c == c;
-    uint64_t pend = __ballot(flag);
     const int lane = threadIdx.x & 63;
-    const int n = gl.n, np = q.low_panels, total = n * np;
-    const T inv_np = T(1) / T(np);
+    RefState s{};
+    s.b2 = b * b;
+    s.E = E;
+    double rtop, rho;
+    ref_grid(P, b, rtop, rho);
+    const double r = ref_sample_r(rtop, rho, lane);
+    const double D = D_of<double>(P, s.b2, E, r);
+    const double Dup = __shfl(D, lane > 0 ? lane - 1 : 0, 64);
+    const double Ddn = __shfl(D, lane < 63 ? lane + 1 : 63, 64);
+    const uint64_t neg = __ballot(D <= 0.0);
+    if (!neg) return NAN;
+    const int kneg = __ffsll((unsigned long long)neg) - 1;
+    double rlo = __shfl(r, kneg, 64);
+    double rhi = __shfl(r, kneg > 0 ? kneg - 1 : 0, 64);
+    const uint64_t mins = __ballot(lane >= 1 && lane < kneg && D < Dup && D < Ddn);
+    bool has_min = false;
+    double rm = 0.0, dm = 0.0, d2m = 0.0;
+    if (mins) {
+        const int k = __ffsll((unsigned long long)mins) - 1;
+        double a = __shfl(r, k + 1, 64), bb = __shfl(r, k - 1, 64), fa = 0.0, fb = 0.0;
+        for (int rd = 0; rd < REF_ROUNDS; ++rd) {
+            const double x = ref_x(a, bb, lane);
+            const double f = dD_of<double>(P, s.b2, E, x);
+            const uint64_t pos = __ballot(f >= 0.0);
+            const int L = ref_pick(pos ? __ffsll((unsigned long long)pos) - 1 : 64);
+            a = __shfl(x, L - 1, 64);
+            bb = __shfl(x, L, 64);
+            fa = __shfl(f, L - 1, 64);
+            fb = __shfl(f, L, 64);
+        }
+        rm = (fb > fa) ? a - fa * (bb - a) / (fb - fa) : 0.5 * (a + bb);
+        rm = fmin(fmax(rm, a), bb);
+        d2m = (fb - fa) / (bb - a);
+        dm = D_of<double>(P, s.b2, E, rm);
+        if (dm <= 0.0) {
+            // the dip reaches zero: the largest root lies in (r_m, r_{k-1})
+            rlo = rm;
+            rhi = __shfl(r, k - 1, 64);
+        } else {
+            has_min = true;
+        }
+    }
+    // root of D in [rlo, rhi] (D(rlo) <= 0 < D(rhi); equal ends if D(rtop) <= 0)
+    double fl = -1.0, fh = 1.0;
+    for (int rd = 0; rd < REF_ROUNDS && rhi > rlo; ++rd) {
+        const double x = ref_x(rlo, rhi, lane);
+        const double f = D_of<double>(P, s.b2, E, x);
+        const uint64_t pos = __ballot(f > 0.0);
+        const int L = ref_pick(pos ? __ffsll((unsigned long long)pos) - 1 : 64);
+        rlo = __shfl(x, L - 1, 64);
+        rhi = __shfl(x, L, 64);
+        fl = __shfl(f, L - 1, 64);
+        fh = __shfl(f, L, 64);
+    }
+    s.rmin = (rhi > rlo && fh > fl) ? rlo - fl * (rhi - rlo) / (fh - fl) : rlo;
+    s.rmin = fmin(fmax(s.rmin, rlo), rhi);
+    double dV;
+    s.Vmin = pot_eval<double, true>(P, s.rmin, dV);
+    const double dD = 2.0 * s.b2 / (s.rmin * s.rmin * s.rmin) - dV / E;
+    s.beta = b / s.rmin;
+    // D''(r_min) by a central difference, one side on each of two lanes
+    const double h = 1e-4 * s.rmin;
+    const double fd = dD_of<double>(P, s.b2, E, s.rmin + (lane == 0 ? h : -h));
+    const double d2D = (__shfl(fd, 0, 64) - __shfl(fd, 1, 64)) / (2.0 * h);
+    ref_map(s, has_min, rm, dm, d2m, dD, d2D);
+    const int M = ref_nodes(s, gl);
+    double I = 0.0;
+    int nonpos = 0;
+    for (int m = lane; m < M; m += 64) I += ref_node(P, gl, s, m, nonpos);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) I += __shfl_xor(I, o, 64);
+    return 3.14159265358979323846 - 2.0 * s.beta * I;
+}
+
+// chi for the lanes of a wave with the refinement done in place (all 64
+// lanes call it; inactive lanes pass active = false).  Used where the items
+// are not stored in a form a separate pass could re-read (the transport
+// integrals' b nodes); FP64 only.
+__device__ double chi_wave_inplace(const Pot& P, const QuadCfg& q, const GLRule& gl, double b,
+                                   double E, bool active)
+{
+    bool flag = false;
+    double c = 0.0;
+    if (active) c = chi_lane<double>(P, q, gl, b, E, flag);
+    if (!q.refine) return c;
+    uint64_t pend = __ballot(active && flag);
+    const int lane = threadIdx.x & 63;
     while (pend) {
         const int src = __ffsll((unsigned long long)pend) - 1;
-        const T rmin = __shfl(s.rmin, src, 64), beta = __shfl(s.beta, src, 64);
-        const T Vmin = __shfl(s.Vmin, src, 64), Ee = __shfl(s.E, src, 64);
-        const T D0 = __shfl(s.D0, src, 64);
-        T I = T(0);
-        for (int m = lane; m < total; m += 64) {
-            const int k = m / n, j = m - k * n;
-            T fq;
-            I += T(gl.w[j]) * inv_np *
-                 node_term<T>(P, rmin, beta, Vmin, Ee, D0, (T(k) + T(gl.t[j])) * inv_np, fq);
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) I += __shfl_xor(I, o, 64);
-        if (lane == src) c = Consts<T>::pi - T(2) * beta * I;
+        const double cr = chi_refine_wave(P, q, gl, __shfl(b, src, 64), __shfl(E, src, 64));
+        if (lane == src) c = cr;
         pend &= pend - 1;
     }
     return c;
 }
 
-// ------------------------------------------------------------------------
-// Host side: Gauss-Legendre nodes by Newton on P_n, potential set-up.
-// ------------------------------------------------------------------------
-static int make_gl(int n, GLRule* g)
+// Refinement pass: each wave scans 64 consecutive items, and every item the
+// lane pass left pending (a sentinel in its output) is re-evaluated by the
+// whole wave.  Job supplies count(n) (the items to scan, at most n),
+// pending(i), inputs(i, b, E) and store(i, chi).
+template <class Job>
+__global__ void __launch_bounds__(256)
+k_refine(Job job, int64_t n, Pot P, QuadCfg q, GLRule gl, dsmc_status* st)
 {
-    if (n == 0) n = 64;
-    if (n < 2 || n > GL_MAX) return arg_error("dsmc_quad: n_nodes %d not in [2, %d]", n, GL_MAX);
-    g->n = n;
-    const double pi = 3.14159265358979323846;
-    for (int i = 0; i < n; ++i) {
-        double x = cos(pi * (i + 0.75) / (n + 0.5));
-        double dp = 1.0;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = x;
-            for (int k = 2; k <= n; ++k) {
-                const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = pk;
+    n = job.count(n);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t base = wave * 64; base < n; base += n_waves * 64) {
+        const int64_t i = base + lane;
+        uint64_t pend = __ballot(i < n && job.pending(i));
+        while (pend) {
+            const int src = __ffsll((unsigned long long)pend) - 1;
+            double b = 0.0, E = 0.0;
+            if (lane == src) job.inputs(i, b, E);
+            b = __shfl(b, src, 64);
+            E = __shfl(E, src, 64);
+            const double c = chi_refine_wave(P, q, gl, b, E);
+            if (lane == src) {
+                if (c != c && st) {
+                    atomicAdd(&st->root_fail, 1);
+                    atomicOr(&st->flags, (uint32_t)DSMC_ST_ROOT_FAIL);
+                }
+                job.store(i, c);
             }
-            dp = n * (x * p1 - p0) / (x * x - 1.0);
-            const double dx = p1 / dp;
-            x -= dx;
-            if (fabs(dx) < 1e-16) break;
+            pend &= pend - 1;
         }
-        // recompute derivative at the converged node
-        double p0 = 1.0, p1 = x;
-        for (int k = 2; k <= n; ++k) {
-            const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-            p0 = p1;
-            p1 = pk;
-        }
-        dp = n * (x * p1 - p0) / (x * x - 1.0);
-        // map [-1, 1] -> [0, 1]
-        g->t[i] = 0.5 * (1.0 - x);
-        g->w[i] = 1.0 / ((1.0 - x * x) * dp * dp);  // (2 / ((1-x^2) P'^2)) / 2
     }
-    return DSMC_OK;
 }
 
-static double host_V(const Pot& P, double r)
-{
-    const dsmc_potential& p = P.p;
-    if (r < P.r_sw) return p.A_sr / r * exp(-p.a_sr * r);
-    double rep = p.A * exp(p.a1 * r + p.a2 * r * r + p.am1 / r + p.am2 / (r * r));
-    double x = p.beta_tt * r, ex = exp(-x), term = 1, S = 1, disp = 0;
-    for (int k = 1; k <= 16; ++k) {
-        term *= x / k;
-        S += term;
-        if (k >= 6 && k % 2 == 0) disp += (1 - ex * S) * p.C[(k - 6) / 2] / pow(r, k);
-    }
-    return rep - disp;
-}
-
-static int make_pot(const dsmc_potential* pot, Pot* P)
-{
-    if (!pot) return arg_error("dsmc potential: null");
-    P->p = *pot;
-    P->fact[0] = 1.0;
-    for (int k = 1; k <= 16; ++k) P->fact[k] = P->fact[k - 1] * k;
-    P->r_sw = 0.0;
-    P->r_zero = 0.0;
-    P->e_scan = 0.0;
-    switch (pot->kind) {
-    case DSMC_POT_HS:
-        if (!(pot->d > 0)) return arg_error("dsmc potential: HS diameter must be > 0");
-        return DSMC_OK;
-    case DSMC_POT_INVPOW:
-        if (pot->n < 1 || pot->n > 12 || !(pot->K >= 0))
-            return arg_error("dsmc potential: INVPOW needs 1 <= n <= 12 and K >= 0");
-        return DSMC_OK;
-    case DSMC_POT_JAGER: {
-        if (!(pot->R_eps > 0) || !(pot->A > 0) || !(pot->beta_tt > 0))
-            return arg_error("dsmc potential: bad JAGER parameters");
-        P->r_sw = 0.4 * pot->R_eps;
-        // largest zero of V: scan in from 50 A, then bisect
-        double hi = 50.0, lo = 50.0;
-        while (host_V(*P, lo) <= 0.0 && lo > 0.05) lo *= 0.99;
-        if (host_V(*P, lo) <= 0.0) return arg_error("dsmc potential: V has no repulsive core");
-        for (int it = 0; it < 200; ++it) {
-            const double m = 0.5 * (lo + hi);
-            if (host_V(*P, m) > 0.0) lo = m; else hi = m;
-        }
-        P->r_zero = hi;
-        // Energy above which r^2 (1 - V(r)/E) is increasing in r on the
-        // outer region (single turning point for every b); below it the root
-        // scan must be fine.  Found on a grid, then doubled for margin.
-        double ecrit = 0.0;
-        for (double E = 1.0; E < 1e5; E *= 1.05) {
-            bool mono = true;
-            double prev = -1e300;
-            for (double r = 0.6 * P->r_zero; r < 40.0; r *= 1.002) {
-                const double B = r * r * (1.0 - host_V(*P, r) / E);
-                if (B < prev) { mono = false; break; }
-                prev = B;
-            }
-            if (mono) { ecrit = E; break; }
-        }
-        P->e_scan = ecrit > 0 ? 2.0 * ecrit : 1e30;
-        return DSMC_OK;
-    }
-    }
-    return arg_error("dsmc potential: kind %d", pot->kind);
-}
+// Sentinel of a pending item: +inf (no chi, cos chi or integrand term takes it).
+template <typename T> __device__ __forceinline__ T pending_mark() { return T(INFINITY); }
+template <typename T> __device__ __forceinline__ bool is_pending(T x) { return x == T(INFINITY); }
 
 // Host-side potential set-up is costly for JAGER (grid search); cache the
 // last one.
@@ -451,125 +195,251 @@ static int get_pot(const dsmc_potential* pot, Pot* out)
     return rc;
 }
 
-static int make_cfg(const dsmc_quad& q, QuadCfg* c, GLRule* gl)
-{
-    c->max_iter = q.max_iter > 0 ? q.max_iter : 60;
-    c->scan_ratio = q.scan_ratio > 0 ? q.scan_ratio : 0.98;
-    c->low_panels = q.low_panels > 0 ? q.low_panels : 4;
-    if (c->low_panels > 16) return arg_error("dsmc_quad: low_panels %d > 16", c->low_panels);
-    if (!(c->scan_ratio > 0.5 && c->scan_ratio < 1.0))
-        return arg_error("dsmc_quad: scan_ratio %g not in (0.5, 1)", c->scan_ratio);
-    return make_gl(q.n_nodes, gl);
-}
-
 constexpr double KB = 1.380649e-23;
 
-// ------------------------------------------------------------------------
-// Kernels
-// ------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_deflect(int64_t n, const T* __restrict__ b, const T* __restrict__ g, T* __restrict__ chi,
-          T half_m_over_k, Pot P, QuadCfg q, GLRule gl, int fold, dsmc_status* st)
+__device__ __forceinline__ void count_root_fail(dsmc_status* st)
 {
-    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < n;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = base + (threadIdx.x & 63);
-        const bool active = p < n;
-        const T gg = active ? g[p] : T(1);
-        const T E = half_m_over_k * gg * gg;
-        T c = chi_quad_wave<T>(P, q, gl, active ? b[p] * T(1e10) : T(1), E, active);
-        if (!active) continue;
-        if (c != c) {
-            if (st) {
-                atomicAdd(&st->root_fail, 1);
-                atomicOr(&st->flags, (uint32_t)DSMC_ST_ROOT_FAIL);
-            }
-        } else if (fold) {
-            c = acos(cos(c));
+    if (st) {
+        atomicAdd(&st->root_fail, 1);
+        atomicOr(&st->flags, (uint32_t)DSMC_ST_ROOT_FAIL);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Kernels.  Each lane-pass kernel evaluates its items with the lane rule and
+// leaves the flagged ones pending; k_refine with the matching job finishes
+// them.
+// ------------------------------------------------------------------------
+// Lane pass of the batch entry point.
+template <typename T>
+__device__ __forceinline__ void deflect_lanes(int64_t n, const T* __restrict__ b,
+                                              const T* __restrict__ g, T* __restrict__ chi,
+                                              double half_m_over_k, const Pot& P, const QuadCfg& q,
+                                              const GLRule& gl, int fold, dsmc_status* st)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const double gg = double(g[p]);
+        bool flag;
+        T c = chi_lane<T>(P, q, gl, double(b[p]) * 1e10, half_m_over_k * gg * gg, flag);
+        if (flag && q.refine) {
+            chi[p] = pending_mark<T>();
+            continue;
         }
+        if (c != c) count_root_fail(st);
+        else if (fold) c = acos(cos(c));
         chi[p] = c;
     }
 }
 
+// The FP32 lane rule fits in 128 VGPRs: four waves per SIMD instead of three
+// hide more of its latency.  The FP64 one would spill under that cap.
+__global__ void __launch_bounds__(256)
+k_deflect_f64(int64_t n, const double* __restrict__ b, const double* __restrict__ g,
+              double* __restrict__ chi, double half_m_over_k, Pot P, QuadCfg q, GLRule gl, int fold,
+              dsmc_status* st)
+{
+    deflect_lanes<double>(n, b, g, chi, half_m_over_k, P, q, gl, fold, st);
+}
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_deflect_f32(int64_t n, const float* __restrict__ b, const float* __restrict__ g,
+              float* __restrict__ chi, double half_m_over_k, Pot P, QuadCfg q, GLRule gl, int fold,
+              dsmc_status* st)
+{
+    deflect_lanes<float>(n, b, g, chi, half_m_over_k, P, q, gl, fold, st);
+}
+
+template <typename T>
+struct DeflectJob {
+    const T* b;
+    const T* g;
+    T* chi;
+    double half_m_over_k;
+    int fold;
+    __device__ int64_t count(int64_t n) const { return n; }
+    __device__ bool pending(int64_t p) const { return is_pending(chi[p]); }
+    __device__ void inputs(int64_t p, double& bb, double& E) const
+    {
+        const double gg = double(g[p]);
+        bb = double(b[p]) * 1e10;
+        E = half_m_over_k * gg * gg;
+    }
+    __device__ void store(int64_t p, double c) const
+    {
+        chi[p] = T(fold && c == c ? acos(cos(c)) : c);
+    }
+};
+
+// Impact parameter (Angstrom) and E/k_B of accepted pair p, in FP64 from the
+// stored velocities and the pair's latent U4 (b^2 / b_max^2 = 1 - exp(-|z|^2/2) = U4).
+template <typename T>
+__device__ __forceinline__ void pair_b_E(const PairsView& pr, const dsmc_rng& rng, const V3<const T>& v,
+                                         double half_m_over_k, double b_max_A, int64_t p,
+                                         T (&xi)[3], double& bb, double& E)
+{
+    T z[2], u4;
+    const int32_t k = pr.cell[p];
+    const uint32_t a = (uint32_t)(p - pr.off[k]);
+    pair_latents(rng, a, (uint32_t)k, xi, z, u4);
+    const int32_t i = pr.i[p], j = pr.j[p];
+    const double rx = double(v.x[i]) - double(v.x[j]);
+    const double ry = double(v.y[i]) - double(v.y[j]);
+    const double rz = double(v.z[i]) - double(v.z[j]);
+    E = half_m_over_k * (rx * rx + ry * ry + rz * rz);
+    bb = b_max_A * sqrt(double(u4));
+}
+
 // Phase A of the in-step ab initio rule.
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_phaseA_jager(int32_t n_cells, PairsView pr, dsmc_rng rng, V3<const T> v, T half_m_over_k,
-               T b_max_A, Pot P, QuadCfg q, GLRule gl, PairBuf<T> out, dsmc_status* st)
+__device__ __forceinline__ void phaseA_jager_lanes(int32_t n_cells, const PairsView& pr,
+                                                   const dsmc_rng& rng, const V3<const T>& v,
+                                                   double half_m_over_k, double b_max_A,
+                                                   const Pot& P, const QuadCfg& q, const GLRule& gl,
+                                                   const PairBuf<T>& out, dsmc_status* st)
 {
     const int64_t np = pr.total(n_cells);
-    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < np;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = base + (threadIdx.x & 63);
-        const bool active = p < np;
-        T xi[3] = {T(0), T(0), T(0)}, z[2], u4 = T(0);
-        T E = T(1), bb = T(1);
-        if (active) {
-            const int32_t k = pr.cell[p];
-            const uint32_t a = (uint32_t)(p - pr.off[k]);
-            pair_latents(rng, a, (uint32_t)k, xi, z, u4);
-            const int32_t i = pr.i[p], j = pr.j[p];
-            const T rx = v.x[i] - v.x[j], ry = v.y[i] - v.y[j], rz = v.z[i] - v.z[j];
-            const T g2 = rx * rx + ry * ry + rz * rz;
-            E = half_m_over_k * g2;
-            bb = b_max_A * sqrt(u4);  // b^2 / b_max^2 = 1 - exp(-|z|^2/2) = U4
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        T xi[3];
+        double bb, E;
+        pair_b_E<T>(pr, rng, v, half_m_over_k, b_max_A, p, xi, bb, E);
+        bool flag;
+        T c = chi_lane<T>(P, q, gl, bb, E, flag);
+        out.c[p] = xi[0];
+        out.d[p] = xi[1];
+        out.e[p] = xi[2];
+        if (flag && q.refine) {
+            out.a[p] = pending_mark<T>();
+            continue;
         }
-        T c = chi_quad_wave<T>(P, q, gl, bb, E, active);
-        if (!active) continue;
         if (c != c) {
-            if (st) {
-                atomicAdd(&st->root_fail, 1);
-                atomicOr(&st->flags, (uint32_t)DSMC_ST_ROOT_FAIL);
-            }
+            count_root_fail(st);
             c = T(0);  // no deflection for a failed evaluation
         }
         out.a[p] = cos(c);
         out.b[p] = sin(c);
-        out.c[p] = xi[0];
-        out.d[p] = xi[1];
-        out.e[p] = xi[2];
     }
 }
 
+__global__ void __launch_bounds__(256)
+k_phaseA_jager_f64(int32_t n_cells, PairsView pr, dsmc_rng rng, V3<const double> v,
+                   double half_m_over_k, double b_max_A, Pot P, QuadCfg q, GLRule gl,
+                   PairBuf<double> out, dsmc_status* st)
+{
+    phaseA_jager_lanes<double>(n_cells, pr, rng, v, half_m_over_k, b_max_A, P, q, gl, out, st);
+}
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_phaseA_jager_f32(int32_t n_cells, PairsView pr, dsmc_rng rng, V3<const float> v,
+                   double half_m_over_k, double b_max_A, Pot P, QuadCfg q, GLRule gl,
+                   PairBuf<float> out, dsmc_status* st)
+{
+    phaseA_jager_lanes<float>(n_cells, pr, rng, v, half_m_over_k, b_max_A, P, q, gl, out, st);
+}
+
+template <typename T>
+struct PhaseAJagerJob {
+    PairsView pr;
+    dsmc_rng rng;
+    V3<const T> v;
+    double half_m_over_k, b_max_A;
+    PairBuf<T> out;
+    int32_t n_cells;
+    __device__ int64_t count(int64_t n) const
+    {
+        const int64_t np = pr.total(n_cells);
+        return np < n ? np : n;
+    }
+    __device__ bool pending(int64_t p) const { return is_pending(out.a[p]); }
+    __device__ void inputs(int64_t p, double& bb, double& E) const
+    {
+        T xi[3];
+        pair_b_E<T>(pr, rng, v, half_m_over_k, b_max_A, p, xi, bb, E);
+    }
+    __device__ void store(int64_t p, double c) const
+    {
+        if (c != c) c = 0.0;
+        out.a[p] = T(cos(c));
+        out.b[p] = T(sin(c));
+    }
+};
+
 // Harvest rows: targets from the quadrature.
+__device__ __forceinline__ void harvest_target(const double* vr, const double* xi, int64_t r,
+                                               double c, float* tgt, double* chi_out)
+{
+    double vh[3], e[3];
+    const double g = unit3<double>(vr[3 * r], vr[3 * r + 1], vr[3 * r + 2], vh);
+    const double xv[3] = {xi[3 * r], xi[3 * r + 1], xi[3 * r + 2]};
+    perp_dir<double>(xv, vh, e);
+    const double cc = cos(c), sc = sin(c);
+    for (int d = 0; d < 3; ++d) tgt[3 * r + d] = (float)(g * (cc * vh[d] + sc * e[d]));
+    if (chi_out) chi_out[r] = c;
+}
+
+__device__ __forceinline__ void harvest_b_E(const double* vr, const double* z, double b_max_A,
+                                            double half_m_over_k, int64_t r, double& bb, double& E)
+{
+    const double v0 = vr[3 * r], v1 = vr[3 * r + 1], v2 = vr[3 * r + 2];
+    const double z0 = z[2 * r], z1 = z[2 * r + 1];
+    const double bt2 = -expm1(-0.5 * (z0 * z0 + z1 * z1));
+    bb = b_max_A * sqrt(bt2);
+    E = half_m_over_k * (v0 * v0 + v1 * v1 + v2 * v2);
+}
+
 __global__ void __launch_bounds__(256)
 k_harvest(int64_t B, const double* __restrict__ vr, const double* __restrict__ xi,
           const double* __restrict__ z, double inv_sv, double b_max_A, double half_m_over_k,
           Pot P, QuadCfg q, GLRule gl, float* __restrict__ x_out, float* __restrict__ g_out,
           float* __restrict__ tgt, double* __restrict__ chi_out, dsmc_status* st)
 {
-    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < B;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = base + (threadIdx.x & 63);
-        const bool active = r < B;
-        const int64_t rr = active ? r : 0;
-        const double v0 = vr[3 * rr], v1 = vr[3 * rr + 1], v2 = vr[3 * rr + 2];
-        const double x0 = xi[3 * rr], x1 = xi[3 * rr + 1], x2 = xi[3 * rr + 2];
-        const double z0 = z[2 * rr], z1 = z[2 * rr + 1];
-        double vh[3], e[3];
-        const double g = unit3<double>(v0, v1, v2, vh);
-        const double bt2 = -expm1(-0.5 * (z0 * z0 + z1 * z1));
-        const double bb = b_max_A * sqrt(bt2);
-        double c = chi_quad_wave<double>(P, q, gl, bb, half_m_over_k * g * g, active);
-        if (!active) continue;
-        if (c != c) {
-            if (st) {
-                atomicAdd(&st->root_fail, 1);
-                atomicOr(&st->flags, (uint32_t)DSMC_ST_ROOT_FAIL);
-            }
-        }
-        const double xv[3] = {x0, x1, x2};
-        perp_dir<double>(xv, vh, e);
-        const double cc = cos(c), sc = sin(c);
-        for (int d = 0; d < 3; ++d) tgt[3 * r + d] = (float)(g * (cc * vh[d] + sc * e[d]));
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < B;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const double v0 = vr[3 * r], v1 = vr[3 * r + 1], v2 = vr[3 * r + 2];
+        double bb, E;
+        harvest_b_E(vr, z, b_max_A, half_m_over_k, r, bb, E);
         float* xo = x_out + 8 * r;
         xo[0] = (float)(v0 * inv_sv); xo[1] = (float)(v1 * inv_sv); xo[2] = (float)(v2 * inv_sv);
-        xo[3] = (float)x0; xo[4] = (float)x1; xo[5] = (float)x2;
-        xo[6] = (float)z0; xo[7] = (float)z1;
-        g_out[r] = (float)g;
-        if (chi_out) chi_out[r] = c;
+        xo[3] = (float)xi[3 * r]; xo[4] = (float)xi[3 * r + 1]; xo[5] = (float)xi[3 * r + 2];
+        xo[6] = (float)z[2 * r]; xo[7] = (float)z[2 * r + 1];
+        g_out[r] = (float)sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+        bool flag;
+        const double c = chi_lane<double>(P, q, gl, bb, E, flag);
+        if (flag && q.refine) {
+            tgt[3 * r] = pending_mark<float>();
+            continue;
+        }
+        if (c != c) count_root_fail(st);
+        harvest_target(vr, xi, r, c, tgt, chi_out);
     }
+}
+
+struct HarvestJob {
+    const double* vr;
+    const double* xi;
+    const double* z;
+    double b_max_A, half_m_over_k;
+    float* tgt;
+    double* chi_out;
+    __device__ int64_t count(int64_t n) const { return n; }
+    __device__ bool pending(int64_t r) const { return is_pending(tgt[3 * r]); }
+    __device__ void inputs(int64_t r, double& bb, double& E) const
+    {
+        harvest_b_E(vr, z, b_max_A, half_m_over_k, r, bb, E);
+    }
+    __device__ void store(int64_t r, double c) const { harvest_target(vr, xi, r, c, tgt, chi_out); }
+};
+
+template <class Job>
+static int launch_refine(const Job& job, int64_t n, const Pot& P, const QuadCfg& q,
+                         const GLRule& gl, dsmc_status* st, hipStream_t s, const char* what)
+{
+    if (!q.refine || n <= 0) return DSMC_OK;
+    int64_t blocks = (n + 255) / 256;
+    const int pb = persistent_blocks(256);
+    if (blocks > pb) blocks = pb;
+    k_refine<Job><<<(int)blocks, 256, 0, s>>>(job, n, P, q, gl, st);
+    DSMC_LAUNCH_CHECK(what);
+    return DSMC_OK;
 }
 
 }  // namespace dsmc
@@ -598,16 +468,21 @@ extern "C" int dsmc_deflect_jager(int64_t n, int32_t dtype, const void* b, const
     const int pb = persistent_blocks(256);
     if (blocks > pb) blocks = pb;
     if (dtype == DSMC_F64) {
-        k_deflect<double><<<blocks, 256, 0, s>>>(n, (const double*)b, (const double*)g,
+        k_deflect_f64<<<blocks, 256, 0, s>>>(n, (const double*)b, (const double*)g,
                                                  (double*)chi, hmk, P, q, gl, fold, st);
     } else if (dtype == DSMC_F32) {
-        k_deflect<float><<<blocks, 256, 0, s>>>(n, (const float*)b, (const float*)g, (float*)chi,
-                                                (float)hmk, P, q, gl, fold, st);
+        k_deflect_f32<<<blocks, 256, 0, s>>>(n, (const float*)b, (const float*)g, (float*)chi,
+                                                hmk, P, q, gl, fold, st);
     } else {
         return arg_error("dsmc_deflect_jager: dtype %d", dtype);
     }
     DSMC_LAUNCH_CHECK("deflect_jager");
-    return DSMC_OK;
+    if (dtype == DSMC_F64)
+        return launch_refine(DeflectJob<double>{(const double*)b, (const double*)g, (double*)chi,
+                                                hmk, fold},
+                             n, P, q, gl, st, s, "deflect_jager:refine");
+    return launch_refine(DeflectJob<float>{(const float*)b, (const float*)g, (float*)chi, hmk, fold},
+                         n, P, q, gl, st, s, "deflect_jager:refine");
 }
 
 extern "C" int dsmc_collide_jager(int32_t n_cells, int32_t dtype, dsmc_vec3 v, dsmc_pairs pairs,
@@ -633,15 +508,24 @@ extern "C" int dsmc_collide_jager(int32_t n_cells, int32_t dtype, dsmc_vec3 v, d
     const int pb = persistent_blocks(256);
     const double hmk = 0.5 * m_red / KB;
     if (dtype == DSMC_F64) {
-        k_phaseA_jager<double><<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const double>(v), hmk,
+        k_phaseA_jager_f64<<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const double>(v), hmk,
                                                  b_max * 1e10, P, q, gl,
                                                  PairBuf<double>::of(ws, pairs.cap), st);
     } else {
-        k_phaseA_jager<float><<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const float>(v), (float)hmk,
-                                                (float)(b_max * 1e10), P, q, gl,
+        k_phaseA_jager_f32<<<pb, 256, 0, s>>>(n_cells, pr, rng, v3<const float>(v), hmk,
+                                                b_max * 1e10, P, q, gl,
                                                 PairBuf<float>::of(ws, pairs.cap), st);
     }
     DSMC_LAUNCH_CHECK("collide_jager:phaseA");
+    if (dtype == DSMC_F64)
+        rc = launch_refine(PhaseAJagerJob<double>{pr, rng, v3<const double>(v), hmk, b_max * 1e10,
+                                                  PairBuf<double>::of(ws, pairs.cap), n_cells},
+                           pairs.cap, P, q, gl, st, s, "collide_jager:refine");
+    else
+        rc = launch_refine(PhaseAJagerJob<float>{pr, rng, v3<const float>(v), hmk, b_max * 1e10,
+                                                 PairBuf<float>::of(ws, pairs.cap), n_cells},
+                           pairs.cap, P, q, gl, st, s, "collide_jager:refine");
+    if (rc) return rc;
     if (schedule == DSMC_SCHED_DEFER) return DSMC_OK;
     return phase_b(RULE_CHI, dtype, n_cells, nullptr, v, pairs, ws, pairs.cap, schedule, s);
 }
@@ -672,7 +556,8 @@ extern "C" int dsmc_harvest_rows(int64_t B, const double* vr, const double* xi, 
                                                      0.5 * m_red / KB, P, q, gl, x_out, g_out,
                                                      target_out, chi_out, st);
     DSMC_LAUNCH_CHECK("harvest_rows");
-    return DSMC_OK;
+    return launch_refine(HarvestJob{vr, xi, z, b_max * 1e10, 0.5 * m_red / KB, target_out, chi_out},
+                         B, P, q, gl, st, as_stream(stream), "harvest_rows:refine");
 }
 
 // ------------------------------------------------------------------------
@@ -768,7 +653,7 @@ k_q2_terms(int64_t n_items, int n_b, const double* __restrict__ E_kelvin, double
         const double h = b_cut_A / n_panels;
         const double b = h * (pnl + bgl.t[node]);
         const double E = active ? E_kelvin[i] : 1.0;
-        double c = chi_quad_wave<double>(P, q, gl, b, E, active);
+        double c = chi_wave_inplace(P, q, gl, b, E, active);
         if (!active) continue;
         if (c != c) {
             if (st) {

@@ -145,3 +145,31 @@ def test_cavity_fullsize_vhs_fp64(orc, dev, api):
     err = worst / math.sqrt(W.KB * 273.15 / W.AR_MASS)
     say(f"  sampled ranges: velocity rel err {err:.3e}")
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_deflection_batch_fullsize(orc, dev, api, dtype):
+    """The deflection batch at its full size (2^20 pairs, g log-uniform
+    100-20 000 m/s, b^2 uniform on [0, (1 nm)^2]) against the oracle on every
+    pair, FP64 and FP32 (the FP32 kernel against the oracle on the
+    FP32-rounded inputs).  RMS, max, 99.9th percentile and the orbiting
+    pairs (|chi| > pi) are reported separately; bounds as for the 8192-pair
+    case."""
+    import os
+    from test_gpu_parity import check_chi
+    say("deflection batch 2^20", dtype)
+    b, g, mr = W.deflection_batch(seed=2, n=1 << 20)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        b = b.astype(np.float32).astype(np.float64)
+        g = g.astype(np.float32).astype(np.float64)
+    P = orc.potential_jager(W.JAGER_PLACEHOLDER)
+    ref, ost = orc.chi_batch(P, b, g, mr, n_threads=min(16, os.cpu_count() or 1))
+    assert np.all(ost == 0)
+    st = api.new_status(dev)
+    chi = api.deflect_jager(torch.as_tensor(b, dtype=tdt, device=dev),
+                            torch.as_tensor(g, dtype=tdt, device=dev), mr,
+                            api.potential_jager(W.JAGER_PLACEHOLDER), st=st)
+    got = chi.double().cpu().numpy()
+    assert api.read_status(st).root_fail == 0 and np.all(np.isfinite(got))
+    check_chi(got, ref, dtype, "batch 2^20")

@@ -391,21 +391,49 @@ def test_deflect_closed_forms(dev, api):
 
 
 def _chi_stats(got, ref):
+    """|theta_got - theta_ref| with theta = arccos(cos chi) in [0, pi] (the
+    folded angle the error metrics use)."""
     d = np.abs(np.arccos(np.clip(np.cos(got), -1, 1)) - np.arccos(np.clip(np.cos(ref), -1, 1)))
+    return d
+
+
+# Bounds on the deflection angle against the oracle (theta, rad).
+#  FP64: 1e-9 where the deflection stays within one half-turn (|chi| <= pi);
+#    1e-7 on orbiting pairs (|chi| > pi), where chi ~ -ln D(r_m) and the
+#    FP64 rounding of D near its minimum (~1e-15 of V/E ~ 10) is amplified by
+#    1 / D(r_m); RMS over all pairs 1e-9.
+#  FP32: 1e-4 (F is formed in FP32 from terms up to |V|/E ~ 10 at the
+#    lowest energies, ~1e-6 absolute), RMS 1e-5.  Pairs with a sharp
+#    integrand peak (most orbiting pairs) are re-evaluated in FP64 by the
+#    refinement pass; orbiting pairs with a milder peak keep the FP32 rule,
+#    so the orbiting bound is the FP32 one.
+CHI_TOL = {"f64": dict(tame=1e-9, orbit=1e-7, rms=1e-9),
+           "f32": dict(tame=1e-4, orbit=1e-4, rms=1e-5)}
+
+
+def check_chi(got, ref, kind, label):
+    d = _chi_stats(got, ref)
+    tame = np.abs(ref) <= np.pi
+    rms = float(np.sqrt(np.mean(d * d)))
+    orb = d[~tame].max() if (~tame).any() else 0.0
+    say(f"  {label}: theta err rms={rms:.3e} max={d.max():.3e} p99.9={np.percentile(d, 99.9):.3e}; "
+        f"|chi|<=pi ({tame.sum()} of {len(d)}): max={d[tame].max():.3e}; "
+        f"orbiting ({(~tame).sum()}): max={orb:.3e}")
+    t = CHI_TOL[kind]
+    assert d[tame].max() < t["tame"] and orb < t["orbit"] and rms < t["rms"]
     return d
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_deflect_jager_against_oracle(orc, dev, api, dtype):
     """chi of the GPU quadrature against the oracle's (Brent + adaptive
-    Gauss-Kronrod) on the deflection-batch distribution.  Bounds: pairs whose
-    deflection stays within one half-turn (|chi| <= pi, i.e. away from
-    orbiting) to 1e-9 (FP64) / 1e-3 (FP32) rad in theta = arccos(cos chi);
-    all pairs, orbiting included (|chi| > pi: the integrand has a sharp peak
-    and both quadratures are least accurate there), to an RMS of 5e-5 (FP64)
-    / 2e-4 (FP32)."""
+    Gauss-Kronrod) on the deflection-batch distribution, 8192 pairs.  The
+    FP32 kernel is compared with the oracle on the FP32-rounded inputs."""
     say("deflect jager", dtype)
     b, g, mr = W.deflection_batch(seed=21, n=8192)
+    if dtype == torch.float32:
+        b = b.astype(np.float32).astype(np.float64)
+        g = g.astype(np.float32).astype(np.float64)
     P = orc.potential_jager(W.JAGER_PLACEHOLDER)
     ref, ost = orc.chi_batch(P, b, g, mr, n_threads=8)
     st = api.new_status(dev)
@@ -415,52 +443,68 @@ def test_deflect_jager_against_oracle(orc, dev, api, dtype):
     got = chi.double().cpu().numpy()
     s = api.read_status(st)
     assert s.root_fail == 0 and np.all(np.isfinite(got))
-    d = _chi_stats(got, ref)
-    tame = np.abs(ref) <= np.pi
-    rms = float(np.sqrt(np.mean(d * d)))
-    say(f"  theta err all: rms={rms:.3e} max={d.max():.3e} p99.9={np.percentile(d, 99.9):.3e}; "
-        f"|chi|<=pi ({tame.sum()} of {len(d)}): max={d[tame].max():.3e}; "
-        f"orbiting (|chi|>pi): max={d[~tame].max() if (~tame).any() else 0:.3e}")
-    if dtype == torch.float64:
-        assert d[tame].max() < 1e-9 and rms < 5e-5
-    else:
-        assert d[tame].max() < 1e-3 and rms < 2e-4
+    check_chi(got, ref, "f64" if dtype == torch.float64 else "f32", "batch 8192")
 
 
-def test_collide_jager_step(orc, dev, api):
+def test_deflect_refinement_off_is_worse(orc, dev, api):
+    """With the FP64 refinement switched off every pair keeps the one-rule
+    result: the orbiting pairs (sharp integrand peaks) then miss the bound the
+    refined kernel meets, which shows the refinement is what meets it."""
+    say("deflect jager, refinement off")
+    b, g, mr = W.deflection_batch(seed=21, n=8192)
+    P = orc.potential_jager(W.JAGER_PLACEHOLDER)
+    ref, _ = orc.chi_batch(P, b, g, mr, n_threads=8)
+    chi = api.deflect_jager(torch.as_tensor(b, device=dev), torch.as_tensor(g, device=dev), mr,
+                            api.potential_jager(W.JAGER_PLACEHOLDER),
+                            quad=api.quad_struct(64, refine=-1))
+    d = _chi_stats(chi.cpu().numpy(), ref)
+    say(f"  refine off: max {d.max():.3e}")
+    assert d.max() > CHI_TOL["f64"]["orbit"]
+
+
+@pytest.mark.parametrize("dtype,T", [(torch.float64, 2000.0), (torch.float64, 200.0),
+                                     (torch.float32, 200.0), (torch.float32, 2000.0)])
+def test_collide_jager_step(orc, dev, api, dtype, T):
     """In-step ab initio rule: chi per accepted pair against the oracle's
-    quadrature (stated), then Phase B from the GPU's angles against the
-    oracle's rotation + pair update (1e-12), and exact conservation."""
-    say("collide jager in-step")
-    pop = W.ragged_population(15, 120, 120, xs="const", T=2000.0)
-    cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, torch.float64, seed=4, step=2)
+    quadrature on the same (b, g) (bounds as for the batch), then Phase B
+    from the GPU's angles against the oracle's rotation + pair update (1e-12
+    FP64 / 1e-5 FP32 of the velocity scale), and exact conservation.  At
+    200 K most pairs lie below the orbiting energy."""
+    say("collide jager in-step", dtype, T)
+    lowp = dtype == torch.float32
+    pop = W.ragged_population(15, 120, 120, xs="const", T=T)
+    cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, dtype, seed=4, step=2)
     vn = vs.clone()
     pot = api.potential_jager(W.JAGER_PLACEHOLDER)
     ws = api.collide_ws(pairs.cap, vn)
     api.collide_jager(vn, pairs, 4, 2, W.AR_MASS / 2, W.B_MAX, pot, ws=ws, st=st)
     n = int(sel["pair_cnt"].sum())
-    buf = ws[: 6 * (pairs.cap + 1) * 8].view(torch.float64).view(6, pairs.cap + 1)[:, :n].cpu().numpy()
+    es = 4 if lowp else 8
+    buf = ws[: 6 * (pairs.cap + 1) * es].view(dtype).view(6, pairs.cap + 1)[:, :n].double()
+    buf = buf.cpu().numpy()
     cc, sc, xi = buf[0], buf[1], buf[2:5].T.copy()
-    U, oxi, z = orc.pair_latents(sel, 4, 2)
-    np.testing.assert_allclose(xi, oxi, rtol=1e-13, atol=1e-13)
+    U, oxi, z = orc.pair_latents(sel, 4, 2, lowp=lowp)
+    np.testing.assert_allclose(xi, oxi, rtol=1e-6 if lowp else 1e-13, atol=1e-6 if lowp else 1e-13)
     vr = v64[:, sel["pair_i"]] - v64[:, sel["pair_j"]]
     g = np.sqrt(np.sum(vr * vr, axis=0))
     P = orc.potential_jager(W.JAGER_PLACEHOLDER)
     ref, _ = orc.chi_batch(P, W.B_MAX * np.sqrt(U[:, 4]), g, W.AR_MASS / 2, n_threads=8)
-    d = np.abs(np.arctan2(sc, cc) - np.arctan2(np.sin(ref), np.cos(ref)))
-    d = np.minimum(d, 2 * np.pi - d)
-    tame = np.abs(ref) <= np.pi
-    say(f"  in-step chi: |chi|<=pi max {d[tame].max():.3e}, all rms {np.sqrt(np.mean(d*d)):.3e}")
-    assert d[tame].max() < 1e-9
+    E = 0.5 * (W.AR_MASS / 2) * g * g / W.KB
+    say(f"  {n} pairs, {np.mean(E < 290.0) * 100:.0f}% below the orbiting energy")
+    check_chi(np.arctan2(sc, cc), ref, "f32" if lowp else "f64", "in-step chi")
+    assert api.read_status(st).root_fail == 0
     vref = orc.apply_chi(sel, v64, cc, sc, xi)
-    err = np.max(np.abs(vn.cpu().numpy() - vref)) / np.max(np.abs(v64))
+    scale = np.max(np.abs(v64))
+    err = np.max(np.abs(vn.double().cpu().numpy() - vref)) / scale
     say(f"  phase B from GPU angles: rel err {err:.3e}")
-    assert err < 1e-12
-    got = vn.cpu().numpy()
-    ocs = cs.cpu().numpy()
-    for k in range(pop.n_cells):
-        a_, b_ = ocs[k], ocs[k + 1]
-        np.testing.assert_allclose(np.sum(got[:, a_:b_] ** 2), np.sum(v64[:, a_:b_] ** 2), rtol=1e-12)
+    assert err < (1e-5 if lowp else 1e-12)
+    if not lowp:
+        got = vn.cpu().numpy()
+        ocs = cs.cpu().numpy()
+        for k in range(pop.n_cells):
+            a_, b_ = ocs[k], ocs[k + 1]
+            np.testing.assert_allclose(np.sum(got[:, a_:b_] ** 2), np.sum(v64[:, a_:b_] ** 2),
+                                       rtol=1e-12)
 
 
 # ---------------------------------------------------------------------------
