@@ -358,6 +358,15 @@ int dsmc_moment_match_backward(int32_t n_cells, const int32_t* cell_start, const
 int dsmc_mse_loss(int64_t B, const float* vr_new, const float* vr_target, double sigma_v,
                   float* dL_dvr, double* loss, dsmc_stream_t stream);
 
+/* MSE on the scattering directions (section "Neural Surrogate Training":
+ * the surrogate's loss on the scattering directions): with g = |v_r'*|,
+ * L = (1/B) sum |v_r' - v_r'*|^2 / (4 g^2) = (1/B) sum |u - u*|^2 / 4, the
+ * velocity MSE above with each pair normalised by its own g^2; writes dL/dv_r'
+ * and adds L to *loss.  Rows with v_r'* = 0 contribute nothing.  Arrays FP32
+ * [B][3]. */
+int dsmc_direction_loss(int64_t B, const float* vr_new, const float* vr_target, float* dL_dvr,
+                        double* loss, dsmc_stream_t stream);
+
 /* Adam (Kingma & Ba 2015) with bias correction on FP32 master parameters;
  * also writes the bf16 copy used by the MFMA forward when param_bf16 != NULL.
  * lr comes from the cosine schedule the caller evaluates. */

@@ -499,6 +499,22 @@ def surrogate_loss_grad(vr_new, vr_target, sigma_v):
     return d / (2.0 * sigma_v ** 2 * d.shape[0])
 
 
+def direction_loss(vr_new, vr_target):
+    """MSE on the scattering directions (section "Neural Surrogate Training"
+    names the surrogate's loss as one on the scattering directions): with
+    u = v_r'/g and g = |v_r'*| = |v_r'|, (1/B) sum |u - u*|^2 / 4, i.e. the
+    velocity MSE with each pair normalised by its own g^2 instead of sigma_v^2."""
+    d = vr_new - vr_target
+    g2 = np.sum(vr_target * vr_target, axis=1)
+    return float(np.sum(np.sum(d * d, axis=1) / (4.0 * g2)) / d.shape[0])
+
+
+def direction_loss_grad(vr_new, vr_target):
+    d = vr_new - vr_target
+    g2 = np.sum(vr_target * vr_target, axis=1)
+    return d / (2.0 * g2[:, None] * d.shape[0])
+
+
 def project_backward(G, y, g):
     """dL/dy from dL/dv_r' for v_r' = g y/|y|: (g/|y|)(G - (G.u) u)."""
     n = np.linalg.norm(y, axis=1)

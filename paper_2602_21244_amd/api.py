@@ -335,6 +335,12 @@ def moment_match_backward(cell_start, mom_pre, v_post, G, stream=None):
     return out
 
 
+def direction_loss(vr_new, vr_target, dL_dvr, loss, stream=None):
+    check(lib().dsmc_direction_loss(int(vr_new.shape[0]), _ptr(vr_new), _ptr(vr_target),
+                                    _ptr(dL_dvr), _ptr(loss), _stream(stream)),
+          "dsmc_direction_loss")
+
+
 def mse_loss(vr_new, vr_target, sigma_v, dL_dvr, loss, stream=None):
     check(lib().dsmc_mse_loss(int(vr_new.shape[0]), _ptr(vr_new), _ptr(vr_target),
                               float(sigma_v), _ptr(dL_dvr), _ptr(loss), _stream(stream)),

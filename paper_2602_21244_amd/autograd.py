@@ -1,5 +1,6 @@
-"""torch.autograd.Function around the hand-written forward/backward kernels of
-the surrogate (rows form: x -> y = f_theta(x) -> v_r' = g y/|y|)."""
+"""torch.autograd.Function wrappers around the hand-written forward/backward
+kernels of the surrogate (rows form: x -> y = f_theta(x) -> v_r' = g y/|y|)
+and of the cell-wise moment matching (v -> u_pre + alpha (v - u_post))."""
 from __future__ import annotations
 
 import torch
@@ -11,7 +12,9 @@ class SurrogateFn(torch.autograd.Function):
     """y_raw, vr' = f(x, g; theta).  The parameters enter through `net` (its
     device weights); the returned gradients are for the tensors in `params`
     (one W and one b per layer, in order), which must be the FP32 (BF16 net) or
-    FP64 (FP64 net) master copies of net's weights."""
+    FP64 (FP64 net) master copies of net's weights.  Only vr' is
+    differentiable: y_raw is returned for inspection (the backward kernel
+    takes dL/dvr' and forms the projection adjoint itself)."""
 
     @staticmethod
     def forward(ctx, x, g, net, *params):
@@ -20,7 +23,7 @@ class SurrogateFn(torch.autograd.Function):
         ctx.net = net
         ctx.save_for_backward(x, g, y)
         ctx.act = act
-        ctx.param_shapes = [p.shape for p in params]
+        ctx.mark_non_differentiable(y)
         return vr, y
 
     @staticmethod
@@ -41,3 +44,28 @@ class SurrogateFn(torch.autograd.Function):
 
 def surrogate(net, x, g, params):
     return SurrogateFn.apply(x, g, net, *params)
+
+
+class MomentMatchFn(torch.autograd.Function):
+    """Centred cell-wise moment matching (eq. cell_energy_clamp, centred
+    reading) of FP64 SoA velocities v[3][n] in cell-sorted order: each cell
+    with N >= 2 and S_post > 0 becomes u_pre + alpha (v - u_post), alpha =
+    sqrt(S_pre / S_post), with the pre-collision moments `mom_pre` (from
+    dsmc_moment_match CAPTURE) held fixed.  The backward is the adjoint
+    kernel dsmc_moment_match_backward."""
+
+    @staticmethod
+    def forward(ctx, v_post, cell_start, mom_pre):
+        out = v_post.detach().clone().contiguous()
+        api.moment_match(cell_start, out, mom_pre, api.L.MM_APPLY)
+        ctx.save_for_backward(v_post.detach().contiguous(), cell_start, mom_pre)
+        return out
+
+    @staticmethod
+    def backward(ctx, G):
+        v_post, cs, mom = ctx.saved_tensors
+        return api.moment_match_backward(cs, mom, v_post, G.contiguous()), None, None
+
+
+def moment_match(v_post, cell_start, mom_pre):
+    return MomentMatchFn.apply(v_post, cell_start, mom_pre)

@@ -3,6 +3,13 @@
 //
 // BF16 path: one fused kernel evaluates the whole MLP on the matrix cores
 // (v_mfma_f32_32x32x16_bf16, FP32 accumulation) for 32-row tiles per wave.
+// Weights are bf16; every activation (and the network input) enters the
+// matrix cores as a bf16 pair hi + lo (hi = bf16(h), lo = bf16(h - hi), 16
+// significant bits), two MFMAs on the same weight fragment.  A trained
+// network's output y can be much shorter than its terms (|y| ~ 0.01 against
+// O(1) contributions), and u = y/|y| then turns single-bf16 rounding of the
+// activations into direction errors of ~0.03 rad; with the pair the result
+// is that of the bf16 weights to ~1e-4 rad.
 // Each layer is computed transposed, D = W * H^T, so a wave's accumulators
 // hold, for its 32 rows, the layer's outputs in the MFMA result layout; after
 // the activation they are converted to bf16 and used directly as the B operand
@@ -212,13 +219,18 @@ __device__ __forceinline__ bf16x8 lds_frag(const __bf16* wl, int off, int frag, 
 // Row mapping of accumulator register r for lane-half h.
 __device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
+// Activation of 8 accumulator values as a bf16 pair: hi = bf16(v), lo =
+// bf16(v - hi).
 template <int ACT>
-__device__ __forceinline__ bf16x8 to_frag(const floatx16& a, int jp)
+__device__ __forceinline__ void to_frag(const floatx16& a, int jp, bf16x8& hi, bf16x8& lo)
 {
-    bf16x8 o;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) o[e] = (__bf16)act_scaled<ACT>(a[8 * jp + e]);
-    return o;
+    for (int e = 0; e < 8; ++e) {
+        const float v = act_scaled<ACT>(a[8 * jp + e]);
+        const __bf16 h = (__bf16)v;
+        hi[e] = h;
+        lo[e] = (__bf16)(v - (float)h);
+    }
 }
 
 struct RowsIO {
@@ -240,7 +252,8 @@ template <typename VT> struct PairsIO {
 
 // Box-Muller on the hardware transcendentals (v_log_f32 is log2, v_sin_f32
 // and v_cos_f32 take revolutions, so sin(2 pi u) needs no scaling): used for
-// the latents of the bf16 network only, whose inputs are rounded to bf16.
+// the latents of the bf16 network only, whose inputs carry 16 significant
+// bits (a bf16 pair), far above the ~1 ulp of these FP32 instructions.
 __device__ __forceinline__ void box_muller_hw(float ua, float ub, float& n1, float& n2)
 {
     const float R = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(1.0f - ua));
@@ -268,11 +281,11 @@ __device__ __forceinline__ void layer_step(const __bf16* wl, int off, int ksl,
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-        bf16x8 b0[NT], b1[NT];
+        bf16x8 b0[NT], b1[NT], c0[NT], c1[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            b0[t] = to_frag<ACT>(acc[t][nb], 0);
-            b1[t] = to_frag<ACT>(acc[t][nb], 1);
+            to_frag<ACT>(acc[t][nb], 0, b0[t], c0[t]);
+            to_frag<ACT>(acc[t][nb], 1, b1[t], c1[t]);
         }
 #pragma unroll
         for (int nb2 = 0; nb2 < NBO; ++nb2) {
@@ -281,7 +294,9 @@ __device__ __forceinline__ void layer_step(const __bf16* wl, int off, int ksl,
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0[t], nxt[t][nb2], 0, 0, 0);
+                nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, c0[t], nxt[t][nb2], 0, 0, 0);
                 nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[t], nxt[t][nb2], 0, 0, 0);
+                nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, c1[t], nxt[t][nb2], 0, 0, 0);
             }
         }
     }
@@ -355,7 +370,7 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
          grp += gstride) {
         int64_t row[NT];
         bool valid[NT];
-        bf16x8 bin[NT][2];
+        float xin[NT][2][8];  // c x of the first two k steps (1 in the bias slots)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             row[t] = (grp * NT + t) * 32 + col;
@@ -363,11 +378,11 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) bin[t][q][e] = (__bf16)0.0f;
+                for (int e = 0; e < 8; ++e) xin[t][q][e] = 0.0f;
             if (PAIRS) {
                 if (h == 1) {
-                    bin[t][0][5] = (__bf16)1.0f;
-                    bin[t][0][6] = (__bf16)1.0f;
+                    xin[t][0][5] = 1.0f;
+                    xin[t][0][6] = 1.0f;
                 }
                 if (valid[t] && sizeof(VT) == 4) {
                     // FP32 latents: the xi draw (slot 2) and the z draw
@@ -383,17 +398,17 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     box_muller_hw(unif24(rr.a), unif24(rr.b), n0, n1);
                     box_muller_hw(unif24(rr.c), unif24(rr.d), n2, spare);
                     if (h == 0) {
-                        bin[t][0][0] = (__bf16)(C * n0);
-                        bin[t][0][1] = (__bf16)(C * n1);
-                        bin[t][0][2] = (__bf16)(C * n2);
+                        xin[t][0][0] = C * n0;
+                        xin[t][0][1] = C * n1;
+                        xin[t][0][2] = C * n2;
                     } else {
                         const int32_t i = pf_i[t], j = pf_j[t];
                         const VT isv = (VT)d.inv_sigma_v;
-                        bin[t][0][0] = (__bf16)(C * (float)((pio.v.x[i] - pio.v.x[j]) * isv));
-                        bin[t][0][1] = (__bf16)(C * (float)((pio.v.y[i] - pio.v.y[j]) * isv));
-                        bin[t][0][2] = (__bf16)(C * (float)((pio.v.z[i] - pio.v.z[j]) * isv));
-                        bin[t][0][3] = (__bf16)(C * n0);
-                        bin[t][0][4] = (__bf16)(C * n1);
+                        xin[t][0][0] = C * (float)((pio.v.x[i] - pio.v.x[j]) * isv);
+                        xin[t][0][1] = C * (float)((pio.v.y[i] - pio.v.y[j]) * isv);
+                        xin[t][0][2] = C * (float)((pio.v.z[i] - pio.v.z[j]) * isv);
+                        xin[t][0][3] = C * n0;
+                        xin[t][0][4] = C * n1;
                     }
                 } else if (valid[t]) {
                     const int64_t r = row[t];
@@ -402,19 +417,19 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     if (h == 0) {
                         VT xi[3];
                         latents_xi(pio.rng, a, (uint32_t)k, xi);
-                        bin[t][0][0] = (__bf16)(C * (float)xi[0]);
-                        bin[t][0][1] = (__bf16)(C * (float)xi[1]);
-                        bin[t][0][2] = (__bf16)(C * (float)xi[2]);
+                        xin[t][0][0] = C * (float)xi[0];
+                        xin[t][0][1] = C * (float)xi[1];
+                        xin[t][0][2] = C * (float)xi[2];
                     } else {
                         VT z[2], u4;
                         latents_z(pio.rng, a, (uint32_t)k, z, u4);
                         const int32_t i = pf_i[t], j = pf_j[t];
                         const VT isv = (VT)d.inv_sigma_v;
-                        bin[t][0][0] = (__bf16)(C * (float)((pio.v.x[i] - pio.v.x[j]) * isv));
-                        bin[t][0][1] = (__bf16)(C * (float)((pio.v.y[i] - pio.v.y[j]) * isv));
-                        bin[t][0][2] = (__bf16)(C * (float)((pio.v.z[i] - pio.v.z[j]) * isv));
-                        bin[t][0][3] = (__bf16)(C * (float)z[0]);
-                        bin[t][0][4] = (__bf16)(C * (float)z[1]);
+                        xin[t][0][0] = C * (float)((pio.v.x[i] - pio.v.x[j]) * isv);
+                        xin[t][0][1] = C * (float)((pio.v.y[i] - pio.v.y[j]) * isv);
+                        xin[t][0][2] = C * (float)((pio.v.z[i] - pio.v.z[j]) * isv);
+                        xin[t][0][3] = C * (float)z[0];
+                        xin[t][0][4] = C * (float)z[1];
                     }
                 }
             } else {
@@ -425,9 +440,9 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     for (int e = 0; e < 8; ++e) {
                         const int c = 16 * q + 8 * h + e;
                         if (c < din) {
-                            if (valid[t]) bin[t][q][e] = (__bf16)(C * rio.x[row[t] * din + c]);
+                            if (valid[t]) xin[t][q][e] = C * rio.x[row[t] * din + c];
                         } else if (c < din + 2) {
-                            bin[t][q][e] = (__bf16)1.0f;
+                            xin[t][q][e] = 1.0f;
                         }
                     }
             }
@@ -435,22 +450,37 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
 
         if (PAIRS) prefetch(grp + gstride);
 
-        // input layer: s = W (c x) + c b
+        // input layer: s = W (c x) + c b, each input as a bf16 pair
+        bf16x8 bin[NT][2], blo[NT][2];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const __bf16 hb = (__bf16)xin[t][q][e];
+                    bin[t][q][e] = hb;
+                    blo[t][q][e] = (__bf16)(xin[t][q][e] - (float)hb);
+                }
         floatx16 acc[NT][NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const bf16x8 a = lds_frag(wl, f.off[0], nb * f.ks[0], lane);
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NT; ++t) {
                 acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bin[t][0], zero, 0, 0, 0);
+                acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[t][0], acc[t][nb], 0, 0, 0);
+            }
         }
         if (f.ks[0] > 1) {
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const bf16x8 a = lds_frag(wl, f.off[0], nb * f.ks[0] + 1, lane);
 #pragma unroll
-                for (int t = 0; t < NT; ++t)
+                for (int t = 0; t < NT; ++t) {
                     acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bin[t][1], acc[t][nb], 0, 0, 0);
+                    acc[t][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[t][1], acc[t][nb], 0, 0, 0);
+                }
             }
         }
         // hidden layers, two at a time so the accumulators alternate
@@ -1095,6 +1125,39 @@ k_mse(int64_t B, const float* __restrict__ a, const float* __restrict__ t, doubl
     }
 }
 
+// MSE on the scattering directions: each pair's term and gradient are
+// normalised by its own g^2 = |v_r'*|^2.  Single workgroup, fixed order.
+__global__ void __launch_bounds__(1024)
+k_dir_loss(int64_t B, const float* __restrict__ a, const float* __restrict__ t,
+           float* __restrict__ grad, double* loss)
+{
+    __shared__ double red[16];
+    double acc = 0.0;
+    const double invB = 1.0 / (double)B;
+    for (int64_t r = threadIdx.x; r < B; r += blockDim.x) {
+        double d[3], g2 = 0.0, dd = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double tv = (double)t[3 * r + c];
+            d[c] = (double)a[3 * r + c] - tv;
+            g2 += tv * tv;
+            dd += d[c] * d[c];
+        }
+        const double w = g2 > 0.0 ? 1.0 / g2 : 0.0;
+        acc += 0.25 * dd * w;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) grad[3 * r + c] = (float)(0.5 * d[c] * w * invB);
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
+        *loss += sum * invB;
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_adam(int64_t n, float* __restrict__ p, __bf16* __restrict__ pb, const float* __restrict__ g,
        float* __restrict__ m, float* __restrict__ v, float b1, float b2, float lr_c, float eps_c,
@@ -1335,6 +1398,16 @@ extern "C" int dsmc_mse_loss(int64_t B, const float* vr_new, const float* vr_tar
     const double scale = 1.0 / (4.0 * sigma_v * sigma_v * (double)B);
     k_mse<<<1, 1024, 0, as_stream(stream)>>>(B, vr_new, vr_target, scale, dL_dvr, loss);
     DSMC_LAUNCH_CHECK("mse");
+    return DSMC_OK;
+}
+
+extern "C" int dsmc_direction_loss(int64_t B, const float* vr_new, const float* vr_target,
+                                   float* dL_dvr, double* loss, dsmc_stream_t stream)
+{
+    if (B < 1 || !vr_new || !vr_target || !dL_dvr || !loss)
+        return arg_error("dsmc_direction_loss: bad arguments");
+    k_dir_loss<<<1, 1024, 0, as_stream(stream)>>>(B, vr_new, vr_target, dL_dvr, loss);
+    DSMC_LAUNCH_CHECK("direction_loss");
     return DSMC_OK;
 }
 

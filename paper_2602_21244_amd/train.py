@@ -3,11 +3,16 @@
 Data ("physics harvesting" on synthetic pairs): rows (v_r, xi, z) with g
 log-uniform on [100, 20000] m/s and isotropic direction; dsmc_harvest_rows
 computes chi(b(z), g) by the quadrature kernel and the target post-collision
-relative velocity.  Each step: forward (MFMA), MSE on the post-collision
-velocities, hand-written backward, Adam with a cosine learning-rate schedule
-decaying to 1e-6 (section "Neural Surrogate Training").
+relative velocity.  Each step: forward (MFMA), the loss, hand-written
+backward, Adam with a cosine learning-rate schedule decaying to 1e-6
+(section "Neural Surrogate Training").  Loss "direction" (default): the MSE
+on the scattering directions, each pair normalised by its own g^2;
+"velocity": the MSE on the post-collision velocities normalised by
+sigma_v^2, which weights a pair by (g / sigma_v)^2 and so leaves the
+directions of slow pairs (most pairs of a 200 K gas) nearly untrained.
 
-    python -m paper_2602_21244_amd.train --steps 4000 --out weights/jager_surrogate_8x128x4.npz
+    python -m paper_2602_21244_amd.train --steps 60000 --pool 4194304 \
+        --out weights/jager_surrogate_8x128x4.npz
 """
 from __future__ import annotations
 
@@ -47,7 +52,7 @@ def direction_error(vr_pred, vr_tgt):
 
 
 def train(steps=4000, batch=65536, pool=1 << 20, lr=2e-3, seed=4, dims=None, out=None,
-          log_every=200, dev=None):
+          log_every=200, dev=None, loss_kind="direction"):
     sys.path.insert(0, os.path.dirname(HERE))
     import workloads as W
 
@@ -82,7 +87,10 @@ def train(steps=4000, batch=65536, pool=1 << 20, lr=2e-3, seed=4, dims=None, out
         xb, gb, tb = x[idx].contiguous(), g[idx].contiguous(), tgt[idx].contiguous()
         y, vr = api.neural_forward_rows(net, xb, gb, act_save=act)
         loss.zero_()
-        api.mse_loss(vr, tb, sigma_v, dvr, loss)
+        if loss_kind == "direction":
+            api.direction_loss(vr, tb, dvr, loss)
+        else:
+            api.mse_loss(vr, tb, sigma_v, dvr, loss)
         dW = grads[0::2]
         db = grads[1::2]
         api.neural_backward(net, xb, act, y, gb, dvr, dW, db, ws=bws)
@@ -104,7 +112,9 @@ def train(steps=4000, batch=65536, pool=1 << 20, lr=2e-3, seed=4, dims=None, out
     if out:
         os.makedirs(os.path.dirname(out), exist_ok=True)
         arrs = {"n_layers": np.int64(len(net.W)), "sigma_v": np.float64(sigma_v),
-                "dims": np.array(dims, np.int64), "history": np.array(hist)}
+                "dims": np.array(dims, np.int64), "history": np.array(hist),
+                "steps": np.int64(steps), "lr": np.float64(lr), "pool": np.int64(pool),
+                "loss": np.array(loss_kind)}
         for l in range(len(net.W)):
             arrs[f"W{l}"] = master[2 * l].double().cpu().numpy()
             arrs[f"b{l}"] = master[2 * l + 1].double().cpu().numpy()
@@ -120,9 +130,10 @@ def main():
     p.add_argument("--pool", type=int, default=1 << 20)
     p.add_argument("--lr", type=float, default=2e-3)
     p.add_argument("--seed", type=int, default=4)
+    p.add_argument("--loss", default="direction", choices=["direction", "velocity"])
     p.add_argument("--out", default=os.path.join(HERE, "weights", "jager_surrogate_8x128x4.npz"))
     a = p.parse_args()
-    train(a.steps, a.batch, a.pool, a.lr, a.seed, out=a.out)
+    train(a.steps, a.batch, a.pool, a.lr, a.seed, out=a.out, loss_kind=a.loss)
 
 
 if __name__ == "__main__":

@@ -611,17 +611,21 @@ def test_backward_fp64_against_oracle(orc, dev, api):
     assert np.max(np.abs(dx.cpu().numpy() - rx)) <= 1e-10 * np.abs(rx).max()
 
 
-def test_backward_bf16_bound(orc, dev, api):
-    say("backward bf16")
-    rows = W.training_rows(seed=8, n=4096)
+@pytest.mark.parametrize("B", [4096, 65536])
+def test_backward_bf16_bound(orc, dev, api, B):
+    """BF16 weight gradients against FP64 gradients of the same bf16-rounded
+    weights; B = 65 536 is the training batch (the weight-gradient GEMMs then
+    split K = B into 128 partial sums)."""
+    say("backward bf16", B)
+    rows = W.training_rows(seed=8, n=B)
     Ws, bs = _net_params(7, W.SURROGATE_DIMS)
     net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=rows["sigma_v"], device=dev)
     x = orc.network_input(rows["vr"], rows["xi"], rows["z"], rows["sigma_v"])
     rng = np.random.default_rng(4)
-    target = rng.normal(size=(4096, 3)) * rows["g"][:, None]
+    target = rng.normal(size=(B, 3)) * rows["g"][:, None]
     xt = torch.as_tensor(x, dtype=torch.float32, device=dev)
     gt = torch.as_tensor(rows["g"], dtype=torch.float32, device=dev)
-    act = api.workspace(api.neural_act_bytes(net, 4096), dev)
+    act = api.workspace(api.neural_act_bytes(net, B), dev)
     y, vr = api.neural_forward_rows(net, xt, gt, act_save=act)
     G = orc.surrogate_loss_grad(vr.double().cpu().numpy(), target, rows["sigma_v"])
     dW = [torch.zeros(w.shape, dtype=torch.float32, device=dev) for w in net.W]
@@ -638,7 +642,7 @@ def test_backward_bf16_bound(orc, dev, api):
 
 
 def test_training_helpers(orc, dev, api):
-    say("mse, adam, moment-match adjoint, harvest")
+    say("mse, direction loss, adam, moment-match adjoint, harvest")
     rng = np.random.default_rng(5)
     a = rng.normal(size=(1000, 3))
     t = rng.normal(size=(1000, 3))
@@ -649,6 +653,17 @@ def test_training_helpers(orc, dev, api):
     af, tf = a.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
     np.testing.assert_allclose(loss.item(), orc.surrogate_loss(af, tf, 2.0), rtol=1e-12)
     np.testing.assert_allclose(grad.cpu().numpy(), orc.surrogate_loss_grad(af, tf, 2.0), rtol=1e-6)
+    # direction loss (per-pair g^2 normalisation), 70 001 rows over several waves
+    a = rng.normal(size=(70001, 3)) * 300.0
+    t = rng.normal(size=(70001, 3)) * 10 ** rng.uniform(2, 4, (70001, 1))
+    grad = torch.zeros(70001, 3, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    api.direction_loss(torch.as_tensor(a, dtype=torch.float32, device=dev),
+                       torch.as_tensor(t, dtype=torch.float32, device=dev), grad, loss)
+    af, tf = a.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
+    np.testing.assert_allclose(loss.item(), orc.direction_loss(af, tf), rtol=1e-12)
+    np.testing.assert_allclose(grad.cpu().numpy(), orc.direction_loss_grad(af, tf), rtol=1e-6,
+                               atol=1e-12)
     p = rng.normal(size=500)
     gr = rng.normal(size=500)
     pt = torch.as_tensor(p, dtype=torch.float32, device=dev)

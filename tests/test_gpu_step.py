@@ -183,14 +183,56 @@ def test_autograd_function_matches_direct_calls(orc, dev, api):
     np.testing.assert_allclose(x.grad.cpu().numpy(), rx, rtol=1e-9, atol=1e-14)
 
 
+def test_autograd_moment_match_matches_oracle(orc, dev, api):
+    """The cell-wise moment matching as a torch.autograd.Function: forward
+    against the oracle's centred matching per cell group, backward (the
+    adjoint kernel) against the oracle's group adjoint and against central
+    finite differences of the oracle's forward."""
+    say("autograd moment matching")
+    from paper_2602_21244_amd.autograd import moment_match
+    pop = W.ragged_population(31, 40, 30, empty_frac=0.1)
+    ocs, operm, _ = orc.sort_cells(pop.cell_of, pop.n_cells)
+    v_pre = pop.v[:, operm].copy()
+    rng = np.random.default_rng(3)
+    v_post = v_pre + rng.normal(0.0, 40.0, v_pre.shape)  # a post-collision state
+    cs = torch.as_tensor(ocs, device=dev)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, torch.as_tensor(v_pre, device=dev).contiguous(), mom, api.L.MM_CAPTURE)
+    vp = torch.as_tensor(v_post, device=dev).contiguous().requires_grad_(True)
+    out = moment_match(vp, cs, mom)
+    Gw = rng.normal(size=v_pre.shape)
+    (out * torch.as_tensor(Gw, device=dev)).sum().backward()   # dL/d out = Gw
+    got, grad = out.detach().cpu().numpy(), vp.grad.cpu().numpy()
+    scale = float(np.max(np.abs(v_post)))
+    n_groups = 0
+    for k in range(pop.n_cells):
+        a, b = ocs[k], ocs[k + 1]
+        if b - a < 2:
+            np.testing.assert_array_equal(got[:, a:b], v_post[:, a:b])
+            np.testing.assert_array_equal(grad[:, a:b], Gw[:, a:b])
+            continue
+        n_groups += 1
+        q, qp, G = v_post[:, a:b].T, v_pre[:, a:b].T, Gw[:, a:b].T
+        np.testing.assert_allclose(got[:, a:b].T, orc.moment_match_group(q, qp),
+                                   rtol=1e-12, atol=1e-12 * scale)
+        ref_g = orc.moment_match_group_backward(G, q, qp)
+        np.testing.assert_allclose(grad[:, a:b].T, ref_g, rtol=1e-10, atol=1e-12)
+        # central differences of L = sum G . f(v) on two components
+        for (m, d) in ((0, 0), (b - a - 1, 2)):
+            h = 1e-4 * scale
+            qh, ql = q.copy(), q.copy()
+            qh[m, d] += h
+            ql[m, d] -= h
+            fd = (np.sum(G * orc.moment_match_group(qh, qp)) -
+                  np.sum(G * orc.moment_match_group(ql, qp))) / (2 * h)
+            assert abs(fd - grad[d, a + m]) < 1e-6 * max(1.0, abs(fd))
+    say(f"  {n_groups} groups checked")
+    assert n_groups > 10
+
+
 def test_training_reduces_error_and_beats_isotropic(dev, api):
-    """The trained surrogate reproduces the ab initio scattering far better
-    than the isotropic law it replaces, and its latent inputs carry the
-    stochastic part of the scattering: for one relative velocity, its output
-    directions spread over the latents, while the same network fed one fixed
-    latent collapses to a single direction (the regression to the mean the
-    latent noise prevents).  The spread of the quadrature targets is printed
-    beside it; matching it takes longer training than this test runs."""
+    """A short training run (300 steps) lowers the direction error and already
+    reproduces the ab initio scattering better than the isotropic law."""
     say("short training run")
     from paper_2602_21244_amd import train as T
     net, master, hist = T.train(steps=300, batch=16384, pool=1 << 16, lr=3e-3, seed=7,
@@ -208,6 +250,39 @@ def test_training_reduces_error_and_beats_isotropic(dev, api):
     err_iso = float(torch.sqrt((T.direction_error(d, tv) ** 2).mean()))
     say(f"  network {err_net:.3f} rad vs isotropic law {err_iso:.3f} rad")
     assert err_net < 0.7 * err_iso
+
+
+def _shipped_surrogate(api, dev):
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2602_21244_amd", "weights", "jager_surrogate_8x128x4.npz")
+    if not os.path.exists(path):
+        pytest.skip("no trained surrogate")
+    z = np.load(path, allow_pickle=False)
+    L = int(z["n_layers"])
+    return api.Net([z[f"W{l}"] for l in range(L)], [z[f"b{l}"] for l in range(L)], act="silu",
+                   wdtype="bf16", sigma_v=float(z["sigma_v"]), device=dev)
+
+
+def test_shipped_surrogate_against_quadrature(dev, api):
+    """The trained weights the benchmark uses, on held-out harvested rows
+    (seed 99): far closer to the quadrature than the isotropic law, and the
+    latent inputs carry the stochastic part of the scattering -- for one
+    relative velocity, the spread of the output directions over 4096 latent
+    draws is within a factor 2 of the spread of the quadrature's targets."""
+    say("shipped surrogate against the quadrature")
+    from paper_2602_21244_amd import train as T
+    net = _shipped_surrogate(api, dev)
+    pot = api.potential_jager(W.JAGER_PLACEHOLDER)
+    xv, gv, tv, _, sv = T.harvest(W, 16384, 99, dev, pot, api.quad_struct(64))
+    y, vr = api.neural_forward_rows(net, xv, gv)
+    err_net = float(torch.sqrt((T.direction_error(vr, tv) ** 2).mean()))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1)
+    d = torch.randn(16384, 3, device=dev, generator=gen, dtype=torch.float64)
+    err_iso = float(torch.sqrt((T.direction_error(d, tv) ** 2).mean()))
+    say(f"  network {err_net:.4f} rad vs isotropic law {err_iso:.3f} rad")
+    assert err_net < 0.1 * err_iso
     # one relative velocity, 4096 latent draws
     rows = W.training_rows(seed=17, n=4096)
     vr0 = np.tile(rows["vr"][:1], (4096, 1))
@@ -222,12 +297,8 @@ def test_training_reduces_error_and_beats_isotropic(dev, api):
         u = u / u.norm(dim=1, keepdim=True)
         return float(1.0 - u.mean(0).norm())   # 0 = all directions equal
 
-    x_fixed = x.clone()
-    x_fixed[:, 3:8] = x[0, 3:8]
-    _, out_fixed = api.neural_forward_rows(net, x_fixed, g)
-    s_tgt, s_net, s_fix = spread(tgt), spread(out), spread(out_fixed)
-    say(f"  direction spread over latents: target {s_tgt:.3f}, network {s_net:.3f}, "
-        f"fixed latent {s_fix:.2e}")
-    # the latents move the output (a fixed latent collapses it to one direction)
-    assert s_fix < 1e-9
-    assert s_net > 1e-5
+    s_tgt, s_net = spread(tgt), spread(out)
+    say(f"  direction spread over latents: target {s_tgt:.3f}, network {s_net:.3f}")
+    # the latents carry the stochastic part: the network's directions spread
+    # over them about as much as the quadrature's targets do
+    assert 0.5 * s_tgt < s_net < 2.0 * s_tgt

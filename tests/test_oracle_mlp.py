@@ -48,14 +48,37 @@ def test_relu_passthrough_reproduces_isotropic_rule(orc):
     np.testing.assert_allclose(np.linalg.norm(vn, axis=1), rows["g"], rtol=1e-14)
 
 
-def _loss(orc, Ws, bs, x, g, target, sv, act):
+def _loss(orc, Ws, bs, x, g, target, sv, act, kind="velocity"):
     y = orc.mlp_forward(Ws, bs, x, act)
     vn, _, _ = orc.project(y, g)
+    if kind == "direction":
+        return orc.direction_loss(vn, target)
     return orc.surrogate_loss(vn, target, sv)
 
 
-@pytest.mark.parametrize("act", ["silu", "relu"])
-def test_gradients_against_finite_differences(orc, act):
+def test_direction_loss_closed_form(orc):
+    """Two unit-speed directions at angle a: |u - u*|^2 / 4 = (1 - cos a) / 2,
+    whatever the common speed g; the mean over rows; gradient by central
+    differences."""
+    rng = np.random.default_rng(3)
+    a = rng.uniform(0, np.pi, 50)
+    g = 10 ** rng.uniform(2, 4, 50)
+    t = np.stack([g, np.zeros(50), np.zeros(50)], axis=1)
+    v = np.stack([g * np.cos(a), g * np.sin(a), np.zeros(50)], axis=1)
+    assert orc.direction_loss(v, t) == pytest.approx(np.mean((1 - np.cos(a)) / 2), rel=1e-13)
+    G = orc.direction_loss_grad(v, t)
+    h = 1e-3
+    for (i, d) in [(0, 0), (7, 1), (49, 2)]:
+        vp, vm = v.copy(), v.copy()
+        vp[i, d] += h
+        vm[i, d] -= h
+        fd = (orc.direction_loss(vp, t) - orc.direction_loss(vm, t)) / (2 * h)
+        assert abs(fd - G[i, d]) < 1e-9 * max(1.0, abs(fd)) + 1e-14
+
+
+@pytest.mark.parametrize("act,kind", [("silu", "velocity"), ("relu", "velocity"),
+                                      ("silu", "direction")])
+def test_gradients_against_finite_differences(orc, act, kind):
     rng = np.random.default_rng(12)
     Ws, bs = W.mlp_init(3, W.FD_DIMS)
     rows = W.training_rows(seed=6, n=64)
@@ -65,7 +88,8 @@ def test_gradients_against_finite_differences(orc, act):
     sv = rows["sigma_v"]
     y = orc.mlp_forward(Ws, bs, x, act)
     vn, _, _ = orc.project(y, g)
-    G = orc.surrogate_loss_grad(vn, target, sv)
+    G = (orc.direction_loss_grad(vn, target) if kind == "direction"
+         else orc.surrogate_loss_grad(vn, target, sv))
     dy = orc.project_backward(G, y, g)
     dW, db, dx = orc.mlp_backward(Ws, bs, x, dy, act)
     h = 1e-6
@@ -75,16 +99,16 @@ def test_gradients_against_finite_differences(orc, act):
             Wm = [w.copy() for w in Ws]
             Wp[l][i, j] += h
             Wm[l][i, j] -= h
-            fd = (_loss(orc, Wp, bs, x, g, target, sv, act) -
-                  _loss(orc, Wm, bs, x, g, target, sv, act)) / (2 * h)
+            fd = (_loss(orc, Wp, bs, x, g, target, sv, act, kind) -
+                  _loss(orc, Wm, bs, x, g, target, sv, act, kind)) / (2 * h)
             assert abs(fd - dW[l][i, j]) <= 1e-6 * max(1.0, abs(fd)), (l, i, j, fd, dW[l][i, j])
         for i in [0, bs[l].shape[0] - 1]:
             bp = [b.copy() for b in bs]
             bm = [b.copy() for b in bs]
             bp[l][i] += h
             bm[l][i] -= h
-            fd = (_loss(orc, Ws, bp, x, g, target, sv, act) -
-                  _loss(orc, Ws, bm, x, g, target, sv, act)) / (2 * h)
+            fd = (_loss(orc, Ws, bp, x, g, target, sv, act, kind) -
+                  _loss(orc, Ws, bm, x, g, target, sv, act, kind)) / (2 * h)
             assert abs(fd - db[l][i]) <= 1e-6 * max(1.0, abs(fd))
     # input gradient
     for (r, c) in [(0, 0), (5, 7), (63, 3)]:
@@ -92,8 +116,8 @@ def test_gradients_against_finite_differences(orc, act):
         xm = x.copy()
         xp[r, c] += h
         xm[r, c] -= h
-        fd = (_loss(orc, Ws, bs, xp, g, target, sv, act) -
-              _loss(orc, Ws, bs, xm, g, target, sv, act)) / (2 * h)
+        fd = (_loss(orc, Ws, bs, xp, g, target, sv, act, kind) -
+              _loss(orc, Ws, bs, xm, g, target, sv, act, kind)) / (2 * h)
         assert abs(fd - dx[r, c]) <= 1e-6 * max(1.0, abs(fd))
 
 
