@@ -198,6 +198,19 @@ int dsmc_sort_cells(int32_t n, int32_t n_cells, const int32_t* cell_of, int32_t 
                     dsmc_vec3 v_in, dsmc_vec3 v_out, int32_t* cell_start, int32_t* perm,
                     void* ws, size_t ws_bytes, dsmc_status* st, dsmc_stream_t stream);
 
+/* dsmc_sort_cells without a workspace, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, bit for bit, with the
+ * scratch in a static device array of the library (about 14 MB, one copy per
+ * GPU, held until the process ends).  Limits: n <= 1 048 576 particles and
+ * n_cells <= 1 048 576; larger inputs return DSMC_E_ARG (use
+ * dsmc_sort_cells).  The call allocates nothing (no hipMalloc/hipFree, no
+ * allocating library routine).  All calls on one GPU share the array:
+ * calls that overlap on one GPU (concurrent streams or threads) race. */
+int dsmc_sort_cells_noalloc(int32_t n, int32_t n_cells, const int32_t* cell_of, int32_t dtype,
+                            dsmc_vec3 v_in, dsmc_vec3 v_out, int32_t* cell_start, int32_t* perm,
+                            dsmc_status* st, dsmc_stream_t stream);
+
 /* Cell moments and cell-wise moment matching (section "Optional Cell-Wise
  * Energy Drift Correction", eq. cell_energy_clamp), FP64 throughout.
  * mom[6*n_cells] per cell: (ux, uy, uz, S, cmax, E) with u the mean velocity,

@@ -95,6 +95,7 @@ SIGNATURES = {
     "dsmc_status_clear": (C.c_int, [_vp, _vp]),
     "dsmc_sort_cells_ws": (_sz, [_i32, _i32]),
     "dsmc_sort_cells": (C.c_int, [_i32, _i32, _vp, _i32, Vec3, Vec3, _vp, _vp, _vp, _sz, _vp, _vp]),
+    "dsmc_sort_cells_noalloc": (C.c_int, [_i32, _i32, _vp, _i32, Vec3, Vec3, _vp, _vp, _vp, _vp]),
     "dsmc_moment_match": (C.c_int, [_i32, _vp, _i32, Vec3, _vp, _i32, _vp, _vp, _vp]),
     "dsmc_select_pairs_ntc_ws": (_sz, [_i32, _i64]),
     "dsmc_select_pairs_ntc": (C.c_int, [_i32, _vp, _i32, Vec3, Xs, _vp, _vp, Rng, Pairs, _vp,

@@ -174,6 +174,15 @@ def moment_match(cell_start, v, mom, mode, pair_cnt=None, st=None, stream=None):
           "dsmc_moment_match")
 
 
+def sort_cells_noalloc(cell_of, n_cells, v_in, cs, perm, v_out, st=None, stream=None):
+    """dsmc_sort_cells_noalloc into caller-provided outputs (the library's
+    static scratch; n and n_cells at most 2^20)."""
+    check(lib().dsmc_sort_cells_noalloc(int(cell_of.numel()), int(n_cells), _ptr(cell_of),
+                                        _dtype(v_in), _vec3(v_in), _vec3(v_out), _ptr(cs),
+                                        _ptr(perm), _ptr(st), _stream(stream)),
+          "dsmc_sort_cells_noalloc")
+
+
 class PairList:
     def __init__(self, n_cells, cap, device):
         self.cap = int(cap)

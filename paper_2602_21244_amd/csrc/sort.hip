@@ -22,6 +22,8 @@
 // cell_start.
 // Ids outside [0, n_cells) are mapped to the key n_cells, so they sort after
 // every kept particle.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace dsmc {
@@ -523,6 +525,82 @@ static int sort_impl(int32_t n, int32_t n_cells, const int32_t* cell_of, dsmc_ve
 }  // namespace dsmc
 
 using namespace dsmc;
+
+// ------------------------------------------------------------------------
+// Allocation-free variant: the scratch lives in a file-scope device array,
+// one copy per GPU, held until the process ends.  Sized for the limits
+// below with a margin (the scan's tile table of the cell counts needs far
+// less than one int per cell).
+// ------------------------------------------------------------------------
+namespace dsmc {
+
+constexpr int32_t NOALLOC_MAX_N = 1 << 20;
+constexpr int32_t NOALLOC_MAX_CELLS = 1 << 20;
+constexpr size_t noalloc_round(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t NOALLOC_TILES = ((size_t)NOALLOC_MAX_N + SORT_TILE - 1) / SORT_TILE;
+constexpr size_t NOALLOC_CHUNKS = (NOALLOC_TILES + HCHUNK - 1) / HCHUNK;
+constexpr size_t NOALLOC_SCRATCH_BYTES =
+    3 * noalloc_round(sizeof(int32_t) * (size_t)NOALLOC_MAX_N) +
+    2 * noalloc_round(sizeof(int32_t) * RADIX * NOALLOC_TILES) +
+    2 * noalloc_round(sizeof(int32_t) * RADIX * NOALLOC_CHUNKS) +
+    noalloc_round(sizeof(int32_t) * RADIX) +
+    noalloc_round(sizeof(int32_t) * ((size_t)NOALLOC_MAX_CELLS + 2)) + 256;
+
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+// Device address of `scratch` on each GPU, taken once per device with that
+// device current (the host-side name of the array is not a device address).
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static int scratch_ptr(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(e, "dsmc_sort_cells_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return arg_error("dsmc_sort_cells_noalloc: device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_check(e, "dsmc_sort_cells_noalloc: hipGetSymbolAddress");
+        if (!p) return arg_error("dsmc_sort_cells_noalloc: null scratch address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DSMC_OK;
+}
+
+}  // namespace dsmc
+
+extern "C" int dsmc_sort_cells_noalloc(int32_t n, int32_t n_cells, const int32_t* cell_of,
+                                       int32_t dtype, dsmc_vec3 v_in, dsmc_vec3 v_out,
+                                       int32_t* cell_start, int32_t* perm, dsmc_status* st,
+                                       dsmc_stream_t stream)
+{
+    if (n < 0 || n_cells < 1) return arg_error("dsmc_sort_cells_noalloc: n=%d n_cells=%d", n, n_cells);
+    if (n > NOALLOC_MAX_N || n_cells > NOALLOC_MAX_CELLS)
+        return arg_error("dsmc_sort_cells_noalloc: n=%d, n_cells=%d beyond the static scratch "
+                         "limits (%d particles, %d cells); use dsmc_sort_cells with a workspace",
+                         n, n_cells, NOALLOC_MAX_N, NOALLOC_MAX_CELLS);
+    if (!cell_start || (n > 0 && (!cell_of || !perm || !v_in.x || !v_in.y || !v_in.z ||
+                                  !v_out.x || !v_out.y || !v_out.z)))
+        return arg_error("dsmc_sort_cells_noalloc: null pointer");
+    if (dtype != DSMC_F64 && dtype != DSMC_F32)
+        return arg_error("dsmc_sort_cells_noalloc: dtype %d", dtype);
+    if (dsmc_sort_cells_ws(n, n_cells) > NOALLOC_SCRATCH_BYTES)
+        return arg_error("dsmc_sort_cells_noalloc: scratch %zu < %zu", NOALLOC_SCRATCH_BYTES,
+                         dsmc_sort_cells_ws(n, n_cells));
+    void* ws = nullptr;
+    int rc = scratch_ptr(&ws);
+    if (rc) return rc;
+    hipStream_t s = as_stream(stream);
+    if (dtype == DSMC_F64)
+        return sort_impl<double>(n, n_cells, cell_of, v_in, v_out, cell_start, perm, ws, st, s);
+    return sort_impl<float>(n, n_cells, cell_of, v_in, v_out, cell_start, perm, ws, st, s);
+}
 
 extern "C" size_t dsmc_sort_cells_ws(int32_t n, int32_t n_cells)
 {
