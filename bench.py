@@ -148,6 +148,18 @@ def main():
     table_build_ms = tb0.elapsed_time(tb1) / 3
     log(f"chi table 512x512 build: {table_build_ms:.3f} ms ({akind} angle network)")
 
+    # launch shape of the fused Phase B + moment matching, tuned on this
+    # step's own pair list (Phase A of the network, deferred)
+    from paper_2602_21244_amd import autotune
+    do_sort()
+    api.moment_match(cs, v, mom, L.MM_CAPTURE)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, pairs, ws=sel_ws, st=st)
+    api.neural_collide(net, v, pairs, 11, 0, schedule=L.SCHED_DEFER, ws=col_ws, st=st)
+    match_shape, match_times = autotune.tune_match_schedule(cs, v, pairs, L.APPLY_DIRECTIONS, mom,
+                                                            col_ws, use_cache=False)
+    log(f"autotuned phase B + match launch shape {match_shape}: {match_times[match_shape]:.4f} ms "
+        f"(default 40/2/1: {match_times[(40, 2, 1)]:.4f} ms)")
+
     def stage_events(k):
         return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
 
@@ -203,6 +215,12 @@ def main():
     log(f"neural: {ms_n:.3f} ms/step (events), wall {wall_n / args.steps * 1e3:.3f} ms/step, "
         f"pairs {n_pairs}, stages {json.dumps({k: round(x, 4) for k, x in per_n.items()})}")
 
+    # the same step captured as one HIP graph and replayed (the launch
+    # sequence of a production loop); every replay recomputes the step from
+    # the same post-streaming input, so its result must equal the eager one
+    graph = graph_replay_timing(step, v, args.steps)
+    log(f"neural step as a HIP graph: {graph}")
+
     # neural directions of this step for the angle comparison
     es = 4
     dirs = col_ws[: 3 * (cap + 1) * es].view(torch.float32).view(3, cap + 1)[:, :n_pairs].clone()
@@ -256,6 +274,11 @@ def main():
     # step: its Phase A reads the pair list and writes one direction per pair
     wall_v, ms_v, per_v = run("vhs", 1, args.table_steps)
     log(f"vhs: {ms_v:.3f} ms/step, stages {json.dumps({k: round(x, 4) for k, x in per_v.items()})}")
+
+    # the isotropic rule as one persistent launch per step (cell work queue:
+    # moments, selection, Phase A/B and matching with the cell in LDS)
+    fused = fused_vhs_timing(api, lib, L, pop, cs, v, do_sort, lam, args.table_steps)
+    log(f"isotropic rule, persistent fused step: {fused}")
 
     # SBT selection (the alternative rate control) on the same sorted input,
     # beside the NTC selection's stage time
@@ -319,6 +342,11 @@ def main():
         "sbt_pairs": sbt_pairs,
         "ntc_select_ms": per_n["select"],
         "ce_viscosity_ms_64_temperatures": ce_ms,
+        "eager_ms_per_step": ms_n,
+        "graph": graph,
+        "match_schedule": {"shape_wave_medium_big_per_cu": list(match_shape),
+                           "ms": match_times[match_shape], "default_ms": match_times[(40, 2, 1)]},
+        "vhs_fused_step": fused,
         "vhs_pairs_per_s": n_pairs / (ms_v * 1e-3),
         "vhs_ms_per_step": ms_v,
         "stage_ms_vhs": per_v,
@@ -351,15 +379,20 @@ def main():
         cpu = cpu_baseline(pop, Ws, bs, sigma_v, args.cpu_sample_pairs)
         log(f"cpu baseline: {cpu}")
 
+    # the step as launched eagerly and as a replayed HIP graph does the same
+    # work; the faster of the two (graph only when its result matched)
+    ms_step = ms_n
+    if graph.get("bit_identical_to_eager") and graph.get("ms_per_step", ms_n) < ms_n:
+        ms_step = graph["ms_per_step"]
     out = {
         "metric": "collision pairs/s: neural vs quadrature \u03c7 at stated angle error; "
                   "% HBM/MFMA peak",
-        "value": n_pairs / (ms_n * 1e-3),
+        "value": n_pairs / (ms_step * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_n,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -373,6 +406,80 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def graph_replay_timing(step, v, reps):
+    """Capture step("neural") as one HIP graph on a side stream, replay it
+    `reps` times between events, and check a replay against the eager step."""
+    import torch
+    out = {}
+    try:
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step("neural")
+        torch.cuda.synchronize()
+        eager = v.clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            step("neural")
+        v.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        out["bit_identical_to_eager"] = bool(torch.equal(v, eager))
+        for _ in range(2):
+            g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        out["ms_per_step"] = e0.elapsed_time(e1) / reps
+        out["replays"] = reps
+    except Exception as e:  # pragma: no cover - reported, the eager number stands
+        out["error"] = repr(e)
+    return out
+
+
+def fused_vhs_timing(api, lib, L, pop, cs, v, do_sort, lam, reps):
+    """dsmc_step_vhs_fused (one persistent launch: moments, NTC, isotropic
+    Phase A/B and moment matching per cell in LDS) after the sort, timed
+    against nothing else; cells it cannot stage (> 3072 particles) counted."""
+    import torch
+    dev = v.device
+    n_cells = pop.n_cells
+    cnt = torch.zeros(n_cells, dtype=torch.int32, device=dev)
+    ws = api.workspace(lib.dsmc_step_vhs_ws(n_cells, 0), dev)
+    st = api.new_status(dev)
+
+    def one():
+        api.check(lib.dsmc_step_vhs_fused(n_cells, api._ptr(cs), L.F32, api._vec3(v),
+                                          api.xs_struct(pop.xs), api._ptr(lam),
+                                          api.rng_struct(11, 0), 1, api._ptr(cnt), api._ptr(ws),
+                                          int(ws.numel()), api._ptr(st), api._stream()),
+                  "dsmc_step_vhs_fused")
+    do_sort()
+    one()
+    torch.cuda.synchronize()
+    ms_sort = []
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tot = 0.0
+    for _ in range(reps):
+        e[0].record()
+        do_sort()
+        e[1].record()
+        one()
+        e[2].record()
+        torch.cuda.synchronize()
+        ms_sort.append(e[0].elapsed_time(e[1]))
+        tot += e[1].elapsed_time(e[2])
+    c = cnt.cpu()
+    return {"fused_kernel_ms": tot / reps, "step_ms_with_sort": tot / reps + float(np.mean(ms_sort)),
+            "pairs": int(c.clamp(min=0).sum()), "cells_not_staged": int((c < 0).sum()),
+            "max_pairs_in_a_cell": int(c.max())}
 
 
 def counter_traffic(kernel, source="mlp.hip"):

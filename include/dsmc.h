@@ -402,9 +402,11 @@ int dsmc_harvest_rows(int64_t B, const double* vr, const double* xi, const doubl
  * sees one read and one write of the velocities.  Results are bit-identical
  * to dsmc_moment_match(CAPTURE) -> dsmc_select_pairs_ntc -> dsmc_collide_vhs
  * -> dsmc_moment_match(APPLY) with the same rng.  pair_cnt[n_cells] receives
- * each cell's accepted pairs; a cell above the LDS capacity (3072 particles
- * or 2048 accepted pairs) is left unchanged with pair_cnt = -1 and
- * DSMC_ST_PAIR_OVERFLOW set, for the separate entry points to handle.
+ * each cell's accepted pairs.  A cell with more than 2048 accepted pairs is
+ * applied in LDS batches of 2048 in candidate order (same result); a cell of
+ * more than 3072 particles (beyond the LDS staging) is left unchanged with
+ * pair_cnt = -1 and DSMC_ST_PAIR_OVERFLOW set, for the separate entry points
+ * to handle.
  * ws: dsmc_step_vhs_ws bytes. */
 size_t dsmc_step_vhs_ws(int32_t n_cells, int64_t cap);
 int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, int32_t dtype, dsmc_vec3 v,
@@ -416,6 +418,21 @@ int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, int32_t dtyp
  * schedule; the autotuner in the Python package sets it. */
 int dsmc_set_block_threshold(int32_t pairs);
 int32_t dsmc_get_block_threshold(void);
+
+/* Launch shape of dsmc_apply_pairs_match (process-wide, as the threshold
+ * above): workgroups per compute unit of its three persistent kernels --
+ * the wave-per-cell kernel, and the medium (256 lanes) and big (512 lanes)
+ * block-per-cell kernels.  Every shape gives the same results bit for bit;
+ * paper_2602_21244_amd/autotune.py measures them on the step's own pair
+ * list and installs the fastest.  Defaults 40 / 2 / 1. */
+typedef struct {
+    int32_t wave_per_cu;    /* 1..256 */
+    int32_t medium_per_cu;  /* 1..64 */
+    int32_t big_per_cu;     /* 1..64 */
+    int32_t reserved;
+} dsmc_match_schedule;
+int dsmc_set_match_schedule(const dsmc_match_schedule* ms);
+int dsmc_get_match_schedule(dsmc_match_schedule* ms);
 
 /* Chapman-Enskog viscosity from the deflection angle (section "Macroscopic
  * Validation: Viscosity and Transport Coefficients", eq. chapman_enskog):

@@ -61,6 +61,11 @@ class Potential(C.Structure):
                 ("K", C.c_double)]
 
 
+class MatchSchedule(C.Structure):
+    _fields_ = [("wave_per_cu", C.c_int32), ("medium_per_cu", C.c_int32),
+                ("big_per_cu", C.c_int32), ("reserved", C.c_int32)]
+
+
 class Quad(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("max_iter", C.c_int32), ("scan_ratio", C.c_double),
                 ("refine", C.c_int32), ("reserved", C.c_int32)]
@@ -152,6 +157,8 @@ SIGNATURES = {
                                     C.POINTER(Potential), Quad, _vp, _vp, _vp, _sz, _vp, _vp]),
     "dsmc_set_block_threshold": (C.c_int, [_i32]),
     "dsmc_get_block_threshold": (_i32, []),
+    "dsmc_set_match_schedule": (C.c_int, [_vp]),
+    "dsmc_get_match_schedule": (C.c_int, [_vp]),
 }
 
 _lib = None

@@ -413,6 +413,17 @@ def get_block_threshold():
     return int(lib().dsmc_get_block_threshold())
 
 
+def set_match_schedule(wave_per_cu, medium_per_cu, big_per_cu):
+    m = L.MatchSchedule(int(wave_per_cu), int(medium_per_cu), int(big_per_cu), 0)
+    check(lib().dsmc_set_match_schedule(C.byref(m)), "dsmc_set_match_schedule")
+
+
+def get_match_schedule():
+    m = L.MatchSchedule()
+    check(lib().dsmc_get_match_schedule(C.byref(m)), "dsmc_get_match_schedule")
+    return (m.wave_per_cu, m.medium_per_cu, m.big_per_cu)
+
+
 # ---------------------------------------------------------------------------
 # Angle network and deflection-angle table
 # ---------------------------------------------------------------------------

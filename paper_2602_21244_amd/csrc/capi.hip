@@ -10,6 +10,7 @@ namespace dsmc {
 
 static thread_local char g_err[512] = "";
 static int32_t g_block_threshold = 48;
+static dsmc_match_schedule g_match_schedule = {40, 2, 1, 0};
 
 void set_error(const char* fmt, ...)
 {
@@ -59,6 +60,7 @@ int persistent_blocks(int threads_per_block)
 }
 
 int32_t block_threshold() { return g_block_threshold; }
+dsmc_match_schedule match_schedule() { return g_match_schedule; }
 
 // --------------------------------------------------------------------------
 // Fills
@@ -265,5 +267,24 @@ int dsmc_set_block_threshold(int32_t pairs)
 }
 
 int32_t dsmc_get_block_threshold(void) { return g_block_threshold; }
+
+int dsmc_set_match_schedule(const dsmc_match_schedule* ms)
+{
+    if (!ms) return arg_error("dsmc_set_match_schedule: null");
+    if (ms->wave_per_cu < 1 || ms->wave_per_cu > 256 || ms->medium_per_cu < 1 ||
+        ms->medium_per_cu > 64 || ms->big_per_cu < 1 || ms->big_per_cu > 64)
+        return arg_error("dsmc_set_match_schedule: %d/%d/%d workgroups per CU out of range",
+                         ms->wave_per_cu, ms->medium_per_cu, ms->big_per_cu);
+    g_match_schedule = *ms;
+    g_match_schedule.reserved = 0;
+    return DSMC_OK;
+}
+
+int dsmc_get_match_schedule(dsmc_match_schedule* ms)
+{
+    if (!ms) return arg_error("dsmc_get_match_schedule: null");
+    *ms = g_match_schedule;
+    return DSMC_OK;
+}
 
 }  // extern "C"

@@ -868,11 +868,12 @@ int phase_b(int rule, int dtype, int32_t n_cells, const int32_t* cell_start, dsm
     const bool need_lane = thr > 0;
     const bool need_rest = thr < INT32_MAX;
     const int cus = device_cus();
-    int wb = n_cells < cus * 40 ? n_cells : cus * 40;
-    wb = wb < 1 ? 1 : wb;
-    int bb = n_cells < cus * 2 ? n_cells : cus * 2;
-    bb = bb < 1 ? 1 : bb;
-    const int bg = n_cells < cus ? n_cells : cus;
+    const dsmc_match_schedule ms = match_schedule();
+    auto grid = [&](int per_cu) {
+        const int64_t g = (int64_t)cus * per_cu;
+        return (int)(g < n_cells ? (g < 1 ? 1 : g) : n_cells);
+    };
+    const int wb = grid(ms.wave_per_cu), bb = grid(ms.medium_per_cu), bg = grid(ms.big_per_cu);
 #define DSMC_PHASEB(T, R)                                                                   \
     do {                                                                                    \
         PairBuf<T> d = PairBuf<T>::of(dirs, cap);                                           \
@@ -969,11 +970,12 @@ extern "C" int dsmc_apply_pairs_match(int32_t n_cells, const int32_t* cell_start
     const PairsView pr = PairsView::of(pairs);
     const MatchArgs ma{cell_start, mom, mode == DSMC_MM_APPLY_LITERAL ? 1 : 0, st};
     const int cus = device_cus();
-    int wb = n_cells < cus * 40 ? n_cells : cus * 40;
-    wb = wb < 1 ? 1 : wb;
-    int bb = n_cells < cus * 2 ? n_cells : cus * 2;
-    bb = bb < 1 ? 1 : bb;
-    const int bg = n_cells < cus ? n_cells : cus;
+    const dsmc_match_schedule ms = match_schedule();
+    auto grid = [&](int per_cu) {
+        const int64_t g = (int64_t)cus * per_cu;
+        return (int)(g < n_cells ? (g < 1 ? 1 : g) : n_cells);
+    };
+    const int wb = grid(ms.wave_per_cu), bb = grid(ms.medium_per_cu), bg = grid(ms.big_per_cu);
 #define DSMC_PHASEB_MATCH(T, R)                                                              \
     do {                                                                                     \
         PairBuf<T> d = PairBuf<T>::of(ws, pairs.cap);                                        \

@@ -23,6 +23,7 @@ int hip_check(hipError_t e, const char* what);
 
 // Persistent grid for data-dependent sizes (pair counts live on the device).
 int persistent_blocks(int threads_per_block);
+dsmc_match_schedule match_schedule();
 // Compute units of the current device.
 int device_cus();
 

@@ -6,7 +6,11 @@
 // write of the velocities per step.  The arithmetic (including the order of
 // every reduction) is that of the separate entry points, so the results are
 // bit-identical to dsmc_moment_match(CAPTURE) -> dsmc_select_pairs_ntc ->
-// dsmc_collide_vhs -> dsmc_moment_match(APPLY).
+// dsmc_collide_vhs -> dsmc_moment_match(APPLY).  A cell with more accepted
+// pairs than LDS holds is applied in batches, in candidate order: the pairs
+// gathered so far get Phase A and Phase B before the next candidates are
+// decided, which then read the pre-step velocities from global memory (not
+// written until the cell's write-back).
 #include <limits.h>
 #include <math.h>
 
@@ -18,7 +22,7 @@ int xs_law_public(const dsmc_xs& xs, double* C, double* e);
 
 constexpr int FS_THREADS = 256;
 constexpr int FS_NMAX = 3072;  // particles of a cell staged in LDS
-constexpr int FS_MMAX = 2048;  // accepted pairs of a cell
+constexpr int FS_MMAX = 2048;  // accepted pairs of one LDS batch
 
 struct FusedArgs {
     int32_t n_cells;
@@ -67,7 +71,7 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
     __shared__ T ldir[3][FS_MMAX];
     __shared__ int32_t first[FS_NMAX];
     __shared__ double mom[6], post[6];
-    __shared__ int32_t s_cell, s_M, s_acc, s_remaining;
+    __shared__ int32_t s_cell, s_M, s_acc, s_remaining, s_base;
     __shared__ int32_t wtot[FS_THREADS / 64];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
@@ -113,8 +117,88 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
         __syncthreads();
         const int32_t M = s_M;
         const double ghat = 2.0 * mom[4];
-        // candidates in chunks; ordered compaction of the accepted ones
+        if (tid == 0) s_base = 0;
+        __syncthreads();
+        // Pre-step velocity of slot i: LDS until the first batch of pairs has
+        // been applied there, then global memory, which keeps the pre-step
+        // values until the write-back (the same numbers either way).
+        auto pre = [&](int32_t i, double& x, double& y, double& z) {
+            if (s_base == 0) {
+                x = lvx[i]; y = lvy[i]; z = lvz[i];
+            } else {
+                x = (double)v.x[s0 + i]; y = (double)v.y[s0 + i]; z = (double)v.z[s0 + i];
+            }
+        };
+        // Phase A and Phase B of the s_acc pairs gathered in lpair (accepted
+        // pairs s_base .. s_base + s_acc - 1 of the cell, in candidate order)
+        auto flush = [&]() {
+            const int32_t nb = s_acc, b0 = s_base;
+            // Phase A on the pre-collision velocities (arithmetic in T, as
+            // the separate isotropic kernel)
+            for (int32_t q = tid; q < nb; q += FS_THREADS) {
+                T xi[3], z[2], u4;
+                pair_latents(A.rng, (uint32_t)(b0 + q), (uint32_t)k, xi, z, u4);
+                const int32_t i = lpair[q] & 0xffff, j = lpair[q] >> 16;
+                double xa, ya, za, xb, yb, zb;
+                pre(i, xa, ya, za);
+                pre(j, xb, yb, zb);
+                T vh[3], e[3];
+                unit3<T>((T)xa - (T)xb, (T)ya - (T)yb, (T)za - (T)zb, vh);
+                const T cc = T(2) * u4 - T(1);
+                const T sc = T(2) * dev_sqrt<T>(u4 * (T(1) - u4));
+                perp_dir<T>(xi, vh, e);
+                ldir[0][q] = cc * vh[0] + sc * e[0];
+                ldir[1][q] = cc * vh[1] + sc * e[1];
+                ldir[2][q] = cc * vh[2] + sc * e[2];
+            }
+            if (tid == 0) s_remaining = nb;
+            __syncthreads();
+            // Phase B: dependency rounds, every value rounded to T as stored
+            while (s_remaining > 0) {
+                for (int32_t q = tid; q < N; q += FS_THREADS) first[q] = INT32_MAX;
+                __syncthreads();
+                for (int32_t q = tid; q < nb; q += FS_THREADS) {
+                    const uint32_t w = lpair[q];
+                    if (w != 0xffffffffu) {
+                        atomicMin(&first[w & 0xffff], q);
+                        atomicMin(&first[w >> 16], q);
+                    }
+                }
+                __syncthreads();
+                int done_here = 0;
+                for (int32_t q = tid; q < nb; q += FS_THREADS) {
+                    const uint32_t w = lpair[q];
+                    if (w == 0xffffffffu) continue;
+                    const int32_t a = w & 0xffff, b = w >> 16;
+                    if (first[a] != q || first[b] != q) continue;
+                    const double xa = lvx[a], ya = lvy[a], za = lvz[a];
+                    const double xb = lvx[b], yb = lvy[b], zb = lvz[b];
+                    const double rx = xa - xb, ry = ya - yb, rz = za - zb;
+                    const double g = sqrt(rx * rx + ry * ry + rz * rz);
+                    const double a0 = ldir[0][q], a1 = ldir[1][q], a2 = ldir[2][q];
+                    const double inv = 1.0 / sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+                    const double u0 = a0 * inv, u1 = a1 * inv, u2 = a2 * inv;
+                    const double cx = 0.5 * (xa + xb), cy = 0.5 * (ya + yb), cz = 0.5 * (za + zb);
+                    const double px = 0.5 * g * u0, py = 0.5 * g * u1, pz = 0.5 * g * u2;
+                    lvx[a] = (double)(T)(cx + px); lvy[a] = (double)(T)(cy + py); lvz[a] = (double)(T)(cz + pz);
+                    lvx[b] = (double)(T)(cx - px); lvy[b] = (double)(T)(cy - py); lvz[b] = (double)(T)(cz - pz);
+                    lpair[q] = 0xffffffffu;
+                    ++done_here;
+                }
+                __syncthreads();
+                if (done_here) atomicSub(&s_remaining, done_here);
+                __syncthreads();
+            }
+            if (tid == 0) {
+                s_base = b0 + nb;
+                s_acc = 0;
+            }
+            __syncthreads();
+        };
+        // candidates in blocks of FS_THREADS; ordered compaction of the
+        // accepted ones into lpair, flushed before a block could overflow it
         for (int32_t base = 0; base < M; base += FS_THREADS) {
+            if (s_acc + FS_THREADS > FS_MMAX) flush();
             const int32_t t = base + tid;
             bool acc = false;
             uint32_t packed = 0;
@@ -124,7 +208,10 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
                 int32_t j = (int32_t)(((uint64_t)r.b * (uint64_t)(N - 1)) >> 32);
                 if (j >= i) j += 1;
                 const double U = unif53(r.c, r.d);
-                const double dx = lvx[i] - lvx[j], dy = lvy[i] - lvy[j], dz = lvz[i] - lvz[j];
+                double xa, ya, za, xb, yb, zb;
+                pre(i, xa, ya, za);
+                pre(j, xb, yb, zb);
+                const double dx = xa - xb, dy = ya - yb, dz = za - zb;
                 const double g2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
                                             __dmul_rn(dz, dz));
                 const double ratio = sqrt(g2) / ghat;
@@ -138,7 +225,7 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
             __syncthreads();
             int off = s_acc;
             for (int w = 0; w < wid; ++w) off += wtot[w];
-            if (acc && off + before < FS_MMAX) lpair[off + before] = packed;
+            if (acc) lpair[off + before] = packed;
             __syncthreads();
             if (tid == 0) {
                 int tot = 0;
@@ -147,68 +234,8 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
             }
             __syncthreads();
         }
-        const int32_t na = s_acc;
-        if (na > FS_MMAX) {
-            if (tid == 0) {
-                A.pair_cnt[k] = -1;
-                if (A.st) atomicOr(&A.st->flags, (uint32_t)DSMC_ST_PAIR_OVERFLOW);
-            }
-            __syncthreads();
-            continue;
-        }
-        // Phase A on the pre-collision velocities (arithmetic in T, as the
-        // separate isotropic kernel)
-        for (int32_t q = tid; q < na; q += FS_THREADS) {
-            T xi[3], z[2], u4;
-            pair_latents(A.rng, (uint32_t)q, (uint32_t)k, xi, z, u4);
-            const int32_t i = lpair[q] & 0xffff, j = lpair[q] >> 16;
-            T vh[3], e[3];
-            unit3<T>((T)lvx[i] - (T)lvx[j], (T)lvy[i] - (T)lvy[j], (T)lvz[i] - (T)lvz[j], vh);
-            const T cc = T(2) * u4 - T(1);
-            const T sc = T(2) * dev_sqrt<T>(u4 * (T(1) - u4));
-            perp_dir<T>(xi, vh, e);
-            ldir[0][q] = cc * vh[0] + sc * e[0];
-            ldir[1][q] = cc * vh[1] + sc * e[1];
-            ldir[2][q] = cc * vh[2] + sc * e[2];
-        }
-        if (tid == 0) s_remaining = na;
-        __syncthreads();
-        // Phase B: dependency rounds, every value rounded to T as stored
-        while (s_remaining > 0) {
-            for (int32_t q = tid; q < N; q += FS_THREADS) first[q] = INT32_MAX;
-            __syncthreads();
-            for (int32_t q = tid; q < na; q += FS_THREADS) {
-                const uint32_t w = lpair[q];
-                if (w != 0xffffffffu) {
-                    atomicMin(&first[w & 0xffff], q);
-                    atomicMin(&first[w >> 16], q);
-                }
-            }
-            __syncthreads();
-            int done_here = 0;
-            for (int32_t q = tid; q < na; q += FS_THREADS) {
-                const uint32_t w = lpair[q];
-                if (w == 0xffffffffu) continue;
-                const int32_t a = w & 0xffff, b = w >> 16;
-                if (first[a] != q || first[b] != q) continue;
-                const double xa = lvx[a], ya = lvy[a], za = lvz[a];
-                const double xb = lvx[b], yb = lvy[b], zb = lvz[b];
-                const double rx = xa - xb, ry = ya - yb, rz = za - zb;
-                const double g = sqrt(rx * rx + ry * ry + rz * rz);
-                const double a0 = ldir[0][q], a1 = ldir[1][q], a2 = ldir[2][q];
-                const double inv = 1.0 / sqrt(a0 * a0 + a1 * a1 + a2 * a2);
-                const double u0 = a0 * inv, u1 = a1 * inv, u2 = a2 * inv;
-                const double cx = 0.5 * (xa + xb), cy = 0.5 * (ya + yb), cz = 0.5 * (za + zb);
-                const double px = 0.5 * g * u0, py = 0.5 * g * u1, pz = 0.5 * g * u2;
-                lvx[a] = (double)(T)(cx + px); lvy[a] = (double)(T)(cy + py); lvz[a] = (double)(T)(cz + pz);
-                lvx[b] = (double)(T)(cx - px); lvy[b] = (double)(T)(cy - py); lvz[b] = (double)(T)(cz - pz);
-                lpair[q] = 0xffffffffu;
-                ++done_here;
-            }
-            __syncthreads();
-            if (done_here) atomicSub(&s_remaining, done_here);
-            __syncthreads();
-        }
+        if (s_acc > 0) flush();
+        const int32_t na = s_base;
         // moment matching (centred), same arithmetic as the separate kernel
         bool write_raw = true;
         if (A.match && na > 0) {

@@ -48,7 +48,8 @@ def test_struct_layout_matches_header():
     structs = {"dsmc_vec3": L.Vec3, "dsmc_rng": L.Rng, "dsmc_status": L.Status,
                "dsmc_pairs": L.Pairs, "dsmc_xs": L.Xs, "dsmc_potential": L.Potential,
                "dsmc_quad": L.Quad, "dsmc_mlp": L.Mlp, "dsmc_anet": L.Anet,
-               "dsmc_chi_table": L.ChiTable, "dsmc_domain": L.Domain}
+               "dsmc_chi_table": L.ChiTable, "dsmc_domain": L.Domain,
+               "dsmc_match_schedule": L.MatchSchedule}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

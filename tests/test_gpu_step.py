@@ -76,6 +76,23 @@ def test_fused_step_bit_identical(dev, api, dtype, match):
     assert torch.equal(v1, v2)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fused_step_many_pairs_bit_identical(dev, api, dtype):
+    """Cells with more accepted pairs than one LDS batch holds (2048): the
+    fused kernel applies them in batches, in candidate order, and still
+    matches the separate entry points bit for bit."""
+    say("fused step, cells with thousands of pairs", dtype)
+    pop = W.ragged_population(33, 16, 2400, empty_frac=0.0, lam_scale=6.0)
+    cs, vs, lam = _prepare(api, dev, pop, dtype)
+    v1, pairs = _separate_step(api, dev, pop, cs, vs, lam, 5, 2, 1)
+    v2, cnt = _fused_step(api, dev, pop, cs, vs, lam, 5, 2, 1)
+    c = cnt.cpu().numpy()
+    say(f"  accepted pairs per cell: max {c.max()}, cells above 2048: {(c > 2048).sum()}")
+    assert (c > 2048).sum() >= 3
+    assert np.array_equal(c, pairs.cnt.cpu().numpy())
+    assert torch.equal(v1, v2)
+
+
 def test_fused_step_oversized_cell_left_alone(dev, api):
     say("fused step oversized cell")
     pop = W.ragged_population(32, 3, 4000, empty_frac=0.0)
@@ -93,8 +110,15 @@ def test_fused_step_oversized_cell_left_alone(dev, api):
         assert torch.equal(v2[:, ocs[k]:ocs[k + 1]], vs[:, ocs[k]:ocs[k + 1]])
 
 
-def test_graph_replay_matches_eager(dev, api):
-    say("hip graph of a whole neural step")
+@pytest.mark.parametrize("path", ["separate", "fused", "jager_fused"])
+def test_graph_replay_matches_eager(dev, api, path):
+    """A whole step captured as one HIP graph and replayed four times, with
+    eager work and synchronisations between replays: every replay equals the
+    eager step bit for bit.  "fused" is the benchmarked form (Phase A
+    deferred, Phase B fused with the moment matching); "jager_fused" the
+    same with the quadrature rule, whose FP64 refinement pass runs inside
+    the graph."""
+    say("hip graph of a whole step", path)
     pop = W.cavity_grid(seed=3, nx=60, ny=60)
     cell_of = torch.as_tensor(pop.cell_of, device=dev)
     v_in = torch.as_tensor(pop.v, dtype=torch.float32, device=dev).contiguous()
@@ -112,6 +136,8 @@ def test_graph_replay_matches_eager(dev, api):
     Ws, bs = W.mlp_init(1, W.SURROGATE_DIMS)
     net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev)
     col_ws = api.collide_ws(pairs.cap, v)
+    pot = api.potential_jager(W.JAGER_PLACEHOLDER)
+    quad = api.quad_struct(64)
     stream = torch.cuda.Stream()
 
     def step():
@@ -121,8 +147,18 @@ def test_graph_replay_matches_eager(dev, api):
                                       api._stream()), "sort")
         api.moment_match(cs, v, mom, api.L.MM_CAPTURE)
         api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 5, 2, pairs, ws=sel_ws, st=st)
-        api.neural_collide(net, v, pairs, 5, 2, ws=col_ws, st=st)
-        api.moment_match(cs, v, mom, api.L.MM_APPLY, pair_cnt=pairs.cnt, st=st)
+        if path == "separate":
+            api.neural_collide(net, v, pairs, 5, 2, ws=col_ws, st=st)
+            api.moment_match(cs, v, mom, api.L.MM_APPLY, pair_cnt=pairs.cnt, st=st)
+            return
+        if path == "fused":
+            api.neural_collide(net, v, pairs, 5, 2, schedule=api.L.SCHED_DEFER, ws=col_ws, st=st)
+            kind = api.L.APPLY_DIRECTIONS
+        else:
+            api.collide_jager(v, pairs, 5, 2, W.AR_MASS / 2, W.B_MAX, pot, quad=quad,
+                              schedule=api.L.SCHED_DEFER, ws=col_ws, st=st)
+            kind = api.L.APPLY_ANGLES
+        api.apply_pairs_match(cs, v, pairs, kind, mom, col_ws, st=st)
 
     with torch.cuda.stream(stream):
         step()  # eager warm-up (sets kernel attributes outside capture)
@@ -156,6 +192,37 @@ def test_autotune_installs_best_threshold(dev, api):
     say("  thresholds ms:", times)
     assert api.get_block_threshold() == thr
     assert times[thr] == min(times.values())
+
+
+def test_autotune_match_schedule(dev, api):
+    """The launch shape of the fused Phase B + moment matching: every shape
+    gives the same velocities bit for bit, and the tuner installs the
+    fastest on the step's own pair list."""
+    say("autotune fused phase B + match")
+    from paper_2602_21244_amd import autotune
+    pop = W.cylinder_grid(seed=5, order="realistic", scale=0.05)
+    cs, vs, lam = _prepare(api, dev, pop, torch.float32)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, vs, mom, api.L.MM_CAPTURE)
+    pairs = api.PairList(pop.n_cells, 1 << 22, dev)
+    api.select_pairs_ntc(cs, vs, pop.xs, lam, mom, 3, 1, pairs)
+    ws = api.collide_ws(pairs.cap, vs)
+    api.collide_vhs(vs.clone(), pairs, 3, 1, schedule=api.L.SCHED_DEFER, ws=ws)
+    before = api.get_match_schedule()
+    ref = None
+    for shape in ((40, 2, 1), (8, 1, 1), (64, 4, 2)):
+        api.set_match_schedule(*shape)
+        v = vs.clone()
+        api.apply_pairs_match(cs, v, pairs, api.L.APPLY_DIRECTIONS, mom, ws)
+        if ref is None:
+            ref = v
+        assert torch.equal(v, ref), shape
+    shape, times = autotune.tune_match_schedule(cs, vs, pairs, api.L.APPLY_DIRECTIONS, mom, ws,
+                                                use_cache=False)
+    say(f"  best {shape}: {times[shape]:.4f} ms (default {times[(40, 2, 1)]:.4f} ms)")
+    assert api.get_match_schedule() == shape
+    assert times[shape] == min(times.values())
+    api.set_match_schedule(*before)
 
 
 def test_autograd_function_matches_direct_calls(orc, dev, api):
