@@ -92,6 +92,8 @@ def main():
     log(f"workload {wname}: {pop.n} particles, {pop.n_cells} cells ({time.time() - t0:.1f}s)")
 
     stream = torch.cuda.current_stream()
+    hbm_ceiling = copy_ceiling(dev)
+    log(f"measured copy ceiling: {hbm_ceiling / 1e9:.0f} GB/s ({hbm_ceiling / PEAK_HBM:.2f} of 8 TB/s)")
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -334,6 +336,9 @@ def main():
         "stage_ms_neural": per_n,
         "stage_ms_quadrature": per_q,
         "sort_GBps_algorithmic": sort_bytes / (per_n["sort"] * 1e-3) / 1e9,
+        "hbm_copy_ceiling_GBps": hbm_ceiling / 1e9,
+        "stage_hbm": stage_rooflines({**per_n, "phaseA_vhs": per_v["phaseA"]}, n, n_cells,
+                                     n_pairs, hbm_ceiling),
         "table_pairs_per_s": n_pairs / (ms_t * 1e-3),
         "table_ms_per_step": ms_t,
         "stage_ms_table": per_t,
@@ -634,7 +639,13 @@ def cpu_baseline(pop, Ws, bs, sigma_v, sample_pairs):
     """The oracle's neural step timed on the host on a bounded sample of the
     same workload: a contiguous range of cells starting at grid row 120 (so it
     holds free-stream, shock-band and empty disc cells) with about
-    `sample_pairs` pairs."""
+    `sample_pairs` pairs.  Timed twice: one thread, and the same cells split
+    into contiguous ranges stepped concurrently on all usable cores (threads:
+    the oracle's C loops and numpy release the interpreter lock; its random
+    numbers are keyed by the global cell id, so the ranges give the same
+    result), BLAS pinned to one thread in both."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     try:
         from threadpoolctl import threadpool_limits
@@ -648,25 +659,85 @@ def cpu_baseline(pop, Ws, bs, sigma_v, sample_pairs):
     target_particles = int(sample_pairs / 0.5)
     k1 = int(np.searchsorted(cs, cs[k0] + target_particles))
     k1 = max(k0 + 1, min(k1, pop.n_cells))
-    sub_cs = (cs[k0: k1 + 1] - cs[k0]).astype(np.int32)
-    sub_v = v[:, cs[k0]: cs[k1]].copy()
-    sub_lam = pop.lam[k0:k1].copy()
     net = {"Ws": Ws, "bs": bs, "act": "silu", "sigma_v": sigma_v}
+
+    def run_range(a, b):
+        sub_cs = (cs[a: b + 1] - cs[a]).astype(np.int32)
+        sub_v = v[:, cs[a]: cs[b]].copy()
+        _, info = oracle.step(sub_cs, sub_v, pop.xs, pop.lam[a:b].copy(), 11, 0, rule="neural",
+                              net=net, cell_base=a)
+        return int(info["sel"]["pair_cnt"].sum())
+
+    try:
+        n_cores = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n_cores = os.cpu_count() or 1
+    n_cores = max(1, min(n_cores, 16))   # the host share of one GPU
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
         if ctx:
             ctx.__enter__()
         t = time.perf_counter()
-        _, info = oracle.step(sub_cs, sub_v, pop.xs, sub_lam, 11, 0, rule="neural", net=net,
-                              cell_base=k0)
-        dt = time.perf_counter() - t
+        npairs = run_range(k0, k1)
+        dt1 = time.perf_counter() - t
+        bounds = np.linspace(k0, k1, 4 * n_cores + 1).astype(int)
+        t = time.perf_counter()
+        with ThreadPoolExecutor(n_cores) as ex:
+            counts = list(ex.map(lambda ab: run_range(*ab), zip(bounds[:-1], bounds[1:])))
+        dtn = time.perf_counter() - t
     finally:
         if ctx:
             ctx.__exit__(None, None, None)
-    npairs = int(info["sel"]["pair_cnt"].sum())
-    return {"value": npairs / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"cells {k0}..{k1 - 1} of {pop.n_cells} ({int(sub_cs[-1])} particles, "
-                      f"{npairs} pairs), one oracle neural step, {dt:.1f} s"}
+    assert sum(counts) == npairs
+    sample = (f"cells {k0}..{k1 - 1} of {pop.n_cells} ({int(cs[k1] - cs[k0])} particles, "
+              f"{npairs} pairs), one oracle neural step")
+    return {"value": npairs / dtn, "unit": "pairs/s", "cores": n_cores, "kind": "oracle",
+            "sample": f"{sample}, {4 * n_cores} cell ranges on {n_cores} threads, {dtn:.1f} s",
+            "one_thread": {"value": npairs / dt1, "cores": 1, "seconds": dt1}}
+
+
+def copy_ceiling(dev, nbytes=1 << 30, reps=5):
+    """Measured HBM ceiling: a plain device-to-device copy (read + write)."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3)
+
+
+def stage_rooflines(per, n, n_cells, n_pairs, ceiling):
+    """Algorithmic HBM bytes of the memory-bound stages of the FP32 step and
+    their rate against the datasheet peak and the measured copy ceiling.
+    sort: 36 B/particle (cell id twice, v read + write, perm); moment capture:
+    12 B/particle + 48 B/cell; selection: 12 B/particle (velocities) + 12 B per
+    accepted pair (i, j, cell) + 8 B/cell (offset, count); isotropic Phase A:
+    48 B/pair (pair record 12, velocities 24, direction 12); Phase B + match:
+    24 B/particle + 24 B/pair (record 12, Phase-A result 12) + 56 B/cell
+    (moments 48, cell bounds 8)."""
+    bytes_ = {
+        "sort": 36.0 * n,
+        "moments": 12.0 * n + 48.0 * n_cells,
+        "select": 12.0 * n + 12.0 * n_pairs + 8.0 * n_cells,
+        "phaseA_vhs": 48.0 * n_pairs,
+        "phaseB_match": 24.0 * n + 24.0 * n_pairs + 56.0 * n_cells,
+    }
+    out = {}
+    for k, b in bytes_.items():
+        ms = per[k]
+        gbs = b / (ms * 1e-3) / 1e9
+        out[k] = {"bytes": b, "ms": ms, "GBps": gbs, "frac_datasheet": gbs * 1e9 / PEAK_HBM,
+                  "frac_copy_ceiling": gbs * 1e9 / ceiling}
+    return out
 
 
 if __name__ == "__main__":
