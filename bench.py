@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--anet-weights", default=os.path.join(ROOT, "paper_2602_21244_amd", "weights",
                                                           "jager_anet.npz"))
     p.add_argument("--table-steps", type=int, default=5)
+    p.add_argument("--split", default="front", choices=["front", "all"],
+                   help="bf16 pair activations in the first layers only (front) or in all")
     return p.parse_args()
 
 
@@ -131,7 +133,10 @@ def main():
     sel_ws = api.workspace(lib.dsmc_select_pairs_ntc_ws(n_cells, cap), dev)
 
     Ws, bs, sigma_v, wkind = load_weights(args.weights, W)
-    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=sigma_v, device=dev)
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=sigma_v, device=dev, split=args.split)
+    other_split = "all" if args.split == "front" else "front"
+    net_other = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=sigma_v, device=dev,
+                        split=other_split)
     col_ws = api.collide_ws(cap, v)
     pot = api.potential_jager(W.JAGER_PLACEHOLDER)
     quad = api.quad_struct(64)
@@ -226,6 +231,14 @@ def main():
     # neural directions of this step for the angle comparison
     es = 4
     dirs = col_ws[: 3 * (cap + 1) * es].view(torch.float32).view(3, cap + 1)[:, :n_pairs].clone()
+
+    # Phase A with the other activation split on the same pairs (the step's
+    # last selection): its time, and the angle between the two directions
+    split_cmp = phase_a_split_compare(api, L, net, net_other, v, pairs, col_ws, st, stream, cap,
+                                      n_pairs, args.steps)
+    split_cmp["timed_split"] = args.split
+    split_cmp["other_split"] = other_split
+    log(f"activation split: {split_cmp}")
 
     wall_q, ms_q, per_q = run("quadrature", 1, args.quad_steps)
     log(f"quadrature: {ms_q:.3f} ms/step, stages {json.dumps({k: round(x, 4) for k, x in per_q.items()})}")
@@ -323,7 +336,7 @@ def main():
     achieved = n_pairs * MLP_FLOP_PER_PAIR / t_mlp
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_BF16,
-                "traffic": counter_traffic("k_mlp_bf16<128, true, float, 0, false, 1, 512>"),
+                "traffic": counter_traffic(MLP_KERNEL[args.split]),
                 "kernel": "k_mlp_bf16 (Phase A of dsmc_neural_collide)",
                 "algorithmic_flop_per_pair": MLP_FLOP_PER_PAIR}
     sort_bytes = n * (4 + 4 + 12 + 12 + 4)  # cell id twice, v read + write, perm
@@ -348,6 +361,7 @@ def main():
         "ntc_select_ms": per_n["select"],
         "ce_viscosity_ms_64_temperatures": ce_ms,
         "eager_ms_per_step": ms_n,
+        "activation_split": split_cmp,
         "graph": graph,
         "match_schedule": {"shape_wave_medium_big_per_cu": list(match_shape),
                            "ms": match_times[match_shape], "default_ms": match_times[(40, 2, 1)]},
@@ -405,7 +419,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "particles": n, "cells": n_cells,
                    "pairs_per_step": n_pairs, "velocities": "fp32 SoA",
-                   "mlp": "8-128x4-3 SiLU bf16/fp32-acc", "moments": "fp64"},
+                   "mlp": "8-128x4-3 SiLU bf16/fp32-acc", "mlp_split": args.split,
+                   "moments": "fp64"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,
@@ -485,6 +500,36 @@ def fused_vhs_timing(api, lib, L, pop, cs, v, do_sort, lam, reps):
     return {"fused_kernel_ms": tot / reps, "step_ms_with_sort": tot / reps + float(np.mean(ms_sort)),
             "pairs": int(c.clamp(min=0).sum()), "cells_not_staged": int((c < 0).sum()),
             "max_pairs_in_a_cell": int(c.max())}
+
+
+MLP_KERNEL = {"all": "k_mlp_bf16<128, true, float, 0, false, 1, 512, 0>",
+              "front": "k_mlp_bf16<128, true, float, 0, false, 1, 512, 1>"}
+
+
+def phase_a_split_compare(api, L, net, net_other, v, pairs, col_ws, st, stream, cap, n_pairs, reps):
+    """Phase A (the network on every pair, directions deferred) with both
+    activation splits: mean event time of each, and the RMS / max angle
+    between their directions on the same pairs."""
+    import torch
+    out = {}
+    dirs = {}
+    for tag, nt in (("timed", net), ("other", net_other)):
+        api.neural_collide(nt, v, pairs, 11, 0, schedule=L.SCHED_DEFER, ws=col_ws, st=st)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            api.neural_collide(nt, v, pairs, 11, 0, schedule=L.SCHED_DEFER, ws=col_ws, st=st)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[f"{tag}_phaseA_ms"] = e0.elapsed_time(e1) / reps
+        dirs[tag] = col_ws[: 3 * (cap + 1) * 4].view(torch.float32).view(3, cap + 1)[:, :n_pairs].double()
+    a, b = dirs["timed"], dirs["other"]
+    c = (a * b).sum(0) / (a.norm(dim=0) * b.norm(dim=0))
+    ang = torch.arccos(torch.clamp(c, -1.0, 1.0))
+    out["angle_rms_between_rad"] = float(torch.sqrt(torch.mean(ang ** 2)))
+    out["angle_max_between_rad"] = float(ang.max())
+    return out
 
 
 def counter_traffic(kernel, source="mlp.hip"):

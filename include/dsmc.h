@@ -143,6 +143,17 @@ typedef struct {
  * (eq. mlp_input plus the two impact latents), so dims[0] must be 8 for the
  * in-step entry point. */
 enum { DSMC_ACT_SILU = 0, DSMC_ACT_RELU = 1 };
+/* How activations enter the matrix cores on the bf16 path (dsmc_mlp.split).
+ * DSMC_SPLIT_ALL (0, the default of a zeroed struct): the network input and
+ * every hidden activation as a bf16 pair hi + lo (16 significant bits); the
+ * result is that of the bf16 weights to ~1e-4 rad in direction.
+ * DSMC_SPLIT_FRONT: the input and the first two hidden activations as pairs,
+ * later hidden activations as one bf16 value: about a sixth fewer matrix
+ * operations and conversions, at a direction error of a few 1e-3 rad for a
+ * trained 8-128x4-3 network (rounding early in the network is amplified
+ * most).  Applies to dsmc_neural_collide; the row entry points always use
+ * DSMC_SPLIT_ALL. */
+enum { DSMC_SPLIT_ALL = 0, DSMC_SPLIT_FRONT = 1 };
 typedef struct {
     int32_t n_layers;
     int32_t dims[7];
@@ -151,6 +162,8 @@ typedef struct {
     const void* W[6];
     const void* b[6];
     double sigma_v;
+    int32_t split;
+    int32_t reserved;
 } dsmc_mlp;
 
 /* Phase-B schedules: LANE: one lane walks a cell's pairs in order; WAVE: one

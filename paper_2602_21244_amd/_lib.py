@@ -15,6 +15,7 @@ WALL_PERIODIC, WALL_SPECULAR, WALL_DIFFUSE = 0, 1, 2
 XS_VHS, XS_CONST = 0, 1
 POT_JAGER, POT_HS, POT_INVPOW = 0, 1, 2
 ACT_SILU, ACT_RELU = 0, 1
+SPLIT_ALL, SPLIT_FRONT = 0, 1
 SCHED_AUTO, SCHED_LANE, SCHED_BLOCK, SCHED_DEFER, SCHED_WAVE = 0, 1, 2, 3, 4
 APPLY_DIRECTIONS, APPLY_ANGLES = 0, 1
 MM_CAPTURE, MM_APPLY, MM_APPLY_LITERAL = 0, 1, 2
@@ -74,7 +75,7 @@ class Quad(C.Structure):
 class Mlp(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("dims", C.c_int32 * 7), ("act", C.c_int32),
                 ("wdtype", C.c_int32), ("W", C.c_void_p * 6), ("b", C.c_void_p * 6),
-                ("sigma_v", C.c_double)]
+                ("sigma_v", C.c_double), ("split", C.c_int32), ("reserved", C.c_int32)]
 
 
 ANET_MAX_LAYERS = 8

@@ -113,8 +113,14 @@ def quad_struct(n_nodes=64, max_iter=60, scan_ratio=0.95, refine=0):
 class Net:
     """Device copy of an MLP for the C-ABI (keeps the tensors alive)."""
 
-    def __init__(self, Ws, bs, act="silu", wdtype="bf16", sigma_v=1.0, device="cuda"):
+    def __init__(self, Ws, bs, act="silu", wdtype="bf16", sigma_v=1.0, device="cuda",
+                 split="all"):
+        """split: "all" (every activation a bf16 pair) or "front" (the input
+        and the first two hidden activations only), see dsmc_mlp.split."""
+        if split not in ("all", "front"):
+            raise ValueError(split)
         self.dims = [int(Ws[0].shape[1])] + [int(w.shape[0]) for w in Ws]
+        self.split = split
         self.act = act
         self.wdtype = wdtype
         self.sigma_v = float(sigma_v)
@@ -145,6 +151,7 @@ class Net:
             m.W[q] = self.W[q].data_ptr()
             m.b[q] = self.b[q].data_ptr()
         m.sigma_v = self.sigma_v
+        m.split = L.SPLIT_FRONT if self.split == "front" else L.SPLIT_ALL
         self.struct = m
         return m
 

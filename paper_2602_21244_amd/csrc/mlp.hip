@@ -40,6 +40,7 @@ struct MlpDev {
     const void* W[MLP_MAX_LAYERS];
     const void* b[MLP_MAX_LAYERS];
     double inv_sigma_v;
+    int split;
 };
 
 static int check_mlp(const dsmc_mlp* net, MlpDev* d)
@@ -65,6 +66,9 @@ static int check_mlp(const dsmc_mlp* net, MlpDev* d)
     if (!(net->sigma_v > 0)) return arg_error("dsmc_mlp: sigma_v must be > 0");
     d->inv_sigma_v = 1.0 / net->sigma_v;
     d->act = net->act;
+    if (net->split != DSMC_SPLIT_ALL && net->split != DSMC_SPLIT_FRONT)
+        return arg_error("dsmc_mlp: split %d", net->split);
+    d->split = net->split;
     return DSMC_OK;
 }
 
@@ -219,17 +223,31 @@ __device__ __forceinline__ bf16x8 lds_frag(const __bf16* wl, int off, int frag, 
 // Row mapping of accumulator register r for lane-half h.
 __device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
-// Activation of 8 accumulator values as a bf16 pair: hi = bf16(v), lo =
-// bf16(v - hi).
-template <int ACT>
+typedef __bf16 bf16x2 __attribute__((__vector_size__(2 * sizeof(__bf16))));
+
+// Activation of 8 accumulator values as bf16 fragments.  PAIR: hi = bf16(v)
+// and lo = bf16(v - hi); two values are rounded by one conversion and hi is
+// read back as floats by shifting/masking the packed halves.  Otherwise hi
+// only (lo is left untouched).
+template <int ACT, bool PAIR>
 __device__ __forceinline__ void to_frag(const floatx16& a, int jp, bf16x8& hi, bf16x8& lo)
 {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const float v = act_scaled<ACT>(a[8 * jp + e]);
-        const __bf16 h = (__bf16)v;
-        hi[e] = h;
-        lo[e] = (__bf16)(v - (float)h);
+    for (int e = 0; e < 8; e += 2) {
+        const float v0 = act_scaled<ACT>(a[8 * jp + e]);
+        const float v1 = act_scaled<ACT>(a[8 * jp + e + 1]);
+        bf16x2 hp;
+        hp[0] = (__bf16)v0;
+        hp[1] = (__bf16)v1;
+        hi[e] = hp[0];
+        hi[e + 1] = hp[1];
+        if (PAIR) {
+            const uint32_t u = __builtin_bit_cast(uint32_t, hp);
+            const float h0 = __builtin_bit_cast(float, u << 16);
+            const float h1 = __builtin_bit_cast(float, u & 0xffff0000u);
+            lo[e] = (__bf16)(v0 - h0);
+            lo[e + 1] = (__bf16)(v1 - h1);
+        }
     }
 }
 
@@ -265,7 +283,8 @@ __device__ __forceinline__ void box_muller_hw(float ua, float ub, float& n1, flo
 // nxt receives s of this layer (NBO blocks).  The activation of block nb
 // produces the inputs of k steps 2 nb and 2 nb + 1, whose MFMAs are issued
 // right away, so the matrix cores run while the next block is activated.
-template <int NB, int NBO, int NT, int ACT>
+// PAIR: each input as a bf16 pair (two MFMAs per k step), else one bf16.
+template <int NB, int NBO, int NT, int ACT, bool PAIR>
 __device__ __forceinline__ void layer_step(const __bf16* wl, int off, int ksl,
                                            const floatx16 (&acc)[NT][NB],
                                            floatx16 (&nxt)[NT][NBO], const bf16x8& bone,
@@ -284,8 +303,8 @@ __device__ __forceinline__ void layer_step(const __bf16* wl, int off, int ksl,
         bf16x8 b0[NT], b1[NT], c0[NT], c1[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            to_frag<ACT>(acc[t][nb], 0, b0[t], c0[t]);
-            to_frag<ACT>(acc[t][nb], 1, b1[t], c1[t]);
+            to_frag<ACT, PAIR>(acc[t][nb], 0, b0[t], c0[t]);
+            to_frag<ACT, PAIR>(acc[t][nb], 1, b1[t], c1[t]);
         }
 #pragma unroll
         for (int nb2 = 0; nb2 < NBO; ++nb2) {
@@ -294,9 +313,11 @@ __device__ __forceinline__ void layer_step(const __bf16* wl, int off, int ksl,
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0[t], nxt[t][nb2], 0, 0, 0);
-                nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, c0[t], nxt[t][nb2], 0, 0, 0);
+                if (PAIR)
+                    nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, c0[t], nxt[t][nb2], 0, 0, 0);
                 nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[t], nxt[t][nb2], 0, 0, 0);
-                nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, c1[t], nxt[t][nb2], 0, 0, 0);
+                if (PAIR)
+                    nxt[t][nb2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, c1[t], nxt[t][nb2], 0, 0, 0);
             }
         }
     }
@@ -323,7 +344,7 @@ __device__ __forceinline__ void save_pre(const RowsIO& rio, int l, const int64_t
 // Each wave processes NT tiles of 32 rows; every A fragment read from LDS
 // feeds NT MFMAs.  Pairs mode: the lane of row r in lane-half 0 computes the
 // pair's xi, the lane in lane-half 1 its z and v_r (dims[0] == 8).
-template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT, int TPB>
+template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT, int TPB, int SPLIT>
 __global__ void __launch_bounds__(TPB)
 k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
 {
@@ -338,7 +359,6 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
     const int64_t nrows = PAIRS ? pio.pr.total(pio.n_cells) : rio.B;
     const int L = d.L, dout = d.dims[L];
     constexpr int NB = H / 32;
-    const int ks_hidden = H / 16 + 1;
     bf16x8 bone;
 #pragma unroll
     for (int e = 0; e < 8; ++e) bone[e] = (__bf16)((h == 0 && e < 2) ? 1.0f : 0.0f);
@@ -484,24 +504,45 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
             }
         }
         // hidden layers, two at a time so the accumulators alternate
-        // between two register sets without copies
+        // between two register sets without copies.  With SPLIT == FRONT
+        // only layers 1 and 2 take pair inputs: they form the first pass
+        // of the loop, and the tail (layers l and l + 1) is paired when
+        // l < 3.
+        constexpr bool LATE = SPLIT == DSMC_SPLIT_ALL;
+        const int ks = H / 16 + 1;
         floatx16 alt[NT][NB];
         floatx16 ao[NT][1];
         int l = 1;
+        if (l + 1 < L - 1) {
+            save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
+            layer_step<NB, NB, NT, ACT, true>(wl, f.off[l], ks, acc, alt, bone, lane);
+            save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
+            layer_step<NB, NB, NT, ACT, true>(wl, f.off[l + 1], ks, alt, acc, bone, lane);
+            l += 2;
+        }
         for (; l + 1 < L - 1; l += 2) {
             save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
-            layer_step<NB, NB, NT, ACT>(wl, f.off[l], ks_hidden, acc, alt, bone, lane);
+            layer_step<NB, NB, NT, ACT, LATE>(wl, f.off[l], ks, acc, alt, bone, lane);
             save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
-            layer_step<NB, NB, NT, ACT>(wl, f.off[l + 1], ks_hidden, alt, acc, bone, lane);
+            layer_step<NB, NB, NT, ACT, LATE>(wl, f.off[l + 1], ks, alt, acc, bone, lane);
         }
-        if (l < L - 1) {
-            save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
-            layer_step<NB, NB, NT, ACT>(wl, f.off[l], ks_hidden, acc, alt, bone, lane);
-            save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
-            layer_step<NB, 1, NT, ACT>(wl, f.off[L - 1], ks_hidden, alt, ao, bone, lane);
+        if (LATE || l < 3) {
+            if (l < L - 1) {
+                save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
+                layer_step<NB, NB, NT, ACT, true>(wl, f.off[l], ks, acc, alt, bone, lane);
+                save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
+                layer_step<NB, 1, NT, ACT, true>(wl, f.off[L - 1], ks, alt, ao, bone, lane);
+            } else {
+                save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
+                layer_step<NB, 1, NT, ACT, true>(wl, f.off[L - 1], ks, acc, ao, bone, lane);
+            }
         } else {
-            save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
-            layer_step<NB, 1, NT, ACT>(wl, f.off[L - 1], ks_hidden, acc, ao, bone, lane);
+            if (l < L - 1) {
+                layer_step<NB, NB, NT, ACT, false>(wl, f.off[l], ks, acc, alt, bone, lane);
+                layer_step<NB, 1, NT, ACT, false>(wl, f.off[L - 1], ks, alt, ao, bone, lane);
+            } else {
+                layer_step<NB, 1, NT, ACT, false>(wl, f.off[L - 1], ks, acc, ao, bone, lane);
+            }
         }
         // output layer result: y = s / c, <= 32 outputs in one block
 #pragma unroll
@@ -552,27 +593,16 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
     }
 }
 
-// Launch shape of the fused kernel: 1 = one 32-row tile per wave, 512-thread
-// workgroups (two waves per SIMD share the LDS copy of the weights); 2 = two
-// tiles per wave (each weight fragment read from LDS feeds two MFMAs),
-// 256 threads; 3 = one tile per wave, 256 threads (one wave per SIMD with the
-// whole register file).  DSMC_MLP_CONFIG selects it (default 1).
-static int mlp_config()
-{
-    static int cfg = -1;
-    if (cfg < 0) {
-        const char* e = getenv("DSMC_MLP_CONFIG");
-        const int v = e ? atoi(e) : 1;
-        cfg = (v == 2 || v == 3) ? v : 1;
-    }
-    return cfg;
-}
-
-template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int NT, int TPB>
+// Launch shape of the fused kernel: one 32-row tile per wave; 512-thread
+// workgroups (two waves per SIMD share the LDS copy of the weights) for
+// hidden width 64 and 128, 256 threads (one wave per SIMD with the whole
+// register file) for width 256.  A persistent grid of one workgroup per CU.
+template <int H, bool PAIRS, typename VT, int ACT, bool SAVE, int SPLIT>
 static int launch_one(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
                       int64_t max_rows, hipStream_t s)
 {
-    auto kern = k_mlp_bf16<H, PAIRS, VT, ACT, SAVE, NT, TPB>;
+    constexpr int NT = 1, TPB = H == 256 ? 256 : 512;
+    auto kern = k_mlp_bf16<H, PAIRS, VT, ACT, SAVE, NT, TPB, SPLIT>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -590,27 +620,31 @@ static int launch_one(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<
     return DSMC_OK;
 }
 
-template <int H, bool PAIRS, typename VT, int ACT, bool SAVE>
-static int launch_nt(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
-                     int64_t max_rows, hipStream_t s)
+// The row entry points (PAIRS false) save pre-activations on request and
+// always carry every activation as a pair; the in-step entry point never
+// saves and follows the network's split setting.
+template <int H, bool PAIRS, typename VT, int ACT>
+static int launch_act(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
+                      int64_t max_rows, hipStream_t s)
 {
-    const int cfg = H == 256 ? 3 : mlp_config();
-    if (cfg == 2) return launch_one<H, PAIRS, VT, ACT, SAVE, 2, 256>(d, f, rio, pio, max_rows, s);
-    if (cfg == 3) return launch_one<H, PAIRS, VT, ACT, SAVE, 1, 256>(d, f, rio, pio, max_rows, s);
-    return launch_one<H, PAIRS, VT, ACT, SAVE, 1, 512>(d, f, rio, pio, max_rows, s);
+    if constexpr (PAIRS) {
+        if (d.split == DSMC_SPLIT_FRONT)
+            return launch_one<H, PAIRS, VT, ACT, false, DSMC_SPLIT_FRONT>(d, f, rio, pio, max_rows, s);
+        return launch_one<H, PAIRS, VT, ACT, false, DSMC_SPLIT_ALL>(d, f, rio, pio, max_rows, s);
+    } else {
+        if (rio.zsave != nullptr)
+            return launch_one<H, PAIRS, VT, ACT, true, DSMC_SPLIT_ALL>(d, f, rio, pio, max_rows, s);
+        return launch_one<H, PAIRS, VT, ACT, false, DSMC_SPLIT_ALL>(d, f, rio, pio, max_rows, s);
+    }
 }
 
 template <int H, bool PAIRS, typename VT>
 static int launch_mlp_bf16(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<VT> pio,
                            int64_t max_rows, hipStream_t s)
 {
-    const bool save = !PAIRS && rio.zsave != nullptr;
-    if (d.act == DSMC_ACT_SILU) {
-        if (save) return launch_nt<H, PAIRS, VT, DSMC_ACT_SILU, true>(d, f, rio, pio, max_rows, s);
-        return launch_nt<H, PAIRS, VT, DSMC_ACT_SILU, false>(d, f, rio, pio, max_rows, s);
-    }
-    if (save) return launch_nt<H, PAIRS, VT, DSMC_ACT_RELU, true>(d, f, rio, pio, max_rows, s);
-    return launch_nt<H, PAIRS, VT, DSMC_ACT_RELU, false>(d, f, rio, pio, max_rows, s);
+    if (d.act == DSMC_ACT_SILU)
+        return launch_act<H, PAIRS, VT, DSMC_ACT_SILU>(d, f, rio, pio, max_rows, s);
+    return launch_act<H, PAIRS, VT, DSMC_ACT_RELU>(d, f, rio, pio, max_rows, s);
 }
 
 // ------------------------------------------------------------------------

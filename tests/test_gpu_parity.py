@@ -534,13 +534,14 @@ def _angle(a, b):
     return np.arccos(np.clip(c, -1, 1))
 
 
+@pytest.mark.parametrize("split", ["all", "front"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_neural_bf16_chi_rms(orc, dev, api, dtype):
-    say("neural bf16 mfma", dtype)
+def test_neural_bf16_chi_rms(orc, dev, api, dtype, split):
+    say("neural bf16 mfma", dtype, split)
     pop = W.cavity_grid(seed=3, nx=40, ny=40)
     cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, dtype, seed=9, step=1)
     Ws, bs = _net_params(4, W.SURROGATE_DIMS)
-    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev)
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev, split=split)
     ws = api.neural_ws(net, pairs, vs)
     vn = vs.clone()
     api.neural_collide(net, vn, pairs, 9, 1, ws=ws, st=st)
