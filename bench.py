@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 MLP_FLOP_PER_PAIR = 2 * (8 * 128 + 3 * 128 * 128 + 128 * 3)  # 101,120 (unpadded)
 PEAK_BF16 = 2.5e15
 PEAK_HBM = 8.0e12
+PEAK_FP32 = 157.3e12   # vector FP32
+PEAK_FP64 = 78.6e12    # vector FP64
 
 
 def log(*a):
@@ -43,6 +45,8 @@ def parse():
     p.add_argument("--order", default="realistic", choices=["realistic", "shuffled", "sorted"])
     p.add_argument("--quad-steps", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip the shuffled-order and FP64-velocity neural step timings")
     p.add_argument("--no-cavity-loop", action="store_true",
                    help="skip the cavity flow-loop timing (profiling runs of the step kernels)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -348,6 +352,7 @@ def main():
         "network_weights": wkind,
         "stage_ms_neural": per_n,
         "stage_ms_quadrature": per_q,
+        "quadrature_valu_roofline": quadrature_valu_roofline(per_q["phaseA"]),
         "sort_GBps_algorithmic": sort_bytes / (per_n["sort"] * 1e-3) / 1e9,
         "hbm_copy_ceiling_GBps": hbm_ceiling / 1e9,
         "stage_hbm": stage_rooflines({**per_n, "phaseA_vhs": per_v["phaseA"]}, n, n_cells,
@@ -377,6 +382,15 @@ def main():
         "cells": n_cells,
         "deflection_batch_2p20": batch,
     }
+
+    # the same neural step with the particles fully shuffled (worst case for
+    # the sort and the gathers) and with FP64 velocities
+    if args.workload == "cylinder" and not args.no_variants:
+        for tag, order, vdt in (("shuffled_fp32", "shuffled", torch.float32),
+                                ("realistic_fp64", "realistic", torch.float64)):
+            extra[f"neural_step_{tag}"] = variant_step_timing(W, api, L, dev, net, order, vdt,
+                                                              max(3, args.steps // 2))
+            log(f"neural step, {tag}: {extra[f'neural_step_{tag}']}")
 
     # surrogate training step (batch 65 536 harvested rows): forward (MFMA),
     # MSE, hand-written backward, Adam on every parameter
@@ -426,6 +440,76 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def variant_step_timing(W, api, L, dev, net, order, vdtype, steps, warm=2):
+    """The timed neural step (sort, capture, NTC select, network Phase A,
+    fused Phase B + matching) on the cylinder population in another particle
+    order and/or velocity precision: mean event time per step and stage."""
+    import torch
+    pop = W.cylinder_grid(seed=5, order=order)
+    code = L.F64 if vdtype == torch.float64 else L.F32
+    cell_of = torch.as_tensor(pop.cell_of, device=dev)
+    v_in = torch.as_tensor(pop.v, dtype=vdtype, device=dev).contiguous()
+    lam = torch.as_tensor(pop.lam, device=dev)
+    n, nc = pop.n, pop.n_cells
+    v = torch.empty_like(v_in)
+    cs = torch.empty(nc + 1, dtype=torch.int32, device=dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    mom = torch.zeros(nc * 6, dtype=torch.float64, device=dev)
+    st = api.new_status(dev)
+    lib = api.lib()
+    swb = lib.dsmc_sort_cells_ws(n, nc)
+    sws = api.workspace(swb, dev)
+    stream = torch.cuda.current_stream()
+
+    def do_sort():
+        api.check(lib.dsmc_sort_cells(n, nc, api._ptr(cell_of), code, api._vec3(v_in), api._vec3(v),
+                                      api._ptr(cs), api._ptr(perm), api._ptr(sws), swb, api._ptr(st),
+                                      api._stream()), "sort")
+
+    do_sort()
+    api.moment_match(cs, v, mom, L.MM_CAPTURE)
+    probe = api.PairList(nc, 1, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, probe, st=st)
+    cap = int(api.read_status(st).n_cand * 1.02) + 1024
+    pairs = api.PairList(nc, cap, dev)
+    sel_ws = api.workspace(lib.dsmc_select_pairs_ntc_ws(nc, cap), dev)
+    col_ws = api.collide_ws(cap, v)
+
+    def step(ev=None):
+        if ev: ev[0].record(stream)
+        do_sort()
+        if ev: ev[1].record(stream)
+        api.moment_match(cs, v, mom, L.MM_CAPTURE)
+        if ev: ev[2].record(stream)
+        api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, pairs, ws=sel_ws, st=st)
+        if ev: ev[3].record(stream)
+        api.neural_collide(net, v, pairs, 11, 0, schedule=L.SCHED_DEFER, ws=col_ws, st=st)
+        if ev: ev[4].record(stream)
+        api.apply_pairs_match(cs, v, pairs, L.APPLY_DIRECTIONS, mom, col_ws, mode=L.MM_APPLY, st=st)
+        if ev: ev[5].record(stream)
+
+    for _ in range(warm):
+        step()
+    torch.cuda.synchronize()
+    api.status_clear(st)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    for q in range(steps):
+        step(evs[q])
+    torch.cuda.synchronize()
+    names = ["sort", "moments", "select", "phaseA", "phaseB_match"]
+    per = {nm: float(np.mean([evs[q][k].elapsed_time(evs[q][k + 1]) for q in range(steps)]))
+           for k, nm in enumerate(names)}
+    ms = float(np.mean([evs[q][0].elapsed_time(evs[q][5]) for q in range(steps)]))
+    s = api.read_status(st)
+    n_pairs = int(pairs.cnt.sum())
+    out = {"order": order, "velocities": "fp64" if code == L.F64 else "fp32", "particles": n,
+           "pairs_per_step": n_pairs, "ms_per_step": ms, "pairs_per_s": n_pairs / (ms * 1e-3),
+           "stage_ms": per, "status_flags": int(s.flags)}
+    del v_in, v, pairs, col_ws, sel_ws, sws
+    torch.cuda.empty_cache()
+    return out
 
 
 def graph_replay_timing(step, v, reps):
@@ -532,6 +616,33 @@ def phase_a_split_compare(api, L, net, net_other, v, pairs, col_ws, st, stream, 
     return out
 
 
+def quadrature_valu_roofline(ms_phase_a):
+    """Executed VALU flop of the in-step quadrature (lane rule plus its FP64
+    refinement pass) from the committed rocprofv3 operation counts, over the
+    live event time of that Phase A; null when the counts were taken on
+    another build of deflect.hip."""
+    from paper_2602_21244_amd.build import compile_signature
+    path = os.path.join(ROOT, "profiles", "valu_flops_quadrature_mach10_cylinder_400x300.md")
+    if not os.path.exists(path):
+        return None
+    try:
+        blob = json.loads(open(path).read().split("```json", 1)[1].split("```", 1)[0])
+        ks = [blob["kernels"]["k_phaseA_jager_f32"], blob["kernels"]["k_refine<PhaseAJagerJob<float> >"]]
+    except (IndexError, KeyError, ValueError):
+        return None
+    if blob.get("compile_signature") != compile_signature(blob.get("source", "deflect.hip")):
+        return None
+    f32 = sum(k["fp32_flop"] for k in ks)
+    f64 = sum(k["fp64_flop"] for k in ks)
+    t = ms_phase_a * 1e-3
+    r32, r64 = f32 / t, f64 / t
+    return {"bound": "alu", "kernels": "k_phaseA_jager_f32 + k_refine (FP64)",
+            "fp32_flop": f32, "fp64_flop": f64, "ms": ms_phase_a,
+            "achieved_fp32_TFLOPs": r32 / 1e12, "achieved_fp64_TFLOPs": r64 / 1e12,
+            "peak_fp32_TFLOPs": PEAK_FP32 / 1e12, "peak_fp64_TFLOPs": PEAK_FP64 / 1e12,
+            "frac": r32 / PEAK_FP32 + r64 / PEAK_FP64}
+
+
 def counter_traffic(kernel, source="mlp.hip"):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy), or None when the
@@ -555,7 +666,7 @@ def deflection_batch_timing(api, W, dev, pot, quad, anet, lne_lo, lne_hi, reps=3
     import torch
     b, g, mr = W.deflection_batch(seed=2, n=1 << 20)
     out = {"pairs": int(b.size)}
-    th = {}
+    th, raw = {}, {}
     for name, dt in (("quadrature_fp64", torch.float64), ("quadrature_fp32", torch.float32)):
         bt = torch.as_tensor(b, dtype=dt, device=dev)
         gt = torch.as_tensor(g, dtype=dt, device=dev)
@@ -569,6 +680,7 @@ def deflection_batch_timing(api, W, dev, pot, quad, anet, lne_lo, lne_hi, reps=3
         ms = e0.elapsed_time(e1) / reps
         out[name] = {"ms": ms, "pairs_per_s": b.size / (ms * 1e-3)}
         th[name] = torch.arccos(torch.clamp(torch.cos(chi.double()), -1, 1))
+        raw[name] = chi.double()
     b64 = torch.as_tensor(b, device=dev)
     g64 = torch.as_tensor(g, device=dev)
     chi64 = torch.as_tensor(th["quadrature_fp64"], device=dev)
@@ -586,6 +698,20 @@ def deflection_batch_timing(api, W, dev, pot, quad, anet, lne_lo, lne_hi, reps=3
     ref = th["quadrature_fp64"]
     out["theta_rms_fp32_vs_fp64_rad"] = float(torch.sqrt(((th["quadrature_fp32"] - ref) ** 2).mean()))
     out["theta_rms_network_vs_fp64_rad"] = float(torch.sqrt(((th_net - ref) ** 2).mean()))
+    # chi itself (not folded into [0, pi]): FP32 against FP64, all pairs and
+    # the orbiting ones (|chi| > pi) separately
+    c64, c32 = raw["quadrature_fp64"], raw["quadrature_fp32"]
+    d = (c32 - c64).abs()
+    orb = c64.abs() > math.pi
+
+    def dist(x):
+        if x.numel() == 0:
+            return {"pairs": 0}
+        return {"pairs": int(x.numel()), "rms": float(torch.sqrt((x ** 2).mean())),
+                "max": float(x.max()), "p99_9": float(torch.quantile(x.float(), 0.999))}
+
+    out["chi_fp32_vs_fp64_rad"] = {"all": dist(d), "orbiting": dist(d[orb]),
+                                   "not_orbiting": dist(d[~orb])}
     return out
 
 
