@@ -14,6 +14,7 @@ Prints ONE JSON line.  --gpus above 1 exits: the path is measured on one GPU.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -209,11 +210,16 @@ def main():
             step(rule)
         torch.cuda.synchronize()
         evs = [stage_events(6) for _ in range(steps)]
+        # no collector pause while the steps are queued: the GPU would idle
+        # between two events and the gap would count as stage time
+        gc.collect()
+        gc.disable()
         t_start = time.perf_counter()
         for q in range(steps):
             step(rule, evs[q])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
+        gc.enable()
         per = {nm: float(np.mean([evs[q][s].elapsed_time(evs[q][s + 1]) for q in range(steps)]))
                for s, nm in enumerate(names)}
         tot = float(np.mean([evs[q][0].elapsed_time(evs[q][5]) for q in range(steps)]))
@@ -495,9 +501,12 @@ def variant_step_timing(W, api, L, dev, net, order, vdtype, steps, warm=2):
     torch.cuda.synchronize()
     api.status_clear(st)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    gc.collect()
+    gc.disable()
     for q in range(steps):
         step(evs[q])
     torch.cuda.synchronize()
+    gc.enable()
     names = ["sort", "moments", "select", "phaseA", "phaseB_match"]
     per = {nm: float(np.mean([evs[q][k].elapsed_time(evs[q][k + 1]) for q in range(steps)]))
            for k, nm in enumerate(names)}
