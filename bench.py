@@ -780,12 +780,11 @@ def train_step_timing(api, W, dev, net, sigma_v, B=65536, steps=5):
     e1.record()
     torch.cuda.synchronize()
     harvest_ms = e0.elapsed_time(e1)
-    master = []
-    for w, b in zip(net.W, net.b):
-        master += [w.float().clone(), b.clone()]
-    ms_ = [torch.zeros_like(p) for p in master]
-    vs_ = [torch.zeros_like(p) for p in master]
-    grads = [torch.zeros_like(p) for p in master]
+    from paper_2602_21244_amd.train import FlatParams
+    Ws = [w.float().cpu().numpy() for w in net.W]
+    bs = [b.cpu().numpy() for b in net.b]
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=sigma_v, device=dev)
+    params = FlatParams(net, Ws, bs, dev)
     act = api.workspace(api.neural_act_bytes(net, B), dev)
     bws = api.workspace(api.lib().dsmc_neural_backward_ws(ctypes.byref(net.struct), B), dev)
     dvr = torch.empty(B, 3, dtype=torch.float32, device=dev)
@@ -795,11 +794,8 @@ def train_step_timing(api, W, dev, net, sigma_v, B=65536, steps=5):
     def one(t):
         y, vr = api.neural_forward_rows(net, x, g, act_save=act)
         api.mse_loss(vr, tgt, sigma_v, dvr, loss)
-        api.neural_backward(net, x, act, y, g, dvr, grads[0::2], grads[1::2], ws=bws)
-        for l in range(len(net.W)):
-            api.adam_step(master[2 * l], grads[2 * l], ms_[2 * l], vs_[2 * l], t, 1e-4,
-                          param_bf16=net.W[l])
-            api.adam_step(master[2 * l + 1], grads[2 * l + 1], ms_[2 * l + 1], vs_[2 * l + 1], t, 1e-4)
+        api.neural_backward(net, x, act, y, g, dvr, params.dW, params.db, ws=bws)
+        params.step(t, 1e-4)
 
     one(1)
     torch.cuda.synchronize()

@@ -380,7 +380,9 @@ int dsmc_moment_match_backward(int32_t n_cells, const int32_t* cell_start, const
 
 /* Training helpers.  MSE on the post-collision velocities of the pair,
  * L = (1/B) sum |v_r' - v_r'*|^2 / (4 sigma_v^2); writes dL/dv_r' and adds L
- * to *loss (device double).  Arrays FP32 [B][3]. */
+ * to *loss (device double; workgroup partial sums are added atomically, so
+ * the last bits of L may differ between runs, dL/dv_r' does not).  Arrays
+ * FP32 [B][3]. */
 int dsmc_mse_loss(int64_t B, const float* vr_new, const float* vr_target, double sigma_v,
                   float* dL_dvr, double* loss, dsmc_stream_t stream);
 
@@ -388,8 +390,8 @@ int dsmc_mse_loss(int64_t B, const float* vr_new, const float* vr_target, double
  * the surrogate's loss on the scattering directions): with g = |v_r'*|,
  * L = (1/B) sum |v_r' - v_r'*|^2 / (4 g^2) = (1/B) sum |u - u*|^2 / 4, the
  * velocity MSE above with each pair normalised by its own g^2; writes dL/dv_r'
- * and adds L to *loss.  Rows with v_r'* = 0 contribute nothing.  Arrays FP32
- * [B][3]. */
+ * and adds L to *loss (atomically per workgroup, as above).  Rows with
+ * v_r'* = 0 contribute nothing.  Arrays FP32 [B][3]. */
 int dsmc_direction_loss(int64_t B, const float* vr_new, const float* vr_target, float* dL_dvr,
                         double* loss, dsmc_stream_t stream);
 

@@ -1120,55 +1120,47 @@ static size_t backward_ws_bytes(const MlpDev& d, int64_t B, size_t es)
 // ------------------------------------------------------------------------
 // Training helpers
 // ------------------------------------------------------------------------
-// Single workgroup: gradient and the loss sum in a fixed order (deterministic).
-__global__ void __launch_bounds__(1024)
-k_mse(int64_t B, const float* __restrict__ a, const float* __restrict__ t, double scale,
-      float* __restrict__ grad, double* loss)
+// Loss kernels: a grid of workgroups, each summing its rows in a fixed order
+// and adding its share to *loss with one FP64 atomic (the order of those few
+// hundred additions varies between runs; the gradient does not).
+__device__ __forceinline__ void block_add_loss(double acc, double scale, double* loss)
 {
-    __shared__ double red[16];
-    double acc = 0.0;
-    const int64_t n3 = 3 * B, step = blockDim.x;
-    int64_t q = threadIdx.x;
-    // eight elements per thread in flight; the sum keeps the thread's order
-    for (; q + 7 * step < n3; q += 8 * step) {
-        float av[8], tv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            av[u] = a[q + u * step];
-            tv[u] = t[q + u * step];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const double dd = (double)av[u] - (double)tv[u];
-            acc += dd * dd;
-            grad[q + u * step] = (float)(2.0 * scale * dd);
-        }
-    }
-    for (; q < n3; q += step) {
-        const double dd = (double)a[q] - (double)t[q];
-        acc += dd * dd;
-        grad[q] = (float)(2.0 * scale * dd);
-    }
+    __shared__ double red[4];
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
         double sum = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
-        *loss += sum * scale;
+        if (sum != 0.0) atomicAdd(loss, sum * scale);
     }
 }
 
+__global__ void __launch_bounds__(256)
+k_mse(int64_t B, const float* __restrict__ a, const float* __restrict__ t, double scale,
+      float* __restrict__ grad, double* loss)
+{
+    double acc = 0.0;
+    const int64_t n3 = 3 * B;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n3;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const double dd = (double)a[q] - (double)t[q];
+        acc += dd * dd;
+        grad[q] = (float)(2.0 * scale * dd);
+    }
+    block_add_loss(acc, scale, loss);
+}
+
 // MSE on the scattering directions: each pair's term and gradient are
-// normalised by its own g^2 = |v_r'*|^2.  Single workgroup, fixed order.
-__global__ void __launch_bounds__(1024)
+// normalised by its own g^2 = |v_r'*|^2.
+__global__ void __launch_bounds__(256)
 k_dir_loss(int64_t B, const float* __restrict__ a, const float* __restrict__ t,
            float* __restrict__ grad, double* loss)
 {
-    __shared__ double red[16];
     double acc = 0.0;
     const double invB = 1.0 / (double)B;
-    for (int64_t r = threadIdx.x; r < B; r += blockDim.x) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < B;
+         r += (int64_t)gridDim.x * blockDim.x) {
         double d[3], g2 = 0.0, dd = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -1182,14 +1174,7 @@ k_dir_loss(int64_t B, const float* __restrict__ a, const float* __restrict__ t,
 #pragma unroll
         for (int c = 0; c < 3; ++c) grad[3 * r + c] = (float)(0.5 * d[c] * w * invB);
     }
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double sum = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
-        *loss += sum * invB;
-    }
+    block_add_loss(acc, invB, loss);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1430,7 +1415,9 @@ extern "C" int dsmc_mse_loss(int64_t B, const float* vr_new, const float* vr_tar
     if (B < 1 || !vr_new || !vr_target || !dL_dvr || !loss || !(sigma_v > 0))
         return arg_error("dsmc_mse_loss: bad arguments");
     const double scale = 1.0 / (4.0 * sigma_v * sigma_v * (double)B);
-    k_mse<<<1, 1024, 0, as_stream(stream)>>>(B, vr_new, vr_target, scale, dL_dvr, loss);
+    int blocks = (int)((3 * B + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    k_mse<<<blocks, 256, 0, as_stream(stream)>>>(B, vr_new, vr_target, scale, dL_dvr, loss);
     DSMC_LAUNCH_CHECK("mse");
     return DSMC_OK;
 }
@@ -1440,7 +1427,9 @@ extern "C" int dsmc_direction_loss(int64_t B, const float* vr_new, const float* 
 {
     if (B < 1 || !vr_new || !vr_target || !dL_dvr || !loss)
         return arg_error("dsmc_direction_loss: bad arguments");
-    k_dir_loss<<<1, 1024, 0, as_stream(stream)>>>(B, vr_new, vr_target, dL_dvr, loss);
+    int blocks = (int)((B + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    k_dir_loss<<<blocks, 256, 0, as_stream(stream)>>>(B, vr_new, vr_target, dL_dvr, loss);
     DSMC_LAUNCH_CHECK("direction_loss");
     return DSMC_OK;
 }

@@ -51,6 +51,42 @@ def direction_error(vr_pred, vr_tgt):
     return torch.arccos(torch.clamp(c, -1, 1))
 
 
+class FlatParams:
+    """The network's parameters in one flat FP32 master buffer (with its
+    gradient and Adam moments beside it) so that one Adam launch updates all
+    of them: the net's bf16 weights become views of one flat bf16 copy that
+    Adam rewrites, its fp32 biases views of the master buffer itself."""
+
+    def __init__(self, net, Ws, bs, dev):
+        offs, o = [], 0
+        for w, b in zip(Ws, bs):
+            nw, nb = int(np.prod(w.shape)), int(np.prod(b.shape))
+            offs.append((o, nw, o + ((nw + 63) // 64) * 64, nb))
+            o = offs[-1][2] + ((nb + 63) // 64) * 64
+        self.n = o
+        self.master = torch.zeros(o, dtype=torch.float32, device=dev)
+        self.grad = torch.zeros_like(self.master)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        for (ow, nw, ob, nb), w, b in zip(offs, Ws, bs):
+            self.master[ow:ow + nw] = torch.as_tensor(np.asarray(w, np.float32).ravel(), device=dev)
+            self.master[ob:ob + nb] = torch.as_tensor(np.asarray(b, np.float32).ravel(), device=dev)
+        self.bf16 = self.master.to(torch.bfloat16)
+        self.W, self.b, self.dW, self.db = [], [], [], []
+        for (ow, nw, ob, nb), w in zip(offs, Ws):
+            shape = tuple(np.asarray(w).shape)
+            self.W.append(self.master[ow:ow + nw].view(shape))
+            self.b.append(self.master[ob:ob + nb])
+            self.dW.append(self.grad[ow:ow + nw].view(shape))
+            self.db.append(self.grad[ob:ob + nb])
+            net.W[len(self.W) - 1] = self.bf16[ow:ow + nw].view(shape)
+            net.b[len(self.b) - 1] = self.master[ob:ob + nb]
+        net.refresh()
+
+    def step(self, t, lr):
+        api.adam_step(self.master, self.grad, self.m, self.v, t, lr, param_bf16=self.bf16)
+
+
 def train(steps=4000, batch=65536, pool=1 << 20, lr=2e-3, seed=4, dims=None, out=None,
           log_every=200, dev=None, loss_kind="direction"):
     sys.path.insert(0, os.path.dirname(HERE))
@@ -66,14 +102,8 @@ def train(steps=4000, batch=65536, pool=1 << 20, lr=2e-3, seed=4, dims=None, out
     torch.cuda.synchronize()
     print(f"harvested {pool} + 65536 rows in {time.time() - t0:.1f}s", flush=True)
     Ws, bs = W.mlp_init(seed, dims)
-    master = []
-    for w, b in zip(Ws, bs):
-        master.append(torch.as_tensor(w, dtype=torch.float32, device=dev).contiguous())
-        master.append(torch.as_tensor(b, dtype=torch.float32, device=dev).contiguous())
     net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=sigma_v, device=dev)
-    mstate = [torch.zeros_like(p) for p in master]
-    vstate = [torch.zeros_like(p) for p in master]
-    grads = [torch.zeros_like(p) for p in master]
+    params = FlatParams(net, Ws, bs, dev)
     act = api.workspace(api.neural_act_bytes(net, batch), dev)
     bws = api.workspace(api.lib().dsmc_neural_backward_ws(__import__("ctypes").byref(net.struct), batch), dev)
     dvr = torch.empty(batch, 3, dtype=torch.float32, device=dev)
@@ -91,16 +121,9 @@ def train(steps=4000, batch=65536, pool=1 << 20, lr=2e-3, seed=4, dims=None, out
             api.direction_loss(vr, tb, dvr, loss)
         else:
             api.mse_loss(vr, tb, sigma_v, dvr, loss)
-        dW = grads[0::2]
-        db = grads[1::2]
-        api.neural_backward(net, xb, act, y, gb, dvr, dW, db, ws=bws)
+        api.neural_backward(net, xb, act, y, gb, dvr, params.dW, params.db, ws=bws)
         lr_t = cosine_lr(t, steps, lr)
-        for l in range(len(net.W)):
-            api.adam_step(master[2 * l], grads[2 * l], mstate[2 * l], vstate[2 * l], t, lr_t,
-                          param_bf16=net.W[l])
-            api.adam_step(master[2 * l + 1], grads[2 * l + 1], mstate[2 * l + 1],
-                          vstate[2 * l + 1], t, lr_t, param_bf16=None)
-            net.b[l].copy_(master[2 * l + 1])
+        params.step(t, lr_t)
         if t % log_every == 0 or t == 1 or t == steps:
             yv, vrv = api.neural_forward_rows(net, xv, gv)
             err = direction_error(vrv, tv)
@@ -116,10 +139,11 @@ def train(steps=4000, batch=65536, pool=1 << 20, lr=2e-3, seed=4, dims=None, out
                 "steps": np.int64(steps), "lr": np.float64(lr), "pool": np.int64(pool),
                 "loss": np.array(loss_kind)}
         for l in range(len(net.W)):
-            arrs[f"W{l}"] = master[2 * l].double().cpu().numpy()
-            arrs[f"b{l}"] = master[2 * l + 1].double().cpu().numpy()
+            arrs[f"W{l}"] = params.W[l].double().cpu().numpy()
+            arrs[f"b{l}"] = params.b[l].double().cpu().numpy()
         np.savez(out, **arrs)
         print("saved", out, flush=True)
+    master = [p for pair in zip(params.W, params.b) for p in pair]
     return net, master, hist
 
 
