@@ -348,6 +348,7 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / PEAK_BF16,
                 "traffic": counter_traffic(MLP_KERNEL[args.split]),
                 "kernel": "k_mlp_bf16 (Phase A of dsmc_neural_collide)",
+                "sq_counters": mlp_sq_counters(MLP_KERNEL[args.split]),
                 "algorithmic_flop_per_pair": MLP_FLOP_PER_PAIR}
     sort_bytes = n * (4 + 4 + 12 + 12 + 4)  # cell id twice, v read + write, perm
     extra = {
@@ -650,6 +651,24 @@ def quadrature_valu_roofline(ms_phase_a):
             "achieved_fp32_TFLOPs": r32 / 1e12, "achieved_fp64_TFLOPs": r64 / 1e12,
             "peak_fp32_TFLOPs": PEAK_FP32 / 1e12, "peak_fp64_TFLOPs": PEAK_FP64 / 1e12,
             "frac": r32 / PEAK_FP32 + r64 / PEAK_FP64}
+
+
+def mlp_sq_counters(kernel):
+    """Matrix-core utilisation of `kernel` from the committed rocprofv3 SQ
+    counter summary (SQ_VALU_MFMA_BUSY_CYCLES over the SIMD cycles at the
+    clock measured in the same pass), or None for another build."""
+    from paper_2602_21244_amd.build import compile_signature
+    path = os.path.join(ROOT, "profiles", "sq_counters_k_mlp_bf16_mach10_cylinder_400x300.md")
+    if not os.path.exists(path):
+        return None
+    try:
+        blob = json.loads(open(path).read().split("```json", 1)[1].split("```", 1)[0])
+        k = blob["kernels"][kernel]
+    except (IndexError, KeyError, ValueError):
+        return None
+    if blob.get("compile_signature") != compile_signature(blob.get("source", "mlp.hip")):
+        return None
+    return k
 
 
 def counter_traffic(kernel, source="mlp.hip"):
