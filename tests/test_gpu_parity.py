@@ -567,6 +567,34 @@ def test_neural_bf16_chi_rms(orc, dev, api, dtype, split):
             assert abs(np.sum(got[:, a:b_] ** 2) / e0 - 1) < 10 * tol
 
 
+def test_neural_split_rejects_unknown_mode(dev, api):
+    """dsmc_mlp.split outside {ALL, FRONT} is an argument error, and the two
+    modes give directions within the bf16 bound of each other."""
+    pop = W.cavity_grid(seed=3, nx=20, ny=20)
+    cs, _, v, _ = _gpu_sort(api, dev, pop)
+    st = api.new_status(dev)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, v, mom, api.L.MM_CAPTURE)
+    lam = torch.as_tensor(pop.lam, device=dev)
+    pairs = api.PairList(pop.n_cells, 200_000, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 3, 0, pairs, st=st)
+    Ws, bs = _net_params(4, W.SURROGATE_DIMS)
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev)
+    ws = api.neural_ws(net, pairs, v)
+    net.struct.split = 7
+    with pytest.raises(RuntimeError):
+        api.neural_collide(net, v.clone(), pairs, 3, 0, schedule=api.L.SCHED_DEFER, ws=ws, st=st)
+    n = int(pairs.cnt.sum())
+    es = 8 if v.dtype == torch.float64 else 4
+    dirs = {}
+    for split in ("all", "front"):
+        net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev, split=split)
+        api.neural_collide(net, v.clone(), pairs, 3, 0, schedule=api.L.SCHED_DEFER, ws=ws, st=st)
+        dirs[split] = ws[: 3 * (pairs.cap + 1) * es].view(v.dtype).view(3, pairs.cap + 1)[:, :n].T.double().cpu().numpy()
+    ang = _angle(dirs["all"], dirs["front"])
+    assert n > 1000 and np.sqrt(np.mean(ang ** 2)) < 1e-2
+
+
 def test_neural_rows_bf16(orc, dev, api):
     say("neural rows bf16")
     rows = W.training_rows(seed=3, n=3000)
