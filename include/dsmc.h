@@ -355,8 +355,10 @@ int dsmc_neural_forward_rows(const dsmc_mlp* net, int64_t B, const void* x, cons
                              void* y_raw, void* vr_out, void* act_save, size_t act_bytes,
                              dsmc_stream_t stream);
 
-/* Backward of the rows form (the hand-written adjoint of the MLP and the
- * energy-shell projection):  given dL/dv_r' [B][3], writes dW[l], db[l]
+/* Backward of the rows form (section "Neural Surrogate Training": the
+ * surrogate is trained by gradient descent on its loss; this is the
+ * hand-written adjoint of eq. mlp_output and of eq. energy_shell_projection):
+ * given dL/dv_r' [B][3], writes dW[l], db[l]
  * (FP32 for the BF16 network, FP64 for the FP64 network; accumulate = 1 adds
  * to them) and, if dx != NULL, dL/dx [B][dims[0]].  The row reduction of dW
  * runs in a fixed order (deterministic).  act_save from the forward call.
@@ -367,8 +369,10 @@ int dsmc_neural_backward(const dsmc_mlp* net, int64_t B, const void* x, const vo
                          void* const* dW, void* const* db, void* dx, int32_t accumulate,
                          void* ws, size_t ws_bytes, dsmc_stream_t stream);
 
-/* Adjoint of the centred moment matching of one cell group (v -> u_pre +
- * alpha (v - u_post)) with respect to the post-collision velocities:
+/* Adjoint of the centred moment matching of one cell group (eq.
+ * cell_energy_clamp, section "Optional Cell-Wise Energy Drift Correction", in
+ * the centred reading v -> u_pre + alpha (v - u_post)) with respect to the
+ * post-collision velocities, for training through the matching:
  *   dL/dv_m = alpha (G_m - mean G) - (alpha / S_post) (sum_i G_i . c_i) c_m,
  * c = v - u_post.  FP64 arrays [3][n] SoA in sorted order, pre-moments from
  * CAPTURE.  Cells with N < 2 or S_post <= 0 pass G through. */

@@ -279,6 +279,16 @@ __device__ __forceinline__ void box_muller_hw(float ua, float ub, float& n1, flo
     n2 = R * __builtin_amdgcn_sinf(ub);
 }
 
+// The same on 53-bit uniforms: 1 - ua is formed in FP64 (it never rounds to
+// zero) and both arguments are then rounded to FP32.
+__device__ __forceinline__ void box_muller_hw53(double ua, double ub, float& n1, float& n2)
+{
+    const float w = (float)(1.0 - ua), b = (float)ub;
+    const float R = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(w));
+    n1 = R * __builtin_amdgcn_cosf(b);
+    n2 = R * __builtin_amdgcn_sinf(b);
+}
+
 // One layer on NT tiles: acc holds s of the previous layer (NB blocks),
 // nxt receives s of this layer (NBO blocks).  The activation of block nb
 // produces the inputs of k steps 2 nb and 2 nb + 1, whose MFMAs are issued
@@ -431,18 +441,25 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                         xin[t][0][4] = C * n1;
                     }
                 } else if (valid[t]) {
+                    // FP64 velocities: the 53-bit uniforms of the FP64
+                    // contract, transformed on the FP32 hardware units
                     const int64_t r = row[t];
                     const int32_t k = pf_k[t];
                     const uint32_t a = (uint32_t)(r - pio.pr.off[k]);
                     if (h == 0) {
-                        VT xi[3];
-                        latents_xi(pio.rng, a, (uint32_t)k, xi);
-                        xin[t][0][0] = C * (float)xi[0];
-                        xin[t][0][1] = C * (float)xi[1];
-                        xin[t][0][2] = C * (float)xi[2];
+                        double U[4];
+                        uniforms_xi(pio.rng, a, (uint32_t)k, U);
+                        float xi[3], spare;
+                        box_muller_hw53(U[0], U[1], xi[0], xi[1]);
+                        box_muller_hw53(U[2], U[3], xi[2], spare);
+                        xin[t][0][0] = C * xi[0];
+                        xin[t][0][1] = C * xi[1];
+                        xin[t][0][2] = C * xi[2];
                     } else {
-                        VT z[2], u4;
-                        latents_z(pio.rng, a, (uint32_t)k, z, u4);
+                        double U[2];
+                        uniforms_z(pio.rng, a, (uint32_t)k, U);
+                        float z[2];
+                        box_muller_hw53(U[0], U[1], z[0], z[1]);
                         const int32_t i = pf_i[t], j = pf_j[t];
                         const VT isv = (VT)d.inv_sigma_v;
                         xin[t][0][0] = C * (float)((pio.v.x[i] - pio.v.x[j]) * isv);
