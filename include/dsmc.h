@@ -415,18 +415,22 @@ int dsmc_harvest_rows(int64_t B, const double* vr, const double* xi, const doubl
                       dsmc_quad quad, float* x_out, float* g_out, float* target_out,
                       double* chi_out, dsmc_status* st, dsmc_stream_t stream);
 
-/* One persistent launch per step for the isotropic rule: each workgroup takes
- * cells from a work queue and, with the cell staged in LDS, runs moments, NTC
+/* One persistent launch per step for the isotropic rule: workgroups take
+ * cells from a work queue and, with the cell staged in LDS, run moments, NTC
  * selection, Phase A, Phase B and (match != 0) centred moment matching; HBM
- * sees one read and one write of the velocities.  Results are bit-identical
- * to dsmc_moment_match(CAPTURE) -> dsmc_select_pairs_ntc -> dsmc_collide_vhs
- * -> dsmc_moment_match(APPLY) with the same rng.  pair_cnt[n_cells] receives
- * each cell's accepted pairs.  A cell with more than 2048 accepted pairs is
- * applied in LDS batches of 2048 in candidate order (same result); a cell of
- * more than 3072 particles (beyond the LDS staging) is left unchanged with
- * pair_cnt = -1 and DSMC_ST_PAIR_OVERFLOW set, for the separate entry points
- * to handle.
- * ws: dsmc_step_vhs_ws bytes. */
+ * sees one read and one write of the velocities.  Cells of up to 320
+ * particles are taken by one-wave workgroups (many resident per CU); larger
+ * ones are listed and taken by a second launch of block-wide workgroups.
+ * Results are bit-identical to dsmc_moment_match(CAPTURE) ->
+ * dsmc_select_pairs_ntc -> dsmc_collide_vhs -> dsmc_moment_match(APPLY) with
+ * the same rng.  pair_cnt[n_cells] receives each cell's accepted pairs.
+ * Accepted pairs beyond one LDS batch (256 in the wave form, 2048 in the
+ * block form) are applied batch by batch in candidate order (same result); a
+ * cell of more than 3072 particles (beyond the LDS staging) is left
+ * unchanged with pair_cnt = -1 and DSMC_ST_PAIR_OVERFLOW set, for the
+ * separate entry points to handle.
+ * ws: dsmc_step_vhs_ws(n_cells, 0) bytes (queues and the list of large
+ * cells). */
 size_t dsmc_step_vhs_ws(int32_t n_cells, int64_t cap);
 int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, int32_t dtype, dsmc_vec3 v,
                         dsmc_xs xs, const double* lambda, dsmc_rng rng, int32_t match,

@@ -2,7 +2,11 @@
 // workgroup takes cells from a work queue (an atomic counter, so cells of any
 // population balance across the grid), stages the cell's velocities in LDS
 // and runs moments, NTC selection, Phase A, Phase B (dependency rounds) and
-// moment matching without touching HBM again.  HBM traffic is one read and one
+// moment matching without touching HBM again.  The launch runs with one wave
+// per workgroup and small LDS tables, so many cells of a few hundred
+// particles are in flight on every CU; cells larger than those tables are
+// listed and taken by a second, block-wide launch with tables for up to 3072
+// particles.  HBM traffic is one read and one
 // write of the velocities per step.  The arithmetic (including the order of
 // every reduction) is that of the separate entry points, so the results are
 // bit-identical to dsmc_moment_match(CAPTURE) -> dsmc_select_pairs_ntc ->
@@ -20,9 +24,10 @@ namespace dsmc {
 
 int xs_law_public(const dsmc_xs& xs, double* C, double* e);
 
-constexpr int FS_THREADS = 256;
-constexpr int FS_NMAX = 3072;  // particles of a cell staged in LDS
-constexpr int FS_MMAX = 2048;  // accepted pairs of one LDS batch
+// Wave form: particles of a cell staged in LDS, accepted pairs of one LDS
+// batch.  Block form: the same for the listed (larger) cells.
+constexpr int FW_THREADS = 64, FW_NMAX = 320, FW_MMAX = 256;
+constexpr int FS_THREADS = 256, FS_NMAX = 3072, FS_MMAX = 2048;
 
 struct FusedArgs {
     int32_t n_cells;
@@ -32,7 +37,8 @@ struct FusedArgs {
     dsmc_rng rng;
     int32_t match;
     int32_t* pair_cnt;
-    int32_t* queue;
+    int32_t* queue;     // [0]: wave-form queue, [1]: block-form queue, [2]: listed cells
+    int32_t* big;       // cells listed for the block form
     dsmc_status* st;
 };
 
@@ -62,34 +68,49 @@ __device__ __forceinline__ void wave0_sums(const double* vx, const double* vy, c
     out6[5] = wave_sum(E);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(FS_THREADS)
+// LISTED = false: every cell from the queue, cells above NMAX particles go to
+// the list; LISTED = true: the listed cells, those above NMAX are left alone.
+template <typename T, int NT, int NMAX, int MMAX, bool LISTED>
+__global__ void __launch_bounds__(NT)
 k_step_vhs_fused(FusedArgs A, V3<T> v)
 {
-    __shared__ double lvx[FS_NMAX], lvy[FS_NMAX], lvz[FS_NMAX];
-    __shared__ uint32_t lpair[FS_MMAX];
-    __shared__ T ldir[3][FS_MMAX];
-    __shared__ int32_t first[FS_NMAX];
+    __shared__ double lvx[NMAX], lvy[NMAX], lvz[NMAX];
+    __shared__ uint32_t lpair[MMAX];
+    __shared__ T ldir[3][MMAX];
+    __shared__ int32_t first[NMAX];
     __shared__ double mom[6], post[6];
     __shared__ int32_t s_cell, s_M, s_acc, s_remaining, s_base;
-    __shared__ int32_t wtot[FS_THREADS / 64];
+    __shared__ int32_t wtot[NT / 64];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
     for (;;) {
-        if (tid == 0) s_cell = atomicAdd(A.queue, 1);
+        if (tid == 0) {
+            if (LISTED) {
+                const int32_t idx = atomicAdd(&A.queue[1], 1);
+                s_cell = idx < A.queue[2] ? A.big[idx] : INT32_MAX;
+            } else {
+                s_cell = atomicAdd(&A.queue[0], 1);
+            }
+        }
         __syncthreads();
         const int32_t k = s_cell;
         if (k >= A.n_cells) break;
         const int32_t s0 = A.cell_start[k], N = A.cell_start[k + 1] - s0;
-        if (N < 2 || N > FS_NMAX) {
+        if (N < 2 || N > NMAX) {
             if (tid == 0) {
-                A.pair_cnt[k] = (N > FS_NMAX) ? -1 : 0;
-                if (N > FS_NMAX && A.st) atomicOr(&A.st->flags, (uint32_t)DSMC_ST_PAIR_OVERFLOW);
+                if (N < 2) {
+                    A.pair_cnt[k] = 0;
+                } else if (!LISTED) {
+                    A.big[atomicAdd(&A.queue[2], 1)] = k;
+                } else {
+                    A.pair_cnt[k] = -1;
+                    if (A.st) atomicOr(&A.st->flags, (uint32_t)DSMC_ST_PAIR_OVERFLOW);
+                }
             }
             __syncthreads();
             continue;
         }
-        for (int32_t q = tid; q < N; q += FS_THREADS) {
+        for (int32_t q = tid; q < N; q += NT) {
             lvx[q] = (double)v.x[s0 + q];
             lvy[q] = (double)v.y[s0 + q];
             lvz[q] = (double)v.z[s0 + q];
@@ -135,7 +156,7 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
             const int32_t nb = s_acc, b0 = s_base;
             // Phase A on the pre-collision velocities (arithmetic in T, as
             // the separate isotropic kernel)
-            for (int32_t q = tid; q < nb; q += FS_THREADS) {
+            for (int32_t q = tid; q < nb; q += NT) {
                 T xi[3], z[2], u4;
                 pair_latents(A.rng, (uint32_t)(b0 + q), (uint32_t)k, xi, z, u4);
                 const int32_t i = lpair[q] & 0xffff, j = lpair[q] >> 16;
@@ -155,9 +176,9 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
             __syncthreads();
             // Phase B: dependency rounds, every value rounded to T as stored
             while (s_remaining > 0) {
-                for (int32_t q = tid; q < N; q += FS_THREADS) first[q] = INT32_MAX;
+                for (int32_t q = tid; q < N; q += NT) first[q] = INT32_MAX;
                 __syncthreads();
-                for (int32_t q = tid; q < nb; q += FS_THREADS) {
+                for (int32_t q = tid; q < nb; q += NT) {
                     const uint32_t w = lpair[q];
                     if (w != 0xffffffffu) {
                         atomicMin(&first[w & 0xffff], q);
@@ -166,7 +187,7 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
                 }
                 __syncthreads();
                 int done_here = 0;
-                for (int32_t q = tid; q < nb; q += FS_THREADS) {
+                for (int32_t q = tid; q < nb; q += NT) {
                     const uint32_t w = lpair[q];
                     if (w == 0xffffffffu) continue;
                     const int32_t a = w & 0xffff, b = w >> 16;
@@ -195,10 +216,10 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
             }
             __syncthreads();
         };
-        // candidates in blocks of FS_THREADS; ordered compaction of the
+        // candidates in blocks of NT; ordered compaction of the
         // accepted ones into lpair, flushed before a block could overflow it
-        for (int32_t base = 0; base < M; base += FS_THREADS) {
-            if (s_acc + FS_THREADS > FS_MMAX) flush();
+        for (int32_t base = 0; base < M; base += NT) {
+            if (s_acc + NT > MMAX) flush();
             const int32_t t = base + tid;
             bool acc = false;
             uint32_t packed = 0;
@@ -229,7 +250,7 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
             __syncthreads();
             if (tid == 0) {
                 int tot = 0;
-                for (int w = 0; w < FS_THREADS / 64; ++w) tot += wtot[w];
+                for (int w = 0; w < NT / 64; ++w) tot += wtot[w];
                 s_acc += tot;
             }
             __syncthreads();
@@ -251,7 +272,7 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
                 if (tid == 0 && A.st) atomicAdd(&A.st->mm_skipped, 1);
             } else {
                 const double alpha = sqrt(mom[3] / Sp);
-                for (int32_t q = tid; q < N; q += FS_THREADS) {
+                for (int32_t q = tid; q < N; q += NT) {
                     v.x[s0 + q] = (T)(mom[0] + alpha * (lvx[q] - post[0]));
                     v.y[s0 + q] = (T)(mom[1] + alpha * (lvy[q] - post[1]));
                     v.z[s0 + q] = (T)(mom[2] + alpha * (lvz[q] - post[2]));
@@ -260,7 +281,7 @@ k_step_vhs_fused(FusedArgs A, V3<T> v)
             }
         }
         if (write_raw) {
-            for (int32_t q = tid; q < N; q += FS_THREADS) {
+            for (int32_t q = tid; q < N; q += NT) {
                 v.x[s0 + q] = (T)lvx[q];
                 v.y[s0 + q] = (T)lvy[q];
                 v.z[s0 + q] = (T)lvz[q];
@@ -277,9 +298,9 @@ using namespace dsmc;
 
 extern "C" size_t dsmc_step_vhs_ws(int32_t n_cells, int64_t cap)
 {
-    (void)n_cells;
     (void)cap;
-    return 256;
+    if (n_cells < 1) return 0;
+    return 256 + align_up(sizeof(int32_t) * (size_t)n_cells);
 }
 
 extern "C" int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, int32_t dtype,
@@ -302,20 +323,32 @@ extern "C" int dsmc_step_vhs_fused(int32_t n_cells, const int32_t* cell_start, i
     A.match = match;
     A.pair_cnt = pair_cnt;
     A.queue = static_cast<int32_t*>(ws);
+    A.big = reinterpret_cast<int32_t*>(static_cast<uint8_t*>(ws) + 256);
     A.st = st;
-    hipStream_t s = as_stream(stream);
-    rc = fill_i32(A.queue, 0, 1, s);
-    if (rc) return rc;
-    const int cus = device_cus();
-    int blocks = cus * 2;
-    if (blocks > n_cells) blocks = n_cells;
-    if (dtype == DSMC_F64) {
-        k_step_vhs_fused<double><<<blocks, FS_THREADS, 0, s>>>(A, v3<double>(v));
-    } else if (dtype == DSMC_F32) {
-        k_step_vhs_fused<float><<<blocks, FS_THREADS, 0, s>>>(A, v3<float>(v));
-    } else {
+    if (dtype != DSMC_F64 && dtype != DSMC_F32)
         return arg_error("dsmc_step_vhs_fused: dtype %d", dtype);
+    hipStream_t s = as_stream(stream);
+    rc = fill_i32(A.queue, 0, 3, s);
+    if (rc) return rc;
+    // wave form: as many one-wave workgroups as the LDS tables let stay
+    // resident (a dozen per CU); block form: one workgroup per CU
+    const int cus = device_cus();
+    int wb = cus * 12, bb = cus;
+    if (wb > n_cells) wb = n_cells;
+    if (bb > n_cells) bb = n_cells;
+    if (dtype == DSMC_F64) {
+        k_step_vhs_fused<double, FW_THREADS, FW_NMAX, FW_MMAX, false>
+            <<<wb, FW_THREADS, 0, s>>>(A, v3<double>(v));
+        DSMC_LAUNCH_CHECK("step_vhs_fused:wave");
+        k_step_vhs_fused<double, FS_THREADS, FS_NMAX, FS_MMAX, true>
+            <<<bb, FS_THREADS, 0, s>>>(A, v3<double>(v));
+    } else {
+        k_step_vhs_fused<float, FW_THREADS, FW_NMAX, FW_MMAX, false>
+            <<<wb, FW_THREADS, 0, s>>>(A, v3<float>(v));
+        DSMC_LAUNCH_CHECK("step_vhs_fused:wave");
+        k_step_vhs_fused<float, FS_THREADS, FS_NMAX, FS_MMAX, true>
+            <<<bb, FS_THREADS, 0, s>>>(A, v3<float>(v));
     }
-    DSMC_LAUNCH_CHECK("step_vhs_fused");
+    DSMC_LAUNCH_CHECK("step_vhs_fused:block");
     return DSMC_OK;
 }
