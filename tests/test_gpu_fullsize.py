@@ -71,10 +71,27 @@ def test_cylinder_fullsize_neural_step(orc, dev, api):
     (the bound of the BF16 arithmetic), and the shift the rounding itself
     causes against the unrounded weights (reported)."""
     say("full-size cylinder step (bench configuration)")
-    pop = W.cylinder_grid(seed=5, order="realistic")
+    _cylinder_neural_case(orc, dev, api, "realistic", torch.float32,
+                          list(itertools.product(_surrogate_nets(), ("all", "front"))))
+
+
+@pytest.mark.parametrize("order,vdtype", [("shuffled", torch.float32), ("realistic", torch.float64)])
+def test_cylinder_fullsize_variants(orc, dev, api, order, vdtype):
+    """The two other forms of the step the benchmark times: particles fully
+    shuffled (FP32) and FP64 velocities, with the trained weights and the
+    benchmark's activation split."""
+    say("full-size cylinder step", order, vdtype)
+    nets = [n for n in _surrogate_nets() if n[0] == "trained"] or _surrogate_nets()[:1]
+    _cylinder_neural_case(orc, dev, api, order, vdtype, [(nets[0], "front")])
+
+
+def _cylinder_neural_case(orc, dev, api, order, vdtype, cases):
+    pop = W.cylinder_grid(seed=5, order=order)
     n, nc = pop.n, pop.n_cells
+    lowp = vdtype == torch.float32
+    es = 4 if lowp else 8
     cell_of = torch.as_tensor(pop.cell_of, device=dev)
-    v_in = torch.as_tensor(pop.v, dtype=torch.float32, device=dev).contiguous()
+    v_in = torch.as_tensor(pop.v, dtype=vdtype, device=dev).contiguous()
     lam = torch.as_tensor(pop.lam, device=dev)
     st = api.new_status(dev)
     cs, perm, v = api.sort_cells(cell_of, nc, v_in, st=st)
@@ -109,7 +126,7 @@ def test_cylinder_fullsize_neural_step(orc, dev, api):
         assert np.array_equal(pairs.j[p0:p0 + m].cpu().numpy(), sel["pair_j"] + a)
         sels[k0] = (sub_cs, sub_v, omom, sel, m, p0, a, b)
     ws = api.collide_ws(cap, v)
-    for (name, Ws, bs, sigma_v), split in itertools.product(_surrogate_nets(), ("all", "front")):
+    for (name, Ws, bs, sigma_v), split in cases:
         v.copy_(v_pre)
         net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=sigma_v, device=dev, split=split)
         name = f"{name}, split {split}"
@@ -121,13 +138,13 @@ def test_cylinder_fullsize_neural_step(orc, dev, api):
         torch.cuda.synchronize()
         say(f"  [{name}] {n} particles, {int(api.read_status(st).n_pairs)} pairs")
         vout = v.double().cpu().numpy()
-        gdirs = ws[: 3 * (cap + 1) * 4].view(torch.float32).view(3, cap + 1)
+        gdirs = ws[: 3 * (cap + 1) * es].view(vdtype).view(3, cap + 1)
         sq_r, sq_u, cnt_a, worst_v = 0.0, 0.0, 0, 0.0
         for k0, k1 in rng_cells:
             sub_cs, sub_v, omom, sel, m, p0, a, b = sels[k0]
             if m == 0:
                 continue
-            U, xi, z = orc.pair_latents(sel, 11, 0, lowp=True)
+            U, xi, z = orc.pair_latents(sel, 11, 0, lowp=lowp)
             vr = (sub_v[:, sel["pair_i"]] - sub_v[:, sel["pair_j"]]).T
             xin = orc.network_input(vr, xi, z, sigma_v)
             u_gpu = gdirs[:, p0:p0 + m].T.double().cpu().numpy()
@@ -155,7 +172,7 @@ def test_cylinder_fullsize_neural_step(orc, dev, api):
         if split == "all":
             # every activation a bf16 pair: the result is that of the weights
             assert rms_r <= 1e-3
-        assert worst_v < 1e-5
+        assert worst_v < (1e-5 if lowp else 1e-11)
 
 
 def test_cavity_fullsize_vhs_fp64(orc, dev, api):
