@@ -443,7 +443,9 @@ def viscosity_ce(omega, T, m):
 # ---------------------------------------------------------------------------
 def act_fn(name, zz):
     if name == "silu":
-        return zz / (1.0 + np.exp(-zz))
+        # exp(-z) overflows to inf for z < -709 and z / inf = -0 is the limit
+        with np.errstate(over="ignore"):
+            return zz / (1.0 + np.exp(-zz))
     if name == "relu":
         return np.maximum(zz, 0.0)
     raise ValueError(name)
