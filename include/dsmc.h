@@ -349,7 +349,9 @@ int dsmc_neural_collide(const dsmc_mlp* net, int32_t n_cells, int32_t dtype, dsm
  * speeds g[B]: y_raw = f_theta(x) [B][dims[L]], vr_out = g * y/|y| [B][3].
  * Array dtype: FP32 for the BF16 network, FP64 for the FP64 network.
  * act_save (nullable): activations kept for dsmc_neural_backward, size
- * dsmc_neural_act_bytes(net, B). */
+ * dsmc_neural_act_bytes(net, B); its contents are private to the pair of
+ * calls (for the BF16 network: FP32 pre-activations and bf16 activations and
+ * inputs, transposed in blocks of 128 rows). */
 size_t dsmc_neural_act_bytes(const dsmc_mlp* net, int64_t B);
 int dsmc_neural_forward_rows(const dsmc_mlp* net, int64_t B, const void* x, const void* g,
                              void* y_raw, void* vr_out, void* act_save, size_t act_bytes,
@@ -360,8 +362,10 @@ int dsmc_neural_forward_rows(const dsmc_mlp* net, int64_t B, const void* x, cons
  * hand-written adjoint of eq. mlp_output and of eq. energy_shell_projection):
  * given dL/dv_r' [B][3], writes dW[l], db[l]
  * (FP32 for the BF16 network, FP64 for the FP64 network; accumulate = 1 adds
- * to them) and, if dx != NULL, dL/dx [B][dims[0]].  The row reduction of dW
- * runs in a fixed order (deterministic).  act_save from the forward call.
+ * to them) and, if dx != NULL, dL/dx [B][dims[0]].  The row reductions of dW
+ * and db run in a fixed order (deterministic).  act_save from the forward
+ * call with the same net and B; for the BF16 network x is not read again
+ * (the forward saved it).
  * ws: dsmc_neural_backward_ws(net, B) bytes. */
 size_t dsmc_neural_backward_ws(const dsmc_mlp* net, int64_t B);
 int dsmc_neural_backward(const dsmc_mlp* net, int64_t B, const void* x, const void* act_save,

@@ -62,15 +62,18 @@ __device__ __forceinline__ float act_deriv(int act, float z)
     }
 }
 
-__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m, int64_t n, float v)
+// zd: dact_z at (m, n) when dact_z is set (loaded by the caller).
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int64_t m, int64_t n, float v,
+                                              float zd)
 {
+    const int64_t oz = gemm_off(m, n, g.ldz, g.bsz), oo = gemm_off(m, n, g.ldo, g.bso);
     if (g.bias) v += g.bias[n];
-    if (g.z_out) g.z_out[m * g.ldz + n] = v;
-    if (g.dact_z) v *= act_deriv(g.act, g.dact_z[m * g.ldz + n]);
+    if (g.z_out) g.z_out[oz] = v;
+    if (g.dact_z) v *= act_deriv(g.act, zd);
     else v = act_apply(g.act, v);
-    if (g.accumulate && g.out_f32) v += g.out_f32[m * g.ldo + n];
-    if (g.out_f32) g.out_f32[m * g.ldo + n] = v;
-    if (g.out_bf16) g.out_bf16[m * g.ldo + n] = (__bf16)v;
+    if (g.accumulate && g.out_f32) v += g.out_f32[oo];
+    if (g.out_f32) g.out_f32[oo] = v;
+    if (g.out_bf16) g.out_bf16[oo] = (__bf16)v;
 }
 
 // One operand tile (rows [r0, r0 + 128) x k [k0, k0 + GK)) in flight: each
@@ -82,9 +85,9 @@ struct TileRegs {
     bf16x8g v[G_CHUNKS];
 };
 
-__device__ __forceinline__ void load_tile(const __bf16* __restrict__ p, int64_t ld, int64_t rows,
-                                          int64_t K, int64_t r0, int64_t k0, bool kcontig,
-                                          TileRegs& R)
+__device__ __forceinline__ void load_tile(const __bf16* __restrict__ p, int64_t ld, int64_t bs,
+                                          int64_t rows, int64_t K, int64_t r0, int64_t k0,
+                                          bool kcontig, TileRegs& R)
 {
     const int t = threadIdx.x;
 #pragma unroll
@@ -96,12 +99,12 @@ __device__ __forceinline__ void load_tile(const __bf16* __restrict__ p, int64_t 
         if (kcontig) {
             gr = r0 + c / (GK / 8);
             gk = k0 + (c % (GK / 8)) * 8;
-            src = p + gr * ld + gk;
+            src = p + gemm_off(gr, gk, ld, bs);
             full = gr < rows && gk + 8 <= K;
         } else {
             gk = k0 + (c >> 4);
             gr = r0 + (c & 15) * 8;
-            src = p + gk * ld + gr;
+            src = p + gemm_off(gk, gr, ld, bs);
             full = gk < K && gr + 8 <= rows;
         }
         if (full && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
@@ -149,7 +152,8 @@ k_gemm_bf16(GemmArgs g)
     // rows.
     // With a K split the grid is tiles x splits in one dimension, split
     // fastest, so a few output tiles with many splits still spread over
-    // every XCD.
+    // every XCD.  With fewer than eight m tiles (a short, wide C) the tiles
+    // are dealt m fastest: the few A rows are shared by every XCD anyway.
     const int64_t m_tiles = (g.M + GM - 1) / GM, n_tiles = (g.N + GN - 1) / GN;
     const int64_t wid = blockIdx.x;
     int64_t mt, nt, split = 0;
@@ -159,10 +163,13 @@ k_gemm_bf16(GemmArgs g)
         const int64_t tile = wid / splits;
         mt = tile / n_tiles;
         nt = tile % n_tiles;
-    } else {
+    } else if (m_tiles >= 8) {
         const int64_t r8 = wid >> 3;
         mt = (r8 / n_tiles) * 8 + (wid & 7);
         nt = r8 % n_tiles;
+    } else {
+        mt = wid % m_tiles;
+        nt = wid / m_tiles;
     }
     if (mt >= m_tiles) return;
     const int64_t m0 = mt * GM, n0 = nt * GN;
@@ -181,21 +188,33 @@ k_gemm_bf16(GemmArgs g)
 
     TileRegs ra, rb;
     if (kbeg < kend) {
-        load_tile(g.a, g.lda, g.M, kend, m0, kbeg, a_kc, ra);
-        load_tile(g.b, g.ldb, g.N, kend, n0, kbeg, b_kc, rb);
+        load_tile(g.a, g.lda, g.bsa, g.M, kend, m0, kbeg, a_kc, ra);
+        load_tile(g.b, g.ldb, g.bsb, g.N, kend, n0, kbeg, b_kc, rb);
         store_tile(ra, a_kc, As[0]);
         store_tile(rb, b_kc, Bs[0]);
     }
     __syncthreads();
     int cur = 0;
+    // row sums of A: thread t adds k half (t & 1) of tile row t >> 1
+    const bool asum = g.asum_out != nullptr && nt == 0;
+    float arow = 0.0f;
     for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
         const bool more = k0 + GK < kend;
         if (more) {
-            load_tile(g.a, g.lda, g.M, kend, m0, k0 + GK, a_kc, ra);
-            load_tile(g.b, g.ldb, g.N, kend, n0, k0 + GK, b_kc, rb);
+            load_tile(g.a, g.lda, g.bsa, g.M, kend, m0, k0 + GK, a_kc, ra);
+            load_tile(g.b, g.ldb, g.bsb, g.N, kend, n0, k0 + GK, b_kc, rb);
         }
         const __bf16* A_ = As[cur];
         const __bf16* B_ = Bs[cur];
+        if (asum) {
+            const __bf16* ar = A_ + (threadIdx.x >> 1) * GLD + (threadIdx.x & 1) * (GK / 2);
+            const bf16x8g a0 = *reinterpret_cast<const bf16x8g*>(ar);
+            const bf16x8g a1 = *reinterpret_cast<const bf16x8g*>(ar + 8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) arow += (float)a0[e];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) arow += (float)a1[e];
+        }
 #pragma unroll
         for (int ks = 0; ks < GK / 16; ++ks) {
             bf16x8g fa[2], fb[2];
@@ -222,10 +241,35 @@ k_gemm_bf16(GemmArgs g)
         cur ^= 1;
     }
 
+    if (asum) {
+        const float tot = arow + __shfl_xor(arow, 1, 64);   // halves in a fixed order
+        const int64_t m = m0 + (threadIdx.x >> 1);
+        if ((threadIdx.x & 1) == 0 && m < g.M) {
+            if (splits > 1) g.asum_part[split * g.M + m] = tot;
+            else g.asum_out[m] = g.accumulate ? g.asum_out[m] + tot : tot;
+        }
+    }
+
     // epilogue: register r of lane (h, col) holds row 8 (r / 4) + 4 h + r % 4, column col
     float* part = g.partial ? g.partial + split * g.M * g.N : nullptr;
+    // The derivative epilogue's z values of each half of the wave's block
+    // are loaded before its first store: the stores may alias them as far as
+    // the compiler knows, so loads interleaved with stores would each wait a
+    // full round trip.
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+        float zd[2][16];
+        if (!part && g.dact_z) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                    const int64_t n = n0 + wn * 64 + j * 32 + col;
+                    zd[j][r] = (m < g.M && n < g.N) ? g.dact_z[gemm_off(m, n, g.ldz, g.bsz)]
+                                                    : 0.0f;
+                }
+        }
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -238,8 +282,9 @@ k_gemm_bf16(GemmArgs g)
                     part[m * g.N + n] = v;
                     continue;
                 }
-                gemm_epilogue(g, m, n, v);
+                gemm_epilogue(g, m, n, v, g.dact_z ? zd[j][r] : 0.0f);
             }
+    }
 }
 
 // Sum of the K-split partials, then the epilogue.  A workgroup takes 64
@@ -270,9 +315,40 @@ k_gemm_reduce(GemmArgs g, int splits)
         __syncthreads();
         if (w == 0 && q < total) {
             const float r = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-            gemm_epilogue(g, q / g.N, q % g.N, r);
+            const int64_t m = q / g.N, n = q % g.N;
+            gemm_epilogue(g, m, n, r,
+                          g.dact_z ? g.dact_z[gemm_off(m, n, g.ldz, g.bsz)] : 0.0f);
         }
         __syncthreads();
+    }
+    // row sums of A from the per-split sums, in the same fixed order (split
+    // s to wave s % 4, the four wave sums in wave order), by the last
+    // workgroups of the grid
+    if (g.asum_out) {
+        const int64_t nb = (g.M + 63) / 64;
+        const int64_t b = (int64_t)gridDim.x - 1 - blockIdx.x;
+        for (int64_t mb = b; mb < nb; mb += gridDim.x) {
+            const int64_t m = mb * 64 + lane;
+            float v = 0.0f;
+            if (m < g.M) {
+                int s = w;
+                for (; s + 12 < splits; s += 16) {
+                    const float a0 = g.asum_part[(int64_t)s * g.M + m];
+                    const float a1 = g.asum_part[(int64_t)(s + 4) * g.M + m];
+                    const float a2 = g.asum_part[(int64_t)(s + 8) * g.M + m];
+                    const float a3 = g.asum_part[(int64_t)(s + 12) * g.M + m];
+                    v += a0; v += a1; v += a2; v += a3;
+                }
+                for (; s < splits; s += 4) v += g.asum_part[(int64_t)s * g.M + m];
+            }
+            part[w][lane] = v;
+            __syncthreads();
+            if (w == 0 && m < g.M) {
+                const float r = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+                g.asum_out[m] = g.accumulate ? g.asum_out[m] + r : r;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -384,9 +460,11 @@ int gemm_bf16(const GemmArgs& g0, int splits, hipStream_t s)
     if (g.M <= 0 || g.N <= 0) return DSMC_OK;
     if (splits < 1) splits = 1;
     const int64_t gx = (g.M + GM - 1) / GM, gy = (g.N + GN - 1) / GN;
-    const int64_t tiles = splits > 1 ? gx * gy * splits : (gx + 7) / 8 * 8 * gy;
+    const int64_t tiles = splits > 1 ? gx * gy * splits : (gx >= 8 ? (gx + 7) / 8 * 8 * gy : gx * gy);
     if (tiles > 2147483647 || splits > 65535) return arg_error("gemm: grid too large");
     if (splits > 1 && !g.partial) return arg_error("gemm: split-K needs a partial buffer");
+    if (splits > 1 && g.asum_out && !g.asum_part)
+        return arg_error("gemm: split-K row sums need a partial buffer");
     if (splits == 1) g.partial = nullptr;
     g.ksplits = splits;
     dim3 grid((unsigned)tiles, 1u, 1u);

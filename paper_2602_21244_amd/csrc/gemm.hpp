@@ -7,6 +7,15 @@ namespace dsmc {
 
 enum { GEMM_ACT_NONE = 0, GEMM_ACT_SILU = 1, GEMM_ACT_SOFTPLUS = 2, GEMM_ACT_RELU = 3 };
 
+constexpr int GEMM_RB = 128;   // rows per block of a row-blocked operand
+
+// Offset of element (i, j) of a matrix with leading dimension ld, or, with
+// block stride bs != 0, of the row-blocked layout described in GemmArgs.
+__host__ __device__ inline int64_t gemm_off(int64_t i, int64_t j, int64_t ld, int64_t bs)
+{
+    return bs ? i * GEMM_RB + (j / GEMM_RB) * bs + (j % GEMM_RB) : i * ld + j;
+}
+
 struct GemmArgs {
     const __bf16* a;
     const __bf16* b;
@@ -22,6 +31,18 @@ struct GemmArgs {
     float* out_f32;        // [M][ldo] or null
     __bf16* out_bf16;      // [M][ldo] or null
     int64_t ldo;
+    // Row blocking: an operand, z or the outputs with bs* != 0 store element
+    // (i, j) of the layouts above (i the index multiplied by ld, j the one
+    // added) at i * ld + (j / GEMM_RB) * bs + j % GEMM_RB, with ld = GEMM_RB:
+    // a [units][rows] matrix kept as blocks of GEMM_RB rows, units-major
+    // inside each block (a tile's rows then lie in one contiguous block).
+    int64_t bsa, bsb, bsz, bso;
+    // Row sums of A over K (sum_k A(m, k), e.g. a bias gradient), when
+    // asum_out is set: FP32, fixed order, += when accumulate; with a K split
+    // the per-split sums go to asum_part [splits][M] and the reduce kernel
+    // adds them in split order.
+    float* asum_out;
+    float* asum_part;
     float* partial;        // split-K partials [splits][M][N] (splits > 1)
     int ksplits;           // set by gemm_bf16: K splits (one 1-D grid of tiles x splits)
 };

@@ -251,12 +251,18 @@ __device__ __forceinline__ void to_frag(const floatx16& a, int jp, bf16x8& hi, b
     }
 }
 
+// Number of GEMM_RB-row blocks of a B-row batch (the row-blocked layout of
+// the saved activations and of the backward's delta^T).
+__host__ __device__ inline int64_t row_blocks(int64_t B) { return (B + GEMM_RB - 1) / GEMM_RB; }
+
 struct RowsIO {
     const float* x;   // [B][dims0]
     const float* g;   // [B]
     float* y_raw;     // [B][dout]
     float* vr_out;    // [B][3]
-    float* zsave;     // [L-1][B][H] pre-activations, or null
+    float* zsave;     // pre-activations of each hidden layer, row-blocked (below), or null
+    __bf16* hsave;    // their bf16 activations, same layout, with zsave
+    __bf16* xsave;    // the inputs in bf16, same layout, with zsave
     int64_t B;
 };
 
@@ -294,12 +300,16 @@ __device__ __forceinline__ void box_muller_hw53(double ua, double ub, float& n1,
 // produces the inputs of k steps 2 nb and 2 nb + 1, whose MFMAs are issued
 // right away, so the matrix cores run while the next block is activated.
 // PAIR: each input as a bf16 pair (two MFMAs per k step), else one bf16.
-template <int NB, int NBO, int NT, int ACT, bool PAIR>
+// SAVE_H (one tile, NT == 1): the activations are also stored in bf16 at
+// hp[unit * GEMM_RB] (the row-blocked layout of the saved activations; hp
+// null for rows past the end).
+template <int NB, int NBO, int NT, int ACT, bool PAIR, bool SAVE_H = false>
 __device__ __forceinline__ void layer_step(const __bf16* wl, int off, int ksl,
                                            const floatx16 (&acc)[NT][NB],
                                            floatx16 (&nxt)[NT][NBO], const bf16x8& bone,
-                                           int lane)
+                                           int lane, __bf16* hp = nullptr)
 {
+    static_assert(!SAVE_H || NT == 1, "activation save takes one tile per wave");
     const floatx16 zero = {};
 #pragma unroll
     for (int nb2 = 0; nb2 < NBO; ++nb2) {
@@ -315,6 +325,17 @@ __device__ __forceinline__ void layer_step(const __bf16* wl, int off, int ksl,
         for (int t = 0; t < NT; ++t) {
             to_frag<ACT, PAIR>(acc[t][nb], 0, b0[t], c0[t]);
             to_frag<ACT, PAIR>(acc[t][nb], 1, b1[t], c1[t]);
+        }
+        if (SAVE_H && hp) {
+            // h = hi / c: the bf16 activation the next layer used, unscaled
+            const int hh = lane >> 5;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                hp[(nb * 32 + acc_row(e, hh)) * GEMM_RB] =
+                    (__bf16)((float)b0[0][e] * ActScale<ACT>::inv);
+                hp[(nb * 32 + acc_row(8 + e, hh)) * GEMM_RB] =
+                    (__bf16)((float)b1[0][e] * ActScale<ACT>::inv);
+            }
         }
 #pragma unroll
         for (int nb2 = 0; nb2 < NBO; ++nb2) {
@@ -339,15 +360,25 @@ __device__ __forceinline__ void save_pre(const RowsIO& rio, int l, const int64_t
                                          int h)
 {
     if (!SAVE) return;
+    // Row-blocked transposed layout (blocks of GEMM_RB rows, [unit][row]
+    // inside a block): the 32 lanes of a lane-half hold 32 consecutive rows
+    // of one unit, so each store is one contiguous run, and a tile's stores
+    // stay inside one block.  The activations are stored by layer_step,
+    // where they are formed.
+    constexpr float IC = ActScale<ACT>::inv;
+    const size_t Bp = (size_t)row_blocks(rio.B) * GEMM_RB;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (!valid[t]) continue;
+        const size_t base = (size_t)(l - 1) * H * Bp + (size_t)(row[t] / GEMM_RB) * H * GEMM_RB +
+                            (size_t)(row[t] % GEMM_RB);
 #pragma unroll
         for (int nb = 0; nb < H / 32; ++nb)
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                rio.zsave[((size_t)(l - 1) * rio.B + row[t]) * H + nb * 32 + acc_row(r, h)] =
-                    acc[t][nb][r] * ActScale<ACT>::inv;
+            for (int r = 0; r < 16; ++r) {
+                const size_t q = base + (size_t)(nb * 32 + acc_row(r, h)) * GEMM_RB;
+                rio.zsave[q] = acc[t][nb][r] * IC;
+            }
     }
 }
 
@@ -477,7 +508,13 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                     for (int e = 0; e < 8; ++e) {
                         const int c = 16 * q + 8 * h + e;
                         if (c < din) {
-                            if (valid[t]) xin[t][q][e] = C * rio.x[row[t] * din + c];
+                            if (valid[t]) {
+                                const float xv = rio.x[row[t] * din + c];
+                                xin[t][q][e] = C * xv;
+                                if (SAVE)
+                                    rio.xsave[gemm_off(c, row[t], 0, (int64_t)din * GEMM_RB)] =
+                                        (__bf16)xv;
+                            }
                         } else if (c < din + 2) {
                             xin[t][q][e] = 1.0f;
                         }
@@ -527,31 +564,38 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
         // l < 3.
         constexpr bool LATE = SPLIT == DSMC_SPLIT_ALL;
         const int ks = H / 16 + 1;
+        // saved activations of hidden layer ll (rows mode, NT == 1)
+        auto hptr = [&](int ll) -> __bf16* {
+            if (!SAVE || !valid[0]) return nullptr;
+            const size_t Bp = (size_t)row_blocks(rio.B) * GEMM_RB;
+            return rio.hsave + (size_t)(ll - 1) * H * Bp +
+                   (size_t)(row[0] / GEMM_RB) * H * GEMM_RB + (size_t)(row[0] % GEMM_RB);
+        };
         floatx16 alt[NT][NB];
         floatx16 ao[NT][1];
         int l = 1;
         if (l + 1 < L - 1) {
             save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
-            layer_step<NB, NB, NT, ACT, true>(wl, f.off[l], ks, acc, alt, bone, lane);
+            layer_step<NB, NB, NT, ACT, true, SAVE>(wl, f.off[l], ks, acc, alt, bone, lane, hptr(l));
             save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
-            layer_step<NB, NB, NT, ACT, true>(wl, f.off[l + 1], ks, alt, acc, bone, lane);
+            layer_step<NB, NB, NT, ACT, true, SAVE>(wl, f.off[l + 1], ks, alt, acc, bone, lane, hptr(l + 1));
             l += 2;
         }
         for (; l + 1 < L - 1; l += 2) {
             save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
-            layer_step<NB, NB, NT, ACT, LATE>(wl, f.off[l], ks, acc, alt, bone, lane);
+            layer_step<NB, NB, NT, ACT, LATE, SAVE && LATE>(wl, f.off[l], ks, acc, alt, bone, lane, hptr(l));
             save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
-            layer_step<NB, NB, NT, ACT, LATE>(wl, f.off[l + 1], ks, alt, acc, bone, lane);
+            layer_step<NB, NB, NT, ACT, LATE, SAVE && LATE>(wl, f.off[l + 1], ks, alt, acc, bone, lane, hptr(l + 1));
         }
         if (LATE || l < 3) {
             if (l < L - 1) {
                 save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
-                layer_step<NB, NB, NT, ACT, true>(wl, f.off[l], ks, acc, alt, bone, lane);
+                layer_step<NB, NB, NT, ACT, true, SAVE>(wl, f.off[l], ks, acc, alt, bone, lane, hptr(l));
                 save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
-                layer_step<NB, 1, NT, ACT, true>(wl, f.off[L - 1], ks, alt, ao, bone, lane);
+                layer_step<NB, 1, NT, ACT, true, SAVE>(wl, f.off[L - 1], ks, alt, ao, bone, lane, hptr(l + 1));
             } else {
                 save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
-                layer_step<NB, 1, NT, ACT, true>(wl, f.off[L - 1], ks, acc, ao, bone, lane);
+                layer_step<NB, 1, NT, ACT, true, SAVE>(wl, f.off[L - 1], ks, acc, ao, bone, lane, hptr(l));
             }
         } else {
             if (l < L - 1) {
@@ -959,16 +1003,13 @@ static int backward_impl(const MlpDev& d, int64_t B, const T* X, const T* Z, con
 // db) and bf16 (the GEMM operand); h_{l-1} is the bf16 activation the forward
 // used.
 struct Bf16BwdWs {
-    float* d32[2];
-    __bf16* d16[2];
-    __bf16* d16t;   // delta^T [out][B]: k-contiguous A of the weight-gradient GEMM
-    __bf16* h16t;   // h^T [in][B]: k-contiguous B of the weight-gradient GEMM
+    __bf16* dt[2];  // delta^T, row-blocked (ping-pong): k-contiguous A of the weight-gradient GEMM
     float* part;
-    float* red;
+    float* apart;   // per-split row sums of delta^T (bias gradient)
     size_t bytes;
 };
 
-constexpr int BWD_SPLITS_MAX = 128;
+constexpr int BWD_SPLITS_MAX = 256;
 
 static Bf16BwdWs bf16_bwd_layout(void* base, const MlpDev& d, int64_t B)
 {
@@ -978,71 +1019,50 @@ static Bf16BwdWs bf16_bwd_layout(void* base, const MlpDev& d, int64_t B)
     uint8_t* p = static_cast<uint8_t*>(base);
     size_t o = 0;
     auto take = [&](size_t b) { uint8_t* r = p ? p + o : nullptr; o += align_up(b); return r; };
-    for (int q = 0; q < 2; ++q) {
-        w.d32[q] = reinterpret_cast<float*>(take(sizeof(float) * (size_t)B * wmax));
-        w.d16[q] = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * (size_t)B * wmax));
-    }
-    w.d16t = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * (size_t)B * wmax));
-    w.h16t = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * (size_t)B * wmax));
+    const size_t Bp = (size_t)(row_blocks(B) * GEMM_RB);
+    for (int q = 0; q < 2; ++q)
+        w.dt[q] = reinterpret_cast<__bf16*>(take(sizeof(__bf16) * Bp * wmax));
     w.part = reinterpret_cast<float*>(take(sizeof(float) * BWD_SPLITS_MAX * (size_t)wmax * wmax));
-    w.red = reinterpret_cast<float*>(take(sizeof(float) * colsum_ws_floats(B, wmax)));
+    w.apart = reinterpret_cast<float*>(take(sizeof(float) * BWD_SPLITS_MAX * (size_t)wmax));
     w.bytes = o;
     return w;
 }
 
+// Projection backward of the bf16 rows form, written as delta^T of the output
+// layer in bf16 (row-blocked, three units): the same arithmetic as
+// k_project_backward.
 __global__ void __launch_bounds__(256)
-k_to_bf16(int64_t n, const float* __restrict__ a, __bf16* __restrict__ b)
+k_project_backward_t16(int64_t B, const float* __restrict__ Y, const float* __restrict__ g,
+                       const float* __restrict__ G, __bf16* __restrict__ dt)
 {
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * blockDim.x)
-        b[q] = (__bf16)a[q];
-}
-
-// out[c][r] = in[r][c] for a rows x cols bf16 matrix, through 64 x 64 LDS
-// tiles (both sides coalesced).
-constexpr int TR_TILE = 64;
-
-__global__ void __launch_bounds__(256)
-k_transpose16(const __bf16* __restrict__ in, int64_t rows, int64_t cols, __bf16* __restrict__ out)
-{
-    __shared__ __bf16 t[TR_TILE][TR_TILE + 2];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * TR_TILE, c0 = (int64_t)blockIdx.y * TR_TILE;
-    for (int r = ty; r < TR_TILE; r += 4)
-        if (r0 + r < rows && c0 + tx < cols) t[r][tx] = in[(r0 + r) * cols + c0 + tx];
-    __syncthreads();
-    for (int c = ty; c < TR_TILE; c += 4)
-        if (c0 + c < cols && r0 + tx < rows) out[(c0 + c) * rows + r0 + tx] = t[tx][c];
-}
-
-static int transpose16(const __bf16* in, int64_t rows, int64_t cols, __bf16* out, hipStream_t s)
-{
-    const int64_t gr = (rows + TR_TILE - 1) / TR_TILE, gc = (cols + TR_TILE - 1) / TR_TILE;
-    if (gr > 2147483647 || gc > 65535) return arg_error("transpose: matrix too large");
-    k_transpose16<<<dim3((unsigned)gr, (unsigned)gc), 256, 0, s>>>(in, rows, cols, out);
-    DSMC_LAUNCH_CHECK("mlp_bwd16:transpose");
-    return DSMC_OK;
-}
-
-// h_{l-1}^T in bf16, [in][B]: x for l == 0, act(z) otherwise, through the
-// same LDS tiles as k_transpose16.
-__global__ void __launch_bounds__(256)
-k_hprev16t(int64_t rows, int cols, const float* __restrict__ X, const float* __restrict__ Zp,
-           int l, int act, __bf16* __restrict__ Ht)
-{
-    __shared__ __bf16 t[TR_TILE][TR_TILE + 2];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * TR_TILE, c0 = (int64_t)blockIdx.y * TR_TILE;
-    for (int r = ty; r < TR_TILE; r += 4)
-        if (r0 + r < rows && c0 + tx < cols) {
-            const int64_t q = (r0 + r) * cols + c0 + tx;
-            t[r][tx] = (__bf16)((l == 0) ? X[q] : act_t<float>(Zp[q], act));
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < B;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const float y0 = Y[r * 3], y1 = Y[r * 3 + 1], y2 = Y[r * 3 + 2];
+        const float n = dev_sqrt<float>(y0 * y0 + y1 * y1 + y2 * y2);
+        float o[3] = {0.f, 0.f, 0.f};
+        if (n > 1e-30f) {
+            const float u0 = y0 / n, u1 = y1 / n, u2 = y2 / n;
+            const float G0 = G[3 * r], G1 = G[3 * r + 1], G2 = G[3 * r + 2];
+            const float Gu = G0 * u0 + G1 * u1 + G2 * u2;
+            const float f = g[r] / n;
+            o[0] = f * (G0 - Gu * u0);
+            o[1] = f * (G1 - Gu * u1);
+            o[2] = f * (G2 - Gu * u2);
         }
-    __syncthreads();
-    for (int c = ty; c < TR_TILE; c += 4)
-        if (c0 + c < cols && r0 + tx < rows) Ht[(c0 + c) * rows + r0 + tx] = t[tx][c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dt[gemm_off(c, r, 0, 3 * GEMM_RB)] = (__bf16)o[c];
+    }
 }
 
+// Backward of the bf16 rows form.  Everything runs on transposed ([unit][row])
+// bf16 matrices, row-blocked as the forward saves them (blocks of GEMM_RB
+// rows, so a tile's rows sit in one contiguous block), so that both factors
+// of each weight gradient (K = batch) are k-contiguous and no transpose pass
+// is needed:
+//   dW_l = delta_l^T h_{l-1}     (h^T and x^T from the forward's act_save)
+//   db_l = row sums of delta_l^T (summed by the same GEMM from its A tiles)
+//   delta_{l-1}^T = (W_l^T delta_l^T) * act'(z_{l-1}^T)   (a GEMM with
+//   M = units, N = batch, whose epilogue reads z^T and writes delta^T)
 static int backward_bf16(const MlpDev& d, int64_t B, const float* X, const float* Z,
                          const float* Y, const float* g, const float* G, float* const* dW,
                          float* const* db, float* dx, int accumulate, void* ws, hipStream_t s)
@@ -1053,37 +1073,31 @@ static int backward_bf16(const MlpDev& d, int64_t B, const float* X, const float
         int64_t b = (n + 255) / 256;
         return (int)(b < 1 ? 1 : (b > pb ? pb : b));
     };
-    int splits = (int)(B / 512);
+    int splits = (int)(B / 256);
     splits = splits < 1 ? 1 : (splits > BWD_SPLITS_MAX ? BWD_SPLITS_MAX : splits);
-    const int dout = d.dims[d.L];
-    int cur = 0;
-    k_project_backward<float><<<grid1(B), 256, 0, s>>>(B, Y, dout, g, G, w.d32[cur]);
-    DSMC_LAUNCH_CHECK("mlp_bwd16:project");
-    k_to_bf16<<<grid1(B * dout), 256, 0, s>>>(B * dout, w.d32[cur], w.d16[cur]);
-    DSMC_LAUNCH_CHECK("mlp_bwd16:to_bf16");
+    const int64_t Bp = row_blocks(B) * GEMM_RB;
     int64_t zoff[MLP_MAX_LAYERS] = {0};
-    for (int l = 1; l < d.L; ++l) zoff[l] = zoff[l - 1] + B * d.dims[l];
+    for (int l = 1; l < d.L; ++l) zoff[l] = zoff[l - 1] + Bp * d.dims[l];
+    const uint8_t* zb = reinterpret_cast<const uint8_t*>(Z);
+    const size_t hoff = align_up(sizeof(float) * (size_t)zoff[d.L - 1]);
+    const __bf16* Hs = reinterpret_cast<const __bf16*>(zb + hoff);
+    const __bf16* Xs = reinterpret_cast<const __bf16*>(
+        zb + hoff + align_up(sizeof(__bf16) * (size_t)zoff[d.L - 1]));
+    int cur = 0;
+    k_project_backward_t16<<<grid1(B), 256, 0, s>>>(B, Y, g, G, w.dt[cur]);
+    DSMC_LAUNCH_CHECK("mlp_bwd16:project");
     const int gact = d.act == DSMC_ACT_RELU ? GEMM_ACT_RELU : GEMM_ACT_SILU;
     for (int l = d.L - 1; l >= 0; --l) {
         const int out = d.dims[l + 1], in = d.dims[l];
-        const float* Zp = (l > 0) ? Z + zoff[l - 1] : nullptr;
-        // both factors of dW have the batch as K: they are written transposed
-        // so that the GEMM stages them with vector loads
-        {
-            const int64_t gr = (B + TR_TILE - 1) / TR_TILE, gc = (in + TR_TILE - 1) / TR_TILE;
-            if (gr > 2147483647 || gc > 65535) return arg_error("mlp_backward: batch too large");
-            k_hprev16t<<<dim3((unsigned)gr, (unsigned)gc), 256, 0, s>>>(B, in, X, Zp, l, d.act,
-                                                                      w.h16t);
-            DSMC_LAUNCH_CHECK("mlp_bwd16:hprev");
-        }
-        int rc = transpose16(w.d16[cur], B, out, w.d16t, s);
-        if (rc) return rc;
+        const __bf16* hT = (l > 0) ? Hs + zoff[l - 1] : Xs;   // saved by the forward
         GemmArgs gw{};
-        gw.a = w.d16t;
-        gw.lda = B;
+        gw.a = w.dt[cur];
+        gw.lda = GEMM_RB;
+        gw.bsa = (int64_t)out * GEMM_RB;
         gw.ta = 0;
-        gw.b = w.h16t;
-        gw.ldb = B;
+        gw.b = hT;
+        gw.ldb = GEMM_RB;
+        gw.bsb = (int64_t)in * GEMM_RB;
         gw.tb = 1;
         gw.M = out;
         gw.N = in;
@@ -1093,30 +1107,49 @@ static int backward_bf16(const MlpDev& d, int64_t B, const float* X, const float
         gw.out_f32 = dW[l];
         gw.ldo = in;
         gw.partial = w.part;
-        rc = gemm_bf16(gw, splits, s);
+        gw.asum_out = db[l];       // db_l = row sums of delta_l^T, the A operand
+        gw.asum_part = w.apart;
+        int rc = gemm_bf16(gw, splits, s);
         if (rc) return rc;
-        rc = colsum_f32(w.d32[cur], B, out, nullptr, w.red, db[l], nullptr, accumulate, s);
-        if (rc) return rc;
-        if (l > 0 || dx) {
+        if (l > 0) {
             GemmArgs gd{};
-            gd.a = w.d16[cur];
-            gd.lda = out;
-            gd.ta = 0;
-            gd.b = static_cast<const __bf16*>(d.W[l]);
+            gd.a = static_cast<const __bf16*>(d.W[l]);   // A(m = unit of l-1, k) = W[k][m]
+            gd.lda = in;
+            gd.ta = 1;
+            gd.b = w.dt[cur];                             // B(k, n = row) = delta^T[k][n]
+            gd.ldb = GEMM_RB;
+            gd.bsb = (int64_t)out * GEMM_RB;
+            gd.tb = 0;
+            gd.M = in;
+            gd.N = B;
+            gd.K = out;
+            gd.dact_z = Z + zoff[l - 1];                  // z^T, row-blocked
+            gd.ldz = GEMM_RB;
+            gd.bsz = (int64_t)in * GEMM_RB;
+            gd.act = gact;
+            gd.out_bf16 = w.dt[1 - cur];
+            gd.ldo = GEMM_RB;
+            gd.bso = (int64_t)in * GEMM_RB;
+            rc = gemm_bf16(gd, 1, s);
+            if (rc) return rc;
+            cur = 1 - cur;
+        } else if (dx) {
+            GemmArgs gd{};
+            gd.a = w.dt[cur];                             // A(m = row, k) = delta^T[k][m]
+            gd.lda = GEMM_RB;
+            gd.bsa = (int64_t)out * GEMM_RB;
+            gd.ta = 1;
+            gd.b = static_cast<const __bf16*>(d.W[0]);   // B(k, n) = W[k][n]
             gd.ldb = in;
             gd.tb = 0;
             gd.M = B;
             gd.N = in;
             gd.K = out;
-            gd.dact_z = Zp;
-            gd.ldz = in;
-            gd.act = l > 0 ? gact : GEMM_ACT_NONE;
-            gd.out_f32 = (l > 0) ? w.d32[1 - cur] : dx;
-            gd.out_bf16 = (l > 0) ? w.d16[1 - cur] : nullptr;
+            gd.act = GEMM_ACT_NONE;
+            gd.out_f32 = dx;
             gd.ldo = in;
             rc = gemm_bf16(gd, 1, s);
             if (rc) return rc;
-            cur = 1 - cur;
         }
     }
     return DSMC_OK;
@@ -1313,11 +1346,18 @@ extern "C" size_t dsmc_neural_act_bytes(const dsmc_mlp* net, int64_t B)
 {
     MlpDev d;
     if (check_mlp(net, &d) != DSMC_OK || B < 0) return 0;
+    // bf16: row-blocked, rows padded to whole blocks
+    const int64_t Bz = net->wdtype == DSMC_BF16 ? row_blocks(B) * GEMM_RB : B;
     size_t n = 0;
-    for (int l = 1; l < d.L; ++l) n += (size_t)B * d.dims[l];
+    for (int l = 1; l < d.L; ++l) n += (size_t)Bz * d.dims[l];
     const size_t es = net->wdtype == DSMC_F64 ? 8 : 4;
-    // hidden pre-activations, plus (reference path) X copy and two buffers
-    return 256 + align_up(es * n) + ref_ws_bytes(d, B, es);
+    // hidden pre-activations, plus (bf16) their bf16 activations, plus
+    // (reference path) X copy and two buffers
+    const size_t h16 = net->wdtype == DSMC_BF16
+                           ? align_up(sizeof(__bf16) * n) +
+                                 align_up(sizeof(__bf16) * (size_t)Bz * d.dims[0])
+                           : 0;
+    return 256 + align_up(es * n) + h16 + ref_ws_bytes(d, B, es);
 }
 
 extern "C" int dsmc_neural_forward_rows(const dsmc_mlp* net, int64_t B, const void* x,
@@ -1339,8 +1379,18 @@ extern "C" int dsmc_neural_forward_rows(const dsmc_mlp* net, int64_t B, const vo
         if (act_save && act_bytes < dsmc_neural_act_bytes(net, B))
             return arg_error("dsmc_neural_forward_rows: act_save too small");
         const FragLayout f = frag_layout(d);
+        // act_save: pre-activations z^T (FP32), activations h^T (bf16), then
+        // the inputs x^T (bf16), each layer row-blocked over row_blocks(B)
+        // blocks
+        const size_t nzp = nz / (size_t)B * (size_t)(row_blocks(B) * GEMM_RB);
+        uint8_t* as = static_cast<uint8_t*>(act_save);
+        const size_t hoff = align_up(sizeof(float) * nzp);
+        const size_t xoff = hoff + align_up(sizeof(__bf16) * nzp);
         RowsIO rio{(const float*)x, (const float*)g, (float*)y_raw, (float*)vr_out,
-                   act_save ? (float*)act_save : nullptr, B};
+                   act_save ? (float*)act_save : nullptr,
+                   act_save ? reinterpret_cast<__bf16*>(as + hoff) : nullptr,
+                   act_save ? reinterpret_cast<__bf16*>(as + xoff) : nullptr,
+                   B};
         PairsIO<float> pio{};
         if (H == 128) rc = launch_mlp_bf16<128, false, float>(d, f, rio, pio, B, s);
         else if (H == 64) rc = launch_mlp_bf16<64, false, float>(d, f, rio, pio, B, s);
