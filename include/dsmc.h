@@ -403,9 +403,15 @@ int dsmc_mse_loss(int64_t B, const float* vr_new, const float* vr_target, double
 int dsmc_direction_loss(int64_t B, const float* vr_new, const float* vr_target, float* dL_dvr,
                         double* loss, dsmc_stream_t stream);
 
+/* Cosine learning-rate schedule of the surrogate training (section "Neural
+ * Surrogate Training": Adam with a cosine schedule): the rate at step t of T,
+ * lr_min + (lr_max - lr_min) (1 + cos(pi min(t, T) / T)) / 2, so lr_max at
+ * t = 0 and lr_min from t = T on.  Host function; T < 1 returns lr_max. */
+double dsmc_cosine_lr(int64_t t, int64_t T, double lr_max, double lr_min);
+
 /* Adam (Kingma & Ba 2015) with bias correction on FP32 master parameters;
  * also writes the bf16 copy used by the MFMA forward when param_bf16 != NULL.
- * lr comes from the cosine schedule the caller evaluates. */
+ * lr: the step's rate, e.g. dsmc_cosine_lr(t, T, lr_max, lr_min). */
 int dsmc_adam_step(int64_t n, float* param, void* param_bf16, const float* grad, float* m,
                    float* v, int64_t t, double lr, double beta1, double beta2, double eps,
                    dsmc_stream_t stream);

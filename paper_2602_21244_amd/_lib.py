@@ -134,6 +134,7 @@ SIGNATURES = {
                                              _vp, _vp, _vp]),
     "dsmc_mse_loss": (C.c_int, [_i64, _vp, _vp, _d, _vp, _vp, _vp]),
     "dsmc_direction_loss": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp]),
+    "dsmc_cosine_lr": (_d, [_i64, _i64, _d, _d]),
     "dsmc_adam_step": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _i64, _d, _d, _d, _d, _vp]),
     "dsmc_harvest_rows": (C.c_int, [_i64, _vp, _vp, _vp, _d, _d, _d, C.POINTER(Potential), Quad,
                                     _vp, _vp, _vp, _vp, _vp, _vp]),

@@ -363,6 +363,10 @@ def mse_loss(vr_new, vr_target, sigma_v, dL_dvr, loss, stream=None):
           "dsmc_mse_loss")
 
 
+def cosine_lr(t, T, lr_max, lr_min=1e-6):
+    return float(lib().dsmc_cosine_lr(int(t), int(T), float(lr_max), float(lr_min)))
+
+
 def adam_step(param, grad, m, v, t, lr, param_bf16=None, beta1=0.9, beta2=0.999, eps=1e-8,
               stream=None):
     check(lib().dsmc_adam_step(int(param.numel()), _ptr(param), _ptr(param_bf16), _ptr(grad),

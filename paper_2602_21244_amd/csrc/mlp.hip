@@ -1501,6 +1501,13 @@ extern "C" int dsmc_direction_loss(int64_t B, const float* vr_new, const float* 
     return DSMC_OK;
 }
 
+extern "C" double dsmc_cosine_lr(int64_t t, int64_t T, double lr_max, double lr_min)
+{
+    if (T < 1) return lr_max;
+    const double f = (double)(t < T ? (t > 0 ? t : 0) : T) / (double)T;
+    return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + cos(M_PI * f));
+}
+
 extern "C" int dsmc_adam_step(int64_t n, float* param, void* param_bf16, const float* grad,
                               float* m, float* v, int64_t t, double lr, double beta1, double beta2,
                               double eps, dsmc_stream_t stream)

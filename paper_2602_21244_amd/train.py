@@ -17,7 +17,6 @@ directions of slow pairs (most pairs of a 200 K gas) nearly untrained.
 from __future__ import annotations
 
 import argparse
-import math
 import os
 import sys
 import time
@@ -28,10 +27,6 @@ import torch
 from . import api
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-
-
-def cosine_lr(t, T, lr_max, lr_min=1e-6):
-    return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * min(t, T) / T))
 
 
 def harvest(workloads, n, seed, dev, pot, quad):
@@ -122,7 +117,7 @@ def train(steps=4000, batch=65536, pool=1 << 20, lr=2e-3, seed=4, dims=None, out
         else:
             api.mse_loss(vr, tb, sigma_v, dvr, loss)
         api.neural_backward(net, xb, act, y, gb, dvr, params.dW, params.db, ws=bws)
-        lr_t = cosine_lr(t, steps, lr)
+        lr_t = api.cosine_lr(t, steps, lr)
         params.step(t, lr_t)
         if t % log_every == 0 or t == 1 or t == steps:
             yv, vrv = api.neural_forward_rows(net, xv, gv)

@@ -24,10 +24,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 E_LO_K, E_HI_K = 5.0, 5.0e5          # table / training range of E_r / k_B
 
 
-def cosine_lr(t, T, lr_max, lr_min=1e-6):
-    return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * min(t, T) / T))
-
-
 def harvest(workloads, n, seed, dev, pot, quad, lne_lo=None, lne_hi=None):
     """n training rows: (x[n,2], y[n]) with y = ln(1 + theta) from quadrature."""
     lne_lo = math.log(E_LO_K) if lne_lo is None else lne_lo
@@ -85,7 +81,7 @@ def train(steps=4000, batch=4096, pool=1 << 20, lr=1e-3, seed=11, dims=None, out
         api.anet_forward(net, xb, yhat, ws)
         api.huber_loss(yhat, yb, dy, loss)
         api.anet_backward(net, dy, dW, db, ws)
-        lr_t = cosine_lr(t, steps, lr)
+        lr_t = api.cosine_lr(t, steps, lr)
         for q, (p, pbf) in enumerate(params):
             api.adam_step(p, grads[q], mst[q], vst[q], t, lr_t, param_bf16=pbf)
         if t % log_every == 0 or t == 1 or t == steps:

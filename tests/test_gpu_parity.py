@@ -706,6 +706,11 @@ def test_training_helpers(orc, dev, api):
     for step in (1, 2, 3):
         orc.adam_step(P, [gr * step], M, S, step, 1e-2)
     np.testing.assert_allclose(pt.cpu().numpy(), P[0], rtol=1e-5, atol=1e-6)
+    # cosine learning-rate schedule (library host function) against the oracle
+    for t, T, lo, hi in [(0, 100, 1e-6, 1e-3), (37, 100, 1e-6, 1e-3), (100, 100, 1e-6, 1e-3),
+                         (250, 100, 1e-6, 1e-3), (1, 1, 0.0, 2.0), (12345, 160000, 1e-6, 5e-3)]:
+        a, b = api.cosine_lr(t, T, hi, lo), orc.cosine_lr(t, T, hi, lo)
+        assert abs(a - b) <= 1e-15 * hi, (t, T, a, b)
     # moment-match adjoint per cell
     pop = W.ragged_population(17, 30, 40)
     cs, perm, vs, _ = _gpu_sort(api, dev, pop)
