@@ -173,7 +173,10 @@ k_gemm_bf16(GemmArgs g)
     }
     if (mt >= m_tiles) return;
     const int64_t m0 = mt * GM, n0 = nt * GN;
-    const int64_t kc = (g.K + splits - 1) / splits;
+    // split length a whole number of k tiles, so every k tile (and every
+    // 8-element chunk of it) starts on a multiple of GK and never straddles a
+    // GEMM_RB block of a row-blocked operand; trailing splits may be empty
+    const int64_t kc = ((g.K + splits - 1) / splits + GK - 1) / GK * GK;
     const int64_t kbeg = split * kc;
     const int64_t kend = kbeg + kc < g.K ? kbeg + kc : g.K;
     const bool a_kc = !g.ta, b_kc = g.tb;

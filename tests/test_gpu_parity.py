@@ -640,11 +640,13 @@ def test_backward_fp64_against_oracle(orc, dev, api):
     assert np.max(np.abs(dx.cpu().numpy() - rx)) <= 1e-10 * np.abs(rx).max()
 
 
-@pytest.mark.parametrize("B", [4096, 65536])
+@pytest.mark.parametrize("B", [1000, 4096, 65536])
 def test_backward_bf16_bound(orc, dev, api, B):
-    """BF16 weight gradients against FP64 gradients of the same bf16-rounded
-    weights; B = 65 536 is the training batch (the weight-gradient GEMMs then
-    split K = B into 128 partial sums)."""
+    """BF16 weight, bias and input gradients against FP64 gradients of the
+    same bf16-rounded weights; B = 65 536 is the training batch (the
+    weight-gradient GEMMs then split K = B into 256 partial sums, whose row
+    sums give db), B = 1000 leaves a partial last block of 128 rows in the
+    saved activations."""
     say("backward bf16", B)
     rows = W.training_rows(seed=8, n=B)
     Ws, bs = _net_params(7, W.SURROGATE_DIMS)
@@ -659,15 +661,25 @@ def test_backward_bf16_bound(orc, dev, api, B):
     G = orc.surrogate_loss_grad(vr.double().cpu().numpy(), target, rows["sigma_v"])
     dW = [torch.zeros(w.shape, dtype=torch.float32, device=dev) for w in net.W]
     db = [torch.zeros_like(b) for b in net.b]
-    api.neural_backward(net, xt, act, y, gt, torch.as_tensor(G, dtype=torch.float32, device=dev), dW, db)
+    dx = torch.zeros_like(xt)
+    api.neural_backward(net, xt, act, y, gt, torch.as_tensor(G, dtype=torch.float32, device=dev),
+                        dW, db, dx=dx)
     Wr = [w.float().double().cpu().numpy() for w in net.W]  # the bf16-rounded weights
     yref = orc.mlp_forward(Wr, bs, x, "silu")
     dy = orc.project_backward(G, yref, rows["g"])
-    rW, rb, _ = orc.mlp_backward(Wr, bs, x, dy, "silu")
+    rW, rb, rx = orc.mlp_backward(Wr, bs, x, dy, "silu")
+
+    def rel(a, r):
+        return np.linalg.norm(a - r) / np.linalg.norm(r)
+
     for l in range(len(Ws)):
-        e = np.linalg.norm(dW[l].cpu().numpy() - rW[l]) / np.linalg.norm(rW[l])
-        say(f"  layer {l}: rel Frobenius error {e:.3e}")
-        assert e < 5e-2
+        e = rel(dW[l].cpu().numpy(), rW[l])
+        eb = rel(db[l].double().cpu().numpy(), rb[l])
+        say(f"  layer {l}: rel Frobenius error dW {e:.3e}, db {eb:.3e}")
+        assert e < 5e-2 and eb < 5e-2
+    ex = rel(dx.double().cpu().numpy(), rx)
+    say(f"  dL/dx: rel Frobenius error {ex:.3e}")
+    assert ex < 5e-2
 
 
 def test_training_helpers(orc, dev, api):
