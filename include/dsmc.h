@@ -151,9 +151,11 @@ enum { DSMC_ACT_SILU = 0, DSMC_ACT_RELU = 1 };
  * later hidden activations as one bf16 value: about a sixth fewer matrix
  * operations and conversions, at a direction error of a few 1e-3 rad for a
  * trained 8-128x4-3 network (rounding early in the network is amplified
- * most).  Applies to dsmc_neural_collide; the row entry points always use
+ * most).  DSMC_SPLIT_FIRST: the input and the first hidden activation only
+ * (a third fewer pair operations than FRONT, about twice its direction
+ * error).  Applies to dsmc_neural_collide; the row entry points always use
  * DSMC_SPLIT_ALL. */
-enum { DSMC_SPLIT_ALL = 0, DSMC_SPLIT_FRONT = 1 };
+enum { DSMC_SPLIT_ALL = 0, DSMC_SPLIT_FRONT = 1, DSMC_SPLIT_FIRST = 2 };
 typedef struct {
     int32_t n_layers;
     int32_t dims[7];

@@ -15,7 +15,7 @@ WALL_PERIODIC, WALL_SPECULAR, WALL_DIFFUSE = 0, 1, 2
 XS_VHS, XS_CONST = 0, 1
 POT_JAGER, POT_HS, POT_INVPOW = 0, 1, 2
 ACT_SILU, ACT_RELU = 0, 1
-SPLIT_ALL, SPLIT_FRONT = 0, 1
+SPLIT_ALL, SPLIT_FRONT, SPLIT_FIRST = 0, 1, 2
 SCHED_AUTO, SCHED_LANE, SCHED_BLOCK, SCHED_DEFER, SCHED_WAVE = 0, 1, 2, 3, 4
 APPLY_DIRECTIONS, APPLY_ANGLES = 0, 1
 MM_CAPTURE, MM_APPLY, MM_APPLY_LITERAL = 0, 1, 2

@@ -110,14 +110,18 @@ def quad_struct(n_nodes=64, max_iter=60, scan_ratio=0.95, refine=0):
     return L.Quad(int(n_nodes), int(max_iter), float(scan_ratio), int(refine), 0)
 
 
+_SPLITS = {"all": L.SPLIT_ALL, "front": L.SPLIT_FRONT, "first": L.SPLIT_FIRST}
+
+
 class Net:
     """Device copy of an MLP for the C-ABI (keeps the tensors alive)."""
 
     def __init__(self, Ws, bs, act="silu", wdtype="bf16", sigma_v=1.0, device="cuda",
                  split="all"):
-        """split: "all" (every activation a bf16 pair) or "front" (the input
-        and the first two hidden activations only), see dsmc_mlp.split."""
-        if split not in ("all", "front"):
+        """split: "all" (every activation a bf16 pair), "front" (the input
+        and the first two hidden activations only) or "first" (the input and
+        the first hidden activation), see dsmc_mlp.split."""
+        if split not in _SPLITS:
             raise ValueError(split)
         self.dims = [int(Ws[0].shape[1])] + [int(w.shape[0]) for w in Ws]
         self.split = split
@@ -151,7 +155,7 @@ class Net:
             m.W[q] = self.W[q].data_ptr()
             m.b[q] = self.b[q].data_ptr()
         m.sigma_v = self.sigma_v
-        m.split = L.SPLIT_FRONT if self.split == "front" else L.SPLIT_ALL
+        m.split = _SPLITS[self.split]
         self.struct = m
         return m
 

@@ -66,7 +66,8 @@ static int check_mlp(const dsmc_mlp* net, MlpDev* d)
     if (!(net->sigma_v > 0)) return arg_error("dsmc_mlp: sigma_v must be > 0");
     d->inv_sigma_v = 1.0 / net->sigma_v;
     d->act = net->act;
-    if (net->split != DSMC_SPLIT_ALL && net->split != DSMC_SPLIT_FRONT)
+    if (net->split != DSMC_SPLIT_ALL && net->split != DSMC_SPLIT_FRONT &&
+        net->split != DSMC_SPLIT_FIRST)
         return arg_error("dsmc_mlp: split %d", net->split);
     d->split = net->split;
     return DSMC_OK;
@@ -563,6 +564,7 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
         // of the loop, and the tail (layers l and l + 1) is paired when
         // l < 3.
         constexpr bool LATE = SPLIT == DSMC_SPLIT_ALL;
+        constexpr bool SECOND = SPLIT != DSMC_SPLIT_FIRST;   // h2 as a pair
         const int ks = H / 16 + 1;
         // saved activations of hidden layer ll (rows mode, NT == 1)
         auto hptr = [&](int ll) -> __bf16* {
@@ -578,7 +580,7 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
             save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
             layer_step<NB, NB, NT, ACT, true, SAVE>(wl, f.off[l], ks, acc, alt, bone, lane, hptr(l));
             save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
-            layer_step<NB, NB, NT, ACT, true, SAVE>(wl, f.off[l + 1], ks, alt, acc, bone, lane, hptr(l + 1));
+            layer_step<NB, NB, NT, ACT, SECOND, SAVE && SECOND>(wl, f.off[l + 1], ks, alt, acc, bone, lane, hptr(l + 1));
             l += 2;
         }
         for (; l + 1 < L - 1; l += 2) {
@@ -592,7 +594,7 @@ k_mlp_bf16(MlpDev d, FragLayout f, RowsIO rio, PairsIO<VT> pio)
                 save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
                 layer_step<NB, NB, NT, ACT, true, SAVE>(wl, f.off[l], ks, acc, alt, bone, lane, hptr(l));
                 save_pre<H, NT, SAVE, ACT>(rio, l + 1, row, valid, alt, h);
-                layer_step<NB, 1, NT, ACT, true, SAVE>(wl, f.off[L - 1], ks, alt, ao, bone, lane, hptr(l + 1));
+                layer_step<NB, 1, NT, ACT, SECOND, SAVE && SECOND>(wl, f.off[L - 1], ks, alt, ao, bone, lane, hptr(l + 1));
             } else {
                 save_pre<H, NT, SAVE, ACT>(rio, l, row, valid, acc, h);
                 layer_step<NB, 1, NT, ACT, true, SAVE>(wl, f.off[L - 1], ks, acc, ao, bone, lane, hptr(l));
@@ -691,6 +693,8 @@ static int launch_act(const MlpDev& d, const FragLayout& f, RowsIO rio, PairsIO<
     if constexpr (PAIRS) {
         if (d.split == DSMC_SPLIT_FRONT)
             return launch_one<H, PAIRS, VT, ACT, false, DSMC_SPLIT_FRONT>(d, f, rio, pio, max_rows, s);
+        if (d.split == DSMC_SPLIT_FIRST)
+            return launch_one<H, PAIRS, VT, ACT, false, DSMC_SPLIT_FIRST>(d, f, rio, pio, max_rows, s);
         return launch_one<H, PAIRS, VT, ACT, false, DSMC_SPLIT_ALL>(d, f, rio, pio, max_rows, s);
     } else {
         if (rio.zsave != nullptr)

@@ -72,7 +72,7 @@ def test_cylinder_fullsize_neural_step(orc, dev, api):
     causes against the unrounded weights (reported)."""
     say("full-size cylinder step (bench configuration)")
     _cylinder_neural_case(orc, dev, api, "realistic", torch.float32,
-                          list(itertools.product(_surrogate_nets(), ("all", "front"))))
+                          list(itertools.product(_surrogate_nets(), ("all", "front", "first"))))
 
 
 @pytest.mark.parametrize("order,vdtype", [("shuffled", torch.float32), ("realistic", torch.float64)])
@@ -82,7 +82,7 @@ def test_cylinder_fullsize_variants(orc, dev, api, order, vdtype):
     benchmark's activation split."""
     say("full-size cylinder step", order, vdtype)
     nets = [n for n in _surrogate_nets() if n[0] == "trained"] or _surrogate_nets()[:1]
-    _cylinder_neural_case(orc, dev, api, order, vdtype, [(nets[0], "front")])
+    _cylinder_neural_case(orc, dev, api, order, vdtype, [(nets[0], "first")])
 
 
 def _cylinder_neural_case(orc, dev, api, order, vdtype, cases):

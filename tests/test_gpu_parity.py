@@ -534,7 +534,7 @@ def _angle(a, b):
     return np.arccos(np.clip(c, -1, 1))
 
 
-@pytest.mark.parametrize("split", ["all", "front"])
+@pytest.mark.parametrize("split", ["all", "front", "first"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_neural_bf16_chi_rms(orc, dev, api, dtype, split):
     say("neural bf16 mfma", dtype, split)
@@ -568,8 +568,8 @@ def test_neural_bf16_chi_rms(orc, dev, api, dtype, split):
 
 
 def test_neural_split_rejects_unknown_mode(dev, api):
-    """dsmc_mlp.split outside {ALL, FRONT} is an argument error, and the two
-    modes give directions within the bf16 bound of each other."""
+    """dsmc_mlp.split outside {ALL, FRONT, FIRST} is an argument error, and
+    the modes give directions within the bf16 bound of each other."""
     pop = W.cavity_grid(seed=3, nx=20, ny=20)
     cs, _, v, _ = _gpu_sort(api, dev, pop)
     st = api.new_status(dev)
@@ -587,12 +587,13 @@ def test_neural_split_rejects_unknown_mode(dev, api):
     n = int(pairs.cnt.sum())
     es = 8 if v.dtype == torch.float64 else 4
     dirs = {}
-    for split in ("all", "front"):
+    for split in ("all", "front", "first"):
         net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev, split=split)
         api.neural_collide(net, v.clone(), pairs, 3, 0, schedule=api.L.SCHED_DEFER, ws=ws, st=st)
         dirs[split] = ws[: 3 * (pairs.cap + 1) * es].view(v.dtype).view(3, pairs.cap + 1)[:, :n].T.double().cpu().numpy()
-    ang = _angle(dirs["all"], dirs["front"])
-    assert n > 1000 and np.sqrt(np.mean(ang ** 2)) < 1e-2
+    assert n > 1000
+    for split in ("front", "first"):
+        assert np.sqrt(np.mean(_angle(dirs["all"], dirs[split]) ** 2)) < 1e-2
 
 
 def test_neural_rows_bf16(orc, dev, api):
