@@ -137,8 +137,10 @@ typedef struct {
 /* Conditional MLP f_theta (section "Cell-Based Neural Collision Operator"):
  * h_l = act(W_l h_{l-1} + b_l) for hidden layers, linear output layer.
  * W[l] is row-major [dims[l+1]][dims[l]].  wdtype DSMC_BF16: W in bf16, b in
- * fp32, MFMA path (hidden widths multiples of 32 up to 256, dims[0] <= 32,
- * dims[L] <= 32).  wdtype DSMC_F64: W, b in fp64, FP64 reference path (any
+ * fp32, MFMA path (every hidden width 64, 128 or 256, dims[0] <= 30,
+ * dims[L] <= 32, and the weights in fragment order within the 160 KB LDS of
+ * a CU: any depth at width 64, up to five hidden layers at 128, one at 256;
+ * other shapes return DSMC_E_UNSUPPORTED).  wdtype DSMC_F64: W, b in fp64, FP64 reference path (any
  * width up to 256).  The input row is x = [v_r/sigma_v (3), xi (3), z (2)]
  * (eq. mlp_input plus the two impact latents), so dims[0] must be 8 for the
  * in-step entry point. */

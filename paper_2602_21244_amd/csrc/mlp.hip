@@ -136,6 +136,9 @@ struct FragLayout {
     size_t bytes;
 };
 
+// LDS of one CU, which holds the whole bf16 network in fragment order.
+constexpr size_t MLP_LDS_BYTES = 160 * 1024;
+
 static FragLayout frag_layout(const MlpDev& d)
 {
     FragLayout f{};
@@ -1286,6 +1289,10 @@ extern "C" int dsmc_neural_collide(const dsmc_mlp* net, int32_t n_cells, int32_t
         if (!mfma_shape_ok(d, &H))
             return DSMC_E_UNSUPPORTED + 0 * arg_error("dsmc_neural_collide: bf16 shape unsupported");
         const FragLayout f = frag_layout(d);
+        if (f.bytes > MLP_LDS_BYTES)
+            return DSMC_E_UNSUPPORTED + 0 * arg_error("dsmc_neural_collide: the bf16 weights need "
+                                                      "%zu bytes of LDS, more than %zu",
+                                                      f.bytes, MLP_LDS_BYTES);
         RowsIO rio{};
         if (dtype == DSMC_F64) {
             PairsIO<double> pio{pr, n_cells, v3<const double>(v), rng, PairBuf<double>::of(ws, pairs.cap)};
@@ -1383,6 +1390,10 @@ extern "C" int dsmc_neural_forward_rows(const dsmc_mlp* net, int64_t B, const vo
         if (act_save && act_bytes < dsmc_neural_act_bytes(net, B))
             return arg_error("dsmc_neural_forward_rows: act_save too small");
         const FragLayout f = frag_layout(d);
+        if (f.bytes > MLP_LDS_BYTES)
+            return DSMC_E_UNSUPPORTED + 0 * arg_error("dsmc_neural_forward_rows: the bf16 weights "
+                                                      "need %zu bytes of LDS, more than %zu",
+                                                      f.bytes, MLP_LDS_BYTES);
         // act_save: pre-activations z^T (FP32), activations h^T (bf16), then
         // the inputs x^T (bf16), each layer row-blocked over row_blocks(B)
         // blocks

@@ -567,6 +567,53 @@ def test_neural_bf16_chi_rms(orc, dev, api, dtype, split):
             assert abs(np.sum(got[:, a:b_] ** 2) / e0 - 1) < 10 * tol
 
 
+@pytest.mark.parametrize("dims", [(8, 64, 64, 3), (8, 256, 3), (8, 128, 128, 128, 3),
+                                  (8, 64, 64, 64, 64, 64, 3),
+                                  (8, 128, 128, 128, 128, 128, 3)])
+def test_neural_bf16_shapes_and_splits(orc, dev, api, dims):
+    """The fused MLP kernel at every hidden width it takes (64, 128, 256) and
+    at one to five hidden layers (five of 128 fill the 160 KB of LDS), with
+    each activation split: directions against FP64 inference of the same
+    bf16-rounded weights."""
+    say("neural bf16 shapes", dims)
+    pop = W.cavity_grid(seed=4, nx=30, ny=30)
+    cs, vs, mom, pairs, st, sel, v64 = _select_case(orc, dev, api, pop, torch.float32, seed=5, step=2)
+    Ws, bs = _net_params(11, dims)
+    n = int(sel["pair_cnt"].sum())
+    U, xi, z = orc.pair_latents(sel, 5, 2, lowp=True)
+    vr = (v64[:, sel["pair_i"]] - v64[:, sel["pair_j"]]).T
+    x = orc.network_input(vr, xi, z, 500.0)
+    for split in ("all", "front", "first"):
+        net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev, split=split)
+        Wr = [w.float().double().cpu().numpy() for w in net.W]   # as the GPU holds them
+        br = [np.asarray(b_, np.float32).astype(np.float64) for b_ in bs]
+        ws = api.neural_ws(net, pairs, vs)
+        api.neural_collide(net, vs.clone(), pairs, 5, 2, schedule=api.L.SCHED_DEFER, ws=ws, st=st)
+        u = ws[: 3 * (pairs.cap + 1) * 4].view(torch.float32).view(3, pairs.cap + 1)[:, :n].T.double().cpu().numpy()
+        ang = _angle(u, orc.mlp_forward(Wr, br, x, "silu"))
+        rms = float(np.sqrt(np.mean(ang ** 2)))
+        say(f"  split {split}: direction rms {rms:.3e} rad, max {ang.max():.3e}")
+        assert n > 500 and rms <= 1e-2
+
+
+def test_neural_bf16_rejects_weights_beyond_lds(dev, api):
+    """A bf16 network whose weights do not fit the LDS of a CU (two hidden
+    layers of 256) is refused as unsupported before any launch."""
+    pop = W.cavity_grid(seed=3, nx=10, ny=10)
+    cs, _, v, _ = _gpu_sort(api, dev, pop)
+    st = api.new_status(dev)
+    mom = torch.zeros(pop.n_cells * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, v, mom, api.L.MM_CAPTURE)
+    lam = torch.as_tensor(pop.lam, device=dev)
+    pairs = api.PairList(pop.n_cells, 50_000, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 3, 0, pairs, st=st)
+    Ws, bs = _net_params(12, (8, 256, 256, 3))
+    net = api.Net(Ws, bs, act="silu", wdtype="bf16", sigma_v=500.0, device=dev)
+    ws = api.neural_ws(net, pairs, v)
+    with pytest.raises(RuntimeError, match=r"code -3: .*LDS"):
+        api.neural_collide(net, v.clone(), pairs, 3, 0, schedule=api.L.SCHED_DEFER, ws=ws, st=st)
+
+
 def test_neural_split_rejects_unknown_mode(dev, api):
     """dsmc_mlp.split outside {ALL, FRONT, FIRST} is an argument error, and
     the modes give directions within the bf16 bound of each other."""
