@@ -1491,14 +1491,18 @@ extern "C" int dsmc_neural_backward(const dsmc_mlp* net, int64_t B, const void* 
                                        false, ws, s);
 }
 
+constexpr int LOSS_BLOCKS = 128;
+
 extern "C" int dsmc_mse_loss(int64_t B, const float* vr_new, const float* vr_target,
                              double sigma_v, float* dL_dvr, double* loss, dsmc_stream_t stream)
 {
     if (B < 1 || !vr_new || !vr_target || !dL_dvr || !loss || !(sigma_v > 0))
         return arg_error("dsmc_mse_loss: bad arguments");
     const double scale = 1.0 / (4.0 * sigma_v * sigma_v * (double)B);
+    // few workgroups: each adds its share with one FP64 atomic on the same
+    // address, and those serialise
     int blocks = (int)((3 * B + 255) / 256);
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > LOSS_BLOCKS) blocks = LOSS_BLOCKS;
     k_mse<<<blocks, 256, 0, as_stream(stream)>>>(B, vr_new, vr_target, scale, dL_dvr, loss);
     DSMC_LAUNCH_CHECK("mse");
     return DSMC_OK;
@@ -1510,7 +1514,7 @@ extern "C" int dsmc_direction_loss(int64_t B, const float* vr_new, const float* 
     if (B < 1 || !vr_new || !vr_target || !dL_dvr || !loss)
         return arg_error("dsmc_direction_loss: bad arguments");
     int blocks = (int)((B + 255) / 256);
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > LOSS_BLOCKS) blocks = LOSS_BLOCKS;
     k_dir_loss<<<blocks, 256, 0, as_stream(stream)>>>(B, vr_new, vr_target, dL_dvr, loss);
     DSMC_LAUNCH_CHECK("direction_loss");
     return DSMC_OK;
