@@ -8,6 +8,8 @@ keyed by the global cell id, so the oracle can step a range on its own).
   weights; Phase B + moment matching to FP32 tolerance given those directions.
 * Cavity step with the isotropic rule (~1 M particles, FP64): velocities to
   1e-12 on sampled ranges.
+* Cylinder step through the persistent one-launch isotropic kernel: bit for
+  bit the separate entry points over all 30 M particles.
 """
 import itertools
 import math
@@ -230,3 +232,45 @@ def test_deflection_batch_fullsize(orc, dev, api, dtype):
     got = chi.double().cpu().numpy()
     assert api.read_status(st).root_fail == 0 and np.all(np.isfinite(got))
     check_chi(got, ref, dtype, "batch 2^20")
+
+
+def test_cylinder_fullsize_fused_vhs_step(dev, api):
+    """The persistent one-launch VHS step (`dsmc_step_vhs_fused`, timed by
+    the benchmark) on the whole Mach-10 cylinder: pair counts and every
+    matched velocity bit-identical to the separate entry points (capture,
+    NTC selection, isotropic collision, moment matching), with every cell
+    staged (the shock-band cells hold ~2 200 particles)."""
+    say("full-size cylinder step, fused isotropic step against separate calls")
+    pop = W.cylinder_grid(seed=5, order="realistic")
+    nc = pop.n_cells
+    cell_of = torch.as_tensor(pop.cell_of, device=dev)
+    v_in = torch.as_tensor(pop.v, dtype=torch.float32, device=dev).contiguous()
+    lam = torch.as_tensor(pop.lam, device=dev)
+    st = api.new_status(dev)
+    cs, _, v0 = api.sort_cells(cell_of, nc, v_in, st=st)
+    v1 = v0.clone()
+    mom = torch.zeros(nc * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, v1, mom, api.L.MM_CAPTURE)
+    probe = api.PairList(nc, 1, dev)
+    api.select_pairs_ntc(cs, v1, pop.xs, lam, mom, 17, 3, probe, st=st)
+    cap = int(api.read_status(st).n_cand * 1.02) + 1024
+    pairs = api.PairList(nc, cap, dev)
+    api.select_pairs_ntc(cs, v1, pop.xs, lam, mom, 17, 3, pairs, st=st)
+    api.collide_vhs(v1, pairs, 17, 3)
+    api.moment_match(cs, v1, mom, api.L.MM_APPLY, pair_cnt=pairs.cnt)
+    v2 = v0.clone()
+    cnt = torch.zeros(nc, dtype=torch.int32, device=dev)
+    lib = api.lib()
+    ws = api.workspace(lib.dsmc_step_vhs_ws(nc, 0), dev)
+    st2 = api.new_status(dev)
+    api.check(lib.dsmc_step_vhs_fused(nc, api._ptr(cs), api._dtype(v2), api._vec3(v2),
+                                      api.xs_struct(pop.xs), api._ptr(lam),
+                                      api.rng_struct(17, 3), 1, api._ptr(cnt), api._ptr(ws),
+                                      int(ws.numel()), api._ptr(st2), api._stream()),
+              "dsmc_step_vhs_fused")
+    c = cnt.cpu().numpy()
+    say(f"  {int(c.clip(min=0).sum())} pairs, cells not staged {int((c < 0).sum())}, "
+        f"max pairs in a cell {int(c.max())}")
+    assert (c >= 0).all()
+    assert np.array_equal(c, pairs.cnt.cpu().numpy())
+    assert torch.equal(v1, v2)
