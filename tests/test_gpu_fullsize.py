@@ -10,6 +10,9 @@ keyed by the global cell id, so the oracle can step a range on its own).
   1e-12 on sampled ranges.
 * Cylinder step through the persistent one-launch isotropic kernel: bit for
   bit the separate entry points over all 30 M particles.
+* Cylinder step with the neural table rule (table from the angle network,
+  Phase B fused with the matching): velocities to the FP32 bound on sampled
+  ranges.
 """
 import itertools
 import math
@@ -274,3 +277,61 @@ def test_cylinder_fullsize_fused_vhs_step(dev, api):
     assert (c >= 0).all()
     assert np.array_equal(c, pairs.cnt.cpu().numpy())
     assert torch.equal(v1, v2)
+
+
+def test_cylinder_fullsize_table_step(orc, dev, api):
+    """The table rule as the benchmark runs it on the Mach-10 cylinder: the
+    512 x 512 table synthesised from the angle network (the shipped weights
+    when present), Phase A by bilinear lookup (deferred), Phase B fused with
+    the moment matching; against the oracle's table step with the same table
+    on sampled cell ranges (shock band, free stream, disc edge): velocities to
+    the FP32 bound."""
+    import os
+    say("full-size cylinder step, table rule")
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2602_21244_amd", "weights", "jager_anet.npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        L = int(z["n_layers"])
+        Ws, bs = [z[f"W{l}"] for l in range(L)], [z[f"b{l}"] for l in range(L)]
+        lo, hi = float(z["lne_lo"]), float(z["lne_hi"])
+    else:
+        Ws, bs = W.mlp_init(11, api.ANGLE_DIMS)
+        lo, hi = math.log(5.0), math.log(5.0e5)
+    net = api.AngleNet(Ws, bs, device=dev)
+    tab = api.ChiTable(512, 512, lo, hi, device=dev)
+    api.chi_table_build(net, tab)
+    table = {"theta": tab.theta.double().cpu().numpy(), "lne_lo": lo, "lne_hi": hi}
+    pop = W.cylinder_grid(seed=5, order="realistic")
+    nc = pop.n_cells
+    cell_of = torch.as_tensor(pop.cell_of, device=dev)
+    v_in = torch.as_tensor(pop.v, dtype=torch.float32, device=dev).contiguous()
+    lam = torch.as_tensor(pop.lam, device=dev)
+    st = api.new_status(dev)
+    cs, _, v = api.sort_cells(cell_of, nc, v_in, st=st)
+    mom = torch.zeros(nc * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, v, mom, api.L.MM_CAPTURE)
+    probe = api.PairList(nc, 1, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, probe, st=st)
+    cap = int(api.read_status(st).n_cand * 1.02) + 1024
+    pairs = api.PairList(nc, cap, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, pairs, st=st)
+    vp = v.double().cpu().numpy()
+    ws = api.collide_ws(cap, v)
+    api.collide_table(tab, v, pairs, 11, 0, W.AR_MASS / 2, schedule=api.L.SCHED_DEFER, ws=ws)
+    api.apply_pairs_match(cs, v, pairs, api.L.APPLY_ANGLES, mom, ws, st=st)
+    vout = v.double().cpu().numpy()
+    ocs = cs.cpu().numpy()
+    band = 150 * 400 + 95
+    worst, n_pairs = 0.0, 0
+    for k0, k1 in _ranges(ocs, [0, band, 80_000, nc - 60], 60):
+        a, b = ocs[k0], ocs[k1]
+        sub_cs = (ocs[k0:k1 + 1] - a).astype(np.int32)
+        ref, info = orc.step(sub_cs, vp[:, a:b], pop.xs, pop.lam[k0:k1], 11, 0, rule="table",
+                             table=table, m_red=W.AR_MASS / 2, lowp=True, match=True,
+                             cell_base=k0)
+        n_pairs += int(info["sel"]["pair_cnt"].sum())
+        scale = max(float(np.max(np.abs(vp[:, a:b]))), math.sqrt(W.KB * 200.0 / W.AR_MASS))
+        worst = max(worst, float(np.max(np.abs(vout[:, a:b] - ref))) / scale)
+    say(f"  sampled ranges ({n_pairs} pairs): velocity rel err {worst:.3e}")
+    assert n_pairs > 10_000 and worst < 1e-5
