@@ -13,6 +13,8 @@ keyed by the global cell id, so the oracle can step a range on its own).
 * Cylinder step with the neural table rule (table from the angle network,
   Phase B fused with the matching): velocities to the FP32 bound on sampled
   ranges.
+* Cylinder step with the ab initio quadrature rule: chi of every sampled pair
+  to the FP32 bounds, velocities to the FP32 bound.
 """
 import itertools
 import math
@@ -335,3 +337,72 @@ def test_cylinder_fullsize_table_step(orc, dev, api):
         worst = max(worst, float(np.max(np.abs(vout[:, a:b] - ref))) / scale)
     say(f"  sampled ranges ({n_pairs} pairs): velocity rel err {worst:.3e}")
     assert n_pairs > 10_000 and worst < 1e-5
+
+
+def _theta_err(got, ref):
+    return np.abs(np.arccos(np.clip(np.cos(got), -1, 1)) - np.arccos(np.clip(np.cos(ref), -1, 1)))
+
+
+def test_cylinder_fullsize_quadrature_step(orc, dev, api):
+    """The ab initio rule as the benchmark runs it on the Mach-10 cylinder
+    (FP32 lane quadrature with the FP64 refinement pass, Phase A deferred,
+    Phase B fused with the moment matching): on sampled cell ranges, chi of
+    every accepted pair against the oracle's quadrature (the FP32 bounds of
+    the batch test: theta 1e-4, RMS 1e-5) and the velocities against the
+    oracle's rotation, pair update and matching from the GPU's angles."""
+    say("full-size cylinder step, quadrature rule")
+    pop = W.cylinder_grid(seed=5, order="realistic")
+    nc = pop.n_cells
+    cell_of = torch.as_tensor(pop.cell_of, device=dev)
+    v_in = torch.as_tensor(pop.v, dtype=torch.float32, device=dev).contiguous()
+    lam = torch.as_tensor(pop.lam, device=dev)
+    st = api.new_status(dev)
+    cs, _, v = api.sort_cells(cell_of, nc, v_in, st=st)
+    mom = torch.zeros(nc * 6, dtype=torch.float64, device=dev)
+    api.moment_match(cs, v, mom, api.L.MM_CAPTURE)
+    probe = api.PairList(nc, 1, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, probe, st=st)
+    cap = int(api.read_status(st).n_cand * 1.02) + 1024
+    pairs = api.PairList(nc, cap, dev)
+    api.select_pairs_ntc(cs, v, pop.xs, lam, mom, 11, 0, pairs, st=st)
+    vp = v.double().cpu().numpy()
+    pot = api.potential_jager(W.JAGER_PLACEHOLDER)
+    ws = api.collide_ws(cap, v)
+    api.collide_jager(v, pairs, 11, 0, W.AR_MASS / 2, W.B_MAX, pot, schedule=api.L.SCHED_DEFER,
+                      ws=ws, st=st)
+    buf = ws[: 6 * (cap + 1) * 4].view(torch.float32).view(6, cap + 1)
+    ang = buf[:5].double().cpu().numpy()     # cos chi, sin chi, xi
+    api.apply_pairs_match(cs, v, pairs, api.L.APPLY_ANGLES, mom, ws, st=st)
+    assert api.read_status(st).root_fail == 0
+    vout = v.double().cpu().numpy()
+    ocs = cs.cpu().numpy()
+    off = pairs.off.cpu().numpy()
+    P = orc.potential_jager(W.JAGER_PLACEHOLDER)
+    band = 150 * 400 + 95
+    d_all, worst_v = [], 0.0
+    for k0, k1 in _ranges(ocs, [0, band, 80_000, nc - 60], 60):
+        a, b = ocs[k0], ocs[k1]
+        sub_cs = (ocs[k0:k1 + 1] - a).astype(np.int32)
+        sub_v = vp[:, a:b]
+        omom = orc.moments(sub_cs, sub_v)
+        sel = orc.select_ntc(sub_cs, sub_v, pop.xs, pop.lam[k0:k1], omom, 11, 0, cell_base=k0)
+        m, p0 = int(sel["pair_cnt"].sum()), int(off[k0])
+        cc, sc, xi = ang[0, p0:p0 + m], ang[1, p0:p0 + m], ang[2:5, p0:p0 + m].T.copy()
+        U, _, _ = orc.pair_latents(sel, 11, 0, lowp=True)
+        vr = sub_v[:, sel["pair_i"]] - sub_v[:, sel["pair_j"]]
+        g = np.sqrt(np.sum(vr * vr, axis=0))
+        ref, _ = orc.chi_batch(P, W.B_MAX * np.sqrt(U[:, 4]), g, W.AR_MASS / 2, n_threads=8)
+        d_all.append((_theta_err(np.arctan2(sc, cc), ref), np.abs(ref) <= np.pi))
+        vb = orc.apply_chi(sel, sub_v, cc, sc, xi)
+        vm, _ = orc.moment_match(sub_cs, omom, sel["pair_cnt"], vb)
+        scale = max(float(np.max(np.abs(sub_v))), math.sqrt(W.KB * 200.0 / W.AR_MASS))
+        worst_v = max(worst_v, float(np.max(np.abs(vout[:, a:b] - vm))) / scale)
+    d = np.concatenate([x for x, _ in d_all])
+    tame = np.concatenate([t for _, t in d_all])
+    rms = float(np.sqrt(np.mean(d * d)))
+    orb = float(d[~tame].max()) if (~tame).any() else 0.0
+    say(f"  {len(d)} pairs: theta err rms {rms:.3e}, max |chi|<=pi {d[tame].max():.3e}, "
+        f"orbiting ({int((~tame).sum())}) max {orb:.3e}; velocity rel err {worst_v:.3e}")
+    assert len(d) > 10_000
+    assert d[tame].max() < 1e-4 and orb < 1e-4 and rms < 1e-5
+    assert worst_v < 1e-5
